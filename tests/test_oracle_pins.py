@@ -1,0 +1,389 @@
+"""Pins of the C oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: binary64
+arithmetic rounded once (correctly rounded for + - * / on binary32 because
+53 >= 2*24+2, Figueroa 1995), an independent recursive evaluator written
+here, closed forms, summation-order adversaries, brute force on tiny trees,
+and published Philox known answers.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ADD, SUB, MUL, DIV, X = 0, 1, 2, 3, 4
+SYM = {"+": ADD, "-": SUB, "*": MUL, "/": DIV, "x": X}
+
+
+def same_bits(a, b):
+    """Equal bit patterns, or both NaN (NaN payloads differ across ISAs)."""
+    a = np.asarray(a, np.float32)
+    b = np.asarray(b, np.float32)
+    return (a.view(np.uint32) == b.view(np.uint32)) | (np.isnan(a) & np.isnan(b))
+
+
+# ------------------------------------------------ independent reference
+
+def ref_op(op, a, b):
+    """binary64 compute, one rounding to binary32 (= correctly rounded)."""
+    a64 = np.asarray(a, np.float32).astype(np.float64)
+    b64 = np.asarray(b, np.float32).astype(np.float64)
+    with np.errstate(all="ignore"):
+        if op == ADD:
+            r = a64 + b64
+        elif op == SUB:
+            r = a64 - b64
+        elif op == MUL:
+            r = a64 * b64
+        else:
+            r = np.where(b64 != 0.0, a64 / np.where(b64 != 0.0, b64, 1.0), 1.0)
+        return r.astype(np.float32)
+
+
+def ref_eval(tree, x):
+    """Recursive evaluation of a prefix tree (first argument evaluated first)."""
+    x = np.asarray(x, np.float32)
+
+    def ev(i):
+        t = tree[i]
+        if t == X:
+            return x.copy(), i + 1
+        a, j = ev(i + 1)
+        b, k = ev(j)
+        return ref_op(t, a, b), k
+
+    v, end = ev(0)
+    assert end == len(tree)
+    return v
+
+
+def parse(expr: str) -> np.ndarray:
+    return np.array([SYM[s] for s in expr.split()], np.uint8)
+
+
+def special_values():
+    f = np.float32
+    vals = [0.0, -0.0, 1.0, -1.0, 0.5, 2.0, 3.0, 1e-45, -1e-45, 1e-40, 1.17549435e-38, 3.4028235e38,
+            -3.4028235e38, np.inf, -np.inf, np.nan, 1.0000001, 0.99999994, 1e-20, 1e20, 7.0, 0.1]
+    return np.array(vals, np.float32)
+
+
+def operand_pairs(rng, n):
+    sp = special_values()
+    a = np.concatenate([np.repeat(sp, sp.size), rng.standard_normal(n).astype(np.float32),
+                        (rng.standard_normal(n) * 1e30).astype(np.float32),
+                        rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32).view(np.float32)])
+    b = np.concatenate([np.tile(sp, sp.size), rng.standard_normal(n).astype(np.float32),
+                        (rng.standard_normal(n) * 1e-30).astype(np.float32),
+                        rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32).view(np.float32)])
+    return a, b
+
+
+# ------------------------------------------------------------ per-op pins
+
+@pytest.mark.parametrize("op", [ADD, SUB, MUL, DIV])
+def test_op_is_correctly_rounded(op):
+    rng = np.random.default_rng(100 + op)
+    a, b = operand_pairs(rng, 3000)
+    got = np.array([oracle.op(op, float(u), float(v)) for u, v in zip(a, b)], np.float32)
+    want = ref_op(op, a, b)
+    bad = ~same_bits(got, want)
+    assert not bad.any(), list(zip(a[bad][:5], b[bad][:5], got[bad][:5], want[bad][:5]))
+
+
+def test_protected_division_rule():
+    # (y != 0) ? x/y : 1.0f (Table 1 footnote): -0 counts as zero, NaN does not
+    assert oracle.op(DIV, 5.0, 0.0) == 1.0
+    assert oracle.op(DIV, 5.0, -0.0) == 1.0
+    assert oracle.op(DIV, float("nan"), 0.0) == 1.0
+    assert np.isnan(oracle.op(DIV, 5.0, float("nan")))
+    assert oracle.op(DIV, 5.0, float("inf")) == 0.0
+
+
+# ------------------------------------------------------ tree evaluation
+
+def all_trees(n_nodes):
+    """Every prefix tree with exactly n_nodes nodes (n odd)."""
+    if n_nodes == 1:
+        yield [X]
+        return
+    for left in range(1, n_nodes - 1, 2):
+        right = n_nodes - 1 - left
+        for lt in all_trees(left):
+            for rt in all_trees(right):
+                for op in (ADD, SUB, MUL, DIV):
+                    yield [op] + lt + rt
+
+
+def test_exhaustive_trees_up_to_7_nodes():
+    trees = [t for n in (1, 3, 5, 7) for t in all_trees(n)]
+    assert len(trees) == 1 + 4 + 32 + 320
+    x48, _ = workloads.cases(48)
+    xs = np.concatenate([x48, special_values()])
+    for t in trees:
+        tree = np.array(t, np.uint8)
+        got = oracle.eval_cases(tree, xs)
+        want = ref_eval(t, xs)
+        assert same_bits(got, want).all(), (t, got, want)
+
+
+def test_random_trees_against_recursive_reference():
+    rng = np.random.default_rng(7)
+    x48, _ = workloads.cases(48)
+    xs = np.concatenate([x48, (rng.standard_normal(16) * 10).astype(np.float32), special_values()])
+    for k in range(400):
+        n = int(rng.integers(0, 32)) * 2 + 1
+        tree = workloads.random_tree(11, k, n)
+        got = oracle.eval_cases(tree, xs)
+        want = ref_eval(list(tree), xs)
+        assert same_bits(got, want).all(), (k, n)
+
+
+def test_deep_tree_within_fp64_error_bound():
+    # A long random tree evaluated in binary32 stays within the forward error
+    # bound of its binary64 evaluation wherever the binary64 value is modest.
+    x = np.linspace(-0.9, 0.9, 48).astype(np.float32)
+    tree = parse("* + x / x x - x * x x")  # x*(x+1)... exact small polynomial-ish tree
+    got = oracle.eval_cases(tree, x).astype(np.float64)
+    xd = x.astype(np.float64)
+    exact = (xd + 1.0) * (xd - xd * xd)
+    # 4 operations, each within 2^-24 relative: |err| <= ~4u * sum of magnitudes
+    u = 2.0 ** -24
+    bound = 6 * u * ((np.abs(xd) + 1) * (np.abs(xd) + xd * xd)) + 1e-30
+    assert np.all(np.abs(got - exact) <= bound)
+
+
+# ----------------------------------------------------------- closed forms
+
+def test_t_minus_t_is_zero():
+    rng = np.random.default_rng(3)
+    x48, _ = workloads.cases(48)
+    for k in range(50):
+        sub = workloads.random_tree(5, k, int(rng.integers(1, 40)) * 2 + 1)
+        tree = np.concatenate([[SUB], sub, sub]).astype(np.uint8)
+        t_val = oracle.eval_cases(sub, x48)
+        got = oracle.eval_cases(tree, x48)
+        fin = np.isfinite(t_val)
+        assert np.all(got[fin] == 0.0) and not np.signbit(got[fin]).any()
+        assert np.all(np.isnan(got[~fin]))
+
+
+def test_x_over_x_is_one_and_zero_divisor_gives_one():
+    x48, _ = workloads.cases(48)
+    assert np.all(x48 != 0)  # 48 evenly spaced points never hit 0
+    assert np.all(oracle.eval_cases(parse("/ x x"), x48) == 1.0)
+    rng = np.random.default_rng(4)
+    for k in range(30):
+        num = workloads.random_tree(6, k, int(rng.integers(0, 30)) * 2 + 1)
+        tree = np.concatenate([[DIV], num, parse("- x x")]).astype(np.uint8)
+        assert np.all(oracle.eval_cases(tree, x48) == 1.0)
+
+
+def test_operand_order_of_sub_and_div():
+    x = np.linspace(-1, 1, 48).astype(np.float32)
+    got = oracle.eval_cases(parse("- x * x x"), x)
+    assert same_bits(got, x - x * x).all()
+    got = oracle.eval_cases(parse("/ x + x x"), x)
+    assert np.all(got == 0.5)
+
+
+def test_constant_tree_fitness_is_mean_abs_target():
+    x, y = workloads.cases(48)
+    out = oracle.eval_cases(parse("- x x"), x)
+    assert np.all(out == 0.0)
+    fit = float(oracle.fitness(out, y))
+    exact = float(np.abs(y.astype(np.float64)).sum() / 48)
+    assert abs(fit - exact) <= 48 * 2.0 ** -24 * exact
+
+
+def load_sextic():
+    trees = {}
+    for line in open(os.path.join(HERE, "golden", "sextic_trees.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, expr = line.split(":", 1)
+        trees[name.strip()] = parse(expr)
+    return trees
+
+
+def test_exact_sextic_trees():
+    trees = load_sextic()
+    x, y = workloads.cases(48)
+    xd = x.astype(np.float64)
+    y64 = xd ** 6 - 2 * xd ** 4 + xd ** 2
+    one = np.float32(1)
+    # the same tree evaluated by numpy binary32 in the tree's own order
+    f_fact = ((x * x) * ((x - one) * (x - one))) * ((x + one) * (x + one))
+    x2 = x * x
+    f_exp = (x2 * (x2 * x2)) - (((x2 * x2) + (x2 * x2)) - x2)
+    for name, same_order, bound in (("factored", f_fact, 2e-7), ("expanded", f_exp, 1e-6)):
+        tree = trees[name]
+        ok, _ = oracle.validate(tree)
+        assert ok
+        out = oracle.eval_cases(tree, x)
+        assert same_bits(out, same_order).all(), name
+        # table computed in binary32 in the same order -> MAE exactly 0
+        assert oracle.fitness(out, same_order) == 0.0
+        # against the binary64 target: tiny error
+        assert float(oracle.fitness(out, y)) <= bound
+        assert np.max(np.abs(out.astype(np.float64) - y64)) <= 4 * bound
+
+
+def test_fitness_sums_in_ascending_order():
+    # e = |0 - y| with y = [1e8, 1, 1, ...]: ascending binary32 sum stays 1e8
+    # (each +1 rounds away), a reversed sum would reach 1e8 + 48.
+    y = np.ones(48, np.float32)
+    y[0] = 1e8
+    out = np.zeros(48, np.float32)
+    got = oracle.fitness(out, y)
+    assert got == np.float32(1e8) / np.float32(48)
+    assert got != np.float32(100000048.0) / np.float32(48)
+
+
+# ------------------------------------------------------------- validation
+
+def test_validation_and_stack_invariants():
+    rng = np.random.default_rng(9)
+    for k in range(200):
+        n = int(rng.integers(0, 200)) * 2 + 1
+        t = workloads.random_tree(9, k, n)
+        ok, ms = oracle.validate(t)
+        assert ok and t.size % 2 == 1
+        assert np.sum(t == X) == np.sum(t != X) + 1
+        # right-to-left height: +1 per leaf, -1 per function
+        h = np.cumsum(np.where(t[::-1] == X, 1, -1))
+        assert ms == h.max() and h[-1] == 1
+        if n > 1:
+            assert not oracle.validate(t[:-1])[0]  # truncated
+        assert not oracle.validate(np.append(t, X))[0]  # trailing leaf
+        bad = t.copy()
+        bad[int(rng.integers(0, n))] = 5 + int(rng.integers(0, 250))
+        assert not oracle.validate(bad)[0]
+    assert not oracle.validate(np.array([], np.uint8))[0]
+    for k in range(1, 20):
+        left = np.array([ADD] * k + [X] * (k + 1), np.uint8)  # (((x+x)+x)...)
+        right = np.array([ADD, X] * k + [X], np.uint8)       # x+(x+(x+...))
+        assert oracle.validate(left) == (True, k + 1)
+        assert oracle.validate(right) == (True, 2)
+
+
+# -------------------------------------------------------------- crossover
+
+def brute_subtree_end(t, p):
+    def walk(i):
+        return i + 1 if t[i] == X else walk(walk(i + 1))
+    return walk(p) - 1
+
+
+def test_crossover_invariants():
+    rng = np.random.default_rng(12)
+    for k in range(300):
+        mum = workloads.random_tree(21, k, int(rng.integers(0, 60)) * 2 + 1)
+        dad = workloads.random_tree(22, k, int(rng.integers(0, 60)) * 2 + 1)
+        p = int(rng.integers(0, mum.size))
+        q = int(rng.integers(0, dad.size))
+        ep, eq = oracle.subtree_end(mum, p), oracle.subtree_end(dad, q)
+        assert ep == brute_subtree_end(mum, p) and eq == brute_subtree_end(dad, q)
+        child = oracle.crossover(mum, dad, p, q)
+        assert child.size == mum.size - (ep - p + 1) + (eq - q + 1)
+        assert np.array_equal(child[:p], mum[:p])
+        assert np.array_equal(child[p:p + eq - q + 1], dad[q:eq + 1])
+        assert np.array_equal(child[p + eq - q + 1:], mum[ep + 1:])
+        assert oracle.validate(child)[0]
+        if p == 0:
+            assert np.array_equal(child, dad[q:eq + 1])
+
+
+# ------------------------------------------------------- Philox, selection
+
+def load_kat():
+    rows = []
+    for line in open(os.path.join(HERE, "golden", "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(s, 16) for s in line.split()]
+        rows.append((v[:4], v[4:6], v[6:10]))
+    return rows
+
+
+def test_philox_known_answers():
+    for ctr, key, want in load_kat():
+        assert oracle.philox4x32_10(ctr, key).tolist() == want
+
+
+def test_tournament_prefers_better_and_treats_nan_as_worst():
+    sizes = np.full(4, 7, np.uint64)
+    fit = np.array([np.nan, 0.5, np.nan, np.nan], np.float32)
+    for child in range(50):
+        m, d, p, q = oracle.choose(fit, 32, 99, 3, child, sizes)
+        assert m == 1 and d == 1  # 32 draws over 4 trees: misses with prob 2^-64
+        assert 0 <= p < 7 and 0 <= q < 7
+    fit = np.array([np.inf, np.nan, 1.0, np.inf], np.float32)
+    for child in range(50):
+        m, _, _, _ = oracle.choose(fit, 32, 5, 0, child, sizes)
+        assert m == 2
+
+
+def test_selection_draws_are_uniform():
+    m_count = np.zeros(10, np.int64)
+    p_count = np.zeros(13, np.int64)
+    fit = np.zeros(10, np.float32)
+    sizes = np.full(10, 13, np.uint64)
+    for child in range(4000):
+        m, d, p, q = oracle.choose(fit, 1, 1234, 77, child, sizes)
+        m_count[m] += 1
+        p_count[p] += 1
+    # chi-square at far-out thresholds (df 9 and 12)
+    assert ((m_count - 400.0) ** 2 / 400.0).sum() < 40
+    e = 4000 / 13
+    assert ((p_count - e) ** 2 / e).sum() < 45
+
+
+def test_generation_children_are_crossovers_of_chosen_parents():
+    x, y = workloads.cases(48)
+    buf, off = workloads.rhh_population(workloads.SEED_BASE + 9, 48, 2, 6)
+    fit = oracle.eval_population(buf, off, x, y)
+    cbuf, coff, capped = oracle.generation(buf, off, fit, 2, 42, 0, 10**9)
+    assert capped == 0
+    sizes = np.diff(off)
+    for j in range(48):
+        m, d, p, q = oracle.choose(fit, 2, 42, 0, j, sizes)
+        mum = buf[off[m]:off[m + 1]]
+        dad = buf[off[d]:off[d + 1]]
+        child = cbuf[coff[j]:coff[j + 1]]
+        assert np.array_equal(child, oracle.crossover(mum, dad, p, q))
+    # a cap below every child size turns every child into a copy of its mum
+    cbuf2, coff2, capped2 = oracle.generation(buf, off, fit, 2, 42, 0, 0)
+    assert capped2 == 48
+    for j in range(48):
+        m, _, _, _ = oracle.choose(fit, 2, 42, 0, j, sizes)
+        assert np.array_equal(cbuf2[coff2[j]:coff2[j + 1]], buf[off[m]:off[m + 1]])
+
+
+def test_population_eval_threads_do_not_change_results():
+    x, y = workloads.cases(48)
+    sizes = workloads.loguniform_sizes(3, 64, 3, 3000)
+    buf, off = workloads.random_population(3, sizes)
+    f1, p1 = oracle.eval_population(buf, off, x, y, threads=1, per_case=True)
+    f8, p8 = oracle.eval_population(buf, off, x, y, threads=8, per_case=True)
+    assert same_bits(f1, f8).all() and same_bits(p1, p8).all()
+
+
+def test_fitness_divides_once_by_n():
+    # MAE = (sum) / (float)N with one correctly rounded division; a multiply
+    # by a rounded 1/N differs for some sums, and those must not be taken.
+    rng = np.random.default_rng(21)
+    out = np.zeros(48, np.float32)
+    differs = 0
+    for v in rng.uniform(0.01, 100.0, 2000).astype(np.float32):
+        y = np.zeros(48, np.float32)
+        y[0] = v
+        want = np.float32(v) / np.float32(48)
+        differs += int(want != np.float32(v) * (np.float32(1) / np.float32(48)))
+        assert oracle.fitness(out, y) == want
+    assert differs > 0
