@@ -1,0 +1,216 @@
+/*
+ * libev - evaluation of prefix-linear GP trees on one AMD Instinct MI355X
+ * (gfx950).  C ABI: plain pointers and sizes only.
+ *
+ * Method: Langdon & Banzhaf, "Faster Genetic Programming GPquick via
+ * multicore and Advanced Vector Extensions" (2019).
+ *
+ *   Trees (Sec. 2.2): each tree is flattened into a buffer of one-byte
+ *   opcodes, root first, children in order.  Tokens:
+ *       EV_ADD 0, EV_SUB 1, EV_MUL 2, EV_DIV 3  functions of two arguments
+ *       EV_X   4                                the input
+ *   "op A B" is A op B; EV_DIV is protected division,
+ *   (B != 0) ? A / B : 1.0f (Sec. 2.1 and the footnote of Table 1).
+ *   All arithmetic is IEEE binary32, round to nearest even, subnormals
+ *   kept, no contraction.
+ *
+ *   Fitness (Table 1, Sec. 3.2): mean over the N cases of |tree(x_i) - y_i|,
+ *   the absolute errors summed in ascending case order in binary32 and the
+ *   sum divided by (float)N (Sec. 2.2, last paragraph: fixed order so that
+ *   every run gives identical results).  Lower is better.
+ *
+ *   Crossover (Sec. 3.1): one child from two parents; the child is the
+ *   mum's tokens before point p, then the dad's whole subtree rooted at q,
+ *   then the mum's tokens after the subtree rooted at p.
+ *
+ *   Selection (Table 1): tournaments choose both parents.
+ *
+ * Error behaviour: every call returns an ev_status; 0 is success, negative
+ * values are errors, and no exception or abort crosses the ABI.
+ * ev_last_error() returns a message for the calling thread's last error.
+ *
+ * Ownership: the library copies caller buffers during a call and keeps no
+ * caller pointer after it returns, except that output pointers passed to
+ * ev_submit are not used at all (results are fetched with ev_result).
+ * Populations live in device memory owned by the context until ev_free_pop
+ * or ev_destroy.
+ *
+ * Threads: a context may be used by one thread at a time, except that
+ * ev_submit, ev_poll, ev_result and ev_wait may be called concurrently
+ * from any threads.
+ */
+#ifndef EV_H
+#define EV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ev_status;
+typedef struct ev_ctx ev_ctx;
+typedef int32_t ev_pop;
+typedef uint64_t ev_ticket;
+
+enum {
+    EV_OK = 0,
+    EV_EINVAL = -1,     /* bad argument or handle */
+    EV_EMALFORMED = -2, /* a tree is not a valid prefix word over tokens 0..4 */
+    EV_ENOMEM = -3,     /* device memory or the context's memory budget exhausted */
+    EV_ECAP = -4,       /* a size limit was exceeded */
+    EV_EBUSY = -5,      /* job can never fit the memory budget */
+    EV_ENOTFOUND = -6,  /* unknown population or ticket */
+    EV_EDEVICE = -7     /* HIP runtime error */
+};
+
+enum { EV_ADD = 0, EV_SUB = 1, EV_MUL = 2, EV_DIV = 3, EV_X = 4 };
+
+/* flags */
+#define EV_DEVICE_PTR 0x1u /* ev_load_trees: bytes/off are device pointers */
+#define EV_OUT_DEVICE 0x2u /* ev_eval_fitness: outputs are device pointers;
+                              the call returns once the work is queued on
+                              the context's stream */
+
+/* Create a context on HIP device `device` with case table 0: x[n_cases],
+ * y[n_cases] (host pointers; the paper's fitness cases are x inputs with
+ * their Sextic targets y = x^6 - 2x^4 + x^2, Sec. 3 and Table 1).
+ * mem_budget_bytes bounds the device memory held by populations, plans and
+ * jobs (0 = no bound).  stream is a hipStream_t to order all work on, or
+ * NULL for a stream owned by the context.
+ * Errors: EV_EINVAL (n_cases < 1, NULL pointers), EV_EDEVICE. */
+ev_status ev_create(ev_ctx **out, int device, const float *x, const float *y, int32_t n_cases,
+                    uint64_t mem_budget_bytes, void *stream);
+
+/* Add another case table (host x[n], y[n]); *table receives its index. */
+ev_status ev_add_cases(ev_ctx *ctx, const float *x, const float *y, int32_t n_cases, int32_t *table);
+
+/* Release every population, plan, job and device buffer of the context. */
+ev_status ev_destroy(ev_ctx *ctx);
+
+/* Thread-local message for the last failing call on this thread. */
+const char *ev_last_error(void);
+
+/* Load n_trees trees.  bytes holds every tree back to back, tree t at
+ * bytes[off[t], off[t+1]); off has n_trees+1 entries, off[0] = 0.  With
+ * EV_DEVICE_PTR both are device pointers, else host pointers.  Every tree
+ * is validated (Sec. 2.2 word: tokens 0..4, one complete prefix tree); on
+ * failure nothing is loaded, EV_EMALFORMED is returned and *bad_tree
+ * (nullable) is the first bad tree.  The structure plan used by
+ * ev_eval_fitness is built here.  *out_pop receives the handle. */
+ev_status ev_load_trees(ev_ctx *ctx, const uint8_t *bytes, const uint64_t *off, int32_t n_trees,
+                        uint32_t flags, ev_pop *out_pop, int32_t *bad_tree);
+
+/* Number of trees and total bytes of a population. */
+ev_status ev_pop_info(ev_ctx *ctx, ev_pop pop, int32_t *n_trees, uint64_t *total_bytes);
+
+/* Copy a population to host memory: bytes (cap_bytes >= total bytes) and
+ * off[n_trees+1]. */
+ev_status ev_get_trees(ev_ctx *ctx, ev_pop pop, uint8_t *bytes, uint64_t *off, uint64_t cap_bytes);
+
+ev_status ev_free_pop(ev_ctx *ctx, ev_pop pop);
+
+/* Evaluate every tree of pop on case table `table` (Sec. 2.2, one pass
+ * over each tree for all cases) and compute its fitness (Table 1).
+ * fitness[n_trees] receives the MAE, per_case[n_trees * N] (nullable) the
+ * tree outputs, row-major by tree.  Host pointers unless EV_OUT_DEVICE.
+ * The fitness is also kept with the population for ev_generation. */
+ev_status ev_eval_fitness(ev_ctx *ctx, ev_pop pop, int32_t table, float *fitness, float *per_case,
+                          uint32_t flags);
+
+/* Subtree crossover (Sec. 3.1) with caller-chosen parents and points.
+ * Child j = crossover(mums_pop tree mum[j] at point p[j],
+ *                     dads_pop tree dad[j] at point q[j]).
+ * mum, dad, p, q are host arrays of n_children entries; p[j] must be below
+ * the mum's size and q[j] below the dad's.  A child larger than size_cap
+ * nodes is replaced by a copy of its mum and counted in *n_capped
+ * (nullable).  *out_children receives the new population (planned, ready
+ * for ev_eval_fitness).  Errors: EV_EINVAL (bad index or point). */
+ev_status ev_crossover(ev_ctx *ctx, ev_pop mums_pop, ev_pop dads_pop, const int32_t *mum,
+                       const int32_t *dad, const uint64_t *p, const uint64_t *q, int32_t n_children,
+                       uint64_t size_cap, ev_pop *out_children, int32_t *n_capped);
+
+/* One generation (Sec. 2.3, Sec. 3.1, Table 1) on the device: for every
+ * child j of the n_trees children, tournaments of size `tournament` over
+ * the parents' fitness from their last ev_eval_fitness pick mum and dad,
+ * Philox4x32-10 draws keyed by (seed, gen, j) pick p and q uniformly over
+ * all nodes, and the child is made by subtree crossover (size_cap as in
+ * ev_crossover).  The draw layout is:
+ *   key = {seed lo32, seed hi32}; ctr = {j, purpose, gen lo32, gen hi32};
+ *   candidate c of role r (0 mum, 1 dad) is word c%4 of purpose
+ *   ((r+1) << 8) | (c/4), mapped to [0, M) by (w * M) >> 32; the points use
+ *   purpose 0x300, p from (w1:w0) and q from (w3:w2), each mapped to
+ *   [0, n) by the high 64 bits of the 128-bit product; better = lower MAE,
+ *   NaN worst, ties keep the earlier candidate. */
+ev_status ev_generation(ev_ctx *ctx, ev_pop parents, uint64_t seed, uint64_t gen, int32_t tournament,
+                        uint64_t size_cap, ev_pop *out_children, int32_t *n_capped);
+
+/* ---- serving: continuously batched evaluation / crossover requests ---- */
+
+enum { EV_JOB_EVAL = 0, EV_JOB_CROSSOVER = 1 };
+
+typedef struct {
+    int32_t kind;          /* EV_JOB_EVAL or EV_JOB_CROSSOVER */
+    int32_t table;         /* case table for evaluation */
+    /* EV_JOB_EVAL: host trees, copied during ev_submit */
+    const uint8_t *bytes;
+    const uint64_t *off;
+    int32_t n_trees;
+    /* EV_JOB_CROSSOVER: parents from a resident population; the children
+     * are evaluated and their fitness returned */
+    ev_pop parents;
+    const int32_t *mum, *dad;
+    const uint64_t *p, *q;
+    int32_t n_children;
+    uint64_t size_cap;
+} ev_job;
+
+/* Queue a job (thread-safe).  Inputs are copied before returning.  A job is
+ * admitted to the device when its memory footprint fits the context's
+ * budget beside the jobs in flight; jobs arriving while others run are
+ * batched into the next device launch.  EV_EBUSY: the job can never fit. */
+ev_status ev_submit(ev_ctx *ctx, const ev_job *job, ev_ticket *out);
+
+/* Non-blocking: *done = 1 once the job finished; *job_status its result. */
+ev_status ev_poll(ev_ctx *ctx, ev_ticket t, int32_t *done, ev_status *job_status);
+
+/* Block until the job finishes. */
+ev_status ev_wait(ev_ctx *ctx, ev_ticket t, ev_status *job_status);
+
+/* Copy a finished job's fitness (n entries) and, if per_case is not NULL,
+ * its per-case outputs (n * N); releases the ticket.  *n_out receives n. */
+ev_status ev_result(ev_ctx *ctx, ev_ticket t, float *fitness, float *per_case, int32_t cap,
+                    int32_t *n_out);
+
+/* Steady-clock nanoseconds at which the job was submitted, started on the
+ * device and finished (0 while not yet reached). */
+ev_status ev_job_timing(ev_ctx *ctx, ev_ticket t, uint64_t *submit_ns, uint64_t *start_ns, uint64_t *done_ns);
+
+/* ---- introspection used by tests and the benchmark ---- */
+
+typedef struct {
+    int32_t levels;          /* levels of the split plan */
+    uint64_t chunks;         /* work items over all levels */
+    uint64_t slots;          /* intermediate result slots over all levels */
+    uint64_t max_stack;      /* deepest operand stack of any work item */
+    uint64_t plan_bytes;     /* device bytes held by the plan */
+} ev_plan_info;
+
+ev_status ev_get_plan_info(ev_ctx *ctx, ev_pop pop, ev_plan_info *info);
+
+/* Tuning knobs (0 keeps the current value): chunk = tokens per work item
+ * of the split, lds_depth = operand-stack entries kept in LDS per wave
+ * (64 or 128).  Plans made afterwards use them; results never depend on
+ * them. */
+ev_status ev_set_tuning(ev_ctx *ctx, uint32_t chunk, uint32_t lds_depth);
+
+/* Device time in milliseconds of the last ev_eval_fitness on this context
+ * (HIP events around the evaluation kernels) and of its dominant kernel
+ * (the level-0 interpreter launch). */
+ev_status ev_last_timing(ev_ctx *ctx, float *eval_ms, float *interp_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,321 @@
+"""Python binding of libev (GP-tree evaluation on MI355X).
+
+Argument marshalling only: every step of evaluation, crossover and selection
+runs in the HIP kernels of ``libev.so`` (built from ``csrc/`` by
+``build.build()``).  The functions carry the names of the C ABI in
+``include/ev.h``; ``Context`` is a small convenience wrapper over them.
+
+Inputs may be numpy arrays (host) or torch tensors on the GPU (device
+pointers, passed with EV_DEVICE_PTR / EV_OUT_DEVICE).  There is no fallback:
+if ``libev.so`` is missing or fails to load, importing the library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libev.so")
+
+EV_OK, EV_EINVAL, EV_EMALFORMED, EV_ENOMEM, EV_ECAP, EV_EBUSY, EV_ENOTFOUND, EV_EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
+EV_ADD, EV_SUB, EV_MUL, EV_DIV, EV_X = 0, 1, 2, 3, 4
+EV_DEVICE_PTR, EV_OUT_DEVICE = 0x1, 0x2
+EV_JOB_EVAL, EV_JOB_CROSSOVER = 0, 1
+
+EXPORTS = [
+    "ev_create", "ev_add_cases", "ev_destroy", "ev_last_error", "ev_load_trees", "ev_pop_info",
+    "ev_get_trees", "ev_free_pop", "ev_eval_fitness", "ev_crossover", "ev_generation", "ev_submit",
+    "ev_poll", "ev_wait", "ev_result", "ev_job_timing", "ev_get_plan_info", "ev_set_tuning",
+    "ev_last_timing",
+]
+
+
+class EvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libev error {code}: {msg}")
+        self.code = code
+
+
+class ev_plan_info(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("chunks", ctypes.c_uint64), ("slots", ctypes.c_uint64),
+                ("max_stack", ctypes.c_uint64), ("plan_bytes", ctypes.c_uint64)]
+
+
+class ev_job(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("table", ctypes.c_int32),
+                ("bytes", ctypes.c_void_p), ("off", ctypes.c_void_p), ("n_trees", ctypes.c_int32),
+                ("parents", ctypes.c_int32),
+                ("mum", ctypes.c_void_p), ("dad", ctypes.c_void_p), ("p", ctypes.c_void_p), ("q", ctypes.c_void_p),
+                ("n_children", ctypes.c_int32), ("size_cap", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libev.so and declare its C signatures (raises if absent)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libev.so not built ({path}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P, i32, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
+    sig = {
+        "ev_create": [ctypes.POINTER(P), ctypes.c_int, P, P, i32, u64, P],
+        "ev_add_cases": [P, P, P, i32, ctypes.POINTER(i32)],
+        "ev_destroy": [P],
+        "ev_last_error": [],
+        "ev_load_trees": [P, P, P, i32, u32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "ev_pop_info": [P, i32, ctypes.POINTER(i32), ctypes.POINTER(u64)],
+        "ev_get_trees": [P, i32, P, P, u64],
+        "ev_free_pop": [P, i32],
+        "ev_eval_fitness": [P, i32, i32, P, P, u32],
+        "ev_crossover": [P, i32, i32, P, P, P, P, i32, u64, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "ev_generation": [P, i32, u64, u64, i32, u64, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "ev_submit": [P, ctypes.POINTER(ev_job), ctypes.POINTER(u64)],
+        "ev_poll": [P, u64, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "ev_wait": [P, u64, ctypes.POINTER(i32)],
+        "ev_result": [P, u64, P, P, i32, ctypes.POINTER(i32)],
+        "ev_job_timing": [P, u64, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)],
+        "ev_get_plan_info": [P, i32, ctypes.POINTER(ev_plan_info)],
+        "ev_set_tuning": [P, u32, u32],
+        "ev_last_timing": [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_char_p if name == "ev_last_error" else ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != EV_OK:
+        raise EvError(rc, (_lib.ev_last_error() or b"").decode(errors="replace"))
+
+
+def _ptr(a) -> int:
+    """Address of a numpy array or a torch tensor."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _is_device(a) -> bool:
+    return (not isinstance(a, np.ndarray)) and getattr(a, "is_cuda", False)
+
+
+# ---------------------------------------------------------------- C names
+
+def ev_create(x, y, device: int = 0, mem_budget: int = 0, stream: int | None = None):
+    lib = load_library()
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.ascontiguousarray(y, np.float32)
+    ctx = ctypes.c_void_p()
+    _check(lib.ev_create(ctypes.byref(ctx), device, _ptr(x), _ptr(y), x.size, mem_budget, stream))
+    return ctx
+
+
+def ev_add_cases(ctx, x, y) -> int:
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.ascontiguousarray(y, np.float32)
+    t = ctypes.c_int32()
+    _check(_lib.ev_add_cases(ctx, _ptr(x), _ptr(y), x.size, ctypes.byref(t)))
+    return t.value
+
+
+def ev_destroy(ctx):
+    _check(_lib.ev_destroy(ctx))
+
+
+def ev_last_error() -> str:
+    return (load_library().ev_last_error() or b"").decode(errors="replace")
+
+
+def ev_load_trees(ctx, buf, off):
+    """buf/off: numpy (host) or torch cuda tensors (device).  Returns a pop."""
+    dev = _is_device(buf)
+    if not dev:
+        buf = np.ascontiguousarray(buf, np.uint8)
+        off = np.ascontiguousarray(off, np.uint64)
+        n = off.size - 1
+    else:
+        n = off.numel() - 1
+    pop = ctypes.c_int32()
+    bad = ctypes.c_int32(-1)
+    rc = _lib.ev_load_trees(ctx, _ptr(buf), _ptr(off), n, EV_DEVICE_PTR if dev else 0, ctypes.byref(pop),
+                            ctypes.byref(bad))
+    if rc != EV_OK:
+        err = EvError(rc, ev_last_error())
+        err.bad_tree = bad.value
+        raise err
+    return pop.value
+
+
+def ev_pop_info(ctx, pop):
+    n = ctypes.c_int32()
+    b = ctypes.c_uint64()
+    _check(_lib.ev_pop_info(ctx, pop, ctypes.byref(n), ctypes.byref(b)))
+    return n.value, b.value
+
+
+def ev_get_trees(ctx, pop):
+    n, total = ev_pop_info(ctx, pop)
+    buf = np.empty(max(total, 1), np.uint8)
+    off = np.empty(n + 1, np.uint64)
+    _check(_lib.ev_get_trees(ctx, pop, _ptr(buf), _ptr(off), buf.size))
+    return buf[:total], off
+
+
+def ev_free_pop(ctx, pop):
+    _check(_lib.ev_free_pop(ctx, pop))
+
+
+def ev_eval_fitness(ctx, pop, table: int = 0, per_case: bool = False, out=None, out_per_case=None):
+    """Host results (numpy) by default; pass torch cuda tensors as out /
+    out_per_case to receive device results without a host copy."""
+    if out is not None:
+        _check(_lib.ev_eval_fitness(ctx, pop, table, _ptr(out), _ptr(out_per_case), EV_OUT_DEVICE))
+        return out, out_per_case
+    n, _ = ev_pop_info(ctx, pop)
+    fit = np.empty(max(n, 1), np.float32)
+    pc = None
+    if per_case:
+        N = _table_n(ctx, table)
+        pc = np.empty((max(n, 1), N), np.float32)
+    _check(_lib.ev_eval_fitness(ctx, pop, table, _ptr(fit), _ptr(pc), 0))
+    return (fit[:n], pc[:n] if pc is not None else None)
+
+
+_table_sizes: dict = {}
+
+
+def _table_n(ctx, table: int) -> int:
+    return _table_sizes[(ctx.value, table)]
+
+
+def ev_crossover(ctx, mums, dads, mum, dad, p, q, size_cap: int = 2**63):
+    mum = np.ascontiguousarray(mum, np.int32)
+    dad = np.ascontiguousarray(dad, np.int32)
+    p = np.ascontiguousarray(p, np.uint64)
+    q = np.ascontiguousarray(q, np.uint64)
+    out = ctypes.c_int32()
+    capped = ctypes.c_int32()
+    _check(_lib.ev_crossover(ctx, mums, dads, _ptr(mum), _ptr(dad), _ptr(p), _ptr(q), mum.size, size_cap,
+                             ctypes.byref(out), ctypes.byref(capped)))
+    return out.value, capped.value
+
+
+def ev_generation(ctx, parents, seed: int, gen: int, tournament: int = 2, size_cap: int = 2**63):
+    out = ctypes.c_int32()
+    capped = ctypes.c_int32()
+    _check(_lib.ev_generation(ctx, parents, seed, gen, tournament, size_cap, ctypes.byref(out), ctypes.byref(capped)))
+    return out.value, capped.value
+
+
+def ev_submit_eval(ctx, buf, off, table: int = 0) -> int:
+    buf = np.ascontiguousarray(buf, np.uint8)
+    off = np.ascontiguousarray(off, np.uint64)
+    j = ev_job(kind=EV_JOB_EVAL, table=table, bytes=_ptr(buf), off=_ptr(off), n_trees=off.size - 1)
+    return ev_submit(ctx, j)
+
+
+def ev_submit_crossover(ctx, parents, mum, dad, p, q, table: int = 0, size_cap: int = 2**63) -> int:
+    mum = np.ascontiguousarray(mum, np.int32)
+    dad = np.ascontiguousarray(dad, np.int32)
+    p = np.ascontiguousarray(p, np.uint64)
+    q = np.ascontiguousarray(q, np.uint64)
+    j = ev_job(kind=EV_JOB_CROSSOVER, table=table, parents=parents, mum=_ptr(mum), dad=_ptr(dad), p=_ptr(p),
+               q=_ptr(q), n_children=mum.size, size_cap=size_cap)
+    return ev_submit(ctx, j)
+
+
+def ev_submit(ctx, job: ev_job) -> int:
+    t = ctypes.c_uint64()
+    _check(_lib.ev_submit(ctx, ctypes.byref(job), ctypes.byref(t)))
+    return t.value
+
+
+def ev_poll(ctx, ticket: int):
+    done = ctypes.c_int32()
+    st = ctypes.c_int32()
+    _check(_lib.ev_poll(ctx, ticket, ctypes.byref(done), ctypes.byref(st)))
+    return bool(done.value), st.value
+
+
+def ev_wait(ctx, ticket: int) -> int:
+    st = ctypes.c_int32()
+    _check(_lib.ev_wait(ctx, ticket, ctypes.byref(st)))
+    return st.value
+
+
+def ev_result(ctx, ticket: int, n: int, N: int, per_case: bool = False):
+    fit = np.empty(max(n, 1), np.float32)
+    pc = np.empty((max(n, 1), N), np.float32) if per_case else None
+    got = ctypes.c_int32()
+    _check(_lib.ev_result(ctx, ticket, _ptr(fit), _ptr(pc), fit.size, ctypes.byref(got)))
+    k = got.value
+    return fit[:k], (pc[:k] if pc is not None else None)
+
+
+def ev_job_timing(ctx, ticket: int):
+    a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(_lib.ev_job_timing(ctx, ticket, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def ev_get_plan_info(ctx, pop) -> dict:
+    info = ev_plan_info()
+    _check(_lib.ev_get_plan_info(ctx, pop, ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in ev_plan_info._fields_}
+
+
+def ev_set_tuning(ctx, chunk: int = 0, lds_depth: int = 0):
+    _check(_lib.ev_set_tuning(ctx, chunk, lds_depth))
+
+
+def ev_last_timing(ctx):
+    a = ctypes.c_float()
+    b = ctypes.c_float()
+    _check(_lib.ev_last_timing(ctx, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+# ------------------------------------------------------------ convenience
+
+class Context:
+    """Owns an ev_ctx; case table 0 is (x, y)."""
+
+    def __init__(self, x, y, device: int = 0, mem_budget: int = 0, stream: int | None = None):
+        self.ctx = ev_create(x, y, device, mem_budget, stream)
+        _table_sizes[(self.ctx.value, 0)] = int(np.asarray(x).size)
+
+    def add_cases(self, x, y) -> int:
+        t = ev_add_cases(self.ctx, x, y)
+        _table_sizes[(self.ctx.value, t)] = int(np.asarray(x).size)
+        return t
+
+    def n_cases(self, table: int = 0) -> int:
+        return _table_sizes[(self.ctx.value, table)]
+
+    def load(self, buf, off) -> int:
+        return ev_load_trees(self.ctx, buf, off)
+
+    def eval(self, pop, table: int = 0, per_case: bool = False):
+        return ev_eval_fitness(self.ctx, pop, table, per_case)
+
+    def close(self):
+        if self.ctx is not None:
+            ev_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

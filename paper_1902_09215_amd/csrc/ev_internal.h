@@ -1,0 +1,61 @@
+// Internal types shared by the libev kernels and the host runtime.
+#pragma once
+#include <stdint.h>
+
+namespace ev {
+
+enum : uint32_t { TOK_ADD = 0, TOK_SUB = 1, TOK_MUL = 2, TOK_DIV = 3, TOK_X = 4, TOK_REF = 5 };
+
+// A work item of the split plan as the structure passes see it.
+struct ChunkIn {
+    uint64_t start;  // first token, offset into the level's sequence
+    uint32_t len;    // tokens
+    uint32_t tree;   // owning tree
+};
+
+struct ChunkStat {
+    uint32_t n_out;   // values written to result slots
+    uint32_t n_frag;  // tokens of the chunk's skeleton fragment
+    uint32_t n_in;    // REF tokens read
+    uint32_t max_m;   // deepest physical operand stack
+    int32_t net;      // sum over tokens of (+1 function, -1 leaf)
+    int32_t minpref;  // minimum of that running sum before a token
+    uint32_t bad;     // a token outside the level's alphabet was seen
+    uint32_t pad;
+};
+
+// A work item as the evaluator sees it (32 bytes).
+struct EvalChunk {
+    uint64_t start;
+    uint32_t len;
+    uint32_t in_end;   // one past the last input slot this chunk reads
+    uint32_t out_end;  // one past the last output slot this chunk writes
+    uint32_t tree;
+    uint32_t pad0, pad1;
+};
+
+struct EvalArgs {
+    const uint8_t* seq;
+    const EvalChunk* chunks;
+    uint32_t n_items;  // chunks * n_cb
+    uint32_t n_cb;     // 64-case blocks per chunk
+    uint32_t* counter;
+    const float* x;
+    int32_t N;
+    uint32_t gstack_entries;  // stack entries per wave in gstack
+    const float* in_res;
+    float* out_res;
+    float* gstack;
+};
+
+static_assert(sizeof(EvalChunk) == 32, "EvalChunk layout");
+
+struct XoPlan {
+    uint64_t mum_off, dad_off;  // tree starts in the parents' buffers
+    uint64_t p, ep, q, eq;      // points and the ends of their subtrees
+    uint64_t child_off, child_len;
+    uint32_t copy_mum;          // child over the size cap: copy of the mum
+    uint32_t pad;
+};
+
+}  // namespace ev

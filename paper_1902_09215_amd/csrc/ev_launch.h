@@ -1,0 +1,24 @@
+// Host-side launchers of the libev kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ev_internal.h"
+
+namespace ev {
+hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
+hipError_t launch_count(const uint8_t* seq, const ChunkIn* in, uint32_t n, ChunkStat* out, uint32_t max_tok,
+                        hipStream_t s);
+hipError_t launch_emit(const uint8_t* seq, const ChunkIn* in, const uint64_t* frag_end, uint32_t n, uint8_t* dst,
+                       hipStream_t s);
+size_t eval_lds_bytes(int D);
+hipError_t eval_occupancy(int D, int* blocks_per_cu);
+hipError_t launch_eval(int D, const EvalArgs& a, uint32_t grid, hipStream_t s);
+hipError_t launch_fitness(const uint64_t* rows, const float* y, int32_t N, uint32_t M, float* fit, float* per_case,
+                          hipStream_t s);
+hipError_t launch_subtree_end(const uint8_t* buf, const uint64_t* base, const uint64_t* pos, uint32_t n,
+                              uint64_t* end_out, hipStream_t s);
+hipError_t launch_xo_copy(const uint8_t* mums, const uint8_t* dads, const XoPlan* plan, uint32_t n,
+                          uint64_t max_child, uint8_t* dst, hipStream_t s);
+hipError_t launch_select(const float* fit, const uint64_t* off, uint32_t M, int32_t k, uint64_t seed, uint64_t gen,
+                         int32_t* mum, int32_t* dad, uint64_t* p, uint64_t* q, hipStream_t s);
+}  // namespace ev

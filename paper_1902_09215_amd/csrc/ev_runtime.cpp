@@ -1,0 +1,819 @@
+// Host runtime of libev: contexts, device populations, the split plan,
+// evaluation, crossover and generations.  See include/ev.h for the ABI.
+#include "ev_runtime.h"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+namespace ev {
+
+thread_local std::string g_err;
+
+ev_status fail(ev_status code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+ev_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(EV_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(x)                                           \
+    do {                                                    \
+        hipError_t e_ = (x);                                \
+        if (e_ != hipSuccess) return hip_fail(e_, #x);      \
+    } while (0)
+
+// ------------------------------------------------------------- memory
+
+ev_status dev_alloc(ev_ctx* c, size_t bytes, void** out)
+{
+    *out = nullptr;
+    if (bytes == 0) bytes = 256;
+    {
+        std::lock_guard<std::mutex> g(c->mem_mu);
+        if (c->budget && c->in_use + bytes > c->budget)
+            return fail(EV_ENOMEM, "memory budget exceeded (%zu + %zu > %zu bytes)", (size_t)c->in_use, bytes,
+                        (size_t)c->budget);
+        c->in_use += bytes;
+    }
+    hipError_t e = hipMalloc(out, bytes);
+    if (e != hipSuccess) {
+        std::lock_guard<std::mutex> g(c->mem_mu);
+        c->in_use -= bytes;
+        *out = nullptr;
+        (void)hipGetLastError();
+        return fail(EV_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    std::lock_guard<std::mutex> g(c->mem_mu);
+    c->sizes[*out] = bytes;
+    return EV_OK;
+}
+
+void dev_free(ev_ctx* c, void* p)
+{
+    if (!p) return;
+    size_t bytes = 0;
+    {
+        std::lock_guard<std::mutex> g(c->mem_mu);
+        auto it = c->sizes.find(p);
+        if (it != c->sizes.end()) {
+            bytes = it->second;
+            c->sizes.erase(it);
+        }
+        c->in_use -= bytes;
+    }
+    (void)hipFree(p);
+}
+
+// ------------------------------------------------------------- plans
+
+void plan_free(ev_ctx* c, Plan& pl)
+{
+    for (auto& L : pl.levels) {
+        if (L.owned) dev_free(c, L.seq);
+        dev_free(c, L.d_chunks);
+    }
+    pl.levels.clear();
+    pl.fin_level.clear();
+    pl.fin_slot.clear();
+}
+
+void rescache_free(ev_ctx* c, ResCache& r)
+{
+    for (float* p : r.res) dev_free(c, p);
+    r.res.clear();
+    dev_free(c, r.d_rows);
+    r.d_rows = nullptr;
+    dev_free(c, r.d_per_case);
+    r.d_per_case = nullptr;
+}
+
+void pop_free(ev_ctx* c, Pop* P)
+{
+    if (!P) return;
+    plan_free(c, P->plan);
+    for (auto& kv : P->res) rescache_free(c, kv.second);
+    P->res.clear();
+    dev_free(c, P->d_bytes);
+    dev_free(c, P->d_off);
+    dev_free(c, P->d_fit);
+    delete P;
+}
+
+// Build the split plan of a population whose bytes are on the device.
+// Level 0 is the trees themselves; each level's chunks produce the next
+// level's skeleton until every tree is one value.
+ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
+{
+    hipStream_t s = x.stream;
+    const int32_t M = P->M;
+    const uint64_t C = c->chunk;
+    Plan& pl = P->plan;
+    pl.chunk = (uint32_t)C;
+    pl.D = c->lds_depth;
+    pl.fin_level.assign(M, -1);
+    pl.fin_slot.assign(M, 0);
+    pl.chunks_total = 0;
+    pl.slots_total = 0;
+    pl.max_stack = 0;
+
+    std::vector<uint64_t> rs(M), rl(M), prev_len(M, 0), ref_base(M, 0);
+    std::vector<char> active(M, 1);
+    for (int32_t t = 0; t < M; t++) {
+        rs[t] = P->h_off[t];
+        rl[t] = P->h_off[t + 1] - P->h_off[t];
+        if (rl[t] == 0) {
+            if (bad_tree) *bad_tree = t;
+            return fail(EV_EMALFORMED, "tree %d is empty", t);
+        }
+    }
+    uint8_t* cur = P->d_bytes;
+    bool cur_owned = false;
+    int level = 0;
+    void* d_in = nullptr;
+    void* d_stat = nullptr;
+    void* d_frag = nullptr;
+    ev_status st = EV_OK;
+    auto cleanup = [&]() {
+        dev_free(c, d_in);
+        dev_free(c, d_stat);
+        dev_free(c, d_frag);
+        d_in = d_stat = d_frag = nullptr;
+    };
+
+    for (;;) {
+        std::vector<ChunkIn> ch;
+        std::vector<uint32_t> tree_first, tree_last;  // chunk ranges per tree (active only)
+        tree_first.assign(M, UINT32_MAX);
+        tree_last.assign(M, 0);
+        for (int32_t t = 0; t < M; t++) {
+            if (!active[t]) continue;
+            const uint64_t len = rl[t];
+            // One work item when the tree is small, or when the last split
+            // did not halve it (a skeleton dense in spine nodes).
+            const bool whole = len <= C || (level > 0 && len * 2 > prev_len[t]);
+            tree_first[t] = (uint32_t)ch.size();
+            if (whole) {
+                if (len > 0xFFFFFFFFull) { cleanup(); return fail(EV_ECAP, "work item of %llu tokens", (unsigned long long)len); }
+                ch.push_back({rs[t], (uint32_t)len, (uint32_t)t});
+            } else {
+                for (uint64_t o = 0; o < len; o += C)
+                    ch.push_back({rs[t] + o, (uint32_t)std::min<uint64_t>(C, len - o), (uint32_t)t});
+            }
+            tree_last[t] = (uint32_t)ch.size() - 1;
+        }
+        const uint32_t n = (uint32_t)ch.size();
+        if (n == 0) break;
+        cleanup();
+        if ((st = dev_alloc(c, n * sizeof(ChunkIn), &d_in)) != EV_OK) return st;
+        if ((st = dev_alloc(c, n * sizeof(ChunkStat), &d_stat)) != EV_OK) { cleanup(); return st; }
+        HIPCHK(hipMemcpyAsync(d_in, ch.data(), n * sizeof(ChunkIn), hipMemcpyHostToDevice, s));
+        HIPCHK(launch_count(cur, (ChunkIn*)d_in, n, (ChunkStat*)d_stat, level == 0 ? TOK_X : TOK_REF, s));
+        std::vector<ChunkStat> cs(n);
+        HIPCHK(hipMemcpyAsync(cs.data(), d_stat, n * sizeof(ChunkStat), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+
+        if (level == 0) {
+            // Sec. 2.2 word: every token fills one open slot and a function
+            // opens two; a tree is valid iff a slot is open before each token
+            // and none after the last.
+            for (int32_t t = 0; t < M; t++) {
+                int64_t open = 1;
+                bool ok = true;
+                for (uint32_t j = tree_first[t]; j <= tree_last[t] && ok; j++) {
+                    if (cs[j].bad || open + cs[j].minpref < 1) ok = false;
+                    open += cs[j].net;
+                }
+                if (!ok || open != 0) {
+                    cleanup();
+                    if (bad_tree) *bad_tree = t;
+                    return fail(EV_EMALFORMED, "tree %d is not a valid prefix tree", t);
+                }
+            }
+        }
+
+        // slot numbering (global over the level's chunks, in sequence order)
+        std::vector<uint64_t> out_end(n), frag_end(n);
+        uint64_t so = 0, sf = 0;
+        uint32_t max_m = 0;
+        for (uint32_t j = 0; j < n; j++) {
+            so += cs[j].n_out;
+            sf += cs[j].n_frag;
+            out_end[j] = so;
+            frag_end[j] = sf;
+            max_m = std::max(max_m, cs[j].max_m);
+        }
+        if (so > 0xFFFFFFF0ull) { cleanup(); return fail(EV_ECAP, "too many intermediate results"); }
+
+        Level L;
+        L.seq = cur;
+        L.owned = cur_owned;
+        L.n_chunks = n;
+        L.n_out = (uint32_t)so;
+        L.max_m = max_m;
+        pl.max_stack = std::max<uint64_t>(pl.max_stack, max_m);
+        pl.chunks_total += n;
+        pl.slots_total += so;
+
+        // eval descriptors, longest first
+        std::vector<EvalChunk> ec(n);
+        for (int32_t t = 0; t < M; t++) {
+            if (tree_first[t] == UINT32_MAX) continue;
+            uint64_t in_run = ref_base[t];
+            for (uint32_t j = tree_first[t]; j <= tree_last[t]; j++) {
+                in_run += cs[j].n_in;
+                ec[j] = EvalChunk{ch[j].start, ch[j].len, (uint32_t)in_run, (uint32_t)out_end[j], (uint32_t)t, 0, 0};
+            }
+        }
+        // every chunk must read only slots the previous level wrote
+        const uint64_t prev_out = pl.levels.empty() ? 0 : pl.levels.back().n_out;
+        for (uint32_t j = 0; j < n; j++) {
+            if (ec[j].in_end > prev_out || (uint64_t)ec[j].in_end < cs[j].n_in) {
+                cleanup();
+                return fail(EV_EDEVICE, "inconsistent split plan at level %d", level);
+            }
+        }
+        std::stable_sort(ec.begin(), ec.end(), [](const EvalChunk& a, const EvalChunk& b) { return a.len > b.len; });
+        void* d_ec = nullptr;
+        if ((st = dev_alloc(c, n * sizeof(EvalChunk), &d_ec)) != EV_OK) { cleanup(); return st; }
+        HIPCHK(hipMemcpyAsync(d_ec, ec.data(), n * sizeof(EvalChunk), hipMemcpyHostToDevice, s));
+        L.d_chunks = (EvalChunk*)d_ec;
+        pl.levels.push_back(L);
+        cur_owned = false;
+
+        // trees finished at this level and the next level's ranges
+        bool any = false;
+        for (int32_t t = 0; t < M; t++) {
+            if (tree_first[t] == UINT32_MAX) continue;
+            const uint32_t j0 = tree_first[t], j1 = tree_last[t];
+            const uint64_t fbeg = frag_end[j0] - cs[j0].n_frag;
+            const uint64_t flen = frag_end[j1] - fbeg;
+            if (flen == 1) {
+                pl.fin_level[t] = level;
+                pl.fin_slot[t] = (uint32_t)(out_end[j1] - 1);
+                active[t] = 0;
+            } else {
+                any = true;
+                prev_len[t] = rl[t];
+                rs[t] = fbeg;
+                rl[t] = flen;
+                ref_base[t] = out_end[j0] - cs[j0].n_out;
+            }
+        }
+        if (!any) break;
+
+        // emit the skeleton of the next level
+        void* d_next = nullptr;
+        if ((st = dev_alloc(c, sf + 64, &d_next)) != EV_OK) { cleanup(); return st; }
+        if ((st = dev_alloc(c, n * sizeof(uint64_t), &d_frag)) != EV_OK) { dev_free(c, d_next); cleanup(); return st; }
+        HIPCHK(hipMemsetAsync(d_next, 0xFF, sf + 64, s));
+        HIPCHK(hipMemcpyAsync(d_frag, frag_end.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        HIPCHK(launch_emit(cur, (ChunkIn*)d_in, (uint64_t*)d_frag, n, (uint8_t*)d_next, s));
+        HIPCHK(hipStreamSynchronize(s));
+        cur = (uint8_t*)d_next;
+        cur_owned = true;
+        level++;
+        if (level > 64) { dev_free(c, d_next); cleanup(); return fail(EV_ECAP, "split plan did not converge"); }
+        // the buffer is owned by the next Level record
+    }
+    cleanup();
+    pl.bytes = 0;
+    for (auto& L : pl.levels) pl.bytes += (uint64_t)L.n_chunks * sizeof(EvalChunk);
+    return EV_OK;
+}
+
+// Make a population from device bytes (takes ownership of d_bytes, also on
+// failure).
+ev_status pop_build(ev_ctx* c, Exec& x, uint8_t* d_bytes, const std::vector<uint64_t>& h_off, Pop** out, int32_t* bad)
+{
+    *out = nullptr;
+    Pop* P = new Pop();
+    P->d_bytes = d_bytes;
+    P->h_off = h_off;
+    P->M = (int32_t)h_off.size() - 1;
+    P->total = h_off.back();
+    ev_status st;
+    if ((st = dev_alloc(c, h_off.size() * sizeof(uint64_t), (void**)&P->d_off)) != EV_OK) { pop_free(c, P); return st; }
+    if ((st = dev_alloc(c, (size_t)std::max(1, P->M) * sizeof(float), (void**)&P->d_fit)) != EV_OK) { pop_free(c, P); return st; }
+    hipError_t e = hipMemcpyAsync(P->d_off, h_off.data(), h_off.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
+                                  x.stream);
+    if (e != hipSuccess) { pop_free(c, P); return hip_fail(e, "upload offsets"); }
+    if ((st = plan_build(c, x, P, bad)) != EV_OK) { pop_free(c, P); return st; }
+    *out = P;
+    return EV_OK;
+}
+
+ev_pop pop_register(ev_ctx* c, Pop* P)
+{
+    std::lock_guard<std::mutex> g(c->pop_mu);
+    const ev_pop id = c->next_pop++;
+    c->pops[id] = P;
+    return id;
+}
+
+Pop* pop_get(ev_ctx* c, ev_pop id)
+{
+    std::lock_guard<std::mutex> g(c->pop_mu);
+    auto it = c->pops.find(id);
+    return it == c->pops.end() ? nullptr : it->second;
+}
+
+// ----------------------------------------------------------- evaluation
+
+ev_status ensure_gstack(ev_ctx* c, Exec& x, size_t bytes)
+{
+    if (bytes <= x.gstack_bytes) return EV_OK;
+    (void)hipStreamSynchronize(x.stream);
+    dev_free(c, x.d_gstack);
+    x.d_gstack = nullptr;
+    x.gstack_bytes = 0;
+    ev_status st = dev_alloc(c, bytes, (void**)&x.d_gstack);
+    if (st == EV_OK) x.gstack_bytes = bytes;
+    return st;
+}
+
+ev_status ensure_counters(ev_ctx* c, Exec& x, size_t n)
+{
+    if (n <= x.n_counters) return EV_OK;
+    (void)hipStreamSynchronize(x.stream);
+    dev_free(c, x.d_counters);
+    x.d_counters = nullptr;
+    x.n_counters = 0;
+    ev_status st = dev_alloc(c, n * sizeof(uint32_t), (void**)&x.d_counters);
+    if (st == EV_OK) x.n_counters = n;
+    return st;
+}
+
+ev_status exec_init(Exec& x, hipStream_t given)
+{
+    if (given) {
+        x.stream = given;
+        x.own_stream = false;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&x.stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+        x.own_stream = true;
+    }
+    (void)hipEventCreate(&x.ev0);
+    (void)hipEventCreate(&x.ev1);
+    (void)hipEventCreate(&x.evi0);
+    (void)hipEventCreate(&x.evi1);
+    return EV_OK;
+}
+
+void exec_free(ev_ctx* c, Exec& x)
+{
+    if (x.stream) (void)hipStreamSynchronize(x.stream);
+    dev_free(c, x.d_gstack);
+    dev_free(c, x.d_counters);
+    x.d_gstack = nullptr;
+    x.d_counters = nullptr;
+    x.gstack_bytes = x.n_counters = 0;
+    if (x.ev0) (void)hipEventDestroy(x.ev0);
+    if (x.ev1) (void)hipEventDestroy(x.ev1);
+    if (x.evi0) (void)hipEventDestroy(x.evi0);
+    if (x.evi1) (void)hipEventDestroy(x.evi1);
+    x.ev0 = x.ev1 = x.evi0 = x.evi1 = nullptr;
+    if (x.own_stream && x.stream) (void)hipStreamDestroy(x.stream);
+    x.stream = nullptr;
+}
+
+ev_status rescache_get(ev_ctx* c, Exec& x, Pop* P, int32_t table, ResCache** out)
+{
+    auto it = P->res.find(table);
+    if (it != P->res.end()) { *out = &it->second; return EV_OK; }
+    ResCache r;
+    const int32_t N = c->tables[table].N;
+    ev_status st;
+    for (auto& L : P->plan.levels) {
+        float* p = nullptr;
+        if ((st = dev_alloc(c, (size_t)std::max<uint32_t>(L.n_out, 1) * N * sizeof(float), (void**)&p)) != EV_OK) {
+            rescache_free(c, r);
+            return st;
+        }
+        r.res.push_back(p);
+    }
+    std::vector<uint64_t> rows(P->M);
+    for (int32_t t = 0; t < P->M; t++)
+        rows[t] = (uint64_t)(uintptr_t)(r.res[P->plan.fin_level[t]] + (size_t)P->plan.fin_slot[t] * N);
+    if ((st = dev_alloc(c, (size_t)std::max(1, P->M) * sizeof(uint64_t), (void**)&r.d_rows)) != EV_OK) {
+        rescache_free(c, r);
+        return st;
+    }
+    hipError_t e = hipMemcpyAsync(r.d_rows, rows.data(), rows.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
+                                  x.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(x.stream);
+    if (e != hipSuccess) { rescache_free(c, r); return hip_fail(e, "upload rows"); }
+    P->res[table] = r;
+    *out = &P->res[table];
+    return EV_OK;
+}
+
+// Queue the evaluation of P on table on c->stream; fit/per_case are device
+// pointers (per_case nullable).
+ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, float* d_per_case, bool timed)
+{
+    const CaseTable& ct = c->tables[table];
+    const int32_t N = ct.N;
+    const uint32_t n_cb = (uint32_t)((N + 63) / 64);
+    const int D = P->plan.D;
+    ResCache* rc = nullptr;
+    ev_status st;
+    if ((st = rescache_get(c, x, P, table, &rc)) != EV_OK) return st;
+    const size_t nl = P->plan.levels.size();
+    if ((st = ensure_counters(c, x, nl)) != EV_OK) return st;
+    // global stack slabs for levels whose stacks can outgrow the LDS ring
+    const uint32_t grid_max = (uint32_t)c->grid_eval[D == 128 ? 1 : 0];
+    size_t need = 0;
+    for (auto& L : P->plan.levels) {
+        if (L.max_m + 16 > (uint32_t)D) {
+            const uint64_t items = (uint64_t)L.n_chunks * n_cb;
+            const uint32_t grid = (uint32_t)std::min<uint64_t>(grid_max, items);
+            need = std::max(need, (size_t)grid * (L.max_m + 16) * 64 * sizeof(float));
+        }
+    }
+    if ((st = ensure_gstack(c, x, need)) != EV_OK) return st;
+    hipStream_t s = x.stream;
+    if (timed) HIPCHK(hipEventRecord(x.ev0, s));
+    HIPCHK(launch_fill_u32(x.d_counters, (uint32_t)nl, 0u, s));
+    for (size_t li = 0; li < nl; li++) {
+        const Level& L = P->plan.levels[li];
+        EvalArgs a;
+        a.seq = L.seq;
+        a.chunks = L.d_chunks;
+        a.n_items = L.n_chunks * n_cb;
+        a.n_cb = n_cb;
+        a.counter = x.d_counters + li;
+        a.x = ct.d_x;
+        a.N = N;
+        a.gstack_entries = L.max_m + 16;
+        a.in_res = li ? rc->res[li - 1] : nullptr;
+        a.out_res = rc->res[li];
+        a.gstack = x.d_gstack;
+        const uint32_t grid = (uint32_t)std::min<uint64_t>(grid_max, a.n_items);
+        if (timed && li == 0) HIPCHK(hipEventRecord(x.evi0, s));
+        HIPCHK(launch_eval(D, a, grid, s));
+        if (timed && li == 0) HIPCHK(hipEventRecord(x.evi1, s));
+    }
+    HIPCHK(launch_fitness(rc->d_rows, ct.d_y, N, (uint32_t)P->M, d_fit, d_per_case, s));
+    if (timed) HIPCHK(hipEventRecord(x.ev1, s));
+    return EV_OK;
+}
+
+// ----------------------------------------------------------- crossover
+
+// Children from explicit parents and points; all arrays on the host.
+ev_status crossover_build(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const int32_t* mum, const int32_t* dad,
+                          const uint64_t* p, const uint64_t* q, int32_t n, uint64_t cap, Pop** out, int32_t* n_capped)
+{
+    hipStream_t s = x.stream;
+    for (int32_t j = 0; j < n; j++) {
+        if (mum[j] < 0 || mum[j] >= mums->M || dad[j] < 0 || dad[j] >= dads->M)
+            return fail(EV_EINVAL, "child %d: parent index out of range", j);
+        const uint64_t nm = mums->h_off[mum[j] + 1] - mums->h_off[mum[j]];
+        const uint64_t nd = dads->h_off[dad[j] + 1] - dads->h_off[dad[j]];
+        if (p[j] >= nm || q[j] >= nd) return fail(EV_EINVAL, "child %d: crossover point out of range", j);
+    }
+    std::vector<uint64_t> qb(2 * (size_t)n), qp(2 * (size_t)n);
+    for (int32_t j = 0; j < n; j++) {
+        qb[j] = mums->h_off[mum[j]];
+        qp[j] = p[j];
+        qb[n + j] = dads->h_off[dad[j]];
+        qp[n + j] = q[j];
+    }
+    void *d_b = nullptr, *d_p = nullptr, *d_e = nullptr, *d_plan = nullptr;
+    auto cleanup = [&]() { dev_free(c, d_b); dev_free(c, d_p); dev_free(c, d_e); dev_free(c, d_plan); };
+    ev_status st;
+    const size_t qn = std::max<size_t>(1, 2 * (size_t)n);
+    if ((st = dev_alloc(c, qn * 8, &d_b)) || (st = dev_alloc(c, qn * 8, &d_p)) || (st = dev_alloc(c, qn * 8, &d_e))) {
+        cleanup();
+        return st;
+    }
+    std::vector<uint64_t> ends(2 * (size_t)n);
+    if (n > 0) {
+        HIPCHK(hipMemcpyAsync(d_b, qb.data(), 2 * (size_t)n * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_p, qp.data(), 2 * (size_t)n * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_subtree_end(mums->d_bytes, (uint64_t*)d_b, (uint64_t*)d_p, (uint32_t)n, (uint64_t*)d_e, s));
+        HIPCHK(launch_subtree_end(dads->d_bytes, (uint64_t*)d_b + n, (uint64_t*)d_p + n, (uint32_t)n,
+                                  (uint64_t*)d_e + n, s));
+        HIPCHK(hipMemcpyAsync(ends.data(), d_e, 2 * (size_t)n * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    std::vector<XoPlan> plan(n);
+    std::vector<uint64_t> off(n + 1, 0);
+    int32_t capped = 0;
+    uint64_t maxlen = 0;
+    for (int32_t j = 0; j < n; j++) {
+        XoPlan& xp = plan[j];
+        const uint64_t nm = mums->h_off[mum[j] + 1] - mums->h_off[mum[j]];
+        xp.mum_off = mums->h_off[mum[j]];
+        xp.dad_off = dads->h_off[dad[j]];
+        xp.p = p[j];
+        xp.ep = ends[j];
+        xp.q = q[j];
+        xp.eq = ends[n + j];
+        const uint64_t len = nm - (xp.ep - xp.p + 1) + (xp.eq - xp.q + 1);
+        xp.copy_mum = len > cap ? 1u : 0u;
+        if (xp.copy_mum) capped++;
+        xp.child_len = xp.copy_mum ? nm : len;
+        xp.child_off = off[j];
+        xp.pad = 0;
+        off[j + 1] = off[j] + xp.child_len;
+        maxlen = std::max(maxlen, xp.child_len);
+    }
+    uint8_t* d_child = nullptr;
+    if ((st = dev_alloc(c, off[n] + 512, (void**)&d_child)) != EV_OK) { cleanup(); return st; }
+    if ((st = dev_alloc(c, std::max<size_t>(1, n) * sizeof(XoPlan), &d_plan)) != EV_OK) {
+        dev_free(c, d_child);
+        cleanup();
+        return st;
+    }
+    if (n > 0) {
+        HIPCHK(hipMemcpyAsync(d_plan, plan.data(), (size_t)n * sizeof(XoPlan), hipMemcpyHostToDevice, s));
+        HIPCHK(launch_xo_copy(mums->d_bytes, dads->d_bytes, (XoPlan*)d_plan, (uint32_t)n, maxlen, d_child, s));
+    }
+    HIPCHK(hipMemsetAsync(d_child + off[n], 0xFF, 512, s));
+    HIPCHK(hipStreamSynchronize(s));
+    cleanup();
+    if (n_capped) *n_capped = capped;
+    return pop_build(c, x, d_child, off, out, nullptr);
+}
+
+}  // namespace ev
+
+// =================================================================== C ABI
+
+using namespace ev;
+
+extern "C" {
+
+const char* ev_last_error(void) { return g_err.c_str(); }
+
+ev_status ev_create(ev_ctx** out, int device, const float* x, const float* y, int32_t n_cases,
+                    uint64_t mem_budget_bytes, void* stream)
+{
+    if (!out || !x || !y || n_cases < 1) return fail(EV_EINVAL, "ev_create: bad arguments");
+    *out = nullptr;
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(EV_EINVAL, "ev_create: no device %d", device);
+    HIPCHK(hipSetDevice(device));
+    ev_ctx* c = new ev_ctx();
+    c->device = device;
+    c->budget = mem_budget_bytes;
+    if (exec_init(c->main, (hipStream_t)stream) != EV_OK) { delete c; return EV_EDEVICE; }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return fail(EV_EDEVICE, "device properties"); }
+    c->num_cus = prop.multiProcessorCount;
+    for (int i = 0; i < 2; i++) {
+        int bpc = 0;
+        if (eval_occupancy(i ? 128 : 64, &bpc) != hipSuccess || bpc < 1) bpc = 1;
+        c->grid_eval[i] = bpc * c->num_cus;
+    }
+    int32_t tid = 0;
+    ev_status st = ev_add_cases(c, x, y, n_cases, &tid);
+    if (st != EV_OK) { ev_destroy(c); return st; }
+    *out = c;
+    return EV_OK;
+}
+
+ev_status ev_add_cases(ev_ctx* c, const float* x, const float* y, int32_t n, int32_t* table)
+{
+    if (!c || !x || !y || n < 1) return fail(EV_EINVAL, "ev_add_cases: bad arguments");
+    HIPCHK(hipSetDevice(c->device));
+    CaseTable t;
+    t.N = n;
+    ev_status st;
+    if ((st = dev_alloc(c, (size_t)n * 4, (void**)&t.d_x)) != EV_OK) return st;
+    if ((st = dev_alloc(c, (size_t)n * 4, (void**)&t.d_y)) != EV_OK) { dev_free(c, t.d_x); return st; }
+    HIPCHK(hipMemcpyAsync(t.d_x, x, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(t.d_y, y, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::lock_guard<std::mutex> g(c->pop_mu);
+    c->tables.push_back(t);
+    if (table) *table = (int32_t)c->tables.size() - 1;
+    return EV_OK;
+}
+
+ev_status ev_destroy(ev_ctx* c)
+{
+    if (!c) return fail(EV_EINVAL, "ev_destroy: NULL context");
+    (void)hipSetDevice(c->device);
+    serve_stop(c);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->pops) pop_free(c, kv.second);
+    c->pops.clear();
+    for (auto& t : c->tables) { dev_free(c, t.d_x); dev_free(c, t.d_y); }
+    exec_free(c, c->main);
+    delete c;
+    return EV_OK;
+}
+
+ev_status ev_load_trees(ev_ctx* c, const uint8_t* bytes, const uint64_t* off, int32_t n, uint32_t flags,
+                        ev_pop* out_pop, int32_t* bad_tree)
+{
+    if (!c || !off || n < 0 || !out_pop) return fail(EV_EINVAL, "ev_load_trees: bad arguments");
+    if (bad_tree) *bad_tree = -1;
+    HIPCHK(hipSetDevice(c->device));
+    std::vector<uint64_t> h_off(n + 1);
+    if (flags & EV_DEVICE_PTR) {
+        HIPCHK(hipMemcpy(h_off.data(), off, (n + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(h_off.data(), off, (n + 1) * sizeof(uint64_t));
+    }
+    if (h_off[0] != 0) return fail(EV_EINVAL, "ev_load_trees: off[0] must be 0");
+    for (int32_t t = 0; t < n; t++) {
+        if (h_off[t + 1] <= h_off[t]) {
+            if (bad_tree) *bad_tree = t;
+            return fail(EV_EMALFORMED, "tree %d is empty or offsets decrease", t);
+        }
+    }
+    const uint64_t total = h_off[n];
+    if (total > 0 && !bytes) return fail(EV_EINVAL, "ev_load_trees: NULL bytes");
+    uint8_t* d = nullptr;
+    ev_status st = dev_alloc(c, total + 512, (void**)&d);
+    if (st != EV_OK) return st;
+    hipError_t e = hipMemcpyAsync(d, bytes, total, (flags & EV_DEVICE_PTR) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d + total, 0xFF, 512, c->stream);
+    if (e != hipSuccess) { dev_free(c, d); return hip_fail(e, "upload trees"); }
+    Pop* P = nullptr;
+    ev_status st2 = pop_build(c, c->main, d, h_off, &P, bad_tree);
+    if (st2 != EV_OK) return st2;
+    *out_pop = pop_register(c, P);
+    return EV_OK;
+}
+
+ev_status ev_pop_info(ev_ctx* c, ev_pop pop, int32_t* n_trees, uint64_t* total_bytes)
+{
+    if (!c) return fail(EV_EINVAL, "NULL context");
+    Pop* P = pop_get(c, pop);
+    if (!P) return fail(EV_ENOTFOUND, "no population %d", pop);
+    if (n_trees) *n_trees = P->M;
+    if (total_bytes) *total_bytes = P->total;
+    return EV_OK;
+}
+
+ev_status ev_get_trees(ev_ctx* c, ev_pop pop, uint8_t* bytes, uint64_t* off, uint64_t cap_bytes)
+{
+    if (!c) return fail(EV_EINVAL, "NULL context");
+    Pop* P = pop_get(c, pop);
+    if (!P) return fail(EV_ENOTFOUND, "no population %d", pop);
+    if (cap_bytes < P->total || (!bytes && P->total) || !off) return fail(EV_EINVAL, "ev_get_trees: buffer too small");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (P->total) HIPCHK(hipMemcpy(bytes, P->d_bytes, P->total, hipMemcpyDeviceToHost));
+    std::memcpy(off, P->h_off.data(), P->h_off.size() * sizeof(uint64_t));
+    return EV_OK;
+}
+
+ev_status ev_free_pop(ev_ctx* c, ev_pop pop)
+{
+    if (!c) return fail(EV_EINVAL, "NULL context");
+    Pop* P = nullptr;
+    {
+        std::lock_guard<std::mutex> g(c->pop_mu);
+        auto it = c->pops.find(pop);
+        if (it == c->pops.end()) return fail(EV_ENOTFOUND, "no population %d", pop);
+        P = it->second;
+        c->pops.erase(it);
+    }
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    pop_free(c, P);
+    return EV_OK;
+}
+
+ev_status ev_eval_fitness(ev_ctx* c, ev_pop pop, int32_t table, float* fitness, float* per_case, uint32_t flags)
+{
+    if (!c || !fitness) return fail(EV_EINVAL, "ev_eval_fitness: bad arguments");
+    Pop* P = pop_get(c, pop);
+    if (!P) return fail(EV_ENOTFOUND, "no population %d", pop);
+    if (table < 0 || table >= (int32_t)c->tables.size()) return fail(EV_EINVAL, "no case table %d", table);
+    HIPCHK(hipSetDevice(c->device));
+    const int32_t N = c->tables[table].N;
+    float* d_pc = nullptr;
+    if (per_case) {
+        if (flags & EV_OUT_DEVICE) {
+            d_pc = per_case;
+        } else {
+            ResCache* rc = nullptr;
+            ev_status st = rescache_get(c, c->main, P, table, &rc);
+            if (st != EV_OK) return st;
+            if (!rc->d_per_case) {
+                st = dev_alloc(c, (size_t)std::max(1, P->M) * N * sizeof(float), (void**)&rc->d_per_case);
+                if (st != EV_OK) return st;
+            }
+            d_pc = rc->d_per_case;
+        }
+    }
+    ev_status st = eval_enqueue(c, c->main, P, table, P->d_fit, d_pc, true);
+    if (st != EV_OK) return st;
+    P->fit_valid = true;
+    if (flags & EV_OUT_DEVICE) {
+        if (P->M) HIPCHK(hipMemcpyAsync(fitness, P->d_fit, (size_t)P->M * 4, hipMemcpyDeviceToDevice, c->stream));
+        return EV_OK;
+    }
+    if (P->M) HIPCHK(hipMemcpyAsync(fitness, P->d_fit, (size_t)P->M * 4, hipMemcpyDeviceToHost, c->stream));
+    if (per_case && P->M)
+        HIPCHK(hipMemcpyAsync(per_case, d_pc, (size_t)P->M * N * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return EV_OK;
+}
+
+ev_status ev_crossover(ev_ctx* c, ev_pop mums_pop, ev_pop dads_pop, const int32_t* mum, const int32_t* dad,
+                       const uint64_t* p, const uint64_t* q, int32_t n, uint64_t size_cap, ev_pop* out,
+                       int32_t* n_capped)
+{
+    if (!c || n < 0 || !out || (n > 0 && (!mum || !dad || !p || !q))) return fail(EV_EINVAL, "ev_crossover: bad arguments");
+    Pop* A = pop_get(c, mums_pop);
+    Pop* B = pop_get(c, dads_pop);
+    if (!A || !B) return fail(EV_ENOTFOUND, "ev_crossover: unknown population");
+    HIPCHK(hipSetDevice(c->device));
+    Pop* C = nullptr;
+    ev_status st = crossover_build(c, c->main, A, B, mum, dad, p, q, n, size_cap, &C, n_capped);
+    if (st != EV_OK) return st;
+    *out = pop_register(c, C);
+    return EV_OK;
+}
+
+ev_status ev_generation(ev_ctx* c, ev_pop parents, uint64_t seed, uint64_t gen, int32_t tournament,
+                        uint64_t size_cap, ev_pop* out, int32_t* n_capped)
+{
+    if (!c || !out || tournament < 1) return fail(EV_EINVAL, "ev_generation: bad arguments");
+    Pop* P = pop_get(c, parents);
+    if (!P) return fail(EV_ENOTFOUND, "no population %d", parents);
+    if (!P->fit_valid) return fail(EV_EINVAL, "ev_generation: parents have no fitness yet");
+    HIPCHK(hipSetDevice(c->device));
+    const int32_t M = P->M;
+    void* d_sel = nullptr;
+    ev_status st = dev_alloc(c, (size_t)std::max(1, M) * 24, &d_sel);
+    if (st != EV_OK) return st;
+    int32_t* d_mum = (int32_t*)d_sel;
+    int32_t* d_dad = d_mum + std::max(1, M);
+    uint64_t* d_p = (uint64_t*)((char*)d_sel + (size_t)std::max(1, M) * 8);
+    uint64_t* d_q = d_p + std::max(1, M);
+    std::vector<int32_t> mum(M), dad(M);
+    std::vector<uint64_t> p(M), q(M);
+    hipError_t e = launch_select(P->d_fit, P->d_off, (uint32_t)M, tournament, seed, gen, d_mum, d_dad, d_p, d_q, c->stream);
+    if (e == hipSuccess && M) e = hipMemcpyAsync(mum.data(), d_mum, M * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && M) e = hipMemcpyAsync(dad.data(), d_dad, M * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && M) e = hipMemcpyAsync(p.data(), d_p, M * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && M) e = hipMemcpyAsync(q.data(), d_q, M * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dev_free(c, d_sel);
+    if (e != hipSuccess) return hip_fail(e, "selection");
+    Pop* C = nullptr;
+    st = crossover_build(c, c->main, P, P, mum.data(), dad.data(), p.data(), q.data(), M, size_cap, &C, n_capped);
+    if (st != EV_OK) return st;
+    *out = pop_register(c, C);
+    return EV_OK;
+}
+
+ev_status ev_get_plan_info(ev_ctx* c, ev_pop pop, ev_plan_info* info)
+{
+    if (!c || !info) return fail(EV_EINVAL, "bad arguments");
+    Pop* P = pop_get(c, pop);
+    if (!P) return fail(EV_ENOTFOUND, "no population %d", pop);
+    info->levels = (int32_t)P->plan.levels.size();
+    info->chunks = P->plan.chunks_total;
+    info->slots = P->plan.slots_total;
+    info->max_stack = P->plan.max_stack;
+    info->plan_bytes = P->plan.bytes;
+    return EV_OK;
+}
+
+ev_status ev_set_tuning(ev_ctx* c, uint32_t chunk, uint32_t lds_depth)
+{
+    if (!c) return fail(EV_EINVAL, "NULL context");
+    if (lds_depth != 0 && lds_depth != 64 && lds_depth != 128) return fail(EV_EINVAL, "lds_depth must be 64 or 128");
+    if (chunk != 0 && chunk < 64) return fail(EV_EINVAL, "chunk must be at least 64 tokens");
+    if (chunk) c->chunk = chunk;
+    if (lds_depth) c->lds_depth = (int)lds_depth;
+    return EV_OK;
+}
+
+ev_status ev_last_timing(ev_ctx* c, float* eval_ms, float* interp_ms)
+{
+    if (!c) return fail(EV_EINVAL, "NULL context");
+    HIPCHK(hipEventSynchronize(c->main.ev1));
+    float a = 0, b = 0;
+    HIPCHK(hipEventElapsedTime(&a, c->main.ev0, c->main.ev1));
+    HIPCHK(hipEventElapsedTime(&b, c->main.evi0, c->main.evi1));
+    if (eval_ms) *eval_ms = a;
+    if (interp_ms) *interp_ms = b;
+    return EV_OK;
+}
+
+}  // extern "C"

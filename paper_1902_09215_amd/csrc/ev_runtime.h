@@ -1,0 +1,130 @@
+// Host-side state of libev.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/ev.h"
+#include "ev_internal.h"
+#include "ev_launch.h"
+
+namespace ev {
+
+struct CaseTable {
+    float* d_x = nullptr;
+    float* d_y = nullptr;
+    int32_t N = 0;
+};
+
+// One level of a population's split plan.
+struct Level {
+    uint8_t* seq = nullptr;  // level 0: the population's bytes; later: skeleton
+    bool owned = false;
+    EvalChunk* d_chunks = nullptr;
+    uint32_t n_chunks = 0;
+    uint32_t n_out = 0;  // result slots written by this level
+    uint32_t max_m = 0;  // deepest physical operand stack of a chunk
+};
+
+struct Plan {
+    std::vector<Level> levels;
+    std::vector<int32_t> fin_level;  // per tree: level holding its value
+    std::vector<uint32_t> fin_slot;  // and the slot
+    uint32_t chunk = 0;
+    int D = 64;
+    uint64_t chunks_total = 0, slots_total = 0, max_stack = 0, bytes = 0;
+};
+
+// Intermediate results of one population for one case table.
+struct ResCache {
+    std::vector<float*> res;     // per level: n_out * N floats
+    uint64_t* d_rows = nullptr;  // per tree: address of its N final values
+    float* d_per_case = nullptr;
+};
+
+struct Pop {
+    uint8_t* d_bytes = nullptr;
+    uint64_t* d_off = nullptr;
+    std::vector<uint64_t> h_off;
+    int32_t M = 0;
+    uint64_t total = 0;
+    Plan plan;
+    float* d_fit = nullptr;
+    bool fit_valid = false;
+    std::map<int32_t, ResCache> res;
+};
+
+// Per-thread execution resources: a stream and the scratch its launches use.
+struct Exec {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint32_t* d_counters = nullptr;
+    size_t n_counters = 0;
+    float* d_gstack = nullptr;
+    size_t gstack_bytes = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, evi0 = nullptr, evi1 = nullptr;
+};
+
+struct Job;
+struct Serve;
+
+}  // namespace ev
+
+struct ev_ctx {
+    int device = 0;
+    int num_cus = 0;
+    int grid_eval[2] = {0, 0};
+    uint32_t chunk = 4096;
+    int lds_depth = 64;
+
+    ev::Exec main;
+    hipStream_t& stream = main.stream;  // the context's stream for the synchronous calls
+
+    std::mutex mem_mu;
+    uint64_t budget = 0, in_use = 0;
+    std::unordered_map<void*, size_t> sizes;
+
+    std::mutex pop_mu;
+    std::vector<ev::CaseTable> tables;
+    std::map<ev_pop, ev::Pop*> pops;
+    ev_pop next_pop = 1;
+
+    ev::Serve* serve = nullptr;
+    std::mutex serve_init_mu;
+};
+
+namespace ev {
+
+extern thread_local std::string g_err;
+ev_status fail(ev_status code, const char* fmt, ...);
+ev_status hip_fail(hipError_t e, const char* what);
+
+ev_status dev_alloc(ev_ctx* c, size_t bytes, void** out);
+void dev_free(ev_ctx* c, void* p);
+
+ev_status exec_init(Exec& x, hipStream_t given);
+void exec_free(ev_ctx* c, Exec& x);
+
+void pop_free(ev_ctx* c, Pop* P);
+ev_status pop_build(ev_ctx* c, Exec& x, uint8_t* d_bytes, const std::vector<uint64_t>& h_off, Pop** out,
+                    int32_t* bad);
+ev_pop pop_register(ev_ctx* c, Pop* P);
+Pop* pop_get(ev_ctx* c, ev_pop id);
+
+ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, float* d_per_case, bool timed);
+ev_status crossover_build(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const int32_t* mum, const int32_t* dad,
+                          const uint64_t* p, const uint64_t* q, int32_t n, uint64_t cap, Pop** out,
+                          int32_t* n_capped);
+
+void serve_stop(ev_ctx* c);
+
+}  // namespace ev

@@ -1,0 +1,277 @@
+"""GPU parity: libev (HIP, through the C ABI) against the oracle, bit for bit.
+
+Floating-point results must match at 0 ULP (or both be NaN: NaN payloads
+differ between x86 and AMD), because both sides apply the same binary32
+operations to the same operands in the same order and reduce the fitness
+in ascending case order.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+ADD, SUB, MUL, DIV, X = 0, 1, 2, 3, 4
+
+
+def same_bits(a, b):
+    a = np.asarray(a, np.float32)
+    b = np.asarray(b, np.float32)
+    return (a.view(np.uint32) == b.view(np.uint32)) | (np.isnan(a) & np.isnan(b))
+
+
+def assert_same(got, want, what=""):
+    ok = same_bits(got, want)
+    if not ok.all():
+        idx = np.argwhere(~ok)[:5]
+        raise AssertionError(f"{what}: {int((~ok).sum())} mismatches, first {idx.tolist()}: "
+                             f"got {np.asarray(got)[tuple(idx.T)]} want {np.asarray(want)[tuple(idx.T)]}")
+
+
+@pytest.fixture(scope="module")
+def ev():
+    import paper_1902_09215_amd as ev
+
+    ev.load_library()
+    return ev
+
+
+def run(ev, buf, off, x, y, chunk=0, lds=0, per_case=True):
+    with ev.Context(x, y) as c:
+        if chunk or lds:
+            ev.ev_set_tuning(c.ctx, chunk, lds)
+        pop = c.load(buf, off)
+        info = ev.ev_get_plan_info(c.ctx, pop)
+        fit, pc = c.eval(pop, per_case=per_case)
+    return fit, pc, info
+
+
+def check(ev, buf, off, x, y, chunk=0, lds=0, threads=8, what=""):
+    want_fit, want_pc = oracle.eval_population(buf, off, x, y, threads=threads, per_case=True)
+    fit, pc, info = run(ev, buf, off, x, y, chunk, lds)
+    assert_same(pc, want_pc, f"per-case {what}")
+    assert_same(fit, want_fit, f"fitness {what}")
+    return info
+
+
+def test_tiny_rhh_population(ev):
+    x, y = workloads.cases(48)
+    buf, off = workloads.rhh_population(workloads.SEED_BASE + 1, 100, 2, 6)
+    print("tiny rhh: 100 trees", flush=True)
+    check(ev, buf, off, x, y, what="tiny")
+
+
+@pytest.mark.parametrize("chunk", [64, 256, 4096, 1 << 20])
+@pytest.mark.parametrize("lds", [64, 128])
+def test_split_invariance(ev, chunk, lds):
+    x, y = workloads.cases(48)
+    sizes = workloads.loguniform_sizes(77, 150, 1, 40000)
+    buf, off = workloads.random_population(77, sizes)
+    print(f"split chunk={chunk} lds={lds} nodes={int(off[-1])}", flush=True)
+    info = check(ev, buf, off, x, y, chunk=chunk, lds=lds, what=f"chunk {chunk} lds {lds}")
+    if chunk <= 4096:
+        assert info["levels"] >= 2
+
+
+def test_deep_stacks_spill_to_memory(ev):
+    # (((x+x)*x)-x)... leans left: the right-to-left stack holds every leaf
+    x, y = workloads.cases(48)
+    trees = []
+    for k, op_cycle in ((3000, [ADD, MUL, SUB, DIV]), (700, [DIV, SUB]), (129, [MUL])):
+        ops = [op_cycle[i % len(op_cycle)] for i in range(k)]
+        trees.append(np.array(ops + [X] * (k + 1), np.uint8))
+        trees.append(np.array(sum(([o, X] for o in ops), []) + [X], np.uint8))  # leans right
+    sizes = [t.size for t in trees]
+    off = workloads.offsets_from_sizes(sizes)
+    buf = np.concatenate(trees)
+    print("deep stacks", flush=True)
+    for chunk, lds in ((1 << 20, 64), (512, 64), (1 << 20, 128), (256, 128)):
+        info = check(ev, buf, off, x, y, chunk=chunk, lds=lds, what=f"deep chunk {chunk} lds {lds}")
+        assert info["max_stack"] >= 128
+
+
+@pytest.mark.parametrize("n_cases", [1, 2, 47, 64, 65, 130, 1024])
+def test_case_counts(ev, n_cases):
+    x, y = workloads.cases(n_cases)
+    sizes = workloads.loguniform_sizes(5, 60, 1, 9000)
+    buf, off = workloads.random_population(5, sizes)
+    print(f"cases N={n_cases}", flush=True)
+    check(ev, buf, off, x, y, chunk=1024, what=f"N={n_cases}")
+
+
+def test_special_inputs(ev):
+    # zero, signed zero, subnormals, huge and infinite inputs drive every
+    # path of protected division and NaN propagation
+    x = np.array([0.0, -0.0, 1e-45, -1e-40, 3.4e38, -3.4e38, np.inf, -np.inf, np.nan, 1.0, -1.0, 0.5,
+                  1e-20, 1e20, 2.0, -3.0], np.float32)
+    y = np.linspace(-1, 1, x.size).astype(np.float32)
+    sizes = workloads.loguniform_sizes(8, 200, 1, 3000)
+    buf, off = workloads.random_population(8, sizes)
+    print("special inputs", flush=True)
+    check(ev, buf, off, x, y, chunk=512, what="special")
+
+
+def test_single_leaf_and_tiny_trees(ev):
+    x, y = workloads.cases(48)
+    trees = [np.array([X], np.uint8), np.array([DIV, X, X], np.uint8), np.array([SUB, X, X], np.uint8),
+             np.array([DIV, X, SUB, X, X], np.uint8)]
+    off = workloads.offsets_from_sizes([t.size for t in trees])
+    buf = np.concatenate(trees)
+    check(ev, buf, off, x, y, what="tiny trees")
+
+
+def test_batched_workload_full_size(ev):
+    # 4000 trees, 10..1e5 nodes (~4.3e7 nodes), in the launch configuration
+    # the benchmark uses
+    buf, off, n = workloads.workload("batched")
+    x, y = workloads.cases(n)
+    print(f"batched: {int(off[-1])} nodes", flush=True)
+    want_fit = oracle.eval_population(buf, off, x, y, threads=16)
+    fit, _, info = run(ev, buf, off, x, y, per_case=False)
+    assert_same(fit, want_fit, "batched fitness")
+
+
+def test_repeatable(ev):
+    x, y = workloads.cases(48)
+    sizes = workloads.loguniform_sizes(9, 300, 1, 20000)
+    buf, off = workloads.random_population(9, sizes)
+    with ev.Context(x, y) as c:
+        pop = c.load(buf, off)
+        a, pa = c.eval(pop, per_case=True)
+        b, pb = c.eval(pop, per_case=True)
+    assert_same(a, b, "repeat fitness")
+    assert_same(pa, pb, "repeat per-case")
+
+
+def test_malformed_trees_are_rejected(ev):
+    x, y = workloads.cases(48)
+    good = workloads.random_tree(1, 1, 21)
+    cases = {
+        "truncated": good[:-1],
+        "trailing": np.append(good, X),
+        "bad opcode": np.concatenate([good[:5], [7], good[6:]]).astype(np.uint8),
+        "reserved token": np.concatenate([[ADD], [5], [X]]).astype(np.uint8),
+    }
+    with ev.Context(x, y) as c:
+        for name, bad in cases.items():
+            trees = [good, bad, good]
+            off = workloads.offsets_from_sizes([t.size for t in trees])
+            with pytest.raises(ev.EvError) as ei:
+                c.load(np.concatenate(trees).astype(np.uint8), off)
+            assert ei.value.code == ev.EV_EMALFORMED, name
+            assert ei.value.bad_tree == 1, name
+        # an empty tree
+        with pytest.raises(ev.EvError):
+            c.load(good, np.array([0, 0, good.size], np.uint64))
+
+
+def test_crossover_matches_oracle(ev):
+    x, y = workloads.cases(48)
+    rng = np.random.default_rng(31)
+    sizes = workloads.loguniform_sizes(31, 64, 1, 20000)
+    buf, off = workloads.random_population(31, sizes)
+    n = 100
+    mum = rng.integers(0, 64, n).astype(np.int32)
+    dad = rng.integers(0, 64, n).astype(np.int32)
+    p = np.array([rng.integers(0, sizes[m]) for m in mum], np.uint64)
+    q = np.array([rng.integers(0, sizes[d]) for d in dad], np.uint64)
+    cap = int(np.median(sizes)) * 2
+    with ev.Context(x, y) as c:
+        pop = c.load(buf, off)
+        kids, capped = ev.ev_crossover(c.ctx, pop, pop, mum, dad, p, q, cap)
+        cbuf, coff = ev.ev_get_trees(c.ctx, kids)
+        fit, pc = c.eval(kids, per_case=True)
+    want = []
+    n_cap = 0
+    for j in range(n):
+        mt = buf[off[mum[j]]:off[mum[j] + 1]]
+        dt = buf[off[dad[j]]:off[dad[j] + 1]]
+        child = oracle.crossover(mt, dt, int(p[j]), int(q[j]))
+        if child.size > cap:
+            child, n_cap = mt, n_cap + 1
+        want.append(child)
+    assert capped == n_cap
+    woff = workloads.offsets_from_sizes([t.size for t in want])
+    assert np.array_equal(coff, woff)
+    assert np.array_equal(cbuf, np.concatenate(want))
+    wfit, wpc = oracle.eval_population(cbuf, coff, x, y, threads=8, per_case=True)
+    assert_same(fit, wfit, "children fitness")
+    assert_same(pc, wpc, "children per-case")
+
+
+def test_generations_match_oracle(ev):
+    # population 48, size-2 tournament, Philox-drawn points, 15e6-node cap
+    x, y = workloads.cases(48)
+    buf, off = workloads.rhh_population(workloads.SEED_BASE + 4, 48, 2, 6)
+    seed, gens, cap = 20240601, 60, 15_000_000
+    with ev.Context(x, y) as c:
+        pop = c.load(buf, off)
+        fit, _ = c.eval(pop)
+        wfit = oracle.eval_population(buf, off, x, y)
+        assert_same(fit, wfit, "gen 0")
+        for g in range(gens):
+            kids, capped = ev.ev_generation(c.ctx, pop, seed, g, 2, cap)
+            wbuf, woff, wcap = oracle.generation(buf, off, wfit, 2, seed, g, cap)
+            gbuf, goff = ev.ev_get_trees(c.ctx, kids)
+            assert capped == wcap
+            assert np.array_equal(goff, woff), f"gen {g} offsets"
+            assert np.array_equal(gbuf, wbuf), f"gen {g} trees"
+            fit, _ = c.eval(kids)
+            wfit = oracle.eval_population(wbuf, woff, x, y, threads=8)
+            assert_same(fit, wfit, f"gen {g + 1} fitness")
+            ev.ev_free_pop(c.ctx, pop)
+            pop, buf, off = kids, wbuf, woff
+
+
+def test_serving_results_same_alone_and_mixed(ev):
+    x, y = workloads.cases(48)
+    x2, y2 = workloads.cases(1024)
+    rng = np.random.default_rng(41)
+    jobs = []
+    for k in range(24):
+        sizes = workloads.loguniform_sizes(100 + k, int(rng.integers(1, 20)), 1, 50000)
+        b, o = workloads.random_population(100 + k, sizes)
+        jobs.append((b, o, int(k % 3 == 0)))
+    with ev.Context(x, y) as c:
+        t1 = c.add_cases(x2, y2)
+        assert t1 == 1
+        alone = []
+        for b, o, tab in jobs:
+            t = ev.ev_submit_eval(c.ctx, b, o, tab)
+            assert ev.ev_wait(c.ctx, t) == 0
+            alone.append(ev.ev_result(c.ctx, t, o.size - 1, c.n_cases(tab), per_case=True))
+        tickets = [ev.ev_submit_eval(c.ctx, b, o, tab) for b, o, tab in jobs]
+        mixed = []
+        for t, (b, o, tab) in zip(tickets, jobs):
+            assert ev.ev_wait(c.ctx, t) == 0
+            mixed.append(ev.ev_result(c.ctx, t, o.size - 1, c.n_cases(tab), per_case=True))
+    for k, ((fa, pa), (fm, pm), (b, o, tab)) in enumerate(zip(alone, mixed, jobs)):
+        assert_same(fa, fm, f"job {k} fitness alone vs mixed")
+        assert_same(pa, pm, f"job {k} per-case alone vs mixed")
+        xs, ys = (x2, y2) if tab else (x, y)
+        wf = oracle.eval_population(b, o, xs, ys, threads=8)
+        assert_same(fa, wf, f"job {k} vs oracle")
+
+
+def test_serving_crossover_jobs(ev):
+    x, y = workloads.cases(48)
+    rng = np.random.default_rng(43)
+    sizes = workloads.loguniform_sizes(43, 32, 1, 5000)
+    buf, off = workloads.random_population(43, sizes)
+    with ev.Context(x, y) as c:
+        pop = c.load(buf, off)
+        n = 20
+        mum = rng.integers(0, 32, n).astype(np.int32)
+        dad = rng.integers(0, 32, n).astype(np.int32)
+        p = np.array([rng.integers(0, sizes[m]) for m in mum], np.uint64)
+        q = np.array([rng.integers(0, sizes[d]) for d in dad], np.uint64)
+        t = ev.ev_submit_crossover(c.ctx, pop, mum, dad, p, q)
+        assert ev.ev_wait(c.ctx, t) == 0
+        fit, _ = ev.ev_result(c.ctx, t, n, 48)
+    kids = [oracle.crossover(buf[off[m]:off[m + 1]], buf[off[d]:off[d + 1]], int(pp), int(qq))
+            for m, d, pp, qq in zip(mum, dad, p, q)]
+    koff = workloads.offsets_from_sizes([k.size for k in kids])
+    wf = oracle.eval_population(np.concatenate(kids), koff, x, y)
+    assert_same(fit, wf, "served crossover")
