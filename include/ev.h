@@ -200,10 +200,12 @@ typedef struct {
 ev_status ev_get_plan_info(ev_ctx *ctx, ev_pop pop, ev_plan_info *info);
 
 /* Tuning knobs (0 keeps the current value): chunk = tokens per work item
- * of the split, lds_depth = operand-stack entries kept in LDS per wave
- * (64 or 128).  Plans made afterwards use them; results never depend on
- * them. */
-ev_status ev_set_tuning(ev_ctx *ctx, uint32_t chunk, uint32_t lds_depth);
+ * of the split, lds_depth = operand-stack entries kept in LDS per wave by
+ * the general interpreter (64 or 128).  flags: EV_TUNE_NO_REGSTACK runs
+ * every work item on the general interpreter instead of the register-stack
+ * one.  Plans made afterwards use them; results never depend on them. */
+#define EV_TUNE_NO_REGSTACK 0x1u
+ev_status ev_set_tuning(ev_ctx *ctx, uint32_t chunk, uint32_t lds_depth, uint32_t flags);
 
 /* Device time in milliseconds of the last ev_eval_fitness on this context
  * (HIP events around the evaluation kernels) and of its dominant kernel

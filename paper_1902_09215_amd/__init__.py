@@ -81,7 +81,7 @@ def load_library(path: str = LIB_PATH):
         "ev_result": [P, u64, P, P, i32, ctypes.POINTER(i32)],
         "ev_job_timing": [P, u64, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)],
         "ev_get_plan_info": [P, i32, ctypes.POINTER(ev_plan_info)],
-        "ev_set_tuning": [P, u32, u32],
+        "ev_set_tuning": [P, u32, u32, u32],
         "ev_last_timing": [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
     }
     for name, args in sig.items():
@@ -275,8 +275,11 @@ def ev_get_plan_info(ctx, pop) -> dict:
     return {k: getattr(info, k) for k, _ in ev_plan_info._fields_}
 
 
-def ev_set_tuning(ctx, chunk: int = 0, lds_depth: int = 0):
-    _check(_lib.ev_set_tuning(ctx, chunk, lds_depth))
+EV_TUNE_NO_REGSTACK = 0x1
+
+
+def ev_set_tuning(ctx, chunk: int = 0, lds_depth: int = 0, flags: int = 0):
+    _check(_lib.ev_set_tuning(ctx, chunk, lds_depth, flags))
 
 
 def ev_last_timing(ctx):

@@ -17,6 +17,12 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location("gen_interp", os.path.join(CSRC, "gen_interp.py"))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    gen.write(os.path.join(CSRC, "ev_interp.inc"))
     out = os.path.join(HERE, "libev.so")
     tmp = out + ".tmp"
     cmd = ["hipcc", *FLAGS, "-o", tmp, *[os.path.join(CSRC, s) for s in SOURCES], "-lpthread"]

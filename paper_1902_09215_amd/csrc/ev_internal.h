@@ -6,6 +6,9 @@ namespace ev {
 
 enum : uint32_t { TOK_ADD = 0, TOK_SUB = 1, TOK_MUL = 2, TOK_DIV = 3, TOK_X = 4, TOK_REF = 5 };
 
+// Register-stack entries of k_run (the interpreter's VGPR window).
+constexpr uint32_t EV_VSTACK_ENTRIES = 64;
+
 // A work item of the split plan as the structure passes see it.
 struct ChunkIn {
     uint64_t start;  // first token, offset into the level's sequence
@@ -21,7 +24,30 @@ struct ChunkStat {
     int32_t net;      // sum over tokens of (+1 function, -1 leaf)
     int32_t minpref;  // minimum of that running sum before a token
     uint32_t bad;     // a token outside the level's alphabet was seen
-    uint32_t pad;
+    uint32_t n_codes; // threaded codes of the chunk (register-stack kernel)
+    uint32_t maxtop;  // highest register-stack index the codes touch
+    uint32_t code_out;  // slot-writing codes (must equal n_out)
+    uint32_t code_in;   // slot-reading codes (must equal n_in)
+};
+
+// A work item of the register-stack kernel (16 bytes).
+struct RunChunk {
+    uint64_t code_begin;  // index of its first code in the level's code stream
+    uint32_t in_end;
+    uint32_t out_end;
+};
+
+struct RunArgs {
+    const uint16_t* codes;
+    const RunChunk* chunks;
+    uint32_t n_items;
+    uint32_t n_cb;
+    uint32_t* counter;
+    const float* x;
+    int32_t N;
+    uint32_t rowb;  // bytes per result slot row (N * 4)
+    const float* in_res;
+    float* out_res;
 };
 
 // A work item as the evaluator sees it (32 bytes).

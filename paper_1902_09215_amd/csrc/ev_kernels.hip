@@ -22,6 +22,7 @@
 #include <stdint.h>
 
 #include "ev_internal.h"
+#include "ev_interp.inc"
 
 namespace ev {
 
@@ -56,6 +57,85 @@ __device__ __forceinline__ float apply_op(uint32_t t, float a, float b)
 // becomes a result slot (or stays an X when it is a bare input), and the
 // spine node itself goes into the skeleton.  At the chunk's first token all
 // values still on the stack become result slots.
+
+// ---------------------------------------------------- threaded-code decode
+//
+// The same right-to-left machine, written for the register-stack kernel:
+//   tv  the top value T is live      P  an X sits on top, not yet placed
+//   m   values below T (T is register-stack entry m)
+// Each action becomes one code; an X is folded into the function or push
+// that consumes it, and a push or load of x directly followed by a function
+// of x becomes one code (op(x, x)).
+
+struct CodeSink {
+    uint16_t* dst;   // nullptr: count only
+    uint64_t at;     // global index of the next code
+    uint32_t n;
+    uint32_t pending;  // EV_K_PUSHX / EV_K_LOADX waiting for fusion, or ~0u
+    uint32_t outs, ins;
+
+    __device__ void put(uint32_t kind)
+    {
+        if (dst) dst[at] = (uint16_t)((uint32_t)(at & (EV_CODE_POS - 1)) * EV_CODE_BLOCK + kind * EV_CODE_STRIDE);
+        at++;
+        n++;
+        outs += (kind == EV_K_OUTT || kind == EV_K_OUTX || kind == EV_K_OUTBOT);
+        ins += (kind == EV_K_PUSHREF || kind == EV_K_LOADREF);
+    }
+    __device__ void emit(uint32_t kind)
+    {
+        if (pending != ~0u) {
+            if (kind >= EV_K_OPX0 && kind <= EV_K_OPX3) {
+                put((pending == EV_K_PUSHX ? EV_K_CH0 : EV_K_LCH0) + (kind - EV_K_OPX0));
+                pending = ~0u;
+                return;
+            }
+            put(pending);
+            pending = ~0u;
+        }
+        if (kind == EV_K_PUSHX || kind == EV_K_LOADX) {
+            pending = kind;
+            return;
+        }
+        put(kind);
+    }
+};
+
+__device__ uint32_t code_machine(const uint8_t* __restrict__ seq, uint64_t start, uint32_t len, CodeSink& o)
+{
+    uint32_t tv = 0, P = 0, m = 0, maxtop = 0;
+    for (uint64_t k = start + len; k-- > start;) {
+        const uint32_t t = seq[k];
+        if (t == TOK_X) {
+            if (!P) P = 1;
+            else if (tv) { o.emit(EV_K_PUSHX); m++; }
+            else { o.emit(EV_K_LOADX); tv = 1; }
+        } else if (t == TOK_REF) {
+            if (P) {
+                if (tv) { o.emit(EV_K_PUSHX); m++; } else { o.emit(EV_K_LOADX); tv = 1; }
+                P = 0;
+            }
+            if (tv) { o.emit(EV_K_PUSHREF); m++; } else { o.emit(EV_K_LOADREF); tv = 1; }
+        } else if (t < TOK_X) {
+            const uint32_t cnt = m + tv + P;
+            if (cnt >= 2) {
+                if (P) { o.emit(EV_K_OPX0 + t); P = 0; } else { o.emit(EV_K_OPS0 + t); m--; }
+            } else {
+                if (cnt == 1 && !P) o.emit(EV_K_OUTT);
+                tv = 0; P = 0; m = 0;
+            }
+        }
+        if (m > maxtop) maxtop = m;
+    }
+    if (m > 0) {
+        o.emit(EV_K_FLUSH);
+        for (uint32_t i = 0; i < m; i++) o.emit(EV_K_OUTBOT);
+    }
+    if (tv) o.emit(EV_K_OUTT);
+    if (P) o.emit(EV_K_OUTX);
+    o.emit(EV_K_END);
+    return maxtop;
+}
 
 struct MachineCounts {
     uint32_t n_out, n_frag, n_in, max_m;
@@ -106,7 +186,13 @@ __global__ void k_count(const uint8_t* __restrict__ seq, const ChunkIn* __restri
     // chunk-start flush: every remaining value becomes a slot
     n_out += cnt;
     n_frag += cnt;
+    CodeSink o{nullptr, 0, 0, ~0u, 0, 0};
+    const uint32_t maxtop = code_machine(seq, c.start, c.len, o);
     ChunkStat s;
+    s.n_codes = o.n;
+    s.maxtop = maxtop;
+    s.code_out = o.outs;
+    s.code_in = o.ins;
     s.n_out = n_out;
     s.n_frag = n_frag;
     s.n_in = n_in;
@@ -114,7 +200,6 @@ __global__ void k_count(const uint8_t* __restrict__ seq, const ChunkIn* __restri
     s.net = R;                                // sum of (+1 function, -1 leaf)
     s.minpref = (c.len ? R - maxR : 0);       // min running sum before a token
     s.bad = bad;
-    s.pad = 0;
     out[ci] = s;
 }
 
@@ -147,6 +232,41 @@ __global__ void k_emit(const uint8_t* __restrict__ seq, const ChunkIn* __restric
         }
     }
     for (uint32_t i = 0; i < cnt; i++) dst[--w] = (uint8_t)TOK_REF;
+}
+
+__global__ void k_decode(const uint8_t* __restrict__ seq, const ChunkIn* __restrict__ in,
+                         const uint64_t* __restrict__ code_begin, uint32_t n, uint16_t* __restrict__ codes)
+{
+    uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ci >= n) return;
+    const uint64_t b = code_begin[ci];
+    if (b == ~0ull) return;  // runs on the general kernel
+    const ChunkIn c = in[ci];
+    CodeSink o{codes, b, 0, ~0u, 0, 0};
+    code_machine(seq, c.start, c.len, o);
+}
+
+// Every code of a register-stack item must name a handler of its own
+// position, the item must end with its only END, and it must write and read
+// exactly the slots the plan gave it; anything else fails the plan before
+// a single code runs.
+__global__ void k_check_codes(const uint16_t* __restrict__ codes, const uint64_t* __restrict__ begin,
+                              const uint32_t* __restrict__ expect, uint32_t n, uint32_t* __restrict__ err)
+{
+    const uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ci >= n) return;
+    const uint64_t b = begin[ci];
+    const uint32_t len = expect[3 * ci], want_out = expect[3 * ci + 1], want_in = expect[3 * ci + 2];
+    uint32_t outs = 0, ins = 0, bad = len == 0;
+    for (uint32_t i = 0; i < len; i++) {
+        const uint32_t v = codes[b + i];
+        const uint32_t pos = v / EV_CODE_BLOCK, r = v % EV_CODE_BLOCK, kind = r / EV_CODE_STRIDE;
+        if (r % EV_CODE_STRIDE || pos != (uint32_t)((b + i) & (EV_CODE_POS - 1)) || kind > EV_K_END) bad = 1;
+        if ((kind == EV_K_END) != (i + 1 == len)) bad = 1;
+        outs += (kind == EV_K_OUTT || kind == EV_K_OUTX || kind == EV_K_OUTBOT);
+        ins += (kind == EV_K_PUSHREF || kind == EV_K_LOADREF);
+    }
+    if (bad || outs != want_out || ins != want_in) atomicOr(err, 1u);
 }
 
 // ------------------------------------------------------------ evaluation
@@ -455,6 +575,44 @@ __global__ void k_select(const float* __restrict__ fit, const uint64_t* __restri
 
 }  // namespace ev
 
+namespace ev {
+
+// --------------------------------------------------- register-stack kernel
+//
+// One wave runs the threaded codes of one work item (lane = test case); see
+// gen_interp.py for the handlers.  Chunks whose stack would outgrow the
+// register window run on k_eval instead.
+__global__ __launch_bounds__(64) void k_run(RunArgs a)
+{
+    const uint32_t lane = threadIdx.x;
+    const_u4p chunks = (const_u4p)(global_u4p)(const void*)a.chunks;
+    uint32_t item = wave_pop(a.counter);
+    while (item < a.n_items) {
+        const uint32_t next = wave_pop(a.counter);
+        const uint32_t ci = item / a.n_cb;
+        const uint32_t cb = item - ci * a.n_cb;
+        const u32x4 d = chunks[ci];
+        const uint64_t code_begin = (uint64_t)d.x | ((uint64_t)d.y << 32);
+        const int32_t cs = (int32_t)(cb * 64u + lane);
+        if (cs < a.N) {
+            const float xv = a.x[cs];
+            const uint32_t lane4 = (uint32_t)cs * 4u;
+            const uint64_t cptr = (uint64_t)(uintptr_t)a.codes + (code_begin & ~(uint64_t)31) * 2u;
+            const uint32_t j0 = (uint32_t)(code_begin & 31u);
+            const uint64_t inp = (uint64_t)(uintptr_t)a.in_res + (uint64_t)d.z * a.rowb;
+            const uint64_t outp = (uint64_t)(uintptr_t)a.out_res + (uint64_t)d.w * a.rowb;
+            asm volatile(EV_INTERP_ASM
+                         :
+                         : [x] "v"(xv), [lane4] "v"(lane4), [cptr] "s"(cptr), [j0] "s"(j0), [inp] "s"(inp),
+                           [outp] "s"(outp), [rowb] "s"(a.rowb)
+                         : EV_INTERP_CLOBBERS);
+        }
+        item = next;
+    }
+}
+
+}  // namespace ev
+
 // ------------------------------------------------------------ launchers
 
 namespace ev {
@@ -502,6 +660,34 @@ hipError_t launch_eval(int D, const EvalArgs& a, uint32_t grid, hipStream_t s)
         hipLaunchKernelGGL(k_eval<128>, dim3(grid), dim3(64), eval_lds_bytes(128), s, a);
     else
         hipLaunchKernelGGL(k_eval<64>, dim3(grid), dim3(64), eval_lds_bytes(64), s, a);
+    return hipGetLastError();
+}
+
+hipError_t run_occupancy(int* blocks_per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, reinterpret_cast<const void*>(&k_run), 64, 0);
+}
+
+hipError_t launch_run(const RunArgs& a, uint32_t grid, hipStream_t s)
+{
+    if (a.n_items == 0 || grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_run, dim3(grid), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_decode(const uint8_t* seq, const ChunkIn* in, const uint64_t* code_begin, uint32_t n, uint16_t* codes,
+                         hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_decode, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, in, code_begin, n, codes);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_codes(const uint16_t* codes, const uint64_t* begin, const uint32_t* expect, uint32_t n,
+                              uint32_t* err, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_codes, dim3(cdiv(n, 64)), dim3(64), 0, s, codes, begin, expect, n, err);
     return hipGetLastError();
 }
 

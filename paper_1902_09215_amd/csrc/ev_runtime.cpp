@@ -83,6 +83,8 @@ void plan_free(ev_ctx* c, Plan& pl)
     for (auto& L : pl.levels) {
         if (L.owned) dev_free(c, L.seq);
         dev_free(c, L.d_chunks);
+        dev_free(c, L.codes);
+        dev_free(c, L.d_run);
     }
     pl.levels.clear();
     pl.fin_level.clear();
@@ -204,25 +206,39 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         }
 
         // slot numbering (global over the level's chunks, in sequence order)
-        std::vector<uint64_t> out_end(n), frag_end(n);
-        uint64_t so = 0, sf = 0;
-        uint32_t max_m = 0;
+        // and the split of the work items between the two kernels
+        std::vector<uint64_t> out_end(n), frag_end(n), code_begin(n, ~0ull);
+        std::vector<char> fast(n, 0);
+        uint64_t so = 0, sf = 0, sc = 0, tokens = 0;
+        uint32_t max_m = 0, n_fast = 0;
         for (uint32_t j = 0; j < n; j++) {
             so += cs[j].n_out;
             sf += cs[j].n_frag;
             out_end[j] = so;
             frag_end[j] = sf;
-            max_m = std::max(max_m, cs[j].max_m);
+            tokens += ch[j].len;
+            if (cs[j].code_out != cs[j].n_out || cs[j].code_in != cs[j].n_in) {
+                cleanup();
+                return fail(EV_EDEVICE, "internal: code stream of work item %u disagrees with the split plan", j);
+            }
+            fast[j] = c->use_run && cs[j].maxtop + 1 <= EV_VSTACK_ENTRIES;
+            if (fast[j]) {
+                code_begin[j] = sc;
+                sc += cs[j].n_codes;
+                n_fast++;
+            } else {
+                max_m = std::max(max_m, cs[j].max_m);
+            }
         }
         if (so > 0xFFFFFFF0ull) { cleanup(); return fail(EV_ECAP, "too many intermediate results"); }
 
         Level L;
         L.seq = cur;
         L.owned = cur_owned;
-        L.n_chunks = n;
         L.n_out = (uint32_t)so;
         L.max_m = max_m;
-        pl.max_stack = std::max<uint64_t>(pl.max_stack, max_m);
+        L.tokens = tokens;
+        for (uint32_t j = 0; j < n; j++) pl.max_stack = std::max<uint64_t>(pl.max_stack, cs[j].maxtop + 1);
         pl.chunks_total += n;
         pl.slots_total += so;
 
@@ -244,13 +260,66 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
                 return fail(EV_EDEVICE, "inconsistent split plan at level %d", level);
             }
         }
-        std::stable_sort(ec.begin(), ec.end(), [](const EvalChunk& a, const EvalChunk& b) { return a.len > b.len; });
-        void* d_ec = nullptr;
-        if ((st = dev_alloc(c, n * sizeof(EvalChunk), &d_ec)) != EV_OK) { cleanup(); return st; }
-        HIPCHK(hipMemcpyAsync(d_ec, ec.data(), n * sizeof(EvalChunk), hipMemcpyHostToDevice, s));
-        L.d_chunks = (EvalChunk*)d_ec;
-        pl.levels.push_back(L);
+        // register-stack items: threaded codes; the rest: k_eval descriptors
+        std::vector<EvalChunk> slow;
+        std::vector<std::pair<uint32_t, RunChunk>> run;
+        for (uint32_t j = 0; j < n; j++) {
+            if (fast[j]) run.push_back({ec[j].len, RunChunk{code_begin[j], ec[j].in_end, ec[j].out_end}});
+            else slow.push_back(ec[j]);
+        }
+        std::stable_sort(slow.begin(), slow.end(), [](const EvalChunk& a, const EvalChunk& b) { return a.len > b.len; });
+        std::stable_sort(run.begin(), run.end(), [](const std::pair<uint32_t, RunChunk>& a,
+                                                    const std::pair<uint32_t, RunChunk>& b) { return a.first > b.first; });
+        L.n_chunks = (uint32_t)slow.size();
+        L.n_run = (uint32_t)run.size();
+        pl.levels.push_back(L);  // owns what is allocated below, freed with the plan
+        Level& LL = pl.levels.back();
         cur_owned = false;
+        if (!slow.empty()) {
+            if ((st = dev_alloc(c, slow.size() * sizeof(EvalChunk), (void**)&LL.d_chunks)) != EV_OK) { cleanup(); return st; }
+            HIPCHK(hipMemcpyAsync(LL.d_chunks, slow.data(), slow.size() * sizeof(EvalChunk), hipMemcpyHostToDevice, s));
+        }
+        if (!run.empty()) {
+            std::vector<RunChunk> rc(run.size());
+            for (size_t i = 0; i < run.size(); i++) rc[i] = run[i].second;
+            if ((st = dev_alloc(c, rc.size() * sizeof(RunChunk), (void**)&LL.d_run)) != EV_OK) { cleanup(); return st; }
+            if ((st = dev_alloc(c, sc * 2 + 256, (void**)&LL.codes)) != EV_OK) { cleanup(); return st; }
+            void* d_cb = nullptr;
+            if ((st = dev_alloc(c, n * sizeof(uint64_t), &d_cb)) != EV_OK) { cleanup(); return st; }
+            HIPCHK(hipMemcpyAsync(LL.d_run, rc.data(), rc.size() * sizeof(RunChunk), hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(d_cb, code_begin.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemsetAsync((uint8_t*)LL.codes + sc * 2, 0, 256, s));
+            HIPCHK(launch_decode(cur, (ChunkIn*)d_in, (uint64_t*)d_cb, n, LL.codes, s));
+            // validate the emitted codes before anything may run them
+            std::vector<uint64_t> vb;
+            std::vector<uint32_t> ve;
+            for (uint32_t j = 0; j < n; j++) {
+                if (!fast[j]) continue;
+                vb.push_back(code_begin[j]);
+                ve.push_back(cs[j].n_codes);
+                ve.push_back(cs[j].n_out);
+                ve.push_back(cs[j].n_in);
+            }
+            void *d_vb = nullptr, *d_ve = nullptr, *d_err = nullptr;
+            if ((st = dev_alloc(c, vb.size() * 8, &d_vb)) || (st = dev_alloc(c, ve.size() * 4, &d_ve)) ||
+                (st = dev_alloc(c, 4, &d_err))) {
+                dev_free(c, d_vb); dev_free(c, d_ve); dev_free(c, d_cb); cleanup();
+                return st;
+            }
+            uint32_t err = 0;
+            HIPCHK(hipMemcpyAsync(d_vb, vb.data(), vb.size() * 8, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(d_ve, ve.data(), ve.size() * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(d_err, &err, 4, hipMemcpyHostToDevice, s));
+            HIPCHK(launch_check_codes(LL.codes, (uint64_t*)d_vb, (uint32_t*)d_ve, (uint32_t)vb.size(), (uint32_t*)d_err, s));
+            HIPCHK(hipMemcpyAsync(&err, d_err, 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            dev_free(c, d_vb);
+            dev_free(c, d_ve);
+            dev_free(c, d_err);
+            dev_free(c, d_cb);
+            if (err) { cleanup(); return fail(EV_EDEVICE, "internal: malformed code stream at level %d", level); }
+        }
+        pl.chunks_total += 0;
 
         // trees finished at this level and the next level's ranges
         bool any = false;
@@ -289,7 +358,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
     }
     cleanup();
     pl.bytes = 0;
-    for (auto& L : pl.levels) pl.bytes += (uint64_t)L.n_chunks * sizeof(EvalChunk);
+    for (auto& L : pl.levels) pl.bytes += (uint64_t)L.n_chunks * sizeof(EvalChunk) + (uint64_t)L.n_run * sizeof(RunChunk);
     return EV_OK;
 }
 
@@ -432,12 +501,12 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
     ev_status st;
     if ((st = rescache_get(c, x, P, table, &rc)) != EV_OK) return st;
     const size_t nl = P->plan.levels.size();
-    if ((st = ensure_counters(c, x, nl)) != EV_OK) return st;
+    if ((st = ensure_counters(c, x, 2 * nl)) != EV_OK) return st;
     // global stack slabs for levels whose stacks can outgrow the LDS ring
     const uint32_t grid_max = (uint32_t)c->grid_eval[D == 128 ? 1 : 0];
     size_t need = 0;
     for (auto& L : P->plan.levels) {
-        if (L.max_m + 16 > (uint32_t)D) {
+        if (L.n_chunks && L.max_m + 16 > (uint32_t)D) {
             const uint64_t items = (uint64_t)L.n_chunks * n_cb;
             const uint32_t grid = (uint32_t)std::min<uint64_t>(grid_max, items);
             need = std::max(need, (size_t)grid * (L.max_m + 16) * 64 * sizeof(float));
@@ -446,9 +515,28 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
     if ((st = ensure_gstack(c, x, need)) != EV_OK) return st;
     hipStream_t s = x.stream;
     if (timed) HIPCHK(hipEventRecord(x.ev0, s));
-    HIPCHK(launch_fill_u32(x.d_counters, (uint32_t)nl, 0u, s));
+    HIPCHK(launch_fill_u32(x.d_counters, (uint32_t)(2 * nl), 0u, s));
     for (size_t li = 0; li < nl; li++) {
         const Level& L = P->plan.levels[li];
+        if (timed && li == 0) HIPCHK(hipEventRecord(x.evi0, s));
+        if (L.n_run) {
+            RunArgs r;
+            r.codes = L.codes;
+            r.chunks = L.d_run;
+            r.n_items = L.n_run * n_cb;
+            r.n_cb = n_cb;
+            r.counter = x.d_counters + nl + li;
+            r.x = ct.d_x;
+            r.N = N;
+            r.rowb = (uint32_t)N * 4u;
+            r.in_res = li ? rc->res[li - 1] : nullptr;
+            r.out_res = rc->res[li];
+            HIPCHK(launch_run(r, (uint32_t)std::min<uint64_t>((uint64_t)c->grid_run, r.n_items), s));
+        }
+        if (L.n_chunks == 0) {
+            if (timed && li == 0) HIPCHK(hipEventRecord(x.evi1, s));
+            continue;
+        }
         EvalArgs a;
         a.seq = L.seq;
         a.chunks = L.d_chunks;
@@ -462,7 +550,6 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
         a.out_res = rc->res[li];
         a.gstack = x.d_gstack;
         const uint32_t grid = (uint32_t)std::min<uint64_t>(grid_max, a.n_items);
-        if (timed && li == 0) HIPCHK(hipEventRecord(x.evi0, s));
         HIPCHK(launch_eval(D, a, grid, s));
         if (timed && li == 0) HIPCHK(hipEventRecord(x.evi1, s));
     }
@@ -580,6 +667,11 @@ ev_status ev_create(ev_ctx** out, int device, const float* x, const float* y, in
         int bpc = 0;
         if (eval_occupancy(i ? 128 : 64, &bpc) != hipSuccess || bpc < 1) bpc = 1;
         c->grid_eval[i] = bpc * c->num_cus;
+    }
+    {
+        int bpc = 0;
+        if (run_occupancy(&bpc) != hipSuccess || bpc < 1) bpc = 1;
+        c->grid_run = bpc * c->num_cus;
     }
     int32_t tid = 0;
     ev_status st = ev_add_cases(c, x, y, n_cases, &tid);
@@ -794,9 +886,10 @@ ev_status ev_get_plan_info(ev_ctx* c, ev_pop pop, ev_plan_info* info)
     return EV_OK;
 }
 
-ev_status ev_set_tuning(ev_ctx* c, uint32_t chunk, uint32_t lds_depth)
+ev_status ev_set_tuning(ev_ctx* c, uint32_t chunk, uint32_t lds_depth, uint32_t flags)
 {
     if (!c) return fail(EV_EINVAL, "NULL context");
+    c->use_run = (flags & EV_TUNE_NO_REGSTACK) == 0;
     if (lds_depth != 0 && lds_depth != 64 && lds_depth != 128) return fail(EV_EINVAL, "lds_depth must be 64 or 128");
     if (chunk != 0 && chunk < 64) return fail(EV_EINVAL, "chunk must be at least 64 tokens");
     if (chunk) c->chunk = chunk;

@@ -29,10 +29,14 @@ struct CaseTable {
 struct Level {
     uint8_t* seq = nullptr;  // level 0: the population's bytes; later: skeleton
     bool owned = false;
-    EvalChunk* d_chunks = nullptr;
+    EvalChunk* d_chunks = nullptr;  // work items of the general kernel (k_eval)
     uint32_t n_chunks = 0;
+    uint16_t* codes = nullptr;      // threaded codes of the register-stack items
+    RunChunk* d_run = nullptr;      // work items of the register-stack kernel (k_run)
+    uint32_t n_run = 0;
+    uint64_t tokens = 0;            // tokens over all work items of the level
     uint32_t n_out = 0;  // result slots written by this level
-    uint32_t max_m = 0;  // deepest physical operand stack of a chunk
+    uint32_t max_m = 0;  // deepest physical operand stack of a k_eval item
 };
 
 struct Plan {
@@ -83,6 +87,8 @@ struct ev_ctx {
     int device = 0;
     int num_cus = 0;
     int grid_eval[2] = {0, 0};
+    int grid_run = 0;
+    bool use_run = true;  // register-stack kernel for the items that fit it
     uint32_t chunk = 4096;
     int lds_depth = 64;
 

@@ -1,0 +1,218 @@
+"""Generate the gfx950 threaded-code interpreter used by k_run (ev_interp.inc).
+
+The structure pass (k_decode) turns each work item's tokens into a stream of
+16-bit codes, one per action of the right-to-left stack machine, with the
+leaves folded into the functions that consume them.  A code's value is the
+byte offset of its handler: position * BLOCK + kind * STRIDE, where position
+is the code's index modulo 32.  Handlers are unrolled per position because
+each must pick the next code out of a fixed SGPR of the 64-byte buffer
+s[64:79] (refilled from s[80:95], prefetched one buffer ahead).
+
+Register use inside the block:
+  v[12 + m]       top of the operand stack (T); v[12..12+m-1] the entries
+                  below it, oldest first.  m = s55.  Relative access uses
+                  GPR-index mode (s_set_gpr_idx_on), set once per handler.
+  v4..v10         temporaries (division), v4 also a staging register
+  %[x], %[lane4]  the lane's input value and byte offset (not clobbered)
+  s[40:41] code pointer (64-byte block), s[42:43] handler table base,
+  s[44:45] jump target, s[46:47] call target, s[48:49] return address,
+  s[50:51] input-slot row pointer, s[52:53] output-slot row pointer,
+  s54 row bytes (cases * 4), s55 m, s[56:57] division scratch, s58 code,
+  s59 flush index.
+"""
+from __future__ import annotations
+
+import os
+import sys
+
+STRIDE = 64
+VSTACK = 64  # register-stack entries: v12 .. v12+VSTACK-1
+KINDS = ["OPS0", "OPS1", "OPS2", "OPS3", "OPX0", "OPX1", "OPX2", "OPX3",
+         "CH0", "CH1", "CH2", "CH3", "LCH0", "LCH1", "LCH2", "LCH3",
+         "PUSHX", "LOADX", "PUSHREF", "LOADREF", "OUTT", "OUTX", "FLUSH", "OUTBOT", "END"]
+NK = len(KINDS)
+BLOCK = NK * STRIDE
+POS = 32
+assert POS * BLOCK < 65536
+VOP = {0: "v_add_f32_e32", 1: "v_sub_f32_e32", 2: "v_mul_f32_e32"}
+
+# Correctly rounded binary32 division a/b (the sequence hipcc emits for
+# IEEE-mode division on gfx950), then protection: b != 0 ? a/b : 1.0f.
+# a in v4, b in v5, result in v6.
+DIV_BODY = """\
+  v_div_scale_f32 v6, s[56:57], v5, v5, v4
+  v_rcp_f32_e32 v7, v6
+  v_div_scale_f32 v8, vcc, v4, v5, v4
+  v_fma_f32 v9, -v6, v7, 1.0
+  v_fmac_f32_e32 v7, v9, v7
+  v_mul_f32_e32 v9, v8, v7
+  v_fma_f32 v10, -v6, v9, v8
+  v_fmac_f32_e32 v9, v10, v7
+  v_fma_f32 v6, -v6, v9, v8
+  v_div_fmas_f32 v6, v6, v7, v9
+  v_div_fixup_f32 v6, v6, v5, v4
+  v_cmp_neq_f32_e32 vcc, 0, v5
+  s_nop 1
+  v_cndmask_b32_e32 v6, 1.0, v6, vcc
+"""
+
+
+def dispatch(pos: int) -> list[str]:
+    """Jump to the handler of the code at position pos+1."""
+    nxt = pos + 1
+    if nxt == POS:
+        return ["s_branch .Lrefill%="]
+    word = 64 + nxt // 2
+    ext = f"s_and_b32 s58, s{word}, 0xffff" if nxt % 2 == 0 else f"s_lshr_b32 s58, s{word}, 16"
+    return [ext, "s_add_u32 s44, s42, s58", "s_addc_u32 s45, s43, 0", "s_setpc_b64 s[44:45]"]
+
+
+def call(routine: str) -> list[str]:
+    return [f"s_add_u32 s46, s42, .L{routine}%= - .Ltab%=", "s_addc_u32 s47, s43, 0",
+            "s_swappc_b64 s[48:49], s[46:47]"]
+
+
+def row_dec(lo: int) -> list[str]:
+    return [f"s_sub_u32 s{lo}, s{lo}, s54", f"s_subb_u32 s{lo + 1}, s{lo + 1}, 0"]
+
+
+def handler(kind: str, pos: int) -> list[str]:
+    k = kind
+    body: list[str]
+    if k.startswith("OPS"):
+        op = int(k[3])
+        # T' = op(T, below): dst v[11+m], src0 v[12+m] (T), src1 v[11+m]
+        body = call("divops") if op == 3 else [
+            "s_set_gpr_idx_on s55, gpr_idx(SRC0,SRC1,DST)", f"{VOP[op]} v11, v12, v11", "s_sub_u32 s55, s55, 1"]
+    elif k.startswith("OPX"):
+        op = int(k[3])
+        # T = op(x, T)
+        body = call("divopx") if op == 3 else [
+            "s_set_gpr_idx_on s55, gpr_idx(SRC1,DST)", f"{VOP[op]} v12, %[x], v12"]
+    elif k.startswith("CH"):
+        op = int(k[2])
+        # push T; T = op(x, x)
+        body = call("divch") if op == 3 else [
+            "s_set_gpr_idx_on s55, gpr_idx(DST)", f"{VOP[op]} v13, %[x], %[x]", "s_add_u32 s55, s55, 1"]
+    elif k.startswith("LCH"):
+        op = int(k[3])
+        # T = op(x, x) with no value below
+        body = call("divlch") if op == 3 else [
+            "s_set_gpr_idx_on s55, gpr_idx(DST)", f"{VOP[op]} v12, %[x], %[x]"]
+    elif k == "PUSHX":
+        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v13, %[x]", "s_add_u32 s55, s55, 1"]
+    elif k == "LOADX":
+        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v12, %[x]"]
+    elif k in ("PUSHREF", "LOADREF"):
+        body = ["s_set_gpr_idx_off"] + row_dec(50) + [
+            "global_load_dword v4, %[lane4], s[50:51]", "s_waitcnt vmcnt(0)",
+            "s_set_gpr_idx_on s55, gpr_idx(DST)"]
+        body += ["v_mov_b32_e32 v13, v4", "s_add_u32 s55, s55, 1"] if k == "PUSHREF" else ["v_mov_b32_e32 v12, v4"]
+    elif k == "OUTT":
+        body = ["s_set_gpr_idx_on s55, gpr_idx(SRC0)", "v_mov_b32_e32 v4, v12", "s_set_gpr_idx_off"] + row_dec(52) + [
+            "global_store_dword %[lane4], v4, s[52:53]"]
+    elif k == "OUTX":
+        body = ["s_set_gpr_idx_off"] + row_dec(52) + ["global_store_dword %[lane4], %[x], s[52:53]"]
+    elif k == "FLUSH":
+        body = ["s_mov_b32 s59, 0"]
+    elif k == "OUTBOT":
+        body = ["s_set_gpr_idx_on s59, gpr_idx(SRC0)", "v_mov_b32_e32 v4, v12", "s_set_gpr_idx_off",
+                "s_add_u32 s59, s59, 1"] + row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]"]
+    elif k == "END":
+        return ["s_set_gpr_idx_off", "s_branch .Lexit%="]
+    else:
+        raise KeyError(k)
+    return body + dispatch(pos)
+
+
+def routines() -> list[str]:
+    out = []
+    out += [".Ldivops%=:", "s_set_gpr_idx_on s55, gpr_idx(SRC0)", "v_mov_b32_e32 v4, v12",
+            "v_mov_b32_e32 v5, v11", "s_set_gpr_idx_off"]
+    out += DIV_BODY.splitlines()
+    out += ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v11, v6", "s_sub_u32 s55, s55, 1",
+            "s_setpc_b64 s[48:49]"]
+    out += [".Ldivopx%=:", "s_set_gpr_idx_on s55, gpr_idx(SRC0)", "v_mov_b32_e32 v5, v12", "s_set_gpr_idx_off",
+            "v_mov_b32_e32 v4, %[x]"]
+    out += DIV_BODY.splitlines()
+    out += ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v12, v6", "s_setpc_b64 s[48:49]"]
+    for name, dst, inc in (("divch", "v13", True), ("divlch", "v12", False)):
+        out += [f".L{name}%=:", "s_set_gpr_idx_off", "v_mov_b32_e32 v4, %[x]", "v_mov_b32_e32 v5, %[x]"]
+        out += DIV_BODY.splitlines()
+        out += ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {dst}, v6"]
+        if inc:
+            out += ["s_add_u32 s55, s55, 1"]
+        out += ["s_setpc_b64 s[48:49]"]
+    # next 64-byte code buffer: move the prefetched one in, prefetch the next
+    out += [".Lrefill%=:", "s_waitcnt lgkmcnt(0)"]
+    out += [f"s_mov_b64 s[{64 + 2 * i}:{65 + 2 * i}], s[{80 + 2 * i}:{81 + 2 * i}]" for i in range(8)]
+    out += ["s_add_u32 s40, s40, 64", "s_addc_u32 s41, s41, 0", "s_load_dwordx16 s[80:95], s[40:41], 0x40",
+            "s_and_b32 s58, s64, 0xffff", "s_add_u32 s44, s42, s58", "s_addc_u32 s45, s43, 0",
+            "s_setpc_b64 s[44:45]"]
+    return out
+
+
+def generate() -> str:
+    lines = [
+        # inputs -> the block's own registers
+        "s_mov_b64 s[40:41], %[cptr]",
+        "s_mov_b32 s59, %[j0]",
+        "s_mov_b64 s[50:51], %[inp]",
+        "s_mov_b64 s[52:53], %[outp]",
+        "s_mov_b32 s54, %[rowb]",
+        "s_mov_b32 s55, 0",
+        "s_load_dwordx16 s[64:79], s[40:41], 0x0",
+        "s_load_dwordx16 s[80:95], s[40:41], 0x40",
+        "s_getpc_b64 s[42:43]",
+        ".Lpc%=:",
+        "s_add_u32 s42, s42, .Ltab%= - .Lpc%=",
+        "s_addc_u32 s43, s43, 0",
+        "s_waitcnt lgkmcnt(0)",
+        # first code: word s[64 + j0/2], half j0 & 1
+        "s_lshr_b32 s58, s59, 1",
+        "s_mov_b32 m0, s58",
+        "s_nop 0",
+        "s_movrels_b32 s58, s64",
+        "s_bitcmp1_b32 s59, 0",
+        "s_cbranch_scc0 .Leven%=",
+        "s_lshr_b32 s58, s58, 16",
+        ".Leven%=:",
+        "s_and_b32 s58, s58, 0xffff",
+        "s_set_gpr_idx_on s55, gpr_idx(DST)",
+        "s_add_u32 s44, s42, s58",
+        "s_addc_u32 s45, s43, 0",
+        "s_setpc_b64 s[44:45]",
+        ".p2align 6",
+        ".Ltab%=:",
+    ]
+    for pos in range(POS):
+        for kind in KINDS:
+            h = handler(kind, pos)
+            lines.append(".p2align 6")
+            lines.append(f".Lh%=_{pos}_{kind}:")
+            lines += h
+    lines += routines()
+    # no scalar prefetch may still be writing s[80:95] once the block is left
+    lines += [".Lexit%=:", "s_waitcnt lgkmcnt(0)"]
+    return "\n".join(lines) + "\n"
+
+
+def write(path: str) -> None:
+    text = generate()
+    body = "\n".join('    "' + ln.replace('"', '\\"') + '\\n"' for ln in text.splitlines())
+    clob = ", ".join([f'"v{i}"' for i in range(4, 12 + VSTACK)] + [f'"s{i}"' for i in range(40, 60)]
+                     + [f'"s{i}"' for i in range(64, 96)] + ['"m0"', '"vcc"', '"scc"'])
+    src = ("// Generated by gen_interp.py: threaded-code interpreter for k_run.\n"
+           f"#define EV_CODE_STRIDE {STRIDE}u\n#define EV_CODE_BLOCK {BLOCK}u\n#define EV_CODE_POS {POS}u\n"
+           f"#define EV_VSTACK {VSTACK}u\n#define EV_INTERP_CLOBBERS {clob}\n"
+           + "".join(f"#define EV_K_{k} {i}u\n" for i, k in enumerate(KINDS))
+           + "#define EV_INTERP_ASM \\\n" + body.replace("\n", " \\\n") + "\n")
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        f.write(src)
+    os.replace(tmp, path)
+
+
+if __name__ == "__main__":
+    write(sys.argv[1] if len(sys.argv) > 1 else os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                               "ev_interp.inc"))

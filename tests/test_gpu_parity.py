@@ -38,21 +38,25 @@ def ev():
     return ev
 
 
-def run(ev, buf, off, x, y, chunk=0, lds=0, per_case=True):
+def run(ev, buf, off, x, y, chunk=0, lds=0, per_case=True, flags=0):
     with ev.Context(x, y) as c:
-        if chunk or lds:
-            ev.ev_set_tuning(c.ctx, chunk, lds)
+        if chunk or lds or flags:
+            ev.ev_set_tuning(c.ctx, chunk, lds, flags)
         pop = c.load(buf, off)
         info = ev.ev_get_plan_info(c.ctx, pop)
         fit, pc = c.eval(pop, per_case=per_case)
     return fit, pc, info
 
 
-def check(ev, buf, off, x, y, chunk=0, lds=0, threads=8, what=""):
+def check(ev, buf, off, x, y, chunk=0, lds=0, threads=8, what="", both=True):
+    """Both interpreters (register-stack and general) against the oracle."""
     want_fit, want_pc = oracle.eval_population(buf, off, x, y, threads=threads, per_case=True)
-    fit, pc, info = run(ev, buf, off, x, y, chunk, lds)
-    assert_same(pc, want_pc, f"per-case {what}")
-    assert_same(fit, want_fit, f"fitness {what}")
+    info = None
+    for flags in ((0, ev.EV_TUNE_NO_REGSTACK) if both else (0,)):
+        fit, pc, inf = run(ev, buf, off, x, y, chunk, lds, flags=flags)
+        assert_same(pc, want_pc, f"per-case {what} flags={flags}")
+        assert_same(fit, want_fit, f"fitness {what} flags={flags}")
+        info = info or inf
     return info
 
 
