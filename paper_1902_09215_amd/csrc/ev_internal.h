@@ -48,6 +48,8 @@ struct RunArgs {
     uint32_t rowb;  // bytes per result slot row (N * 4)
     const float* in_res;
     float* out_res;
+    float* slab;            // spill slabs, one per wave of the grid
+    uint64_t slab_entries;  // rows of 64 floats per slab
 };
 
 // A work item as the evaluator sees it (32 bytes).

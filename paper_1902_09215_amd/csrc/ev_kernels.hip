@@ -26,6 +26,11 @@
 
 namespace ev {
 
+// Read-only data that is wave-uniform goes through the scalar cache.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) u32x4* const_u4p;
+typedef const __attribute__((address_space(1))) u32x4* global_u4p;
+
 // ------------------------------------------------------------ utilities
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t n, uint32_t v)
@@ -58,31 +63,39 @@ __device__ __forceinline__ float apply_op(uint32_t t, float a, float b)
 // spine node itself goes into the skeleton.  At the chunk's first token all
 // values still on the stack become result slots.
 
-// ---------------------------------------------------- threaded-code decode
+// ------------------------------------------------------ structure machine
 //
-// The same right-to-left machine, written for the register-stack kernel:
+// The right-to-left stack machine of both interpreters, run without values:
 //   tv  the top value T is live      P  an X sits on top, not yet placed
-//   m   values below T (T is register-stack entry m)
-// Each action becomes one code; an X is folded into the function or push
-// that consumes it, and a push or load of x directly followed by a function
-// of x becomes one code (op(x, x)).
+//   m   values below T               base  of those, how many live in the
+//                                          wave's spill slab (multiple of
+//                                          the half window)
+// A function meeting fewer than two values is a "spine" node: its subtree
+// leaves the chunk; the value it would take from the chunk (at most one)
+// becomes a result slot (or stays an X when it is a bare input) and the
+// node goes into the next level's skeleton.  At the chunk's first token all
+// values still on the stack become result slots.  For the register-stack
+// interpreter every action is also written as one code, an X folded into
+// the function or push that consumes it, and a push or load of x directly
+// followed by a function of x fused into one code; SPILL and FILL keep T
+// inside the window of EV_VSTACK register entries.  One implementation
+// serves counting and emission, so the two cannot disagree.
 
-struct CodeSink {
-    uint16_t* dst;   // nullptr: count only
-    uint64_t at;     // global index of the next code
-    uint32_t n;
+struct Sink {
+    uint16_t* codes;   // nullptr: count codes only
+    uint64_t at;       // global index of the next code
+    uint8_t* frag;     // nullptr: count fragment tokens only
+    uint64_t w;        // one past the next fragment token (written backwards)
+    uint32_t n_codes, n_frag, n_out, n_in;
     uint32_t pending;  // EV_K_PUSHX / EV_K_LOADX waiting for fusion, or ~0u
-    uint32_t outs, ins;
 
     __device__ void put(uint32_t kind)
     {
-        if (dst) dst[at] = (uint16_t)((uint32_t)(at & (EV_CODE_POS - 1)) * EV_CODE_BLOCK + kind * EV_CODE_STRIDE);
+        if (codes) codes[at] = (uint16_t)((uint32_t)(at & (EV_CODE_POS - 1)) * EV_CODE_BLOCK + kind * EV_CODE_STRIDE);
         at++;
-        n++;
-        outs += (kind == EV_K_OUTT || kind == EV_K_OUTX || kind == EV_K_OUTBOT);
-        ins += (kind == EV_K_PUSHREF || kind == EV_K_LOADREF);
+        n_codes++;
     }
-    __device__ void emit(uint32_t kind)
+    __device__ void code(uint32_t kind)
     {
         if (pending != ~0u) {
             if (kind >= EV_K_OPX0 && kind <= EV_K_OPX3) {
@@ -99,182 +112,218 @@ struct CodeSink {
         }
         put(kind);
     }
+    __device__ void ftok(uint32_t t)
+    {
+        if (frag) frag[--w] = (uint8_t)t;
+        n_frag++;
+    }
 };
 
-__device__ uint32_t code_machine(const uint8_t* __restrict__ seq, uint64_t start, uint32_t len, CodeSink& o)
+// Reads one chunk's tokens right to left, 16 bytes per load.
+struct RevTokens {
+    const uint8_t* seq;
+    uint64_t k, lo, wb;
+    u32x4 wd;
+    __device__ RevTokens(const uint8_t* s, uint64_t start, uint32_t len) : seq(s), k(start + len), lo(start), wb(~0ull) {}
+    __device__ bool next(uint32_t& t)
+    {
+        if (k <= lo) return false;
+        k--;
+        const uint64_t b = k & ~(uint64_t)15;
+        if (b != wb) {
+            wd = *reinterpret_cast<const u32x4*>(seq + b);
+            wb = b;
+        }
+        const uint32_t j = (uint32_t)(k & 15);
+        const uint32_t word = j >= 8 ? (j >= 12 ? wd.w : wd.z) : (j >= 4 ? wd.y : wd.x);
+        t = (word >> (8 * (j & 3))) & 255u;
+        return true;
+    }
+};
+
+struct MachineOut {
+    uint32_t maxtop;  // deepest m
+    int32_t net;      // sum over tokens of (+1 function, -1 leaf)
+    int32_t minpref;  // minimum of that running sum before a token
+    uint32_t bad;     // a token above max_tok
+};
+
+__device__ MachineOut run_machine(const uint8_t* __restrict__ seq, uint64_t start, uint32_t len, uint32_t max_tok,
+                                  Sink& o)
 {
-    uint32_t tv = 0, P = 0, m = 0, maxtop = 0;
-    for (uint64_t k = start + len; k-- > start;) {
-        const uint32_t t = seq[k];
+    uint32_t tv = 0, P = 0, m = 0, base = 0, maxtop = 0, bad = 0;
+    int32_t R = 0, maxR = INT32_MIN;
+    RevTokens rt(seq, start, len);
+    uint32_t t;
+    while (rt.next(t)) {
+        bad |= t > max_tok;
+        R += t < TOK_X ? 1 : -1;
+        maxR = R > maxR ? R : maxR;
         if (t == TOK_X) {
-            if (!P) P = 1;
-            else if (tv) { o.emit(EV_K_PUSHX); m++; }
-            else { o.emit(EV_K_LOADX); tv = 1; }
+            if (!P) {
+                P = 1;
+            } else if (tv) {
+                if (m + 1 - base > EV_VSTACK - 1) { o.code(EV_K_SPILL); base += EV_VHALF; }
+                o.code(EV_K_PUSHX);
+                m++;
+            } else {
+                o.code(EV_K_LOADX);
+                tv = 1;
+            }
         } else if (t == TOK_REF) {
+            o.n_in++;
             if (P) {
-                if (tv) { o.emit(EV_K_PUSHX); m++; } else { o.emit(EV_K_LOADX); tv = 1; }
+                if (tv) {
+                    if (m + 1 - base > EV_VSTACK - 1) { o.code(EV_K_SPILL); base += EV_VHALF; }
+                    o.code(EV_K_PUSHX);
+                    m++;
+                } else {
+                    o.code(EV_K_LOADX);
+                    tv = 1;
+                }
                 P = 0;
             }
-            if (tv) { o.emit(EV_K_PUSHREF); m++; } else { o.emit(EV_K_LOADREF); tv = 1; }
+            if (tv) {
+                if (m + 1 - base > EV_VSTACK - 1) { o.code(EV_K_SPILL); base += EV_VHALF; }
+                o.code(EV_K_PUSHREF);
+                m++;
+            } else {
+                o.code(EV_K_LOADREF);
+                tv = 1;
+            }
         } else if (t < TOK_X) {
             const uint32_t cnt = m + tv + P;
             if (cnt >= 2) {
-                if (P) { o.emit(EV_K_OPX0 + t); P = 0; } else { o.emit(EV_K_OPS0 + t); m--; }
+                if (P) {
+                    o.code(EV_K_OPX0 + t);
+                    P = 0;
+                } else {
+                    if (m == base && base > 0) { o.code(EV_K_FILL); base -= EV_VHALF; }
+                    o.code(EV_K_OPS0 + t);
+                    m--;
+                }
             } else {
-                if (cnt == 1 && !P) o.emit(EV_K_OUTT);
+                if (cnt == 1) {
+                    if (!P) { o.code(EV_K_OUTT); o.n_out++; }
+                    o.ftok(P ? TOK_X : TOK_REF);
+                }
+                o.ftok(t);
                 tv = 0; P = 0; m = 0;
             }
         }
-        if (m > maxtop) maxtop = m;
+        maxtop = m > maxtop ? m : maxtop;
     }
-    if (m > 0) {
-        o.emit(EV_K_FLUSH);
-        for (uint32_t i = 0; i < m; i++) o.emit(EV_K_OUTBOT);
+    // chunk start: every value left becomes a slot, the bottom one first
+    if (base > 0) {
+        o.code(EV_K_FLUSH);
+        for (uint32_t i = 0; i < base; i++) o.code(EV_K_OUTMEM);
     }
-    if (tv) o.emit(EV_K_OUTT);
-    if (P) o.emit(EV_K_OUTX);
-    o.emit(EV_K_END);
-    return maxtop;
-}
-
-struct MachineCounts {
-    uint32_t n_out, n_frag, n_in, max_m;
-};
-
-__device__ __forceinline__ uint32_t ld_tok(const uint8_t* __restrict__ seq, uint64_t k)
-{
-    return seq[k];
+    if (m > base) {
+        o.code(EV_K_FLUSH);
+        for (uint32_t i = base; i < m; i++) o.code(EV_K_OUTBOT);
+    }
+    if (tv) o.code(EV_K_OUTT);
+    if (P) o.code(EV_K_OUTX);
+    o.code(EV_K_END);
+    const uint32_t left = m + tv + P;
+    o.n_out += left;
+    for (uint32_t i = 0; i < left; i++) o.ftok(TOK_REF);
+    MachineOut r;
+    r.maxtop = maxtop;
+    r.net = R;
+    r.minpref = len ? R - maxR : 0;
+    r.bad = bad;
+    return r;
 }
 
 __global__ void k_count(const uint8_t* __restrict__ seq, const ChunkIn* __restrict__ in, uint32_t n,
                         ChunkStat* __restrict__ out, uint32_t max_tok)
 {
-    uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
     if (ci >= n) return;
-    ChunkIn c = in[ci];
-    uint32_t cnt = 0, P = 0, m = 0, max_m = 0;
-    uint32_t n_out = 0, n_frag = 0, n_in = 0, bad = 0;
-    int32_t R = 0, maxR = INT32_MIN;
-    for (uint64_t k = c.start + c.len; k-- > c.start;) {
-        uint32_t t = ld_tok(seq, k);
-        if (t > max_tok) bad = 1;
-        if (t >= TOK_X) {
-            R -= 1;
-            if (t == TOK_X) {
-                if (P) m++; else P = 1;
-            } else {
-                n_in++;
-                if (P) { m++; P = 0; }
-                m++;
-            }
-            cnt++;
-        } else {
-            R += 1;
-            if (cnt < 2) {
-                if (cnt == 1) { if (!P) n_out++; n_frag++; }
-                n_frag++;
-                cnt = 0; P = 0; m = 0;
-            } else {
-                if (!P) m--;
-                P = 0;
-                cnt--;
-            }
-        }
-        if (m > max_m) max_m = m;
-        if (R > maxR) maxR = R;
-    }
-    // chunk-start flush: every remaining value becomes a slot
-    n_out += cnt;
-    n_frag += cnt;
-    CodeSink o{nullptr, 0, 0, ~0u, 0, 0};
-    const uint32_t maxtop = code_machine(seq, c.start, c.len, o);
+    const ChunkIn c = in[ci];
+    Sink o{nullptr, 0, nullptr, 0, 0, 0, 0, 0, ~0u};
+    const MachineOut r = run_machine(seq, c.start, c.len, max_tok, o);
     ChunkStat s;
-    s.n_codes = o.n;
-    s.maxtop = maxtop;
-    s.code_out = o.outs;
-    s.code_in = o.ins;
-    s.n_out = n_out;
-    s.n_frag = n_frag;
-    s.n_in = n_in;
-    s.max_m = max_m;
-    s.net = R;                                // sum of (+1 function, -1 leaf)
-    s.minpref = (c.len ? R - maxR : 0);       // min running sum before a token
-    s.bad = bad;
+    s.n_out = o.n_out;
+    s.n_frag = o.n_frag;
+    s.n_in = o.n_in;
+    s.max_m = r.maxtop + 1;
+    s.net = r.net;
+    s.minpref = r.minpref;
+    s.bad = r.bad;
+    s.n_codes = o.n_codes;
+    s.maxtop = r.maxtop;
+    s.code_out = o.n_out;
+    s.code_in = o.n_in;
     out[ci] = s;
 }
 
+// Emission: the chunk's skeleton fragment (ending at frag_end[ci]) and, for
+// register-stack items, its codes (from code_begin[ci]).
 __global__ void k_emit(const uint8_t* __restrict__ seq, const ChunkIn* __restrict__ in,
-                       const uint64_t* __restrict__ frag_end, uint32_t n, uint8_t* __restrict__ dst)
+                       const uint64_t* __restrict__ frag_end, const uint64_t* __restrict__ code_begin, uint32_t n,
+                       uint8_t* __restrict__ dst, uint16_t* __restrict__ codes)
 {
-    uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
     if (ci >= n) return;
-    ChunkIn c = in[ci];
-    uint64_t w = frag_end[ci];
-    uint32_t cnt = 0, P = 0;
-    for (uint64_t k = c.start + c.len; k-- > c.start;) {
-        uint32_t t = ld_tok(seq, k);
-        if (t >= TOK_X) {
-            if (t == TOK_X) {
-                if (!P) P = 1;
-            } else {
-                P = 0;
-            }
-            cnt++;
-        } else {
-            if (cnt < 2) {
-                if (cnt == 1) dst[--w] = P ? (uint8_t)TOK_X : (uint8_t)TOK_REF;
-                dst[--w] = (uint8_t)t;
-                cnt = 0; P = 0;
-            } else {
-                P = 0;
-                cnt--;
-            }
-        }
-    }
-    for (uint32_t i = 0; i < cnt; i++) dst[--w] = (uint8_t)TOK_REF;
-}
-
-__global__ void k_decode(const uint8_t* __restrict__ seq, const ChunkIn* __restrict__ in,
-                         const uint64_t* __restrict__ code_begin, uint32_t n, uint16_t* __restrict__ codes)
-{
-    uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ci >= n) return;
-    const uint64_t b = code_begin[ci];
-    if (b == ~0ull) return;  // runs on the general kernel
     const ChunkIn c = in[ci];
-    CodeSink o{codes, b, 0, ~0u, 0, 0};
-    code_machine(seq, c.start, c.len, o);
+    const bool has_codes = codes && code_begin[ci] != ~0ull;
+    if (!dst && !has_codes) return;
+    Sink o{has_codes ? codes : nullptr, has_codes ? code_begin[ci] : 0, dst, dst ? frag_end[ci] : 0, 0, 0, 0, 0, ~0u};
+    run_machine(seq, c.start, c.len, TOK_REF, o);
 }
 
 // Every code of a register-stack item must name a handler of its own
-// position, the item must end with its only END, and it must write and read
-// exactly the slots the plan gave it; anything else fails the plan before
-// a single code runs.
+// position and the item must end with its only END; simulating the codes
+// must keep T inside the register window, every read entry below it, the
+// slab within its entries, and must write and read exactly the slots the
+// plan gave the item.  Anything else fails the plan before a code runs.
 __global__ void k_check_codes(const uint16_t* __restrict__ codes, const uint64_t* __restrict__ begin,
-                              const uint32_t* __restrict__ expect, uint32_t n, uint32_t* __restrict__ err)
+                              const uint32_t* __restrict__ expect, uint32_t n, uint32_t slab_entries,
+                              uint32_t* __restrict__ err)
 {
     const uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
     if (ci >= n) return;
     const uint64_t b = begin[ci];
     const uint32_t len = expect[3 * ci], want_out = expect[3 * ci + 1], want_in = expect[3 * ci + 2];
     uint32_t outs = 0, ins = 0, bad = len == 0;
+    int32_t idx = 0, slab = 0, fl = 0;
     for (uint32_t i = 0; i < len; i++) {
         const uint32_t v = codes[b + i];
-        const uint32_t pos = v / EV_CODE_BLOCK, r = v % EV_CODE_BLOCK, kind = r / EV_CODE_STRIDE;
-        if (r % EV_CODE_STRIDE || pos != (uint32_t)((b + i) & (EV_CODE_POS - 1)) || kind > EV_K_END) bad = 1;
-        if ((kind == EV_K_END) != (i + 1 == len)) bad = 1;
-        outs += (kind == EV_K_OUTT || kind == EV_K_OUTX || kind == EV_K_OUTBOT);
-        ins += (kind == EV_K_PUSHREF || kind == EV_K_LOADREF);
+        const uint32_t pos = v / EV_CODE_BLOCK, r = v % EV_CODE_BLOCK, k = r / EV_CODE_STRIDE;
+        if (r % EV_CODE_STRIDE || pos != (uint32_t)((b + i) & (EV_CODE_POS - 1)) || k > EV_K_OUTMEM) bad = 1;
+        if ((k == EV_K_END) != (i + 1 == len)) bad = 1;
+        if (k <= EV_K_OPS3) {
+            bad |= idx < 1;
+            idx--;
+        } else if ((k >= EV_K_CH0 && k <= EV_K_CH3) || k == EV_K_PUSHX || k == EV_K_PUSHREF) {
+            idx++;
+        } else if (k == EV_K_FLUSH) {
+            fl = 0;
+        } else if (k == EV_K_OUTBOT) {
+            bad |= fl >= idx;
+            fl++;
+        } else if (k == EV_K_OUTMEM) {
+            bad |= fl >= slab;
+            fl++;
+        } else if (k == EV_K_SPILL) {
+            bad |= idx < (int32_t)EV_VHALF;
+            idx -= EV_VHALF;
+            slab += EV_VHALF;
+        } else if (k == EV_K_FILL) {
+            bad |= slab < (int32_t)EV_VHALF || idx != 0;
+            idx += EV_VHALF;
+            slab -= EV_VHALF;
+        }
+        bad |= idx < 0 || idx > (int32_t)EV_VSTACK - 1 || slab < 0 || slab > (int32_t)slab_entries;
+        outs += (k == EV_K_OUTT || k == EV_K_OUTX || k == EV_K_OUTBOT || k == EV_K_OUTMEM);
+        ins += (k == EV_K_PUSHREF || k == EV_K_LOADREF);
     }
     if (bad || outs != want_out || ins != want_in) atomicOr(err, 1u);
 }
 
 // ------------------------------------------------------------ evaluation
-
-// Read-only data that is wave-uniform goes through the scalar cache.
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef const __attribute__((address_space(4))) u32x4* const_u4p;
-typedef const __attribute__((address_space(1))) u32x4* global_u4p;
 
 __device__ __forceinline__ EvalChunk load_chunk(const_u4p base, uint32_t i)
 {
@@ -586,6 +635,8 @@ __global__ __launch_bounds__(64) void k_run(RunArgs a)
 {
     const uint32_t lane = threadIdx.x;
     const_u4p chunks = (const_u4p)(global_u4p)(const void*)a.chunks;
+    // this wave's spill slab: slab_entries rows of 64 lanes
+    const uint64_t smem = (uint64_t)(uintptr_t)a.slab + (uint64_t)blockIdx.x * a.slab_entries * 256u;
     uint32_t item = wave_pop(a.counter);
     while (item < a.n_items) {
         const uint32_t next = wave_pop(a.counter);
@@ -601,10 +652,11 @@ __global__ __launch_bounds__(64) void k_run(RunArgs a)
             const uint32_t j0 = (uint32_t)(code_begin & 31u);
             const uint64_t inp = (uint64_t)(uintptr_t)a.in_res + (uint64_t)d.z * a.rowb;
             const uint64_t outp = (uint64_t)(uintptr_t)a.out_res + (uint64_t)d.w * a.rowb;
+            const uint32_t slane = lane * 4u;
             asm volatile(EV_INTERP_ASM
                          :
-                         : [x] "v"(xv), [lane4] "v"(lane4), [cptr] "s"(cptr), [j0] "s"(j0), [inp] "s"(inp),
-                           [outp] "s"(outp), [rowb] "s"(a.rowb)
+                         : [x] "v"(xv), [lane4] "v"(lane4), [slane] "v"(slane), [cptr] "s"(cptr), [j0] "s"(j0),
+                           [inp] "s"(inp), [outp] "s"(outp), [rowb] "s"(a.rowb), [smem] "s"(smem)
                          : EV_INTERP_CLOBBERS);
         }
         item = next;
@@ -634,11 +686,11 @@ hipError_t launch_count(const uint8_t* seq, const ChunkIn* in, uint32_t n, Chunk
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const uint8_t* seq, const ChunkIn* in, const uint64_t* frag_end, uint32_t n, uint8_t* dst,
-                       hipStream_t s)
+hipError_t launch_emit(const uint8_t* seq, const ChunkIn* in, const uint64_t* frag_end, const uint64_t* code_begin,
+                       uint32_t n, uint8_t* dst, uint16_t* codes, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, in, frag_end, n, dst);
+    hipLaunchKernelGGL(k_emit, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, in, frag_end, code_begin, n, dst, codes);
     return hipGetLastError();
 }
 
@@ -675,19 +727,12 @@ hipError_t launch_run(const RunArgs& a, uint32_t grid, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_decode(const uint8_t* seq, const ChunkIn* in, const uint64_t* code_begin, uint32_t n, uint16_t* codes,
-                         hipStream_t s)
-{
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_decode, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, in, code_begin, n, codes);
-    return hipGetLastError();
-}
 
 hipError_t launch_check_codes(const uint16_t* codes, const uint64_t* begin, const uint32_t* expect, uint32_t n,
-                              uint32_t* err, hipStream_t s)
+                              uint32_t slab_entries, uint32_t* err, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_check_codes, dim3(cdiv(n, 64)), dim3(64), 0, s, codes, begin, expect, n, err);
+    hipLaunchKernelGGL(k_check_codes, dim3(cdiv(n, 64)), dim3(64), 0, s, codes, begin, expect, n, slab_entries, err);
     return hipGetLastError();
 }
 

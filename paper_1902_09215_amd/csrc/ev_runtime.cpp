@@ -143,29 +143,42 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
     uint8_t* cur = P->d_bytes;
     bool cur_owned = false;
     int level = 0;
-    void* d_in = nullptr;
-    void* d_stat = nullptr;
-    void* d_frag = nullptr;
+    void *d_in = nullptr, *d_stat = nullptr, *d_frag = nullptr, *d_cb = nullptr;
     ev_status st = EV_OK;
     auto cleanup = [&]() {
         dev_free(c, d_in);
         dev_free(c, d_stat);
         dev_free(c, d_frag);
-        d_in = d_stat = d_frag = nullptr;
+        dev_free(c, d_cb);
+        d_in = d_stat = d_frag = d_cb = nullptr;
+    };
+    auto count = [&](const std::vector<ChunkIn>& ch, std::vector<ChunkStat>& cs) -> ev_status {
+        const uint32_t n = (uint32_t)ch.size();
+        dev_free(c, d_in);
+        dev_free(c, d_stat);
+        d_in = d_stat = nullptr;
+        ev_status e;
+        if ((e = dev_alloc(c, n * sizeof(ChunkIn), &d_in)) != EV_OK) return e;
+        if ((e = dev_alloc(c, n * sizeof(ChunkStat), &d_stat)) != EV_OK) return e;
+        cs.resize(n);
+        HIPCHK(hipMemcpyAsync(d_in, ch.data(), n * sizeof(ChunkIn), hipMemcpyHostToDevice, s));
+        HIPCHK(launch_count(cur, (ChunkIn*)d_in, n, (ChunkStat*)d_stat, level == 0 ? TOK_X : TOK_REF, s));
+        HIPCHK(hipMemcpyAsync(cs.data(), d_stat, n * sizeof(ChunkStat), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return EV_OK;
     };
 
     for (;;) {
         std::vector<ChunkIn> ch;
-        std::vector<uint32_t> tree_first, tree_last;  // chunk ranges per tree (active only)
-        tree_first.assign(M, UINT32_MAX);
-        tree_last.assign(M, 0);
+        std::vector<char> forced(M, 0);
         for (int32_t t = 0; t < M; t++) {
             if (!active[t]) continue;
             const uint64_t len = rl[t];
             // One work item when the tree is small, or when the last split
-            // did not halve it (a skeleton dense in spine nodes).
-            const bool whole = len <= C || (level > 0 && len * 2 > prev_len[t]);
-            tree_first[t] = (uint32_t)ch.size();
+            // did not halve it (a skeleton dense in spine nodes): the latter
+            // must stay whole, or the levels would not converge.
+            forced[t] = level > 0 && len * 2 > prev_len[t];
+            const bool whole = len <= C || forced[t];
             if (whole) {
                 if (len > 0xFFFFFFFFull) { cleanup(); return fail(EV_ECAP, "work item of %llu tokens", (unsigned long long)len); }
                 ch.push_back({rs[t], (uint32_t)len, (uint32_t)t});
@@ -173,31 +186,24 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
                 for (uint64_t o = 0; o < len; o += C)
                     ch.push_back({rs[t] + o, (uint32_t)std::min<uint64_t>(C, len - o), (uint32_t)t});
             }
-            tree_last[t] = (uint32_t)ch.size() - 1;
         }
-        const uint32_t n = (uint32_t)ch.size();
-        if (n == 0) break;
-        cleanup();
-        if ((st = dev_alloc(c, n * sizeof(ChunkIn), &d_in)) != EV_OK) return st;
-        if ((st = dev_alloc(c, n * sizeof(ChunkStat), &d_stat)) != EV_OK) { cleanup(); return st; }
-        HIPCHK(hipMemcpyAsync(d_in, ch.data(), n * sizeof(ChunkIn), hipMemcpyHostToDevice, s));
-        HIPCHK(launch_count(cur, (ChunkIn*)d_in, n, (ChunkStat*)d_stat, level == 0 ? TOK_X : TOK_REF, s));
-        std::vector<ChunkStat> cs(n);
-        HIPCHK(hipMemcpyAsync(cs.data(), d_stat, n * sizeof(ChunkStat), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        if (ch.empty()) break;
+        std::vector<ChunkStat> cs;
+        if ((st = count(ch, cs)) != EV_OK) { cleanup(); return st; }
 
         if (level == 0) {
             // Sec. 2.2 word: every token fills one open slot and a function
             // opens two; a tree is valid iff a slot is open before each token
             // and none after the last.
+            std::vector<int64_t> open(M, 1);
+            std::vector<char> ok(M, 1);
+            for (size_t j = 0; j < ch.size(); j++) {
+                const uint32_t t = ch[j].tree;
+                if (cs[j].bad || open[t] + cs[j].minpref < 1) ok[t] = 0;
+                open[t] += cs[j].net;
+            }
             for (int32_t t = 0; t < M; t++) {
-                int64_t open = 1;
-                bool ok = true;
-                for (uint32_t j = tree_first[t]; j <= tree_last[t] && ok; j++) {
-                    if (cs[j].bad || open + cs[j].minpref < 1) ok = false;
-                    open += cs[j].net;
-                }
-                if (!ok || open != 0) {
+                if (!ok[t] || open[t] != 0) {
                     cleanup();
                     if (bad_tree) *bad_tree = t;
                     return fail(EV_EMALFORMED, "tree %d is not a valid prefix tree", t);
@@ -205,44 +211,37 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             }
         }
 
+        const uint32_t n = (uint32_t)ch.size();
+
         // slot numbering (global over the level's chunks, in sequence order)
         // and the split of the work items between the two kernels
         std::vector<uint64_t> out_end(n), frag_end(n), code_begin(n, ~0ull);
         std::vector<char> fast(n, 0);
+        std::vector<uint32_t> tree_first(M, UINT32_MAX), tree_last(M, 0);
         uint64_t so = 0, sf = 0, sc = 0, tokens = 0;
-        uint32_t max_m = 0, n_fast = 0;
+        uint32_t max_m = 0, slab_top = 0;
         for (uint32_t j = 0; j < n; j++) {
+            const uint32_t t = ch[j].tree;
+            if (tree_first[t] == UINT32_MAX) tree_first[t] = j;
+            tree_last[t] = j;
             so += cs[j].n_out;
             sf += cs[j].n_frag;
             out_end[j] = so;
             frag_end[j] = sf;
             tokens += ch[j].len;
-            if (cs[j].code_out != cs[j].n_out || cs[j].code_in != cs[j].n_in) {
-                cleanup();
-                return fail(EV_EDEVICE, "internal: code stream of work item %u disagrees with the split plan", j);
-            }
-            fast[j] = c->use_run && cs[j].maxtop + 1 <= EV_VSTACK_ENTRIES;
+            pl.max_stack = std::max<uint64_t>(pl.max_stack, cs[j].maxtop + 1);
+            fast[j] = c->use_run;
             if (fast[j]) {
                 code_begin[j] = sc;
                 sc += cs[j].n_codes;
-                n_fast++;
+                slab_top = std::max(slab_top, cs[j].maxtop);
             } else {
                 max_m = std::max(max_m, cs[j].max_m);
             }
         }
         if (so > 0xFFFFFFF0ull) { cleanup(); return fail(EV_ECAP, "too many intermediate results"); }
 
-        Level L;
-        L.seq = cur;
-        L.owned = cur_owned;
-        L.n_out = (uint32_t)so;
-        L.max_m = max_m;
-        L.tokens = tokens;
-        for (uint32_t j = 0; j < n; j++) pl.max_stack = std::max<uint64_t>(pl.max_stack, cs[j].maxtop + 1);
-        pl.chunks_total += n;
-        pl.slots_total += so;
-
-        // eval descriptors, longest first
+        // input slots: the k-th REF of this level is the previous level's slot k
         std::vector<EvalChunk> ec(n);
         for (int32_t t = 0; t < M; t++) {
             if (tree_first[t] == UINT32_MAX) continue;
@@ -252,7 +251,6 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
                 ec[j] = EvalChunk{ch[j].start, ch[j].len, (uint32_t)in_run, (uint32_t)out_end[j], (uint32_t)t, 0, 0};
             }
         }
-        // every chunk must read only slots the previous level wrote
         const uint64_t prev_out = pl.levels.empty() ? 0 : pl.levels.back().n_out;
         for (uint32_t j = 0; j < n; j++) {
             if (ec[j].in_end > prev_out || (uint64_t)ec[j].in_end < cs[j].n_in) {
@@ -260,7 +258,17 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
                 return fail(EV_EDEVICE, "inconsistent split plan at level %d", level);
             }
         }
-        // register-stack items: threaded codes; the rest: k_eval descriptors
+
+        Level L;
+        L.seq = cur;
+        L.owned = cur_owned;
+        L.n_out = (uint32_t)so;
+        L.max_m = max_m;
+        L.tokens = tokens;
+        // a stack deeper than the register window spills half-windows to a slab
+        L.slab_entries = slab_top + 1 > EV_VSTACK_ENTRIES ? slab_top + EV_VSTACK_ENTRIES / 2 : 0;
+        pl.chunks_total += n;
+        pl.slots_total += so;
         std::vector<EvalChunk> slow;
         std::vector<std::pair<uint32_t, RunChunk>> run;
         for (uint32_t j = 0; j < n; j++) {
@@ -284,42 +292,9 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             for (size_t i = 0; i < run.size(); i++) rc[i] = run[i].second;
             if ((st = dev_alloc(c, rc.size() * sizeof(RunChunk), (void**)&LL.d_run)) != EV_OK) { cleanup(); return st; }
             if ((st = dev_alloc(c, sc * 2 + 256, (void**)&LL.codes)) != EV_OK) { cleanup(); return st; }
-            void* d_cb = nullptr;
-            if ((st = dev_alloc(c, n * sizeof(uint64_t), &d_cb)) != EV_OK) { cleanup(); return st; }
             HIPCHK(hipMemcpyAsync(LL.d_run, rc.data(), rc.size() * sizeof(RunChunk), hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(d_cb, code_begin.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
             HIPCHK(hipMemsetAsync((uint8_t*)LL.codes + sc * 2, 0, 256, s));
-            HIPCHK(launch_decode(cur, (ChunkIn*)d_in, (uint64_t*)d_cb, n, LL.codes, s));
-            // validate the emitted codes before anything may run them
-            std::vector<uint64_t> vb;
-            std::vector<uint32_t> ve;
-            for (uint32_t j = 0; j < n; j++) {
-                if (!fast[j]) continue;
-                vb.push_back(code_begin[j]);
-                ve.push_back(cs[j].n_codes);
-                ve.push_back(cs[j].n_out);
-                ve.push_back(cs[j].n_in);
-            }
-            void *d_vb = nullptr, *d_ve = nullptr, *d_err = nullptr;
-            if ((st = dev_alloc(c, vb.size() * 8, &d_vb)) || (st = dev_alloc(c, ve.size() * 4, &d_ve)) ||
-                (st = dev_alloc(c, 4, &d_err))) {
-                dev_free(c, d_vb); dev_free(c, d_ve); dev_free(c, d_cb); cleanup();
-                return st;
-            }
-            uint32_t err = 0;
-            HIPCHK(hipMemcpyAsync(d_vb, vb.data(), vb.size() * 8, hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(d_ve, ve.data(), ve.size() * 4, hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(d_err, &err, 4, hipMemcpyHostToDevice, s));
-            HIPCHK(launch_check_codes(LL.codes, (uint64_t*)d_vb, (uint32_t*)d_ve, (uint32_t)vb.size(), (uint32_t*)d_err, s));
-            HIPCHK(hipMemcpyAsync(&err, d_err, 4, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            dev_free(c, d_vb);
-            dev_free(c, d_ve);
-            dev_free(c, d_err);
-            dev_free(c, d_cb);
-            if (err) { cleanup(); return fail(EV_EDEVICE, "internal: malformed code stream at level %d", level); }
         }
-        pl.chunks_total += 0;
 
         // trees finished at this level and the next level's ranges
         bool any = false;
@@ -340,21 +315,62 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
                 ref_base[t] = out_end[j0] - cs[j0].n_out;
             }
         }
-        if (!any) break;
 
-        // emit the skeleton of the next level
-        void* d_next = nullptr;
-        if ((st = dev_alloc(c, sf + 64, &d_next)) != EV_OK) { cleanup(); return st; }
-        if ((st = dev_alloc(c, n * sizeof(uint64_t), &d_frag)) != EV_OK) { dev_free(c, d_next); cleanup(); return st; }
-        HIPCHK(hipMemsetAsync(d_next, 0xFF, sf + 64, s));
-        HIPCHK(hipMemcpyAsync(d_frag, frag_end.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-        HIPCHK(launch_emit(cur, (ChunkIn*)d_in, (uint64_t*)d_frag, n, (uint8_t*)d_next, s));
-        HIPCHK(hipStreamSynchronize(s));
-        cur = (uint8_t*)d_next;
+        // one pass writes the next level's skeleton and this level's codes
+        uint8_t* d_next = nullptr;
+        if (any) {
+            if ((st = dev_alloc(c, sf + 64, (void**)&d_next)) != EV_OK) { cleanup(); return st; }
+            HIPCHK(hipMemsetAsync(d_next, 0xFF, sf + 64, s));
+            dev_free(c, d_frag);
+            d_frag = nullptr;
+            if ((st = dev_alloc(c, n * sizeof(uint64_t), &d_frag)) != EV_OK) { dev_free(c, d_next); cleanup(); return st; }
+            HIPCHK(hipMemcpyAsync(d_frag, frag_end.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        }
+        if (any || !run.empty()) {
+            dev_free(c, d_cb);
+            d_cb = nullptr;
+            if ((st = dev_alloc(c, n * sizeof(uint64_t), &d_cb)) != EV_OK) { dev_free(c, d_next); cleanup(); return st; }
+            HIPCHK(hipMemcpyAsync(d_cb, code_begin.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+            HIPCHK(launch_emit(cur, (ChunkIn*)d_in, (uint64_t*)d_frag, (uint64_t*)d_cb, n, d_next,
+                               run.empty() ? nullptr : LL.codes, s));
+        }
+        if (!run.empty()) {
+            // validate the emitted codes before anything may run them
+            std::vector<uint64_t> vb;
+            std::vector<uint32_t> ve;
+            for (uint32_t j = 0; j < n; j++) {
+                if (!fast[j]) continue;
+                vb.push_back(code_begin[j]);
+                ve.push_back(cs[j].n_codes);
+                ve.push_back(cs[j].n_out);
+                ve.push_back(cs[j].n_in);
+            }
+            void *d_vb = nullptr, *d_ve = nullptr, *d_err = nullptr;
+            if ((st = dev_alloc(c, vb.size() * 8, &d_vb)) || (st = dev_alloc(c, ve.size() * 4, &d_ve)) ||
+                (st = dev_alloc(c, 4, &d_err))) {
+                dev_free(c, d_vb); dev_free(c, d_ve); dev_free(c, d_next); cleanup();
+                return st;
+            }
+            uint32_t err = 0;
+            HIPCHK(hipMemcpyAsync(d_vb, vb.data(), vb.size() * 8, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(d_ve, ve.data(), ve.size() * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(d_err, &err, 4, hipMemcpyHostToDevice, s));
+            HIPCHK(launch_check_codes(LL.codes, (uint64_t*)d_vb, (uint32_t*)d_ve, (uint32_t)vb.size(), LL.slab_entries,
+                                      (uint32_t*)d_err, s));
+            HIPCHK(hipMemcpyAsync(&err, d_err, 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            dev_free(c, d_vb);
+            dev_free(c, d_ve);
+            dev_free(c, d_err);
+            if (err) { dev_free(c, d_next); cleanup(); return fail(EV_EDEVICE, "internal: malformed code stream at level %d", level); }
+        } else {
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        if (!any) break;
+        cur = d_next;
         cur_owned = true;
         level++;
         if (level > 64) { dev_free(c, d_next); cleanup(); return fail(EV_ECAP, "split plan did not converge"); }
-        // the buffer is owned by the next Level record
     }
     cleanup();
     pl.bytes = 0;
@@ -511,6 +527,11 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
             const uint32_t grid = (uint32_t)std::min<uint64_t>(grid_max, items);
             need = std::max(need, (size_t)grid * (L.max_m + 16) * 64 * sizeof(float));
         }
+        if (L.n_run && L.slab_entries) {
+            const uint64_t items = (uint64_t)L.n_run * n_cb;
+            const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)c->grid_run, items);
+            need = std::max(need, (size_t)grid * L.slab_entries * 64 * sizeof(float));
+        }
     }
     if ((st = ensure_gstack(c, x, need)) != EV_OK) return st;
     hipStream_t s = x.stream;
@@ -531,6 +552,8 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
             r.rowb = (uint32_t)N * 4u;
             r.in_res = li ? rc->res[li - 1] : nullptr;
             r.out_res = rc->res[li];
+            r.slab = x.d_gstack;
+            r.slab_entries = L.slab_entries;
             HIPCHK(launch_run(r, (uint32_t)std::min<uint64_t>((uint64_t)c->grid_run, r.n_items), s));
         }
         if (L.n_chunks == 0) {

@@ -17,8 +17,15 @@ Register use inside the block:
   s[40:41] code pointer (64-byte block), s[42:43] handler table base,
   s[44:45] jump target, s[46:47] call target, s[48:49] return address,
   s[50:51] input-slot row pointer, s[52:53] output-slot row pointer,
-  s54 row bytes (cases * 4), s55 m, s[56:57] division scratch, s58 code,
-  s59 flush index.
+  s54 row bytes (cases * 4), s55 window index of T, s[56:57] division
+  scratch, s58 code, s59 flush index, s[60:61] next free entry of the
+  wave's spill slab in global memory, s[62:63] the slab's base.
+
+When the decoder sees the stack outgrow the 64-entry window it emits SPILL
+(store the bottom 32 entries to the slab, shift the window down); when a
+function needs an entry below the window it emits FILL (the reverse).  So
+the kernel never tests the stack depth; the device validator simulates the
+window index and slab depth of every code stream before it may run.
 """
 from __future__ import annotations
 
@@ -27,9 +34,11 @@ import sys
 
 STRIDE = 64
 VSTACK = 64  # register-stack entries: v12 .. v12+VSTACK-1
+HALF = VSTACK // 2  # entries moved by one spill or fill
 KINDS = ["OPS0", "OPS1", "OPS2", "OPS3", "OPX0", "OPX1", "OPX2", "OPX3",
          "CH0", "CH1", "CH2", "CH3", "LCH0", "LCH1", "LCH2", "LCH3",
-         "PUSHX", "LOADX", "PUSHREF", "LOADREF", "OUTT", "OUTX", "FLUSH", "OUTBOT", "END"]
+         "PUSHX", "LOADX", "PUSHREF", "LOADREF", "OUTT", "OUTX", "FLUSH", "OUTBOT", "END",
+         "SPILL", "FILL", "OUTMEM"]
 NK = len(KINDS)
 BLOCK = NK * STRIDE
 POS = 32
@@ -120,6 +129,8 @@ def handler(kind: str, pos: int) -> list[str]:
                 "s_add_u32 s59, s59, 1"] + row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]"]
     elif k == "END":
         return ["s_set_gpr_idx_off", "s_branch .Lexit%="]
+    elif k in ("SPILL", "FILL", "OUTMEM"):
+        body = call(k.lower())
     else:
         raise KeyError(k)
     return body + dispatch(pos)
@@ -143,6 +154,27 @@ def routines() -> list[str]:
         if inc:
             out += ["s_add_u32 s55, s55, 1"]
         out += ["s_setpc_b64 s[48:49]"]
+    # spill: the window's bottom HALF entries to the slab, then shift down
+    out += [".Lspill%=:", "s_set_gpr_idx_off"]
+    for g in range(HALF // 16):
+        out += [f"global_store_dword %[slane], v{12 + 16 * g + i}, s[60:61]" + (f" offset:{256 * i}" if i else "")
+                for i in range(16)]
+        out += ["s_add_u32 s60, s60, 4096", "s_addc_u32 s61, s61, 0"]
+    out += [f"v_mov_b32_e32 v{12 + i}, v{12 + HALF + i}" for i in range(VSTACK - HALF)]
+    out += [f"s_sub_u32 s55, s55, {HALF}", "s_setpc_b64 s[48:49]"]
+    # fill: shift up, then the top HALF entries of the slab into the bottom
+    out += [".Lfill%=:", "s_set_gpr_idx_off"]
+    out += [f"v_mov_b32_e32 v{12 + HALF + i}, v{12 + i}" for i in range(VSTACK - HALF)]
+    for g in reversed(range(HALF // 16)):
+        out += ["s_sub_u32 s60, s60, 4096", "s_subb_u32 s61, s61, 0"]
+        out += [f"global_load_dword v{12 + 16 * g + i}, %[slane], s[60:61]" + (f" offset:{256 * i}" if i else "")
+                for i in range(16)]
+    out += ["s_waitcnt vmcnt(0)", f"s_add_u32 s55, s55, {HALF}", "s_setpc_b64 s[48:49]"]
+    # chunk-end flush of an entry that lives in the slab (entry s59)
+    out += [".Loutmem%=:", "s_set_gpr_idx_off", "s_lshl_b32 s46, s59, 8", "s_add_u32 s46, s62, s46",
+            "s_addc_u32 s47, s63, 0", "global_load_dword v4, %[slane], s[46:47]", "s_waitcnt vmcnt(0)",
+            "s_add_u32 s59, s59, 1"] + row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]",
+                                                     "s_setpc_b64 s[48:49]"]
     # next 64-byte code buffer: move the prefetched one in, prefetch the next
     out += [".Lrefill%=:", "s_waitcnt lgkmcnt(0)"]
     out += [f"s_mov_b64 s[{64 + 2 * i}:{65 + 2 * i}], s[{80 + 2 * i}:{81 + 2 * i}]" for i in range(8)]
@@ -161,6 +193,8 @@ def generate() -> str:
         "s_mov_b64 s[52:53], %[outp]",
         "s_mov_b32 s54, %[rowb]",
         "s_mov_b32 s55, 0",
+        "s_mov_b64 s[60:61], %[smem]",
+        "s_mov_b64 s[62:63], %[smem]",
         "s_load_dwordx16 s[64:79], s[40:41], 0x0",
         "s_load_dwordx16 s[80:95], s[40:41], 0x40",
         "s_getpc_b64 s[42:43]",
@@ -200,11 +234,11 @@ def generate() -> str:
 def write(path: str) -> None:
     text = generate()
     body = "\n".join('    "' + ln.replace('"', '\\"') + '\\n"' for ln in text.splitlines())
-    clob = ", ".join([f'"v{i}"' for i in range(4, 12 + VSTACK)] + [f'"s{i}"' for i in range(40, 60)]
+    clob = ", ".join([f'"v{i}"' for i in range(4, 12 + VSTACK)] + [f'"s{i}"' for i in range(40, 64)]
                      + [f'"s{i}"' for i in range(64, 96)] + ['"m0"', '"vcc"', '"scc"'])
     src = ("// Generated by gen_interp.py: threaded-code interpreter for k_run.\n"
            f"#define EV_CODE_STRIDE {STRIDE}u\n#define EV_CODE_BLOCK {BLOCK}u\n#define EV_CODE_POS {POS}u\n"
-           f"#define EV_VSTACK {VSTACK}u\n#define EV_INTERP_CLOBBERS {clob}\n"
+           f"#define EV_VSTACK {VSTACK}u\n#define EV_VHALF {HALF}u\n#define EV_INTERP_CLOBBERS {clob}\n"
            + "".join(f"#define EV_K_{k} {i}u\n" for i, k in enumerate(KINDS))
            + "#define EV_INTERP_ASM \\\n" + body.replace("\n", " \\\n") + "\n")
     tmp = path + ".tmp"
