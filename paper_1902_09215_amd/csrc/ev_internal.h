@@ -30,6 +30,36 @@ struct ChunkStat {
     uint32_t code_in;   // slot-reading codes (must equal n_in)
 };
 
+// Structure segments (SEG_TOKENS tokens of one chunk).
+constexpr uint32_t SEG_TOKENS = 256;
+struct SegIn {
+    uint64_t start;
+    uint32_t len;
+    uint32_t last;  // holds the chunk's first token (read last)
+};
+
+struct ChunkSegs {
+    uint32_t first;  // first segment (token order)
+    uint32_t n_seg;
+};
+
+struct SegFn {
+    int32_t a, b;      // the segment maps cnt to max(cnt + a, b)
+    int32_t net;       // sum over tokens of (+1 function, -1 leaf)
+    int32_t minpref;   // minimum of that running sum before a token
+    uint32_t bad, n_in;
+    uint32_t left_x;   // its first token is an X
+    uint32_t pad;
+};
+
+struct SegStart {
+    uint32_t cnt, P;
+};
+
+struct SegCount {
+    uint32_t n_codes, n_frag, n_out, n_in, maxtop, pad;
+};
+
 // A work item of the register-stack kernel (16 bytes).
 struct RunChunk {
     uint64_t code_begin;  // index of its first code in the level's code stream

@@ -50,25 +50,12 @@ __device__ __forceinline__ float apply_op(uint32_t t, float a, float b)
     }
 }
 
-// -------------------------------------------- structure passes (integer)
-//
-// The stack machine of the evaluator, without values.  State:
-//   cnt  values of the chunk on the logical stack
-//   P    1 when the top of the stack is an X not yet written anywhere
-//   m    physical stack entries (entries below the register-held top,
-//        plus possibly one unused bottom entry)
-// A function meeting fewer than two values is a "spine" node: its subtree
-// leaves the chunk.  The value it would take from the chunk (at most one)
-// becomes a result slot (or stays an X when it is a bare input), and the
-// spine node itself goes into the skeleton.  At the chunk's first token all
-// values still on the stack become result slots.
-
 // ------------------------------------------------------ structure machine
 //
 // The right-to-left stack machine of both interpreters, run without values:
 //   tv  the top value T is live      P  an X sits on top, not yet placed
 //   m   values below T               base  of those, how many live in the
-//                                          wave's spill slab (multiple of
+//                                          wave's spill slab (a multiple of
 //                                          the half window)
 // A function meeting fewer than two values is a "spine" node: its subtree
 // leaves the chunk; the value it would take from the chunk (at most one)
@@ -78,8 +65,24 @@ __device__ __forceinline__ float apply_op(uint32_t t, float a, float b)
 // interpreter every action is also written as one code, an X folded into
 // the function or push that consumes it, and a push or load of x directly
 // followed by a function of x fused into one code; SPILL and FILL keep T
-// inside the window of EV_VSTACK register entries.  One implementation
-// serves counting and emission, so the two cannot disagree.
+// inside the window of EV_VSTACK register entries.
+//
+// The structure passes run in parallel over 256-token segments.  The number
+// of values on the stack, cnt, changes as cnt+1 for a leaf and max(cnt-1, 0)
+// for a function (spine included), maps of the form c -> max(c+a, b) that
+// compose associatively; so a per-segment map, folded over a chunk's
+// segments, gives each segment its starting state (cnt; P is whether the
+// previously read token was an X; tv and m follow).  The window is put in a
+// fixed position for the starting m at every segment boundary (extra SPILL
+// or FILL codes), so each segment's codes depend on its own tokens only.
+// One implementation serves counting and emission, so they cannot disagree.
+
+// Window base for a given m at a segment boundary: T at index m if m < 48,
+// else at an index in [16, 47].
+__device__ __forceinline__ uint32_t norm_base(uint32_t m)
+{
+    return m < EV_VSTACK - EV_VHALF / 2 ? 0u : (m - EV_VHALF / 2) / EV_VHALF * EV_VHALF;
+}
 
 struct Sink {
     uint16_t* codes;   // nullptr: count codes only
@@ -95,6 +98,13 @@ struct Sink {
         at++;
         n_codes++;
     }
+    __device__ void flush()
+    {
+        if (pending != ~0u) {
+            put(pending);
+            pending = ~0u;
+        }
+    }
     __device__ void code(uint32_t kind)
     {
         if (pending != ~0u) {
@@ -103,8 +113,7 @@ struct Sink {
                 pending = ~0u;
                 return;
             }
-            put(pending);
-            pending = ~0u;
+            flush();
         }
         if (kind == EV_K_PUSHX || kind == EV_K_LOADX) {
             pending = kind;
@@ -119,7 +128,7 @@ struct Sink {
     }
 };
 
-// Reads one chunk's tokens right to left, 16 bytes per load.
+// Reads tokens right to left, 16 bytes per load.
 struct RevTokens {
     const uint8_t* seq;
     uint64_t k, lo, wb;
@@ -141,24 +150,19 @@ struct RevTokens {
     }
 };
 
-struct MachineOut {
-    uint32_t maxtop;  // deepest m
-    int32_t net;      // sum over tokens of (+1 function, -1 leaf)
-    int32_t minpref;  // minimum of that running sum before a token
-    uint32_t bad;     // a token above max_tok
-};
-
-__device__ MachineOut run_machine(const uint8_t* __restrict__ seq, uint64_t start, uint32_t len, uint32_t max_tok,
-                                  Sink& o)
+// Machine over one segment from a given start.  last: the segment holding
+// the chunk's first token (it ends with the chunk's flush and END); other
+// segments end by putting the window in its boundary position.
+__device__ uint32_t run_segment(const uint8_t* __restrict__ seq, uint64_t start, uint32_t len, uint32_t cnt_in,
+                                uint32_t P_in, bool last, Sink& o)
 {
-    uint32_t tv = 0, P = 0, m = 0, base = 0, maxtop = 0, bad = 0;
-    int32_t R = 0, maxR = INT32_MIN;
+    uint32_t P = P_in;
+    uint32_t tv = cnt_in > P ? 1u : 0u;
+    uint32_t m = cnt_in - tv - P;
+    uint32_t base = norm_base(m), maxtop = m;
     RevTokens rt(seq, start, len);
     uint32_t t;
     while (rt.next(t)) {
-        bad |= t > max_tok;
-        R += t < TOK_X ? 1 : -1;
-        maxR = R > maxR ? R : maxR;
         if (t == TOK_X) {
             if (!P) {
                 P = 1;
@@ -213,7 +217,14 @@ __device__ MachineOut run_machine(const uint8_t* __restrict__ seq, uint64_t star
         }
         maxtop = m > maxtop ? m : maxtop;
     }
-    // chunk start: every value left becomes a slot, the bottom one first
+    if (!last) {
+        o.flush();
+        const uint32_t nb = norm_base(m);
+        while (base < nb) { o.put(EV_K_SPILL); base += EV_VHALF; }
+        while (base > nb) { o.put(EV_K_FILL); base -= EV_VHALF; }
+        return maxtop;
+    }
+    // the chunk's first token: every value left becomes a slot, bottom first
     if (base > 0) {
         o.code(EV_K_FLUSH);
         for (uint32_t i = 0; i < base; i++) o.code(EV_K_OUTMEM);
@@ -228,77 +239,184 @@ __device__ MachineOut run_machine(const uint8_t* __restrict__ seq, uint64_t star
     const uint32_t left = m + tv + P;
     o.n_out += left;
     for (uint32_t i = 0; i < left; i++) o.ftok(TOK_REF);
-    MachineOut r;
-    r.maxtop = maxtop;
-    r.net = R;
-    r.minpref = len ? R - maxR : 0;
+    return maxtop;
+}
+
+// Segments of a level: segment s of chunk c covers tokens
+// [c.start + s*SEG, ...) and is read after segment s+1.
+
+// Per segment: its cnt map (a, b), validity counters and input references.
+__global__ void k_seg_fn(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs, uint32_t n,
+                         SegFn* __restrict__ out, uint32_t max_tok)
+{
+    const uint32_t si = blockIdx.x * blockDim.x + threadIdx.x;
+    if (si >= n) return;
+    const SegIn g = segs[si];
+    int32_t a = 0, b = INT32_MIN / 2, R = 0, maxR = INT32_MIN;
+    uint32_t bad = 0, n_in = 0, last_t = 0;
+    RevTokens rt(seq, g.start, g.len);
+    uint32_t t;
+    while (rt.next(t)) {
+        bad |= t > max_tok;
+        n_in += t == TOK_REF;
+        if (t < TOK_X) {
+            a -= 1;
+            b = b - 1 > 0 ? b - 1 : 0;
+            R += 1;
+        } else {
+            a += 1;
+            b += 1;
+            R -= 1;
+        }
+        maxR = R > maxR ? R : maxR;
+        last_t = t;
+    }
+    SegFn f;
+    f.a = a;
+    f.b = b;
+    f.net = R;
+    f.minpref = R - maxR;
+    f.bad = bad;
+    f.n_in = n_in;
+    f.left_x = last_t == TOK_X;
+    f.pad = 0;
+    out[si] = f;
+}
+
+// Per chunk: fold the segment maps in reading order to give every segment
+// its start (cnt, P), and combine the validity counters in token order.
+__global__ void k_seg_scan(const ChunkSegs* __restrict__ cseg, uint32_t n, const SegFn* __restrict__ fn,
+                           SegStart* __restrict__ st, ChunkStat* __restrict__ cstat)
+{
+    const uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ci >= n) return;
+    const ChunkSegs cs = cseg[ci];
+    int32_t c = 0;
+    uint32_t P = 0;
+    for (uint32_t k = cs.n_seg; k-- > 0;) {
+        const SegFn f = fn[cs.first + k];
+        st[cs.first + k] = SegStart{(uint32_t)c, P};
+        c = c + f.a > f.b ? c + f.a : f.b;
+        P = f.left_x;
+    }
+    int32_t S = 0, minp = INT32_MAX;
+    uint32_t bad = 0;
+    for (uint32_t k = 0; k < cs.n_seg; k++) {
+        const SegFn f = fn[cs.first + k];
+        minp = S + f.minpref < minp ? S + f.minpref : minp;
+        S += f.net;
+        bad |= f.bad;
+    }
+    ChunkStat r = {};
+    r.net = S;
+    r.minpref = cs.n_seg ? minp : 0;
     r.bad = bad;
-    return r;
+    cstat[ci] = r;
 }
 
-__global__ void k_count(const uint8_t* __restrict__ seq, const ChunkIn* __restrict__ in, uint32_t n,
-                        ChunkStat* __restrict__ out, uint32_t max_tok)
+__global__ void k_seg_count(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs, uint32_t n,
+                            const SegStart* __restrict__ st, SegCount* __restrict__ out)
 {
-    const uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ci >= n) return;
-    const ChunkIn c = in[ci];
+    const uint32_t si = blockIdx.x * blockDim.x + threadIdx.x;
+    if (si >= n) return;
+    const SegIn g = segs[si];
     Sink o{nullptr, 0, nullptr, 0, 0, 0, 0, 0, ~0u};
-    const MachineOut r = run_machine(seq, c.start, c.len, max_tok, o);
-    ChunkStat s;
-    s.n_out = o.n_out;
-    s.n_frag = o.n_frag;
-    s.n_in = o.n_in;
-    s.max_m = r.maxtop + 1;
-    s.net = r.net;
-    s.minpref = r.minpref;
-    s.bad = r.bad;
-    s.n_codes = o.n_codes;
-    s.maxtop = r.maxtop;
-    s.code_out = o.n_out;
-    s.code_in = o.n_in;
-    out[ci] = s;
+    const uint32_t maxtop = run_segment(seq, g.start, g.len, st[si].cnt, st[si].P, g.last != 0, o);
+    out[si] = SegCount{o.n_codes, o.n_frag, o.n_out, o.n_in, maxtop, 0};
 }
 
-// Emission: the chunk's skeleton fragment (ending at frag_end[ci]) and, for
-// register-stack items, its codes (from code_begin[ci]).
-__global__ void k_emit(const uint8_t* __restrict__ seq, const ChunkIn* __restrict__ in,
-                       const uint64_t* __restrict__ frag_end, const uint64_t* __restrict__ code_begin, uint32_t n,
-                       uint8_t* __restrict__ dst, uint16_t* __restrict__ codes)
+// Per chunk: totals for the plan, and each segment's code and fragment
+// positions once the chunk's own bases are known (second launch).
+__global__ void k_seg_chunk(const ChunkSegs* __restrict__ cseg, uint32_t n, const SegCount* __restrict__ cnt,
+                            ChunkStat* __restrict__ cstat, const uint64_t* __restrict__ code_begin,
+                            const uint64_t* __restrict__ frag_end, uint64_t* __restrict__ seg_code,
+                            uint64_t* __restrict__ seg_frag)
 {
     const uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
     if (ci >= n) return;
-    const ChunkIn c = in[ci];
-    const bool has_codes = codes && code_begin[ci] != ~0ull;
+    const ChunkSegs cs = cseg[ci];
+    if (!code_begin) {
+        uint32_t nc = 0, nf = 0, no = 0, ni = 0, mt = 0;
+        for (uint32_t k = 0; k < cs.n_seg; k++) {
+            const SegCount s = cnt[cs.first + k];
+            nc += s.n_codes;
+            nf += s.n_frag;
+            no += s.n_out;
+            ni += s.n_in;
+            mt = s.maxtop > mt ? s.maxtop : mt;
+        }
+        ChunkStat r = cstat[ci];
+        r.n_codes = nc;
+        r.n_frag = nf;
+        r.n_out = no;
+        r.n_in = ni;
+        r.maxtop = mt;
+        r.max_m = mt + 1;
+        r.code_out = no;
+        r.code_in = ni;
+        cstat[ci] = r;
+        return;
+    }
+    // codes run in reading order (last segment first); fragments and slots
+    // lie in token order
+    uint64_t at = code_begin[ci];
+    for (uint32_t k = cs.n_seg; k-- > 0;) {
+        seg_code[cs.first + k] = at == ~0ull ? ~0ull : at;
+        if (at != ~0ull) at += cnt[cs.first + k].n_codes;
+    }
+    uint64_t w = frag_end ? frag_end[ci] : 0;
+    for (uint32_t k = cs.n_seg; k-- > 0;) {
+        seg_frag[cs.first + k] = w;
+        w -= cnt[cs.first + k].n_frag;
+    }
+}
+
+__global__ void k_seg_emit(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs, uint32_t n,
+                           const SegStart* __restrict__ st, const uint64_t* __restrict__ seg_code,
+                           const uint64_t* __restrict__ seg_frag, uint8_t* __restrict__ dst, uint16_t* __restrict__ codes)
+{
+    const uint32_t si = blockIdx.x * blockDim.x + threadIdx.x;
+    if (si >= n) return;
+    const SegIn g = segs[si];
+    const bool has_codes = codes && seg_code[si] != ~0ull;
     if (!dst && !has_codes) return;
-    Sink o{has_codes ? codes : nullptr, has_codes ? code_begin[ci] : 0, dst, dst ? frag_end[ci] : 0, 0, 0, 0, 0, ~0u};
-    run_machine(seq, c.start, c.len, TOK_REF, o);
+    Sink o{has_codes ? codes : nullptr, has_codes ? seg_code[si] : 0, dst, dst ? seg_frag[si] : 0, 0, 0, 0, 0, ~0u};
+    run_segment(seq, g.start, g.len, st[si].cnt, st[si].P, g.last != 0, o);
 }
 
-// Every code of a register-stack item must name a handler of its own
-// position and the item must end with its only END; simulating the codes
-// must keep T inside the register window, every read entry below it, the
-// slab within its entries, and must write and read exactly the slots the
-// plan gave the item.  Anything else fails the plan before a code runs.
-__global__ void k_check_codes(const uint16_t* __restrict__ codes, const uint64_t* __restrict__ begin,
-                              const uint32_t* __restrict__ expect, uint32_t n, uint32_t slab_entries,
-                              uint32_t* __restrict__ err)
+// Every code must name a handler of its own position and only a chunk's
+// last segment may (and must) end with END; simulating the codes from the
+// segment's start must keep T inside the register window, every read entry
+// below it, the slab within its rows, must end with the window in its
+// boundary position and must write and read exactly the slots the plan
+// gave the segment.  Anything else fails the plan before a code runs.
+__global__ void k_seg_check(const uint16_t* __restrict__ codes, const SegIn* __restrict__ segs, uint32_t n,
+                            const SegStart* __restrict__ st, const uint64_t* __restrict__ seg_code,
+                            const SegCount* __restrict__ cnt, uint32_t slab_entries, uint32_t* __restrict__ err)
 {
-    const uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ci >= n) return;
-    const uint64_t b = begin[ci];
-    const uint32_t len = expect[3 * ci], want_out = expect[3 * ci + 1], want_in = expect[3 * ci + 2];
-    uint32_t outs = 0, ins = 0, bad = len == 0;
-    int32_t idx = 0, slab = 0, fl = 0;
+    const uint32_t si = blockIdx.x * blockDim.x + threadIdx.x;
+    if (si >= n) return;
+    const uint64_t b = seg_code[si];
+    if (b == ~0ull) return;
+    const SegIn g = segs[si];
+    const SegCount sc = cnt[si];
+    const uint32_t len = sc.n_codes;
+    const uint32_t P = st[si].P, tv = st[si].cnt > P ? 1u : 0u, m0 = st[si].cnt - tv - P;
+    int32_t slab = (int32_t)norm_base(m0), idx = (int32_t)(m0 - (uint32_t)slab), fl = 0;
+    uint32_t outs = 0, ins = 0, bad = 0, ended = 0, m = m0;
     for (uint32_t i = 0; i < len; i++) {
         const uint32_t v = codes[b + i];
         const uint32_t pos = v / EV_CODE_BLOCK, r = v % EV_CODE_BLOCK, k = r / EV_CODE_STRIDE;
         if (r % EV_CODE_STRIDE || pos != (uint32_t)((b + i) & (EV_CODE_POS - 1)) || k > EV_K_OUTMEM) bad = 1;
-        if ((k == EV_K_END) != (i + 1 == len)) bad = 1;
+        bad |= ended;
+        if (k == EV_K_END) ended = 1;
         if (k <= EV_K_OPS3) {
             bad |= idx < 1;
             idx--;
+            m--;
         } else if ((k >= EV_K_CH0 && k <= EV_K_CH3) || k == EV_K_PUSHX || k == EV_K_PUSHREF) {
             idx++;
+            m++;
         } else if (k == EV_K_FLUSH) {
             fl = 0;
         } else if (k == EV_K_OUTBOT) {
@@ -312,7 +430,7 @@ __global__ void k_check_codes(const uint16_t* __restrict__ codes, const uint64_t
             idx -= EV_VHALF;
             slab += EV_VHALF;
         } else if (k == EV_K_FILL) {
-            bad |= slab < (int32_t)EV_VHALF || idx != 0;
+            bad |= slab < (int32_t)EV_VHALF || idx > (int32_t)EV_VHALF - 1;
             idx += EV_VHALF;
             slab -= EV_VHALF;
         }
@@ -320,7 +438,10 @@ __global__ void k_check_codes(const uint16_t* __restrict__ codes, const uint64_t
         outs += (k == EV_K_OUTT || k == EV_K_OUTX || k == EV_K_OUTBOT || k == EV_K_OUTMEM);
         ins += (k == EV_K_PUSHREF || k == EV_K_LOADREF);
     }
-    if (bad || outs != want_out || ins != want_in) atomicOr(err, 1u);
+    bad |= (ended != 0) != (g.last != 0);
+    // a segment hands the next one the window in its boundary position
+    if (!g.last) bad |= (uint32_t)slab != norm_base((uint32_t)(idx + slab));
+    if (bad || outs != sc.n_out || ins != sc.n_in) atomicOr(err, 1u);
 }
 
 // ------------------------------------------------------------ evaluation
@@ -678,19 +799,55 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_count(const uint8_t* seq, const ChunkIn* in, uint32_t n, ChunkStat* out, uint32_t max_tok,
-                        hipStream_t s)
+hipError_t launch_seg_fn(const uint8_t* seq, const SegIn* segs, uint32_t n, SegFn* out, uint32_t max_tok,
+                         hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, in, n, out, max_tok);
+    hipLaunchKernelGGL(k_seg_fn, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, out, max_tok);
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const uint8_t* seq, const ChunkIn* in, const uint64_t* frag_end, const uint64_t* code_begin,
-                       uint32_t n, uint8_t* dst, uint16_t* codes, hipStream_t s)
+hipError_t launch_seg_scan(const ChunkSegs* cseg, uint32_t n, const SegFn* fn, SegStart* st, ChunkStat* cstat,
+                           hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, in, frag_end, code_begin, n, dst, codes);
+    hipLaunchKernelGGL(k_seg_scan, dim3(cdiv(n, 64)), dim3(64), 0, s, cseg, n, fn, st, cstat);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_count(const uint8_t* seq, const SegIn* segs, uint32_t n, const SegStart* st, SegCount* out,
+                            hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_count, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, st, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_chunk(const ChunkSegs* cseg, uint32_t n, const SegCount* cnt, ChunkStat* cstat,
+                            const uint64_t* code_begin, const uint64_t* frag_end, uint64_t* seg_code, uint64_t* seg_frag,
+                            hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_chunk, dim3(cdiv(n, 64)), dim3(64), 0, s, cseg, n, cnt, cstat, code_begin, frag_end,
+                       seg_code, seg_frag);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_emit(const uint8_t* seq, const SegIn* segs, uint32_t n, const SegStart* st, const uint64_t* seg_code,
+                           const uint64_t* seg_frag, uint8_t* dst, uint16_t* codes, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_emit, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, st, seg_code, seg_frag, dst, codes);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_check(const uint16_t* codes, const SegIn* segs, uint32_t n, const SegStart* st,
+                            const uint64_t* seg_code, const SegCount* cnt, uint32_t slab_entries, uint32_t* err,
+                            hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_check, dim3(cdiv(n, 64)), dim3(64), 0, s, codes, segs, n, st, seg_code, cnt, slab_entries,
+                       err);
     return hipGetLastError();
 }
 
@@ -728,13 +885,6 @@ hipError_t launch_run(const RunArgs& a, uint32_t grid, hipStream_t s)
 }
 
 
-hipError_t launch_check_codes(const uint16_t* codes, const uint64_t* begin, const uint32_t* expect, uint32_t n,
-                              uint32_t slab_entries, uint32_t* err, hipStream_t s)
-{
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_check_codes, dim3(cdiv(n, 64)), dim3(64), 0, s, codes, begin, expect, n, slab_entries, err);
-    return hipGetLastError();
-}
 
 hipError_t launch_fitness(const uint64_t* rows, const float* y, int32_t N, uint32_t M, float* fit, float* per_case,
                           hipStream_t s)

@@ -6,18 +6,27 @@
 
 namespace ev {
 hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
-hipError_t launch_count(const uint8_t* seq, const ChunkIn* in, uint32_t n, ChunkStat* out, uint32_t max_tok,
-                        hipStream_t s);
-hipError_t launch_emit(const uint8_t* seq, const ChunkIn* in, const uint64_t* frag_end, const uint64_t* code_begin,
-                       uint32_t n, uint8_t* dst, uint16_t* codes, hipStream_t s);
+hipError_t launch_seg_fn(const uint8_t* seq, const SegIn* segs, uint32_t n, SegFn* out, uint32_t max_tok,
+                         hipStream_t s);
+hipError_t launch_seg_scan(const ChunkSegs* cseg, uint32_t n, const SegFn* fn, SegStart* st, ChunkStat* cstat,
+                           hipStream_t s);
+hipError_t launch_seg_count(const uint8_t* seq, const SegIn* segs, uint32_t n, const SegStart* st, SegCount* out,
+                            hipStream_t s);
+hipError_t launch_seg_chunk(const ChunkSegs* cseg, uint32_t n, const SegCount* cnt, ChunkStat* cstat,
+                            const uint64_t* code_begin, const uint64_t* frag_end, uint64_t* seg_code, uint64_t* seg_frag,
+                            hipStream_t s);
+hipError_t launch_seg_emit(const uint8_t* seq, const SegIn* segs, uint32_t n, const SegStart* st, const uint64_t* seg_code,
+                           const uint64_t* seg_frag, uint8_t* dst, uint16_t* codes, hipStream_t s);
+hipError_t launch_seg_check(const uint16_t* codes, const SegIn* segs, uint32_t n, const SegStart* st,
+                            const uint64_t* seg_code, const SegCount* cnt, uint32_t slab_entries, uint32_t* err,
+                            hipStream_t s);
 size_t eval_lds_bytes(int D);
 hipError_t eval_occupancy(int D, int* blocks_per_cu);
 hipError_t launch_eval(int D, const EvalArgs& a, uint32_t grid, hipStream_t s);
 hipError_t run_occupancy(int* blocks_per_cu);
 hipError_t launch_run(const RunArgs& a, uint32_t grid, hipStream_t s);
 
-hipError_t launch_check_codes(const uint16_t* codes, const uint64_t* begin, const uint32_t* expect, uint32_t n,
-                              uint32_t slab_entries, uint32_t* err, hipStream_t s);
+
 hipError_t launch_fitness(const uint64_t* rows, const float* y, int32_t N, uint32_t M, float* fit, float* per_case,
                           hipStream_t s);
 hipError_t launch_subtree_end(const uint8_t* buf, const uint64_t* base, const uint64_t* pos, uint32_t n,

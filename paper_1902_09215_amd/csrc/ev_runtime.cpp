@@ -36,44 +36,87 @@ ev_status hip_fail(hipError_t e, const char* what)
 
 // ------------------------------------------------------------- memory
 
+// Device memory goes through a per-context cache: freed blocks are kept in
+// size classes and handed out again, so the plan and crossover temporaries
+// of every generation cost no hipMalloc/hipFree (hipFree synchronizes the
+// device).  A block is only ever freed after the stream that used it has
+// been synchronized.  The budget bounds live bytes; cached blocks are
+// released first when the device runs short.
+static size_t size_class(size_t bytes)
+{
+    if (bytes <= 256) return 256;
+    if (bytes <= (256ull << 20)) {
+        size_t c = 256;
+        while (c < bytes) c <<= 1;
+        return c;
+    }
+    const size_t g = 64ull << 20;
+    return (bytes + g - 1) / g * g;
+}
+
+static void cache_release(ev_ctx* c)
+{
+    for (auto& kv : c->cache)
+        for (void* p : kv.second) (void)hipFree(p);
+    c->cache.clear();
+    c->cached = 0;
+}
+
 ev_status dev_alloc(ev_ctx* c, size_t bytes, void** out)
 {
     *out = nullptr;
-    if (bytes == 0) bytes = 256;
+    const size_t cls = size_class(bytes);
     {
         std::lock_guard<std::mutex> g(c->mem_mu);
-        if (c->budget && c->in_use + bytes > c->budget)
-            return fail(EV_ENOMEM, "memory budget exceeded (%zu + %zu > %zu bytes)", (size_t)c->in_use, bytes,
+        if (c->budget && c->in_use + cls > c->budget)
+            return fail(EV_ENOMEM, "memory budget exceeded (%zu + %zu > %zu bytes)", (size_t)c->in_use, cls,
                         (size_t)c->budget);
-        c->in_use += bytes;
+        auto it = c->cache.find(cls);
+        if (it != c->cache.end() && !it->second.empty()) {
+            *out = it->second.back();
+            it->second.pop_back();
+            c->cached -= cls;
+            c->in_use += cls;
+            c->sizes[*out] = cls;
+            return EV_OK;
+        }
+        c->in_use += cls;
     }
-    hipError_t e = hipMalloc(out, bytes);
+    hipError_t e = hipMalloc(out, cls);
     if (e != hipSuccess) {
-        std::lock_guard<std::mutex> g(c->mem_mu);
-        c->in_use -= bytes;
-        *out = nullptr;
         (void)hipGetLastError();
-        return fail(EV_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        std::lock_guard<std::mutex> g(c->mem_mu);
+        cache_release(c);
+        e = hipMalloc(out, cls);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            c->in_use -= cls;
+            *out = nullptr;
+            return fail(EV_ENOMEM, "hipMalloc(%zu): %s", cls, hipGetErrorString(e));
+        }
     }
     std::lock_guard<std::mutex> g(c->mem_mu);
-    c->sizes[*out] = bytes;
+    c->sizes[*out] = cls;
     return EV_OK;
 }
 
 void dev_free(ev_ctx* c, void* p)
 {
     if (!p) return;
-    size_t bytes = 0;
-    {
-        std::lock_guard<std::mutex> g(c->mem_mu);
-        auto it = c->sizes.find(p);
-        if (it != c->sizes.end()) {
-            bytes = it->second;
-            c->sizes.erase(it);
-        }
-        c->in_use -= bytes;
-    }
-    (void)hipFree(p);
+    std::lock_guard<std::mutex> g(c->mem_mu);
+    auto it = c->sizes.find(p);
+    if (it == c->sizes.end()) return;
+    const size_t cls = it->second;
+    c->sizes.erase(it);
+    c->in_use -= cls;
+    c->cache[cls].push_back(p);
+    c->cached += cls;
+}
+
+void dev_cache_release(ev_ctx* c)
+{
+    std::lock_guard<std::mutex> g(c->mem_mu);
+    cache_release(c);
 }
 
 // ------------------------------------------------------------- plans
@@ -143,26 +186,47 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
     uint8_t* cur = P->d_bytes;
     bool cur_owned = false;
     int level = 0;
-    void *d_in = nullptr, *d_stat = nullptr, *d_frag = nullptr, *d_cb = nullptr;
+    // per-level device scratch: segments, their maps/starts/counts/positions
+    void *d_seg = nullptr, *d_cseg = nullptr, *d_fn = nullptr, *d_st = nullptr, *d_cnt = nullptr, *d_stat = nullptr,
+         *d_cb = nullptr, *d_fe = nullptr, *d_scode = nullptr, *d_sfrag = nullptr, *d_err = nullptr;
     ev_status st = EV_OK;
     auto cleanup = [&]() {
-        dev_free(c, d_in);
-        dev_free(c, d_stat);
-        dev_free(c, d_frag);
-        dev_free(c, d_cb);
-        d_in = d_stat = d_frag = d_cb = nullptr;
+        for (void** p : {&d_seg, &d_cseg, &d_fn, &d_st, &d_cnt, &d_stat, &d_cb, &d_fe, &d_scode, &d_sfrag, &d_err}) {
+            dev_free(c, *p);
+            *p = nullptr;
+        }
     };
+    auto realloc = [&](void** p, size_t bytes) -> ev_status {
+        dev_free(c, *p);
+        *p = nullptr;
+        return dev_alloc(c, bytes, p);
+    };
+    uint32_t n_seg = 0;
+    // count pass over a level's chunks: per-chunk totals in cs
     auto count = [&](const std::vector<ChunkIn>& ch, std::vector<ChunkStat>& cs) -> ev_status {
         const uint32_t n = (uint32_t)ch.size();
-        dev_free(c, d_in);
-        dev_free(c, d_stat);
-        d_in = d_stat = nullptr;
+        std::vector<SegIn> sg;
+        std::vector<ChunkSegs> cg(n);
+        for (uint32_t j = 0; j < n; j++) {
+            cg[j].first = (uint32_t)sg.size();
+            for (uint64_t o = 0; o < ch[j].len; o += SEG_TOKENS)
+                sg.push_back(SegIn{ch[j].start + o, (uint32_t)std::min<uint64_t>(SEG_TOKENS, ch[j].len - o), o == 0 ? 1u : 0u});
+            cg[j].n_seg = (uint32_t)sg.size() - cg[j].first;
+        }
+        n_seg = (uint32_t)sg.size();
         ev_status e;
-        if ((e = dev_alloc(c, n * sizeof(ChunkIn), &d_in)) != EV_OK) return e;
-        if ((e = dev_alloc(c, n * sizeof(ChunkStat), &d_stat)) != EV_OK) return e;
+        if ((e = realloc(&d_seg, n_seg * sizeof(SegIn))) || (e = realloc(&d_cseg, n * sizeof(ChunkSegs))) ||
+            (e = realloc(&d_fn, n_seg * sizeof(SegFn))) || (e = realloc(&d_st, n_seg * sizeof(SegStart))) ||
+            (e = realloc(&d_cnt, n_seg * sizeof(SegCount))) || (e = realloc(&d_stat, n * sizeof(ChunkStat))))
+            return e;
         cs.resize(n);
-        HIPCHK(hipMemcpyAsync(d_in, ch.data(), n * sizeof(ChunkIn), hipMemcpyHostToDevice, s));
-        HIPCHK(launch_count(cur, (ChunkIn*)d_in, n, (ChunkStat*)d_stat, level == 0 ? TOK_X : TOK_REF, s));
+        HIPCHK(hipMemcpyAsync(d_seg, sg.data(), n_seg * sizeof(SegIn), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_cseg, cg.data(), n * sizeof(ChunkSegs), hipMemcpyHostToDevice, s));
+        HIPCHK(launch_seg_fn(cur, (SegIn*)d_seg, n_seg, (SegFn*)d_fn, level == 0 ? TOK_X : TOK_REF, s));
+        HIPCHK(launch_seg_scan((ChunkSegs*)d_cseg, n, (SegFn*)d_fn, (SegStart*)d_st, (ChunkStat*)d_stat, s));
+        HIPCHK(launch_seg_count(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (SegCount*)d_cnt, s));
+        HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, n, (SegCount*)d_cnt, (ChunkStat*)d_stat, nullptr, nullptr, nullptr,
+                                nullptr, s));
         HIPCHK(hipMemcpyAsync(cs.data(), d_stat, n * sizeof(ChunkStat), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         return EV_OK;
@@ -316,61 +380,39 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             }
         }
 
-        // one pass writes the next level's skeleton and this level's codes
+        // one pass writes the next level's skeleton and this level's codes,
+        // then every code stream is validated before anything may run it
         uint8_t* d_next = nullptr;
-        if (any) {
-            if ((st = dev_alloc(c, sf + 64, (void**)&d_next)) != EV_OK) { cleanup(); return st; }
-            HIPCHK(hipMemsetAsync(d_next, 0xFF, sf + 64, s));
-            dev_free(c, d_frag);
-            d_frag = nullptr;
-            if ((st = dev_alloc(c, n * sizeof(uint64_t), &d_frag)) != EV_OK) { dev_free(c, d_next); cleanup(); return st; }
-            HIPCHK(hipMemcpyAsync(d_frag, frag_end.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-        }
+        if (any && (st = dev_alloc(c, sf + 64, (void**)&d_next)) != EV_OK) { cleanup(); return st; }
+        if (any) HIPCHK(hipMemsetAsync(d_next, 0xFF, sf + 64, s));
         if (any || !run.empty()) {
-            dev_free(c, d_cb);
-            d_cb = nullptr;
-            if ((st = dev_alloc(c, n * sizeof(uint64_t), &d_cb)) != EV_OK) { dev_free(c, d_next); cleanup(); return st; }
-            HIPCHK(hipMemcpyAsync(d_cb, code_begin.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-            HIPCHK(launch_emit(cur, (ChunkIn*)d_in, (uint64_t*)d_frag, (uint64_t*)d_cb, n, d_next,
-                               run.empty() ? nullptr : LL.codes, s));
-        }
-        if (!run.empty()) {
-            // validate the emitted codes before anything may run them
-            std::vector<uint64_t> vb;
-            std::vector<uint32_t> ve;
-            for (uint32_t j = 0; j < n; j++) {
-                if (!fast[j]) continue;
-                vb.push_back(code_begin[j]);
-                ve.push_back(cs[j].n_codes);
-                ve.push_back(cs[j].n_out);
-                ve.push_back(cs[j].n_in);
-            }
-            void *d_vb = nullptr, *d_ve = nullptr, *d_err = nullptr;
-            if ((st = dev_alloc(c, vb.size() * 8, &d_vb)) || (st = dev_alloc(c, ve.size() * 4, &d_ve)) ||
-                (st = dev_alloc(c, 4, &d_err))) {
-                dev_free(c, d_vb); dev_free(c, d_ve); dev_free(c, d_next); cleanup();
+            if ((st = realloc(&d_cb, n * sizeof(uint64_t))) || (st = realloc(&d_fe, n * sizeof(uint64_t))) ||
+                (st = realloc(&d_scode, n_seg * sizeof(uint64_t))) || (st = realloc(&d_sfrag, n_seg * sizeof(uint64_t))) ||
+                (st = realloc(&d_err, 4))) {
+                dev_free(c, d_next);
+                cleanup();
                 return st;
             }
             uint32_t err = 0;
-            HIPCHK(hipMemcpyAsync(d_vb, vb.data(), vb.size() * 8, hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(d_ve, ve.data(), ve.size() * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(d_cb, code_begin.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(d_fe, frag_end.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
             HIPCHK(hipMemcpyAsync(d_err, &err, 4, hipMemcpyHostToDevice, s));
-            HIPCHK(launch_check_codes(LL.codes, (uint64_t*)d_vb, (uint32_t*)d_ve, (uint32_t)vb.size(), LL.slab_entries,
-                                      (uint32_t*)d_err, s));
+            HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, n, (SegCount*)d_cnt, (ChunkStat*)d_stat, (uint64_t*)d_cb,
+                                    (uint64_t*)d_fe, (uint64_t*)d_scode, (uint64_t*)d_sfrag, s));
+            HIPCHK(launch_seg_emit(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode, (uint64_t*)d_sfrag,
+                                   d_next, run.empty() ? nullptr : LL.codes, s));
+            if (!run.empty())
+                HIPCHK(launch_seg_check(LL.codes, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode,
+                                        (SegCount*)d_cnt, LL.slab_entries, (uint32_t*)d_err, s));
             HIPCHK(hipMemcpyAsync(&err, d_err, 4, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            dev_free(c, d_vb);
-            dev_free(c, d_ve);
-            dev_free(c, d_err);
             if (err) { dev_free(c, d_next); cleanup(); return fail(EV_EDEVICE, "internal: malformed code stream at level %d", level); }
-        } else {
-            HIPCHK(hipStreamSynchronize(s));
         }
         if (!any) break;
         cur = d_next;
         cur_owned = true;
         level++;
-        if (level > 64) { dev_free(c, d_next); cleanup(); return fail(EV_ECAP, "split plan did not converge"); }
+        if (level > 64) { dev_free(c, cur); cleanup(); return fail(EV_ECAP, "split plan did not converge"); }
     }
     cleanup();
     pl.bytes = 0;
@@ -731,6 +773,7 @@ ev_status ev_destroy(ev_ctx* c)
     c->pops.clear();
     for (auto& t : c->tables) { dev_free(c, t.d_x); dev_free(c, t.d_y); }
     exec_free(c, c->main);
+    dev_cache_release(c);
     delete c;
     return EV_OK;
 }

@@ -98,7 +98,9 @@ struct ev_ctx {
 
     std::mutex mem_mu;
     uint64_t budget = 0, in_use = 0;
-    std::unordered_map<void*, size_t> sizes;
+    std::unordered_map<void*, size_t> sizes;   // live blocks and their size class
+    std::map<size_t, std::vector<void*>> cache;  // freed blocks by size class
+    uint64_t cached = 0;
 
     std::mutex pop_mu;
     std::vector<ev::CaseTable> tables;
@@ -117,6 +119,7 @@ ev_status hip_fail(hipError_t e, const char* what);
 
 ev_status dev_alloc(ev_ctx* c, size_t bytes, void** out);
 void dev_free(ev_ctx* c, void* p);
+void dev_cache_release(ev_ctx* c);
 
 ev_status exec_init(Exec& x, hipStream_t given);
 void exec_free(ev_ctx* c, Exec& x);
