@@ -7,7 +7,8 @@ namespace ev {
 enum : uint32_t { TOK_ADD = 0, TOK_SUB = 1, TOK_MUL = 2, TOK_DIV = 3, TOK_X = 4, TOK_REF = 5 };
 
 // Register-stack entries of k_run (the interpreter's VGPR window).
-constexpr uint32_t EV_VSTACK_ENTRIES = 64;
+#include "ev_interp.inc"
+constexpr uint32_t EV_VSTACK_ENTRIES = EV_VSTACK;
 
 // A work item of the split plan as the structure passes see it.
 struct ChunkIn {

@@ -33,7 +33,7 @@ import os
 import sys
 
 STRIDE = 64
-VSTACK = 64  # register-stack entries: v12 .. v12+VSTACK-1
+VSTACK = int(os.environ.get("EV_VSTACK", "64"))  # register-stack entries: v12 .. v12+VSTACK-1
 HALF = VSTACK // 2  # entries moved by one spill or fill
 KINDS = ["OPS0", "OPS1", "OPS2", "OPS3", "OPX0", "OPX1", "OPX2", "OPX3",
          "CH0", "CH1", "CH2", "CH3", "LCH0", "LCH1", "LCH2", "LCH3",
