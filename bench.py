@@ -38,10 +38,23 @@ def pct(a, q):
 
 def cpu_baseline(buf, off, x, y, fit, n_cases, budget_s=12.0):
     """The oracle as it stands, on the host cores: generations of the same
-    population (sequential selection + crossover, threaded evaluation)."""
+    population (sequential selection + crossover, threaded evaluation); for
+    populations too large for that, the evaluation of the smallest trees."""
     import oracle
 
     threads = min(os.cpu_count() or 1, 64)
+    if int(off[-1]) > 2e8:
+        sizes = np.diff(off)
+        order = np.argsort(sizes)
+        take = [int(t) for t in order[:threads]]
+        parts = [buf[off[t]:off[t + 1]] for t in take]
+        soff = np.zeros(len(parts) + 1, np.uint64)
+        np.cumsum([p.size for p in parts], out=soff[1:])
+        t0 = time.perf_counter()
+        oracle.eval_population(np.concatenate(parts), soff, x, y, threads=threads)
+        el = time.perf_counter() - t0
+        return {"value": int(soff[-1]) * n_cases / el, "unit": "GPops/s", "cores": threads, "kind": "oracle",
+                "sample": f"oracle evaluation of the {len(take)} smallest trees ({int(soff[-1])} nodes), {el:.1f} s"}
     done_nodes, t0, gens = 0, time.perf_counter(), 0
     while True:
         cbuf, coff, _ = oracle.generation(buf, off, fit, 2, 1234, 10_000 + gens, 15_000_000)
@@ -56,6 +69,116 @@ def cpu_baseline(buf, off, x, y, fit, n_cases, budget_s=12.0):
                       f"(selection+crossover single-threaded, evaluation on {threads} threads), {el:.1f} s"}
 
 
+def serve_bench(args, ev, workloads):
+    """Serving: a Poisson stream of evaluation (80%) and crossover (20%)
+    requests, one tree per evaluation request with sizes log-uniform in
+    [10, 1e8], 48 or 1024 cases, against the same stream served FIFO one
+    request at a time with no batching or overlap (the plain form)."""
+    rng = np.random.default_rng(0x5EED0005)
+    x48, y48 = workloads.cases(48)
+    x1k, y1k = workloads.cases(1024)
+    # a pool of distinct trees that the requests draw from
+    pool_sizes = workloads.loguniform_sizes(0x5EED0005, 256, 10, 1e8)
+    pbuf, poff = workloads.random_population(0x5EED0005, pool_sizes)
+    c = ev.Context(x48, y48, device=0, mem_budget=200 << 30)
+    t1k = c.add_cases(x1k, y1k)
+    par_sizes = workloads.loguniform_sizes(0x5EED0006, 64, 10, 1e6)
+    par_buf, par_off = workloads.random_population(0x5EED0006, par_sizes)
+    parents = c.load(par_buf, par_off)
+    c.eval(parents)
+    reqs = []
+    for i in range(args.requests):
+        table = 0 if rng.random() < 0.5 else t1k
+        if rng.random() < 0.8:
+            t = int(rng.integers(0, pool_sizes.size))
+            reqs.append(("eval", table, t, int(pool_sizes[t])))
+        else:
+            k = 4
+            mum = rng.integers(0, 64, k).astype(np.int32)
+            dad = rng.integers(0, 64, k).astype(np.int32)
+            p = np.array([rng.integers(0, par_sizes[m]) for m in mum], np.uint64)
+            q = np.array([rng.integers(0, par_sizes[d]) for d in dad], np.uint64)
+            nodes = int(sum(par_sizes[m] for m in mum))
+            reqs.append(("xo", table, (mum, dad, p, q), nodes))
+
+    def tree(t):
+        b = pbuf[poff[t]:poff[t + 1]]
+        return b, np.array([0, b.size], np.uint64)
+
+    def submit(r):
+        kind, table, arg, _ = r
+        if kind == "eval":
+            b, o = tree(arg)
+            return ev.ev_submit_eval(c.ctx, b, o, table)
+        mum, dad, p, q = arg
+        return ev.ev_submit_crossover(c.ctx, parents, mum, dad, p, q, table)
+
+    def n_cases(table):
+        return 48 if table == 0 else 1024
+
+    # plain service times: each request alone, synchronously, one at a time
+    service = []
+    for r in reqs[: min(len(reqs), 400)]:
+        t0 = time.perf_counter()
+        tk = submit(r)
+        ev.ev_wait(c.ctx, tk)
+        service.append(time.perf_counter() - t0)
+        ev.ev_result(c.ctx, tk, 8, n_cases(r[1]))
+    service = np.array(service)
+    mean_service = float(service.mean())
+    # offered load: arrivals at rate load / (mean service time of the plain form)
+    lam = args.load / mean_service
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, len(reqs)))
+    # plain FIFO server under that stream (service times resampled)
+    svc = np.resize(service, len(reqs))
+    done_plain = np.empty(len(reqs))
+    t_free = 0.0
+    for i, a in enumerate(arrivals):
+        start = max(a, t_free)
+        t_free = done_plain[i] = start + svc[i]
+    lat_plain = (done_plain - arrivals) * 1e3
+    # served: open loop, continuous batching inside libev
+    tickets = []
+    t_start = time.perf_counter()
+    for i, r in enumerate(reqs):
+        now = time.perf_counter() - t_start
+        if arrivals[i] > now:
+            time.sleep(arrivals[i] - now)
+        tickets.append((submit(r), r, time.perf_counter()))
+    lat, work = [], 0
+    for tk, r, t_sub in tickets:
+        ev.ev_wait(c.ctx, tk)
+        s_ns, _, d_ns = ev.ev_job_timing(c.ctx, tk)
+        lat.append((d_ns - s_ns) / 1e6)
+        work += r[3] * n_cases(r[1])
+        ev.ev_result(c.ctx, tk, 8, n_cases(r[1]))
+    makespan = time.perf_counter() - t_start
+    line = {
+        "metric": "GPops/s (tree nodes x fitness cases /s) on 1 MI355X; p99 eval latency",
+        "value": work / makespan,
+        "unit": "GPops/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": 0,
+        "ms_per_step": makespan / len(reqs) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serving: Poisson stream, 80% eval / 20% crossover, trees log-uniform 10..1e8 "
+                               "nodes, 48 or 1024 cases, 200 GB memory budget",
+                   "requests": len(reqs), "offered_load": args.load},
+        "p50_latency_ms": pct(lat, 50),
+        "p99_latency_ms": pct(lat, 99),
+        "plain_fifo": {"p50_latency_ms": pct(lat_plain, 50), "p99_latency_ms": pct(lat_plain, 99),
+                       "mean_service_ms": mean_service * 1e3,
+                       "gpops_per_s": work / max(done_plain[-1], 1e-9)},
+    }
+    print(json.dumps(line), flush=True)
+    c.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +189,10 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--lds", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--plain-trees", type=int, default=300)
+    ap.add_argument("--cap", type=int, default=15_000_000, help="child size cap of the generation step")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
+    ap.add_argument("--load", type=float, default=0.8, help="serving: offered load as a fraction of capacity")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the evaluation path of this build is single-GPU "
@@ -75,6 +202,8 @@ def main():
     import paper_1902_09215_amd as ev
     import workloads
 
+    if args.workload == "serving":
+        return serve_bench(args, ev, workloads)
     buf, off, n_cases = workloads.workload(args.workload)
     x, y = workloads.cases(n_cases)
     M = off.size - 1
@@ -106,14 +235,14 @@ def main():
     # ---- generation steps (the whole hot path)
     seed = 0x5EED
     for w in range(args.warmup):
-        kids, _ = ev.ev_generation(c.ctx, parents, seed, 1_000_000 + w, 2, 15_000_000)
+        kids, _ = ev.ev_generation(c.ctx, parents, seed, 1_000_000 + w, 2, args.cap)
         ev.ev_eval_fitness(c.ctx, kids)
         ev.ev_free_pop(c.ctx, kids)
     step_ms, child_nodes = [], 0
     t_all = time.perf_counter()
     for s in range(args.steps):
         t0 = time.perf_counter()
-        kids, _ = ev.ev_generation(c.ctx, parents, seed, s, 2, 15_000_000)
+        kids, _ = ev.ev_generation(c.ctx, parents, seed, s, 2, args.cap)
         ev.ev_eval_fitness(c.ctx, kids)
         t1 = time.perf_counter()
         child_nodes += ev.ev_pop_info(c.ctx, kids)[1]
@@ -121,6 +250,26 @@ def main():
         step_ms.append((t1 - t0) * 1e3)
     total_s = time.perf_counter() - t_all
     value = child_nodes * n_cases / sum(step_ms) * 1e3
+
+    # ---- the plain form: one tree per launch (its own population and call)
+    plain = None
+    if args.workload in ("batched", "tiny"):
+        rng = np.random.default_rng(7)
+        pick = np.sort(rng.choice(M, size=min(M, args.plain_trees), replace=False))
+        t_plain, nodes_plain, same = 0.0, 0, True
+        for t in pick:
+            tb = np.ascontiguousarray(buf[off[t]:off[t + 1]])
+            p1 = c.load(tb, np.array([0, tb.size], np.uint64))
+            f1, _ = c.eval(p1)  # first call builds device caches
+            t0 = time.perf_counter()
+            f1, _ = c.eval(p1)
+            t_plain += time.perf_counter() - t0
+            nodes_plain += tb.size
+            same &= f1.view(np.uint32)[0] == fit.view(np.uint32)[t] or (np.isnan(f1[0]) and np.isnan(fit[t]))
+            ev.ev_free_pop(c.ctx, p1)
+        plain = {"gpops_per_s": nodes_plain * n_cases / t_plain, "trees": int(pick.size),
+                 "ms_per_tree": t_plain / pick.size * 1e3, "bitexact_vs_batched": bool(same),
+                 "batched_speedup": eval_gpops / (nodes_plain * n_cases / t_plain)}
 
     cpu = None
     if not args.no_cpu:
@@ -169,6 +318,7 @@ def main():
             "avg_launch_ms": interp_ms,
             "traffic": None,
         },
+        "plain_one_tree_per_launch": plain,
         "cpu_baseline": cpu,
     }
     del line["config"]["chunk"]

@@ -77,7 +77,8 @@ enum { EV_ADD = 0, EV_SUB = 1, EV_MUL = 2, EV_DIV = 3, EV_X = 4 };
  * y[n_cases] (host pointers; the paper's fitness cases are x inputs with
  * their Sextic targets y = x^6 - 2x^4 + x^2, Sec. 3 and Table 1).
  * mem_budget_bytes bounds the device memory held by populations, plans and
- * jobs (0 = no bound).  stream is a hipStream_t to order all work on, or
+ * jobs (0 = all the device has free at creation, less a margin; a larger
+ * value is lowered to that).  stream is a hipStream_t to order all work on, or
  * NULL for a stream owned by the context.
  * Errors: EV_EINVAL (n_cases < 1, NULL pointers), EV_EDEVICE. */
 ev_status ev_create(ev_ctx **out, int device, const float *x, const float *y, int32_t n_cases,

@@ -404,14 +404,18 @@ __global__ void k_seg_check(const uint16_t* __restrict__ codes, const SegIn* __r
     const uint32_t P = st[si].P, tv = st[si].cnt > P ? 1u : 0u, m0 = st[si].cnt - tv - P;
     int32_t slab = (int32_t)norm_base(m0), idx = (int32_t)(m0 - (uint32_t)slab), fl = 0;
     uint32_t outs = 0, ins = 0, bad = 0, ended = 0, m = m0;
+    // bad: 1 a code names another position or no handler, 2 the window or
+    // slab leaves its bounds, 4 END misplaced, 8 boundary position, 16/32
+    // slots written/read differ from the plan
     for (uint32_t i = 0; i < len; i++) {
         const uint32_t v = codes[b + i];
         const uint32_t pos = v / EV_CODE_BLOCK, r = v % EV_CODE_BLOCK, k = r / EV_CODE_STRIDE;
-        if (r % EV_CODE_STRIDE || pos != (uint32_t)((b + i) & (EV_CODE_POS - 1)) || k > EV_K_OUTMEM) bad = 1;
-        bad |= ended;
+        if (r % EV_CODE_STRIDE || pos != (uint32_t)((b + i) & (EV_CODE_POS - 1)) || k > EV_K_OUTMEM) bad |= 1;
+        if (ended) bad |= 4;
         if (k == EV_K_END) ended = 1;
+        uint32_t w = 0;
         if (k <= EV_K_OPS3) {
-            bad |= idx < 1;
+            w |= idx < 1;
             idx--;
             m--;
         } else if ((k >= EV_K_CH0 && k <= EV_K_CH3) || k == EV_K_PUSHX || k == EV_K_PUSHREF) {
@@ -420,28 +424,34 @@ __global__ void k_seg_check(const uint16_t* __restrict__ codes, const SegIn* __r
         } else if (k == EV_K_FLUSH) {
             fl = 0;
         } else if (k == EV_K_OUTBOT) {
-            bad |= fl >= idx;
+            w |= fl >= idx;
             fl++;
         } else if (k == EV_K_OUTMEM) {
-            bad |= fl >= slab;
+            w |= fl >= slab;
             fl++;
         } else if (k == EV_K_SPILL) {
-            bad |= idx < (int32_t)EV_VHALF;
+            w |= idx < (int32_t)EV_VHALF;
             idx -= EV_VHALF;
             slab += EV_VHALF;
         } else if (k == EV_K_FILL) {
-            bad |= slab < (int32_t)EV_VHALF || idx > (int32_t)EV_VHALF - 1;
+            w |= slab < (int32_t)EV_VHALF || idx > (int32_t)EV_VHALF - 1;
             idx += EV_VHALF;
             slab -= EV_VHALF;
         }
-        bad |= idx < 0 || idx > (int32_t)EV_VSTACK - 1 || slab < 0 || slab > (int32_t)slab_entries;
+        w |= idx < 0 || idx > (int32_t)EV_VSTACK - 1 || slab < 0 || slab > (int32_t)slab_entries;
+        if (w) bad |= 2;
         outs += (k == EV_K_OUTT || k == EV_K_OUTX || k == EV_K_OUTBOT || k == EV_K_OUTMEM);
         ins += (k == EV_K_PUSHREF || k == EV_K_LOADREF);
     }
-    bad |= (ended != 0) != (g.last != 0);
+    if ((ended != 0) != (g.last != 0)) bad |= 4;
     // a segment hands the next one the window in its boundary position
-    if (!g.last) bad |= (uint32_t)slab != norm_base((uint32_t)(idx + slab));
-    if (bad || outs != sc.n_out || ins != sc.n_in) atomicOr(err, 1u);
+    if (!g.last && (uint32_t)slab != norm_base((uint32_t)(idx + slab))) bad |= 8;
+    if (outs != sc.n_out) bad |= 16;
+    if (ins != sc.n_in) bad |= 32;
+    if (bad) {
+        atomicOr(err, bad);
+        atomicMin(err + 1, si);
+    }
 }
 
 // ------------------------------------------------------------ evaluation

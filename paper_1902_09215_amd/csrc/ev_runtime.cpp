@@ -80,6 +80,13 @@ ev_status dev_alloc(ev_ctx* c, size_t bytes, void** out)
             c->sizes[*out] = cls;
             return EV_OK;
         }
+        // Live and cached blocks together stay below the device's free
+        // memory: the driver accepts allocations beyond it and then moves
+        // buffers out of HBM while kernels use them.
+        if (c->in_use + c->cached + cls > c->hold_limit) cache_release(c);
+        if (c->in_use + cls > c->hold_limit)
+            return fail(EV_ENOMEM, "device memory exhausted (%zu + %zu > %zu bytes held)", (size_t)c->in_use, cls,
+                        (size_t)c->hold_limit);
         c->in_use += cls;
     }
     hipError_t e = hipMalloc(out, cls);
@@ -202,15 +209,18 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         return dev_alloc(c, bytes, p);
     };
     uint32_t n_seg = 0;
+    std::vector<uint32_t> seg_chunk;  // chunk of every segment of the level
     // count pass over a level's chunks: per-chunk totals in cs
     auto count = [&](const std::vector<ChunkIn>& ch, std::vector<ChunkStat>& cs) -> ev_status {
         const uint32_t n = (uint32_t)ch.size();
         std::vector<SegIn> sg;
+        seg_chunk.clear();
         std::vector<ChunkSegs> cg(n);
         for (uint32_t j = 0; j < n; j++) {
             cg[j].first = (uint32_t)sg.size();
             for (uint64_t o = 0; o < ch[j].len; o += SEG_TOKENS)
                 sg.push_back(SegIn{ch[j].start + o, (uint32_t)std::min<uint64_t>(SEG_TOKENS, ch[j].len - o), o == 0 ? 1u : 0u});
+            seg_chunk.resize(sg.size(), j);
             cg[j].n_seg = (uint32_t)sg.size() - cg[j].first;
         }
         n_seg = (uint32_t)sg.size();
@@ -220,16 +230,15 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             (e = realloc(&d_cnt, n_seg * sizeof(SegCount))) || (e = realloc(&d_stat, n * sizeof(ChunkStat))))
             return e;
         cs.resize(n);
-        HIPCHK(hipMemcpyAsync(d_seg, sg.data(), n_seg * sizeof(SegIn), hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(d_cseg, cg.data(), n * sizeof(ChunkSegs), hipMemcpyHostToDevice, s));
+        if ((e = put(x, d_seg, sg.data(), n_seg * sizeof(SegIn))) || (e = put(x, d_cseg, cg.data(), n * sizeof(ChunkSegs))))
+            return e;
         HIPCHK(launch_seg_fn(cur, (SegIn*)d_seg, n_seg, (SegFn*)d_fn, level == 0 ? TOK_X : TOK_REF, s));
         HIPCHK(launch_seg_scan((ChunkSegs*)d_cseg, n, (SegFn*)d_fn, (SegStart*)d_st, (ChunkStat*)d_stat, s));
         HIPCHK(launch_seg_count(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (SegCount*)d_cnt, s));
         HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, n, (SegCount*)d_cnt, (ChunkStat*)d_stat, nullptr, nullptr, nullptr,
                                 nullptr, s));
-        HIPCHK(hipMemcpyAsync(cs.data(), d_stat, n * sizeof(ChunkStat), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        return EV_OK;
+        if ((e = get(x, cs.data(), d_stat, n * sizeof(ChunkStat)))) return e;
+        return sync(x);
     };
 
     for (;;) {
@@ -276,6 +285,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         }
 
         const uint32_t n = (uint32_t)ch.size();
+        const std::vector<uint64_t> rs0 = rs;
 
         // slot numbering (global over the level's chunks, in sequence order)
         // and the split of the work items between the two kernels
@@ -329,8 +339,10 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         L.n_out = (uint32_t)so;
         L.max_m = max_m;
         L.tokens = tokens;
-        // a stack deeper than the register window spills half-windows to a slab
-        L.slab_entries = slab_top + 1 > EV_VSTACK_ENTRIES ? slab_top + EV_VSTACK_ENTRIES / 2 : 0;
+        // a stack deeper than the register window spills half-windows to a
+        // slab; so does one that reaches the window's upper quarter at a
+        // segment boundary, where the window is re-centred
+        L.slab_entries = slab_top + 1 > EV_VSTACK_ENTRIES - EV_VHALF / 2 ? slab_top + EV_VHALF : 0;
         pl.chunks_total += n;
         pl.slots_total += so;
         std::vector<EvalChunk> slow;
@@ -349,14 +361,14 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         cur_owned = false;
         if (!slow.empty()) {
             if ((st = dev_alloc(c, slow.size() * sizeof(EvalChunk), (void**)&LL.d_chunks)) != EV_OK) { cleanup(); return st; }
-            HIPCHK(hipMemcpyAsync(LL.d_chunks, slow.data(), slow.size() * sizeof(EvalChunk), hipMemcpyHostToDevice, s));
+            if ((st = put(x, LL.d_chunks, slow.data(), slow.size() * sizeof(EvalChunk))) != EV_OK) { cleanup(); return st; }
         }
         if (!run.empty()) {
             std::vector<RunChunk> rc(run.size());
             for (size_t i = 0; i < run.size(); i++) rc[i] = run[i].second;
             if ((st = dev_alloc(c, rc.size() * sizeof(RunChunk), (void**)&LL.d_run)) != EV_OK) { cleanup(); return st; }
             if ((st = dev_alloc(c, sc * 2 + 256, (void**)&LL.codes)) != EV_OK) { cleanup(); return st; }
-            HIPCHK(hipMemcpyAsync(LL.d_run, rc.data(), rc.size() * sizeof(RunChunk), hipMemcpyHostToDevice, s));
+            if ((st = put(x, LL.d_run, rc.data(), rc.size() * sizeof(RunChunk))) != EV_OK) { cleanup(); return st; }
             HIPCHK(hipMemsetAsync((uint8_t*)LL.codes + sc * 2, 0, 256, s));
         }
 
@@ -388,15 +400,18 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         if (any || !run.empty()) {
             if ((st = realloc(&d_cb, n * sizeof(uint64_t))) || (st = realloc(&d_fe, n * sizeof(uint64_t))) ||
                 (st = realloc(&d_scode, n_seg * sizeof(uint64_t))) || (st = realloc(&d_sfrag, n_seg * sizeof(uint64_t))) ||
-                (st = realloc(&d_err, 4))) {
+                (st = realloc(&d_err, 8))) {
                 dev_free(c, d_next);
                 cleanup();
                 return st;
             }
-            uint32_t err = 0;
-            HIPCHK(hipMemcpyAsync(d_cb, code_begin.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(d_fe, frag_end.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(d_err, &err, 4, hipMemcpyHostToDevice, s));
+            uint32_t err[2] = {0, UINT32_MAX};
+            if ((st = put(x, d_cb, code_begin.data(), n * sizeof(uint64_t))) || (st = put(x, d_fe, frag_end.data(), n * sizeof(uint64_t))) ||
+                (st = put(x, d_err, err, 8))) {
+                dev_free(c, d_next);
+                cleanup();
+                return st;
+            }
             HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, n, (SegCount*)d_cnt, (ChunkStat*)d_stat, (uint64_t*)d_cb,
                                     (uint64_t*)d_fe, (uint64_t*)d_scode, (uint64_t*)d_sfrag, s));
             HIPCHK(launch_seg_emit(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode, (uint64_t*)d_sfrag,
@@ -404,15 +419,35 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             if (!run.empty())
                 HIPCHK(launch_seg_check(LL.codes, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode,
                                         (SegCount*)d_cnt, LL.slab_entries, (uint32_t*)d_err, s));
-            HIPCHK(hipMemcpyAsync(&err, d_err, 4, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            if (err) { dev_free(c, d_next); cleanup(); return fail(EV_EDEVICE, "internal: malformed code stream at level %d", level); }
+            if ((st = get(x, err, d_err, 8)) || (st = sync(x))) {
+                dev_free(c, d_next);
+                cleanup();
+                return st;
+            }
+            if (err[0]) {
+                dev_free(c, d_next);
+                cleanup();
+                const uint32_t sj = err[1] < seg_chunk.size() ? seg_chunk[err[1]] : 0;
+                const uint32_t t = ch[sj].tree;
+                return fail(EV_EDEVICE,
+                            "internal: malformed code stream at level %d (flags %u, tree %u of %u tokens, chunk at "
+                            "token %llu of its level, segment %u)",
+                            level, err[0], t, (unsigned)ch[sj].len, (unsigned long long)(ch[sj].start - rs0[t]),
+                            err[1]);
+            }
         }
         if (!any) break;
         cur = d_next;
         cur_owned = true;
         level++;
-        if (level > 64) { dev_free(c, cur); cleanup(); return fail(EV_ECAP, "split plan did not converge"); }
+        if (level > 64) {
+            dev_free(c, cur);
+            cleanup();
+            int32_t t = 0;
+            while (t < M && !active[t]) t++;
+            return fail(EV_ECAP, "split plan did not converge (tree %d: %llu tokens after %llu)", t,
+                        (unsigned long long)(t < M ? rl[t] : 0), (unsigned long long)(t < M ? prev_len[t] : 0));
+        }
     }
     cleanup();
     pl.bytes = 0;
@@ -433,9 +468,7 @@ ev_status pop_build(ev_ctx* c, Exec& x, uint8_t* d_bytes, const std::vector<uint
     ev_status st;
     if ((st = dev_alloc(c, h_off.size() * sizeof(uint64_t), (void**)&P->d_off)) != EV_OK) { pop_free(c, P); return st; }
     if ((st = dev_alloc(c, (size_t)std::max(1, P->M) * sizeof(float), (void**)&P->d_fit)) != EV_OK) { pop_free(c, P); return st; }
-    hipError_t e = hipMemcpyAsync(P->d_off, h_off.data(), h_off.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
-                                  x.stream);
-    if (e != hipSuccess) { pop_free(c, P); return hip_fail(e, "upload offsets"); }
+    if ((st = put(x, P->d_off, h_off.data(), h_off.size() * sizeof(uint64_t))) != EV_OK) { pop_free(c, P); return st; }
     if ((st = plan_build(c, x, P, bad)) != EV_OK) { pop_free(c, P); return st; }
     *out = P;
     return EV_OK;
@@ -461,7 +494,7 @@ Pop* pop_get(ev_ctx* c, ev_pop id)
 ev_status ensure_gstack(ev_ctx* c, Exec& x, size_t bytes)
 {
     if (bytes <= x.gstack_bytes) return EV_OK;
-    (void)hipStreamSynchronize(x.stream);
+    if (ev_status st = sync(x)) return st;
     dev_free(c, x.d_gstack);
     x.d_gstack = nullptr;
     x.gstack_bytes = 0;
@@ -473,7 +506,7 @@ ev_status ensure_gstack(ev_ctx* c, Exec& x, size_t bytes)
 ev_status ensure_counters(ev_ctx* c, Exec& x, size_t n)
 {
     if (n <= x.n_counters) return EV_OK;
-    (void)hipStreamSynchronize(x.stream);
+    if (ev_status st = sync(x)) return st;
     dev_free(c, x.d_counters);
     x.d_counters = nullptr;
     x.n_counters = 0;
@@ -492,6 +525,7 @@ ev_status exec_init(Exec& x, hipStream_t given)
         if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
         x.own_stream = true;
     }
+    (void)hipEventCreateWithFlags(&x.done, hipEventDisableTiming);
     (void)hipEventCreate(&x.ev0);
     (void)hipEventCreate(&x.ev1);
     (void)hipEventCreate(&x.evi0);
@@ -499,19 +533,90 @@ ev_status exec_init(Exec& x, hipStream_t given)
     return EV_OK;
 }
 
+// A region of n bytes in x's pinned staging buffer.  When the buffer is
+// full the stream is synchronized first (every staged copy has then landed)
+// and the buffer is reused, or replaced by a larger one.
+ev_status stage(Exec& x, size_t n, void** out)
+{
+    n = (n + 255) & ~(size_t)255;
+    if (x.pin_off + n > x.pin_cap) {
+        ev_status st = sync(x);
+        if (st != EV_OK) return st;
+        if (n > x.pin_cap) {
+            if (x.pin) (void)hipHostFree(x.pin);
+            x.pin = nullptr;
+            x.pin_cap = 0;
+            const size_t cap = std::max<size_t>(n, (size_t)4 << 20);
+            hipError_t e = hipHostMalloc((void**)&x.pin, cap, hipHostMallocDefault);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                x.pin = nullptr;
+                return fail(EV_ENOMEM, "hipHostMalloc(%zu): %s", cap, hipGetErrorString(e));
+            }
+            x.pin_cap = cap;
+        }
+    }
+    *out = x.pin + x.pin_off;
+    x.pin_off += n;
+    return EV_OK;
+}
+
+// Host-to-device copy on x's stream (src may be reused on return).
+ev_status put(Exec& x, void* dst, const void* src, size_t n)
+{
+    if (n == 0) return EV_OK;
+    void* p = nullptr;
+    ev_status st = stage(x, n, &p);
+    if (st != EV_OK) return st;
+    std::memcpy(p, src, n);
+    HIPCHK(hipMemcpyAsync(dst, p, n, hipMemcpyHostToDevice, x.stream));
+    return EV_OK;
+}
+
+// Device-to-host copy on x's stream; dst holds the data once sync(x) returns.
+ev_status get(Exec& x, void* dst, const void* src, size_t n)
+{
+    if (n == 0) return EV_OK;
+    void* p = nullptr;
+    ev_status st = stage(x, n, &p);
+    if (st != EV_OK) return st;
+    HIPCHK(hipMemcpyAsync(p, src, n, hipMemcpyDeviceToHost, x.stream));
+    x.pin_out.push_back(Exec::Out{dst, p, n});
+    return EV_OK;
+}
+
+// Waits for everything enqueued on x's stream so far (the stream may be
+// shared with other Execs: their later work is not waited for).
+ev_status sync(Exec& x)
+{
+    hipError_t e = hipEventRecord(x.done, x.stream);
+    if (e == hipSuccess) e = hipEventSynchronize(x.done);
+    if (e == hipSuccess)
+        for (const Exec::Out& o : x.pin_out) std::memcpy(o.dst, o.src, o.n);
+    x.pin_out.clear();
+    x.pin_off = 0;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return EV_OK;
+}
+
 void exec_free(ev_ctx* c, Exec& x)
 {
     if (x.stream) (void)hipStreamSynchronize(x.stream);
+    if (x.pin) (void)hipHostFree(x.pin);
+    x.pin = nullptr;
+    x.pin_cap = x.pin_off = 0;
+    x.pin_out.clear();
     dev_free(c, x.d_gstack);
     dev_free(c, x.d_counters);
     x.d_gstack = nullptr;
     x.d_counters = nullptr;
     x.gstack_bytes = x.n_counters = 0;
+    if (x.done) (void)hipEventDestroy(x.done);
     if (x.ev0) (void)hipEventDestroy(x.ev0);
     if (x.ev1) (void)hipEventDestroy(x.ev1);
     if (x.evi0) (void)hipEventDestroy(x.evi0);
     if (x.evi1) (void)hipEventDestroy(x.evi1);
-    x.ev0 = x.ev1 = x.evi0 = x.evi1 = nullptr;
+    x.done = x.ev0 = x.ev1 = x.evi0 = x.evi1 = nullptr;
     if (x.own_stream && x.stream) (void)hipStreamDestroy(x.stream);
     x.stream = nullptr;
 }
@@ -538,10 +643,10 @@ ev_status rescache_get(ev_ctx* c, Exec& x, Pop* P, int32_t table, ResCache** out
         rescache_free(c, r);
         return st;
     }
-    hipError_t e = hipMemcpyAsync(r.d_rows, rows.data(), rows.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
-                                  x.stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(x.stream);
-    if (e != hipSuccess) { rescache_free(c, r); return hip_fail(e, "upload rows"); }
+    if ((st = put(x, r.d_rows, rows.data(), rows.size() * sizeof(uint64_t))) != EV_OK || (st = sync(x)) != EV_OK) {
+        rescache_free(c, r);
+        return st;
+    }
     P->res[table] = r;
     *out = &P->res[table];
     return EV_OK;
@@ -654,13 +759,17 @@ ev_status crossover_build(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const int32_
     }
     std::vector<uint64_t> ends(2 * (size_t)n);
     if (n > 0) {
-        HIPCHK(hipMemcpyAsync(d_b, qb.data(), 2 * (size_t)n * 8, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(d_p, qp.data(), 2 * (size_t)n * 8, hipMemcpyHostToDevice, s));
+        if ((st = put(x, d_b, qb.data(), 2 * (size_t)n * 8)) || (st = put(x, d_p, qp.data(), 2 * (size_t)n * 8))) {
+            cleanup();
+            return st;
+        }
         HIPCHK(launch_subtree_end(mums->d_bytes, (uint64_t*)d_b, (uint64_t*)d_p, (uint32_t)n, (uint64_t*)d_e, s));
         HIPCHK(launch_subtree_end(dads->d_bytes, (uint64_t*)d_b + n, (uint64_t*)d_p + n, (uint32_t)n,
                                   (uint64_t*)d_e + n, s));
-        HIPCHK(hipMemcpyAsync(ends.data(), d_e, 2 * (size_t)n * 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        if ((st = get(x, ends.data(), d_e, 2 * (size_t)n * 8)) || (st = sync(x))) {
+            cleanup();
+            return st;
+        }
     }
     std::vector<XoPlan> plan(n);
     std::vector<uint64_t> off(n + 1, 0);
@@ -692,11 +801,19 @@ ev_status crossover_build(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const int32_
         return st;
     }
     if (n > 0) {
-        HIPCHK(hipMemcpyAsync(d_plan, plan.data(), (size_t)n * sizeof(XoPlan), hipMemcpyHostToDevice, s));
+        if ((st = put(x, d_plan, plan.data(), (size_t)n * sizeof(XoPlan))) != EV_OK) {
+            dev_free(c, d_child);
+            cleanup();
+            return st;
+        }
         HIPCHK(launch_xo_copy(mums->d_bytes, dads->d_bytes, (XoPlan*)d_plan, (uint32_t)n, maxlen, d_child, s));
     }
     HIPCHK(hipMemsetAsync(d_child + off[n], 0xFF, 512, s));
-    HIPCHK(hipStreamSynchronize(s));
+    if ((st = sync(x)) != EV_OK) {
+        dev_free(c, d_child);
+        cleanup();
+        return st;
+    }
     cleanup();
     if (n_capped) *n_capped = capped;
     return pop_build(c, x, d_child, off, out, nullptr);
@@ -724,6 +841,14 @@ ev_status ev_create(ev_ctx** out, int device, const float* x, const float* y, in
     ev_ctx* c = new ev_ctx();
     c->device = device;
     c->budget = mem_budget_bytes;
+    {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) { delete c; return fail(EV_EDEVICE, "hipMemGetInfo"); }
+        // leave room for the runtime's own buffers and other contexts
+        const size_t margin = std::max<size_t>((size_t)4 << 30, free_b / 32);
+        c->hold_limit = free_b > margin ? free_b - margin : free_b / 2;
+        if (c->budget == 0 || c->budget > c->hold_limit) c->budget = c->hold_limit;
+    }
     if (exec_init(c->main, (hipStream_t)stream) != EV_OK) { delete c; return EV_EDEVICE; }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return fail(EV_EDEVICE, "device properties"); }
@@ -754,9 +879,12 @@ ev_status ev_add_cases(ev_ctx* c, const float* x, const float* y, int32_t n, int
     ev_status st;
     if ((st = dev_alloc(c, (size_t)n * 4, (void**)&t.d_x)) != EV_OK) return st;
     if ((st = dev_alloc(c, (size_t)n * 4, (void**)&t.d_y)) != EV_OK) { dev_free(c, t.d_x); return st; }
-    HIPCHK(hipMemcpyAsync(t.d_x, x, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(t.d_y, y, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    if ((st = put(c->main, t.d_x, x, (size_t)n * 4)) || (st = put(c->main, t.d_y, y, (size_t)n * 4)) ||
+        (st = sync(c->main))) {
+        dev_free(c, t.d_x);
+        dev_free(c, t.d_y);
+        return st;
+    }
     std::lock_guard<std::mutex> g(c->pop_mu);
     c->tables.push_back(t);
     if (table) *table = (int32_t)c->tables.size() - 1;
@@ -768,7 +896,7 @@ ev_status ev_destroy(ev_ctx* c)
     if (!c) return fail(EV_EINVAL, "ev_destroy: NULL context");
     (void)hipSetDevice(c->device);
     serve_stop(c);
-    (void)hipStreamSynchronize(c->stream);
+    (void)sync(c->main);
     for (auto& kv : c->pops) pop_free(c, kv.second);
     c->pops.clear();
     for (auto& t : c->tables) { dev_free(c, t.d_x); dev_free(c, t.d_y); }
@@ -786,7 +914,9 @@ ev_status ev_load_trees(ev_ctx* c, const uint8_t* bytes, const uint64_t* off, in
     HIPCHK(hipSetDevice(c->device));
     std::vector<uint64_t> h_off(n + 1);
     if (flags & EV_DEVICE_PTR) {
-        HIPCHK(hipMemcpy(h_off.data(), off, (n + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        ev_status st0 = get(c->main, h_off.data(), off, (n + 1) * sizeof(uint64_t));
+        if (st0 == EV_OK) st0 = sync(c->main);
+        if (st0 != EV_OK) return st0;
     } else {
         std::memcpy(h_off.data(), off, (n + 1) * sizeof(uint64_t));
     }
@@ -802,8 +932,13 @@ ev_status ev_load_trees(ev_ctx* c, const uint8_t* bytes, const uint64_t* off, in
     uint8_t* d = nullptr;
     ev_status st = dev_alloc(c, total + 512, (void**)&d);
     if (st != EV_OK) return st;
-    hipError_t e = hipMemcpyAsync(d, bytes, total, (flags & EV_DEVICE_PTR) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                                  c->stream);
+    hipError_t e = hipSuccess;
+    if (flags & EV_DEVICE_PTR) {
+        e = hipMemcpyAsync(d, bytes, total, hipMemcpyDeviceToDevice, c->stream);
+    } else if ((st = put(c->main, d, bytes, total)) != EV_OK) {
+        dev_free(c, d);
+        return st;
+    }
     if (e == hipSuccess) e = hipMemsetAsync(d + total, 0xFF, 512, c->stream);
     if (e != hipSuccess) { dev_free(c, d); return hip_fail(e, "upload trees"); }
     Pop* P = nullptr;
@@ -830,8 +965,9 @@ ev_status ev_get_trees(ev_ctx* c, ev_pop pop, uint8_t* bytes, uint64_t* off, uin
     if (!P) return fail(EV_ENOTFOUND, "no population %d", pop);
     if (cap_bytes < P->total || (!bytes && P->total) || !off) return fail(EV_EINVAL, "ev_get_trees: buffer too small");
     HIPCHK(hipSetDevice(c->device));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    if (P->total) HIPCHK(hipMemcpy(bytes, P->d_bytes, P->total, hipMemcpyDeviceToHost));
+    ev_status st = get(c->main, bytes, P->d_bytes, P->total);
+    if (st == EV_OK) st = sync(c->main);
+    if (st != EV_OK) return st;
     std::memcpy(off, P->h_off.data(), P->h_off.size() * sizeof(uint64_t));
     return EV_OK;
 }
@@ -848,7 +984,7 @@ ev_status ev_free_pop(ev_ctx* c, ev_pop pop)
         c->pops.erase(it);
     }
     (void)hipSetDevice(c->device);
-    (void)hipStreamSynchronize(c->stream);
+    (void)sync(c->main);
     pop_free(c, P);
     return EV_OK;
 }
@@ -883,11 +1019,9 @@ ev_status ev_eval_fitness(ev_ctx* c, ev_pop pop, int32_t table, float* fitness, 
         if (P->M) HIPCHK(hipMemcpyAsync(fitness, P->d_fit, (size_t)P->M * 4, hipMemcpyDeviceToDevice, c->stream));
         return EV_OK;
     }
-    if (P->M) HIPCHK(hipMemcpyAsync(fitness, P->d_fit, (size_t)P->M * 4, hipMemcpyDeviceToHost, c->stream));
-    if (per_case && P->M)
-        HIPCHK(hipMemcpyAsync(per_case, d_pc, (size_t)P->M * N * 4, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    return EV_OK;
+    if ((st = get(c->main, fitness, P->d_fit, (size_t)P->M * 4)) != EV_OK) return st;
+    if (per_case && (st = get(c->main, per_case, d_pc, (size_t)P->M * N * 4)) != EV_OK) return st;
+    return sync(c->main);
 }
 
 ev_status ev_crossover(ev_ctx* c, ev_pop mums_pop, ev_pop dads_pop, const int32_t* mum, const int32_t* dad,
@@ -925,13 +1059,15 @@ ev_status ev_generation(ev_ctx* c, ev_pop parents, uint64_t seed, uint64_t gen, 
     std::vector<int32_t> mum(M), dad(M);
     std::vector<uint64_t> p(M), q(M);
     hipError_t e = launch_select(P->d_fit, P->d_off, (uint32_t)M, tournament, seed, gen, d_mum, d_dad, d_p, d_q, c->stream);
-    if (e == hipSuccess && M) e = hipMemcpyAsync(mum.data(), d_mum, M * 4, hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess && M) e = hipMemcpyAsync(dad.data(), d_dad, M * 4, hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess && M) e = hipMemcpyAsync(p.data(), d_p, M * 8, hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess && M) e = hipMemcpyAsync(q.data(), d_q, M * 8, hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) st = hip_fail(e, "selection");
+    if (st == EV_OK) st = get(c->main, mum.data(), d_mum, (size_t)M * 4);
+    if (st == EV_OK) st = get(c->main, dad.data(), d_dad, (size_t)M * 4);
+    if (st == EV_OK) st = get(c->main, p.data(), d_p, (size_t)M * 8);
+    if (st == EV_OK) st = get(c->main, q.data(), d_q, (size_t)M * 8);
+    if (st == EV_OK) st = sync(c->main);
+    else (void)sync(c->main);
     dev_free(c, d_sel);
-    if (e != hipSuccess) return hip_fail(e, "selection");
+    if (st != EV_OK) return st;
     Pop* C = nullptr;
     st = crossover_build(c, c->main, P, P, mum.data(), dad.data(), p.data(), q.data(), M, size_cap, &C, n_capped);
     if (st != EV_OK) return st;

@@ -68,7 +68,8 @@ struct Pop {
     std::map<int32_t, ResCache> res;
 };
 
-// Per-thread execution resources: a stream and the scratch its launches use.
+// Per-thread execution resources: a stream (possibly shared) and the scratch
+// its launches use.
 struct Exec {
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -76,7 +77,18 @@ struct Exec {
     size_t n_counters = 0;
     float* d_gstack = nullptr;
     size_t gstack_bytes = 0;
+    hipEvent_t done = nullptr;  // completion marker of sync()
     hipEvent_t ev0 = nullptr, ev1 = nullptr, evi0 = nullptr, evi1 = nullptr;
+    // Pinned host staging of the stream's transfers: copies are plain DMA
+    // from and to it; device-to-host data is handed out at the next sync().
+    uint8_t* pin = nullptr;
+    size_t pin_cap = 0, pin_off = 0;
+    struct Out {
+        void* dst;
+        const void* src;
+        size_t n;
+    };
+    std::vector<Out> pin_out;
 };
 
 struct Job;
@@ -98,6 +110,7 @@ struct ev_ctx {
 
     std::mutex mem_mu;
     uint64_t budget = 0, in_use = 0;
+    uint64_t hold_limit = ~0ull;  // live + cached bytes, below the device's free memory
     std::unordered_map<void*, size_t> sizes;   // live blocks and their size class
     std::map<size_t, std::vector<void*>> cache;  // freed blocks by size class
     uint64_t cached = 0;
@@ -122,6 +135,10 @@ void dev_free(ev_ctx* c, void* p);
 void dev_cache_release(ev_ctx* c);
 
 ev_status exec_init(Exec& x, hipStream_t given);
+ev_status stage(Exec& x, size_t n, void** out);
+ev_status put(Exec& x, void* dst, const void* src, size_t n);
+ev_status get(Exec& x, void* dst, const void* src, size_t n);
+ev_status sync(Exec& x);
 void exec_free(ev_ctx* c, Exec& x);
 
 void pop_free(ev_ctx* c, Pop* P);

@@ -1,13 +1,15 @@
 // Serving loop of libev: ev_submit / ev_poll / ev_wait / ev_result.
 //
 // Requests are queued in arrival order.  Worker threads, each with its own
-// HIP stream and scratch, take the queue head as soon as its estimated
+// scratch and pinned staging, take the queue head as soon as its estimated
 // device footprint fits the budget beside the jobs already in flight, and
 // fold every other queued evaluation request on the same case table that
 // also fits into the same device launch (continuous batching).  Several
-// workers run at once, so work admitted while other work is on the GPU
-// overlaps with it.  Each tree's result depends only on the tree, never on
-// the batch it rode in.
+// workers run at once: one batches, stages and plans on the host while the
+// others' kernels run.  All device work goes to the context's one stream,
+// in the order the workers enqueue it.  Each tree's result depends only on
+// the tree, never on the batch it rode in.
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 
@@ -32,6 +34,7 @@ struct Job {
     ev_status status = EV_OK;
     std::vector<float> fitness, per_case;
     uint64_t t_submit = 0, t_start = 0, t_done = 0;
+    std::string err;  // the failing call's message (set on the worker thread)
 };
 
 static uint64_t now_ns()
@@ -69,6 +72,7 @@ static uint64_t footprint(uint64_t nodes, uint64_t trees, int32_t N, uint32_t ch
 static void finish(Serve* S, Job* j, ev_status st)
 {
     std::lock_guard<std::mutex> g(S->mu);
+    if (st != EV_OK) j->err = g_err;
     j->status = st;
     j->done = true;
     j->t_done = now_ns();
@@ -83,10 +87,7 @@ static ev_status run_eval_batch(ev_ctx* c, Exec& x, std::vector<Job*>& batch)
     std::vector<uint64_t> off(1, 0);
     uint64_t total = 0;
     for (Job* j : batch) total += j->off.back();
-    std::vector<uint8_t> bytes;
-    bytes.reserve(total);
     for (Job* j : batch) {
-        bytes.insert(bytes.end(), j->bytes.begin(), j->bytes.end());
         const uint64_t base = off.back();
         for (int32_t t = 0; t < j->n; t++) off.push_back(base + j->off[t + 1]);
     }
@@ -99,11 +100,22 @@ static ev_status run_eval_batch(ev_ctx* c, Exec& x, std::vector<Job*>& batch)
     float* d_pc = nullptr;
     std::vector<float> fit(M), pc((size_t)M * N);
     if ((st = dev_alloc(c, total + 512, (void**)&d)) == EV_OK) {
-        hipError_t e = hipMemcpyAsync(d, bytes.data(), total, hipMemcpyHostToDevice, x.stream);
-        if (e == hipSuccess) e = hipMemsetAsync(d + total, 0xFF, 512, x.stream);
-        if (e != hipSuccess) {
+        // the batch's trees are gathered straight into pinned staging
+        uint8_t* h = nullptr;
+        st = stage(x, total, (void**)&h);
+        hipError_t e = hipSuccess;
+        if (st == EV_OK) {
+            for (Job* j : batch) {
+                std::memcpy(h, j->bytes.data(), j->bytes.size());
+                h += j->bytes.size();
+            }
+            e = hipMemcpyAsync(d, h - total, total, hipMemcpyHostToDevice, x.stream);
+            if (e == hipSuccess) e = hipMemsetAsync(d + total, 0xFF, 512, x.stream);
+            if (e != hipSuccess) st = hip_fail(e, "serve upload");
+        }
+        if (st != EV_OK) {
+            (void)sync(x);
             dev_free(c, d);
-            st = hip_fail(e, "serve upload");
         } else {
             int32_t bad = -1;
             st = pop_build(c, x, d, off, &P, &bad);
@@ -111,12 +123,10 @@ static ev_status run_eval_batch(ev_ctx* c, Exec& x, std::vector<Job*>& batch)
     }
     if (st == EV_OK) st = dev_alloc(c, (size_t)std::max(1, M) * N * sizeof(float), (void**)&d_pc);
     if (st == EV_OK) st = eval_enqueue(c, x, P, table, P->d_fit, d_pc, false);
-    if (st == EV_OK) {
-        hipError_t e = hipMemcpyAsync(fit.data(), P->d_fit, (size_t)M * 4, hipMemcpyDeviceToHost, x.stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(pc.data(), d_pc, (size_t)M * N * 4, hipMemcpyDeviceToHost, x.stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(x.stream);
-        if (e != hipSuccess) st = hip_fail(e, "serve download");
-    }
+    if (st == EV_OK) st = get(x, fit.data(), P->d_fit, (size_t)M * 4);
+    if (st == EV_OK) st = get(x, pc.data(), d_pc, (size_t)M * N * 4);
+    if (st == EV_OK) st = sync(x);
+    else (void)sync(x);
     dev_free(c, d_pc);
     if (P) pop_free(c, P);
     int32_t at = 0;
@@ -148,12 +158,11 @@ static ev_status run_crossover(ev_ctx* c, Exec& x, Job* j)
         j->fitness.resize(C->M);
         j->per_case.resize((size_t)C->M * N);
         j->N = N;
-        hipError_t e = hipMemcpyAsync(j->fitness.data(), C->d_fit, (size_t)C->M * 4, hipMemcpyDeviceToHost, x.stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(j->per_case.data(), d_pc, (size_t)C->M * N * 4, hipMemcpyDeviceToHost, x.stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(x.stream);
-        if (e != hipSuccess) st = hip_fail(e, "serve download");
+        st = get(x, j->fitness.data(), C->d_fit, (size_t)C->M * 4);
+        if (st == EV_OK) st = get(x, j->per_case.data(), d_pc, (size_t)C->M * N * 4);
     }
+    if (st == EV_OK) st = sync(x);
+    else (void)sync(x);
     dev_free(c, d_pc);
     pop_free(c, C);
     return st;
@@ -221,10 +230,13 @@ static Serve* serve_get(ev_ctx* c)
     if (c->serve) return c->serve;
     Serve* S = new Serve();
     S->budget = c->budget;
+    // Workers overlap their host work (batching, planning, staging) with the
+    // device work of the others; all of them enqueue on the context's one
+    // stream, each with its own scratch, staging and completion event.
     const int W = 3;
     for (int i = 0; i < W; i++) {
         auto x = std::make_unique<Exec>();
-        if (exec_init(*x, nullptr) != EV_OK) break;
+        if (exec_init(*x, c->main.stream) != EV_OK) break;
         S->execs.push_back(std::move(x));
     }
     for (auto& x : S->execs) S->workers.emplace_back(worker, c, S, x.get());
@@ -365,9 +377,10 @@ ev_status ev_result(ev_ctx* c, ev_ticket t, float* fitness, float* per_case, int
         if (!j->done) return fail(EV_EBUSY, "ticket %llu not finished", (unsigned long long)t);
         if (j->status != EV_OK) {
             const ev_status st = j->status;
+            const std::string msg = j->err;
             S->jobs.erase(it);
             delete j;
-            return fail(st, "job failed");
+            return fail(st, "job failed: %s", msg.c_str());
         }
         if (cap < (int32_t)j->fitness.size()) return fail(EV_EINVAL, "ev_result: cap %d < %zu", cap, j->fitness.size());
         S->jobs.erase(it);

@@ -259,6 +259,55 @@ def test_serving_results_same_alone_and_mixed(ev):
         assert_same(fa, wf, f"job {k} vs oracle")
 
 
+def test_serving_under_load(ev):
+    # 600 requests queued at once on two case tables: single trees of up to
+    # 4e6 nodes drawn from a pool (so batches of a few hundred trees, with
+    # repeats) and crossover requests; every served result must equal the
+    # direct evaluation of the same tree, bit for bit.
+    x, y = workloads.cases(48)
+    x2, y2 = workloads.cases(1024)
+    rng = np.random.default_rng(47)
+    psizes = workloads.loguniform_sizes(47, 48, 10, 4e6)
+    pbuf, poff = workloads.random_population(47, psizes)
+    qsizes = workloads.loguniform_sizes(48, 32, 1, 5000)
+    qbuf, qoff = workloads.random_population(48, qsizes)
+    with ev.Context(x, y) as c:
+        t1 = c.add_cases(x2, y2)
+        pool = c.load(pbuf, poff)
+        direct = [c.eval(pool, 0)[0], c.eval(pool, t1)[0]]
+        parents = c.load(qbuf, qoff)
+        reqs, tickets = [], []
+        for _ in range(600):
+            tab = int(rng.integers(0, 2))
+            if rng.random() < 0.8:
+                t = int(rng.integers(0, psizes.size))
+                reqs.append(("eval", tab, t))
+                tickets.append(ev.ev_submit_eval(c.ctx, pbuf[poff[t]:poff[t + 1]],
+                                                 np.array([0, psizes[t]], np.uint64), tab))
+            else:
+                mum = rng.integers(0, 32, 4).astype(np.int32)
+                dad = rng.integers(0, 32, 4).astype(np.int32)
+                p = np.array([rng.integers(0, qsizes[m]) for m in mum], np.uint64)
+                q = np.array([rng.integers(0, qsizes[d]) for d in dad], np.uint64)
+                reqs.append(("xo", tab, (mum, dad, p, q)))
+                tickets.append(ev.ev_submit_crossover(c.ctx, parents, mum, dad, p, q, tab))
+        got = []
+        for t, r in zip(tickets, reqs):
+            assert ev.ev_wait(c.ctx, t) == 0, f"request {r[:2]} failed"
+            got.append(ev.ev_result(c.ctx, t, 4, c.n_cases(r[1]))[0])
+    cases = [(x, y), (x2, y2)]
+    for k, (r, f) in enumerate(zip(reqs, got)):
+        if r[0] == "eval":
+            assert_same(f, direct[r[1]][r[2]:r[2] + 1], f"request {k} (tree {r[2]}, table {r[1]})")
+        else:
+            mum, dad, p, q = r[2]
+            kids = [oracle.crossover(qbuf[qoff[m]:qoff[m + 1]], qbuf[qoff[d]:qoff[d + 1]], int(pp), int(qq))
+                    for m, d, pp, qq in zip(mum, dad, p, q)]
+            koff = workloads.offsets_from_sizes([kk.size for kk in kids])
+            want = oracle.eval_population(np.concatenate(kids), koff, *cases[r[1]])
+            assert_same(f, want, f"request {k} (crossover, table {r[1]})")
+
+
 def test_serving_crossover_jobs(ev):
     x, y = workloads.cases(48)
     rng = np.random.default_rng(43)
@@ -279,3 +328,45 @@ def test_serving_crossover_jobs(ev):
     koff = workloads.offsets_from_sizes([k.size for k in kids])
     wf = oracle.eval_population(np.concatenate(kids), koff, x, y)
     assert_same(fit, wf, "served crossover")
+
+
+def test_giant_population_sampled(ev):
+    # 48 random trees with log-uniform sizes in [1e6, 4e8] (about 3.2e9
+    # nodes), evaluated in the benchmark's launch configuration; the oracle
+    # recomputes a sample of trees (the three smallest, the median and the
+    # largest), each bit for bit.
+    buf, off, n = workloads.workload("giant")
+    x, y = workloads.cases(n)
+    sizes = np.diff(off)
+    print(f"giant: {int(off[-1])} nodes, largest {int(sizes.max())}", flush=True)
+    with ev.Context(x, y) as c:
+        pop = c.load(buf, off)
+        info = ev.ev_get_plan_info(c.ctx, pop)
+        fit, pc = c.eval(pop, per_case=True)
+    print(f"giant plan {info}", flush=True)
+    order = np.argsort(sizes)
+    sample = sorted(set(order[:3].tolist() + [int(order[len(order) // 2]), int(order[-1])]))
+    parts = [buf[off[t]:off[t + 1]] for t in sample]
+    soff = workloads.offsets_from_sizes([p.size for p in parts])
+    want_fit, want_pc = oracle.eval_population(np.concatenate(parts), soff, x, y, threads=len(sample), per_case=True)
+    assert_same(fit[sample], want_fit, "giant fitness")
+    assert_same(pc[sample], want_pc, "giant per-case")
+
+
+def test_single_tree_populations(ev):
+    # every tree alone as its own population: each plan stands on its own
+    # (a lone tree whose stack only reaches the window's upper quarter still
+    # needs its spill slab)
+    buf, off, n = workloads.workload("batched")
+    x, y = workloads.cases(n)
+    sizes = np.diff(off)
+    pick = [int(t) for t in np.argsort(sizes)[::37][:120]] + [55, 57, 150, 155]
+    parts = [buf[off[t]:off[t + 1]] for t in pick]
+    want = oracle.eval_population(np.concatenate(parts), workloads.offsets_from_sizes([p.size for p in parts]), x, y,
+                                  threads=8)
+    with ev.Context(x, y) as c:
+        for i, p in enumerate(parts):
+            pop = c.load(np.ascontiguousarray(p), np.array([0, p.size], np.uint64))
+            f, _ = c.eval(pop)
+            assert_same(f, want[i:i + 1], f"tree {pick[i]} alone")
+            ev.ev_free_pop(c.ctx, pop)
