@@ -179,6 +179,53 @@ def serve_bench(args, ev, workloads):
     c.close()
 
 
+def calibrate_copy():
+    """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings give
+    the factor that turns those counters into HBM bytes."""
+    import torch
+
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
+
+
+KERNEL_SOURCES = ("paper_1902_09215_amd/csrc/ev_kernels.hip", "paper_1902_09215_amd/csrc/ev_internal.h",
+                  "paper_1902_09215_amd/csrc/gen_interp.py")
+
+
+def kernel_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per level-0 k_run launch from the committed counter summary
+    of this workload, or None when the kernel sources changed since."""
+    import re
+
+    path = os.path.join(ROOT, "profiles", f"k_run_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    vals = dict(re.findall(r"^- (\w+): ([0-9a-f.e+]+)$", text, re.M))
+    if vals.get("kernel_hash") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,11 +240,16 @@ def main():
     ap.add_argument("--cap", type=int, default=15_000_000, help="child size cap of the generation step")
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
     ap.add_argument("--load", type=float, default=0.8, help="serving: offered load as a fraction of capacity")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the evaluation path of this build is single-GPU "
-              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        print("bench.py runs on one GPU only: libev evaluates on a single device; sharding a "
+              "population over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
+
+    if args.calibrate_copy:
+        return calibrate_copy()
 
     import paper_1902_09215_amd as ev
     import workloads
@@ -308,7 +360,7 @@ def main():
             "load_and_plan_s": t_load,
         },
         "roofline": {
-            "kernel": "k_eval (level-0 interpreter launch)",
+            "kernel": "k_run (level-0 register-stack interpreter launch)",
             "bound": "alu",
             "achieved": interp_gpops / 1e12,
             "peak": PEAK_GPOPS / 1e12,
@@ -316,7 +368,8 @@ def main():
             "frac": interp_gpops / PEAK_GPOPS,
             "frac_unpacked": interp_gpops / PEAK_UNPACKED,
             "avg_launch_ms": interp_ms,
-            "traffic": None,
+            "work_per_launch": f"{nodes} level-0 tokens x {n_cases} cases",
+            "traffic": measured_traffic(args.workload),
         },
         "plain_one_tree_per_launch": plain,
         "cpu_baseline": cpu,

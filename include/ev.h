@@ -208,6 +208,17 @@ ev_status ev_get_plan_info(ev_ctx *ctx, ev_pop pop, ev_plan_info *info);
 #define EV_TUNE_NO_REGSTACK 0x1u
 ev_status ev_set_tuning(ev_ctx *ctx, uint32_t chunk, uint32_t lds_depth, uint32_t flags);
 
+/* Autotuner: re-plans population pop at each candidate work-item size
+ * (1024 .. 65536 tokens), times `reps` evaluations on case table `table`
+ * with device events, and keeps the fastest: pop is left planned with it and
+ * it becomes the context's work-item size for later plans.  Results never
+ * depend on the choice (every function node combines the same operands,
+ * Sec. 2.2).  *best_chunk and *best_ms (nullable) receive the choice and its
+ * median evaluation time.  Errors: EV_EINVAL, EV_ENOTFOUND, EV_ENOMEM,
+ * EV_EDEVICE. */
+ev_status ev_autotune(ev_ctx *ctx, ev_pop pop, int32_t table, int32_t reps, uint32_t *best_chunk,
+                      float *best_ms);
+
 /* Device time in milliseconds of the last ev_eval_fitness on this context
  * (HIP events around the evaluation kernels) and of its dominant kernel
  * (the level-0 interpreter launch). */

@@ -28,7 +28,7 @@ EXPORTS = [
     "ev_create", "ev_add_cases", "ev_destroy", "ev_last_error", "ev_load_trees", "ev_pop_info",
     "ev_get_trees", "ev_free_pop", "ev_eval_fitness", "ev_crossover", "ev_generation", "ev_submit",
     "ev_poll", "ev_wait", "ev_result", "ev_job_timing", "ev_get_plan_info", "ev_set_tuning",
-    "ev_last_timing",
+    "ev_autotune", "ev_last_timing",
 ]
 
 
@@ -82,6 +82,7 @@ def load_library(path: str = LIB_PATH):
         "ev_job_timing": [P, u64, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)],
         "ev_get_plan_info": [P, i32, ctypes.POINTER(ev_plan_info)],
         "ev_set_tuning": [P, u32, u32, u32],
+        "ev_autotune": [P, i32, i32, i32, ctypes.POINTER(u32), ctypes.POINTER(ctypes.c_float)],
         "ev_last_timing": [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
     }
     for name, args in sig.items():
@@ -280,6 +281,14 @@ EV_TUNE_NO_REGSTACK = 0x1
 
 def ev_set_tuning(ctx, chunk: int = 0, lds_depth: int = 0, flags: int = 0):
     _check(_lib.ev_set_tuning(ctx, chunk, lds_depth, flags))
+
+
+def ev_autotune(ctx, pop, table: int = 0, reps: int = 5):
+    """Pick the fastest work-item size for pop (see ev.h); returns (chunk, ms)."""
+    best = ctypes.c_uint32()
+    ms = ctypes.c_float()
+    _check(_lib.ev_autotune(ctx, pop, table, reps, ctypes.byref(best), ctypes.byref(ms)))
+    return best.value, ms.value
 
 
 def ev_last_timing(ctx):

@@ -561,27 +561,34 @@ ev_status stage(Exec& x, size_t n, void** out)
     return EV_OK;
 }
 
+// Large transfers pass through the staging buffer in pieces of this size.
+static constexpr size_t STAGE_PIECE = (size_t)64 << 20;
+
 // Host-to-device copy on x's stream (src may be reused on return).
 ev_status put(Exec& x, void* dst, const void* src, size_t n)
 {
-    if (n == 0) return EV_OK;
-    void* p = nullptr;
-    ev_status st = stage(x, n, &p);
-    if (st != EV_OK) return st;
-    std::memcpy(p, src, n);
-    HIPCHK(hipMemcpyAsync(dst, p, n, hipMemcpyHostToDevice, x.stream));
+    for (size_t o = 0; o < n; o += STAGE_PIECE) {
+        const size_t k = std::min(STAGE_PIECE, n - o);
+        void* p = nullptr;
+        ev_status st = stage(x, k, &p);
+        if (st != EV_OK) return st;
+        std::memcpy(p, (const uint8_t*)src + o, k);
+        HIPCHK(hipMemcpyAsync((uint8_t*)dst + o, p, k, hipMemcpyHostToDevice, x.stream));
+    }
     return EV_OK;
 }
 
 // Device-to-host copy on x's stream; dst holds the data once sync(x) returns.
 ev_status get(Exec& x, void* dst, const void* src, size_t n)
 {
-    if (n == 0) return EV_OK;
-    void* p = nullptr;
-    ev_status st = stage(x, n, &p);
-    if (st != EV_OK) return st;
-    HIPCHK(hipMemcpyAsync(p, src, n, hipMemcpyDeviceToHost, x.stream));
-    x.pin_out.push_back(Exec::Out{dst, p, n});
+    for (size_t o = 0; o < n; o += STAGE_PIECE) {
+        const size_t k = std::min(STAGE_PIECE, n - o);
+        void* p = nullptr;
+        ev_status st = stage(x, k, &p);
+        if (st != EV_OK) return st;
+        HIPCHK(hipMemcpyAsync(p, (const uint8_t*)src + o, k, hipMemcpyDeviceToHost, x.stream));
+        x.pin_out.push_back(Exec::Out{(uint8_t*)dst + o, p, k});
+    }
     return EV_OK;
 }
 
@@ -1096,6 +1103,56 @@ ev_status ev_set_tuning(ev_ctx* c, uint32_t chunk, uint32_t lds_depth, uint32_t 
     if (chunk != 0 && chunk < 64) return fail(EV_EINVAL, "chunk must be at least 64 tokens");
     if (chunk) c->chunk = chunk;
     if (lds_depth) c->lds_depth = (int)lds_depth;
+    return EV_OK;
+}
+
+ev_status ev_autotune(ev_ctx* c, ev_pop pop, int32_t table, int32_t reps, uint32_t* best_chunk, float* best_ms)
+{
+    if (!c || reps < 1) return fail(EV_EINVAL, "ev_autotune: bad arguments");
+    Pop* P = pop_get(c, pop);
+    if (!P) return fail(EV_ENOTFOUND, "no population %d", pop);
+    if (table < 0 || table >= (int32_t)c->tables.size()) return fail(EV_EINVAL, "no case table %d", table);
+    HIPCHK(hipSetDevice(c->device));
+    Exec& x = c->main;
+    // re-plan P with work items of `chunk` tokens
+    auto replan = [&](uint32_t chunk) -> ev_status {
+        if (ev_status st = sync(x)) return st;
+        for (auto& kv : P->res) rescache_free(c, kv.second);
+        P->res.clear();
+        plan_free(c, P->plan);
+        const uint32_t keep = c->chunk;
+        c->chunk = chunk;
+        ev_status st = plan_build(c, x, P, nullptr);
+        c->chunk = keep;
+        return st;
+    };
+    static const uint32_t cand[] = {1024, 2048, 4096, 8192, 16384, 32768, 65536};
+    uint32_t best = 0;
+    float best_t = 0;
+    for (uint32_t chunk : cand) {
+        ev_status st = replan(chunk);
+        if (st == EV_ENOMEM) continue;  // a finer split may not fit: skip it
+        if (st != EV_OK) return st;
+        std::vector<float> t;
+        for (int32_t r = 0; r <= reps; r++) {  // the first run warms the caches
+            if ((st = eval_enqueue(c, x, P, table, P->d_fit, nullptr, true)) != EV_OK) return st;
+            if ((st = sync(x)) != EV_OK) return st;
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, x.ev0, x.ev1));
+            if (r) t.push_back(ms);
+        }
+        std::sort(t.begin(), t.end());
+        const float med = t[t.size() / 2];
+        if (!best || med < best_t) {
+            best = chunk;
+            best_t = med;
+        }
+    }
+    if (!best) return fail(EV_ENOMEM, "ev_autotune: no candidate plan fits in memory");
+    if (ev_status st = replan(best)) return st;
+    c->chunk = best;
+    if (best_chunk) *best_chunk = best;
+    if (best_ms) *best_ms = best_t;
     return EV_OK;
 }
 

@@ -100,17 +100,13 @@ static ev_status run_eval_batch(ev_ctx* c, Exec& x, std::vector<Job*>& batch)
     float* d_pc = nullptr;
     std::vector<float> fit(M), pc((size_t)M * N);
     if ((st = dev_alloc(c, total + 512, (void**)&d)) == EV_OK) {
-        // the batch's trees are gathered straight into pinned staging
-        uint8_t* h = nullptr;
-        st = stage(x, total, (void**)&h);
-        hipError_t e = hipSuccess;
+        uint64_t at = 0;
+        for (Job* j : batch) {
+            if (st == EV_OK) st = put(x, d + at, j->bytes.data(), j->bytes.size());
+            at += j->bytes.size();
+        }
         if (st == EV_OK) {
-            for (Job* j : batch) {
-                std::memcpy(h, j->bytes.data(), j->bytes.size());
-                h += j->bytes.size();
-            }
-            e = hipMemcpyAsync(d, h - total, total, hipMemcpyHostToDevice, x.stream);
-            if (e == hipSuccess) e = hipMemsetAsync(d + total, 0xFF, 512, x.stream);
+            hipError_t e = hipMemsetAsync(d + total, 0xFF, 512, x.stream);
             if (e != hipSuccess) st = hip_fail(e, "serve upload");
         }
         if (st != EV_OK) {

@@ -5,6 +5,8 @@ differ between x86 and AMD), because both sides apply the same binary32
 operations to the same operands in the same order and reduce the fitness
 in ascending case order.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -227,6 +229,54 @@ def test_generations_match_oracle(ev):
             assert_same(fit, wfit, f"gen {g + 1} fitness")
             ev.ev_free_pop(c.ctx, pop)
             pop, buf, off = kids, wbuf, woff
+
+
+def test_generation_loop_1000_generations(ev):
+    # The full generational loop on the device: population 48, ramped
+    # half-and-half start, size-2 tournaments, Philox points, 15e6-node cap,
+    # 1000 generations.  Every generation's trees and fitness are compared
+    # with the oracle's, bit for bit.
+    x, y = workloads.cases(48)
+    buf, off = workloads.rhh_population(workloads.SEED_BASE + 4, 48, 2, 6)
+    seed, gens, cap = 0x5EED0004, 1000, 15_000_000
+    threads = min(os.cpu_count() or 1, 16)
+    with ev.Context(x, y) as c:
+        pop = c.load(buf, off)
+        fit, _ = c.eval(pop)
+        wfit = oracle.eval_population(buf, off, x, y, threads=threads)
+        assert_same(fit, wfit, "gen 0")
+        for g in range(gens):
+            kids, capped = ev.ev_generation(c.ctx, pop, seed, g, 2, cap)
+            wbuf, woff, wcap = oracle.generation(buf, off, wfit, 2, seed, g, cap)
+            gbuf, goff = ev.ev_get_trees(c.ctx, kids)
+            assert capped == wcap, f"gen {g} capped"
+            assert np.array_equal(goff, woff), f"gen {g} offsets"
+            assert np.array_equal(gbuf, wbuf), f"gen {g} trees"
+            fit, _ = c.eval(kids)
+            wfit = oracle.eval_population(wbuf, woff, x, y, threads=threads)
+            assert_same(fit, wfit, f"gen {g + 1} fitness")
+            ev.ev_free_pop(c.ctx, pop)
+            pop, buf, off = kids, wbuf, woff
+            if g % 100 == 99:
+                print(f"generation {g + 1}: mean size {np.diff(off).mean():.0f}, best {np.nanmin(wfit):.6g}",
+                      flush=True)
+
+
+def test_autotune_keeps_results(ev):
+    x, y = workloads.cases(48)
+    sizes = workloads.loguniform_sizes(53, 500, 10, 1e5)
+    buf, off = workloads.random_population(53, sizes)
+    with ev.Context(x, y) as c:
+        pop = c.load(buf, off)
+        fit0, pc0 = c.eval(pop, per_case=True)
+        chunk, ms = ev.ev_autotune(c.ctx, pop, 0, 3)
+        assert chunk in (1024, 2048, 4096, 8192, 16384, 32768, 65536) and ms > 0
+        fit1, pc1 = c.eval(pop, per_case=True)
+        pop2 = c.load(buf, off)  # planned with the tuned size
+        fit2, _ = c.eval(pop2)
+    assert_same(fit0, fit1, "fitness after autotune")
+    assert_same(pc0, pc1, "per-case after autotune")
+    assert_same(fit0, fit2, "fitness of a population planned with the tuned size")
 
 
 def test_serving_results_same_alone_and_mixed(ev):
