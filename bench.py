@@ -235,6 +235,7 @@ def main():
     ap.add_argument("--eval-reps", type=int, default=50)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--lds", type=int, default=0)
+    ap.add_argument("--chunk-hi", type=int, default=0, help="work-item size of the skeleton levels")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-trees", type=int, default=300)
     ap.add_argument("--cap", type=int, default=15_000_000, help="child size cap of the generation step")
@@ -260,8 +261,8 @@ def main():
     x, y = workloads.cases(n_cases)
     M = off.size - 1
     c = ev.Context(x, y, device=0)
-    if args.chunk or args.lds:
-        ev.ev_set_tuning(c.ctx, args.chunk, args.lds)
+    if args.chunk or args.lds or args.chunk_hi:
+        ev.ev_set_tuning(c.ctx, args.chunk, args.lds, 0, args.chunk_hi)
     t_load = time.perf_counter()
     parents = c.load(buf, off)
     t_load = time.perf_counter() - t_load

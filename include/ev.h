@@ -201,12 +201,14 @@ typedef struct {
 ev_status ev_get_plan_info(ev_ctx *ctx, ev_pop pop, ev_plan_info *info);
 
 /* Tuning knobs (0 keeps the current value): chunk = tokens per work item
- * of the split, lds_depth = operand-stack entries kept in LDS per wave by
- * the general interpreter (64 or 128).  flags: EV_TUNE_NO_REGSTACK runs
- * every work item on the general interpreter instead of the register-stack
- * one.  Plans made afterwards use them; results never depend on them. */
+ * of the split at level 0, chunk_hi = at the skeleton levels (default:
+ * the same as chunk), lds_depth = operand-stack entries kept in LDS
+ * per wave by the general interpreter (64 or 128).  flags:
+ * EV_TUNE_NO_REGSTACK runs every work item on the general interpreter
+ * instead of the register-stack one.  Plans made afterwards use them;
+ * results never depend on them. */
 #define EV_TUNE_NO_REGSTACK 0x1u
-ev_status ev_set_tuning(ev_ctx *ctx, uint32_t chunk, uint32_t lds_depth, uint32_t flags);
+ev_status ev_set_tuning(ev_ctx *ctx, uint32_t chunk, uint32_t chunk_hi, uint32_t lds_depth, uint32_t flags);
 
 /* Autotuner: re-plans population pop at each candidate work-item size
  * (1024 .. 65536 tokens), times `reps` evaluations on case table `table`

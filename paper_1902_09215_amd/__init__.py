@@ -81,7 +81,7 @@ def load_library(path: str = LIB_PATH):
         "ev_result": [P, u64, P, P, i32, ctypes.POINTER(i32)],
         "ev_job_timing": [P, u64, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)],
         "ev_get_plan_info": [P, i32, ctypes.POINTER(ev_plan_info)],
-        "ev_set_tuning": [P, u32, u32, u32],
+        "ev_set_tuning": [P, u32, u32, u32, u32],
         "ev_autotune": [P, i32, i32, i32, ctypes.POINTER(u32), ctypes.POINTER(ctypes.c_float)],
         "ev_last_timing": [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
     }
@@ -279,8 +279,8 @@ def ev_get_plan_info(ctx, pop) -> dict:
 EV_TUNE_NO_REGSTACK = 0x1
 
 
-def ev_set_tuning(ctx, chunk: int = 0, lds_depth: int = 0, flags: int = 0):
-    _check(_lib.ev_set_tuning(ctx, chunk, lds_depth, flags))
+def ev_set_tuning(ctx, chunk: int = 0, lds_depth: int = 0, flags: int = 0, chunk_hi: int = 0):
+    _check(_lib.ev_set_tuning(ctx, chunk, chunk_hi, lds_depth, flags))
 
 
 def ev_autotune(ctx, pop, table: int = 0, reps: int = 5):

@@ -69,7 +69,7 @@ struct RunChunk {
 };
 
 struct RunArgs {
-    const uint16_t* codes;
+    const uint32_t* codes;
     const RunChunk* chunks;
     uint32_t n_items;
     uint32_t n_cb;
@@ -81,6 +81,7 @@ struct RunArgs {
     float* out_res;
     float* slab;            // spill slabs, one per wave of the grid
     uint64_t slab_entries;  // rows of 64 floats per slab
+    uint32_t* flag;         // set to 1 if the interpreter's table cannot be used (see gen_interp.py)
 };
 
 // A work item as the evaluator sees it (32 bytes).

@@ -84,17 +84,26 @@ __device__ __forceinline__ uint32_t norm_base(uint32_t m)
     return m < EV_VSTACK - EV_VHALF / 2 ? 0u : (m - EV_VHALF / 2) / EV_VHALF * EV_VHALF;
 }
 
+// Handler offset of a code at index `at` (its position is at mod 32): the
+// layout written by gen_interp.py.
+__device__ __forceinline__ uint32_t code_value(uint64_t at, uint32_t kind)
+{
+    const uint32_t pos = (uint32_t)(at & (EV_CODE_POS - 1));
+    if ((pos & 15u) == 15u) return EV_CODE_TBASE + (pos >> 4) * EV_NK * EV_CODE_TSTRIDE + kind * EV_CODE_TSTRIDE;
+    return (pos - (pos >> 4)) * EV_NK * EV_CODE_NSTRIDE + kind * EV_CODE_NSTRIDE;
+}
+
 struct Sink {
-    uint16_t* codes;   // nullptr: count codes only
+    uint32_t* codes;   // nullptr: count codes only
     uint64_t at;       // global index of the next code
     uint8_t* frag;     // nullptr: count fragment tokens only
     uint64_t w;        // one past the next fragment token (written backwards)
     uint32_t n_codes, n_frag, n_out, n_in;
-    uint32_t pending;  // EV_K_PUSHX / EV_K_LOADX waiting for fusion, or ~0u
+    uint32_t pending;  // an action waiting for a partner to fuse with, or ~0u
 
     __device__ void put(uint32_t kind)
     {
-        if (codes) codes[at] = (uint16_t)((uint32_t)(at & (EV_CODE_POS - 1)) * EV_CODE_BLOCK + kind * EV_CODE_STRIDE);
+        if (codes) codes[at] = code_value(at, kind);
         at++;
         n_codes++;
     }
@@ -105,17 +114,30 @@ struct Sink {
             pending = ~0u;
         }
     }
+    // Fusions: a push or load of x then a function of x (CH, LCH); two
+    // pushes of x (PUSH2X); two pops by + - * in a row (OPSab).
     __device__ void code(uint32_t kind)
     {
         if (pending != ~0u) {
-            if (kind >= EV_K_OPX0 && kind <= EV_K_OPX3) {
-                put((pending == EV_K_PUSHX ? EV_K_CH0 : EV_K_LCH0) + (kind - EV_K_OPX0));
+            const uint32_t p = pending;
+            if ((p == EV_K_PUSHX || p == EV_K_LOADX) && kind >= EV_K_OPX0 && kind <= EV_K_OPX3) {
                 pending = ~0u;
+                put((p == EV_K_PUSHX ? EV_K_CH0 : EV_K_LCH0) + (kind - EV_K_OPX0));
+                return;
+            }
+            if (p == EV_K_PUSHX && kind == EV_K_PUSHX) {
+                pending = ~0u;
+                put(EV_K_PUSH2X);
+                return;
+            }
+            if (p <= EV_K_OPS2 && kind <= EV_K_OPS2) {
+                pending = ~0u;
+                put(EV_K_OPS00 + p * 3u + kind);
                 return;
             }
             flush();
         }
-        if (kind == EV_K_PUSHX || kind == EV_K_LOADX) {
+        if (kind == EV_K_PUSHX || kind == EV_K_LOADX || kind <= EV_K_OPS2) {
             pending = kind;
             return;
         }
@@ -373,7 +395,7 @@ __global__ void k_seg_chunk(const ChunkSegs* __restrict__ cseg, uint32_t n, cons
 
 __global__ void k_seg_emit(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs, uint32_t n,
                            const SegStart* __restrict__ st, const uint64_t* __restrict__ seg_code,
-                           const uint64_t* __restrict__ seg_frag, uint8_t* __restrict__ dst, uint16_t* __restrict__ codes)
+                           const uint64_t* __restrict__ seg_frag, uint8_t* __restrict__ dst, uint32_t* __restrict__ codes)
 {
     const uint32_t si = blockIdx.x * blockDim.x + threadIdx.x;
     if (si >= n) return;
@@ -390,7 +412,7 @@ __global__ void k_seg_emit(const uint8_t* __restrict__ seq, const SegIn* __restr
 // below it, the slab within its rows, must end with the window in its
 // boundary position and must write and read exactly the slots the plan
 // gave the segment.  Anything else fails the plan before a code runs.
-__global__ void k_seg_check(const uint16_t* __restrict__ codes, const SegIn* __restrict__ segs, uint32_t n,
+__global__ void k_seg_check(const uint32_t* __restrict__ codes, const SegIn* __restrict__ segs, uint32_t n,
                             const SegStart* __restrict__ st, const uint64_t* __restrict__ seg_code,
                             const SegCount* __restrict__ cnt, uint32_t slab_entries, uint32_t* __restrict__ err)
 {
@@ -409,8 +431,18 @@ __global__ void k_seg_check(const uint16_t* __restrict__ codes, const SegIn* __r
     // slots written/read differ from the plan
     for (uint32_t i = 0; i < len; i++) {
         const uint32_t v = codes[b + i];
-        const uint32_t pos = v / EV_CODE_BLOCK, r = v % EV_CODE_BLOCK, k = r / EV_CODE_STRIDE;
-        if (r % EV_CODE_STRIDE || pos != (uint32_t)((b + i) & (EV_CODE_POS - 1)) || k > EV_K_OUTMEM) bad |= 1;
+        const uint32_t pos = (uint32_t)((b + i) & (EV_CODE_POS - 1));
+        uint32_t k;
+        if ((pos & 15u) == 15u) {
+            const uint32_t base = EV_CODE_TBASE + (pos >> 4) * EV_NK * EV_CODE_TSTRIDE;
+            k = (v - base) / EV_CODE_TSTRIDE;
+            if (v < base || (v - base) % EV_CODE_TSTRIDE) bad |= 1;
+        } else {
+            const uint32_t base = (pos - (pos >> 4)) * EV_NK * EV_CODE_NSTRIDE;
+            k = (v - base) / EV_CODE_NSTRIDE;
+            if (v < base || (v - base) % EV_CODE_NSTRIDE) bad |= 1;
+        }
+        if (k >= EV_NK) bad |= 1;
         if (ended) bad |= 4;
         if (k == EV_K_END) ended = 1;
         uint32_t w = 0;
@@ -418,9 +450,16 @@ __global__ void k_seg_check(const uint16_t* __restrict__ codes, const SegIn* __r
             w |= idx < 1;
             idx--;
             m--;
+        } else if (k >= EV_K_OPS00 && k < EV_NK) {
+            w |= idx < 2;
+            idx -= 2;
+            m -= 2;
         } else if ((k >= EV_K_CH0 && k <= EV_K_CH3) || k == EV_K_PUSHX || k == EV_K_PUSHREF) {
             idx++;
             m++;
+        } else if (k == EV_K_PUSH2X) {
+            idx += 2;
+            m += 2;
         } else if (k == EV_K_FLUSH) {
             fl = 0;
         } else if (k == EV_K_OUTBOT) {
@@ -779,7 +818,7 @@ __global__ __launch_bounds__(64) void k_run(RunArgs a)
         if (cs < a.N) {
             const float xv = a.x[cs];
             const uint32_t lane4 = (uint32_t)cs * 4u;
-            const uint64_t cptr = (uint64_t)(uintptr_t)a.codes + (code_begin & ~(uint64_t)31) * 2u;
+            const uint64_t cptr = (uint64_t)(uintptr_t)a.codes + (code_begin & ~(uint64_t)31) * 4u;
             const uint32_t j0 = (uint32_t)(code_begin & 31u);
             const uint64_t inp = (uint64_t)(uintptr_t)a.in_res + (uint64_t)d.z * a.rowb;
             const uint64_t outp = (uint64_t)(uintptr_t)a.out_res + (uint64_t)d.w * a.rowb;
@@ -787,7 +826,8 @@ __global__ __launch_bounds__(64) void k_run(RunArgs a)
             asm volatile(EV_INTERP_ASM
                          :
                          : [x] "v"(xv), [lane4] "v"(lane4), [slane] "v"(slane), [cptr] "s"(cptr), [j0] "s"(j0),
-                           [inp] "s"(inp), [outp] "s"(outp), [rowb] "s"(a.rowb), [smem] "s"(smem)
+                           [inp] "s"(inp), [outp] "s"(outp), [rowb] "s"(a.rowb), [smem] "s"(smem),
+                           [flag] "s"(a.flag)
                          : EV_INTERP_CLOBBERS);
         }
         item = next;
@@ -844,14 +884,14 @@ hipError_t launch_seg_chunk(const ChunkSegs* cseg, uint32_t n, const SegCount* c
 }
 
 hipError_t launch_seg_emit(const uint8_t* seq, const SegIn* segs, uint32_t n, const SegStart* st, const uint64_t* seg_code,
-                           const uint64_t* seg_frag, uint8_t* dst, uint16_t* codes, hipStream_t s)
+                           const uint64_t* seg_frag, uint8_t* dst, uint32_t* codes, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_seg_emit, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, st, seg_code, seg_frag, dst, codes);
     return hipGetLastError();
 }
 
-hipError_t launch_seg_check(const uint16_t* codes, const SegIn* segs, uint32_t n, const SegStart* st,
+hipError_t launch_seg_check(const uint32_t* codes, const SegIn* segs, uint32_t n, const SegStart* st,
                             const uint64_t* seg_code, const SegCount* cnt, uint32_t slab_entries, uint32_t* err,
                             hipStream_t s)
 {

@@ -16,8 +16,8 @@ hipError_t launch_seg_chunk(const ChunkSegs* cseg, uint32_t n, const SegCount* c
                             const uint64_t* code_begin, const uint64_t* frag_end, uint64_t* seg_code, uint64_t* seg_frag,
                             hipStream_t s);
 hipError_t launch_seg_emit(const uint8_t* seq, const SegIn* segs, uint32_t n, const SegStart* st, const uint64_t* seg_code,
-                           const uint64_t* seg_frag, uint8_t* dst, uint16_t* codes, hipStream_t s);
-hipError_t launch_seg_check(const uint16_t* codes, const SegIn* segs, uint32_t n, const SegStart* st,
+                           const uint64_t* seg_frag, uint8_t* dst, uint32_t* codes, hipStream_t s);
+hipError_t launch_seg_check(const uint32_t* codes, const SegIn* segs, uint32_t n, const SegStart* st,
                             const uint64_t* seg_code, const SegCount* cnt, uint32_t slab_entries, uint32_t* err,
                             hipStream_t s);
 size_t eval_lds_bytes(int D);

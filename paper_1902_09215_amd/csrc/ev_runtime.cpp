@@ -170,9 +170,11 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
 {
     hipStream_t s = x.stream;
     const int32_t M = P->M;
-    const uint64_t C = c->chunk;
+    const uint64_t C0 = c->chunk;
+    // work-item size of the skeleton levels (by default the same as level 0)
+    const uint64_t C1 = c->chunk_hi ? c->chunk_hi : C0;
     Plan& pl = P->plan;
-    pl.chunk = (uint32_t)C;
+    pl.chunk = (uint32_t)C0;
     pl.D = c->lds_depth;
     pl.fin_level.assign(M, -1);
     pl.fin_slot.assign(M, 0);
@@ -242,6 +244,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
     };
 
     for (;;) {
+        const uint64_t C = level == 0 ? C0 : C1;
         std::vector<ChunkIn> ch;
         std::vector<char> forced(M, 0);
         for (int32_t t = 0; t < M; t++) {
@@ -367,9 +370,10 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             std::vector<RunChunk> rc(run.size());
             for (size_t i = 0; i < run.size(); i++) rc[i] = run[i].second;
             if ((st = dev_alloc(c, rc.size() * sizeof(RunChunk), (void**)&LL.d_run)) != EV_OK) { cleanup(); return st; }
-            if ((st = dev_alloc(c, sc * 2 + 256, (void**)&LL.codes)) != EV_OK) { cleanup(); return st; }
+            if ((st = dev_alloc(c, sc * 4 + 512, (void**)&LL.codes)) != EV_OK) { cleanup(); return st; }
             if ((st = put(x, LL.d_run, rc.data(), rc.size() * sizeof(RunChunk))) != EV_OK) { cleanup(); return st; }
-            HIPCHK(hipMemsetAsync((uint8_t*)LL.codes + sc * 2, 0, 256, s));
+            // the interpreter reads up to 192 bytes past a stream's last code block
+            HIPCHK(hipMemsetAsync((uint8_t*)LL.codes + sc * 4, 0, 512, s));
         }
 
         // trees finished at this level and the next level's ranges
@@ -708,6 +712,7 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
             r.out_res = rc->res[li];
             r.slab = x.d_gstack;
             r.slab_entries = L.slab_entries;
+            r.flag = c->d_flag;
             HIPCHK(launch_run(r, (uint32_t)std::min<uint64_t>((uint64_t)c->grid_run, r.n_items), s));
         }
         if (L.n_chunks == 0) {
@@ -834,6 +839,8 @@ using namespace ev;
 
 extern "C" {
 
+static ev_status run_probe(ev_ctx* c);
+
 const char* ev_last_error(void) { return g_err.c_str(); }
 
 ev_status ev_create(ev_ctx** out, int device, const float* x, const float* y, int32_t n_cases,
@@ -872,9 +879,62 @@ ev_status ev_create(ev_ctx** out, int device, const float* x, const float* y, in
     }
     int32_t tid = 0;
     ev_status st = ev_add_cases(c, x, y, n_cases, &tid);
+    if (st == EV_OK) st = dev_alloc(c, 256, (void**)&c->d_flag);
+    if (st == EV_OK) st = run_probe(c);
     if (st != EV_OK) { ev_destroy(c); return st; }
     *out = c;
     return EV_OK;
+}
+
+// One launch of k_run over a one-code stream (END) on case table 0: the
+// interpreter's prologue sets the flag word when its jump table cannot be
+// used from the address the code object was loaded at; the register-stack
+// path is then switched off for the context.
+static ev_status run_probe(ev_ctx* c)
+{
+    Exec& x = c->main;
+    void* buf = nullptr;
+    ev_status st = dev_alloc(c, 4096, &buf);
+    if (st != EV_OK) return st;
+    uint32_t* codes = (uint32_t*)buf;                    // [0, 1024): one code and zeros
+    RunChunk* chunk = (RunChunk*)((char*)buf + 1024);  // [1024, 1040)
+    uint32_t* counter = (uint32_t*)((char*)buf + 1280);
+    float* slot = (float*)((char*)buf + 2048);
+    std::vector<uint8_t> h(1536, 0);
+    const uint32_t end_code = EV_K_END * EV_CODE_NSTRIDE;  // END at position 0
+    std::memcpy(h.data(), &end_code, 4);
+    const RunChunk rc{0, 0, 0};
+    std::memcpy(h.data() + 1024, &rc, sizeof rc);
+    const uint32_t zero = 0;
+    if ((st = put(x, buf, h.data(), h.size())) == EV_OK) st = put(x, c->d_flag, &zero, 4);
+    RunArgs r{};
+    r.codes = codes;
+    r.chunks = chunk;
+    r.n_items = 1;
+    r.n_cb = 1;
+    r.counter = counter;
+    r.x = c->tables[0].d_x;
+    r.N = 1;
+    r.rowb = 4;
+    r.in_res = slot;
+    r.out_res = slot;
+    r.slab = nullptr;
+    r.slab_entries = 0;
+    r.flag = c->d_flag;
+    uint32_t flag = 0;
+    if (st == EV_OK) {
+        hipError_t e = launch_run(r, 1, x.stream);
+        if (e != hipSuccess) st = hip_fail(e, "probe launch");
+    }
+    if (st == EV_OK) st = get(x, &flag, c->d_flag, 4);
+    if (st == EV_OK) st = sync(x);
+    else (void)sync(x);
+    dev_free(c, buf);
+    if (st == EV_OK && flag) {
+        c->run_ok = false;
+        c->use_run = false;
+    }
+    return st;
 }
 
 ev_status ev_add_cases(ev_ctx* c, const float* x, const float* y, int32_t n, int32_t* table)
@@ -907,6 +967,7 @@ ev_status ev_destroy(ev_ctx* c)
     for (auto& kv : c->pops) pop_free(c, kv.second);
     c->pops.clear();
     for (auto& t : c->tables) { dev_free(c, t.d_x); dev_free(c, t.d_y); }
+    dev_free(c, c->d_flag);
     exec_free(c, c->main);
     dev_cache_release(c);
     delete c;
@@ -1095,13 +1156,15 @@ ev_status ev_get_plan_info(ev_ctx* c, ev_pop pop, ev_plan_info* info)
     return EV_OK;
 }
 
-ev_status ev_set_tuning(ev_ctx* c, uint32_t chunk, uint32_t lds_depth, uint32_t flags)
+ev_status ev_set_tuning(ev_ctx* c, uint32_t chunk, uint32_t chunk_hi, uint32_t lds_depth, uint32_t flags)
 {
     if (!c) return fail(EV_EINVAL, "NULL context");
-    c->use_run = (flags & EV_TUNE_NO_REGSTACK) == 0;
     if (lds_depth != 0 && lds_depth != 64 && lds_depth != 128) return fail(EV_EINVAL, "lds_depth must be 64 or 128");
-    if (chunk != 0 && chunk < 64) return fail(EV_EINVAL, "chunk must be at least 64 tokens");
+    if ((chunk != 0 && chunk < 64) || (chunk_hi != 0 && chunk_hi < 64))
+        return fail(EV_EINVAL, "work items must be at least 64 tokens");
+    c->use_run = c->run_ok && (flags & EV_TUNE_NO_REGSTACK) == 0;
     if (chunk) c->chunk = chunk;
+    if (chunk_hi) c->chunk_hi = chunk_hi;
     if (lds_depth) c->lds_depth = (int)lds_depth;
     return EV_OK;
 }

@@ -31,7 +31,7 @@ struct Level {
     bool owned = false;
     EvalChunk* d_chunks = nullptr;  // work items of the general kernel (k_eval)
     uint32_t n_chunks = 0;
-    uint16_t* codes = nullptr;      // threaded codes of the register-stack items
+    uint32_t* codes = nullptr;      // threaded codes of the register-stack items
     RunChunk* d_run = nullptr;      // work items of the register-stack kernel (k_run)
     uint32_t n_run = 0;
     uint64_t tokens = 0;            // tokens over all work items of the level
@@ -102,7 +102,10 @@ struct ev_ctx {
     int grid_eval[2] = {0, 0};
     int grid_run = 0;
     bool use_run = true;  // register-stack kernel for the items that fit it
-    uint32_t chunk = 4096;
+    bool run_ok = true;   // the register-stack kernel can run here (probed at creation)
+    uint32_t* d_flag = nullptr;  // the probe's flag word
+    uint32_t chunk = 4096;     // tokens per work item at level 0
+    uint32_t chunk_hi = 0;     // at the skeleton levels (0: the same as chunk)
     int lds_depth = 64;
 
     ev::Exec main;

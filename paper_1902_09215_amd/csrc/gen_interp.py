@@ -1,12 +1,26 @@
 """Generate the gfx950 threaded-code interpreter used by k_run (ev_interp.inc).
 
-The structure pass (k_decode) turns each work item's tokens into a stream of
-16-bit codes, one per action of the right-to-left stack machine, with the
-leaves folded into the functions that consume them.  A code's value is the
-byte offset of its handler: position * BLOCK + kind * STRIDE, where position
-is the code's index modulo 32.  Handlers are unrolled per position because
-each must pick the next code out of a fixed SGPR of the 64-byte buffer
-s[64:79] (refilled from s[80:95], prefetched one buffer ahead).
+The structure passes (k_seg_count / k_seg_emit) turn each work item's tokens
+into a stream of 32-bit codes, one per action of the right-to-left stack
+machine, with leaves folded into the functions that consume them and common
+pairs of actions fused into one code.  A code's value is the byte offset of
+its handler from the handler table: handlers are unrolled per position
+(the code's index modulo 32), because each must find the next code in a
+fixed SGPR of the 128-byte code block held in s[64:95].
+
+Code blocks: s[64:79] holds positions 0..15 and s[80:95] positions 16..31.
+Position 15's handler waits for the upper half and starts loading the next
+block's lower half into s[64:79]; position 31's handler advances the block
+pointer, waits for that lower half and starts loading the upper half.  So a
+refill costs one scalar load per 16 codes and no register copies.
+
+Dispatch is `s_add_u32 s44, s42, s[next]` + `s_setpc_b64 s[44:45]`, with s45
+(and s47, for calls) equal to the table's high address word: the table must
+not cross a 4 GiB boundary, which the prologue checks (a launch that finds a
+carry writes 1 to the flag word and evaluates nothing; the library probes
+this once per device and falls back to k_eval if ever needed).  Every
+handler is placed with .org at its exact offset, so a handler that outgrew
+its slot is an assembler error, never a wrong jump.
 
 Register use inside the block:
   v[12 + m]       top of the operand stack (T); v[12..12+m-1] the entries
@@ -14,36 +28,50 @@ Register use inside the block:
                   GPR-index mode (s_set_gpr_idx_on), set once per handler.
   v4..v10         temporaries (division), v4 also a staging register
   %[x], %[lane4]  the lane's input value and byte offset (not clobbered)
-  s[40:41] code pointer (64-byte block), s[42:43] handler table base,
+  s[40:41] code block pointer (128-byte aligned), s[42:43] handler table,
   s[44:45] jump target, s[46:47] call target, s[48:49] return address,
   s[50:51] input-slot row pointer, s[52:53] output-slot row pointer,
   s54 row bytes (cases * 4), s55 window index of T, s[56:57] division
-  scratch, s58 code, s59 flush index, s[60:61] next free entry of the
+  scratch, s58 scratch, s59 flush index, s[60:61] next free entry of the
   wave's spill slab in global memory, s[62:63] the slab's base.
 
-When the decoder sees the stack outgrow the 64-entry window it emits SPILL
-(store the bottom 32 entries to the slab, shift the window down); when a
-function needs an entry below the window it emits FILL (the reverse).  So
-the kernel never tests the stack depth; the device validator simulates the
-window index and slab depth of every code stream before it may run.
+When the structure machine sees the stack outgrow the window it emits SPILL
+(store the bottom half of the window to the slab, shift the window down);
+when a function needs an entry below the window it emits FILL (the
+reverse).  So the kernel never tests the stack depth; the device validator
+simulates the window index and slab depth of every code stream before it
+may run.
 """
 from __future__ import annotations
 
 import os
 import sys
 
-STRIDE = 64
 VSTACK = int(os.environ.get("EV_VSTACK", "64"))  # register-stack entries: v12 .. v12+VSTACK-1
 HALF = VSTACK // 2  # entries moved by one spill or fill
+POS = 32  # positions per 128-byte code block
+NSTRIDE = 32  # bytes per handler at ordinary positions
+TSTRIDE = 64  # bytes per handler at positions 15 and 31 (they also refill)
 KINDS = ["OPS0", "OPS1", "OPS2", "OPS3", "OPX0", "OPX1", "OPX2", "OPX3",
          "CH0", "CH1", "CH2", "CH3", "LCH0", "LCH1", "LCH2", "LCH3",
          "PUSHX", "LOADX", "PUSHREF", "LOADREF", "OUTT", "OUTX", "FLUSH", "OUTBOT", "END",
-         "SPILL", "FILL", "OUTMEM"]
+         "SPILL", "FILL", "OUTMEM", "PUSH2X"] + [f"OPS{a}{b}" for a in range(3) for b in range(3)]
 NK = len(KINDS)
-BLOCK = NK * STRIDE
-POS = 32
-assert POS * BLOCK < 65536
+TBASE = (POS - 2) * NK * NSTRIDE  # first byte of the position-15 and -31 handlers
+TABLE_BYTES = TBASE + 2 * NK * TSTRIDE
 VOP = {0: "v_add_f32_e32", 1: "v_sub_f32_e32", 2: "v_mul_f32_e32"}
+
+
+def is_transition(pos: int) -> bool:
+    return pos % 16 == 15
+
+
+def code_of(pos: int, kind: int) -> int:
+    """Handler offset from the table base for a code at this position."""
+    if is_transition(pos):
+        return TBASE + (pos // 16) * NK * TSTRIDE + kind * TSTRIDE
+    return (pos - pos // 16) * NK * NSTRIDE + kind * NSTRIDE
+
 
 # Correctly rounded binary32 division a/b (the sequence hipcc emits for
 # IEEE-mode division on gfx950), then protection: b != 0 ? a/b : 1.0f.
@@ -67,18 +95,20 @@ DIV_BODY = """\
 
 
 def dispatch(pos: int) -> list[str]:
-    """Jump to the handler of the code at position pos+1."""
-    nxt = pos + 1
-    if nxt == POS:
-        return ["s_branch .Lrefill%="]
-    word = 64 + nxt // 2
-    ext = f"s_and_b32 s58, s{word}, 0xffff" if nxt % 2 == 0 else f"s_lshr_b32 s58, s{word}, 16"
-    return [ext, "s_add_u32 s44, s42, s58", "s_addc_u32 s45, s43, 0", "s_setpc_b64 s[44:45]"]
+    """Jump to the handler of the code at position pos+1 (refilling the
+    code block halves at positions 15 and 31)."""
+    nxt = (pos + 1) % POS
+    pre: list[str] = []
+    if pos == 15:
+        pre = ["s_waitcnt lgkmcnt(0)", "s_load_dwordx16 s[64:79], s[40:41], 0x80"]
+    elif pos == 31:
+        pre = ["s_add_u32 s40, s40, 0x80", "s_addc_u32 s41, s41, 0", "s_waitcnt lgkmcnt(0)",
+               "s_load_dwordx16 s[80:95], s[40:41], 0x40"]
+    return pre + [f"s_add_u32 s44, s42, s{64 + nxt}", "s_setpc_b64 s[44:45]"]
 
 
 def call(routine: str) -> list[str]:
-    return [f"s_add_u32 s46, s42, .L{routine}%= - .Ltab%=", "s_addc_u32 s47, s43, 0",
-            "s_swappc_b64 s[48:49], s[46:47]"]
+    return [f"s_add_u32 s46, s42, .L{routine}%= - .Ltab%=", "s_swappc_b64 s[48:49], s[46:47]"]
 
 
 def row_dec(lo: int) -> list[str]:
@@ -88,11 +118,17 @@ def row_dec(lo: int) -> list[str]:
 def handler(kind: str, pos: int) -> list[str]:
     k = kind
     body: list[str]
-    if k.startswith("OPS"):
-        op = int(k[3])
+    if k in ("OPS0", "OPS1", "OPS2"):
         # T' = op(T, below): dst v[11+m], src0 v[12+m] (T), src1 v[11+m]
-        body = call("divops") if op == 3 else [
-            "s_set_gpr_idx_on s55, gpr_idx(SRC0,SRC1,DST)", f"{VOP[op]} v11, v12, v11", "s_sub_u32 s55, s55, 1"]
+        body = ["s_set_gpr_idx_on s55, gpr_idx(SRC0,SRC1,DST)", f"{VOP[int(k[3])]} v11, v12, v11",
+                "s_sub_u32 s55, s55, 1"]
+    elif k == "OPS3":
+        body = call("divops")
+    elif len(k) == 5 and k.startswith("OPS"):
+        # two pops in a row: the second works one entry lower
+        a, b = int(k[3]), int(k[4])
+        body = ["s_set_gpr_idx_on s55, gpr_idx(SRC0,SRC1,DST)", f"{VOP[a]} v11, v12, v11",
+                f"{VOP[b]} v10, v11, v10", "s_sub_u32 s55, s55, 2"]
     elif k.startswith("OPX"):
         op = int(k[3])
         # T = op(x, T)
@@ -110,27 +146,19 @@ def handler(kind: str, pos: int) -> list[str]:
             "s_set_gpr_idx_on s55, gpr_idx(DST)", f"{VOP[op]} v12, %[x], %[x]"]
     elif k == "PUSHX":
         body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v13, %[x]", "s_add_u32 s55, s55, 1"]
+    elif k == "PUSH2X":
+        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v13, %[x]", "v_mov_b32_e32 v14, %[x]",
+                "s_add_u32 s55, s55, 2"]
     elif k == "LOADX":
         body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v12, %[x]"]
-    elif k in ("PUSHREF", "LOADREF"):
-        body = ["s_set_gpr_idx_off"] + row_dec(50) + [
-            "global_load_dword v4, %[lane4], s[50:51]", "s_waitcnt vmcnt(0)",
-            "s_set_gpr_idx_on s55, gpr_idx(DST)"]
-        body += ["v_mov_b32_e32 v13, v4", "s_add_u32 s55, s55, 1"] if k == "PUSHREF" else ["v_mov_b32_e32 v12, v4"]
-    elif k == "OUTT":
-        body = ["s_set_gpr_idx_on s55, gpr_idx(SRC0)", "v_mov_b32_e32 v4, v12", "s_set_gpr_idx_off"] + row_dec(52) + [
-            "global_store_dword %[lane4], v4, s[52:53]"]
+    elif k in ("PUSHREF", "LOADREF", "OUTT", "OUTBOT", "SPILL", "FILL", "OUTMEM"):
+        body = call(k.lower())
     elif k == "OUTX":
         body = ["s_set_gpr_idx_off"] + row_dec(52) + ["global_store_dword %[lane4], %[x], s[52:53]"]
     elif k == "FLUSH":
         body = ["s_mov_b32 s59, 0"]
-    elif k == "OUTBOT":
-        body = ["s_set_gpr_idx_on s59, gpr_idx(SRC0)", "v_mov_b32_e32 v4, v12", "s_set_gpr_idx_off",
-                "s_add_u32 s59, s59, 1"] + row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]"]
     elif k == "END":
         return ["s_set_gpr_idx_off", "s_branch .Lexit%="]
-    elif k in ("SPILL", "FILL", "OUTMEM"):
-        body = call(k.lower())
     else:
         raise KeyError(k)
     return body + dispatch(pos)
@@ -154,6 +182,21 @@ def routines() -> list[str]:
         if inc:
             out += ["s_add_u32 s55, s55, 1"]
         out += ["s_setpc_b64 s[48:49]"]
+    # a value from the previous level's slot (rows read downwards)
+    for name, dst, inc in (("pushref", "v13", True), ("loadref", "v12", False)):
+        out += [f".L{name}%=:", "s_set_gpr_idx_off"] + row_dec(50) + [
+            "global_load_dword v4, %[lane4], s[50:51]", "s_waitcnt vmcnt(0)",
+            "s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {dst}, v4"]
+        if inc:
+            out += ["s_add_u32 s55, s55, 1"]
+        out += ["s_setpc_b64 s[48:49]"]
+    # T to the next output slot (rows written downwards)
+    out += [".Loutt%=:", "s_set_gpr_idx_on s55, gpr_idx(SRC0)", "v_mov_b32_e32 v4, v12", "s_set_gpr_idx_off"]
+    out += row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]", "s_setpc_b64 s[48:49]"]
+    # chunk-end flush of the window entry s59
+    out += [".Loutbot%=:", "s_set_gpr_idx_on s59, gpr_idx(SRC0)", "v_mov_b32_e32 v4, v12", "s_set_gpr_idx_off",
+            "s_add_u32 s59, s59, 1"] + row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]",
+                                                     "s_setpc_b64 s[48:49]"]
     # spill: the window's bottom HALF entries to the slab, then shift down
     out += [".Lspill%=:", "s_set_gpr_idx_off"]
     for g in range(HALF // 16):
@@ -173,14 +216,8 @@ def routines() -> list[str]:
     # chunk-end flush of an entry that lives in the slab (entry s59)
     out += [".Loutmem%=:", "s_set_gpr_idx_off", "s_lshl_b32 s46, s59, 8", "s_add_u32 s46, s62, s46",
             "s_addc_u32 s47, s63, 0", "global_load_dword v4, %[slane], s[46:47]", "s_waitcnt vmcnt(0)",
-            "s_add_u32 s59, s59, 1"] + row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]",
-                                                     "s_setpc_b64 s[48:49]"]
-    # next 64-byte code buffer: move the prefetched one in, prefetch the next
-    out += [".Lrefill%=:", "s_waitcnt lgkmcnt(0)"]
-    out += [f"s_mov_b64 s[{64 + 2 * i}:{65 + 2 * i}], s[{80 + 2 * i}:{81 + 2 * i}]" for i in range(8)]
-    out += ["s_add_u32 s40, s40, 64", "s_addc_u32 s41, s41, 0", "s_load_dwordx16 s[80:95], s[40:41], 0x40",
-            "s_and_b32 s58, s64, 0xffff", "s_add_u32 s44, s42, s58", "s_addc_u32 s45, s43, 0",
-            "s_setpc_b64 s[44:45]"]
+            "s_mov_b32 s47, s43", "s_add_u32 s59, s59, 1"] + row_dec(52) + [
+            "global_store_dword %[lane4], v4, s[52:53]", "s_setpc_b64 s[48:49]"]
     return out
 
 
@@ -195,38 +232,43 @@ def generate() -> str:
         "s_mov_b32 s55, 0",
         "s_mov_b64 s[60:61], %[smem]",
         "s_mov_b64 s[62:63], %[smem]",
-        "s_load_dwordx16 s[64:79], s[40:41], 0x0",
+        # the lower half holds the next block's codes when we start in the upper half
+        "s_cmp_lt_u32 s59, 16",
+        "s_cselect_b32 s58, 0, 0x80",
+        "s_load_dwordx16 s[64:79], s[40:41], s58",
         "s_load_dwordx16 s[80:95], s[40:41], 0x40",
         "s_getpc_b64 s[42:43]",
         ".Lpc%=:",
         "s_add_u32 s42, s42, .Ltab%= - .Lpc%=",
         "s_addc_u32 s43, s43, 0",
+        # the whole table and its routines must share the high address word
+        "s_add_u32 s46, s42, .Lend%= - .Ltab%=",
+        "s_cbranch_scc1 .Lcarry%=",
+        "s_mov_b32 s45, s43",
+        "s_mov_b32 s47, s43",
         "s_waitcnt lgkmcnt(0)",
-        # first code: word s[64 + j0/2], half j0 & 1
-        "s_lshr_b32 s58, s59, 1",
-        "s_mov_b32 m0, s58",
+        "s_mov_b32 m0, s59",
         "s_nop 0",
         "s_movrels_b32 s58, s64",
-        "s_bitcmp1_b32 s59, 0",
-        "s_cbranch_scc0 .Leven%=",
-        "s_lshr_b32 s58, s58, 16",
-        ".Leven%=:",
-        "s_and_b32 s58, s58, 0xffff",
-        "s_set_gpr_idx_on s55, gpr_idx(DST)",
         "s_add_u32 s44, s42, s58",
-        "s_addc_u32 s45, s43, 0",
         "s_setpc_b64 s[44:45]",
+        ".Lcarry%=:",
+        "s_waitcnt lgkmcnt(0)",
+        "v_mov_b32_e32 v4, 1",
+        "v_mov_b32_e32 v5, 0",
+        "global_store_dword v5, v4, %[flag]",
+        "s_branch .Lexit%=",
         ".p2align 6",
         ".Ltab%=:",
     ]
-    for pos in range(POS):
-        for kind in KINDS:
-            h = handler(kind, pos)
-            lines.append(".p2align 6")
-            lines.append(f".Lh%=_{pos}_{kind}:")
-            lines += h
+    # handlers in address order (positions 15 and 31 sit after the others)
+    for off, pos, ki in sorted((code_of(pos, ki), pos, ki) for pos in range(POS) for ki in range(NK)):
+        lines.append(f".org .Ltab%= + {off}")
+        lines += handler(KINDS[ki], pos)
+    lines.append(f".org .Ltab%= + {TABLE_BYTES}")
     lines += routines()
-    # no scalar prefetch may still be writing s[80:95] once the block is left
+    lines.append(".Lend%=:")
+    # no scalar load may still be writing s[64:95] once the block is left
     lines += [".Lexit%=:", "s_waitcnt lgkmcnt(0)"]
     return "\n".join(lines) + "\n"
 
@@ -237,7 +279,8 @@ def write(path: str) -> None:
     clob = ", ".join([f'"v{i}"' for i in range(4, 12 + VSTACK)] + [f'"s{i}"' for i in range(40, 64)]
                      + [f'"s{i}"' for i in range(64, 96)] + ['"m0"', '"vcc"', '"scc"'])
     src = ("// Generated by gen_interp.py: threaded-code interpreter for k_run.\n"
-           f"#define EV_CODE_STRIDE {STRIDE}u\n#define EV_CODE_BLOCK {BLOCK}u\n#define EV_CODE_POS {POS}u\n"
+           f"#define EV_CODE_POS {POS}u\n#define EV_CODE_NSTRIDE {NSTRIDE}u\n#define EV_CODE_TSTRIDE {TSTRIDE}u\n"
+           f"#define EV_CODE_TBASE {TBASE}u\n#define EV_NK {NK}u\n"
            f"#define EV_VSTACK {VSTACK}u\n#define EV_VHALF {HALF}u\n#define EV_INTERP_CLOBBERS {clob}\n"
            + "".join(f"#define EV_K_{k} {i}u\n" for i, k in enumerate(KINDS))
            + "#define EV_INTERP_ASM \\\n" + body.replace("\n", " \\\n") + "\n")

@@ -40,22 +40,22 @@ def ev():
     return ev
 
 
-def run(ev, buf, off, x, y, chunk=0, lds=0, per_case=True, flags=0):
+def run(ev, buf, off, x, y, chunk=0, lds=0, per_case=True, flags=0, chunk_hi=0):
     with ev.Context(x, y) as c:
-        if chunk or lds or flags:
-            ev.ev_set_tuning(c.ctx, chunk, lds, flags)
+        if chunk or lds or flags or chunk_hi:
+            ev.ev_set_tuning(c.ctx, chunk, lds, flags, chunk_hi)
         pop = c.load(buf, off)
         info = ev.ev_get_plan_info(c.ctx, pop)
         fit, pc = c.eval(pop, per_case=per_case)
     return fit, pc, info
 
 
-def check(ev, buf, off, x, y, chunk=0, lds=0, threads=8, what="", both=True):
+def check(ev, buf, off, x, y, chunk=0, lds=0, threads=8, what="", both=True, chunk_hi=0):
     """Both interpreters (register-stack and general) against the oracle."""
     want_fit, want_pc = oracle.eval_population(buf, off, x, y, threads=threads, per_case=True)
     info = None
     for flags in ((0, ev.EV_TUNE_NO_REGSTACK) if both else (0,)):
-        fit, pc, inf = run(ev, buf, off, x, y, chunk, lds, flags=flags)
+        fit, pc, inf = run(ev, buf, off, x, y, chunk, lds, flags=flags, chunk_hi=chunk_hi)
         assert_same(pc, want_pc, f"per-case {what} flags={flags}")
         assert_same(fit, want_fit, f"fitness {what} flags={flags}")
         info = info or inf
@@ -79,6 +79,17 @@ def test_split_invariance(ev, chunk, lds):
     info = check(ev, buf, off, x, y, chunk=chunk, lds=lds, what=f"chunk {chunk} lds {lds}")
     if chunk <= 4096:
         assert info["levels"] >= 2
+
+
+@pytest.mark.parametrize("chunk_hi", [64, 256, 4096])
+def test_skeleton_split_invariance(ev, chunk_hi):
+    # the skeleton levels split at their own work-item size
+    x, y = workloads.cases(48)
+    sizes = workloads.loguniform_sizes(78, 60, 1000, 200000)
+    buf, off = workloads.random_population(78, sizes)
+    print(f"skeleton split chunk_hi={chunk_hi} nodes={int(off[-1])}", flush=True)
+    info = check(ev, buf, off, x, y, chunk=1024, chunk_hi=chunk_hi, what=f"chunk_hi {chunk_hi}")
+    assert info["levels"] >= 2
 
 
 def test_deep_stacks_spill_to_memory(ev):
