@@ -55,6 +55,8 @@ struct SegFn {
 
 struct SegStart {
     uint32_t cnt, P;
+    uint32_t ref0;  // REF tokens the chunk's later segments hold (read before this one)
+    uint32_t pad;
 };
 
 struct SegCount {
@@ -82,6 +84,7 @@ struct RunArgs {
     float* slab;            // spill slabs, one per wave of the grid
     uint64_t slab_entries;  // rows of 64 floats per slab
     uint32_t* flag;         // set to 1 if the interpreter's table cannot be used (see gen_interp.py)
+    uint32_t refs;          // 1 at the skeleton levels: REF slots are read ahead
 };
 
 // A work item as the evaluator sees it (32 bytes).

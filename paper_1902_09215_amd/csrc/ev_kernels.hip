@@ -100,6 +100,7 @@ struct Sink {
     uint64_t w;        // one past the next fragment token (written backwards)
     uint32_t n_codes, n_frag, n_out, n_in;
     uint32_t pending;  // an action waiting for a partner to fuse with, or ~0u
+    uint32_t ref;      // index of the next REF within the work item (its ring slot mod EV_RING)
 
     __device__ void put(uint32_t kind)
     {
@@ -209,12 +210,13 @@ __device__ uint32_t run_segment(const uint8_t* __restrict__ seq, uint64_t start,
                 }
                 P = 0;
             }
+            const uint32_t slot = o.ref++ & (EV_RING - 1);
             if (tv) {
                 if (m + 1 - base > EV_VSTACK - 1) { o.code(EV_K_SPILL); base += EV_VHALF; }
-                o.code(EV_K_PUSHREF);
+                o.code(EV_K_PUSHREF0 + slot);
                 m++;
             } else {
-                o.code(EV_K_LOADREF);
+                o.code(EV_K_LOADREF0 + slot);
                 tv = 1;
             }
         } else if (t < TOK_X) {
@@ -314,12 +316,13 @@ __global__ void k_seg_scan(const ChunkSegs* __restrict__ cseg, uint32_t n, const
     if (ci >= n) return;
     const ChunkSegs cs = cseg[ci];
     int32_t c = 0;
-    uint32_t P = 0;
+    uint32_t P = 0, refs = 0;
     for (uint32_t k = cs.n_seg; k-- > 0;) {
         const SegFn f = fn[cs.first + k];
-        st[cs.first + k] = SegStart{(uint32_t)c, P};
+        st[cs.first + k] = SegStart{(uint32_t)c, P, refs, 0};
         c = c + f.a > f.b ? c + f.a : f.b;
         P = f.left_x;
+        refs += f.n_in;
     }
     int32_t S = 0, minp = INT32_MAX;
     uint32_t bad = 0;
@@ -342,7 +345,7 @@ __global__ void k_seg_count(const uint8_t* __restrict__ seq, const SegIn* __rest
     const uint32_t si = blockIdx.x * blockDim.x + threadIdx.x;
     if (si >= n) return;
     const SegIn g = segs[si];
-    Sink o{nullptr, 0, nullptr, 0, 0, 0, 0, 0, ~0u};
+    Sink o{nullptr, 0, nullptr, 0, 0, 0, 0, 0, ~0u, st[si].ref0};
     const uint32_t maxtop = run_segment(seq, g.start, g.len, st[si].cnt, st[si].P, g.last != 0, o);
     out[si] = SegCount{o.n_codes, o.n_frag, o.n_out, o.n_in, maxtop, 0};
 }
@@ -402,7 +405,8 @@ __global__ void k_seg_emit(const uint8_t* __restrict__ seq, const SegIn* __restr
     const SegIn g = segs[si];
     const bool has_codes = codes && seg_code[si] != ~0ull;
     if (!dst && !has_codes) return;
-    Sink o{has_codes ? codes : nullptr, has_codes ? seg_code[si] : 0, dst, dst ? seg_frag[si] : 0, 0, 0, 0, 0, ~0u};
+    Sink o{has_codes ? codes : nullptr, has_codes ? seg_code[si] : 0, dst, dst ? seg_frag[si] : 0, 0, 0, 0, 0, ~0u,
+           st[si].ref0};
     run_segment(seq, g.start, g.len, st[si].cnt, st[si].P, g.last != 0, o);
 }
 
@@ -423,7 +427,7 @@ __global__ void k_seg_check(const uint32_t* __restrict__ codes, const SegIn* __r
     const SegIn g = segs[si];
     const SegCount sc = cnt[si];
     const uint32_t len = sc.n_codes;
-    const uint32_t P = st[si].P, tv = st[si].cnt > P ? 1u : 0u, m0 = st[si].cnt - tv - P;
+    const uint32_t P = st[si].P, tv = st[si].cnt > P ? 1u : 0u, m0 = st[si].cnt - tv - P, ref0 = st[si].ref0;
     int32_t slab = (int32_t)norm_base(m0), idx = (int32_t)(m0 - (uint32_t)slab), fl = 0;
     uint32_t outs = 0, ins = 0, bad = 0, ended = 0, m = m0;
     // bad: 1 a code names another position or no handler, 2 the window or
@@ -450,13 +454,20 @@ __global__ void k_seg_check(const uint32_t* __restrict__ codes, const SegIn* __r
             w |= idx < 1;
             idx--;
             m--;
-        } else if (k >= EV_K_OPS00 && k < EV_NK) {
+        } else if (k >= EV_K_OPS00 && k <= EV_K_OPS22) {
             w |= idx < 2;
             idx -= 2;
             m -= 2;
-        } else if ((k >= EV_K_CH0 && k <= EV_K_CH3) || k == EV_K_PUSHX || k == EV_K_PUSHREF) {
+        } else if ((k >= EV_K_CH0 && k <= EV_K_CH3) || k == EV_K_PUSHX) {
             idx++;
             m++;
+        } else if (k >= EV_K_PUSHREF0 && k < EV_K_PUSHREF0 + EV_RING) {
+            // the REF's ring slot follows from its index within the work item
+            bad |= (k - EV_K_PUSHREF0 != ((ref0 + ins) & (EV_RING - 1))) ? 1u : 0u;
+            idx++;
+            m++;
+        } else if (k >= EV_K_LOADREF0 && k < EV_K_LOADREF0 + EV_RING) {
+            bad |= (k - EV_K_LOADREF0 != ((ref0 + ins) & (EV_RING - 1))) ? 1u : 0u;
         } else if (k == EV_K_PUSH2X) {
             idx += 2;
             m += 2;
@@ -480,7 +491,7 @@ __global__ void k_seg_check(const uint32_t* __restrict__ codes, const SegIn* __r
         w |= idx < 0 || idx > (int32_t)EV_VSTACK - 1 || slab < 0 || slab > (int32_t)slab_entries;
         if (w) bad |= 2;
         outs += (k == EV_K_OUTT || k == EV_K_OUTX || k == EV_K_OUTBOT || k == EV_K_OUTMEM);
-        ins += (k == EV_K_PUSHREF || k == EV_K_LOADREF);
+        ins += (k >= EV_K_PUSHREF0 && k < EV_K_PUSHREF0 + EV_RING) || (k >= EV_K_LOADREF0 && k < EV_K_LOADREF0 + EV_RING);
     }
     if ((ended != 0) != (g.last != 0)) bad |= 4;
     // a segment hands the next one the window in its boundary position
@@ -827,7 +838,7 @@ __global__ __launch_bounds__(64) void k_run(RunArgs a)
                          :
                          : [x] "v"(xv), [lane4] "v"(lane4), [slane] "v"(slane), [cptr] "s"(cptr), [j0] "s"(j0),
                            [inp] "s"(inp), [outp] "s"(outp), [rowb] "s"(a.rowb), [smem] "s"(smem),
-                           [flag] "s"(a.flag)
+                           [flag] "s"(a.flag), [refs] "s"(a.refs)
                          : EV_INTERP_CLOBBERS);
         }
         item = next;

@@ -143,7 +143,7 @@ void plan_free(ev_ctx* c, Plan& pl)
 
 void rescache_free(ev_ctx* c, ResCache& r)
 {
-    for (float* p : r.res) dev_free(c, p);
+    for (float* p : r.res) dev_free(c, p - (size_t)EV_RING * r.N);
     r.res.clear();
     dev_free(c, r.d_rows);
     r.d_rows = nullptr;
@@ -638,14 +638,18 @@ ev_status rescache_get(ev_ctx* c, Exec& x, Pop* P, int32_t table, ResCache** out
     if (it != P->res.end()) { *out = &it->second; return EV_OK; }
     ResCache r;
     const int32_t N = c->tables[table].N;
+    r.N = N;
     ev_status st;
     for (auto& L : P->plan.levels) {
         float* p = nullptr;
-        if ((st = dev_alloc(c, (size_t)std::max<uint32_t>(L.n_out, 1) * N * sizeof(float), (void**)&p)) != EV_OK) {
+        // EV_RING rows in front: the next level reads up to that many rows
+        // ahead of (below) its lowest slot
+        const size_t rows = (size_t)std::max<uint32_t>(L.n_out, 1) + EV_RING;
+        if ((st = dev_alloc(c, rows * N * sizeof(float), (void**)&p)) != EV_OK) {
             rescache_free(c, r);
             return st;
         }
-        r.res.push_back(p);
+        r.res.push_back(p + (size_t)EV_RING * N);
     }
     std::vector<uint64_t> rows(P->M);
     for (int32_t t = 0; t < P->M; t++)
@@ -709,6 +713,7 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
             r.N = N;
             r.rowb = (uint32_t)N * 4u;
             r.in_res = li ? rc->res[li - 1] : nullptr;
+            r.refs = li ? 1u : 0u;
             r.out_res = rc->res[li];
             r.slab = x.d_gstack;
             r.slab_entries = L.slab_entries;
@@ -921,6 +926,7 @@ static ev_status run_probe(ev_ctx* c)
     r.slab = nullptr;
     r.slab_entries = 0;
     r.flag = c->d_flag;
+    r.refs = 0;
     uint32_t flag = 0;
     if (st == EV_OK) {
         hipError_t e = launch_run(r, 1, x.stream);

@@ -51,7 +51,8 @@ struct Plan {
 
 // Intermediate results of one population for one case table.
 struct ResCache {
-    std::vector<float*> res;     // per level: n_out * N floats
+    int32_t N = 0;
+    std::vector<float*> res;     // per level: n_out * N floats (EV_RING padding rows before)
     uint64_t* d_rows = nullptr;  // per tree: address of its N final values
     float* d_per_case = nullptr;
 };

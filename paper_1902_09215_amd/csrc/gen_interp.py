@@ -26,11 +26,12 @@ Register use inside the block:
   v[12 + m]       top of the operand stack (T); v[12..12+m-1] the entries
                   below it, oldest first.  m = s55.  Relative access uses
                   GPR-index mode (s_set_gpr_idx_on), set once per handler.
+  v[12+VSTACK ..] the ring of slot values read ahead at the skeleton levels
   v4..v10         temporaries (division), v4 also a staging register
   %[x], %[lane4]  the lane's input value and byte offset (not clobbered)
   s[40:41] code block pointer (128-byte aligned), s[42:43] handler table,
   s[44:45] jump target, s[46:47] call target, s[48:49] return address,
-  s[50:51] input-slot row pointer, s[52:53] output-slot row pointer,
+  s[50:51] read-ahead pointer into the input slot rows, s[52:53] output-slot row pointer,
   s54 row bytes (cases * 4), s55 window index of T, s[56:57] division
   scratch, s58 scratch, s59 flush index, s[60:61] next free entry of the
   wave's spill slab in global memory, s[62:63] the slab's base.
@@ -47,15 +48,18 @@ from __future__ import annotations
 import os
 import sys
 
-VSTACK = int(os.environ.get("EV_VSTACK", "64"))  # register-stack entries: v12 .. v12+VSTACK-1
+VSTACK = int(os.environ.get("EV_VSTACK", "56"))  # register-stack entries: v12 .. v12+VSTACK-1
 HALF = VSTACK // 2  # entries moved by one spill or fill
+RING = 8  # slot values read ahead: v[12+VSTACK] .. v[12+VSTACK+RING-1]
+RING0 = 12 + VSTACK
 POS = 32  # positions per 128-byte code block
 NSTRIDE = 32  # bytes per handler at ordinary positions
 TSTRIDE = 64  # bytes per handler at positions 15 and 31 (they also refill)
 KINDS = ["OPS0", "OPS1", "OPS2", "OPS3", "OPX0", "OPX1", "OPX2", "OPX3",
          "CH0", "CH1", "CH2", "CH3", "LCH0", "LCH1", "LCH2", "LCH3",
-         "PUSHX", "LOADX", "PUSHREF", "LOADREF", "OUTT", "OUTX", "FLUSH", "OUTBOT", "END",
-         "SPILL", "FILL", "OUTMEM", "PUSH2X"] + [f"OPS{a}{b}" for a in range(3) for b in range(3)]
+         "PUSHX", "LOADX", "OUTT", "OUTX", "FLUSH", "OUTBOT", "END",
+         "SPILL", "FILL", "OUTMEM", "PUSH2X"] + [f"OPS{a}{b}" for a in range(3) for b in range(3)] \
+    + [f"PUSHREF{r}" for r in range(RING)] + [f"LOADREF{r}" for r in range(RING)]
 NK = len(KINDS)
 TBASE = (POS - 2) * NK * NSTRIDE  # first byte of the position-15 and -31 handlers
 TABLE_BYTES = TBASE + 2 * NK * TSTRIDE
@@ -151,7 +155,7 @@ def handler(kind: str, pos: int) -> list[str]:
                 "s_add_u32 s55, s55, 2"]
     elif k == "LOADX":
         body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v12, %[x]"]
-    elif k in ("PUSHREF", "LOADREF", "OUTT", "OUTBOT", "SPILL", "FILL", "OUTMEM"):
+    elif k in ("OUTT", "OUTBOT", "SPILL", "FILL", "OUTMEM") or k.startswith("PUSHREF") or k.startswith("LOADREF"):
         body = call(k.lower())
     elif k == "OUTX":
         body = ["s_set_gpr_idx_off"] + row_dec(52) + ["global_store_dword %[lane4], %[x], s[52:53]"]
@@ -182,14 +186,18 @@ def routines() -> list[str]:
         if inc:
             out += ["s_add_u32 s55, s55, 1"]
         out += ["s_setpc_b64 s[48:49]"]
-    # a value from the previous level's slot (rows read downwards)
-    for name, dst, inc in (("pushref", "v13", True), ("loadref", "v12", False)):
-        out += [f".L{name}%=:", "s_set_gpr_idx_off"] + row_dec(50) + [
-            "global_load_dword v4, %[lane4], s[50:51]", "s_waitcnt vmcnt(0)",
-            "s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {dst}, v4"]
-        if inc:
-            out += ["s_add_u32 s55, s55, 1"]
-        out += ["s_setpc_b64 s[48:49]"]
+    # a value from the previous level's slots (rows read downwards): REF j of
+    # a work item takes ring register j % RING, loaded RING REFs earlier, and
+    # starts the load of the row REF j + RING will take.  Vector memory
+    # operations complete in issue order, so at most RING-1 later loads can
+    # still be outstanding when REF j's row has arrived.
+    for r in range(RING):
+        for name, dst, inc in ((f"pushref{r}", "v13", True), (f"loadref{r}", "v12", False)):
+            out += [f".L{name}%=:", f"s_waitcnt vmcnt({RING - 1})", "s_set_gpr_idx_on s55, gpr_idx(DST)",
+                    f"v_mov_b32_e32 {dst}, v{RING0 + r}", "s_set_gpr_idx_off"]
+            if inc:
+                out += ["s_add_u32 s55, s55, 1"]
+            out += row_dec(50) + [f"global_load_dword v{RING0 + r}, %[lane4], s[50:51]", "s_setpc_b64 s[48:49]"]
     # T to the next output slot (rows written downwards)
     out += [".Loutt%=:", "s_set_gpr_idx_on s55, gpr_idx(SRC0)", "v_mov_b32_e32 v4, v12", "s_set_gpr_idx_off"]
     out += row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]", "s_setpc_b64 s[48:49]"]
@@ -198,20 +206,21 @@ def routines() -> list[str]:
             "s_add_u32 s59, s59, 1"] + row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]",
                                                      "s_setpc_b64 s[48:49]"]
     # spill: the window's bottom HALF entries to the slab, then shift down
+    groups = [(g0, min(16, HALF - g0)) for g0 in range(0, HALF, 16)]
     out += [".Lspill%=:", "s_set_gpr_idx_off"]
-    for g in range(HALF // 16):
-        out += [f"global_store_dword %[slane], v{12 + 16 * g + i}, s[60:61]" + (f" offset:{256 * i}" if i else "")
-                for i in range(16)]
-        out += ["s_add_u32 s60, s60, 4096", "s_addc_u32 s61, s61, 0"]
+    for g0, n in groups:
+        out += [f"global_store_dword %[slane], v{12 + g0 + i}, s[60:61]" + (f" offset:{256 * i}" if i else "")
+                for i in range(n)]
+        out += [f"s_add_u32 s60, s60, {256 * n}", "s_addc_u32 s61, s61, 0"]
     out += [f"v_mov_b32_e32 v{12 + i}, v{12 + HALF + i}" for i in range(VSTACK - HALF)]
     out += [f"s_sub_u32 s55, s55, {HALF}", "s_setpc_b64 s[48:49]"]
     # fill: shift up, then the top HALF entries of the slab into the bottom
     out += [".Lfill%=:", "s_set_gpr_idx_off"]
     out += [f"v_mov_b32_e32 v{12 + HALF + i}, v{12 + i}" for i in range(VSTACK - HALF)]
-    for g in reversed(range(HALF // 16)):
-        out += ["s_sub_u32 s60, s60, 4096", "s_subb_u32 s61, s61, 0"]
-        out += [f"global_load_dword v{12 + 16 * g + i}, %[slane], s[60:61]" + (f" offset:{256 * i}" if i else "")
-                for i in range(16)]
+    for g0, n in reversed(groups):
+        out += [f"s_sub_u32 s60, s60, {256 * n}", "s_subb_u32 s61, s61, 0"]
+        out += [f"global_load_dword v{12 + g0 + i}, %[slane], s[60:61]" + (f" offset:{256 * i}" if i else "")
+                for i in range(n)]
     out += ["s_waitcnt vmcnt(0)", f"s_add_u32 s55, s55, {HALF}", "s_setpc_b64 s[48:49]"]
     # chunk-end flush of an entry that lives in the slab (entry s59)
     out += [".Loutmem%=:", "s_set_gpr_idx_off", "s_lshl_b32 s46, s59, 8", "s_add_u32 s46, s62, s46",
@@ -232,6 +241,11 @@ def generate() -> str:
         "s_mov_b32 s55, 0",
         "s_mov_b64 s[60:61], %[smem]",
         "s_mov_b64 s[62:63], %[smem]",
+        # skeleton levels: start reading the first RING slot rows
+        "s_cmp_eq_u32 %[refs], 0",
+        "s_cbranch_scc1 .Lnoref%=",
+    ] + sum((row_dec(50) + [f"global_load_dword v{RING0 + r}, %[lane4], s[50:51]"] for r in range(RING)), []) + [
+        ".Lnoref%=:",
         # the lower half holds the next block's codes when we start in the upper half
         "s_cmp_lt_u32 s59, 16",
         "s_cselect_b32 s58, 0, 0x80",
@@ -269,19 +283,21 @@ def generate() -> str:
     lines += routines()
     lines.append(".Lend%=:")
     # no scalar load may still be writing s[64:95] once the block is left
-    lines += [".Lexit%=:", "s_waitcnt lgkmcnt(0)"]
+    # nor a vector load still be writing the ring registers
+    lines += [".Lexit%=:", "s_waitcnt vmcnt(0) lgkmcnt(0)"]
     return "\n".join(lines) + "\n"
 
 
 def write(path: str) -> None:
     text = generate()
     body = "\n".join('    "' + ln.replace('"', '\\"') + '\\n"' for ln in text.splitlines())
-    clob = ", ".join([f'"v{i}"' for i in range(4, 12 + VSTACK)] + [f'"s{i}"' for i in range(40, 64)]
+    clob = ", ".join([f'"v{i}"' for i in range(4, RING0 + RING)] + [f'"s{i}"' for i in range(40, 64)]
                      + [f'"s{i}"' for i in range(64, 96)] + ['"m0"', '"vcc"', '"scc"'])
     src = ("// Generated by gen_interp.py: threaded-code interpreter for k_run.\n"
            f"#define EV_CODE_POS {POS}u\n#define EV_CODE_NSTRIDE {NSTRIDE}u\n#define EV_CODE_TSTRIDE {TSTRIDE}u\n"
            f"#define EV_CODE_TBASE {TBASE}u\n#define EV_NK {NK}u\n"
-           f"#define EV_VSTACK {VSTACK}u\n#define EV_VHALF {HALF}u\n#define EV_INTERP_CLOBBERS {clob}\n"
+           f"#define EV_VSTACK {VSTACK}u\n#define EV_VHALF {HALF}u\n#define EV_RING {RING}u\n"
+           f"#define EV_INTERP_CLOBBERS {clob}\n"
            + "".join(f"#define EV_K_{k} {i}u\n" for i, k in enumerate(KINDS))
            + "#define EV_INTERP_ASM \\\n" + body.replace("\n", " \\\n") + "\n")
     tmp = path + ".tmp"
