@@ -194,17 +194,17 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
 
 
-KERNEL_SOURCES = ("paper_1902_09215_amd/csrc/ev_kernels.hip", "paper_1902_09215_amd/csrc/ev_internal.h",
-                  "paper_1902_09215_amd/csrc/gen_interp.py")
-
-
 def kernel_hash():
+    """Hash of what the level-0 k_run launch runs: the interpreter generator
+    and the kernel's own source text."""
     import hashlib
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1902_09215_amd/csrc/gen_interp.py"), "rb") as fh:
+        h.update(fh.read())
+    src = open(os.path.join(ROOT, "paper_1902_09215_amd/csrc/ev_kernels.hip")).read()
+    i = src.index("void k_run(RunArgs a)")
+    h.update(src[i:src.index("\n}\n", i)].encode())
     return h.hexdigest()[:16]
 
 
