@@ -89,8 +89,10 @@ __device__ __forceinline__ uint32_t norm_base(uint32_t m)
 __device__ __forceinline__ uint32_t code_value(uint64_t at, uint32_t kind)
 {
     const uint32_t pos = (uint32_t)(at & (EV_CODE_POS - 1));
-    if ((pos & 15u) == 15u) return EV_CODE_TBASE + (pos >> 4) * EV_NK * EV_CODE_TSTRIDE + kind * EV_CODE_TSTRIDE;
-    return (pos - (pos >> 4)) * EV_NK * EV_CODE_NSTRIDE + kind * EV_CODE_NSTRIDE;
+    const bool tr = (pos & 15u) == 15u;
+    const uint32_t base = tr ? EV_CODE_TBASE + (pos >> 4) * EV_NK * EV_CODE_TSTRIDE
+                             : (pos - (pos >> 4)) * EV_NK * EV_CODE_NSTRIDE;
+    return base + kind * (tr ? EV_CODE_TSTRIDE : EV_CODE_NSTRIDE);
 }
 
 struct Sink {
@@ -149,6 +151,33 @@ struct Sink {
         if (frag) frag[--w] = (uint8_t)t;
         n_frag++;
     }
+    // put(e) unless e is ~0u, without branching on e
+    __device__ __forceinline__ void put_if(uint32_t e)
+    {
+        const uint32_t has = e != ~0u ? 1u : 0u;
+        if (codes && has) codes[at] = code_value(at, e);
+        at += has;
+        n_codes += has;
+    }
+    // code() for kind in {none (~0u), OPX*, OPS*, PUSHX, LOADX}, with selects:
+    // the same fusions and the same order of codes as code()
+    __device__ __forceinline__ void code_fast(uint32_t kind)
+    {
+        const uint32_t p = pending;
+        const bool none = kind == ~0u;
+        const bool ch = (p == EV_K_PUSHX || p == EV_K_LOADX) && kind - EV_K_OPX0 < 4u;
+        const bool xx = p == EV_K_PUSHX && kind == EV_K_PUSHX;
+        const bool ops = p <= EV_K_OPS2 && kind <= EV_K_OPS2;
+        const bool fused = ch || xx || ops;
+        const uint32_t fk = ch ? (p == EV_K_PUSHX ? EV_K_CH0 : EV_K_LCH0) + (kind - EV_K_OPX0)
+                               : (xx ? EV_K_PUSH2X : EV_K_OPS00 + p * 3u + kind);
+        const bool defer = kind == EV_K_PUSHX || kind == EV_K_LOADX || kind <= EV_K_OPS2;
+        const uint32_t e1 = none ? ~0u : (fused ? fk : p);
+        const uint32_t e2 = (none || fused || defer) ? ~0u : kind;
+        pending = none ? p : ((fused || !defer) ? ~0u : kind);
+        put_if(e1);
+        put_if(e2);
+    }
 };
 
 // Reads tokens right to left, 16 bytes per load.
@@ -186,6 +215,22 @@ __device__ uint32_t run_segment(const uint8_t* __restrict__ seq, uint64_t start,
     RevTokens rt(seq, start, len);
     uint32_t t;
     while (rt.next(t)) {
+        // Common tokens, decided with selects so that lanes on different
+        // token kinds do not diverge: a function finding two values without
+        // a FILL, and an x needing no SPILL.  The rest take the full path.
+        const uint32_t cnt = m + tv + P;
+        const bool fast_fn = t < TOK_X && cnt >= 2 && (P || m != base || base == 0);
+        const bool fast_x = t == TOK_X && !(P && tv && m + 1 - base > EV_VSTACK - 1);
+        if (fast_fn || fast_x) {
+            const uint32_t kx = !P ? ~0u : (tv ? EV_K_PUSHX : EV_K_LOADX);
+            const uint32_t kind = fast_fn ? (P ? EV_K_OPX0 + t : EV_K_OPS0 + t) : kx;
+            m = fast_fn ? m - (P ? 0u : 1u) : m + ((P && tv) ? 1u : 0u);
+            tv = fast_fn ? tv : (tv | P);
+            P = fast_fn ? 0u : 1u;
+            o.code_fast(kind);
+            maxtop = m > maxtop ? m : maxtop;
+            continue;
+        }
         if (t == TOK_X) {
             if (!P) {
                 P = 1;
@@ -435,63 +480,54 @@ __global__ void k_seg_check(const uint32_t* __restrict__ codes, const SegIn* __r
     // slots written/read differ from the plan
     for (uint32_t i = 0; i < len; i++) {
         const uint32_t v = codes[b + i];
+        // decode (selects): handler base and stride of this position
         const uint32_t pos = (uint32_t)((b + i) & (EV_CODE_POS - 1));
-        uint32_t k;
-        if ((pos & 15u) == 15u) {
-            const uint32_t base = EV_CODE_TBASE + (pos >> 4) * EV_NK * EV_CODE_TSTRIDE;
-            k = (v - base) / EV_CODE_TSTRIDE;
-            if (v < base || (v - base) % EV_CODE_TSTRIDE) bad |= 1;
-        } else {
-            const uint32_t base = (pos - (pos >> 4)) * EV_NK * EV_CODE_NSTRIDE;
-            k = (v - base) / EV_CODE_NSTRIDE;
-            if (v < base || (v - base) % EV_CODE_NSTRIDE) bad |= 1;
-        }
-        if (k >= EV_NK) bad |= 1;
+        const bool tr = (pos & 15u) == 15u;
+        const uint32_t base = tr ? EV_CODE_TBASE + (pos >> 4) * EV_NK * EV_CODE_TSTRIDE
+                                 : (pos - (pos >> 4)) * EV_NK * EV_CODE_NSTRIDE;
+        const uint32_t stride = tr ? EV_CODE_TSTRIDE : EV_CODE_NSTRIDE;
+        const uint32_t rel = v - base;
+        const uint32_t k = rel / stride;
+        if (v < base || rel % stride || k >= EV_NK) bad |= 1;
         if (ended) bad |= 4;
-        if (k == EV_K_END) ended = 1;
-        uint32_t w = 0;
-        if (k <= EV_K_OPS3) {
-            w |= idx < 1;
-            idx--;
-            m--;
-        } else if (k >= EV_K_OPS00 && k <= EV_K_OPS22) {
-            w |= idx < 2;
-            idx -= 2;
-            m -= 2;
-        } else if ((k >= EV_K_CH0 && k <= EV_K_CH3) || k == EV_K_PUSHX) {
-            idx++;
-            m++;
-        } else if (k >= EV_K_PUSHREF0 && k < EV_K_PUSHREF0 + EV_RING) {
-            // the REF's ring slot follows from its index within the work item
-            bad |= (k - EV_K_PUSHREF0 != ((ref0 + ins) & (EV_RING - 1))) ? 1u : 0u;
-            idx++;
-            m++;
-        } else if (k >= EV_K_LOADREF0 && k < EV_K_LOADREF0 + EV_RING) {
-            bad |= (k - EV_K_LOADREF0 != ((ref0 + ins) & (EV_RING - 1))) ? 1u : 0u;
-        } else if (k == EV_K_PUSH2X) {
-            idx += 2;
-            m += 2;
-        } else if (k == EV_K_FLUSH) {
-            fl = 0;
-        } else if (k == EV_K_OUTBOT) {
-            w |= fl >= idx;
-            fl++;
-        } else if (k == EV_K_OUTMEM) {
-            w |= fl >= slab;
-            fl++;
-        } else if (k == EV_K_SPILL) {
-            w |= idx < (int32_t)EV_VHALF;
-            idx -= EV_VHALF;
-            slab += EV_VHALF;
-        } else if (k == EV_K_FILL) {
-            w |= slab < (int32_t)EV_VHALF || idx > (int32_t)EV_VHALF - 1;
-            idx += EV_VHALF;
-            slab -= EV_VHALF;
+        // stack actions of the common kinds, with selects
+        const bool ops1 = k <= EV_K_OPS3;
+        const bool ops2 = k >= EV_K_OPS00 && k <= EV_K_OPS22;
+        const bool pref = k >= EV_K_PUSHREF0 && k < EV_K_PUSHREF0 + EV_RING;
+        const bool lref = k >= EV_K_LOADREF0 && k < EV_K_LOADREF0 + EV_RING;
+        const bool push1 = (k >= EV_K_CH0 && k <= EV_K_CH3) || k == EV_K_PUSHX || pref;
+        const int32_t need = ops1 ? 1 : (ops2 ? 2 : 0);
+        const int32_t d = ops1 ? -1 : ops2 ? -2 : push1 ? 1 : (k == EV_K_PUSH2X ? 2 : 0);
+        uint32_t w = idx < need ? 1u : 0u;
+        // a REF's ring slot follows from its index within the work item
+        const uint32_t slot = (ref0 + ins) & (EV_RING - 1);
+        if ((pref && k - EV_K_PUSHREF0 != slot) || (lref && k - EV_K_LOADREF0 != slot)) bad |= 1;
+        idx += d;
+        m += (uint32_t)d;
+        ins += (pref || lref) ? 1u : 0u;
+        if (k >= EV_K_OUTT && k <= EV_K_OUTMEM) {  // the rare kinds
+            if (k == EV_K_END) ended = 1;
+            if (k == EV_K_FLUSH) {
+                fl = 0;
+            } else if (k == EV_K_OUTBOT) {
+                w |= fl >= idx;
+                fl++;
+            } else if (k == EV_K_OUTMEM) {
+                w |= fl >= slab;
+                fl++;
+            } else if (k == EV_K_SPILL) {
+                w |= idx < (int32_t)EV_VHALF;
+                idx -= EV_VHALF;
+                slab += EV_VHALF;
+            } else if (k == EV_K_FILL) {
+                w |= slab < (int32_t)EV_VHALF || idx > (int32_t)EV_VHALF - 1;
+                idx += EV_VHALF;
+                slab -= EV_VHALF;
+            }
+            outs += (k == EV_K_OUTT || k == EV_K_OUTX || k == EV_K_OUTBOT || k == EV_K_OUTMEM);
         }
         w |= idx < 0 || idx > (int32_t)EV_VSTACK - 1 || slab < 0 || slab > (int32_t)slab_entries;
         if (w) bad |= 2;
-        outs += (k == EV_K_OUTT || k == EV_K_OUTX || k == EV_K_OUTBOT || k == EV_K_OUTMEM);
-        ins += (k >= EV_K_PUSHREF0 && k < EV_K_PUSHREF0 + EV_RING) || (k >= EV_K_LOADREF0 && k < EV_K_LOADREF0 + EV_RING);
     }
     if ((ended != 0) != (g.last != 0)) bad |= 4;
     // a segment hands the next one the window in its boundary position
