@@ -221,6 +221,12 @@ ev_status ev_set_tuning(ev_ctx *ctx, uint32_t chunk, uint32_t chunk_hi, uint32_t
 ev_status ev_autotune(ev_ctx *ctx, ev_pop pop, int32_t table, int32_t reps, uint32_t *best_chunk,
                       float *best_ms);
 
+/* Device time in milliseconds of each plan level of the last
+ * ev_eval_fitness on this context (levels in evaluation order; the first
+ * also holds the counter reset before it).  ms[0..min(cap, levels)) is
+ * filled; *n_levels (nullable) receives the number of levels. */
+ev_status ev_last_level_times(ev_ctx *ctx, float *ms, int32_t cap, int32_t *n_levels);
+
 /* Device time in milliseconds of the last ev_eval_fitness on this context
  * (HIP events around the evaluation kernels) and of its dominant kernel
  * (the level-0 interpreter launch). */

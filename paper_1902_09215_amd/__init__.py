@@ -28,7 +28,7 @@ EXPORTS = [
     "ev_create", "ev_add_cases", "ev_destroy", "ev_last_error", "ev_load_trees", "ev_pop_info",
     "ev_get_trees", "ev_free_pop", "ev_eval_fitness", "ev_crossover", "ev_generation", "ev_submit",
     "ev_poll", "ev_wait", "ev_result", "ev_job_timing", "ev_get_plan_info", "ev_set_tuning",
-    "ev_autotune", "ev_last_timing",
+    "ev_autotune", "ev_last_level_times", "ev_last_timing",
 ]
 
 
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
         "ev_get_plan_info": [P, i32, ctypes.POINTER(ev_plan_info)],
         "ev_set_tuning": [P, u32, u32, u32, u32],
         "ev_autotune": [P, i32, i32, i32, ctypes.POINTER(u32), ctypes.POINTER(ctypes.c_float)],
+        "ev_last_level_times": [P, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)],
         "ev_last_timing": [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
     }
     for name, args in sig.items():
@@ -289,6 +290,14 @@ def ev_autotune(ctx, pop, table: int = 0, reps: int = 5):
     ms = ctypes.c_float()
     _check(_lib.ev_autotune(ctx, pop, table, reps, ctypes.byref(best), ctypes.byref(ms)))
     return best.value, ms.value
+
+
+def ev_last_level_times(ctx):
+    """Device ms per plan level of the last ev_eval_fitness (a list)."""
+    ms = (ctypes.c_float * 64)()
+    n = ctypes.c_int32()
+    _check(_lib.ev_last_level_times(ctx, ms, 64, ctypes.byref(n)))
+    return [ms[i] for i in range(min(n.value, 64))]
 
 
 def ev_last_timing(ctx):

@@ -31,6 +31,10 @@ struct ChunkStat {
     uint32_t code_in;   // slot-reading codes (must equal n_in)
 };
 
+// Bytes of 0xFF after a population's trees: room for the wide reads of
+// the subtree scan and the token readers.
+constexpr uint64_t EV_POP_PAD = 2048;
+
 // Structure segments (SEG_TOKENS tokens of one chunk).
 constexpr uint32_t SEG_TOKENS = 256;
 struct SegIn {

@@ -714,17 +714,24 @@ __global__ __launch_bounds__(64) void k_subtree_end(const uint8_t* __restrict__ 
                                                     const uint64_t* __restrict__ pos, uint32_t n,
                                                     uint64_t* __restrict__ end_out)
 {
+    // One wave per query; it reads 1 KiB per step, 16 aligned bytes per
+    // lane (the population buffer carries EV_POP_PAD bytes of padding, so
+    // the last step stays inside it).
     const uint32_t qi = blockIdx.x;
     if (qi >= n) return;
     const uint32_t lane = threadIdx.x;
-    const uint8_t* t = buf + base[qi];
-    uint64_t k = pos[qi];
+    const uint64_t a = base[qi] + pos[qi];
+    uint64_t w = a & ~(uint64_t)15;
     int32_t open = 1;  // slots still to fill before the subtree is complete
     for (;;) {
-        const uint8_t* tb = t + k + lane * 4u;
-        const uint32_t wv = (uint32_t)tb[0] | ((uint32_t)tb[1] << 8) | ((uint32_t)tb[2] << 16) | ((uint32_t)tb[3] << 24);
+        const uint64_t addr = w + (uint64_t)lane * 16u;
+        const u32x4 v = *reinterpret_cast<const u32x4*>(buf + addr);
         int32_t c = 0;
-        for (int j = 0; j < 4; j++) c += (((wv >> (8 * j)) & 255u) < TOK_X) ? 1 : -1;
+        for (int j = 0; j < 16; j++) {
+            const uint32_t word = j >= 8 ? (j >= 12 ? v.w : v.z) : (j >= 4 ? v.y : v.x);
+            const uint32_t tok = (word >> (8 * (j & 3))) & 255u;
+            c += addr + j >= a ? (tok < TOK_X ? 1 : -1) : 0;
+        }
         int32_t pre = c;
         for (int d = 1; d < 64; d <<= 1) {
             const int32_t o = __shfl_up(pre, d, 64);
@@ -732,24 +739,38 @@ __global__ __launch_bounds__(64) void k_subtree_end(const uint8_t* __restrict__ 
         }
         const int32_t before = pre - c;
         int32_t hit = -1, cc = 0;
-        for (int j = 0; j < 4; j++) {
-            cc += (((wv >> (8 * j)) & 255u) < TOK_X) ? 1 : -1;
-            if (hit < 0 && open + before + cc == 0) hit = j;
+        for (int j = 0; j < 16; j++) {
+            const uint32_t word = j >= 8 ? (j >= 12 ? v.w : v.z) : (j >= 4 ? v.y : v.x);
+            const uint32_t tok = (word >> (8 * (j & 3))) & 255u;
+            if (addr + j >= a) {
+                cc += tok < TOK_X ? 1 : -1;
+                if (hit < 0 && open + before + cc == 0) hit = j;
+            }
         }
         const uint64_t mask = __ballot(hit >= 0);
         if (mask) {
             const int first = __ffsll((unsigned long long)mask) - 1;
             const int j = __shfl(hit, first, 64);
-            if (lane == 0) end_out[qi] = k + (uint64_t)first * 4u + (uint64_t)j;
+            if (lane == 0) end_out[qi] = w + (uint64_t)first * 16u + (uint64_t)j - base[qi];
             return;
         }
         open += __shfl(pre, 63, 64);
-        k += 256;
+        w += 1024;
     }
 }
 
 // Copy children: mum[0,p) + dad[q, eq] + mum(ep, nm).  Grid: x = 4 KiB pieces
-// of the child, y = child.
+// of the child, y = child.  Whole aligned words inside a child are written
+// with one store each; the child's first and last partial words byte by
+// byte (a neighbouring child may share them).
+__device__ __forceinline__ uint8_t child_byte(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
+                                              const XoPlan& x, uint64_t i, uint64_t a, uint64_t b)
+{
+    if (x.copy_mum || i < a) return mums[x.mum_off + i];
+    if (i < b) return dads[x.dad_off + x.q + (i - a)];
+    return mums[x.mum_off + x.ep + 1 + (i - b)];
+}
+
 __global__ void k_xo_copy(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
                           const XoPlan* __restrict__ plan, uint32_t n_children, uint8_t* __restrict__ dst)
 {
@@ -760,15 +781,25 @@ __global__ void k_xo_copy(const uint8_t* __restrict__ mums, const uint8_t* __res
     if (lo >= x.child_len) return;
     const uint64_t hi = lo + 4096u < x.child_len ? lo + 4096u : x.child_len;
     const uint64_t a = x.p, b = x.p + (x.eq - x.q + 1);
-    uint8_t* out = dst + x.child_off;
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        uint8_t v;
-        if (x.copy_mum) v = mums[x.mum_off + i];
-        else if (i < a) v = mums[x.mum_off + i];
-        else if (i < b) v = dads[x.dad_off + x.q + (i - a)];
-        else v = mums[x.mum_off + x.ep + 1 + (i - b)];
-        out[i] = v;
+    // output words [w0, w1) lie wholly inside this child's bytes [lo, hi)
+    const uint64_t o0 = x.child_off + lo, o1 = x.child_off + hi;
+    const uint64_t w0 = (o0 + 3) & ~(uint64_t)3, w1 = o1 & ~(uint64_t)3;
+    if (w0 >= w1) {
+        for (uint64_t o = o0 + threadIdx.x; o < o1; o += blockDim.x)
+            dst[o] = child_byte(mums, dads, x, o - x.child_off, a, b);
+        return;
     }
+    for (uint64_t w = w0 + 4u * threadIdx.x; w < w1; w += 4u * blockDim.x) {
+        const uint64_t i = w - x.child_off;
+        const uint32_t v = (uint32_t)child_byte(mums, dads, x, i, a, b) |
+                           ((uint32_t)child_byte(mums, dads, x, i + 1, a, b) << 8) |
+                           ((uint32_t)child_byte(mums, dads, x, i + 2, a, b) << 16) |
+                           ((uint32_t)child_byte(mums, dads, x, i + 3, a, b) << 24);
+        *reinterpret_cast<uint32_t*>(dst + w) = v;
+    }
+    const uint32_t t = threadIdx.x;
+    if (t < w0 - o0) dst[o0 + t] = child_byte(mums, dads, x, o0 + t - x.child_off, a, b);
+    if (t < o1 - w1) dst[w1 + t] = child_byte(mums, dads, x, w1 + t - x.child_off, a, b);
 }
 
 // ------------------------------------------------------ selection (Table 1)

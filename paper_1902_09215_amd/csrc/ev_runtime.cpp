@@ -622,6 +622,8 @@ void exec_free(ev_ctx* c, Exec& x)
     x.d_gstack = nullptr;
     x.d_counters = nullptr;
     x.gstack_bytes = x.n_counters = 0;
+    for (hipEvent_t e : x.evl) (void)hipEventDestroy(e);
+    x.evl.clear();
     if (x.done) (void)hipEventDestroy(x.done);
     if (x.ev0) (void)hipEventDestroy(x.ev0);
     if (x.ev1) (void)hipEventDestroy(x.ev1);
@@ -632,10 +634,36 @@ void exec_free(ev_ctx* c, Exec& x)
     x.stream = nullptr;
 }
 
+ev_status rescache_build(ev_ctx* c, Exec& x, Pop* P, int32_t table, ResCache** out);
+
+// Drop the cached result slots of every population but P (they are
+// rebuilt on their next evaluation).  Waits for the context's stream first,
+// since queued evaluations may still use them.
+static void rescache_evict_others(ev_ctx* c, Exec& x, Pop* P)
+{
+    (void)sync(x);
+    std::lock_guard<std::mutex> g(c->pop_mu);
+    for (auto& kv : c->pops) {
+        if (kv.second == P) continue;
+        for (auto& r : kv.second->res) rescache_free(c, r.second);
+        kv.second->res.clear();
+    }
+}
+
 ev_status rescache_get(ev_ctx* c, Exec& x, Pop* P, int32_t table, ResCache** out)
 {
     auto it = P->res.find(table);
     if (it != P->res.end()) { *out = &it->second; return EV_OK; }
+    ev_status st0 = rescache_build(c, x, P, table, out);
+    // only the synchronous API (the context's own Exec) evicts: serving
+    // workers never touch registered populations' slots, the API might
+    if (st0 != EV_ENOMEM || &x != &c->main) return st0;
+    rescache_evict_others(c, x, P);
+    return rescache_build(c, x, P, table, out);
+}
+
+ev_status rescache_build(ev_ctx* c, Exec& x, Pop* P, int32_t table, ResCache** out)
+{
     ResCache r;
     const int32_t N = c->tables[table].N;
     r.N = N;
@@ -697,6 +725,14 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
     }
     if ((st = ensure_gstack(c, x, need)) != EV_OK) return st;
     hipStream_t s = x.stream;
+    if (timed) {
+        while (x.evl.size() < nl) {
+            hipEvent_t e = nullptr;
+            HIPCHK(hipEventCreate(&e));
+            x.evl.push_back(e);
+        }
+        x.n_levels_timed = (uint32_t)nl;
+    }
     if (timed) HIPCHK(hipEventRecord(x.ev0, s));
     HIPCHK(launch_fill_u32(x.d_counters, (uint32_t)(2 * nl), 0u, s));
     for (size_t li = 0; li < nl; li++) {
@@ -722,6 +758,7 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
         }
         if (L.n_chunks == 0) {
             if (timed && li == 0) HIPCHK(hipEventRecord(x.evi1, s));
+            if (timed) HIPCHK(hipEventRecord(x.evl[li], s));
             continue;
         }
         EvalArgs a;
@@ -739,6 +776,7 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
         const uint32_t grid = (uint32_t)std::min<uint64_t>(grid_max, a.n_items);
         HIPCHK(launch_eval(D, a, grid, s));
         if (timed && li == 0) HIPCHK(hipEventRecord(x.evi1, s));
+        if (timed) HIPCHK(hipEventRecord(x.evl[li], s));
     }
     HIPCHK(launch_fitness(rc->d_rows, ct.d_y, N, (uint32_t)P->M, d_fit, d_per_case, s));
     if (timed) HIPCHK(hipEventRecord(x.ev1, s));
@@ -811,7 +849,7 @@ ev_status crossover_build(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const int32_
         maxlen = std::max(maxlen, xp.child_len);
     }
     uint8_t* d_child = nullptr;
-    if ((st = dev_alloc(c, off[n] + 512, (void**)&d_child)) != EV_OK) { cleanup(); return st; }
+    if ((st = dev_alloc(c, off[n] + EV_POP_PAD, (void**)&d_child)) != EV_OK) { cleanup(); return st; }
     if ((st = dev_alloc(c, std::max<size_t>(1, n) * sizeof(XoPlan), &d_plan)) != EV_OK) {
         dev_free(c, d_child);
         cleanup();
@@ -825,7 +863,7 @@ ev_status crossover_build(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const int32_
         }
         HIPCHK(launch_xo_copy(mums->d_bytes, dads->d_bytes, (XoPlan*)d_plan, (uint32_t)n, maxlen, d_child, s));
     }
-    HIPCHK(hipMemsetAsync(d_child + off[n], 0xFF, 512, s));
+    HIPCHK(hipMemsetAsync(d_child + off[n], 0xFF, EV_POP_PAD, s));
     if ((st = sync(x)) != EV_OK) {
         dev_free(c, d_child);
         cleanup();
@@ -1004,7 +1042,7 @@ ev_status ev_load_trees(ev_ctx* c, const uint8_t* bytes, const uint64_t* off, in
     const uint64_t total = h_off[n];
     if (total > 0 && !bytes) return fail(EV_EINVAL, "ev_load_trees: NULL bytes");
     uint8_t* d = nullptr;
-    ev_status st = dev_alloc(c, total + 512, (void**)&d);
+    ev_status st = dev_alloc(c, total + EV_POP_PAD, (void**)&d);
     if (st != EV_OK) return st;
     hipError_t e = hipSuccess;
     if (flags & EV_DEVICE_PTR) {
@@ -1013,7 +1051,7 @@ ev_status ev_load_trees(ev_ctx* c, const uint8_t* bytes, const uint64_t* off, in
         dev_free(c, d);
         return st;
     }
-    if (e == hipSuccess) e = hipMemsetAsync(d + total, 0xFF, 512, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d + total, 0xFF, EV_POP_PAD, c->stream);
     if (e != hipSuccess) { dev_free(c, d); return hip_fail(e, "upload trees"); }
     Pop* P = nullptr;
     ev_status st2 = pop_build(c, c->main, d, h_off, &P, bad_tree);
@@ -1222,6 +1260,22 @@ ev_status ev_autotune(ev_ctx* c, ev_pop pop, int32_t table, int32_t reps, uint32
     c->chunk = best;
     if (best_chunk) *best_chunk = best;
     if (best_ms) *best_ms = best_t;
+    return EV_OK;
+}
+
+ev_status ev_last_level_times(ev_ctx* c, float* ms, int32_t cap, int32_t* n_levels)
+{
+    if (!c || (cap > 0 && !ms)) return fail(EV_EINVAL, "ev_last_level_times: bad arguments");
+    Exec& x = c->main;
+    const int32_t n = (int32_t)x.n_levels_timed;
+    if (n_levels) *n_levels = n;
+    if (n == 0) return EV_OK;
+    HIPCHK(hipEventSynchronize(x.evl[n - 1]));
+    hipEvent_t prev = x.ev0;
+    for (int32_t i = 0; i < n && i < cap; i++) {
+        HIPCHK(hipEventElapsedTime(&ms[i], prev, x.evl[i]));
+        prev = x.evl[i];
+    }
     return EV_OK;
 }
 

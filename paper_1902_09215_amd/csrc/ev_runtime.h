@@ -80,6 +80,8 @@ struct Exec {
     size_t gstack_bytes = 0;
     hipEvent_t done = nullptr;  // completion marker of sync()
     hipEvent_t ev0 = nullptr, ev1 = nullptr, evi0 = nullptr, evi1 = nullptr;
+    std::vector<hipEvent_t> evl;  // timed evaluations: one event after each plan level
+    uint32_t n_levels_timed = 0;
     // Pinned host staging of the stream's transfers: copies are plain DMA
     // from and to it; device-to-host data is handed out at the next sync().
     uint8_t* pin = nullptr;

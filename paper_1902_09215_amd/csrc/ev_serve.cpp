@@ -99,14 +99,14 @@ static ev_status run_eval_batch(ev_ctx* c, Exec& x, std::vector<Job*>& batch)
     Pop* P = nullptr;
     float* d_pc = nullptr;
     std::vector<float> fit(M), pc((size_t)M * N);
-    if ((st = dev_alloc(c, total + 512, (void**)&d)) == EV_OK) {
+    if ((st = dev_alloc(c, total + EV_POP_PAD, (void**)&d)) == EV_OK) {
         uint64_t at = 0;
         for (Job* j : batch) {
             if (st == EV_OK) st = put(x, d + at, j->bytes.data(), j->bytes.size());
             at += j->bytes.size();
         }
         if (st == EV_OK) {
-            hipError_t e = hipMemsetAsync(d + total, 0xFF, 512, x.stream);
+            hipError_t e = hipMemsetAsync(d + total, 0xFF, EV_POP_PAD, x.stream);
             if (e != hipSuccess) st = hip_fail(e, "serve upload");
         }
         if (st != EV_OK) {
