@@ -246,15 +246,15 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
     for (;;) {
         const uint64_t C = level == 0 ? C0 : C1;
         std::vector<ChunkIn> ch;
-        std::vector<char> forced(M, 0);
         for (int32_t t = 0; t < M; t++) {
             if (!active[t]) continue;
             const uint64_t len = rl[t];
             // One work item when the tree is small, or when the last split
-            // did not halve it (a skeleton dense in spine nodes): the latter
-            // must stay whole, or the levels would not converge.
-            forced[t] = level > 0 && len * 2 > prev_len[t];
-            const bool whole = len <= C || forced[t];
+            // did not halve it.  A skeleton dense in long spine paths
+            // shrinks slowly (only items holding a path's bottom reduce;
+            // the others copy slot values into new slots), so it is cheaper
+            // to finish it in one item than to split it level after level.
+            const bool whole = len <= C || (level > 0 && len * 2 > prev_len[t]);
             if (whole) {
                 if (len > 0xFFFFFFFFull) { cleanup(); return fail(EV_ECAP, "work item of %llu tokens", (unsigned long long)len); }
                 ch.push_back({rs[t], (uint32_t)len, (uint32_t)t});

@@ -414,6 +414,26 @@ def test_giant_population_sampled(ev):
     assert_same(pc[sample], want_pc, "giant per-case")
 
 
+def test_giant_max_population_sampled(ev):
+    # 48 random trees of 4e8 nodes (19.2e9 nodes, the 20 GB population),
+    # evaluated whole in the benchmark's launch configuration; the oracle
+    # recomputes two trees, each bit for bit.
+    buf, off, n = workloads.workload("giant_max")
+    x, y = workloads.cases(n)
+    print(f"giant_max: {int(off[-1])} nodes", flush=True)
+    with ev.Context(x, y) as c:
+        pop = c.load(buf, off)
+        info = ev.ev_get_plan_info(c.ctx, pop)
+        fit, pc = c.eval(pop, per_case=True)
+    print(f"giant_max plan {info}", flush=True)
+    sample = [0, 47]
+    parts = [buf[off[t]:off[t + 1]] for t in sample]
+    soff = workloads.offsets_from_sizes([p.size for p in parts])
+    want_fit, want_pc = oracle.eval_population(np.concatenate(parts), soff, x, y, threads=len(sample), per_case=True)
+    assert_same(fit[sample], want_fit, "giant_max fitness")
+    assert_same(pc[sample], want_pc, "giant_max per-case")
+
+
 def test_single_tree_populations(ev):
     # every tree alone as its own population: each plan stands on its own
     # (a lone tree whose stack only reaches the window's upper quarter still
