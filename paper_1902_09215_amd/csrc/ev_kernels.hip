@@ -314,6 +314,21 @@ __device__ uint32_t run_segment(const uint8_t* __restrict__ seq, uint64_t start,
 // Segments of a level: segment s of chunk c covers tokens
 // [c.start + s*SEG, ...) and is read after segment s+1.
 
+// The segments of every chunk: block j writes chunk j's.
+__global__ void k_seg_build(const ChunkIn* __restrict__ ch, const ChunkSegs* __restrict__ cg, uint32_t n,
+                            uint32_t seg_len, SegIn* __restrict__ seg)
+{
+    const uint32_t j = blockIdx.x;
+    if (j >= n) return;
+    const ChunkIn c = ch[j];
+    const ChunkSegs g = cg[j];
+    for (uint32_t k = threadIdx.x; k < g.n_seg; k += blockDim.x) {
+        const uint64_t o = (uint64_t)k * seg_len;
+        const uint32_t len = c.len - (uint32_t)o < seg_len ? c.len - (uint32_t)o : seg_len;
+        seg[g.first + k] = SegIn{c.start + o, len, k == 0 ? 1u : 0u};
+    }
+}
+
 // Per segment: its cnt map (a, b), validity counters and input references.
 __global__ void k_seg_fn(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs, uint32_t n,
                          SegFn* __restrict__ out, uint32_t max_tok)
@@ -924,6 +939,14 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3(cdiv(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_build(const ChunkIn* ch, const ChunkSegs* cg, uint32_t n, uint32_t seg_len, SegIn* seg,
+                            hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_build, dim3(n), dim3(64), 0, s, ch, cg, n, seg_len, seg);
     return hipGetLastError();
 }
 

@@ -6,6 +6,8 @@
 
 namespace ev {
 hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
+hipError_t launch_seg_build(const ChunkIn* ch, const ChunkSegs* cg, uint32_t n, uint32_t seg_len, SegIn* seg,
+                            hipStream_t s);
 hipError_t launch_seg_fn(const uint8_t* seq, const SegIn* segs, uint32_t n, SegFn* out, uint32_t max_tok,
                          hipStream_t s);
 hipError_t launch_seg_scan(const ChunkSegs* cseg, uint32_t n, const SegFn* fn, SegStart* st, ChunkStat* cstat,

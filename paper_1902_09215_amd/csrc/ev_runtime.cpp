@@ -182,8 +182,17 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
     pl.slots_total = 0;
     pl.max_stack = 0;
 
-    std::vector<uint64_t> rs(M), rl(M), prev_len(M, 0), ref_base(M, 0);
-    std::vector<char> active(M, 1);
+    PlanScratch& W = x.plan;
+    auto& rs = W.rs;
+    auto& rl = W.rl;
+    auto& prev_len = W.prev_len;
+    auto& ref_base = W.ref_base;
+    auto& active = W.active;
+    rs.assign(M, 0);
+    rl.assign(M, 0);
+    prev_len.assign(M, 0);
+    ref_base.assign(M, 0);
+    active.assign(M, 1);
     for (int32_t t = 0; t < M; t++) {
         rs[t] = P->h_off[t];
         rl[t] = P->h_off[t + 1] - P->h_off[t];
@@ -197,10 +206,10 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
     int level = 0;
     // per-level device scratch: segments, their maps/starts/counts/positions
     void *d_seg = nullptr, *d_cseg = nullptr, *d_fn = nullptr, *d_st = nullptr, *d_cnt = nullptr, *d_stat = nullptr,
-         *d_cb = nullptr, *d_fe = nullptr, *d_scode = nullptr, *d_sfrag = nullptr, *d_err = nullptr;
+         *d_cb = nullptr, *d_fe = nullptr, *d_scode = nullptr, *d_sfrag = nullptr, *d_err = nullptr, *d_ch = nullptr;
     ev_status st = EV_OK;
     auto cleanup = [&]() {
-        for (void** p : {&d_seg, &d_cseg, &d_fn, &d_st, &d_cnt, &d_stat, &d_cb, &d_fe, &d_scode, &d_sfrag, &d_err}) {
+        for (void** p : {&d_seg, &d_cseg, &d_fn, &d_st, &d_cnt, &d_stat, &d_cb, &d_fe, &d_scode, &d_sfrag, &d_err, &d_ch}) {
             dev_free(c, *p);
             *p = nullptr;
         }
@@ -211,29 +220,32 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         return dev_alloc(c, bytes, p);
     };
     uint32_t n_seg = 0;
-    std::vector<uint32_t> seg_chunk;  // chunk of every segment of the level
-    // count pass over a level's chunks: per-chunk totals in cs
+    auto& cg = W.cg;  // per chunk of the level: its first segment and count
+    // count pass over a level's chunks: per-chunk totals in cs.  Segments
+    // are 256 tokens at level 0 and 64 at the skeleton levels, which have
+    // few tokens and need the extra parallelism.
     auto count = [&](const std::vector<ChunkIn>& ch, std::vector<ChunkStat>& cs) -> ev_status {
         const uint32_t n = (uint32_t)ch.size();
-        std::vector<SegIn> sg;
-        seg_chunk.clear();
-        std::vector<ChunkSegs> cg(n);
+        const uint32_t seg_len = level == 0 ? SEG_TOKENS : SEG_TOKENS / 4;
+        cg.resize(n);
+        uint64_t ns = 0;
         for (uint32_t j = 0; j < n; j++) {
-            cg[j].first = (uint32_t)sg.size();
-            for (uint64_t o = 0; o < ch[j].len; o += SEG_TOKENS)
-                sg.push_back(SegIn{ch[j].start + o, (uint32_t)std::min<uint64_t>(SEG_TOKENS, ch[j].len - o), o == 0 ? 1u : 0u});
-            seg_chunk.resize(sg.size(), j);
-            cg[j].n_seg = (uint32_t)sg.size() - cg[j].first;
+            cg[j].first = (uint32_t)ns;
+            cg[j].n_seg = (ch[j].len + seg_len - 1) / seg_len;
+            ns += cg[j].n_seg;
         }
-        n_seg = (uint32_t)sg.size();
+        if (ns > 0xFFFFFFF0ull) return fail(EV_ECAP, "too many structure segments");
+        n_seg = (uint32_t)ns;
         ev_status e;
         if ((e = realloc(&d_seg, n_seg * sizeof(SegIn))) || (e = realloc(&d_cseg, n * sizeof(ChunkSegs))) ||
             (e = realloc(&d_fn, n_seg * sizeof(SegFn))) || (e = realloc(&d_st, n_seg * sizeof(SegStart))) ||
-            (e = realloc(&d_cnt, n_seg * sizeof(SegCount))) || (e = realloc(&d_stat, n * sizeof(ChunkStat))))
+            (e = realloc(&d_cnt, n_seg * sizeof(SegCount))) || (e = realloc(&d_stat, n * sizeof(ChunkStat))) ||
+            (e = realloc(&d_ch, n * sizeof(ChunkIn))))
             return e;
         cs.resize(n);
-        if ((e = put(x, d_seg, sg.data(), n_seg * sizeof(SegIn))) || (e = put(x, d_cseg, cg.data(), n * sizeof(ChunkSegs))))
+        if ((e = put(x, d_ch, ch.data(), n * sizeof(ChunkIn))) || (e = put(x, d_cseg, cg.data(), n * sizeof(ChunkSegs))))
             return e;
+        HIPCHK(launch_seg_build((ChunkIn*)d_ch, (ChunkSegs*)d_cseg, n, seg_len, (SegIn*)d_seg, s));
         HIPCHK(launch_seg_fn(cur, (SegIn*)d_seg, n_seg, (SegFn*)d_fn, level == 0 ? TOK_X : TOK_REF, s));
         HIPCHK(launch_seg_scan((ChunkSegs*)d_cseg, n, (SegFn*)d_fn, (SegStart*)d_st, (ChunkStat*)d_stat, s));
         HIPCHK(launch_seg_count(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (SegCount*)d_cnt, s));
@@ -245,7 +257,8 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
 
     for (;;) {
         const uint64_t C = level == 0 ? C0 : C1;
-        std::vector<ChunkIn> ch;
+        auto& ch = W.ch;
+        ch.clear();
         for (int32_t t = 0; t < M; t++) {
             if (!active[t]) continue;
             const uint64_t len = rl[t];
@@ -264,15 +277,17 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             }
         }
         if (ch.empty()) break;
-        std::vector<ChunkStat> cs;
+        auto& cs = W.cs;
         if ((st = count(ch, cs)) != EV_OK) { cleanup(); return st; }
 
         if (level == 0) {
             // Sec. 2.2 word: every token fills one open slot and a function
             // opens two; a tree is valid iff a slot is open before each token
             // and none after the last.
-            std::vector<int64_t> open(M, 1);
-            std::vector<char> ok(M, 1);
+            auto& open = W.open_cnt;
+            auto& ok = W.ok;
+            open.assign(M, 1);
+            ok.assign(M, 1);
             for (size_t j = 0; j < ch.size(); j++) {
                 const uint32_t t = ch[j].tree;
                 if (cs[j].bad || open[t] + cs[j].minpref < 1) ok[t] = 0;
@@ -288,13 +303,23 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         }
 
         const uint32_t n = (uint32_t)ch.size();
-        const std::vector<uint64_t> rs0 = rs;
+        auto& rs0 = W.rs0;
+        rs0 = rs;
 
         // slot numbering (global over the level's chunks, in sequence order)
         // and the split of the work items between the two kernels
-        std::vector<uint64_t> out_end(n), frag_end(n), code_begin(n, ~0ull);
-        std::vector<char> fast(n, 0);
-        std::vector<uint32_t> tree_first(M, UINT32_MAX), tree_last(M, 0);
+        auto& out_end = W.out_end;
+        auto& frag_end = W.frag_end;
+        auto& code_begin = W.code_begin;
+        auto& fast = W.fast;
+        auto& tree_first = W.tree_first;
+        auto& tree_last = W.tree_last;
+        out_end.assign(n, 0);
+        frag_end.assign(n, 0);
+        code_begin.assign(n, ~0ull);
+        fast.assign(n, 0);
+        tree_first.assign(M, UINT32_MAX);
+        tree_last.assign(M, 0);
         uint64_t so = 0, sf = 0, sc = 0, tokens = 0;
         uint32_t max_m = 0, slab_top = 0;
         for (uint32_t j = 0; j < n; j++) {
@@ -319,7 +344,8 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         if (so > 0xFFFFFFF0ull) { cleanup(); return fail(EV_ECAP, "too many intermediate results"); }
 
         // input slots: the k-th REF of this level is the previous level's slot k
-        std::vector<EvalChunk> ec(n);
+        auto& ec = W.ec;
+        ec.assign(n, EvalChunk{});
         for (int32_t t = 0; t < M; t++) {
             if (tree_first[t] == UINT32_MAX) continue;
             uint64_t in_run = ref_base[t];
@@ -348,8 +374,10 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         L.slab_entries = slab_top + 1 > EV_VSTACK_ENTRIES - EV_VHALF / 2 ? slab_top + EV_VHALF : 0;
         pl.chunks_total += n;
         pl.slots_total += so;
-        std::vector<EvalChunk> slow;
-        std::vector<std::pair<uint32_t, RunChunk>> run;
+        auto& slow = W.slow;
+        auto& run = W.run;
+        slow.clear();
+        run.clear();
         for (uint32_t j = 0; j < n; j++) {
             if (fast[j]) run.push_back({ec[j].len, RunChunk{code_begin[j], ec[j].in_end, ec[j].out_end}});
             else slow.push_back(ec[j]);
@@ -367,7 +395,8 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             if ((st = put(x, LL.d_chunks, slow.data(), slow.size() * sizeof(EvalChunk))) != EV_OK) { cleanup(); return st; }
         }
         if (!run.empty()) {
-            std::vector<RunChunk> rc(run.size());
+            auto& rc = W.rc;
+            rc.resize(run.size());
             for (size_t i = 0; i < run.size(); i++) rc[i] = run[i].second;
             if ((st = dev_alloc(c, rc.size() * sizeof(RunChunk), (void**)&LL.d_run)) != EV_OK) { cleanup(); return st; }
             if ((st = dev_alloc(c, sc * 4 + 512, (void**)&LL.codes)) != EV_OK) { cleanup(); return st; }
@@ -431,7 +460,12 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             if (err[0]) {
                 dev_free(c, d_next);
                 cleanup();
-                const uint32_t sj = err[1] < seg_chunk.size() ? seg_chunk[err[1]] : 0;
+                // the chunk holding the failing segment
+                uint32_t sj = 0;
+                for (uint32_t lo = 0, hi = (uint32_t)cg.size(); lo < hi;) {
+                    const uint32_t mid = (lo + hi) / 2;
+                    if (cg[mid].first <= err[1]) { sj = mid; lo = mid + 1; } else { hi = mid; }
+                }
                 const uint32_t t = ch[sj].tree;
                 return fail(EV_EDEVICE,
                             "internal: malformed code stream at level %d (flags %u, tree %u of %u tokens, chunk at "

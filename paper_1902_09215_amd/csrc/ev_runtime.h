@@ -69,6 +69,21 @@ struct Pop {
     std::map<int32_t, ResCache> res;
 };
 
+// Host-side working vectors of plan_build, kept across calls so that their
+// (large) buffers are reused instead of freshly mapped and faulted in.
+struct PlanScratch {
+    std::vector<uint64_t> rs, rl, prev_len, ref_base, rs0, out_end, frag_end, code_begin;
+    std::vector<int64_t> open_cnt;
+    std::vector<char> active, ok, fast;
+    std::vector<uint32_t> tree_first, tree_last;
+    std::vector<ChunkIn> ch;
+    std::vector<ChunkSegs> cg;
+    std::vector<ChunkStat> cs;
+    std::vector<EvalChunk> ec, slow;
+    std::vector<std::pair<uint32_t, RunChunk>> run;
+    std::vector<RunChunk> rc;
+};
+
 // Per-thread execution resources: a stream (possibly shared) and the scratch
 // its launches use.
 struct Exec {
@@ -92,6 +107,7 @@ struct Exec {
         size_t n;
     };
     std::vector<Out> pin_out;
+    PlanScratch plan;
 };
 
 struct Job;
