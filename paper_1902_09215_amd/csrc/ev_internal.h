@@ -32,8 +32,8 @@ struct ChunkStat {
 };
 
 // Bytes of 0xFF after a population's trees: room for the wide reads of
-// the subtree scan and the token readers.
-constexpr uint64_t EV_POP_PAD = 2048;
+// the subtree scan (up to 4 KiB past a subtree's end) and the token readers.
+constexpr uint64_t EV_POP_PAD = 4096 + 64;
 
 // Structure segments (SEG_TOKENS tokens of one chunk).
 constexpr uint32_t SEG_TOKENS = 256;

@@ -180,27 +180,33 @@ struct Sink {
     }
 };
 
-// Reads tokens right to left, 16 bytes per load.
-struct RevTokens {
-    const uint8_t* seq;
-    uint64_t k, lo, wb;
-    u32x4 wd;
-    __device__ RevTokens(const uint8_t* s, uint64_t start, uint32_t len) : seq(s), k(start + len), lo(start), wb(~0ull) {}
-    __device__ bool next(uint32_t& t)
-    {
-        if (k <= lo) return false;
-        k--;
-        const uint64_t b = k & ~(uint64_t)15;
-        if (b != wb) {
-            wd = *reinterpret_cast<const u32x4*>(seq + b);
-            wb = b;
+// Calls f(t) for the tokens of [start, start+len) right to left.  Tokens
+// are read in aligned 16-byte blocks, the next block to the left in flight
+// while a block's tokens are worked (a block loop around a token loop, so
+// that the prefetched block needs no conditional copy).  Whole blocks are
+// read: up to 15 bytes on either side of the range, and the range's first
+// block once more at the end, all inside the buffers' padding.
+template <class F>
+__device__ __forceinline__ void for_tokens_rev(const uint8_t* __restrict__ seq, uint64_t start, uint32_t len, F&& f)
+{
+    if (!len) return;
+    const uint64_t first = start & ~(uint64_t)15;
+    uint64_t b = (start + len - 1) & ~(uint64_t)15;
+    uint32_t jhi = (uint32_t)((start + len - 1) & 15);
+    u32x4 nxt = *reinterpret_cast<const u32x4*>(seq + b);
+    for (;;) {
+        const u32x4 cur = nxt;
+        nxt = *reinterpret_cast<const u32x4*>(seq + (b > first ? b - 16 : b));
+        const uint32_t jlo = b == first ? (uint32_t)(start & 15) : 0u;
+        for (uint32_t j = jhi + 1; j-- > jlo;) {
+            const uint32_t word = j >= 8 ? (j >= 12 ? cur.w : cur.z) : (j >= 4 ? cur.y : cur.x);
+            f((word >> (8 * (j & 3))) & 255u);
         }
-        const uint32_t j = (uint32_t)(k & 15);
-        const uint32_t word = j >= 8 ? (j >= 12 ? wd.w : wd.z) : (j >= 4 ? wd.y : wd.x);
-        t = (word >> (8 * (j & 3))) & 255u;
-        return true;
+        if (b == first) break;
+        b -= 16;
+        jhi = 15;
     }
-};
+}
 
 // Machine over one segment from a given start.  last: the segment holding
 // the chunk's first token (it ends with the chunk's flush and END); other
@@ -212,9 +218,7 @@ __device__ uint32_t run_segment(const uint8_t* __restrict__ seq, uint64_t start,
     uint32_t tv = cnt_in > P ? 1u : 0u;
     uint32_t m = cnt_in - tv - P;
     uint32_t base = norm_base(m), maxtop = m;
-    RevTokens rt(seq, start, len);
-    uint32_t t;
-    while (rt.next(t)) {
+    for_tokens_rev(seq, start, len, [&](const uint32_t t) {
         // Common tokens, decided with selects so that lanes on different
         // token kinds do not diverge: a function finding two values without
         // a FILL, and an x needing no SPILL.  The rest take the full path.
@@ -229,7 +233,7 @@ __device__ uint32_t run_segment(const uint8_t* __restrict__ seq, uint64_t start,
             P = fast_fn ? 0u : 1u;
             o.code_fast(kind);
             maxtop = m > maxtop ? m : maxtop;
-            continue;
+            return;
         }
         if (t == TOK_X) {
             if (!P) {
@@ -285,7 +289,7 @@ __device__ uint32_t run_segment(const uint8_t* __restrict__ seq, uint64_t start,
             }
         }
         maxtop = m > maxtop ? m : maxtop;
-    }
+    });
     if (!last) {
         o.flush();
         const uint32_t nb = norm_base(m);
@@ -294,13 +298,14 @@ __device__ uint32_t run_segment(const uint8_t* __restrict__ seq, uint64_t start,
         return maxtop;
     }
     // the chunk's first token: every value left becomes a slot, bottom first
+    // (nothing is pending after a FLUSH, so the runs are put directly)
     if (base > 0) {
         o.code(EV_K_FLUSH);
-        for (uint32_t i = 0; i < base; i++) o.code(EV_K_OUTMEM);
+        for (uint32_t i = 0; i < base; i++) o.put(EV_K_OUTMEM);
     }
     if (m > base) {
         o.code(EV_K_FLUSH);
-        for (uint32_t i = base; i < m; i++) o.code(EV_K_OUTBOT);
+        for (uint32_t i = base; i < m; i++) o.put(EV_K_OUTBOT);
     }
     if (tv) o.code(EV_K_OUTT);
     if (P) o.code(EV_K_OUTX);
@@ -314,17 +319,21 @@ __device__ uint32_t run_segment(const uint8_t* __restrict__ seq, uint64_t start,
 // Segments of a level: segment s of chunk c covers tokens
 // [c.start + s*SEG, ...) and is read after segment s+1.
 
-// The segments of every chunk: block j writes chunk j's.
+// The segments of every chunk: block j writes chunk j's.  Segment 0 holds
+// the chunk's first `head` tokens and the others `seg_len` each: segment 0
+// also emits the chunk's final flush (a slot per value left), so it is kept
+// short to keep its lane from lagging behind the wave.
 __global__ void k_seg_build(const ChunkIn* __restrict__ ch, const ChunkSegs* __restrict__ cg, uint32_t n,
-                            uint32_t seg_len, SegIn* __restrict__ seg)
+                            uint32_t seg_len, uint32_t head, SegIn* __restrict__ seg)
 {
     const uint32_t j = blockIdx.x;
     if (j >= n) return;
     const ChunkIn c = ch[j];
     const ChunkSegs g = cg[j];
     for (uint32_t k = threadIdx.x; k < g.n_seg; k += blockDim.x) {
-        const uint64_t o = (uint64_t)k * seg_len;
-        const uint32_t len = c.len - (uint32_t)o < seg_len ? c.len - (uint32_t)o : seg_len;
+        const uint32_t o = k == 0 ? 0u : head + (k - 1) * seg_len;
+        const uint32_t cap = k == 0 ? head : seg_len;
+        const uint32_t len = c.len - o < cap ? c.len - o : cap;
         seg[g.first + k] = SegIn{c.start + o, len, k == 0 ? 1u : 0u};
     }
 }
@@ -338,9 +347,7 @@ __global__ void k_seg_fn(const uint8_t* __restrict__ seq, const SegIn* __restric
     const SegIn g = segs[si];
     int32_t a = 0, b = INT32_MIN / 2, R = 0, maxR = INT32_MIN;
     uint32_t bad = 0, n_in = 0, last_t = 0;
-    RevTokens rt(seq, g.start, g.len);
-    uint32_t t;
-    while (rt.next(t)) {
+    for_tokens_rev(seq, g.start, g.len, [&](const uint32_t t) {
         bad |= t > max_tok;
         n_in += t == TOK_REF;
         if (t < TOK_X) {
@@ -354,7 +361,7 @@ __global__ void k_seg_fn(const uint8_t* __restrict__ seq, const SegIn* __restric
         }
         maxR = R > maxR ? R : maxR;
         last_t = t;
-    }
+    });
     SegFn f;
     f.a = a;
     f.b = b;
@@ -489,60 +496,85 @@ __global__ void k_seg_check(const uint32_t* __restrict__ codes, const SegIn* __r
     const uint32_t len = sc.n_codes;
     const uint32_t P = st[si].P, tv = st[si].cnt > P ? 1u : 0u, m0 = st[si].cnt - tv - P, ref0 = st[si].ref0;
     int32_t slab = (int32_t)norm_base(m0), idx = (int32_t)(m0 - (uint32_t)slab), fl = 0;
-    uint32_t outs = 0, ins = 0, bad = 0, ended = 0, m = m0;
+    uint32_t outs = 0, ins = 0, bad = 0, ended = 0, tail = 0, m = m0;
     // bad: 1 a code names another position or no handler, 2 the window or
     // slab leaves its bounds, 4 END misplaced, 8 boundary position, 16/32
     // slots written/read differ from the plan
-    for (uint32_t i = 0; i < len; i++) {
-        const uint32_t v = codes[b + i];
-        // decode (selects): handler base and stride of this position
-        const uint32_t pos = (uint32_t)((b + i) & (EV_CODE_POS - 1));
-        const bool tr = (pos & 15u) == 15u;
-        const uint32_t base = tr ? EV_CODE_TBASE + (pos >> 4) * EV_NK * EV_CODE_TSTRIDE
-                                 : (pos - (pos >> 4)) * EV_NK * EV_CODE_NSTRIDE;
-        const uint32_t stride = tr ? EV_CODE_TSTRIDE : EV_CODE_NSTRIDE;
-        const uint32_t rel = v - base;
-        const uint32_t k = rel / stride;
-        if (v < base || rel % stride || k >= EV_NK) bad |= 1;
-        if (ended) bad |= 4;
-        // stack actions of the common kinds, with selects
-        const bool ops1 = k <= EV_K_OPS3;
-        const bool ops2 = k >= EV_K_OPS00 && k <= EV_K_OPS22;
-        const bool pref = k >= EV_K_PUSHREF0 && k < EV_K_PUSHREF0 + EV_RING;
-        const bool lref = k >= EV_K_LOADREF0 && k < EV_K_LOADREF0 + EV_RING;
-        const bool push1 = (k >= EV_K_CH0 && k <= EV_K_CH3) || k == EV_K_PUSHX || pref;
-        const int32_t need = ops1 ? 1 : (ops2 ? 2 : 0);
-        const int32_t d = ops1 ? -1 : ops2 ? -2 : push1 ? 1 : (k == EV_K_PUSH2X ? 2 : 0);
-        uint32_t w = idx < need ? 1u : 0u;
-        // a REF's ring slot follows from its index within the work item
-        const uint32_t slot = (ref0 + ins) & (EV_RING - 1);
-        if ((pref && k - EV_K_PUSHREF0 != slot) || (lref && k - EV_K_LOADREF0 != slot)) bad |= 1;
-        idx += d;
-        m += (uint32_t)d;
-        ins += (pref || lref) ? 1u : 0u;
-        if (k >= EV_K_OUTT && k <= EV_K_OUTMEM) {  // the rare kinds
-            if (k == EV_K_END) ended = 1;
-            if (k == EV_K_FLUSH) {
-                fl = 0;
-            } else if (k == EV_K_OUTBOT) {
-                w |= fl >= idx;
-                fl++;
-            } else if (k == EV_K_OUTMEM) {
-                w |= fl >= slab;
-                fl++;
-            } else if (k == EV_K_SPILL) {
-                w |= idx < (int32_t)EV_VHALF;
-                idx -= EV_VHALF;
-                slab += EV_VHALF;
-            } else if (k == EV_K_FILL) {
-                w |= slab < (int32_t)EV_VHALF || idx > (int32_t)EV_VHALF - 1;
-                idx += EV_VHALF;
-                slab -= EV_VHALF;
+    // codes are read in aligned blocks of four, the next block in flight
+    // (at most seven codes past the stream, inside the buffer's zero tail)
+    const uint32_t sk = (uint32_t)(b & 3u);
+    const uint32_t* cb = codes + (b - sk);
+    u32x4 nxt = *reinterpret_cast<const u32x4*>(cb);
+    for (uint32_t q0 = 0; q0 < sk + len; q0 += 4) {
+        const u32x4 cur = nxt;
+        nxt = *reinterpret_cast<const u32x4*>(cb + q0 + 4);
+        const uint32_t jlo = q0 ? 0u : sk, jend = sk + len - q0 < 4u ? sk + len - q0 : 4u;
+        for (uint32_t j = jlo; j < jend; j++) {
+            const uint32_t i = q0 + j - sk;
+            const uint32_t v = j >= 2 ? (j == 3 ? cur.w : cur.z) : (j == 1 ? cur.y : cur.x);
+            // decode (selects): handler base and stride of this position
+            const uint32_t pos = (uint32_t)((b + i) & (EV_CODE_POS - 1));
+            const bool tr = (pos & 15u) == 15u;
+            const uint32_t base = tr ? EV_CODE_TBASE + (pos >> 4) * EV_NK * EV_CODE_TSTRIDE
+                                     : (pos - (pos >> 4)) * EV_NK * EV_CODE_NSTRIDE;
+            const uint32_t stride = tr ? EV_CODE_TSTRIDE : EV_CODE_NSTRIDE;
+            const uint32_t rel = v - base;
+            const uint32_t k = rel / stride;
+            if (v < base || rel % stride || k >= EV_NK) bad |= 1;
+            if (ended) bad |= 4;
+            if (tail) {
+                // after a FLUSH only the chunk's final slot writes and END may
+                // follow, none of which moves the window (a short path for
+                // the long runs of OUTMEM and OUTBOT)
+                const bool isF = k == EV_K_FLUSH, isB = k == EV_K_OUTBOT, isM = k == EV_K_OUTMEM;
+                const bool isT = k == EV_K_OUTT, isX = k == EV_K_OUTX, isE = k == EV_K_END;
+                const bool w = !(isF || isB || isM || isT || isX || isE) || (isB && fl >= idx) || (isM && fl >= slab);
+                fl = isF ? 0 : fl + ((isB || isM) ? 1 : 0);
+                outs += (isB || isM || isT || isX) ? 1u : 0u;
+                ended |= isE ? 1u : 0u;
+                if (w) bad |= 2;
+                continue;
             }
-            outs += (k == EV_K_OUTT || k == EV_K_OUTX || k == EV_K_OUTBOT || k == EV_K_OUTMEM);
+            // stack actions of the common kinds, with selects
+            const bool ops1 = k <= EV_K_OPS3;
+            const bool ops2 = k >= EV_K_OPS00 && k <= EV_K_OPS22;
+            const bool pref = k >= EV_K_PUSHREF0 && k < EV_K_PUSHREF0 + EV_RING;
+            const bool lref = k >= EV_K_LOADREF0 && k < EV_K_LOADREF0 + EV_RING;
+            const bool push1 = (k >= EV_K_CH0 && k <= EV_K_CH3) || k == EV_K_PUSHX || pref;
+            const int32_t need = ops1 ? 1 : (ops2 ? 2 : 0);
+            const int32_t d = ops1 ? -1 : ops2 ? -2 : push1 ? 1 : (k == EV_K_PUSH2X ? 2 : 0);
+            uint32_t w = idx < need ? 1u : 0u;
+            // a REF's ring slot follows from its index within the work item
+            const uint32_t slot = (ref0 + ins) & (EV_RING - 1);
+            if ((pref && k - EV_K_PUSHREF0 != slot) || (lref && k - EV_K_LOADREF0 != slot)) bad |= 1;
+            idx += d;
+            m += (uint32_t)d;
+            ins += (pref || lref) ? 1u : 0u;
+            if (k >= EV_K_OUTT && k <= EV_K_OUTMEM) {  // the rare kinds
+                if (k == EV_K_END) ended = 1;
+                if (k == EV_K_FLUSH) {
+                    fl = 0;
+                    tail = 1;
+                } else if (k == EV_K_OUTBOT) {
+                    w |= fl >= idx;
+                    fl++;
+                } else if (k == EV_K_OUTMEM) {
+                    w |= fl >= slab;
+                    fl++;
+                } else if (k == EV_K_SPILL) {
+                    w |= idx < (int32_t)EV_VHALF;
+                    idx -= EV_VHALF;
+                    slab += EV_VHALF;
+                } else if (k == EV_K_FILL) {
+                    w |= slab < (int32_t)EV_VHALF || idx > (int32_t)EV_VHALF - 1;
+                    idx += EV_VHALF;
+                    slab -= EV_VHALF;
+                }
+                outs += (k == EV_K_OUTT || k == EV_K_OUTX || k == EV_K_OUTBOT || k == EV_K_OUTMEM);
+            }
+            w |= idx < 0 || idx > (int32_t)EV_VSTACK - 1 || slab < 0 || slab > (int32_t)slab_entries;
+            if (w) bad |= 2;
         }
-        w |= idx < 0 || idx > (int32_t)EV_VSTACK - 1 || slab < 0 || slab > (int32_t)slab_entries;
-        if (w) bad |= 2;
     }
     if ((ended != 0) != (g.last != 0)) bad |= 4;
     // a segment hands the next one the window in its boundary position
@@ -729,9 +761,9 @@ __global__ __launch_bounds__(64) void k_subtree_end(const uint8_t* __restrict__ 
                                                     const uint64_t* __restrict__ pos, uint32_t n,
                                                     uint64_t* __restrict__ end_out)
 {
-    // One wave per query; it reads 1 KiB per step, 16 aligned bytes per
-    // lane (the population buffer carries EV_POP_PAD bytes of padding, so
-    // the last step stays inside it).
+    // One wave per query; it reads 4 KiB per step, 64 aligned bytes per
+    // lane (the population buffer carries EV_POP_PAD >= 4 KiB of padding,
+    // so the last step stays inside it).
     const uint32_t qi = blockIdx.x;
     if (qi >= n) return;
     const uint32_t lane = threadIdx.x;
@@ -739,14 +771,18 @@ __global__ __launch_bounds__(64) void k_subtree_end(const uint8_t* __restrict__ 
     uint64_t w = a & ~(uint64_t)15;
     int32_t open = 1;  // slots still to fill before the subtree is complete
     for (;;) {
-        const uint64_t addr = w + (uint64_t)lane * 16u;
-        const u32x4 v = *reinterpret_cast<const u32x4*>(buf + addr);
+        const uint64_t addr = w + (uint64_t)lane * 64u;
+        const u32x4* src = reinterpret_cast<const u32x4*>(buf + addr);
+        const u32x4 v0 = src[0], v1 = src[1], v2 = src[2], v3 = src[3];
+        auto tok_at = [&](int j) {
+            const u32x4& v = j >= 32 ? (j >= 48 ? v3 : v2) : (j >= 16 ? v1 : v0);
+            const int i = j & 15;
+            const uint32_t word = i >= 8 ? (i >= 12 ? v.w : v.z) : (i >= 4 ? v.y : v.x);
+            return (word >> (8 * (i & 3))) & 255u;
+        };
         int32_t c = 0;
-        for (int j = 0; j < 16; j++) {
-            const uint32_t word = j >= 8 ? (j >= 12 ? v.w : v.z) : (j >= 4 ? v.y : v.x);
-            const uint32_t tok = (word >> (8 * (j & 3))) & 255u;
-            c += addr + j >= a ? (tok < TOK_X ? 1 : -1) : 0;
-        }
+#pragma unroll
+        for (int j = 0; j < 64; j++) c += addr + j >= a ? (tok_at(j) < TOK_X ? 1 : -1) : 0;
         int32_t pre = c;
         for (int d = 1; d < 64; d <<= 1) {
             const int32_t o = __shfl_up(pre, d, 64);
@@ -754,11 +790,10 @@ __global__ __launch_bounds__(64) void k_subtree_end(const uint8_t* __restrict__ 
         }
         const int32_t before = pre - c;
         int32_t hit = -1, cc = 0;
-        for (int j = 0; j < 16; j++) {
-            const uint32_t word = j >= 8 ? (j >= 12 ? v.w : v.z) : (j >= 4 ? v.y : v.x);
-            const uint32_t tok = (word >> (8 * (j & 3))) & 255u;
+#pragma unroll
+        for (int j = 0; j < 64; j++) {
             if (addr + j >= a) {
-                cc += tok < TOK_X ? 1 : -1;
+                cc += tok_at(j) < TOK_X ? 1 : -1;
                 if (hit < 0 && open + before + cc == 0) hit = j;
             }
         }
@@ -766,11 +801,11 @@ __global__ __launch_bounds__(64) void k_subtree_end(const uint8_t* __restrict__ 
         if (mask) {
             const int first = __ffsll((unsigned long long)mask) - 1;
             const int j = __shfl(hit, first, 64);
-            if (lane == 0) end_out[qi] = w + (uint64_t)first * 16u + (uint64_t)j - base[qi];
+            if (lane == 0) end_out[qi] = w + (uint64_t)first * 64u + (uint64_t)j - base[qi];
             return;
         }
         open += __shfl(pre, 63, 64);
-        w += 1024;
+        w += 4096;
     }
 }
 
@@ -787,11 +822,13 @@ __device__ __forceinline__ uint8_t child_byte(const uint8_t* __restrict__ mums, 
 }
 
 __global__ void k_xo_copy(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
-                          const XoPlan* __restrict__ plan, uint32_t n_children, uint8_t* __restrict__ dst)
+                          const XoPlan* __restrict__ plan, const uint64_t* __restrict__ off, uint32_t n_children,
+                          uint8_t* __restrict__ dst)
 {
     const uint32_t j = blockIdx.y;
     if (j >= n_children) return;
-    const XoPlan x = plan[j];
+    XoPlan x = plan[j];
+    x.child_off = off[j];
     const uint64_t lo = (uint64_t)blockIdx.x * 4096u;
     if (lo >= x.child_len) return;
     const uint64_t hi = lo + 4096u < x.child_len ? lo + 4096u : x.child_len;
@@ -815,6 +852,96 @@ __global__ void k_xo_copy(const uint8_t* __restrict__ mums, const uint8_t* __res
     const uint32_t t = threadIdx.x;
     if (t < w0 - o0) dst[o0 + t] = child_byte(mums, dads, x, o0 + t - x.child_off, a, b);
     if (t < o1 - w1) dst[w1 + t] = child_byte(mums, dads, x, w1 + t - x.child_off, a, b);
+}
+
+// Per child j: the two subtree queries, (tree start, point) in the mum's
+// and the dad's buffer, at j and n + j.
+__global__ void k_xo_query(const uint64_t* __restrict__ moff, const uint64_t* __restrict__ doff,
+                           const int32_t* __restrict__ mum, const int32_t* __restrict__ dad,
+                           const uint64_t* __restrict__ p, const uint64_t* __restrict__ q, uint32_t n,
+                           uint64_t* __restrict__ qb, uint64_t* __restrict__ qp)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    qb[j] = moff[mum[j]];
+    qp[j] = p[j];
+    qb[n + j] = doff[dad[j]];
+    qp[n + j] = q[j];
+}
+
+// Child plans of Sec. 2.3's crossover, one thread per child: the child's
+// length is the mum's with its subtree at p replaced by the dad's subtree
+// at q, or the mum's own when that exceeds the size cap.  len[j] gets the
+// length, with bit 63 set for a capped child.
+__global__ void k_xo_plan(const uint64_t* __restrict__ moff, const uint64_t* __restrict__ doff,
+                          const int32_t* __restrict__ mum, const int32_t* __restrict__ dad,
+                          const uint64_t* __restrict__ p, const uint64_t* __restrict__ q,
+                          const uint64_t* __restrict__ ends, uint32_t n, uint64_t cap, XoPlan* __restrict__ plan,
+                          uint64_t* __restrict__ len)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    XoPlan x;
+    const uint64_t m0 = moff[mum[j]], nm = moff[mum[j] + 1] - m0;
+    x.mum_off = m0;
+    x.dad_off = doff[dad[j]];
+    x.p = p[j];
+    x.ep = ends[j];
+    x.q = q[j];
+    x.eq = ends[n + j];
+    const uint64_t l = nm - (x.ep - x.p + 1) + (x.eq - x.q + 1);
+    x.copy_mum = l > cap ? 1u : 0u;
+    x.child_len = x.copy_mum ? nm : l;
+    x.child_off = 0;
+    x.pad = 0;
+    plan[j] = x;
+    len[j] = x.child_len | ((uint64_t)x.copy_mum << 63);
+}
+
+// One block: the children's offsets (exclusive scan of the lengths in
+// off[0, n), in place; off[n] the total), sum[0] the number capped and
+// sum[1] the longest child.
+__global__ __launch_bounds__(1024) void k_xo_offsets(uint64_t* __restrict__ off, uint32_t n, uint64_t* __restrict__ sum)
+{
+    __shared__ uint64_t part[1024];
+    __shared__ unsigned long long s_max;
+    __shared__ uint32_t s_capped;
+    const uint32_t t = threadIdx.x;
+    if (t == 0) {
+        s_max = 0;
+        s_capped = 0;
+    }
+    const uint32_t per = (n + 1023u) / 1024u;
+    const uint32_t j0 = t * per < n ? t * per : n, j1 = j0 + per < n ? j0 + per : n;
+    uint64_t mine = 0, mx = 0;
+    uint32_t capped = 0;
+    for (uint32_t j = j0; j < j1; j++) {
+        const uint64_t v = off[j], l = v & ~(1ull << 63);
+        mine += l;
+        mx = l > mx ? l : mx;
+        capped += (uint32_t)(v >> 63);
+    }
+    part[t] = mine;
+    __syncthreads();
+    atomicMax(&s_max, (unsigned long long)mx);
+    atomicAdd(&s_capped, capped);
+    for (uint32_t d = 1; d < 1024; d <<= 1) {
+        const uint64_t v = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint64_t at = part[t] - mine;
+    for (uint32_t j = j0; j < j1; j++) {
+        const uint64_t l = off[j] & ~(1ull << 63);
+        off[j] = at;
+        at += l;
+    }
+    if (t == 1023) off[n] = part[1023];
+    if (t == 0) {
+        sum[0] = s_capped;
+        sum[1] = s_max;
+    }
 }
 
 // ------------------------------------------------------ selection (Table 1)
@@ -942,11 +1069,11 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_seg_build(const ChunkIn* ch, const ChunkSegs* cg, uint32_t n, uint32_t seg_len, SegIn* seg,
-                            hipStream_t s)
+hipError_t launch_seg_build(const ChunkIn* ch, const ChunkSegs* cg, uint32_t n, uint32_t seg_len, uint32_t head,
+                            SegIn* seg, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_build, dim3(n), dim3(64), 0, s, ch, cg, n, seg_len, seg);
+    hipLaunchKernelGGL(k_seg_build, dim3(n), dim3(64), 0, s, ch, cg, n, seg_len, head, seg);
     return hipGetLastError();
 }
 
@@ -1053,11 +1180,31 @@ hipError_t launch_subtree_end(const uint8_t* buf, const uint64_t* base, const ui
     return hipGetLastError();
 }
 
-hipError_t launch_xo_copy(const uint8_t* mums, const uint8_t* dads, const XoPlan* plan, uint32_t n,
-                          uint64_t max_child, uint8_t* dst, hipStream_t s)
+hipError_t launch_xo_copy(const uint8_t* mums, const uint8_t* dads, const XoPlan* plan, const uint64_t* off,
+                          uint32_t n, uint64_t max_child, uint8_t* dst, hipStream_t s)
 {
     if (n == 0 || max_child == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_xo_copy, dim3(cdiv(max_child, 4096), n), dim3(256), 0, s, mums, dads, plan, n, dst);
+    hipLaunchKernelGGL(k_xo_copy, dim3(cdiv(max_child, 4096), n), dim3(256), 0, s, mums, dads, plan, off, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_xo_query(const uint64_t* moff, const uint64_t* doff, const int32_t* mum, const int32_t* dad,
+                           const uint64_t* p, const uint64_t* q, uint32_t n, uint64_t* qb, uint64_t* qp, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_xo_query, dim3(cdiv(n, 256)), dim3(256), 0, s, moff, doff, mum, dad, p, q, n, qb, qp);
+    return hipGetLastError();
+}
+
+hipError_t launch_xo_plan(const uint64_t* moff, const uint64_t* doff, const int32_t* mum, const int32_t* dad,
+                          const uint64_t* p, const uint64_t* q, const uint64_t* ends, uint32_t n, uint64_t cap,
+                          XoPlan* plan, uint64_t* off, uint64_t* sum, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_xo_plan, dim3(cdiv(n, 256)), dim3(256), 0, s, moff, doff, mum, dad, p, q, ends, n, cap, plan, off);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_xo_offsets, dim3(1), dim3(1024), 0, s, off, n, sum);
     return hipGetLastError();
 }
 

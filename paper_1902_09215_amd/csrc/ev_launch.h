@@ -6,8 +6,8 @@
 
 namespace ev {
 hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
-hipError_t launch_seg_build(const ChunkIn* ch, const ChunkSegs* cg, uint32_t n, uint32_t seg_len, SegIn* seg,
-                            hipStream_t s);
+hipError_t launch_seg_build(const ChunkIn* ch, const ChunkSegs* cg, uint32_t n, uint32_t seg_len, uint32_t head,
+                            SegIn* seg, hipStream_t s);
 hipError_t launch_seg_fn(const uint8_t* seq, const SegIn* segs, uint32_t n, SegFn* out, uint32_t max_tok,
                          hipStream_t s);
 hipError_t launch_seg_scan(const ChunkSegs* cseg, uint32_t n, const SegFn* fn, SegStart* st, ChunkStat* cstat,
@@ -33,8 +33,13 @@ hipError_t launch_fitness(const uint64_t* rows, const float* y, int32_t N, uint3
                           hipStream_t s);
 hipError_t launch_subtree_end(const uint8_t* buf, const uint64_t* base, const uint64_t* pos, uint32_t n,
                               uint64_t* end_out, hipStream_t s);
-hipError_t launch_xo_copy(const uint8_t* mums, const uint8_t* dads, const XoPlan* plan, uint32_t n,
-                          uint64_t max_child, uint8_t* dst, hipStream_t s);
+hipError_t launch_xo_copy(const uint8_t* mums, const uint8_t* dads, const XoPlan* plan, const uint64_t* off,
+                          uint32_t n, uint64_t max_child, uint8_t* dst, hipStream_t s);
+hipError_t launch_xo_query(const uint64_t* moff, const uint64_t* doff, const int32_t* mum, const int32_t* dad,
+                           const uint64_t* p, const uint64_t* q, uint32_t n, uint64_t* qb, uint64_t* qp, hipStream_t s);
+hipError_t launch_xo_plan(const uint64_t* moff, const uint64_t* doff, const int32_t* mum, const int32_t* dad,
+                          const uint64_t* p, const uint64_t* q, const uint64_t* ends, uint32_t n, uint64_t cap,
+                          XoPlan* plan, uint64_t* off, uint64_t* sum, hipStream_t s);
 hipError_t launch_select(const float* fit, const uint64_t* off, uint32_t M, int32_t k, uint64_t seed, uint64_t gen,
                          int32_t* mum, int32_t* dad, uint64_t* p, uint64_t* q, hipStream_t s);
 }  // namespace ev

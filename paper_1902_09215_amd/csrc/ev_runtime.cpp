@@ -208,30 +208,64 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
     void *d_seg = nullptr, *d_cseg = nullptr, *d_fn = nullptr, *d_st = nullptr, *d_cnt = nullptr, *d_stat = nullptr,
          *d_cb = nullptr, *d_fe = nullptr, *d_scode = nullptr, *d_sfrag = nullptr, *d_err = nullptr, *d_ch = nullptr;
     ev_status st = EV_OK;
+    // also frees a skeleton not yet handed to a level
     auto cleanup = [&]() {
         for (void** p : {&d_seg, &d_cseg, &d_fn, &d_st, &d_cnt, &d_stat, &d_cb, &d_fe, &d_scode, &d_sfrag, &d_err, &d_ch}) {
             dev_free(c, *p);
             *p = nullptr;
         }
+        if (cur_owned) dev_free(c, cur);
+        cur_owned = false;
     };
     auto realloc = [&](void** p, size_t bytes) -> ev_status {
         dev_free(c, *p);
         *p = nullptr;
         return dev_alloc(c, bytes, p);
     };
+    // validator flags of every level, two words each (flags, first failing
+    // segment), read back with the next level's counts or after the last
+    // level, so that validation costs no wait of its own
+    constexpr int MAX_LEVELS = 64;
+    uint32_t verr[2] = {0, 0};
+    {
+        auto& e0 = W.err0;
+        e0.resize(2 * (MAX_LEVELS + 1));
+        for (size_t i = 0; i < e0.size(); i += 2) e0[i] = 0, e0[i + 1] = UINT32_MAX;
+        if ((st = dev_alloc(c, e0.size() * 4, &d_err)) || (st = put(x, d_err, e0.data(), e0.size() * 4))) {
+            cleanup();
+            return st;
+        }
+    }
+    // the failure a level's validation found: chunk and tree of the segment
+    auto code_error = [&](int lv, const uint32_t* e, const std::vector<ChunkIn>& lch, const std::vector<ChunkSegs>& lcg,
+                          const std::vector<uint64_t>& lrs0) -> ev_status {
+        uint32_t sj = 0;
+        for (uint32_t lo = 0, hi = (uint32_t)lcg.size(); lo < hi;) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (lcg[mid].first <= e[1]) { sj = mid; lo = mid + 1; } else { hi = mid; }
+        }
+        const uint32_t t = lch[sj].tree;
+        return fail(EV_EDEVICE,
+                    "internal: malformed code stream at level %d (flags %u, tree %u of %u tokens, chunk at token %llu "
+                    "of its level, segment %u)",
+                    lv, e[0], t, (unsigned)lch[sj].len, (unsigned long long)(lch[sj].start - lrs0[t]), e[1]);
+    };
     uint32_t n_seg = 0;
     auto& cg = W.cg;  // per chunk of the level: its first segment and count
     // count pass over a level's chunks: per-chunk totals in cs.  Segments
     // are 256 tokens at level 0 and 64 at the skeleton levels, which have
-    // few tokens and need the extra parallelism.
+    // few tokens and need the extra parallelism; a chunk's first segment,
+    // which also emits the chunk's final flush, is a quarter of that.
     auto count = [&](const std::vector<ChunkIn>& ch, std::vector<ChunkStat>& cs) -> ev_status {
         const uint32_t n = (uint32_t)ch.size();
         const uint32_t seg_len = level == 0 ? SEG_TOKENS : SEG_TOKENS / 4;
+        const uint32_t head = seg_len / 4;
         cg.resize(n);
         uint64_t ns = 0;
         for (uint32_t j = 0; j < n; j++) {
             cg[j].first = (uint32_t)ns;
-            cg[j].n_seg = (ch[j].len + seg_len - 1) / seg_len;
+            const uint32_t len = ch[j].len;
+            cg[j].n_seg = len <= head ? 1u : 1u + (len - head + seg_len - 1) / seg_len;
             ns += cg[j].n_seg;
         }
         if (ns > 0xFFFFFFF0ull) return fail(EV_ECAP, "too many structure segments");
@@ -245,18 +279,24 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         cs.resize(n);
         if ((e = put(x, d_ch, ch.data(), n * sizeof(ChunkIn))) || (e = put(x, d_cseg, cg.data(), n * sizeof(ChunkSegs))))
             return e;
-        HIPCHK(launch_seg_build((ChunkIn*)d_ch, (ChunkSegs*)d_cseg, n, seg_len, (SegIn*)d_seg, s));
+        HIPCHK(launch_seg_build((ChunkIn*)d_ch, (ChunkSegs*)d_cseg, n, seg_len, head, (SegIn*)d_seg, s));
         HIPCHK(launch_seg_fn(cur, (SegIn*)d_seg, n_seg, (SegFn*)d_fn, level == 0 ? TOK_X : TOK_REF, s));
         HIPCHK(launch_seg_scan((ChunkSegs*)d_cseg, n, (SegFn*)d_fn, (SegStart*)d_st, (ChunkStat*)d_stat, s));
         HIPCHK(launch_seg_count(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (SegCount*)d_cnt, s));
         HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, n, (SegCount*)d_cnt, (ChunkStat*)d_stat, nullptr, nullptr, nullptr,
                                 nullptr, s));
         if ((e = get(x, cs.data(), d_stat, n * sizeof(ChunkStat)))) return e;
+        if (level > 0 && (e = get(x, verr, (uint32_t*)d_err + 2 * (level - 1), 8))) return e;
         return sync(x);
     };
 
     for (;;) {
         const uint64_t C = level == 0 ? C0 : C1;
+        if (level > 0) {  // the previous level's chunks, for its validation's report
+            std::swap(W.ch, W.ch_prev);
+            std::swap(W.cg, W.cg_prev);
+            std::swap(W.rs0, W.rs0_prev);
+        }
         auto& ch = W.ch;
         ch.clear();
         for (int32_t t = 0; t < M; t++) {
@@ -279,88 +319,88 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         if (ch.empty()) break;
         auto& cs = W.cs;
         if ((st = count(ch, cs)) != EV_OK) { cleanup(); return st; }
-
-        if (level == 0) {
-            // Sec. 2.2 word: every token fills one open slot and a function
-            // opens two; a tree is valid iff a slot is open before each token
-            // and none after the last.
-            auto& open = W.open_cnt;
-            auto& ok = W.ok;
-            open.assign(M, 1);
-            ok.assign(M, 1);
-            for (size_t j = 0; j < ch.size(); j++) {
-                const uint32_t t = ch[j].tree;
-                if (cs[j].bad || open[t] + cs[j].minpref < 1) ok[t] = 0;
-                open[t] += cs[j].net;
-            }
-            for (int32_t t = 0; t < M; t++) {
-                if (!ok[t] || open[t] != 0) {
-                    cleanup();
-                    if (bad_tree) *bad_tree = t;
-                    return fail(EV_EMALFORMED, "tree %d is not a valid prefix tree", t);
-                }
-            }
+        if (level > 0 && verr[0]) {
+            cleanup();
+            return code_error(level - 1, verr, W.ch_prev, W.cg_prev, W.rs0_prev);
         }
 
         const uint32_t n = (uint32_t)ch.size();
         auto& rs0 = W.rs0;
         rs0 = rs;
 
-        // slot numbering (global over the level's chunks, in sequence order)
-        // and the split of the work items between the two kernels
+        // One pass over the chunks in sequence order (a tree's chunks are
+        // adjacent): at level 0 the trees' validity (Sec. 2.2: every token
+        // fills one open slot and a function opens two; a tree is valid iff
+        // a slot is open before each token and none after the last), the
+        // slot, fragment and code numbering, the input slots (the k-th REF
+        // of a level is the previous level's slot k) and the work items'
+        // length buckets.
         auto& out_end = W.out_end;
         auto& frag_end = W.frag_end;
         auto& code_begin = W.code_begin;
-        auto& fast = W.fast;
+        auto& in_end = W.in_end;
         auto& tree_first = W.tree_first;
         auto& tree_last = W.tree_last;
-        out_end.assign(n, 0);
-        frag_end.assign(n, 0);
-        code_begin.assign(n, ~0ull);
-        fast.assign(n, 0);
+        out_end.resize(n);
+        frag_end.resize(n);
+        code_begin.resize(n);
+        in_end.resize(n);
         tree_first.assign(M, UINT32_MAX);
-        tree_last.assign(M, 0);
-        uint64_t so = 0, sf = 0, sc = 0, tokens = 0;
+        tree_last.resize(M);
+        const bool run_items = c->use_run;
+        const uint64_t prev_out = pl.levels.empty() ? 0 : pl.levels.back().n_out;
+        // work items go longest first, for the balance of the kernels'
+        // dynamic work queues: a stable counting sort on the length's bit
+        // count (the order inside a power of two does not matter)
+        auto bucket = [](uint32_t len) { return len ? (uint32_t)__builtin_clz(len) : 32u; };  // 0: longest
+        uint32_t at[34] = {};
+        uint64_t so = 0, sf = 0, sc = 0, tokens = 0, in_run = 0, max_stack = pl.max_stack;
         uint32_t max_m = 0, slab_top = 0;
+        int64_t open = 0;
+        bool ok = true, consistent = true;
+        int32_t t_cur = -1;
+        auto tree_valid = [&]() { return level > 0 || t_cur < 0 || (ok && open == 0); };
         for (uint32_t j = 0; j < n; j++) {
+            const ChunkStat& k = cs[j];
             const uint32_t t = ch[j].tree;
-            if (tree_first[t] == UINT32_MAX) tree_first[t] = j;
+            if ((int32_t)t != t_cur) {
+                if (!tree_valid()) break;
+                t_cur = (int32_t)t;
+                tree_first[t] = j;
+                in_run = ref_base[t];
+                open = 1;
+                ok = true;
+            }
             tree_last[t] = j;
-            so += cs[j].n_out;
-            sf += cs[j].n_frag;
+            if (k.bad || open + k.minpref < 1) ok = false;
+            open += k.net;
+            so += k.n_out;
+            sf += k.n_frag;
             out_end[j] = so;
             frag_end[j] = sf;
             tokens += ch[j].len;
-            pl.max_stack = std::max<uint64_t>(pl.max_stack, cs[j].maxtop + 1);
-            fast[j] = c->use_run;
-            if (fast[j]) {
+            in_run += k.n_in;
+            in_end[j] = (uint32_t)in_run;
+            consistent &= in_run <= prev_out && in_run >= k.n_in;
+            max_stack = std::max<uint64_t>(max_stack, k.maxtop + 1);
+            if (run_items) {
                 code_begin[j] = sc;
-                sc += cs[j].n_codes;
-                slab_top = std::max(slab_top, cs[j].maxtop);
+                sc += k.n_codes;
+                slab_top = std::max(slab_top, k.maxtop);
             } else {
-                max_m = std::max(max_m, cs[j].max_m);
+                code_begin[j] = ~0ull;
+                max_m = std::max(max_m, k.max_m);
             }
+            at[bucket(ch[j].len) + 1]++;
         }
+        if (!tree_valid()) {
+            cleanup();
+            if (bad_tree) *bad_tree = t_cur;
+            return fail(EV_EMALFORMED, "tree %d is not a valid prefix tree", t_cur);
+        }
+        pl.max_stack = max_stack;
         if (so > 0xFFFFFFF0ull) { cleanup(); return fail(EV_ECAP, "too many intermediate results"); }
-
-        // input slots: the k-th REF of this level is the previous level's slot k
-        auto& ec = W.ec;
-        ec.assign(n, EvalChunk{});
-        for (int32_t t = 0; t < M; t++) {
-            if (tree_first[t] == UINT32_MAX) continue;
-            uint64_t in_run = ref_base[t];
-            for (uint32_t j = tree_first[t]; j <= tree_last[t]; j++) {
-                in_run += cs[j].n_in;
-                ec[j] = EvalChunk{ch[j].start, ch[j].len, (uint32_t)in_run, (uint32_t)out_end[j], (uint32_t)t, 0, 0};
-            }
-        }
-        const uint64_t prev_out = pl.levels.empty() ? 0 : pl.levels.back().n_out;
-        for (uint32_t j = 0; j < n; j++) {
-            if (ec[j].in_end > prev_out || (uint64_t)ec[j].in_end < cs[j].n_in) {
-                cleanup();
-                return fail(EV_EDEVICE, "inconsistent split plan at level %d", level);
-            }
-        }
+        if (!consistent) { cleanup(); return fail(EV_EDEVICE, "inconsistent split plan at level %d", level); }
 
         Level L;
         L.seq = cur;
@@ -374,34 +414,34 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         L.slab_entries = slab_top + 1 > EV_VSTACK_ENTRIES - EV_VHALF / 2 ? slab_top + EV_VHALF : 0;
         pl.chunks_total += n;
         pl.slots_total += so;
+        for (int k = 0; k < 33; k++) at[k + 1] += at[k];
+        const uint32_t n_run = run_items ? n : 0, n_slow = run_items ? 0 : n;
         auto& slow = W.slow;
-        auto& run = W.run;
-        slow.clear();
-        run.clear();
+        auto& rc = W.rc;
+        slow.resize(n_slow);
+        rc.resize(n_run);
         for (uint32_t j = 0; j < n; j++) {
-            if (fast[j]) run.push_back({ec[j].len, RunChunk{code_begin[j], ec[j].in_end, ec[j].out_end}});
-            else slow.push_back(ec[j]);
+            const uint32_t i = at[bucket(ch[j].len)]++;
+            if (run_items)
+                rc[i] = RunChunk{code_begin[j], in_end[j], (uint32_t)out_end[j]};
+            else
+                slow[i] = EvalChunk{ch[j].start, ch[j].len, in_end[j], (uint32_t)out_end[j], ch[j].tree, 0, 0};
         }
-        std::stable_sort(slow.begin(), slow.end(), [](const EvalChunk& a, const EvalChunk& b) { return a.len > b.len; });
-        std::stable_sort(run.begin(), run.end(), [](const std::pair<uint32_t, RunChunk>& a,
-                                                    const std::pair<uint32_t, RunChunk>& b) { return a.first > b.first; });
-        L.n_chunks = (uint32_t)slow.size();
-        L.n_run = (uint32_t)run.size();
+        L.n_chunks = n_slow;
+        L.n_run = n_run;
         pl.levels.push_back(L);  // owns what is allocated below, freed with the plan
         Level& LL = pl.levels.back();
         cur_owned = false;
-        if (!slow.empty()) {
+        if (n_slow) {
             if ((st = dev_alloc(c, slow.size() * sizeof(EvalChunk), (void**)&LL.d_chunks)) != EV_OK) { cleanup(); return st; }
             if ((st = put(x, LL.d_chunks, slow.data(), slow.size() * sizeof(EvalChunk))) != EV_OK) { cleanup(); return st; }
         }
-        if (!run.empty()) {
-            auto& rc = W.rc;
-            rc.resize(run.size());
-            for (size_t i = 0; i < run.size(); i++) rc[i] = run[i].second;
+        if (n_run) {
             if ((st = dev_alloc(c, rc.size() * sizeof(RunChunk), (void**)&LL.d_run)) != EV_OK) { cleanup(); return st; }
             if ((st = dev_alloc(c, sc * 4 + 512, (void**)&LL.codes)) != EV_OK) { cleanup(); return st; }
             if ((st = put(x, LL.d_run, rc.data(), rc.size() * sizeof(RunChunk))) != EV_OK) { cleanup(); return st; }
-            // the interpreter reads up to 192 bytes past a stream's last code block
+            // the interpreter reads up to 192 bytes past a stream's last code
+            // block, the validator up to 28
             HIPCHK(hipMemsetAsync((uint8_t*)LL.codes + sc * 4, 0, 512, s));
         }
 
@@ -430,17 +470,11 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         uint8_t* d_next = nullptr;
         if (any && (st = dev_alloc(c, sf + 64, (void**)&d_next)) != EV_OK) { cleanup(); return st; }
         if (any) HIPCHK(hipMemsetAsync(d_next, 0xFF, sf + 64, s));
-        if (any || !run.empty()) {
+        if (any || n_run) {
             if ((st = realloc(&d_cb, n * sizeof(uint64_t))) || (st = realloc(&d_fe, n * sizeof(uint64_t))) ||
                 (st = realloc(&d_scode, n_seg * sizeof(uint64_t))) || (st = realloc(&d_sfrag, n_seg * sizeof(uint64_t))) ||
-                (st = realloc(&d_err, 8))) {
-                dev_free(c, d_next);
-                cleanup();
-                return st;
-            }
-            uint32_t err[2] = {0, UINT32_MAX};
-            if ((st = put(x, d_cb, code_begin.data(), n * sizeof(uint64_t))) || (st = put(x, d_fe, frag_end.data(), n * sizeof(uint64_t))) ||
-                (st = put(x, d_err, err, 8))) {
+                (st = put(x, d_cb, code_begin.data(), n * sizeof(uint64_t))) ||
+                (st = put(x, d_fe, frag_end.data(), n * sizeof(uint64_t)))) {
                 dev_free(c, d_next);
                 cleanup();
                 return st;
@@ -448,38 +482,27 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, n, (SegCount*)d_cnt, (ChunkStat*)d_stat, (uint64_t*)d_cb,
                                     (uint64_t*)d_fe, (uint64_t*)d_scode, (uint64_t*)d_sfrag, s));
             HIPCHK(launch_seg_emit(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode, (uint64_t*)d_sfrag,
-                                   d_next, run.empty() ? nullptr : LL.codes, s));
-            if (!run.empty())
+                                   d_next, n_run ? LL.codes : nullptr, s));
+            if (n_run)
                 HIPCHK(launch_seg_check(LL.codes, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode,
-                                        (SegCount*)d_cnt, LL.slab_entries, (uint32_t*)d_err, s));
-            if ((st = get(x, err, d_err, 8)) || (st = sync(x))) {
-                dev_free(c, d_next);
+                                        (SegCount*)d_cnt, LL.slab_entries, (uint32_t*)d_err + 2 * level, s));
+        }
+        if (!any) {
+            // the last level: its validation must pass before the plan is used
+            if ((st = get(x, verr, (uint32_t*)d_err + 2 * level, 8)) || (st = sync(x))) {
                 cleanup();
                 return st;
             }
-            if (err[0]) {
-                dev_free(c, d_next);
+            if (verr[0]) {
                 cleanup();
-                // the chunk holding the failing segment
-                uint32_t sj = 0;
-                for (uint32_t lo = 0, hi = (uint32_t)cg.size(); lo < hi;) {
-                    const uint32_t mid = (lo + hi) / 2;
-                    if (cg[mid].first <= err[1]) { sj = mid; lo = mid + 1; } else { hi = mid; }
-                }
-                const uint32_t t = ch[sj].tree;
-                return fail(EV_EDEVICE,
-                            "internal: malformed code stream at level %d (flags %u, tree %u of %u tokens, chunk at "
-                            "token %llu of its level, segment %u)",
-                            level, err[0], t, (unsigned)ch[sj].len, (unsigned long long)(ch[sj].start - rs0[t]),
-                            err[1]);
+                return code_error(level, verr, ch, cg, rs0);
             }
+            break;
         }
-        if (!any) break;
         cur = d_next;
         cur_owned = true;
         level++;
-        if (level > 64) {
-            dev_free(c, cur);
+        if (level > MAX_LEVELS) {
             cleanup();
             int32_t t = 0;
             while (t < M && !active[t]) t++;
@@ -495,18 +518,22 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
 
 // Make a population from device bytes (takes ownership of d_bytes, also on
 // failure).
-ev_status pop_build(ev_ctx* c, Exec& x, uint8_t* d_bytes, const std::vector<uint64_t>& h_off, Pop** out, int32_t* bad)
+ev_status pop_build(ev_ctx* c, Exec& x, uint8_t* d_bytes, const std::vector<uint64_t>& h_off, Pop** out, int32_t* bad,
+                    uint64_t* d_off)
 {
     *out = nullptr;
     Pop* P = new Pop();
     P->d_bytes = d_bytes;
+    P->d_off = d_off;
     P->h_off = h_off;
     P->M = (int32_t)h_off.size() - 1;
     P->total = h_off.back();
     ev_status st;
-    if ((st = dev_alloc(c, h_off.size() * sizeof(uint64_t), (void**)&P->d_off)) != EV_OK) { pop_free(c, P); return st; }
+    if (!d_off) {
+        if ((st = dev_alloc(c, h_off.size() * sizeof(uint64_t), (void**)&P->d_off)) != EV_OK) { pop_free(c, P); return st; }
+        if ((st = put(x, P->d_off, h_off.data(), h_off.size() * sizeof(uint64_t))) != EV_OK) { pop_free(c, P); return st; }
+    }
     if ((st = dev_alloc(c, (size_t)std::max(1, P->M) * sizeof(float), (void**)&P->d_fit)) != EV_OK) { pop_free(c, P); return st; }
-    if ((st = put(x, P->d_off, h_off.data(), h_off.size() * sizeof(uint64_t))) != EV_OK) { pop_free(c, P); return st; }
     if ((st = plan_build(c, x, P, bad)) != EV_OK) { pop_free(c, P); return st; }
     *out = P;
     return EV_OK;
@@ -820,10 +847,73 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
 // ----------------------------------------------------------- crossover
 
 // Children from explicit parents and points; all arrays on the host.
+// Children of Sec. 2.3's crossover from parent indices and points already on
+// the device (d_mum, d_dad, d_p, d_q; n each, valid for the parents): the
+// subtree ends, child lengths and offsets are found on the device, so the
+// host waits once, for the offsets it needs to size the new buffer.
+ev_status crossover_build_dev(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const int32_t* d_mum, const int32_t* d_dad,
+                              const uint64_t* d_p, const uint64_t* d_q, int32_t n, uint64_t cap, Pop** out,
+                              int32_t* n_capped)
+{
+    hipStream_t s = x.stream;
+    const size_t qn = std::max<size_t>(1, 2 * (size_t)n);
+    void *d_b = nullptr, *d_qp = nullptr, *d_e = nullptr, *d_plan = nullptr, *d_sum = nullptr;
+    uint64_t* d_off = nullptr;
+    auto cleanup = [&]() {
+        for (void* p : {d_b, d_qp, d_e, d_plan, d_sum}) dev_free(c, p);
+    };
+    ev_status st;
+    if ((st = dev_alloc(c, qn * 8, &d_b)) || (st = dev_alloc(c, qn * 8, &d_qp)) || (st = dev_alloc(c, qn * 8, &d_e)) ||
+        (st = dev_alloc(c, std::max<size_t>(1, n) * sizeof(XoPlan), &d_plan)) || (st = dev_alloc(c, 16, &d_sum)) ||
+        (st = dev_alloc(c, ((size_t)n + 1) * 8, (void**)&d_off))) {
+        cleanup();
+        dev_free(c, d_off);
+        return st;
+    }
+    std::vector<uint64_t> off((size_t)n + 1, 0);
+    uint64_t sum[2] = {0, 0};
+    if (n > 0) {
+        uint64_t* qb = (uint64_t*)d_b;
+        uint64_t* qp = (uint64_t*)d_qp;
+        uint64_t* ends = (uint64_t*)d_e;
+        HIPCHK(launch_xo_query(mums->d_off, dads->d_off, d_mum, d_dad, d_p, d_q, (uint32_t)n, qb, qp, s));
+        if (mums == dads) {
+            HIPCHK(launch_subtree_end(mums->d_bytes, qb, qp, 2u * (uint32_t)n, ends, s));
+        } else {
+            HIPCHK(launch_subtree_end(mums->d_bytes, qb, qp, (uint32_t)n, ends, s));
+            HIPCHK(launch_subtree_end(dads->d_bytes, qb + n, qp + n, (uint32_t)n, ends + n, s));
+        }
+        HIPCHK(launch_xo_plan(mums->d_off, dads->d_off, d_mum, d_dad, d_p, d_q, ends, (uint32_t)n, cap, (XoPlan*)d_plan,
+                              d_off, (uint64_t*)d_sum, s));
+        if ((st = get(x, off.data(), d_off, ((size_t)n + 1) * 8)) || (st = get(x, sum, d_sum, 16)) || (st = sync(x))) {
+            cleanup();
+            dev_free(c, d_off);
+            return st;
+        }
+    } else if ((st = put(x, d_off, off.data(), 8)) != EV_OK) {
+        cleanup();
+        dev_free(c, d_off);
+        return st;
+    }
+    uint8_t* d_child = nullptr;
+    if ((st = dev_alloc(c, off[n] + EV_POP_PAD, (void**)&d_child)) != EV_OK) {
+        cleanup();
+        dev_free(c, d_off);
+        return st;
+    }
+    HIPCHK(launch_xo_copy(mums->d_bytes, dads->d_bytes, (XoPlan*)d_plan, d_off, (uint32_t)n, sum[1], d_child, s));
+    HIPCHK(hipMemsetAsync(d_child + off[n], 0xFF, EV_POP_PAD, s));
+    // the scratch goes back to the cache while the copy may still run: every
+    // later use of it is ordered after the copy on the context's one stream
+    cleanup();
+    if (n_capped) *n_capped = (int32_t)sum[0];
+    return pop_build(c, x, d_child, off, out, nullptr, d_off);
+}
+
+// The same from host arrays, checked against the parents first.
 ev_status crossover_build(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const int32_t* mum, const int32_t* dad,
                           const uint64_t* p, const uint64_t* q, int32_t n, uint64_t cap, Pop** out, int32_t* n_capped)
 {
-    hipStream_t s = x.stream;
     for (int32_t j = 0; j < n; j++) {
         if (mum[j] < 0 || mum[j] >= mums->M || dad[j] < 0 || dad[j] >= dads->M)
             return fail(EV_EINVAL, "child %d: parent index out of range", j);
@@ -831,81 +921,22 @@ ev_status crossover_build(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const int32_
         const uint64_t nd = dads->h_off[dad[j] + 1] - dads->h_off[dad[j]];
         if (p[j] >= nm || q[j] >= nd) return fail(EV_EINVAL, "child %d: crossover point out of range", j);
     }
-    std::vector<uint64_t> qb(2 * (size_t)n), qp(2 * (size_t)n);
-    for (int32_t j = 0; j < n; j++) {
-        qb[j] = mums->h_off[mum[j]];
-        qp[j] = p[j];
-        qb[n + j] = dads->h_off[dad[j]];
-        qp[n + j] = q[j];
-    }
-    void *d_b = nullptr, *d_p = nullptr, *d_e = nullptr, *d_plan = nullptr;
-    auto cleanup = [&]() { dev_free(c, d_b); dev_free(c, d_p); dev_free(c, d_e); dev_free(c, d_plan); };
-    ev_status st;
-    const size_t qn = std::max<size_t>(1, 2 * (size_t)n);
-    if ((st = dev_alloc(c, qn * 8, &d_b)) || (st = dev_alloc(c, qn * 8, &d_p)) || (st = dev_alloc(c, qn * 8, &d_e))) {
-        cleanup();
+    void* d_in = nullptr;
+    const size_t m = std::max<size_t>(1, n);
+    ev_status st = dev_alloc(c, m * 24, &d_in);
+    if (st != EV_OK) return st;
+    int32_t* d_mum = (int32_t*)d_in;
+    int32_t* d_dad = d_mum + m;
+    uint64_t* d_p = (uint64_t*)((char*)d_in + m * 8);
+    uint64_t* d_q = d_p + m;
+    if (n > 0 && ((st = put(x, d_mum, mum, (size_t)n * 4)) || (st = put(x, d_dad, dad, (size_t)n * 4)) ||
+                  (st = put(x, d_p, p, (size_t)n * 8)) || (st = put(x, d_q, q, (size_t)n * 8)))) {
+        dev_free(c, d_in);
         return st;
     }
-    std::vector<uint64_t> ends(2 * (size_t)n);
-    if (n > 0) {
-        if ((st = put(x, d_b, qb.data(), 2 * (size_t)n * 8)) || (st = put(x, d_p, qp.data(), 2 * (size_t)n * 8))) {
-            cleanup();
-            return st;
-        }
-        HIPCHK(launch_subtree_end(mums->d_bytes, (uint64_t*)d_b, (uint64_t*)d_p, (uint32_t)n, (uint64_t*)d_e, s));
-        HIPCHK(launch_subtree_end(dads->d_bytes, (uint64_t*)d_b + n, (uint64_t*)d_p + n, (uint32_t)n,
-                                  (uint64_t*)d_e + n, s));
-        if ((st = get(x, ends.data(), d_e, 2 * (size_t)n * 8)) || (st = sync(x))) {
-            cleanup();
-            return st;
-        }
-    }
-    std::vector<XoPlan> plan(n);
-    std::vector<uint64_t> off(n + 1, 0);
-    int32_t capped = 0;
-    uint64_t maxlen = 0;
-    for (int32_t j = 0; j < n; j++) {
-        XoPlan& xp = plan[j];
-        const uint64_t nm = mums->h_off[mum[j] + 1] - mums->h_off[mum[j]];
-        xp.mum_off = mums->h_off[mum[j]];
-        xp.dad_off = dads->h_off[dad[j]];
-        xp.p = p[j];
-        xp.ep = ends[j];
-        xp.q = q[j];
-        xp.eq = ends[n + j];
-        const uint64_t len = nm - (xp.ep - xp.p + 1) + (xp.eq - xp.q + 1);
-        xp.copy_mum = len > cap ? 1u : 0u;
-        if (xp.copy_mum) capped++;
-        xp.child_len = xp.copy_mum ? nm : len;
-        xp.child_off = off[j];
-        xp.pad = 0;
-        off[j + 1] = off[j] + xp.child_len;
-        maxlen = std::max(maxlen, xp.child_len);
-    }
-    uint8_t* d_child = nullptr;
-    if ((st = dev_alloc(c, off[n] + EV_POP_PAD, (void**)&d_child)) != EV_OK) { cleanup(); return st; }
-    if ((st = dev_alloc(c, std::max<size_t>(1, n) * sizeof(XoPlan), &d_plan)) != EV_OK) {
-        dev_free(c, d_child);
-        cleanup();
-        return st;
-    }
-    if (n > 0) {
-        if ((st = put(x, d_plan, plan.data(), (size_t)n * sizeof(XoPlan))) != EV_OK) {
-            dev_free(c, d_child);
-            cleanup();
-            return st;
-        }
-        HIPCHK(launch_xo_copy(mums->d_bytes, dads->d_bytes, (XoPlan*)d_plan, (uint32_t)n, maxlen, d_child, s));
-    }
-    HIPCHK(hipMemsetAsync(d_child + off[n], 0xFF, EV_POP_PAD, s));
-    if ((st = sync(x)) != EV_OK) {
-        dev_free(c, d_child);
-        cleanup();
-        return st;
-    }
-    cleanup();
-    if (n_capped) *n_capped = capped;
-    return pop_build(c, x, d_child, off, out, nullptr);
+    st = crossover_build_dev(c, x, mums, dads, d_mum, d_dad, d_p, d_q, n, cap, out, n_capped);
+    dev_free(c, d_in);
+    return st;
 }
 
 }  // namespace ev
@@ -1202,20 +1233,14 @@ ev_status ev_generation(ev_ctx* c, ev_pop parents, uint64_t seed, uint64_t gen, 
     int32_t* d_dad = d_mum + std::max(1, M);
     uint64_t* d_p = (uint64_t*)((char*)d_sel + (size_t)std::max(1, M) * 8);
     uint64_t* d_q = d_p + std::max(1, M);
-    std::vector<int32_t> mum(M), dad(M);
-    std::vector<uint64_t> p(M), q(M);
     hipError_t e = launch_select(P->d_fit, P->d_off, (uint32_t)M, tournament, seed, gen, d_mum, d_dad, d_p, d_q, c->stream);
-    if (e != hipSuccess) st = hip_fail(e, "selection");
-    if (st == EV_OK) st = get(c->main, mum.data(), d_mum, (size_t)M * 4);
-    if (st == EV_OK) st = get(c->main, dad.data(), d_dad, (size_t)M * 4);
-    if (st == EV_OK) st = get(c->main, p.data(), d_p, (size_t)M * 8);
-    if (st == EV_OK) st = get(c->main, q.data(), d_q, (size_t)M * 8);
-    if (st == EV_OK) st = sync(c->main);
-    else (void)sync(c->main);
-    dev_free(c, d_sel);
-    if (st != EV_OK) return st;
+    if (e != hipSuccess) {
+        dev_free(c, d_sel);
+        return hip_fail(e, "selection");
+    }
     Pop* C = nullptr;
-    st = crossover_build(c, c->main, P, P, mum.data(), dad.data(), p.data(), q.data(), M, size_cap, &C, n_capped);
+    st = crossover_build_dev(c, c->main, P, P, d_mum, d_dad, d_p, d_q, M, size_cap, &C, n_capped);
+    dev_free(c, d_sel);
     if (st != EV_OK) return st;
     *out = pop_register(c, C);
     return EV_OK;

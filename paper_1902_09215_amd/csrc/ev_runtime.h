@@ -73,14 +73,14 @@ struct Pop {
 // (large) buffers are reused instead of freshly mapped and faulted in.
 struct PlanScratch {
     std::vector<uint64_t> rs, rl, prev_len, ref_base, rs0, out_end, frag_end, code_begin;
-    std::vector<int64_t> open_cnt;
-    std::vector<char> active, ok, fast;
-    std::vector<uint32_t> tree_first, tree_last;
-    std::vector<ChunkIn> ch;
-    std::vector<ChunkSegs> cg;
+    std::vector<char> active;
+    std::vector<uint32_t> tree_first, tree_last, in_end;
+    std::vector<ChunkIn> ch, ch_prev;
+    std::vector<ChunkSegs> cg, cg_prev;
+    std::vector<uint64_t> rs0_prev;
+    std::vector<uint32_t> err0;
     std::vector<ChunkStat> cs;
-    std::vector<EvalChunk> ec, slow;
-    std::vector<std::pair<uint32_t, RunChunk>> run;
+    std::vector<EvalChunk> slow;
     std::vector<RunChunk> rc;
 };
 
@@ -164,8 +164,9 @@ ev_status sync(Exec& x);
 void exec_free(ev_ctx* c, Exec& x);
 
 void pop_free(ev_ctx* c, Pop* P);
+// d_off: the offsets already on the device (adopted), or nullptr to upload h_off
 ev_status pop_build(ev_ctx* c, Exec& x, uint8_t* d_bytes, const std::vector<uint64_t>& h_off, Pop** out,
-                    int32_t* bad);
+                    int32_t* bad, uint64_t* d_off = nullptr);
 ev_pop pop_register(ev_ctx* c, Pop* P);
 Pop* pop_get(ev_ctx* c, ev_pop id);
 
@@ -173,6 +174,9 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
 ev_status crossover_build(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const int32_t* mum, const int32_t* dad,
                           const uint64_t* p, const uint64_t* q, int32_t n, uint64_t cap, Pop** out,
                           int32_t* n_capped);
+ev_status crossover_build_dev(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const int32_t* d_mum, const int32_t* d_dad,
+                              const uint64_t* d_p, const uint64_t* d_q, int32_t n, uint64_t cap, Pop** out,
+                              int32_t* n_capped);
 
 void serve_stop(ev_ctx* c);
 
