@@ -202,7 +202,8 @@ ev_status ev_get_plan_info(ev_ctx *ctx, ev_pop pop, ev_plan_info *info);
 
 /* Tuning knobs (0 keeps the current value): chunk = tokens per work item
  * of the split at level 0, chunk_hi = at the skeleton levels (default:
- * the same as chunk), lds_depth = operand-stack entries kept in LDS
+ * twice chunk: a skeleton level is short, and a longer work item there
+ * saves whole levels), lds_depth = operand-stack entries kept in LDS
  * per wave by the general interpreter (64 or 128).  flags:
  * EV_TUNE_NO_REGSTACK runs every work item on the general interpreter
  * instead of the register-stack one.  Plans made afterwards use them;

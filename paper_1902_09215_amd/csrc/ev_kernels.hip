@@ -85,14 +85,24 @@ __device__ __forceinline__ uint32_t norm_base(uint32_t m)
 }
 
 // Handler offset of a code at index `at` (its position is at mod 32): the
-// layout written by gen_interp.py.
+// layout written by gen_interp.py.  Arithmetic only, so that no branch
+// appears around it.
+static_assert(EV_CODE_POS == 32 && EV_CODE_NSTRIDE == 32 && EV_CODE_TSTRIDE == 64, "code layout");
+// tr: 1 at the refill positions 15 and 31, whose handlers are 64 bytes apart
+__device__ __forceinline__ uint32_t code_tr(uint32_t pos) { return ((pos & 15u) + 1u) >> 4; }
+// offset of kind 0's handler at a position
+__device__ __forceinline__ uint32_t code_base(uint32_t pos)
+{
+    const uint32_t hi = pos >> 4;  // second half of the block
+    const uint32_t nb = (pos - hi) * (EV_NK * EV_CODE_NSTRIDE);
+    const uint32_t tb = EV_CODE_TBASE + hi * (EV_NK * EV_CODE_TSTRIDE);
+    const uint32_t mask = 0u - code_tr(pos);
+    return (nb & ~mask) | (tb & mask);
+}
 __device__ __forceinline__ uint32_t code_value(uint64_t at, uint32_t kind)
 {
-    const uint32_t pos = (uint32_t)(at & (EV_CODE_POS - 1));
-    const bool tr = (pos & 15u) == 15u;
-    const uint32_t base = tr ? EV_CODE_TBASE + (pos >> 4) * EV_NK * EV_CODE_TSTRIDE
-                             : (pos - (pos >> 4)) * EV_NK * EV_CODE_NSTRIDE;
-    return base + kind * (tr ? EV_CODE_TSTRIDE : EV_CODE_NSTRIDE);
+    const uint32_t pos = (uint32_t)at & 31u;
+    return code_base(pos) + (kind << (5u + code_tr(pos)));
 }
 
 struct Sink {
@@ -374,36 +384,77 @@ __global__ void k_seg_fn(const uint8_t* __restrict__ seq, const SegIn* __restric
     out[si] = f;
 }
 
-// Per chunk: fold the segment maps in reading order to give every segment
-// its start (cnt, P), and combine the validity counters in token order.
-__global__ void k_seg_scan(const ChunkSegs* __restrict__ cseg, uint32_t n, const SegFn* __restrict__ fn,
-                           SegStart* __restrict__ st, ChunkStat* __restrict__ cstat)
+// Per chunk, one wave: fold the segment maps in reading order (last segment
+// first) to give every segment its start (cnt, P, REFs read before it), and
+// combine the validity counters.  The maps compose as
+//   (a1, b1) then (a2, b2) = (a1 + a2, max(b1 + a2, b2)),
+// so each group of 64 segments is an exclusive scan across the lanes.  The
+// minimum running sum before a token, over token order, is
+//   S + min_k (minpref_k - suffix_k),  S the chunk's sum and suffix_k the sum
+// over segments k.. n-1, which reading order accumulates.
+__global__ __launch_bounds__(64) void k_seg_scan(const ChunkSegs* __restrict__ cseg, uint32_t n,
+                                                 const SegFn* __restrict__ fn, SegStart* __restrict__ st,
+                                                 ChunkStat* __restrict__ cstat)
 {
-    const uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t ci = blockIdx.x;
     if (ci >= n) return;
+    const int lane = (int)threadIdx.x;
     const ChunkSegs cs = cseg[ci];
-    int32_t c = 0;
-    uint32_t P = 0, refs = 0;
-    for (uint32_t k = cs.n_seg; k-- > 0;) {
-        const SegFn f = fn[cs.first + k];
-        st[cs.first + k] = SegStart{(uint32_t)c, P, refs, 0};
-        c = c + f.a > f.b ? c + f.a : f.b;
-        P = f.left_x;
-        refs += f.n_in;
+    constexpr int32_t NONE = INT32_MIN / 2;
+    int32_t c = 0, suf = 0, mmin = INT32_MAX;
+    uint32_t P = 0, refs = 0, bad = 0;
+    for (uint32_t g = 0; g < cs.n_seg; g += 64) {
+        const uint32_t r = g + (uint32_t)lane;
+        const bool in = r < cs.n_seg;
+        const uint32_t k = in ? cs.n_seg - 1 - r : 0;
+        SegFn f = {0, NONE, 0, 0, 0, 0, 0, 0};
+        if (in) f = fn[cs.first + k];
+        int32_t A = f.a, B = f.b, net = f.net;
+        uint32_t nin = f.n_in;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t A0 = __shfl_up(A, d, 64), B0 = __shfl_up(B, d, 64), t0 = __shfl_up(net, d, 64);
+            const uint32_t n0 = __shfl_up(nin, d, 64);
+            if (lane >= d) {
+                B = B0 + A > B ? B0 + A : B;
+                A = A0 + A;
+                net += t0;
+                nin += n0;
+            }
+        }
+        int32_t Ae = __shfl_up(A, 1, 64), Be = __shfl_up(B, 1, 64);
+        uint32_t ne = __shfl_up(nin, 1, 64), Pe = __shfl_up(f.left_x, 1, 64);
+        if (lane == 0) {
+            Ae = 0;
+            Be = NONE;
+            ne = 0;
+            Pe = P;
+        }
+        if (in) {
+            const int32_t cnt = c + Ae > Be ? c + Ae : Be;
+            st[cs.first + k] = SegStart{(uint32_t)cnt, Pe, refs + ne, 0};
+            const int32_t v = f.minpref - (suf + net);
+            mmin = v < mmin ? v : mmin;
+            bad |= f.bad;
+        }
+        const int32_t A63 = __shfl(A, 63, 64), B63 = __shfl(B, 63, 64);
+        c = c + A63 > B63 ? c + A63 : B63;
+        const uint32_t last = (cs.n_seg - g < 64u ? cs.n_seg - g : 64u) - 1u;
+        P = __shfl(f.left_x, (int)last, 64);
+        refs += __shfl(nin, 63, 64);
+        suf += __shfl(net, 63, 64);
     }
-    int32_t S = 0, minp = INT32_MAX;
-    uint32_t bad = 0;
-    for (uint32_t k = 0; k < cs.n_seg; k++) {
-        const SegFn f = fn[cs.first + k];
-        minp = S + f.minpref < minp ? S + f.minpref : minp;
-        S += f.net;
-        bad |= f.bad;
+    for (int d = 32; d > 0; d >>= 1) {
+        const int32_t o = __shfl_xor(mmin, d, 64);
+        mmin = o < mmin ? o : mmin;
+        bad |= __shfl_xor(bad, d, 64);
     }
-    ChunkStat r = {};
-    r.net = S;
-    r.minpref = cs.n_seg ? minp : 0;
-    r.bad = bad;
-    cstat[ci] = r;
+    if (lane == 0) {
+        ChunkStat r = {};
+        r.net = suf;
+        r.minpref = cs.n_seg ? suf + mmin : 0;
+        r.bad = bad;
+        cstat[ci] = r;
+    }
 }
 
 __global__ void k_seg_count(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs, uint32_t n,
@@ -417,49 +468,79 @@ __global__ void k_seg_count(const uint8_t* __restrict__ seq, const SegIn* __rest
     out[si] = SegCount{o.n_codes, o.n_frag, o.n_out, o.n_in, maxtop, 0};
 }
 
-// Per chunk: totals for the plan, and each segment's code and fragment
-// positions once the chunk's own bases are known (second launch).
-__global__ void k_seg_chunk(const ChunkSegs* __restrict__ cseg, uint32_t n, const SegCount* __restrict__ cnt,
-                            ChunkStat* __restrict__ cstat, const uint64_t* __restrict__ code_begin,
-                            const uint64_t* __restrict__ frag_end, uint64_t* __restrict__ seg_code,
-                            uint64_t* __restrict__ seg_frag)
+// Per chunk, one wave: totals for the plan (first launch, no code_begin),
+// or each segment's code and fragment positions once the chunk's own bases
+// are known (second launch).  Codes run in reading order (last segment
+// first); fragments and slots lie in token order, a segment's fragment
+// ending where the next one's begins.
+__global__ __launch_bounds__(64) void k_seg_chunk(const ChunkSegs* __restrict__ cseg, uint32_t n,
+                                                  const SegCount* __restrict__ cnt, ChunkStat* __restrict__ cstat,
+                                                  const uint64_t* __restrict__ code_begin,
+                                                  const uint64_t* __restrict__ frag_end, uint64_t* __restrict__ seg_code,
+                                                  uint64_t* __restrict__ seg_frag)
 {
-    const uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t ci = blockIdx.x;
     if (ci >= n) return;
+    const int lane = (int)threadIdx.x;
     const ChunkSegs cs = cseg[ci];
     if (!code_begin) {
         uint32_t nc = 0, nf = 0, no = 0, ni = 0, mt = 0;
-        for (uint32_t k = 0; k < cs.n_seg; k++) {
-            const SegCount s = cnt[cs.first + k];
-            nc += s.n_codes;
-            nf += s.n_frag;
-            no += s.n_out;
-            ni += s.n_in;
-            mt = s.maxtop > mt ? s.maxtop : mt;
+        for (uint32_t k = (uint32_t)lane; k < cs.n_seg; k += 64) {
+            const SegCount q = cnt[cs.first + k];
+            nc += q.n_codes;
+            nf += q.n_frag;
+            no += q.n_out;
+            ni += q.n_in;
+            mt = q.maxtop > mt ? q.maxtop : mt;
         }
-        ChunkStat r = cstat[ci];
-        r.n_codes = nc;
-        r.n_frag = nf;
-        r.n_out = no;
-        r.n_in = ni;
-        r.maxtop = mt;
-        r.max_m = mt + 1;
-        r.code_out = no;
-        r.code_in = ni;
-        cstat[ci] = r;
+        for (int d = 32; d > 0; d >>= 1) {
+            nc += __shfl_xor(nc, d, 64);
+            nf += __shfl_xor(nf, d, 64);
+            no += __shfl_xor(no, d, 64);
+            ni += __shfl_xor(ni, d, 64);
+            const uint32_t o = __shfl_xor(mt, d, 64);
+            mt = o > mt ? o : mt;
+        }
+        if (lane == 0) {
+            ChunkStat r = cstat[ci];
+            r.n_codes = nc;
+            r.n_frag = nf;
+            r.n_out = no;
+            r.n_in = ni;
+            r.maxtop = mt;
+            r.max_m = mt + 1;
+            r.code_out = no;
+            r.code_in = ni;
+            cstat[ci] = r;
+        }
         return;
     }
-    // codes run in reading order (last segment first); fragments and slots
-    // lie in token order
-    uint64_t at = code_begin[ci];
-    for (uint32_t k = cs.n_seg; k-- > 0;) {
-        seg_code[cs.first + k] = at == ~0ull ? ~0ull : at;
-        if (at != ~0ull) at += cnt[cs.first + k].n_codes;
-    }
-    uint64_t w = frag_end ? frag_end[ci] : 0;
-    for (uint32_t k = cs.n_seg; k-- > 0;) {
-        seg_frag[cs.first + k] = w;
-        w -= cnt[cs.first + k].n_frag;
+    const uint64_t cb = code_begin[ci];
+    uint64_t at = cb, w = frag_end ? frag_end[ci] : 0;
+    for (uint32_t g = 0; g < cs.n_seg; g += 64) {
+        const uint32_t r = g + (uint32_t)lane;
+        const bool in = r < cs.n_seg;
+        const uint32_t k = in ? cs.n_seg - 1 - r : 0;
+        uint64_t c = 0, f = 0;
+        if (in) {
+            c = cnt[cs.first + k].n_codes;
+            f = cnt[cs.first + k].n_frag;
+        }
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t c0 = __shfl_up(c, d, 64), f0 = __shfl_up(f, d, 64);
+            if (lane >= d) {
+                c += c0;
+                f += f0;
+            }
+        }
+        uint64_t ce = __shfl_up(c, 1, 64), fe = __shfl_up(f, 1, 64);
+        if (lane == 0) ce = fe = 0;
+        if (in) {
+            seg_code[cs.first + k] = cb == ~0ull ? ~0ull : at + ce;
+            seg_frag[cs.first + k] = w - fe;
+        }
+        at += __shfl(c, 63, 64);
+        w -= __shfl(f, 63, 64);
     }
 }
 
@@ -512,15 +593,13 @@ __global__ void k_seg_check(const uint32_t* __restrict__ codes, const SegIn* __r
         for (uint32_t j = jlo; j < jend; j++) {
             const uint32_t i = q0 + j - sk;
             const uint32_t v = j >= 2 ? (j == 3 ? cur.w : cur.z) : (j == 1 ? cur.y : cur.x);
-            // decode (selects): handler base and stride of this position
+            // decode: handler base and stride of this position
             const uint32_t pos = (uint32_t)((b + i) & (EV_CODE_POS - 1));
-            const bool tr = (pos & 15u) == 15u;
-            const uint32_t base = tr ? EV_CODE_TBASE + (pos >> 4) * EV_NK * EV_CODE_TSTRIDE
-                                     : (pos - (pos >> 4)) * EV_NK * EV_CODE_NSTRIDE;
-            const uint32_t stride = tr ? EV_CODE_TSTRIDE : EV_CODE_NSTRIDE;
+            const uint32_t sh = 5u + code_tr(pos);  // log2 of the stride
+            const uint32_t base = code_base(pos);
             const uint32_t rel = v - base;
-            const uint32_t k = rel / stride;
-            if (v < base || rel % stride || k >= EV_NK) bad |= 1;
+            const uint32_t k = rel >> sh;
+            if (v < base || (rel & ((1u << sh) - 1u)) || k >= EV_NK) bad |= 1;
             if (ended) bad |= 4;
             if (tail) {
                 // after a FLUSH only the chunk's final slot writes and END may
@@ -1089,7 +1168,7 @@ hipError_t launch_seg_scan(const ChunkSegs* cseg, uint32_t n, const SegFn* fn, S
                            hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_scan, dim3(cdiv(n, 64)), dim3(64), 0, s, cseg, n, fn, st, cstat);
+    hipLaunchKernelGGL(k_seg_scan, dim3(n), dim3(64), 0, s, cseg, n, fn, st, cstat);
     return hipGetLastError();
 }
 
@@ -1106,7 +1185,7 @@ hipError_t launch_seg_chunk(const ChunkSegs* cseg, uint32_t n, const SegCount* c
                             hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_chunk, dim3(cdiv(n, 64)), dim3(64), 0, s, cseg, n, cnt, cstat, code_begin, frag_end,
+    hipLaunchKernelGGL(k_seg_chunk, dim3(n), dim3(64), 0, s, cseg, n, cnt, cstat, code_begin, frag_end,
                        seg_code, seg_frag);
     return hipGetLastError();
 }

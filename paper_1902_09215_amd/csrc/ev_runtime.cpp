@@ -171,8 +171,10 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
     hipStream_t s = x.stream;
     const int32_t M = P->M;
     const uint64_t C0 = c->chunk;
-    // work-item size of the skeleton levels (by default the same as level 0)
-    const uint64_t C1 = c->chunk_hi ? c->chunk_hi : C0;
+    // work-item size of the skeleton levels (by default twice level 0's: a
+    // skeleton level has few tokens, and longer items there end more trees
+    // a level earlier, which saves a level's fixed latency)
+    const uint64_t C1 = c->chunk_hi ? c->chunk_hi : 2 * C0;
     Plan& pl = P->plan;
     pl.chunk = (uint32_t)C0;
     pl.D = c->lds_depth;

@@ -124,7 +124,7 @@ struct ev_ctx {
     bool run_ok = true;   // the register-stack kernel can run here (probed at creation)
     uint32_t* d_flag = nullptr;  // the probe's flag word
     uint32_t chunk = 4096;     // tokens per work item at level 0
-    uint32_t chunk_hi = 0;     // at the skeleton levels (0: the same as chunk)
+    uint32_t chunk_hi = 0;     // at the skeleton levels (0: twice chunk)
     int lds_depth = 64;
 
     ev::Exec main;
