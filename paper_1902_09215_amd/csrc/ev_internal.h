@@ -48,6 +48,40 @@ struct ChunkSegs {
     uint32_t n_seg;
 };
 
+// A tree's part of one level of the split plan (host to device): its range
+// in the level's sequence and where its chunks and segments go.
+struct TreeLvl {
+    uint64_t start, len;  // the tree's tokens at this level
+    uint32_t chunk_first, n_chunks;
+    uint32_t seg_first;   // first segment of its first chunk
+    uint32_t C;           // tokens per chunk (all but the last are full)
+    uint32_t tree;
+    uint32_t ref_base;    // its first input slot: the previous level's slot index
+};
+
+// A tree's totals over its chunks at one level (device to host).
+struct TreeSum {
+    uint64_t n_out, n_frag, n_codes;
+    uint32_t bad;     // 1: not a valid prefix tree (level 0); 2: input slots out of range
+    uint32_t maxtop;  // highest register-stack index of its chunks' codes
+    uint32_t max_m;   // deepest physical stack of its chunks
+    uint32_t pad;
+};
+
+// Per tree id: its bases over the level's chunks (host to device), and the
+// places of its work items in their length buckets: its full chunks (all
+// but the last) take rank_full, rank_full + 1, ... of theirs, its last
+// chunk rank_last of its own.
+struct TreeBase {
+    uint64_t out, frag, code;
+    uint32_t chunk_first, n_chunks;
+    uint32_t rank_full, rank_last;
+};
+
+// Work items, longest first: the number of buckets of the counting sort on
+// a length's bit count.
+constexpr uint32_t EV_LEN_BUCKETS = 33;
+
 struct SegFn {
     int32_t a, b;      // the segment maps cnt to max(cnt + a, b)
     int32_t net;       // sum over tokens of (+1 function, -1 leaf)

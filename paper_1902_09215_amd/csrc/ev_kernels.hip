@@ -348,6 +348,126 @@ __global__ void k_seg_build(const ChunkIn* __restrict__ ch, const ChunkSegs* __r
     }
 }
 
+// ------------------------------------------------- split plan on the device
+//
+// A level's chunks and segments from its trees: block i writes the chunks
+// of tree i (all but the last hold C tokens) and their segment records.
+__device__ __forceinline__ uint32_t seg_count(uint32_t len, uint32_t seg_len, uint32_t head)
+{
+    return len <= head ? 1u : 1u + (len - head + seg_len - 1) / seg_len;
+}
+
+__global__ __launch_bounds__(64) void k_plan_chunks(const TreeLvl* __restrict__ trees, uint32_t n_trees,
+                                                    uint32_t seg_len, uint32_t head, ChunkIn* __restrict__ ch,
+                                                    ChunkSegs* __restrict__ cg)
+{
+    const uint32_t i = blockIdx.x;
+    if (i >= n_trees) return;
+    const TreeLvl tl = trees[i];
+    const uint32_t full = seg_count(tl.C, seg_len, head);
+    for (uint32_t k = threadIdx.x; k < tl.n_chunks; k += blockDim.x) {
+        const uint64_t o = (uint64_t)k * tl.C;
+        const uint32_t len = tl.len - o < tl.C ? (uint32_t)(tl.len - o) : tl.C;
+        const uint32_t j = tl.chunk_first + k;
+        ch[j] = ChunkIn{tl.start + o, len, tl.tree};
+        cg[j] = ChunkSegs{tl.seg_first + k * full, seg_count(len, seg_len, head)};
+    }
+}
+
+__device__ __forceinline__ uint32_t len_bucket(uint32_t len) { return len ? (uint32_t)__clz(len) : 32u; }
+
+// One wave per tree: the numbering of its chunks' slots, fragment tokens and
+// codes relative to the tree (exclusive for codes, inclusive for slots and
+// fragments), its chunks' input slots (the k-th REF of a level reads the
+// previous level's slot k), the tree's totals and, at level 0, its validity
+// (Sec. 2.2: every token fills one open slot and a function opens two; a
+// tree is valid iff a slot is open before each token and none after the
+// last).
+__global__ __launch_bounds__(64) void k_plan_trees(const TreeLvl* __restrict__ trees, uint32_t n_trees,
+                                                   const ChunkStat* __restrict__ cs, uint32_t level, uint64_t prev_out,
+                                                   uint64_t* __restrict__ code_loc, uint64_t* __restrict__ out_loc,
+                                                   uint64_t* __restrict__ frag_loc, uint32_t* __restrict__ in_end,
+                                                   TreeSum* __restrict__ sum)
+{
+    const uint32_t i = blockIdx.x;
+    if (i >= n_trees) return;
+    const int lane = (int)threadIdx.x;
+    const TreeLvl tl = trees[i];
+    uint64_t c_out = 0, c_frag = 0, c_code = 0, c_in = tl.ref_base;
+    int64_t c_open = 1;
+    uint32_t bad = 0, maxtop = 0, max_m = 0;
+    for (uint32_t g = 0; g < tl.n_chunks; g += 64) {
+        const uint32_t k = g + (uint32_t)lane;
+        const bool in = k < tl.n_chunks;
+        const uint32_t j = tl.chunk_first + (in ? k : 0);
+        ChunkStat q = {};
+        if (in) q = cs[j];
+        uint64_t so = q.n_out, sf = q.n_frag, sc = q.n_codes, si = q.n_in;
+        int64_t sn = q.net;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t a = __shfl_up(so, d, 64), b = __shfl_up(sf, d, 64), c = __shfl_up(sc, d, 64),
+                           e = __shfl_up(si, d, 64);
+            const int64_t f = __shfl_up(sn, d, 64);
+            if (lane >= d) {
+                so += a;
+                sf += b;
+                sc += c;
+                si += e;
+                sn += f;
+            }
+        }
+        if (in) {
+            code_loc[j] = c_code + sc - q.n_codes;
+            out_loc[j] = c_out + so;
+            frag_loc[j] = c_frag + sf;
+            const uint64_t ie = c_in + si;
+            in_end[j] = (uint32_t)ie;
+            if (ie > prev_out) bad |= 2u;
+            if (level == 0 && (q.bad || c_open + (sn - q.net) + q.minpref < 1)) bad |= 1u;
+            maxtop = q.maxtop > maxtop ? q.maxtop : maxtop;
+            max_m = q.max_m > max_m ? q.max_m : max_m;
+        }
+        c_out += __shfl(so, 63, 64);
+        c_frag += __shfl(sf, 63, 64);
+        c_code += __shfl(sc, 63, 64);
+        c_in += __shfl(si, 63, 64);
+        c_open += __shfl(sn, 63, 64);
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        bad |= __shfl_xor(bad, d, 64);
+        const uint32_t a = __shfl_xor(maxtop, d, 64), b = __shfl_xor(max_m, d, 64);
+        maxtop = a > maxtop ? a : maxtop;
+        max_m = b > max_m ? b : max_m;
+    }
+    if (level == 0 && c_open != 0) bad |= 1u;
+    if (lane == 0) sum[i] = TreeSum{c_out, c_frag, c_code, bad, maxtop, max_m, 0};
+}
+
+// Per chunk: its global numbering from its tree's bases, and its work item,
+// placed longest first (bucket_start: the first place of each length
+// bucket; the tree gives the chunk's rank inside its bucket).
+__global__ void k_plan_items(const ChunkIn* __restrict__ ch, uint32_t n, const TreeBase* __restrict__ base,
+                             const uint64_t* __restrict__ code_loc, const uint64_t* __restrict__ out_loc,
+                             const uint64_t* __restrict__ frag_loc, const uint32_t* __restrict__ in_end,
+                             const uint32_t* __restrict__ bucket_start, uint64_t* __restrict__ code_begin,
+                             uint64_t* __restrict__ frag_end, RunChunk* __restrict__ run, EvalChunk* __restrict__ slow)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const ChunkIn c = ch[j];
+    const TreeBase b = base[c.tree];
+    const uint64_t cb = b.code + code_loc[j];
+    const uint32_t oe = (uint32_t)(b.out + out_loc[j]);
+    code_begin[j] = run ? cb : ~0ull;
+    frag_end[j] = b.frag + frag_loc[j];
+    const uint32_t k = j - b.chunk_first;
+    const uint32_t at = bucket_start[len_bucket(c.len)] + (k + 1 < b.n_chunks ? b.rank_full + k : b.rank_last);
+    if (run)
+        run[at] = RunChunk{cb, in_end[j], oe};
+    else
+        slow[at] = EvalChunk{c.start, c.len, in_end[j], oe, c.tree, 0, 0};
+}
+
 // Per segment: its cnt map (a, b), validity counters and input references.
 __global__ void k_seg_fn(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs, uint32_t n,
                          SegFn* __restrict__ out, uint32_t max_tok)
@@ -1153,6 +1273,35 @@ hipError_t launch_seg_build(const ChunkIn* ch, const ChunkSegs* cg, uint32_t n, 
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_seg_build, dim3(n), dim3(64), 0, s, ch, cg, n, seg_len, head, seg);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_chunks(const TreeLvl* trees, uint32_t n_trees, uint32_t seg_len, uint32_t head, ChunkIn* ch,
+                              ChunkSegs* cg, hipStream_t s)
+{
+    if (n_trees == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_plan_chunks, dim3(n_trees), dim3(64), 0, s, trees, n_trees, seg_len, head, ch, cg);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_trees(const TreeLvl* trees, uint32_t n_trees, const ChunkStat* cs, uint32_t level,
+                             uint64_t prev_out, uint64_t* code_loc, uint64_t* out_loc, uint64_t* frag_loc,
+                             uint32_t* in_end, TreeSum* sum, hipStream_t s)
+{
+    if (n_trees == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_plan_trees, dim3(n_trees), dim3(64), 0, s, trees, n_trees, cs, level, prev_out, code_loc,
+                       out_loc, frag_loc, in_end, sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_items(const ChunkIn* ch, uint32_t n, const TreeBase* base, const uint64_t* code_loc,
+                             const uint64_t* out_loc, const uint64_t* frag_loc, const uint32_t* in_end,
+                             const uint32_t* cursor,
+                             uint64_t* code_begin, uint64_t* frag_end, RunChunk* run, EvalChunk* slow, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_plan_items, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, base, code_loc, out_loc, frag_loc,
+                       in_end, cursor, code_begin, frag_end, run, slow);
     return hipGetLastError();
 }
 

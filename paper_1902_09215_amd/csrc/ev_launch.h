@@ -8,6 +8,15 @@ namespace ev {
 hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
 hipError_t launch_seg_build(const ChunkIn* ch, const ChunkSegs* cg, uint32_t n, uint32_t seg_len, uint32_t head,
                             SegIn* seg, hipStream_t s);
+hipError_t launch_plan_chunks(const TreeLvl* trees, uint32_t n_trees, uint32_t seg_len, uint32_t head, ChunkIn* ch,
+                              ChunkSegs* cg, hipStream_t s);
+hipError_t launch_plan_trees(const TreeLvl* trees, uint32_t n_trees, const ChunkStat* cs, uint32_t level,
+                             uint64_t prev_out, uint64_t* code_loc, uint64_t* out_loc, uint64_t* frag_loc,
+                             uint32_t* in_end, TreeSum* sum, hipStream_t s);
+hipError_t launch_plan_items(const ChunkIn* ch, uint32_t n, const TreeBase* base, const uint64_t* code_loc,
+                             const uint64_t* out_loc, const uint64_t* frag_loc, const uint32_t* in_end,
+                             const uint32_t* cursor,
+                             uint64_t* code_begin, uint64_t* frag_end, RunChunk* run, EvalChunk* slow, hipStream_t s);
 hipError_t launch_seg_fn(const uint8_t* seq, const SegIn* segs, uint32_t n, SegFn* out, uint32_t max_tok,
                          hipStream_t s);
 hipError_t launch_seg_scan(const ChunkSegs* cseg, uint32_t n, const SegFn* fn, SegStart* st, ChunkStat* cstat,

@@ -165,7 +165,10 @@ void pop_free(ev_ctx* c, Pop* P)
 
 // Build the split plan of a population whose bytes are on the device.
 // Level 0 is the trees themselves; each level's chunks produce the next
-// level's skeleton until every tree is one value.
+// level's skeleton until every tree is one value.  The host keeps what is
+// per tree (its range at the level, its first input slot, where it ends);
+// chunks, segments and their numbering are made on the device, and the host
+// waits once per level, for the trees' totals that size the level's buffers.
 ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
 {
     hipStream_t s = x.stream;
@@ -206,13 +209,16 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
     uint8_t* cur = P->d_bytes;
     bool cur_owned = false;
     int level = 0;
-    // per-level device scratch: segments, their maps/starts/counts/positions
-    void *d_seg = nullptr, *d_cseg = nullptr, *d_fn = nullptr, *d_st = nullptr, *d_cnt = nullptr, *d_stat = nullptr,
-         *d_cb = nullptr, *d_fe = nullptr, *d_scode = nullptr, *d_sfrag = nullptr, *d_err = nullptr, *d_ch = nullptr;
+    // per-level device scratch: the level's trees, chunks and segments, the
+    // segments' maps, starts, counts and positions, the chunks' numbering
+    void *d_tl = nullptr, *d_ch = nullptr, *d_cseg = nullptr, *d_seg = nullptr, *d_fn = nullptr, *d_st = nullptr,
+         *d_cnt = nullptr, *d_stat = nullptr, *d_loc = nullptr, *d_inend = nullptr, *d_sum = nullptr, *d_tb = nullptr,
+         *d_cb = nullptr, *d_fe = nullptr, *d_scode = nullptr, *d_sfrag = nullptr, *d_err = nullptr;
     ev_status st = EV_OK;
     // also frees a skeleton not yet handed to a level
     auto cleanup = [&]() {
-        for (void** p : {&d_seg, &d_cseg, &d_fn, &d_st, &d_cnt, &d_stat, &d_cb, &d_fe, &d_scode, &d_sfrag, &d_err, &d_ch}) {
+        for (void** p : {&d_tl, &d_ch, &d_cseg, &d_seg, &d_fn, &d_st, &d_cnt, &d_stat, &d_loc, &d_inend, &d_sum, &d_tb,
+                         &d_cb, &d_fe, &d_scode, &d_sfrag, &d_err}) {
             dev_free(c, *p);
             *p = nullptr;
         }
@@ -225,7 +231,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         return dev_alloc(c, bytes, p);
     };
     // validator flags of every level, two words each (flags, first failing
-    // segment), read back with the next level's counts or after the last
+    // segment), read back with the next level's totals or after the last
     // level, so that validation costs no wait of its own
     constexpr int MAX_LEVELS = 64;
     uint32_t verr[2] = {0, 0};
@@ -238,69 +244,31 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             return st;
         }
     }
-    // the failure a level's validation found: chunk and tree of the segment
-    auto code_error = [&](int lv, const uint32_t* e, const std::vector<ChunkIn>& lch, const std::vector<ChunkSegs>& lcg,
-                          const std::vector<uint64_t>& lrs0) -> ev_status {
-        uint32_t sj = 0;
-        for (uint32_t lo = 0, hi = (uint32_t)lcg.size(); lo < hi;) {
-            const uint32_t mid = (lo + hi) / 2;
-            if (lcg[mid].first <= e[1]) { sj = mid; lo = mid + 1; } else { hi = mid; }
-        }
-        const uint32_t t = lch[sj].tree;
-        return fail(EV_EDEVICE,
-                    "internal: malformed code stream at level %d (flags %u, tree %u of %u tokens, chunk at token %llu "
-                    "of its level, segment %u)",
-                    lv, e[0], t, (unsigned)lch[sj].len, (unsigned long long)(lch[sj].start - lrs0[t]), e[1]);
+    auto code_error = [&](int lv, const uint32_t* e) -> ev_status {
+        return fail(EV_EDEVICE, "internal: malformed code stream at level %d (flags %u, segment %u)", lv, e[0], e[1]);
     };
-    uint32_t n_seg = 0;
-    auto& cg = W.cg;  // per chunk of the level: its first segment and count
-    // count pass over a level's chunks: per-chunk totals in cs.  Segments
-    // are 256 tokens at level 0 and 64 at the skeleton levels, which have
-    // few tokens and need the extra parallelism; a chunk's first segment,
-    // which also emits the chunk's final flush, is a quarter of that.
-    auto count = [&](const std::vector<ChunkIn>& ch, std::vector<ChunkStat>& cs) -> ev_status {
-        const uint32_t n = (uint32_t)ch.size();
-        const uint32_t seg_len = level == 0 ? SEG_TOKENS : SEG_TOKENS / 4;
-        const uint32_t head = seg_len / 4;
-        cg.resize(n);
-        uint64_t ns = 0;
-        for (uint32_t j = 0; j < n; j++) {
-            cg[j].first = (uint32_t)ns;
-            const uint32_t len = ch[j].len;
-            cg[j].n_seg = len <= head ? 1u : 1u + (len - head + seg_len - 1) / seg_len;
-            ns += cg[j].n_seg;
-        }
-        if (ns > 0xFFFFFFF0ull) return fail(EV_ECAP, "too many structure segments");
-        n_seg = (uint32_t)ns;
-        ev_status e;
-        if ((e = realloc(&d_seg, n_seg * sizeof(SegIn))) || (e = realloc(&d_cseg, n * sizeof(ChunkSegs))) ||
-            (e = realloc(&d_fn, n_seg * sizeof(SegFn))) || (e = realloc(&d_st, n_seg * sizeof(SegStart))) ||
-            (e = realloc(&d_cnt, n_seg * sizeof(SegCount))) || (e = realloc(&d_stat, n * sizeof(ChunkStat))) ||
-            (e = realloc(&d_ch, n * sizeof(ChunkIn))))
-            return e;
-        cs.resize(n);
-        if ((e = put(x, d_ch, ch.data(), n * sizeof(ChunkIn))) || (e = put(x, d_cseg, cg.data(), n * sizeof(ChunkSegs))))
-            return e;
-        HIPCHK(launch_seg_build((ChunkIn*)d_ch, (ChunkSegs*)d_cseg, n, seg_len, head, (SegIn*)d_seg, s));
-        HIPCHK(launch_seg_fn(cur, (SegIn*)d_seg, n_seg, (SegFn*)d_fn, level == 0 ? TOK_X : TOK_REF, s));
-        HIPCHK(launch_seg_scan((ChunkSegs*)d_cseg, n, (SegFn*)d_fn, (SegStart*)d_st, (ChunkStat*)d_stat, s));
-        HIPCHK(launch_seg_count(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (SegCount*)d_cnt, s));
-        HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, n, (SegCount*)d_cnt, (ChunkStat*)d_stat, nullptr, nullptr, nullptr,
-                                nullptr, s));
-        if ((e = get(x, cs.data(), d_stat, n * sizeof(ChunkStat)))) return e;
-        if (level > 0 && (e = get(x, verr, (uint32_t*)d_err + 2 * (level - 1), 8))) return e;
-        return sync(x);
-    };
+    auto& tl = W.tl;      // the level's trees
+    auto& tsum = W.tsum;  // their totals
+    auto& tb = W.tb;      // per tree id: its bases over the level's chunks
+    tb.resize((size_t)std::max(1, M) + 4);  // + the length buckets' first places
+    uint32_t hist[EV_LEN_BUCKETS];
+    // work items go longest first, for the balance of the kernels' dynamic
+    // work queues: a counting sort on the length's bit count (the order
+    // inside a power of two does not matter)
+    auto bucket = [](uint64_t len) { return len ? (uint32_t)__builtin_clz((uint32_t)len) : 32u; };
 
     for (;;) {
         const uint64_t C = level == 0 ? C0 : C1;
-        if (level > 0) {  // the previous level's chunks, for its validation's report
-            std::swap(W.ch, W.ch_prev);
-            std::swap(W.cg, W.cg_prev);
-            std::swap(W.rs0, W.rs0_prev);
-        }
-        auto& ch = W.ch;
-        ch.clear();
+        // Segments are 256 tokens at level 0 and 64 at the skeleton levels,
+        // which have few tokens and need the extra parallelism; a chunk's
+        // first segment, which also emits the chunk's final flush, is a
+        // quarter of that.
+        const uint32_t seg_len = level == 0 ? SEG_TOKENS : SEG_TOKENS / 4;
+        const uint32_t head = seg_len / 4;
+        auto nseg = [&](uint64_t len) -> uint64_t { return len <= head ? 1 : 1 + (len - head + seg_len - 1) / seg_len; };
+        tl.clear();
+        std::fill(hist, hist + EV_LEN_BUCKETS, 0u);
+        uint64_t n = 0, ns = 0, tokens = 0;
         for (int32_t t = 0; t < M; t++) {
             if (!active[t]) continue;
             const uint64_t len = rl[t];
@@ -310,138 +278,126 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             // the others copy slot values into new slots), so it is cheaper
             // to finish it in one item than to split it level after level.
             const bool whole = len <= C || (level > 0 && len * 2 > prev_len[t]);
-            if (whole) {
-                if (len > 0xFFFFFFFFull) { cleanup(); return fail(EV_ECAP, "work item of %llu tokens", (unsigned long long)len); }
-                ch.push_back({rs[t], (uint32_t)len, (uint32_t)t});
-            } else {
-                for (uint64_t o = 0; o < len; o += C)
-                    ch.push_back({rs[t] + o, (uint32_t)std::min<uint64_t>(C, len - o), (uint32_t)t});
+            if (whole && len > 0xFFFFFFFFull) {
+                cleanup();
+                return fail(EV_ECAP, "work item of %llu tokens", (unsigned long long)len);
+            }
+            const uint64_t Ct = whole ? len : C;
+            const uint64_t nc = whole ? 1 : (len + C - 1) / C;
+            TreeLvl v;
+            v.start = rs[t];
+            v.len = len;
+            v.chunk_first = (uint32_t)n;
+            v.n_chunks = (uint32_t)nc;
+            v.seg_first = (uint32_t)ns;
+            v.C = (uint32_t)Ct;
+            v.tree = (uint32_t)t;
+            v.ref_base = (uint32_t)ref_base[t];
+            tl.push_back(v);
+            // the ranks of its work items in their length buckets
+            TreeBase& r = tb[t];
+            r.chunk_first = (uint32_t)n;
+            r.n_chunks = (uint32_t)nc;
+            r.rank_full = hist[bucket(Ct)];
+            hist[bucket(Ct)] += (uint32_t)(nc - 1);
+            r.rank_last = hist[bucket(len - (nc - 1) * Ct)]++;
+            n += nc;
+            ns += (nc - 1) * nseg(Ct) + nseg(len - (nc - 1) * Ct);
+            tokens += len;
+            if (n > 0xFFFFFFF0ull || ns > 0xFFFFFFF0ull) {
+                cleanup();
+                return fail(EV_ECAP, "too many work items or structure segments at level %d", level);
             }
         }
-        if (ch.empty()) break;
-        auto& cs = W.cs;
-        if ((st = count(ch, cs)) != EV_OK) { cleanup(); return st; }
+        if (tl.empty()) break;
+        const uint32_t nt = (uint32_t)tl.size(), n_seg = (uint32_t)ns;
+
+        // device: chunks, segments, their counts, and each tree's numbering
+        if ((st = realloc(&d_tl, nt * sizeof(TreeLvl))) || (st = realloc(&d_ch, n * sizeof(ChunkIn))) ||
+            (st = realloc(&d_cseg, n * sizeof(ChunkSegs))) || (st = realloc(&d_seg, n_seg * sizeof(SegIn))) ||
+            (st = realloc(&d_fn, n_seg * sizeof(SegFn))) || (st = realloc(&d_st, n_seg * sizeof(SegStart))) ||
+            (st = realloc(&d_cnt, n_seg * sizeof(SegCount))) || (st = realloc(&d_stat, n * sizeof(ChunkStat))) ||
+            (st = realloc(&d_loc, n * 3 * sizeof(uint64_t))) || (st = realloc(&d_inend, n * sizeof(uint32_t))) ||
+            (st = realloc(&d_sum, nt * sizeof(TreeSum))) ||
+            (st = put(x, d_tl, tl.data(), nt * sizeof(TreeLvl)))) {
+            cleanup();
+            return st;
+        }
+        uint64_t* d_cloc = (uint64_t*)d_loc;
+        uint64_t* d_oloc = d_cloc + n;
+        uint64_t* d_floc = d_oloc + n;
+        const uint64_t prev_out = pl.levels.empty() ? 0 : pl.levels.back().n_out;
+        HIPCHK(launch_plan_chunks((TreeLvl*)d_tl, nt, seg_len, head, (ChunkIn*)d_ch, (ChunkSegs*)d_cseg, s));
+        HIPCHK(launch_seg_build((ChunkIn*)d_ch, (ChunkSegs*)d_cseg, (uint32_t)n, seg_len, head, (SegIn*)d_seg, s));
+        HIPCHK(launch_seg_fn(cur, (SegIn*)d_seg, n_seg, (SegFn*)d_fn, level == 0 ? TOK_X : TOK_REF, s));
+        HIPCHK(launch_seg_scan((ChunkSegs*)d_cseg, (uint32_t)n, (SegFn*)d_fn, (SegStart*)d_st, (ChunkStat*)d_stat, s));
+        HIPCHK(launch_seg_count(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (SegCount*)d_cnt, s));
+        HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, (uint32_t)n, (SegCount*)d_cnt, (ChunkStat*)d_stat, nullptr, nullptr,
+                                nullptr, nullptr, s));
+        HIPCHK(launch_plan_trees((TreeLvl*)d_tl, nt, (ChunkStat*)d_stat, (uint32_t)level, prev_out, d_cloc, d_oloc,
+                                 d_floc, (uint32_t*)d_inend, (TreeSum*)d_sum, s));
+        tsum.resize(nt);
+        if ((st = get(x, tsum.data(), d_sum, nt * sizeof(TreeSum))) ||
+            (level > 0 && (st = get(x, verr, (uint32_t*)d_err + 2 * (level - 1), 8))) || (st = sync(x))) {
+            cleanup();
+            return st;
+        }
         if (level > 0 && verr[0]) {
             cleanup();
-            return code_error(level - 1, verr, W.ch_prev, W.cg_prev, W.rs0_prev);
+            return code_error(level - 1, verr);
         }
 
-        const uint32_t n = (uint32_t)ch.size();
-        auto& rs0 = W.rs0;
-        rs0 = rs;
-
-        // One pass over the chunks in sequence order (a tree's chunks are
-        // adjacent): at level 0 the trees' validity (Sec. 2.2: every token
-        // fills one open slot and a function opens two; a tree is valid iff
-        // a slot is open before each token and none after the last), the
-        // slot, fragment and code numbering, the input slots (the k-th REF
-        // of a level is the previous level's slot k) and the work items'
-        // length buckets.
-        auto& out_end = W.out_end;
-        auto& frag_end = W.frag_end;
-        auto& code_begin = W.code_begin;
-        auto& in_end = W.in_end;
-        auto& tree_first = W.tree_first;
-        auto& tree_last = W.tree_last;
-        out_end.resize(n);
-        frag_end.resize(n);
-        code_begin.resize(n);
-        in_end.resize(n);
-        tree_first.assign(M, UINT32_MAX);
-        tree_last.resize(M);
-        const bool run_items = c->use_run;
-        const uint64_t prev_out = pl.levels.empty() ? 0 : pl.levels.back().n_out;
-        // work items go longest first, for the balance of the kernels'
-        // dynamic work queues: a stable counting sort on the length's bit
-        // count (the order inside a power of two does not matter)
-        auto bucket = [](uint32_t len) { return len ? (uint32_t)__builtin_clz(len) : 32u; };  // 0: longest
-        uint32_t at[34] = {};
-        uint64_t so = 0, sf = 0, sc = 0, tokens = 0, in_run = 0, max_stack = pl.max_stack;
-        uint32_t max_m = 0, slab_top = 0;
-        int64_t open = 0;
-        bool ok = true, consistent = true;
-        int32_t t_cur = -1;
-        auto tree_valid = [&]() { return level > 0 || t_cur < 0 || (ok && open == 0); };
-        for (uint32_t j = 0; j < n; j++) {
-            const ChunkStat& k = cs[j];
-            const uint32_t t = ch[j].tree;
-            if ((int32_t)t != t_cur) {
-                if (!tree_valid()) break;
-                t_cur = (int32_t)t;
-                tree_first[t] = j;
-                in_run = ref_base[t];
-                open = 1;
-                ok = true;
+        // host: the trees' bases (sequence order is tree order), validity
+        // and the level's totals
+        uint64_t so = 0, sf = 0, sc = 0;
+        uint32_t slab_top = 0, max_m = 0;
+        for (uint32_t i = 0; i < nt; i++) {
+            const TreeSum& q = tsum[i];
+            const uint32_t t = tl[i].tree;
+            if (q.bad & 1u) {
+                cleanup();
+                if (bad_tree) *bad_tree = (int32_t)t;
+                return fail(EV_EMALFORMED, "tree %u is not a valid prefix tree", t);
             }
-            tree_last[t] = j;
-            if (k.bad || open + k.minpref < 1) ok = false;
-            open += k.net;
-            so += k.n_out;
-            sf += k.n_frag;
-            out_end[j] = so;
-            frag_end[j] = sf;
-            tokens += ch[j].len;
-            in_run += k.n_in;
-            in_end[j] = (uint32_t)in_run;
-            consistent &= in_run <= prev_out && in_run >= k.n_in;
-            max_stack = std::max<uint64_t>(max_stack, k.maxtop + 1);
-            if (run_items) {
-                code_begin[j] = sc;
-                sc += k.n_codes;
-                slab_top = std::max(slab_top, k.maxtop);
-            } else {
-                code_begin[j] = ~0ull;
-                max_m = std::max(max_m, k.max_m);
+            if (q.bad & 2u) {
+                cleanup();
+                return fail(EV_EDEVICE, "inconsistent split plan at level %d", level);
             }
-            at[bucket(ch[j].len) + 1]++;
+            tb[t].out = so;
+            tb[t].frag = sf;
+            tb[t].code = sc;
+            so += q.n_out;
+            sf += q.n_frag;
+            sc += q.n_codes;
+            slab_top = std::max(slab_top, q.maxtop);
+            max_m = std::max(max_m, q.max_m);
+            pl.max_stack = std::max<uint64_t>(pl.max_stack, q.maxtop + 1);
         }
-        if (!tree_valid()) {
-            cleanup();
-            if (bad_tree) *bad_tree = t_cur;
-            return fail(EV_EMALFORMED, "tree %d is not a valid prefix tree", t_cur);
-        }
-        pl.max_stack = max_stack;
         if (so > 0xFFFFFFF0ull) { cleanup(); return fail(EV_ECAP, "too many intermediate results"); }
-        if (!consistent) { cleanup(); return fail(EV_EDEVICE, "inconsistent split plan at level %d", level); }
+        const bool run_items = c->use_run;
 
         Level L;
         L.seq = cur;
         L.owned = cur_owned;
         L.n_out = (uint32_t)so;
-        L.max_m = max_m;
+        L.max_m = run_items ? 0 : max_m;
         L.tokens = tokens;
         // a stack deeper than the register window spills half-windows to a
         // slab; so does one that reaches the window's upper quarter at a
         // segment boundary, where the window is re-centred
-        L.slab_entries = slab_top + 1 > EV_VSTACK_ENTRIES - EV_VHALF / 2 ? slab_top + EV_VHALF : 0;
+        L.slab_entries = run_items && slab_top + 1 > EV_VSTACK_ENTRIES - EV_VHALF / 2 ? slab_top + EV_VHALF : 0;
+        L.n_chunks = run_items ? 0 : (uint32_t)n;
+        L.n_run = run_items ? (uint32_t)n : 0;
         pl.chunks_total += n;
         pl.slots_total += so;
-        for (int k = 0; k < 33; k++) at[k + 1] += at[k];
-        const uint32_t n_run = run_items ? n : 0, n_slow = run_items ? 0 : n;
-        auto& slow = W.slow;
-        auto& rc = W.rc;
-        slow.resize(n_slow);
-        rc.resize(n_run);
-        for (uint32_t j = 0; j < n; j++) {
-            const uint32_t i = at[bucket(ch[j].len)]++;
-            if (run_items)
-                rc[i] = RunChunk{code_begin[j], in_end[j], (uint32_t)out_end[j]};
-            else
-                slow[i] = EvalChunk{ch[j].start, ch[j].len, in_end[j], (uint32_t)out_end[j], ch[j].tree, 0, 0};
-        }
-        L.n_chunks = n_slow;
-        L.n_run = n_run;
         pl.levels.push_back(L);  // owns what is allocated below, freed with the plan
         Level& LL = pl.levels.back();
         cur_owned = false;
-        if (n_slow) {
-            if ((st = dev_alloc(c, slow.size() * sizeof(EvalChunk), (void**)&LL.d_chunks)) != EV_OK) { cleanup(); return st; }
-            if ((st = put(x, LL.d_chunks, slow.data(), slow.size() * sizeof(EvalChunk))) != EV_OK) { cleanup(); return st; }
-        }
-        if (n_run) {
-            if ((st = dev_alloc(c, rc.size() * sizeof(RunChunk), (void**)&LL.d_run)) != EV_OK) { cleanup(); return st; }
+        if (!run_items) {
+            if ((st = dev_alloc(c, n * sizeof(EvalChunk), (void**)&LL.d_chunks)) != EV_OK) { cleanup(); return st; }
+        } else {
+            if ((st = dev_alloc(c, n * sizeof(RunChunk), (void**)&LL.d_run)) != EV_OK) { cleanup(); return st; }
             if ((st = dev_alloc(c, sc * 4 + 512, (void**)&LL.codes)) != EV_OK) { cleanup(); return st; }
-            if ((st = put(x, LL.d_run, rc.data(), rc.size() * sizeof(RunChunk))) != EV_OK) { cleanup(); return st; }
             // the interpreter reads up to 192 bytes past a stream's last code
             // block, the validator up to 28
             HIPCHK(hipMemsetAsync((uint8_t*)LL.codes + sc * 4, 0, 512, s));
@@ -449,43 +405,54 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
 
         // trees finished at this level and the next level's ranges
         bool any = false;
-        for (int32_t t = 0; t < M; t++) {
-            if (tree_first[t] == UINT32_MAX) continue;
-            const uint32_t j0 = tree_first[t], j1 = tree_last[t];
-            const uint64_t fbeg = frag_end[j0] - cs[j0].n_frag;
-            const uint64_t flen = frag_end[j1] - fbeg;
-            if (flen == 1) {
+        for (uint32_t i = 0; i < nt; i++) {
+            const uint32_t t = tl[i].tree;
+            const TreeSum& q = tsum[i];
+            if (q.n_frag == 1) {
                 pl.fin_level[t] = level;
-                pl.fin_slot[t] = (uint32_t)(out_end[j1] - 1);
+                pl.fin_slot[t] = (uint32_t)(tb[t].out + q.n_out - 1);
                 active[t] = 0;
             } else {
                 any = true;
                 prev_len[t] = rl[t];
-                rs[t] = fbeg;
-                rl[t] = flen;
-                ref_base[t] = out_end[j0] - cs[j0].n_out;
+                rs[t] = tb[t].frag;
+                rl[t] = q.n_frag;
+                ref_base[t] = tb[t].out;
             }
         }
 
-        // one pass writes the next level's skeleton and this level's codes,
-        // then every code stream is validated before anything may run it
+        // the chunks' numbering and work items (longest first: each length
+        // bucket's first place), then one pass writes the next level's
+        // skeleton and this level's codes, and every code stream is
+        // validated before anything may run it
+        uint32_t cursor[EV_LEN_BUCKETS];
+        for (uint32_t k = 0, a = 0; k < EV_LEN_BUCKETS; k++) {
+            cursor[k] = a;
+            a += hist[k];
+        }
+        static_assert(sizeof(cursor) <= 4 * sizeof(TreeBase), "bucket starts ride after the trees' bases");
+        std::memcpy(&tb[tb.size() - 4], cursor, sizeof(cursor));
         uint8_t* d_next = nullptr;
         if (any && (st = dev_alloc(c, sf + 64, (void**)&d_next)) != EV_OK) { cleanup(); return st; }
-        if (any) HIPCHK(hipMemsetAsync(d_next, 0xFF, sf + 64, s));
-        if (any || n_run) {
-            if ((st = realloc(&d_cb, n * sizeof(uint64_t))) || (st = realloc(&d_fe, n * sizeof(uint64_t))) ||
-                (st = realloc(&d_scode, n_seg * sizeof(uint64_t))) || (st = realloc(&d_sfrag, n_seg * sizeof(uint64_t))) ||
-                (st = put(x, d_cb, code_begin.data(), n * sizeof(uint64_t))) ||
-                (st = put(x, d_fe, frag_end.data(), n * sizeof(uint64_t)))) {
-                dev_free(c, d_next);
-                cleanup();
-                return st;
-            }
-            HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, n, (SegCount*)d_cnt, (ChunkStat*)d_stat, (uint64_t*)d_cb,
-                                    (uint64_t*)d_fe, (uint64_t*)d_scode, (uint64_t*)d_sfrag, s));
+        // emission writes every byte of [0, sf); the tail is padding
+        if (any) HIPCHK(hipMemsetAsync(d_next + sf, 0xFF, 64, s));
+        const size_t tb_bytes = (size_t)std::max(1, M) * sizeof(TreeBase);
+        if ((st = realloc(&d_tb, tb.size() * sizeof(TreeBase))) || (st = realloc(&d_cb, n * sizeof(uint64_t))) ||
+            (st = realloc(&d_fe, n * sizeof(uint64_t))) || (st = realloc(&d_scode, n_seg * sizeof(uint64_t))) ||
+            (st = realloc(&d_sfrag, n_seg * sizeof(uint64_t))) || (st = put(x, d_tb, tb.data(), tb.size() * sizeof(TreeBase)))) {
+            dev_free(c, d_next);
+            cleanup();
+            return st;
+        }
+        HIPCHK(launch_plan_items((ChunkIn*)d_ch, (uint32_t)n, (TreeBase*)d_tb, d_cloc, d_oloc, d_floc,
+                                 (uint32_t*)d_inend, (uint32_t*)((uint8_t*)d_tb + tb_bytes), (uint64_t*)d_cb,
+                                 (uint64_t*)d_fe, run_items ? LL.d_run : nullptr, run_items ? nullptr : LL.d_chunks, s));
+        if (any || run_items) {
+            HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, (uint32_t)n, (SegCount*)d_cnt, (ChunkStat*)d_stat,
+                                    (uint64_t*)d_cb, (uint64_t*)d_fe, (uint64_t*)d_scode, (uint64_t*)d_sfrag, s));
             HIPCHK(launch_seg_emit(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode, (uint64_t*)d_sfrag,
-                                   d_next, n_run ? LL.codes : nullptr, s));
-            if (n_run)
+                                   d_next, run_items ? LL.codes : nullptr, s));
+            if (run_items)
                 HIPCHK(launch_seg_check(LL.codes, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode,
                                         (SegCount*)d_cnt, LL.slab_entries, (uint32_t*)d_err + 2 * level, s));
         }
@@ -497,7 +464,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             }
             if (verr[0]) {
                 cleanup();
-                return code_error(level, verr, ch, cg, rs0);
+                return code_error(level, verr);
             }
             break;
         }

@@ -72,16 +72,12 @@ struct Pop {
 // Host-side working vectors of plan_build, kept across calls so that their
 // (large) buffers are reused instead of freshly mapped and faulted in.
 struct PlanScratch {
-    std::vector<uint64_t> rs, rl, prev_len, ref_base, rs0, out_end, frag_end, code_begin;
+    std::vector<uint64_t> rs, rl, prev_len, ref_base;
     std::vector<char> active;
-    std::vector<uint32_t> tree_first, tree_last, in_end;
-    std::vector<ChunkIn> ch, ch_prev;
-    std::vector<ChunkSegs> cg, cg_prev;
-    std::vector<uint64_t> rs0_prev;
     std::vector<uint32_t> err0;
-    std::vector<ChunkStat> cs;
-    std::vector<EvalChunk> slow;
-    std::vector<RunChunk> rc;
+    std::vector<TreeLvl> tl;
+    std::vector<TreeSum> tsum;
+    std::vector<TreeBase> tb;
 };
 
 // Per-thread execution resources: a stream (possibly shared) and the scratch
