@@ -450,8 +450,15 @@ __global__ void k_plan_items(const ChunkIn* __restrict__ ch, uint32_t n, const T
                              const uint64_t* __restrict__ code_loc, const uint64_t* __restrict__ out_loc,
                              const uint64_t* __restrict__ frag_loc, const uint32_t* __restrict__ in_end,
                              const uint32_t* __restrict__ bucket_start, uint64_t* __restrict__ code_begin,
-                             uint64_t* __restrict__ frag_end, RunChunk* __restrict__ run, EvalChunk* __restrict__ slow)
+                             uint64_t* __restrict__ frag_end, RunChunk* __restrict__ run, EvalChunk* __restrict__ slow,
+                             uint32_t* __restrict__ code_tail, uint8_t* __restrict__ frag_tail)
 {
+    if (blockIdx.x == 0) {
+        // the padding after the level's code stream (zeros) and after the
+        // next level's skeleton (0xFF): the readers' wide loads reach it
+        for (uint32_t i = threadIdx.x; code_tail && i < 128; i += blockDim.x) code_tail[i] = 0;
+        for (uint32_t i = threadIdx.x; frag_tail && i < 64; i += blockDim.x) frag_tail[i] = 0xFF;
+    }
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const ChunkIn c = ch[j];
@@ -1022,8 +1029,10 @@ __device__ __forceinline__ uint8_t child_byte(const uint8_t* __restrict__ mums, 
 
 __global__ void k_xo_copy(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
                           const XoPlan* __restrict__ plan, const uint64_t* __restrict__ off, uint32_t n_children,
-                          uint8_t* __restrict__ dst)
+                          uint8_t* __restrict__ dst, uint8_t* __restrict__ pad, uint32_t pad_len)
 {
+    if (blockIdx.x == 0 && blockIdx.y == 0)  // the buffer's padding of 0xFF after the children
+        for (uint32_t i = threadIdx.x; i < pad_len; i += blockDim.x) pad[i] = 0xFF;
     const uint32_t j = blockIdx.y;
     if (j >= n_children) return;
     XoPlan x = plan[j];
@@ -1098,9 +1107,9 @@ __global__ void k_xo_plan(const uint64_t* __restrict__ moff, const uint64_t* __r
 }
 
 // One block: the children's offsets (exclusive scan of the lengths in
-// off[0, n), in place; off[n] the total), sum[0] the number capped and
-// sum[1] the longest child.
-__global__ __launch_bounds__(1024) void k_xo_offsets(uint64_t* __restrict__ off, uint32_t n, uint64_t* __restrict__ sum)
+// off[0, n), in place; off[n] the total), off[n + 1] the number capped and
+// off[n + 2] the longest child.
+__global__ __launch_bounds__(1024) void k_xo_offsets(uint64_t* __restrict__ off, uint32_t n)
 {
     __shared__ uint64_t part[1024];
     __shared__ unsigned long long s_max;
@@ -1138,8 +1147,8 @@ __global__ __launch_bounds__(1024) void k_xo_offsets(uint64_t* __restrict__ off,
     }
     if (t == 1023) off[n] = part[1023];
     if (t == 0) {
-        sum[0] = s_capped;
-        sum[1] = s_max;
+        off[n + 1] = s_capped;
+        off[n + 2] = s_max;
     }
 }
 
@@ -1297,11 +1306,12 @@ hipError_t launch_plan_trees(const TreeLvl* trees, uint32_t n_trees, const Chunk
 hipError_t launch_plan_items(const ChunkIn* ch, uint32_t n, const TreeBase* base, const uint64_t* code_loc,
                              const uint64_t* out_loc, const uint64_t* frag_loc, const uint32_t* in_end,
                              const uint32_t* cursor,
-                             uint64_t* code_begin, uint64_t* frag_end, RunChunk* run, EvalChunk* slow, hipStream_t s)
+                             uint64_t* code_begin, uint64_t* frag_end, RunChunk* run, EvalChunk* slow,
+                             uint32_t* code_tail, uint8_t* frag_tail, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_plan_items, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, base, code_loc, out_loc, frag_loc,
-                       in_end, cursor, code_begin, frag_end, run, slow);
+                       in_end, cursor, code_begin, frag_end, run, slow, code_tail, frag_tail);
     return hipGetLastError();
 }
 
@@ -1409,10 +1419,11 @@ hipError_t launch_subtree_end(const uint8_t* buf, const uint64_t* base, const ui
 }
 
 hipError_t launch_xo_copy(const uint8_t* mums, const uint8_t* dads, const XoPlan* plan, const uint64_t* off,
-                          uint32_t n, uint64_t max_child, uint8_t* dst, hipStream_t s)
+                          uint32_t n, uint64_t max_child, uint8_t* dst, uint8_t* pad, uint32_t pad_len, hipStream_t s)
 {
-    if (n == 0 || max_child == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_xo_copy, dim3(cdiv(max_child, 4096), n), dim3(256), 0, s, mums, dads, plan, off, n, dst);
+    if (n == 0 || max_child == 0) return hipMemsetAsync(pad, 0xFF, pad_len, s);
+    hipLaunchKernelGGL(k_xo_copy, dim3(cdiv(max_child, 4096), n), dim3(256), 0, s, mums, dads, plan, off, n, dst, pad,
+                       pad_len);
     return hipGetLastError();
 }
 
@@ -1426,13 +1437,13 @@ hipError_t launch_xo_query(const uint64_t* moff, const uint64_t* doff, const int
 
 hipError_t launch_xo_plan(const uint64_t* moff, const uint64_t* doff, const int32_t* mum, const int32_t* dad,
                           const uint64_t* p, const uint64_t* q, const uint64_t* ends, uint32_t n, uint64_t cap,
-                          XoPlan* plan, uint64_t* off, uint64_t* sum, hipStream_t s)
+                          XoPlan* plan, uint64_t* off, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_xo_plan, dim3(cdiv(n, 256)), dim3(256), 0, s, moff, doff, mum, dad, p, q, ends, n, cap, plan, off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_xo_offsets, dim3(1), dim3(1024), 0, s, off, n, sum);
+    hipLaunchKernelGGL(k_xo_offsets, dim3(1), dim3(1024), 0, s, off, n);
     return hipGetLastError();
 }
 

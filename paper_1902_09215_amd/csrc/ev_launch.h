@@ -16,7 +16,8 @@ hipError_t launch_plan_trees(const TreeLvl* trees, uint32_t n_trees, const Chunk
 hipError_t launch_plan_items(const ChunkIn* ch, uint32_t n, const TreeBase* base, const uint64_t* code_loc,
                              const uint64_t* out_loc, const uint64_t* frag_loc, const uint32_t* in_end,
                              const uint32_t* cursor,
-                             uint64_t* code_begin, uint64_t* frag_end, RunChunk* run, EvalChunk* slow, hipStream_t s);
+                             uint64_t* code_begin, uint64_t* frag_end, RunChunk* run, EvalChunk* slow,
+                             uint32_t* code_tail, uint8_t* frag_tail, hipStream_t s);
 hipError_t launch_seg_fn(const uint8_t* seq, const SegIn* segs, uint32_t n, SegFn* out, uint32_t max_tok,
                          hipStream_t s);
 hipError_t launch_seg_scan(const ChunkSegs* cseg, uint32_t n, const SegFn* fn, SegStart* st, ChunkStat* cstat,
@@ -43,12 +44,12 @@ hipError_t launch_fitness(const uint64_t* rows, const float* y, int32_t N, uint3
 hipError_t launch_subtree_end(const uint8_t* buf, const uint64_t* base, const uint64_t* pos, uint32_t n,
                               uint64_t* end_out, hipStream_t s);
 hipError_t launch_xo_copy(const uint8_t* mums, const uint8_t* dads, const XoPlan* plan, const uint64_t* off,
-                          uint32_t n, uint64_t max_child, uint8_t* dst, hipStream_t s);
+                          uint32_t n, uint64_t max_child, uint8_t* dst, uint8_t* pad, uint32_t pad_len, hipStream_t s);
 hipError_t launch_xo_query(const uint64_t* moff, const uint64_t* doff, const int32_t* mum, const int32_t* dad,
                            const uint64_t* p, const uint64_t* q, uint32_t n, uint64_t* qb, uint64_t* qp, hipStream_t s);
 hipError_t launch_xo_plan(const uint64_t* moff, const uint64_t* doff, const int32_t* mum, const int32_t* dad,
                           const uint64_t* p, const uint64_t* q, const uint64_t* ends, uint32_t n, uint64_t cap,
-                          XoPlan* plan, uint64_t* off, uint64_t* sum, hipStream_t s);
+                          XoPlan* plan, uint64_t* off, hipStream_t s);
 hipError_t launch_select(const float* fit, const uint64_t* off, uint32_t M, int32_t k, uint64_t seed, uint64_t gen,
                          int32_t* mum, int32_t* dad, uint64_t* p, uint64_t* q, hipStream_t s);
 }  // namespace ev

@@ -397,10 +397,10 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             if ((st = dev_alloc(c, n * sizeof(EvalChunk), (void**)&LL.d_chunks)) != EV_OK) { cleanup(); return st; }
         } else {
             if ((st = dev_alloc(c, n * sizeof(RunChunk), (void**)&LL.d_run)) != EV_OK) { cleanup(); return st; }
-            if ((st = dev_alloc(c, sc * 4 + 512, (void**)&LL.codes)) != EV_OK) { cleanup(); return st; }
+            // 512 zero bytes after the stream (written with the work items):
             // the interpreter reads up to 192 bytes past a stream's last code
             // block, the validator up to 28
-            HIPCHK(hipMemsetAsync((uint8_t*)LL.codes + sc * 4, 0, 512, s));
+            if ((st = dev_alloc(c, sc * 4 + 512, (void**)&LL.codes)) != EV_OK) { cleanup(); return st; }
         }
 
         // trees finished at this level and the next level's ranges
@@ -432,10 +432,10 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         }
         static_assert(sizeof(cursor) <= 4 * sizeof(TreeBase), "bucket starts ride after the trees' bases");
         std::memcpy(&tb[tb.size() - 4], cursor, sizeof(cursor));
+        // emission writes every byte of the next skeleton, [0, sf); 64 bytes
+        // of padding follow (written with the work items)
         uint8_t* d_next = nullptr;
         if (any && (st = dev_alloc(c, sf + 64, (void**)&d_next)) != EV_OK) { cleanup(); return st; }
-        // emission writes every byte of [0, sf); the tail is padding
-        if (any) HIPCHK(hipMemsetAsync(d_next + sf, 0xFF, 64, s));
         const size_t tb_bytes = (size_t)std::max(1, M) * sizeof(TreeBase);
         if ((st = realloc(&d_tb, tb.size() * sizeof(TreeBase))) || (st = realloc(&d_cb, n * sizeof(uint64_t))) ||
             (st = realloc(&d_fe, n * sizeof(uint64_t))) || (st = realloc(&d_scode, n_seg * sizeof(uint64_t))) ||
@@ -446,7 +446,8 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         }
         HIPCHK(launch_plan_items((ChunkIn*)d_ch, (uint32_t)n, (TreeBase*)d_tb, d_cloc, d_oloc, d_floc,
                                  (uint32_t*)d_inend, (uint32_t*)((uint8_t*)d_tb + tb_bytes), (uint64_t*)d_cb,
-                                 (uint64_t*)d_fe, run_items ? LL.d_run : nullptr, run_items ? nullptr : LL.d_chunks, s));
+                                 (uint64_t*)d_fe, run_items ? LL.d_run : nullptr, run_items ? nullptr : LL.d_chunks,
+                                 run_items ? LL.codes + sc : nullptr, any ? d_next + sf : nullptr, s));
         if (any || run_items) {
             HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, (uint32_t)n, (SegCount*)d_cnt, (ChunkStat*)d_stat,
                                     (uint64_t*)d_cb, (uint64_t*)d_fe, (uint64_t*)d_scode, (uint64_t*)d_sfrag, s));
@@ -716,7 +717,7 @@ ev_status rescache_build(ev_ctx* c, Exec& x, Pop* P, int32_t table, ResCache** o
         rescache_free(c, r);
         return st;
     }
-    if ((st = put(x, r.d_rows, rows.data(), rows.size() * sizeof(uint64_t))) != EV_OK || (st = sync(x)) != EV_OK) {
+    if ((st = put(x, r.d_rows, rows.data(), rows.size() * sizeof(uint64_t))) != EV_OK) {
         rescache_free(c, r);
         return st;
     }
@@ -826,21 +827,21 @@ ev_status crossover_build_dev(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const in
 {
     hipStream_t s = x.stream;
     const size_t qn = std::max<size_t>(1, 2 * (size_t)n);
-    void *d_b = nullptr, *d_qp = nullptr, *d_e = nullptr, *d_plan = nullptr, *d_sum = nullptr;
+    void *d_b = nullptr, *d_qp = nullptr, *d_e = nullptr, *d_plan = nullptr;
     uint64_t* d_off = nullptr;
     auto cleanup = [&]() {
-        for (void* p : {d_b, d_qp, d_e, d_plan, d_sum}) dev_free(c, p);
+        for (void* p : {d_b, d_qp, d_e, d_plan}) dev_free(c, p);
     };
     ev_status st;
     if ((st = dev_alloc(c, qn * 8, &d_b)) || (st = dev_alloc(c, qn * 8, &d_qp)) || (st = dev_alloc(c, qn * 8, &d_e)) ||
-        (st = dev_alloc(c, std::max<size_t>(1, n) * sizeof(XoPlan), &d_plan)) || (st = dev_alloc(c, 16, &d_sum)) ||
-        (st = dev_alloc(c, ((size_t)n + 1) * 8, (void**)&d_off))) {
+        (st = dev_alloc(c, std::max<size_t>(1, n) * sizeof(XoPlan), &d_plan)) ||
+        (st = dev_alloc(c, ((size_t)n + 3) * 8, (void**)&d_off))) {
         cleanup();
         dev_free(c, d_off);
         return st;
     }
-    std::vector<uint64_t> off((size_t)n + 1, 0);
-    uint64_t sum[2] = {0, 0};
+    // the offsets, then the number capped and the longest child
+    std::vector<uint64_t> off((size_t)n + 3, 0);
     if (n > 0) {
         uint64_t* qb = (uint64_t*)d_b;
         uint64_t* qp = (uint64_t*)d_qp;
@@ -853,8 +854,8 @@ ev_status crossover_build_dev(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const in
             HIPCHK(launch_subtree_end(dads->d_bytes, qb + n, qp + n, (uint32_t)n, ends + n, s));
         }
         HIPCHK(launch_xo_plan(mums->d_off, dads->d_off, d_mum, d_dad, d_p, d_q, ends, (uint32_t)n, cap, (XoPlan*)d_plan,
-                              d_off, (uint64_t*)d_sum, s));
-        if ((st = get(x, off.data(), d_off, ((size_t)n + 1) * 8)) || (st = get(x, sum, d_sum, 16)) || (st = sync(x))) {
+                              d_off, s));
+        if ((st = get(x, off.data(), d_off, ((size_t)n + 3) * 8)) || (st = sync(x))) {
             cleanup();
             dev_free(c, d_off);
             return st;
@@ -870,12 +871,14 @@ ev_status crossover_build_dev(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const in
         dev_free(c, d_off);
         return st;
     }
-    HIPCHK(launch_xo_copy(mums->d_bytes, dads->d_bytes, (XoPlan*)d_plan, d_off, (uint32_t)n, sum[1], d_child, s));
-    HIPCHK(hipMemsetAsync(d_child + off[n], 0xFF, EV_POP_PAD, s));
+    const uint64_t capped = off[n + 1], longest = off[n + 2];
+    off.resize((size_t)n + 1);
+    HIPCHK(launch_xo_copy(mums->d_bytes, dads->d_bytes, (XoPlan*)d_plan, d_off, (uint32_t)n, longest, d_child,
+                          d_child + off[n], (uint32_t)EV_POP_PAD, s));
     // the scratch goes back to the cache while the copy may still run: every
     // later use of it is ordered after the copy on the context's one stream
     cleanup();
-    if (n_capped) *n_capped = (int32_t)sum[0];
+    if (n_capped) *n_capped = (int32_t)capped;
     return pop_build(c, x, d_child, off, out, nullptr, d_off);
 }
 
