@@ -14,8 +14,12 @@ block's lower half into s[64:79]; position 31's handler advances the block
 pointer, waits for that lower half and starts loading the upper half.  So a
 refill costs one scalar load per 16 codes and no register copies.
 
-Dispatch is `s_add_u32 s44, s42, s[next]` + `s_setpc_b64 s[44:45]`, with s45
-(and s47, for calls) equal to the table's high address word: the table must
+Dispatch is `s_add_u32 s44, s42, s[next]` + `s_setpc_b64 s[44:45]`.  A code
+whose work lives in a shared routine (division, slot reads and writes,
+spills) sets s[44:45] to the next handler first and jumps to the routine,
+which ends by jumping there: one jump more than a plain code, not a call
+and a return.  s45 (and s47, for routine jumps) equal the table's high
+address word: the table must
 not cross a 4 GiB boundary, which the prologue checks (a launch that finds a
 carry writes 1 to the flag word and evaluates nothing; the library probes
 this once per device and falls back to k_eval if ever needed).  Every
@@ -30,7 +34,7 @@ Register use inside the block:
   v4..v10         temporaries (division), v4 also a staging register
   %[x], %[lane4]  the lane's input value and byte offset (not clobbered)
   s[40:41] code block pointer (128-byte aligned), s[42:43] handler table,
-  s[44:45] jump target, s[46:47] call target, s[48:49] return address,
+  s[44:45] jump target (the next handler), s[46:47] routine target,
   s[50:51] read-ahead pointer into the input slot rows, s[52:53] output-slot row pointer,
   s54 row bytes (cases * 4), s55 window index of T, s[56:57] division
   scratch, s58 scratch, s59 flush index, s[60:61] next free entry of the
@@ -98,8 +102,8 @@ DIV_BODY = """\
 """
 
 
-def dispatch(pos: int) -> list[str]:
-    """Jump to the handler of the code at position pos+1 (refilling the
+def next_target(pos: int) -> list[str]:
+    """s[44:45] = the handler of the code at position pos+1 (refilling the
     code block halves at positions 15 and 31)."""
     nxt = (pos + 1) % POS
     pre: list[str] = []
@@ -108,11 +112,19 @@ def dispatch(pos: int) -> list[str]:
     elif pos == 31:
         pre = ["s_add_u32 s40, s40, 0x80", "s_addc_u32 s41, s41, 0", "s_waitcnt lgkmcnt(0)",
                "s_load_dwordx16 s[80:95], s[40:41], 0x40"]
-    return pre + [f"s_add_u32 s44, s42, s{64 + nxt}", "s_setpc_b64 s[44:45]"]
+    return pre + [f"s_add_u32 s44, s42, s{64 + nxt}"]
 
 
-def call(routine: str) -> list[str]:
-    return [f"s_add_u32 s46, s42, .L{routine}%= - .Ltab%=", "s_swappc_b64 s[48:49], s[46:47]"]
+def dispatch(pos: int) -> list[str]:
+    """Jump to the handler of the code at position pos+1."""
+    return next_target(pos) + ["s_setpc_b64 s[44:45]"]
+
+
+def tail_jump(routine: str) -> list[str]:
+    """Jump to a shared routine, which ends by jumping to s[44:45]: the next
+    code's handler, set up before the jump (one jump instead of a call, a
+    return and a dispatch)."""
+    return [f"s_add_u32 s46, s42, .L{routine}%= - .Ltab%=", "s_setpc_b64 s[46:47]"]
 
 
 def row_dec(lo: int) -> list[str]:
@@ -122,12 +134,13 @@ def row_dec(lo: int) -> list[str]:
 def handler(kind: str, pos: int) -> list[str]:
     k = kind
     body: list[str]
+    routine = None
     if k in ("OPS0", "OPS1", "OPS2"):
         # T' = op(T, below): dst v[11+m], src0 v[12+m] (T), src1 v[11+m]
         body = ["s_set_gpr_idx_on s55, gpr_idx(SRC0,SRC1,DST)", f"{VOP[int(k[3])]} v11, v12, v11",
                 "s_sub_u32 s55, s55, 1"]
     elif k == "OPS3":
-        body = call("divops")
+        routine = "divops"
     elif len(k) == 5 and k.startswith("OPS"):
         # two pops in a row: the second works one entry lower
         a, b = int(k[3]), int(k[4])
@@ -136,18 +149,24 @@ def handler(kind: str, pos: int) -> list[str]:
     elif k.startswith("OPX"):
         op = int(k[3])
         # T = op(x, T)
-        body = call("divopx") if op == 3 else [
-            "s_set_gpr_idx_on s55, gpr_idx(SRC1,DST)", f"{VOP[op]} v12, %[x], v12"]
+        if op == 3:
+            routine = "divopx"
+        else:
+            body = ["s_set_gpr_idx_on s55, gpr_idx(SRC1,DST)", f"{VOP[op]} v12, %[x], v12"]
     elif k.startswith("CH"):
         op = int(k[2])
         # push T; T = op(x, x)
-        body = call("divch") if op == 3 else [
-            "s_set_gpr_idx_on s55, gpr_idx(DST)", f"{VOP[op]} v13, %[x], %[x]", "s_add_u32 s55, s55, 1"]
+        if op == 3:
+            routine = "divch"
+        else:
+            body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"{VOP[op]} v13, %[x], %[x]", "s_add_u32 s55, s55, 1"]
     elif k.startswith("LCH"):
         op = int(k[3])
         # T = op(x, x) with no value below
-        body = call("divlch") if op == 3 else [
-            "s_set_gpr_idx_on s55, gpr_idx(DST)", f"{VOP[op]} v12, %[x], %[x]"]
+        if op == 3:
+            routine = "divlch"
+        else:
+            body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"{VOP[op]} v12, %[x], %[x]"]
     elif k == "PUSHX":
         body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v13, %[x]", "s_add_u32 s55, s55, 1"]
     elif k == "PUSH2X":
@@ -156,7 +175,7 @@ def handler(kind: str, pos: int) -> list[str]:
     elif k == "LOADX":
         body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v12, %[x]"]
     elif k in ("OUTT", "OUTBOT", "SPILL", "FILL", "OUTMEM") or k.startswith("PUSHREF") or k.startswith("LOADREF"):
-        body = call(k.lower())
+        routine = k.lower()
     elif k == "OUTX":
         body = ["s_set_gpr_idx_off"] + row_dec(52) + ["global_store_dword %[lane4], %[x], s[52:53]"]
     elif k == "FLUSH":
@@ -165,6 +184,8 @@ def handler(kind: str, pos: int) -> list[str]:
         return ["s_set_gpr_idx_off", "s_branch .Lexit%="]
     else:
         raise KeyError(k)
+    if routine is not None:
+        return next_target(pos) + tail_jump(routine)
     return body + dispatch(pos)
 
 
@@ -174,18 +195,18 @@ def routines() -> list[str]:
             "v_mov_b32_e32 v5, v11", "s_set_gpr_idx_off"]
     out += DIV_BODY.splitlines()
     out += ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v11, v6", "s_sub_u32 s55, s55, 1",
-            "s_setpc_b64 s[48:49]"]
+            "s_setpc_b64 s[44:45]"]
     out += [".Ldivopx%=:", "s_set_gpr_idx_on s55, gpr_idx(SRC0)", "v_mov_b32_e32 v5, v12", "s_set_gpr_idx_off",
             "v_mov_b32_e32 v4, %[x]"]
     out += DIV_BODY.splitlines()
-    out += ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v12, v6", "s_setpc_b64 s[48:49]"]
+    out += ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v12, v6", "s_setpc_b64 s[44:45]"]
     for name, dst, inc in (("divch", "v13", True), ("divlch", "v12", False)):
         out += [f".L{name}%=:", "s_set_gpr_idx_off", "v_mov_b32_e32 v4, %[x]", "v_mov_b32_e32 v5, %[x]"]
         out += DIV_BODY.splitlines()
         out += ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {dst}, v6"]
         if inc:
             out += ["s_add_u32 s55, s55, 1"]
-        out += ["s_setpc_b64 s[48:49]"]
+        out += ["s_setpc_b64 s[44:45]"]
     # a value from the previous level's slots (rows read downwards): REF j of
     # a work item takes ring register j % RING, loaded RING REFs earlier, and
     # starts the load of the row REF j + RING will take.  Vector memory
@@ -197,14 +218,14 @@ def routines() -> list[str]:
                     f"v_mov_b32_e32 {dst}, v{RING0 + r}", "s_set_gpr_idx_off"]
             if inc:
                 out += ["s_add_u32 s55, s55, 1"]
-            out += row_dec(50) + [f"global_load_dword v{RING0 + r}, %[lane4], s[50:51]", "s_setpc_b64 s[48:49]"]
+            out += row_dec(50) + [f"global_load_dword v{RING0 + r}, %[lane4], s[50:51]", "s_setpc_b64 s[44:45]"]
     # T to the next output slot (rows written downwards)
     out += [".Loutt%=:", "s_set_gpr_idx_on s55, gpr_idx(SRC0)", "v_mov_b32_e32 v4, v12", "s_set_gpr_idx_off"]
-    out += row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]", "s_setpc_b64 s[48:49]"]
+    out += row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]", "s_setpc_b64 s[44:45]"]
     # chunk-end flush of the window entry s59
     out += [".Loutbot%=:", "s_set_gpr_idx_on s59, gpr_idx(SRC0)", "v_mov_b32_e32 v4, v12", "s_set_gpr_idx_off",
             "s_add_u32 s59, s59, 1"] + row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]",
-                                                     "s_setpc_b64 s[48:49]"]
+                                                     "s_setpc_b64 s[44:45]"]
     # spill: the window's bottom HALF entries to the slab, then shift down
     groups = [(g0, min(16, HALF - g0)) for g0 in range(0, HALF, 16)]
     out += [".Lspill%=:", "s_set_gpr_idx_off"]
@@ -213,7 +234,7 @@ def routines() -> list[str]:
                 for i in range(n)]
         out += [f"s_add_u32 s60, s60, {256 * n}", "s_addc_u32 s61, s61, 0"]
     out += [f"v_mov_b32_e32 v{12 + i}, v{12 + HALF + i}" for i in range(VSTACK - HALF)]
-    out += [f"s_sub_u32 s55, s55, {HALF}", "s_setpc_b64 s[48:49]"]
+    out += [f"s_sub_u32 s55, s55, {HALF}", "s_setpc_b64 s[44:45]"]
     # fill: shift up, then the top HALF entries of the slab into the bottom
     out += [".Lfill%=:", "s_set_gpr_idx_off"]
     out += [f"v_mov_b32_e32 v{12 + HALF + i}, v{12 + i}" for i in range(VSTACK - HALF)]
@@ -221,12 +242,12 @@ def routines() -> list[str]:
         out += [f"s_sub_u32 s60, s60, {256 * n}", "s_subb_u32 s61, s61, 0"]
         out += [f"global_load_dword v{12 + g0 + i}, %[slane], s[60:61]" + (f" offset:{256 * i}" if i else "")
                 for i in range(n)]
-    out += ["s_waitcnt vmcnt(0)", f"s_add_u32 s55, s55, {HALF}", "s_setpc_b64 s[48:49]"]
+    out += ["s_waitcnt vmcnt(0)", f"s_add_u32 s55, s55, {HALF}", "s_setpc_b64 s[44:45]"]
     # chunk-end flush of an entry that lives in the slab (entry s59)
     out += [".Loutmem%=:", "s_set_gpr_idx_off", "s_lshl_b32 s46, s59, 8", "s_add_u32 s46, s62, s46",
             "s_addc_u32 s47, s63, 0", "global_load_dword v4, %[slane], s[46:47]", "s_waitcnt vmcnt(0)",
             "s_mov_b32 s47, s43", "s_add_u32 s59, s59, 1"] + row_dec(52) + [
-            "global_store_dword %[lane4], v4, s[52:53]", "s_setpc_b64 s[48:49]"]
+            "global_store_dword %[lane4], v4, s[52:53]", "s_setpc_b64 s[44:45]"]
     return out
 
 
