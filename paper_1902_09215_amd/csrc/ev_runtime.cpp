@@ -39,9 +39,17 @@ ev_status hip_fail(hipError_t e, const char* what)
 // Device memory goes through a per-context cache: freed blocks are kept in
 // size classes and handed out again, so the plan and crossover temporaries
 // of every generation cost no hipMalloc/hipFree (hipFree synchronizes the
-// device).  A block is only ever freed after the stream that used it has
-// been synchronized.  The budget bounds live bytes; cached blocks are
-// released first when the device runs short.
+// device).  A block goes back to the cache while work that uses it may
+// still be queued: all of a context's work runs on its one stream, so the
+// block's next user is ordered after it, and hipFree waits for the device.
+// The budget bounds live bytes; when live plus cached bytes would exceed
+// what the device can hold, the cached blocks idle the longest are
+// released first.
+// Powers of two up to 256 MiB, then steps of 2^(1/4) (rounded to 2 MiB): a
+// large block serves requests from about 84% of its size up, so the large
+// buffers of successive generations, whose sizes wander by a few percent,
+// keep finding one in the cache (a fresh multi-GB hipMalloc on a nearly
+// full device has taken over a second).
 static size_t size_class(size_t bytes)
 {
     if (bytes <= 256) return 256;
@@ -50,8 +58,14 @@ static size_t size_class(size_t bytes)
         while (c < bytes) c <<= 1;
         return c;
     }
-    const size_t g = 64ull << 20;
-    return (bytes + g - 1) / g * g;
+    const size_t g = 2ull << 20;
+    double c = (double)(256ull << 20);
+    size_t cls = 256ull << 20;
+    while (cls < bytes) {
+        c *= 1.189207115002721;  // 2^(1/4)
+        cls = ((size_t)c + g - 1) / g * g;
+    }
+    return cls;
 }
 
 static void cache_release(ev_ctx* c)
@@ -59,7 +73,30 @@ static void cache_release(ev_ctx* c)
     for (auto& kv : c->cache)
         for (void* p : kv.second) (void)hipFree(p);
     c->cache.clear();
+    c->cache_tick.clear();
     c->cached = 0;
+}
+
+// Release cached blocks, those idle the longest first, until `need` more
+// bytes fit under the hold limit (or nothing is cached).
+static void cache_trim(ev_ctx* c, size_t need)
+{
+    if (c->in_use + c->cached + need <= c->hold_limit) return;
+    std::vector<std::pair<uint64_t, void*>> order;
+    order.reserve(c->cache_tick.size());
+    for (auto& kv : c->cache_tick) order.push_back({kv.second, kv.first});
+    std::sort(order.begin(), order.end());
+    for (auto& o : order) {
+        if (c->in_use + c->cached + need <= c->hold_limit) break;
+        void* p = o.second;
+        const size_t cls = c->sizes_cached[p];
+        auto& bin = c->cache[cls];
+        bin.erase(std::find(bin.begin(), bin.end(), p));
+        c->cache_tick.erase(p);
+        c->sizes_cached.erase(p);
+        c->cached -= cls;
+        (void)hipFree(p);
+    }
 }
 
 ev_status dev_alloc(ev_ctx* c, size_t bytes, void** out)
@@ -71,19 +108,25 @@ ev_status dev_alloc(ev_ctx* c, size_t bytes, void** out)
         if (c->budget && c->in_use + cls > c->budget)
             return fail(EV_ENOMEM, "memory budget exceeded (%zu + %zu > %zu bytes)", (size_t)c->in_use, cls,
                         (size_t)c->budget);
-        auto it = c->cache.find(cls);
-        if (it != c->cache.end() && !it->second.empty()) {
+        // the same size class, or for a large request the next one up
+        const size_t slack = cls >= (256ull << 20) ? cls / 4 : 0;
+        for (auto it = c->cache.lower_bound(cls); it != c->cache.end() && it->first <= cls + slack; ++it) {
+            if (it->second.empty()) continue;
+            const size_t got = it->first;
+            if (c->budget && c->in_use + got > c->budget) break;
             *out = it->second.back();
             it->second.pop_back();
-            c->cached -= cls;
-            c->in_use += cls;
-            c->sizes[*out] = cls;
+            c->cache_tick.erase(*out);
+            c->sizes_cached.erase(*out);
+            c->cached -= got;
+            c->in_use += got;
+            c->sizes[*out] = got;
             return EV_OK;
         }
         // Live and cached blocks together stay below the device's free
         // memory: the driver accepts allocations beyond it and then moves
         // buffers out of HBM while kernels use them.
-        if (c->in_use + c->cached + cls > c->hold_limit) cache_release(c);
+        cache_trim(c, cls);
         if (c->in_use + cls > c->hold_limit)
             return fail(EV_ENOMEM, "device memory exhausted (%zu + %zu > %zu bytes held)", (size_t)c->in_use, cls,
                         (size_t)c->hold_limit);
@@ -117,6 +160,8 @@ void dev_free(ev_ctx* c, void* p)
     c->sizes.erase(it);
     c->in_use -= cls;
     c->cache[cls].push_back(p);
+    c->cache_tick[p] = c->tick++;
+    c->sizes_cached[p] = cls;
     c->cached += cls;
 }
 

@@ -131,6 +131,9 @@ struct ev_ctx {
     uint64_t hold_limit = ~0ull;  // live + cached bytes, below the device's free memory
     std::unordered_map<void*, size_t> sizes;   // live blocks and their size class
     std::map<size_t, std::vector<void*>> cache;  // freed blocks by size class
+    std::unordered_map<void*, uint64_t> cache_tick;    // cached block -> when it was freed
+    std::unordered_map<void*, size_t> sizes_cached;    // cached block -> its size class
+    uint64_t tick = 0;
     uint64_t cached = 0;
 
     std::mutex pop_mu;
