@@ -57,6 +57,8 @@ struct TreeLvl {
     uint32_t C;           // tokens per chunk (all but the last are full)
     uint32_t tree;
     uint32_t ref_base;    // its first input slot: the previous level's slot index
+    uint32_t rank_full;   // places of its work items in their length buckets:
+    uint32_t rank_last;   //   full chunks rank_full, rank_full + 1, ...; the last rank_last
 };
 
 // A tree's totals over its chunks at one level (device to host).
@@ -68,10 +70,9 @@ struct TreeSum {
     uint32_t pad;
 };
 
-// Per tree id: its bases over the level's chunks (host to device), and the
-// places of its work items in their length buckets: its full chunks (all
-// but the last) take rank_full, rank_full + 1, ... of theirs, its last
-// chunk rank_last of its own.
+// Per tree id: its bases over the level's chunks (made on the device from
+// the trees' totals), and its chunks and their places in the length
+// buckets (copied from its TreeLvl).
 struct TreeBase {
     uint64_t out, frag, code;
     uint32_t chunk_first, n_chunks;
@@ -81,6 +82,20 @@ struct TreeBase {
 // Work items, longest first: the number of buckets of the counting sort on
 // a length's bit count.
 constexpr uint32_t EV_LEN_BUCKETS = 33;
+
+// Levels a split plan may have.
+constexpr int EV_MAX_LEVELS = 64;
+
+// Where each tree's value ends up: its level's result rows, and its slot.
+struct FitArgs {
+    const float* res[EV_MAX_LEVELS + 1];
+    const uint32_t* fin;  // per tree: level, slot
+    const float* y;
+    int32_t N;
+    uint32_t M;
+    float* fit;
+    float* per_case;
+};
 
 struct SegFn {
     int32_t a, b;      // the segment maps cnt to max(cnt + a, b)

@@ -359,9 +359,12 @@ __device__ __forceinline__ uint32_t seg_count(uint32_t len, uint32_t seg_len, ui
 
 __global__ __launch_bounds__(64) void k_plan_chunks(const TreeLvl* __restrict__ trees, uint32_t n_trees,
                                                     uint32_t seg_len, uint32_t head, ChunkIn* __restrict__ ch,
-                                                    ChunkSegs* __restrict__ cg)
+                                                    ChunkSegs* __restrict__ cg, uint32_t* __restrict__ err_init,
+                                                    uint32_t n_err)
 {
     const uint32_t i = blockIdx.x;
+    if (i == 0 && err_init)  // the validator's words of every level: no flags, no failing segment
+        for (uint32_t k = threadIdx.x; k < n_err; k += blockDim.x) err_init[k] = (k & 1u) ? UINT32_MAX : 0u;
     if (i >= n_trees) return;
     const TreeLvl tl = trees[i];
     const uint32_t full = seg_count(tl.C, seg_len, head);
@@ -441,6 +444,44 @@ __global__ __launch_bounds__(64) void k_plan_trees(const TreeLvl* __restrict__ t
     }
     if (level == 0 && c_open != 0) bad |= 1u;
     if (lane == 0) sum[i] = TreeSum{c_out, c_frag, c_code, bad, maxtop, max_m, 0};
+}
+
+// One block: the trees' bases over the level's chunks, in sequence order
+// (which is tree order): exclusive sums of their slots, fragment tokens and
+// codes, stored by tree id with the tree's chunk range and bucket ranks.
+__global__ __launch_bounds__(1024) void k_plan_bases(const TreeLvl* __restrict__ trees, uint32_t n_trees,
+                                                     const TreeSum* __restrict__ sum, TreeBase* __restrict__ base)
+{
+    __shared__ uint64_t po[1024], pf[1024], pc[1024];
+    const uint32_t t = threadIdx.x;
+    const uint32_t per = (n_trees + 1023u) / 1024u;
+    const uint32_t i0 = t * per < n_trees ? t * per : n_trees, i1 = i0 + per < n_trees ? i0 + per : n_trees;
+    uint64_t so = 0, sf = 0, sc = 0;
+    for (uint32_t i = i0; i < i1; i++) {
+        so += sum[i].n_out;
+        sf += sum[i].n_frag;
+        sc += sum[i].n_codes;
+    }
+    po[t] = so;
+    pf[t] = sf;
+    pc[t] = sc;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024; d <<= 1) {
+        const uint64_t a = t >= d ? po[t - d] : 0, b = t >= d ? pf[t - d] : 0, c = t >= d ? pc[t - d] : 0;
+        __syncthreads();
+        po[t] += a;
+        pf[t] += b;
+        pc[t] += c;
+        __syncthreads();
+    }
+    uint64_t o = po[t] - so, f = pf[t] - sf, c = pc[t] - sc;
+    for (uint32_t i = i0; i < i1; i++) {
+        const TreeLvl tl = trees[i];
+        base[tl.tree] = TreeBase{o, f, c, tl.chunk_first, tl.n_chunks, tl.rank_full, tl.rank_last};
+        o += sum[i].n_out;
+        f += sum[i].n_frag;
+        c += sum[i].n_codes;
+    }
 }
 
 // Per chunk: its global numbering from its tree's bases, and its work item,
@@ -942,27 +983,26 @@ template __global__ void k_eval<128>(EvalArgs);
 //
 // Table 1: (1/N) sum |GP(x_i) - y_i|; the sum runs over i in ascending order
 // in binary32 (Sec. 2.2) and is then divided by (float)N.
-__global__ void k_fitness(const uint64_t* __restrict__ rows, const float* __restrict__ y, int32_t N, uint32_t M,
-                          float* __restrict__ fit, float* __restrict__ per_case)
+__global__ void k_fitness(FitArgs a)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= M) return;
-    const float* r = reinterpret_cast<const float*>(rows[t]);
+    if (t >= a.M) return;
+    const float* r = a.res[a.fin[2 * t]] + (size_t)a.fin[2 * t + 1] * (size_t)a.N;
     float s = 0.0f;
-    for (int32_t i = 0; i < N; i++) {
+    for (int32_t i = 0; i < a.N; i++) {
         const float v = r[i];
-        s = s + fabsf(v - y[i]);
-        if (per_case) per_case[(size_t)t * (size_t)N + i] = v;
+        s = s + fabsf(v - a.y[i]);
+        if (a.per_case) a.per_case[(size_t)t * (size_t)a.N + i] = v;
     }
-    fit[t] = s / (float)N;
+    a.fit[t] = s / (float)a.N;
 }
 
 // ---------------------------------------------------------------- crossover
 //
 // Sec. 3.1: the subtree rooted at p ends where the open-slot count started at
-// p first drops to zero.  One wave scans 256 tokens per step: each lane takes
-// four, the wave prefix-sums their net effect and the first lane whose
-// running minimum reaches zero holds the end.
+// p first drops to zero.  One wave scans 4096 tokens per step: each lane
+// takes 64, the wave prefix-sums their net effect, and the first lane whose
+// running count reaches zero holds the end.
 __global__ __launch_bounds__(64) void k_subtree_end(const uint8_t* __restrict__ buf, const uint64_t* __restrict__ base,
                                                     const uint64_t* __restrict__ pos, uint32_t n,
                                                     uint64_t* __restrict__ end_out)
@@ -1286,10 +1326,18 @@ hipError_t launch_seg_build(const ChunkIn* ch, const ChunkSegs* cg, uint32_t n, 
 }
 
 hipError_t launch_plan_chunks(const TreeLvl* trees, uint32_t n_trees, uint32_t seg_len, uint32_t head, ChunkIn* ch,
-                              ChunkSegs* cg, hipStream_t s)
+                              ChunkSegs* cg, uint32_t* err_init, uint32_t n_err, hipStream_t s)
 {
     if (n_trees == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_plan_chunks, dim3(n_trees), dim3(64), 0, s, trees, n_trees, seg_len, head, ch, cg);
+    hipLaunchKernelGGL(k_plan_chunks, dim3(n_trees), dim3(64), 0, s, trees, n_trees, seg_len, head, ch, cg, err_init,
+                       n_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_bases(const TreeLvl* trees, uint32_t n_trees, const TreeSum* sum, TreeBase* base, hipStream_t s)
+{
+    if (n_trees == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_plan_bases, dim3(1), dim3(1024), 0, s, trees, n_trees, sum, base);
     return hipGetLastError();
 }
 
@@ -1402,11 +1450,10 @@ hipError_t launch_run(const RunArgs& a, uint32_t grid, hipStream_t s)
 
 
 
-hipError_t launch_fitness(const uint64_t* rows, const float* y, int32_t N, uint32_t M, float* fit, float* per_case,
-                          hipStream_t s)
+hipError_t launch_fitness(const FitArgs& a, hipStream_t s)
 {
-    if (M == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fitness, dim3(cdiv(M, 64)), dim3(64), 0, s, rows, y, N, M, fit, per_case);
+    if (a.M == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fitness, dim3(cdiv(a.M, 64)), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

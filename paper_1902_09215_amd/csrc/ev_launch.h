@@ -9,7 +9,8 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
 hipError_t launch_seg_build(const ChunkIn* ch, const ChunkSegs* cg, uint32_t n, uint32_t seg_len, uint32_t head,
                             SegIn* seg, hipStream_t s);
 hipError_t launch_plan_chunks(const TreeLvl* trees, uint32_t n_trees, uint32_t seg_len, uint32_t head, ChunkIn* ch,
-                              ChunkSegs* cg, hipStream_t s);
+                              ChunkSegs* cg, uint32_t* err_init, uint32_t n_err, hipStream_t s);
+hipError_t launch_plan_bases(const TreeLvl* trees, uint32_t n_trees, const TreeSum* sum, TreeBase* base, hipStream_t s);
 hipError_t launch_plan_trees(const TreeLvl* trees, uint32_t n_trees, const ChunkStat* cs, uint32_t level,
                              uint64_t prev_out, uint64_t* code_loc, uint64_t* out_loc, uint64_t* frag_loc,
                              uint32_t* in_end, TreeSum* sum, hipStream_t s);
@@ -39,8 +40,7 @@ hipError_t run_occupancy(int* blocks_per_cu);
 hipError_t launch_run(const RunArgs& a, uint32_t grid, hipStream_t s);
 
 
-hipError_t launch_fitness(const uint64_t* rows, const float* y, int32_t N, uint32_t M, float* fit, float* per_case,
-                          hipStream_t s);
+hipError_t launch_fitness(const FitArgs& a, hipStream_t s);
 hipError_t launch_subtree_end(const uint8_t* buf, const uint64_t* base, const uint64_t* pos, uint32_t n,
                               uint64_t* end_out, hipStream_t s);
 hipError_t launch_xo_copy(const uint8_t* mums, const uint8_t* dads, const XoPlan* plan, const uint64_t* off,

@@ -184,14 +184,15 @@ void plan_free(ev_ctx* c, Plan& pl)
     pl.levels.clear();
     pl.fin_level.clear();
     pl.fin_slot.clear();
+    dev_free(c, pl.d_fin);
+    pl.d_fin = nullptr;
 }
 
 void rescache_free(ev_ctx* c, ResCache& r)
 {
     for (float* p : r.res) dev_free(c, p - (size_t)EV_RING * r.N);
     r.res.clear();
-    dev_free(c, r.d_rows);
-    r.d_rows = nullptr;
+
     dev_free(c, r.d_per_case);
     r.d_per_case = nullptr;
 }
@@ -278,16 +279,13 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
     // validator flags of every level, two words each (flags, first failing
     // segment), read back with the next level's totals or after the last
     // level, so that validation costs no wait of its own
-    constexpr int MAX_LEVELS = 64;
+    // (set by the first level's chunk kernel)
+    constexpr int MAX_LEVELS = EV_MAX_LEVELS;
+    constexpr uint32_t N_ERR = 2 * (MAX_LEVELS + 1);
     uint32_t verr[2] = {0, 0};
-    {
-        auto& e0 = W.err0;
-        e0.resize(2 * (MAX_LEVELS + 1));
-        for (size_t i = 0; i < e0.size(); i += 2) e0[i] = 0, e0[i + 1] = UINT32_MAX;
-        if ((st = dev_alloc(c, e0.size() * 4, &d_err)) || (st = put(x, d_err, e0.data(), e0.size() * 4))) {
-            cleanup();
-            return st;
-        }
+    if ((st = dev_alloc(c, N_ERR * 4, &d_err)) != EV_OK) {
+        cleanup();
+        return st;
     }
     auto code_error = [&](int lv, const uint32_t* e) -> ev_status {
         return fail(EV_EDEVICE, "internal: malformed code stream at level %d (flags %u, segment %u)", lv, e[0], e[1]);
@@ -295,7 +293,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
     auto& tl = W.tl;      // the level's trees
     auto& tsum = W.tsum;  // their totals
     auto& tb = W.tb;      // per tree id: its bases over the level's chunks
-    tb.resize((size_t)std::max(1, M) + 4);  // + the length buckets' first places
+    tb.resize((size_t)std::max(1, M));
     uint32_t hist[EV_LEN_BUCKETS];
     // work items go longest first, for the balance of the kernels' dynamic
     // work queues: a counting sort on the length's bit count (the order
@@ -338,14 +336,11 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             v.C = (uint32_t)Ct;
             v.tree = (uint32_t)t;
             v.ref_base = (uint32_t)ref_base[t];
-            tl.push_back(v);
             // the ranks of its work items in their length buckets
-            TreeBase& r = tb[t];
-            r.chunk_first = (uint32_t)n;
-            r.n_chunks = (uint32_t)nc;
-            r.rank_full = hist[bucket(Ct)];
+            v.rank_full = hist[bucket(Ct)];
             hist[bucket(Ct)] += (uint32_t)(nc - 1);
-            r.rank_last = hist[bucket(len - (nc - 1) * Ct)]++;
+            v.rank_last = hist[bucket(len - (nc - 1) * Ct)]++;
+            tl.push_back(v);
             n += nc;
             ns += (nc - 1) * nseg(Ct) + nseg(len - (nc - 1) * Ct);
             tokens += len;
@@ -357,14 +352,22 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         if (tl.empty()) break;
         const uint32_t nt = (uint32_t)tl.size(), n_seg = (uint32_t)ns;
 
+        // each length bucket's first place
+        uint32_t cursor[EV_LEN_BUCKETS];
+        for (uint32_t k = 0, a = 0; k < EV_LEN_BUCKETS; k++) {
+            cursor[k] = a;
+            a += hist[k];
+        }
         // device: chunks, segments, their counts, and each tree's numbering
-        if ((st = realloc(&d_tl, nt * sizeof(TreeLvl))) || (st = realloc(&d_ch, n * sizeof(ChunkIn))) ||
+        const size_t tl_bytes = nt * sizeof(TreeLvl);
+        if ((st = realloc(&d_tl, tl_bytes + sizeof(cursor))) || (st = realloc(&d_ch, n * sizeof(ChunkIn))) ||
             (st = realloc(&d_cseg, n * sizeof(ChunkSegs))) || (st = realloc(&d_seg, n_seg * sizeof(SegIn))) ||
             (st = realloc(&d_fn, n_seg * sizeof(SegFn))) || (st = realloc(&d_st, n_seg * sizeof(SegStart))) ||
             (st = realloc(&d_cnt, n_seg * sizeof(SegCount))) || (st = realloc(&d_stat, n * sizeof(ChunkStat))) ||
             (st = realloc(&d_loc, n * 3 * sizeof(uint64_t))) || (st = realloc(&d_inend, n * sizeof(uint32_t))) ||
             (st = realloc(&d_sum, nt * sizeof(TreeSum))) ||
-            (st = put(x, d_tl, tl.data(), nt * sizeof(TreeLvl)))) {
+            (st = realloc(&d_tb, (size_t)std::max(1, M) * sizeof(TreeBase))) ||
+            (st = put(x, d_tl, tl.data(), tl_bytes)) || (st = put(x, (uint8_t*)d_tl + tl_bytes, cursor, sizeof(cursor)))) {
             cleanup();
             return st;
         }
@@ -372,7 +375,8 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
         uint64_t* d_oloc = d_cloc + n;
         uint64_t* d_floc = d_oloc + n;
         const uint64_t prev_out = pl.levels.empty() ? 0 : pl.levels.back().n_out;
-        HIPCHK(launch_plan_chunks((TreeLvl*)d_tl, nt, seg_len, head, (ChunkIn*)d_ch, (ChunkSegs*)d_cseg, s));
+        HIPCHK(launch_plan_chunks((TreeLvl*)d_tl, nt, seg_len, head, (ChunkIn*)d_ch, (ChunkSegs*)d_cseg,
+                                  level == 0 ? (uint32_t*)d_err : nullptr, N_ERR, s));
         HIPCHK(launch_seg_build((ChunkIn*)d_ch, (ChunkSegs*)d_cseg, (uint32_t)n, seg_len, head, (SegIn*)d_seg, s));
         HIPCHK(launch_seg_fn(cur, (SegIn*)d_seg, n_seg, (SegFn*)d_fn, level == 0 ? TOK_X : TOK_REF, s));
         HIPCHK(launch_seg_scan((ChunkSegs*)d_cseg, (uint32_t)n, (SegFn*)d_fn, (SegStart*)d_st, (ChunkStat*)d_stat, s));
@@ -381,6 +385,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
                                 nullptr, nullptr, s));
         HIPCHK(launch_plan_trees((TreeLvl*)d_tl, nt, (ChunkStat*)d_stat, (uint32_t)level, prev_out, d_cloc, d_oloc,
                                  d_floc, (uint32_t*)d_inend, (TreeSum*)d_sum, s));
+        HIPCHK(launch_plan_bases((TreeLvl*)d_tl, nt, (TreeSum*)d_sum, (TreeBase*)d_tb, s));
         tsum.resize(nt);
         if ((st = get(x, tsum.data(), d_sum, nt * sizeof(TreeSum))) ||
             (level > 0 && (st = get(x, verr, (uint32_t*)d_err + 2 * (level - 1), 8))) || (st = sync(x))) {
@@ -466,31 +471,22 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             }
         }
 
-        // the chunks' numbering and work items (longest first: each length
-        // bucket's first place), then one pass writes the next level's
+        // the chunks' numbering and work items (longest first, from each
+        // length bucket's first place), then one pass writes the next level's
         // skeleton and this level's codes, and every code stream is
         // validated before anything may run it
-        uint32_t cursor[EV_LEN_BUCKETS];
-        for (uint32_t k = 0, a = 0; k < EV_LEN_BUCKETS; k++) {
-            cursor[k] = a;
-            a += hist[k];
-        }
-        static_assert(sizeof(cursor) <= 4 * sizeof(TreeBase), "bucket starts ride after the trees' bases");
-        std::memcpy(&tb[tb.size() - 4], cursor, sizeof(cursor));
         // emission writes every byte of the next skeleton, [0, sf); 64 bytes
         // of padding follow (written with the work items)
         uint8_t* d_next = nullptr;
         if (any && (st = dev_alloc(c, sf + 64, (void**)&d_next)) != EV_OK) { cleanup(); return st; }
-        const size_t tb_bytes = (size_t)std::max(1, M) * sizeof(TreeBase);
-        if ((st = realloc(&d_tb, tb.size() * sizeof(TreeBase))) || (st = realloc(&d_cb, n * sizeof(uint64_t))) ||
-            (st = realloc(&d_fe, n * sizeof(uint64_t))) || (st = realloc(&d_scode, n_seg * sizeof(uint64_t))) ||
-            (st = realloc(&d_sfrag, n_seg * sizeof(uint64_t))) || (st = put(x, d_tb, tb.data(), tb.size() * sizeof(TreeBase)))) {
+        if ((st = realloc(&d_cb, n * sizeof(uint64_t))) || (st = realloc(&d_fe, n * sizeof(uint64_t))) ||
+            (st = realloc(&d_scode, n_seg * sizeof(uint64_t))) || (st = realloc(&d_sfrag, n_seg * sizeof(uint64_t)))) {
             dev_free(c, d_next);
             cleanup();
             return st;
         }
         HIPCHK(launch_plan_items((ChunkIn*)d_ch, (uint32_t)n, (TreeBase*)d_tb, d_cloc, d_oloc, d_floc,
-                                 (uint32_t*)d_inend, (uint32_t*)((uint8_t*)d_tb + tb_bytes), (uint64_t*)d_cb,
+                                 (uint32_t*)d_inend, (uint32_t*)((uint8_t*)d_tl + tl_bytes), (uint64_t*)d_cb,
                                  (uint64_t*)d_fe, run_items ? LL.d_run : nullptr, run_items ? nullptr : LL.d_chunks,
                                  run_items ? LL.codes + sc : nullptr, any ? d_next + sf : nullptr, s));
         if (any || run_items) {
@@ -503,6 +499,17 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
                                         (SegCount*)d_cnt, LL.slab_entries, (uint32_t*)d_err + 2 * level, s));
         }
         if (!any) {
+            // where each tree's value is, for the fitness kernel
+            auto& fin = W.fin;
+            fin.resize(2 * (size_t)std::max(1, M));
+            for (int32_t t = 0; t < M; t++) {
+                fin[2 * (size_t)t] = (uint32_t)pl.fin_level[t];
+                fin[2 * (size_t)t + 1] = pl.fin_slot[t];
+            }
+            if ((st = dev_alloc(c, fin.size() * 4, (void**)&pl.d_fin)) || (st = put(x, pl.d_fin, fin.data(), fin.size() * 4))) {
+                cleanup();
+                return st;
+            }
             // the last level: its validation must pass before the plan is used
             if ((st = get(x, verr, (uint32_t*)d_err + 2 * level, 8)) || (st = sync(x))) {
                 cleanup();
@@ -755,17 +762,6 @@ ev_status rescache_build(ev_ctx* c, Exec& x, Pop* P, int32_t table, ResCache** o
         }
         r.res.push_back(p + (size_t)EV_RING * N);
     }
-    std::vector<uint64_t> rows(P->M);
-    for (int32_t t = 0; t < P->M; t++)
-        rows[t] = (uint64_t)(uintptr_t)(r.res[P->plan.fin_level[t]] + (size_t)P->plan.fin_slot[t] * N);
-    if ((st = dev_alloc(c, (size_t)std::max(1, P->M) * sizeof(uint64_t), (void**)&r.d_rows)) != EV_OK) {
-        rescache_free(c, r);
-        return st;
-    }
-    if ((st = put(x, r.d_rows, rows.data(), rows.size() * sizeof(uint64_t))) != EV_OK) {
-        rescache_free(c, r);
-        return st;
-    }
     P->res[table] = r;
     *out = &P->res[table];
     return EV_OK;
@@ -854,7 +850,15 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
         if (timed && li == 0) HIPCHK(hipEventRecord(x.evi1, s));
         if (timed) HIPCHK(hipEventRecord(x.evl[li], s));
     }
-    HIPCHK(launch_fitness(rc->d_rows, ct.d_y, N, (uint32_t)P->M, d_fit, d_per_case, s));
+    FitArgs fa = {};
+    for (size_t li = 0; li < nl; li++) fa.res[li] = rc->res[li];
+    fa.fin = P->plan.d_fin;
+    fa.y = ct.d_y;
+    fa.N = N;
+    fa.M = (uint32_t)P->M;
+    fa.fit = d_fit;
+    fa.per_case = d_per_case;
+    HIPCHK(launch_fitness(fa, s));
     if (timed) HIPCHK(hipEventRecord(x.ev1, s));
     return EV_OK;
 }

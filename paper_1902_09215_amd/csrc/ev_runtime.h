@@ -44,6 +44,7 @@ struct Plan {
     std::vector<Level> levels;
     std::vector<int32_t> fin_level;  // per tree: level holding its value
     std::vector<uint32_t> fin_slot;  // and the slot
+    uint32_t* d_fin = nullptr;       // both on the device: level, slot per tree
     uint32_t chunk = 0;
     int D = 64;
     uint64_t chunks_total = 0, slots_total = 0, max_stack = 0, bytes = 0;
@@ -53,7 +54,6 @@ struct Plan {
 struct ResCache {
     int32_t N = 0;
     std::vector<float*> res;     // per level: n_out * N floats (EV_RING padding rows before)
-    uint64_t* d_rows = nullptr;  // per tree: address of its N final values
     float* d_per_case = nullptr;
 };
 
@@ -74,7 +74,7 @@ struct Pop {
 struct PlanScratch {
     std::vector<uint64_t> rs, rl, prev_len, ref_base;
     std::vector<char> active;
-    std::vector<uint32_t> err0;
+    std::vector<uint32_t> fin;
     std::vector<TreeLvl> tl;
     std::vector<TreeSum> tsum;
     std::vector<TreeBase> tb;

@@ -184,6 +184,37 @@ def test_malformed_trees_are_rejected(ev):
             c.load(good, np.array([0, 0, good.size], np.uint64))
 
 
+def test_malformed_multi_chunk_trees_are_rejected(ev):
+    # Validity of trees split over many work items: the per-chunk counters are
+    # combined across chunk boundaries on the device (Sec. 2.2's slot count).
+    x, y = workloads.cases(48)
+    good = workloads.random_tree(2, 2, 4001)
+    mid = good.size // 2
+    cases = {
+        "truncated": good[:-1],
+        "two trees in one": np.concatenate([good, good]),
+        "leaf dropped mid-way": np.delete(good, mid + np.flatnonzero(good[mid:] == X)[0]),
+        "function dropped mid-way": np.delete(good, mid + np.flatnonzero(good[mid:] < X)[0]),
+        "bad opcode mid-way": np.concatenate([good[:mid], [9], good[mid + 1:]]).astype(np.uint8),
+    }
+    for chunk in (64, 1000):
+        with ev.Context(x, y) as c:
+            ev.ev_set_tuning(c.ctx, chunk, 0, 0, chunk)
+            for name, bad in cases.items():
+                trees = [good, bad.astype(np.uint8), good]
+                off = workloads.offsets_from_sizes([t.size for t in trees])
+                with pytest.raises(ev.EvError) as ei:
+                    c.load(np.concatenate(trees).astype(np.uint8), off)
+                assert ei.value.code == ev.EV_EMALFORMED, (name, chunk)
+                assert ei.value.bad_tree == 1, (name, chunk)
+            # the valid trees alone still load and match the oracle
+            trees = [good, good]
+            off = workloads.offsets_from_sizes([t.size for t in trees])
+            fit, _ = c.eval(c.load(np.concatenate(trees).astype(np.uint8), off))
+            ref = oracle.eval_population(np.concatenate(trees).astype(np.uint8), off, x, y)
+            assert_same(fit, ref, f"valid trees, chunk {chunk}")
+
+
 def test_crossover_matches_oracle(ev):
     x, y = workloads.cases(48)
     rng = np.random.default_rng(31)
