@@ -73,16 +73,32 @@ enum { EV_ADD = 0, EV_SUB = 1, EV_MUL = 2, EV_DIV = 3, EV_X = 4 };
                               the call returns once the work is queued on
                               the context's stream */
 
+/* Where the context's device memory comes from.  alloc(bytes, user) returns
+ * a block of device memory on the context's device, aligned to 256 bytes, or
+ * NULL when it has none; free(ptr, user) takes back a block alloc returned.
+ * The context keeps freed blocks for reuse (so a generation allocates
+ * nothing once the sizes have been seen) and hands a block back only after
+ * the work queued on its stream has finished.  Both may be called from the
+ * serving workers' threads. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+} ev_allocator;
+
 /* Create a context on HIP device `device` with case table 0: x[n_cases],
  * y[n_cases] (host pointers; the paper's fitness cases are x inputs with
  * their Sextic targets y = x^6 - 2x^4 + x^2, Sec. 3 and Table 1).
  * mem_budget_bytes bounds the device memory held by populations, plans and
  * jobs (0 = all the device has free at creation, less a margin; a larger
- * value is lowered to that).  stream is a hipStream_t to order all work on, or
- * NULL for a stream owned by the context.
- * Errors: EV_EINVAL (n_cases < 1, NULL pointers), EV_EDEVICE. */
+ * value is lowered to that).  alloc, if not NULL, supplies every device block
+ * the context holds (for example a framework's caching allocator); NULL uses
+ * hipMalloc/hipFree.  The struct is copied.  stream is a hipStream_t to order
+ * all work on, or NULL for a stream owned by the context.
+ * Errors: EV_EINVAL (n_cases < 1, NULL pointers, an allocator without both
+ * functions), EV_EDEVICE. */
 ev_status ev_create(ev_ctx **out, int device, const float *x, const float *y, int32_t n_cases,
-                    uint64_t mem_budget_bytes, void *stream);
+                    uint64_t mem_budget_bytes, const ev_allocator *alloc, void *stream);
 
 /* Add another case table (host x[n], y[n]); *table receives its index. */
 ev_status ev_add_cases(ev_ctx *ctx, const float *x, const float *y, int32_t n_cases, int32_t *table);
@@ -134,7 +150,9 @@ ev_status ev_crossover(ev_ctx *ctx, ev_pop mums_pop, ev_pop dads_pop, const int3
 
 /* One generation (Sec. 2.3, Sec. 3.1, Table 1) on the device: for every
  * child j of the n_trees children, tournaments of size `tournament` over
- * the parents' fitness from their last ev_eval_fitness pick mum and dad,
+ * the parents' fitness pick mum and dad (fitness: a device pointer to the
+ * parents' n_trees values, complete when the call is made, or NULL for those
+ * of their last ev_eval_fitness),
  * Philox4x32-10 draws keyed by (seed, gen, j) pick p and q uniformly over
  * all nodes, and the child is made by subtree crossover (size_cap as in
  * ev_crossover).  The draw layout is:
@@ -144,8 +162,8 @@ ev_status ev_crossover(ev_ctx *ctx, ev_pop mums_pop, ev_pop dads_pop, const int3
  *   purpose 0x300, p from (w1:w0) and q from (w3:w2), each mapped to
  *   [0, n) by the high 64 bits of the 128-bit product; better = lower MAE,
  *   NaN worst, ties keep the earlier candidate. */
-ev_status ev_generation(ev_ctx *ctx, ev_pop parents, uint64_t seed, uint64_t gen, int32_t tournament,
-                        uint64_t size_cap, ev_pop *out_children, int32_t *n_capped);
+ev_status ev_generation(ev_ctx *ctx, ev_pop parents, const float *fitness, uint64_t seed, uint64_t gen,
+                        int32_t tournament, uint64_t size_cap, ev_pop *out_children, int32_t *n_capped);
 
 /* ---- serving: continuously batched evaluation / crossover requests ---- */
 

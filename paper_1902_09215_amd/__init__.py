@@ -43,6 +43,14 @@ class ev_plan_info(ctypes.Structure):
                 ("max_stack", ctypes.c_uint64), ("plan_bytes", ctypes.c_uint64)]
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class ev_allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", ctypes.c_void_p)]
+
+
 class ev_job(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("table", ctypes.c_int32),
                 ("bytes", ctypes.c_void_p), ("off", ctypes.c_void_p), ("n_trees", ctypes.c_int32),
@@ -61,10 +69,18 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"libev.so not built ({path}); run __graft_entry__.build()")
+    # One HIP runtime per process: torch ships its own, and a process that
+    # loaded another one first cannot use torch's device memory (or torch at
+    # all) afterwards.  Loading torch first makes libev use torch's runtime,
+    # so device tensors and torch's caching allocator work with it.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P, i32, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
     sig = {
-        "ev_create": [ctypes.POINTER(P), ctypes.c_int, P, P, i32, u64, P],
+        "ev_create": [ctypes.POINTER(P), ctypes.c_int, P, P, i32, u64, ctypes.POINTER(ev_allocator), P],
         "ev_add_cases": [P, P, P, i32, ctypes.POINTER(i32)],
         "ev_destroy": [P],
         "ev_last_error": [],
@@ -74,7 +90,7 @@ def load_library(path: str = LIB_PATH):
         "ev_free_pop": [P, i32],
         "ev_eval_fitness": [P, i32, i32, P, P, u32],
         "ev_crossover": [P, i32, i32, P, P, P, P, i32, u64, ctypes.POINTER(i32), ctypes.POINTER(i32)],
-        "ev_generation": [P, i32, u64, u64, i32, u64, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "ev_generation": [P, i32, P, u64, u64, i32, u64, ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "ev_submit": [P, ctypes.POINTER(ev_job), ctypes.POINTER(u64)],
         "ev_poll": [P, u64, ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "ev_wait": [P, u64, ctypes.POINTER(i32)],
@@ -114,13 +130,36 @@ def _is_device(a) -> bool:
 
 # ---------------------------------------------------------------- C names
 
-def ev_create(x, y, device: int = 0, mem_budget: int = 0, stream: int | None = None):
+def ev_create(x, y, device: int = 0, mem_budget: int = 0, stream: int | None = None, allocator=None):
+    """allocator: None (hipMalloc), or an ev_allocator (see torch_allocator);
+    the caller keeps it alive for the context's lifetime."""
     lib = load_library()
     x = np.ascontiguousarray(x, np.float32)
     y = np.ascontiguousarray(y, np.float32)
     ctx = ctypes.c_void_p()
-    _check(lib.ev_create(ctypes.byref(ctx), device, _ptr(x), _ptr(y), x.size, mem_budget, stream))
+    _check(lib.ev_create(ctypes.byref(ctx), device, _ptr(x), _ptr(y), x.size, mem_budget,
+                         ctypes.byref(allocator) if allocator is not None else None, stream))
     return ctx
+
+
+def torch_allocator(device: int = 0):
+    """An ev_allocator drawing device blocks from torch's caching allocator
+    (``torch.cuda.caching_allocator_alloc`` / ``_delete``).  Keep the returned
+    object alive while a context uses it."""
+    import torch
+
+    def alloc(nbytes, _user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device)
+        except RuntimeError:
+            return None
+
+    def free(ptr, _user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = ev_allocator(_ALLOC_FN(alloc), _FREE_FN(free), None)
+    a._keep = (alloc, free)  # the Python functions behind the C callbacks
+    return a
 
 
 def ev_add_cases(ctx, x, y) -> int:
@@ -213,10 +252,13 @@ def ev_crossover(ctx, mums, dads, mum, dad, p, q, size_cap: int = 2**63):
     return out.value, capped.value
 
 
-def ev_generation(ctx, parents, seed: int, gen: int, tournament: int = 2, size_cap: int = 2**63):
+def ev_generation(ctx, parents, seed: int, gen: int, tournament: int = 2, size_cap: int = 2**63, fitness=None):
+    """fitness: a torch CUDA tensor of the parents' fitness, or None for the
+    values of their last evaluation."""
     out = ctypes.c_int32()
     capped = ctypes.c_int32()
-    _check(_lib.ev_generation(ctx, parents, seed, gen, tournament, size_cap, ctypes.byref(out), ctypes.byref(capped)))
+    _check(_lib.ev_generation(ctx, parents, _ptr(fitness), seed, gen, tournament, size_cap, ctypes.byref(out),
+                              ctypes.byref(capped)))
     return out.value, capped.value
 
 
@@ -312,8 +354,9 @@ def ev_last_timing(ctx):
 class Context:
     """Owns an ev_ctx; case table 0 is (x, y)."""
 
-    def __init__(self, x, y, device: int = 0, mem_budget: int = 0, stream: int | None = None):
-        self.ctx = ev_create(x, y, device, mem_budget, stream)
+    def __init__(self, x, y, device: int = 0, mem_budget: int = 0, stream: int | None = None, allocator=None):
+        self.allocator = allocator  # kept alive with the context
+        self.ctx = ev_create(x, y, device, mem_budget, stream, allocator)
         _table_sizes[(self.ctx.value, 0)] = int(np.asarray(x).size)
 
     def add_cases(self, x, y) -> int:

@@ -68,10 +68,29 @@ static size_t size_class(size_t bytes)
     return cls;
 }
 
+// Hand a cached block back: to the caller's allocator, once the context's
+// stream has finished every queued use of it (hipFree waits by itself).
+static void block_free(ev_ctx* c, void* p)
+{
+    if (c->ext.alloc) {
+        (void)hipStreamSynchronize(c->main.stream);
+        c->ext.free(p, c->ext.user);
+    } else {
+        (void)hipFree(p);
+    }
+}
+
+static hipError_t block_alloc(ev_ctx* c, void** out, size_t bytes)
+{
+    if (!c->ext.alloc) return hipMalloc(out, bytes);
+    *out = c->ext.alloc(bytes, c->ext.user);
+    return *out ? hipSuccess : hipErrorOutOfMemory;
+}
+
 static void cache_release(ev_ctx* c)
 {
     for (auto& kv : c->cache)
-        for (void* p : kv.second) (void)hipFree(p);
+        for (void* p : kv.second) block_free(c, p);
     c->cache.clear();
     c->cache_tick.clear();
     c->cached = 0;
@@ -95,7 +114,7 @@ static void cache_trim(ev_ctx* c, size_t need)
         c->cache_tick.erase(p);
         c->sizes_cached.erase(p);
         c->cached -= cls;
-        (void)hipFree(p);
+        block_free(c, p);
     }
 }
 
@@ -132,12 +151,12 @@ ev_status dev_alloc(ev_ctx* c, size_t bytes, void** out)
                         (size_t)c->hold_limit);
         c->in_use += cls;
     }
-    hipError_t e = hipMalloc(out, cls);
+    hipError_t e = block_alloc(c, out, cls);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         std::lock_guard<std::mutex> g(c->mem_mu);
         cache_release(c);
-        e = hipMalloc(out, cls);
+        e = block_alloc(c, out, cls);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             c->in_use -= cls;
@@ -973,9 +992,10 @@ static ev_status run_probe(ev_ctx* c);
 const char* ev_last_error(void) { return g_err.c_str(); }
 
 ev_status ev_create(ev_ctx** out, int device, const float* x, const float* y, int32_t n_cases,
-                    uint64_t mem_budget_bytes, void* stream)
+                    uint64_t mem_budget_bytes, const ev_allocator* alloc, void* stream)
 {
     if (!out || !x || !y || n_cases < 1) return fail(EV_EINVAL, "ev_create: bad arguments");
+    if (alloc && (!alloc->alloc || !alloc->free)) return fail(EV_EINVAL, "ev_create: allocator needs alloc and free");
     *out = nullptr;
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
@@ -983,6 +1003,7 @@ ev_status ev_create(ev_ctx** out, int device, const float* x, const float* y, in
     HIPCHK(hipSetDevice(device));
     ev_ctx* c = new ev_ctx();
     c->device = device;
+    if (alloc) c->ext = *alloc;
     c->budget = mem_budget_bytes;
     {
         size_t free_b = 0, total_b = 0;
@@ -1238,13 +1259,13 @@ ev_status ev_crossover(ev_ctx* c, ev_pop mums_pop, ev_pop dads_pop, const int32_
     return EV_OK;
 }
 
-ev_status ev_generation(ev_ctx* c, ev_pop parents, uint64_t seed, uint64_t gen, int32_t tournament,
-                        uint64_t size_cap, ev_pop* out, int32_t* n_capped)
+ev_status ev_generation(ev_ctx* c, ev_pop parents, const float* fitness, uint64_t seed, uint64_t gen,
+                        int32_t tournament, uint64_t size_cap, ev_pop* out, int32_t* n_capped)
 {
     if (!c || !out || tournament < 1) return fail(EV_EINVAL, "ev_generation: bad arguments");
     Pop* P = pop_get(c, parents);
     if (!P) return fail(EV_ENOTFOUND, "no population %d", parents);
-    if (!P->fit_valid) return fail(EV_EINVAL, "ev_generation: parents have no fitness yet");
+    if (!fitness && !P->fit_valid) return fail(EV_EINVAL, "ev_generation: parents have no fitness yet");
     HIPCHK(hipSetDevice(c->device));
     const int32_t M = P->M;
     void* d_sel = nullptr;
@@ -1254,7 +1275,8 @@ ev_status ev_generation(ev_ctx* c, ev_pop parents, uint64_t seed, uint64_t gen, 
     int32_t* d_dad = d_mum + std::max(1, M);
     uint64_t* d_p = (uint64_t*)((char*)d_sel + (size_t)std::max(1, M) * 8);
     uint64_t* d_q = d_p + std::max(1, M);
-    hipError_t e = launch_select(P->d_fit, P->d_off, (uint32_t)M, tournament, seed, gen, d_mum, d_dad, d_p, d_q, c->stream);
+    hipError_t e = launch_select(fitness ? fitness : P->d_fit, P->d_off, (uint32_t)M, tournament, seed, gen, d_mum,
+                                 d_dad, d_p, d_q, c->stream);
     if (e != hipSuccess) {
         dev_free(c, d_sel);
         return hip_fail(e, "selection");

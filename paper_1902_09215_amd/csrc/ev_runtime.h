@@ -127,6 +127,7 @@ struct ev_ctx {
     hipStream_t& stream = main.stream;  // the context's stream for the synchronous calls
 
     std::mutex mem_mu;
+    ev_allocator ext = {};     // the caller's allocator (ext.alloc == nullptr: hipMalloc)
     uint64_t budget = 0, in_use = 0;
     uint64_t hold_limit = ~0ull;  // live + cached bytes, below the device's free memory
     std::unordered_map<void*, size_t> sizes;   // live blocks and their size class

@@ -273,6 +273,77 @@ def test_generations_match_oracle(ev):
             pop, buf, off = kids, wbuf, woff
 
 
+def test_generation_with_caller_fitness(ev):
+    # ev_generation's tournaments over a caller-given device fitness vector:
+    # the same children as the oracle's generation over that vector.
+    import torch
+
+    x, y = workloads.cases(48)
+    buf, off = workloads.rhh_population(workloads.SEED_BASE + 6, 48, 2, 6)
+    seed, cap = 77, 15_000_000
+    with ev.Context(x, y) as c:
+        pop = c.load(buf, off)
+        fit, _ = c.eval(pop)
+        # the stored fitness and the same values passed in give one result
+        a, _ = ev.ev_generation(c.ctx, pop, seed, 0, 2, cap)
+        fit_dev = torch.from_numpy(fit).cuda()
+        torch.cuda.synchronize()
+        b, _ = ev.ev_generation(c.ctx, pop, seed, 0, 2, cap, fitness=fit_dev)
+        ab, ao = ev.ev_get_trees(c.ctx, a)
+        bb, bo = ev.ev_get_trees(c.ctx, b)
+        assert np.array_equal(ao, bo) and np.array_equal(ab, bb)
+        # another fitness vector (ranks reversed) selects other parents
+        other = (-fit).astype(np.float32)
+        other_dev = torch.from_numpy(other).cuda()
+        torch.cuda.synchronize()
+        k, capped = ev.ev_generation(c.ctx, pop, seed, 0, 2, cap, fitness=other_dev)
+        kb, ko = ev.ev_get_trees(c.ctx, k)
+    wbuf, woff, wcap = oracle.generation(buf, off, other, 2, seed, 0, cap)
+    assert capped == wcap
+    assert np.array_equal(ko, woff) and np.array_equal(kb, wbuf)
+    assert not (np.array_equal(ko, ao) and np.array_equal(kb, ab))
+
+
+def test_caller_allocator(ev):
+    # Every device block of a context can come from the caller's allocator
+    # (here torch's caching allocator); results are the same, and every block
+    # goes back by the time the context is destroyed.
+    import torch
+
+    x, y = workloads.cases(48)
+    sizes = workloads.loguniform_sizes(41, 200, 10, 50000)
+    buf, off = workloads.random_population(41, sizes)
+    calls = {"alloc": 0, "free": 0, "live": set()}
+
+    def alloc(nbytes, _user):
+        p = torch.cuda.caching_allocator_alloc(int(nbytes), 0)
+        calls["alloc"] += 1
+        calls["live"].add(p)
+        return p
+
+    def free(ptr, _user):
+        calls["free"] += 1
+        calls["live"].discard(ptr)
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = ev.ev_allocator(ev._ALLOC_FN(alloc), ev._FREE_FN(free), None)
+    with ev.Context(x, y) as c0:
+        pop = c0.load(buf, off)
+        want, wpc = c0.eval(pop, per_case=True)
+        k0, _ = ev.ev_generation(c0.ctx, pop, 5, 1, 2, 10**7)
+        wk, _ = c0.eval(k0)
+    with ev.Context(x, y, allocator=a) as c:
+        pop = c.load(buf, off)
+        got, gpc = c.eval(pop, per_case=True)
+        k, _ = ev.ev_generation(c.ctx, pop, 5, 1, 2, 10**7)
+        gk, _ = c.eval(k)
+    assert calls["alloc"] > 0
+    assert calls["free"] == calls["alloc"] and not calls["live"]
+    assert_same(got, want, "fitness")
+    assert_same(gpc, wpc, "per-case")
+    assert_same(gk, wk, "children's fitness")
+
+
 def test_generation_loop_1000_generations(ev):
     # The full generational loop on the device: population 48, ramped
     # half-and-half start, size-2 tournaments, Philox points, 15e6-node cap,
