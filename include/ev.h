@@ -131,10 +131,13 @@ ev_status ev_free_pop(ev_ctx *ctx, ev_pop pop);
 /* Evaluate every tree of pop on case table `table` (Sec. 2.2, one pass
  * over each tree for all cases) and compute its fitness (Table 1).
  * fitness[n_trees] receives the MAE, per_case[n_trees * N] (nullable) the
- * tree outputs, row-major by tree.  Host pointers unless EV_OUT_DEVICE.
- * The fitness is also kept with the population for ev_generation. */
+ * tree outputs, row-major by tree, and hits[n_trees] (nullable) the number of
+ * cases within 0.01 of the target (Sec. 3.2: |out - y| <= 0.01f with the
+ * fitness's own binary32 error term; reported only, not used by selection).
+ * Host pointers unless EV_OUT_DEVICE.  The fitness is also kept with the
+ * population for ev_generation. */
 ev_status ev_eval_fitness(ev_ctx *ctx, ev_pop pop, int32_t table, float *fitness, float *per_case,
-                          uint32_t flags);
+                          int32_t *hits, uint32_t flags);
 
 /* Subtree crossover (Sec. 3.1) with caller-chosen parents and points.
  * Child j = crossover(mums_pop tree mum[j] at point p[j],

@@ -41,6 +41,8 @@ def _load():
     lib.or_eval_cases.restype = ctypes.c_int
     lib.or_fitness.argtypes = [P, P, i32]
     lib.or_fitness.restype = ctypes.c_float
+    lib.or_hits.argtypes = [P, P, i32]
+    lib.or_hits.restype = ctypes.c_int32
     lib.or_eval_population.argtypes = [P, P, i32, P, P, i32, P, P, i32]
     lib.or_eval_population.restype = ctypes.c_int64
     lib.or_subtree_end.argtypes = [P, u64, u64]
@@ -102,6 +104,14 @@ def eval_population(buf, off, x, y, threads: int = 1, per_case: bool = False):
     if rc != 0:
         raise ValueError(f"tree {-rc - 1} invalid")
     return (fit, pc) if per_case else fit
+
+
+def hits(per_case, y) -> np.ndarray:
+    """Hits of each tree from its per-case outputs (Sec. 3.2)."""
+    pc = np.ascontiguousarray(per_case, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    lib = _load()
+    return np.array([lib.or_hits(_p(pc[t]), _p(y), y.size) for t in range(pc.shape[0])], np.int32)
 
 
 def subtree_end(tree, p: int) -> int:

@@ -89,6 +89,14 @@ float or_fitness(const float *out, const float *y, int32_t N)
     return s / (float)N;
 }
 
+int32_t or_hits(const float *out, const float *y, int32_t N)
+{
+    int32_t h = 0;
+    for (int32_t i = 0; i < N; i++)
+        if (fabsf(out[i] - y[i]) <= 0.01f) h++;
+    return h;
+}
+
 typedef struct {
     const uint8_t *buf;
     const uint64_t *off;

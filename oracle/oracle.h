@@ -42,6 +42,10 @@ int or_eval_cases(const uint8_t *t, uint64_t n, const float *x, int32_t N, float
  * plain loop (Sec. 2.2 last paragraph, Sec. 3.2, Table 1). */
 float or_fitness(const float *out, const float *y, int32_t N);
 
+/* Hits (Sec. 3.2, reported only): the cases whose absolute error, the same
+ * binary32 term the fitness sums, is at most 0.01 (a NaN error is no hit). */
+int32_t or_hits(const float *out, const float *y, int32_t N);
+
 /* Population: fitness[M], per_case[M*N] (nullable).  threads >= 1 assigns
  * trees to threads dynamically (Sec. 2.3); results do not depend on it.
  * Returns 0, or -(t+1) for the first tree t that failed. */

@@ -88,7 +88,7 @@ def load_library(path: str = LIB_PATH):
         "ev_pop_info": [P, i32, ctypes.POINTER(i32), ctypes.POINTER(u64)],
         "ev_get_trees": [P, i32, P, P, u64],
         "ev_free_pop": [P, i32],
-        "ev_eval_fitness": [P, i32, i32, P, P, u32],
+        "ev_eval_fitness": [P, i32, i32, P, P, P, u32],
         "ev_crossover": [P, i32, i32, P, P, P, P, i32, u64, ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "ev_generation": [P, i32, P, u64, u64, i32, u64, ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "ev_submit": [P, ctypes.POINTER(ev_job), ctypes.POINTER(u64)],
@@ -217,20 +217,24 @@ def ev_free_pop(ctx, pop):
     _check(_lib.ev_free_pop(ctx, pop))
 
 
-def ev_eval_fitness(ctx, pop, table: int = 0, per_case: bool = False, out=None, out_per_case=None):
-    """Host results (numpy) by default; pass torch cuda tensors as out /
-    out_per_case to receive device results without a host copy."""
+def ev_eval_fitness(ctx, pop, table: int = 0, per_case: bool = False, out=None, out_per_case=None,
+                    hits: bool = False, out_hits=None):
+    """Host results (numpy) by default: (fitness, per_case or None), plus the
+    hits (int32 per tree) when hits=True.  Pass torch cuda tensors as out /
+    out_per_case / out_hits to receive device results without a host copy."""
     if out is not None:
-        _check(_lib.ev_eval_fitness(ctx, pop, table, _ptr(out), _ptr(out_per_case), EV_OUT_DEVICE))
-        return out, out_per_case
+        _check(_lib.ev_eval_fitness(ctx, pop, table, _ptr(out), _ptr(out_per_case), _ptr(out_hits), EV_OUT_DEVICE))
+        return (out, out_per_case, out_hits) if out_hits is not None else (out, out_per_case)
     n, _ = ev_pop_info(ctx, pop)
     fit = np.empty(max(n, 1), np.float32)
     pc = None
     if per_case:
         N = _table_n(ctx, table)
         pc = np.empty((max(n, 1), N), np.float32)
-    _check(_lib.ev_eval_fitness(ctx, pop, table, _ptr(fit), _ptr(pc), 0))
-    return (fit[:n], pc[:n] if pc is not None else None)
+    h = np.empty(max(n, 1), np.int32) if hits else None
+    _check(_lib.ev_eval_fitness(ctx, pop, table, _ptr(fit), _ptr(pc), _ptr(h), 0))
+    res = (fit[:n], pc[:n] if pc is not None else None)
+    return res + (h[:n],) if hits else res
 
 
 _table_sizes: dict = {}
@@ -370,8 +374,8 @@ class Context:
     def load(self, buf, off) -> int:
         return ev_load_trees(self.ctx, buf, off)
 
-    def eval(self, pop, table: int = 0, per_case: bool = False):
-        return ev_eval_fitness(self.ctx, pop, table, per_case)
+    def eval(self, pop, table: int = 0, per_case: bool = False, hits: bool = False):
+        return ev_eval_fitness(self.ctx, pop, table, per_case, hits=hits)
 
     def close(self):
         if self.ctx is not None:

@@ -95,6 +95,7 @@ struct FitArgs {
     uint32_t M;
     float* fit;
     float* per_case;
+    int32_t* hits;  // nullable: per tree, the cases within 0.01 of the target
 };
 
 struct SegFn {

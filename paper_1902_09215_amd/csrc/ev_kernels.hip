@@ -989,12 +989,16 @@ __global__ void k_fitness(FitArgs a)
     if (t >= a.M) return;
     const float* r = a.res[a.fin[2 * t]] + (size_t)a.fin[2 * t + 1] * (size_t)a.N;
     float s = 0.0f;
+    int32_t h = 0;
     for (int32_t i = 0; i < a.N; i++) {
         const float v = r[i];
-        s = s + fabsf(v - a.y[i]);
+        const float e = fabsf(v - a.y[i]);
+        s = s + e;
+        h += e <= 0.01f ? 1 : 0;  // a hit (Sec. 3.2); a NaN error is none
         if (a.per_case) a.per_case[(size_t)t * (size_t)a.N + i] = v;
     }
     a.fit[t] = s / (float)a.N;
+    if (a.hits) a.hits[t] = h;
 }
 
 // ---------------------------------------------------------------- crossover

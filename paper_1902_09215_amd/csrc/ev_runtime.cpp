@@ -225,6 +225,7 @@ void pop_free(ev_ctx* c, Pop* P)
     dev_free(c, P->d_bytes);
     dev_free(c, P->d_off);
     dev_free(c, P->d_fit);
+    dev_free(c, P->d_hits);
     delete P;
 }
 
@@ -788,7 +789,8 @@ ev_status rescache_build(ev_ctx* c, Exec& x, Pop* P, int32_t table, ResCache** o
 
 // Queue the evaluation of P on table on c->stream; fit/per_case are device
 // pointers (per_case nullable).
-ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, float* d_per_case, bool timed)
+ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, float* d_per_case, bool timed,
+                       int32_t* d_hits)
 {
     const CaseTable& ct = c->tables[table];
     const int32_t N = ct.N;
@@ -877,6 +879,7 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
     fa.M = (uint32_t)P->M;
     fa.fit = d_fit;
     fa.per_case = d_per_case;
+    fa.hits = d_hits;
     HIPCHK(launch_fitness(fa, s));
     if (timed) HIPCHK(hipEventRecord(x.ev1, s));
     return EV_OK;
@@ -1208,7 +1211,8 @@ ev_status ev_free_pop(ev_ctx* c, ev_pop pop)
     return EV_OK;
 }
 
-ev_status ev_eval_fitness(ev_ctx* c, ev_pop pop, int32_t table, float* fitness, float* per_case, uint32_t flags)
+ev_status ev_eval_fitness(ev_ctx* c, ev_pop pop, int32_t table, float* fitness, float* per_case, int32_t* hits,
+                          uint32_t flags)
 {
     if (!c || !fitness) return fail(EV_EINVAL, "ev_eval_fitness: bad arguments");
     Pop* P = pop_get(c, pop);
@@ -1231,7 +1235,19 @@ ev_status ev_eval_fitness(ev_ctx* c, ev_pop pop, int32_t table, float* fitness, 
             d_pc = rc->d_per_case;
         }
     }
-    ev_status st = eval_enqueue(c, c->main, P, table, P->d_fit, d_pc, true);
+    int32_t* d_hits = nullptr;
+    if (hits) {
+        if (flags & EV_OUT_DEVICE) {
+            d_hits = hits;
+        } else {
+            if (!P->d_hits) {
+                ev_status st = dev_alloc(c, (size_t)std::max(1, P->M) * sizeof(int32_t), (void**)&P->d_hits);
+                if (st != EV_OK) return st;
+            }
+            d_hits = P->d_hits;
+        }
+    }
+    ev_status st = eval_enqueue(c, c->main, P, table, P->d_fit, d_pc, true, d_hits);
     if (st != EV_OK) return st;
     P->fit_valid = true;
     if (flags & EV_OUT_DEVICE) {
@@ -1240,6 +1256,7 @@ ev_status ev_eval_fitness(ev_ctx* c, ev_pop pop, int32_t table, float* fitness, 
     }
     if ((st = get(c->main, fitness, P->d_fit, (size_t)P->M * 4)) != EV_OK) return st;
     if (per_case && (st = get(c->main, per_case, d_pc, (size_t)P->M * N * 4)) != EV_OK) return st;
+    if (hits && (st = get(c->main, hits, d_hits, (size_t)P->M * 4)) != EV_OK) return st;
     return sync(c->main);
 }
 
@@ -1344,7 +1361,7 @@ ev_status ev_autotune(ev_ctx* c, ev_pop pop, int32_t table, int32_t reps, uint32
         if (st != EV_OK) return st;
         std::vector<float> t;
         for (int32_t r = 0; r <= reps; r++) {  // the first run warms the caches
-            if ((st = eval_enqueue(c, x, P, table, P->d_fit, nullptr, true)) != EV_OK) return st;
+            if ((st = eval_enqueue(c, x, P, table, P->d_fit, nullptr, true, nullptr)) != EV_OK) return st;
             if ((st = sync(x)) != EV_OK) return st;
             float ms = 0;
             HIPCHK(hipEventElapsedTime(&ms, x.ev0, x.ev1));

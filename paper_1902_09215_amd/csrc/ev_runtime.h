@@ -65,6 +65,7 @@ struct Pop {
     uint64_t total = 0;
     Plan plan;
     float* d_fit = nullptr;
+    int32_t* d_hits = nullptr;  // the last evaluation's hits, when asked for
     bool fit_valid = false;
     std::map<int32_t, ResCache> res;
 };
@@ -170,7 +171,8 @@ ev_status pop_build(ev_ctx* c, Exec& x, uint8_t* d_bytes, const std::vector<uint
 ev_pop pop_register(ev_ctx* c, Pop* P);
 Pop* pop_get(ev_ctx* c, ev_pop id);
 
-ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, float* d_per_case, bool timed);
+ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, float* d_per_case, bool timed,
+                       int32_t* d_hits);
 ev_status crossover_build(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const int32_t* mum, const int32_t* dad,
                           const uint64_t* p, const uint64_t* q, int32_t n, uint64_t cap, Pop** out,
                           int32_t* n_capped);

@@ -118,7 +118,7 @@ static ev_status run_eval_batch(ev_ctx* c, Exec& x, std::vector<Job*>& batch)
         }
     }
     if (st == EV_OK) st = dev_alloc(c, (size_t)std::max(1, M) * N * sizeof(float), (void**)&d_pc);
-    if (st == EV_OK) st = eval_enqueue(c, x, P, table, P->d_fit, d_pc, false);
+    if (st == EV_OK) st = eval_enqueue(c, x, P, table, P->d_fit, d_pc, false, nullptr);
     if (st == EV_OK) st = get(x, fit.data(), P->d_fit, (size_t)M * 4);
     if (st == EV_OK) st = get(x, pc.data(), d_pc, (size_t)M * N * 4);
     if (st == EV_OK) st = sync(x);
@@ -149,7 +149,7 @@ static ev_status run_crossover(ev_ctx* c, Exec& x, Job* j)
     const int32_t N = c->tables[j->table].N;
     float* d_pc = nullptr;
     st = dev_alloc(c, (size_t)std::max(1, C->M) * N * sizeof(float), (void**)&d_pc);
-    if (st == EV_OK) st = eval_enqueue(c, x, C, j->table, C->d_fit, d_pc, false);
+    if (st == EV_OK) st = eval_enqueue(c, x, C, j->table, C->d_fit, d_pc, false, nullptr);
     if (st == EV_OK) {
         j->fitness.resize(C->M);
         j->per_case.resize((size_t)C->M * N);

@@ -46,18 +46,21 @@ def run(ev, buf, off, x, y, chunk=0, lds=0, per_case=True, flags=0, chunk_hi=0):
             ev.ev_set_tuning(c.ctx, chunk, lds, flags, chunk_hi)
         pop = c.load(buf, off)
         info = ev.ev_get_plan_info(c.ctx, pop)
-        fit, pc = c.eval(pop, per_case=per_case)
-    return fit, pc, info
+        fit, pc, hits = c.eval(pop, per_case=per_case, hits=True)
+    return fit, pc, info, hits
 
 
 def check(ev, buf, off, x, y, chunk=0, lds=0, threads=8, what="", both=True, chunk_hi=0):
-    """Both interpreters (register-stack and general) against the oracle."""
+    """Both interpreters (register-stack and general) against the oracle:
+    per-case values, fitness and hits."""
     want_fit, want_pc = oracle.eval_population(buf, off, x, y, threads=threads, per_case=True)
+    want_hits = oracle.hits(want_pc, y)
     info = None
     for flags in ((0, ev.EV_TUNE_NO_REGSTACK) if both else (0,)):
-        fit, pc, inf = run(ev, buf, off, x, y, chunk, lds, flags=flags, chunk_hi=chunk_hi)
+        fit, pc, inf, hits = run(ev, buf, off, x, y, chunk, lds, flags=flags, chunk_hi=chunk_hi)
         assert_same(pc, want_pc, f"per-case {what} flags={flags}")
         assert_same(fit, want_fit, f"fitness {what} flags={flags}")
+        assert np.array_equal(hits, want_hits), f"hits {what} flags={flags}"
         info = info or inf
     return info
 
@@ -145,9 +148,10 @@ def test_batched_workload_full_size(ev):
     buf, off, n = workloads.workload("batched")
     x, y = workloads.cases(n)
     print(f"batched: {int(off[-1])} nodes", flush=True)
-    want_fit = oracle.eval_population(buf, off, x, y, threads=16)
-    fit, _, info = run(ev, buf, off, x, y, per_case=False)
+    want_fit, want_pc = oracle.eval_population(buf, off, x, y, threads=16, per_case=True)
+    fit, _, info, hits = run(ev, buf, off, x, y, per_case=False)
     assert_same(fit, want_fit, "batched fitness")
+    assert np.array_equal(hits, oracle.hits(want_pc, y)), "batched hits"
 
 
 def test_repeatable(ev):
@@ -269,6 +273,31 @@ def test_generations_match_oracle(ev):
             fit, _ = c.eval(kids)
             wfit = oracle.eval_population(wbuf, woff, x, y, threads=8)
             assert_same(fit, wfit, f"gen {g + 1} fitness")
+            ev.ev_free_pop(c.ctx, pop)
+            pop, buf, off = kids, wbuf, woff
+
+
+def test_generations_tournament_7_population_500(ev):
+    # Table 1's tournament size (7) on a population of 500: trees, fitness and
+    # hits bit-identical to the oracle's generations.
+    x, y = workloads.cases(48)
+    buf, off = workloads.rhh_population(workloads.SEED_BASE + 7, 500, 2, 6)
+    seed, gens, cap = 4242, 12, 15_000_000
+    with ev.Context(x, y) as c:
+        pop = c.load(buf, off)
+        fit, _ = c.eval(pop)
+        wfit = oracle.eval_population(buf, off, x, y, threads=8)
+        assert_same(fit, wfit, "gen 0")
+        for g in range(gens):
+            kids, capped = ev.ev_generation(c.ctx, pop, seed, g, 7, cap)
+            wbuf, woff, wcap = oracle.generation(buf, off, wfit, 7, seed, g, cap)
+            gbuf, goff = ev.ev_get_trees(c.ctx, kids)
+            assert capped == wcap
+            assert np.array_equal(goff, woff) and np.array_equal(gbuf, wbuf), f"gen {g} trees"
+            fit, _, hits = c.eval(kids, hits=True)
+            wfit, wpc = oracle.eval_population(wbuf, woff, x, y, threads=8, per_case=True)
+            assert_same(fit, wfit, f"gen {g + 1} fitness")
+            assert np.array_equal(hits, oracle.hits(wpc, y)), f"gen {g + 1} hits"
             ev.ev_free_pop(c.ctx, pop)
             pop, buf, off = kids, wbuf, woff
 

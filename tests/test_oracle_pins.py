@@ -234,6 +234,25 @@ def test_exact_sextic_trees():
         assert np.max(np.abs(out.astype(np.float64) - y64)) <= 4 * bound
 
 
+def test_hits_closed_forms():
+    # Sec. 3.2: a hit is a case within 0.01 of the target (reading S18:
+    # |out - y| <= 0.01f on the fitness's own binary32 error term).
+    x, y = workloads.cases(48)
+    zero = oracle.eval_cases(parse("- x x"), x)
+    want = int(np.count_nonzero(np.abs(y) <= np.float32(0.01)))
+    assert oracle.hits(zero[None, :], y)[0] == want
+    assert 0 < want < 48  # the constant 0 is close to the target only near x = 0 and x = +-1
+    # both exact Sextic trees are solutions: 48 hits (Sec. 4: "48 out of 48")
+    for name, tree in load_sextic().items():
+        out = oracle.eval_cases(tree, x)
+        assert oracle.hits(out[None, :], y)[0] == 48, name
+    # the boundary is inclusive; NaN is never a hit
+    t = np.zeros(3, np.float32)
+    edge = np.array([[0.01, np.nextafter(np.float32(0.01), np.float32(1)), np.nan]], np.float32)
+    assert oracle.hits(edge, t)[0] == 1
+    assert oracle.hits(-edge, t)[0] == 1
+
+
 def test_fitness_sums_in_ascending_order():
     # e = |0 - y| with y = [1e8, 1, 1, ...]: ascending binary32 sum stays 1e8
     # (each +1 rounds away), a reversed sum would reach 1e8 + 48.
