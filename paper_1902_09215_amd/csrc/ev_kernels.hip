@@ -128,7 +128,8 @@ struct Sink {
         }
     }
     // Fusions: a push or load of x then a function of x (CH, LCH); two
-    // pushes of x (PUSH2X); two pops by + - * in a row (OPSab).
+    // pushes of x (PUSH2X), which waits in turn for a function of x
+    // (PXCH: push x, push op(x, x)); two pops by + - * in a row (OPSab).
     __device__ void code(uint32_t kind)
     {
         if (pending != ~0u) {
@@ -138,9 +139,13 @@ struct Sink {
                 put((p == EV_K_PUSHX ? EV_K_CH0 : EV_K_LCH0) + (kind - EV_K_OPX0));
                 return;
             }
-            if (p == EV_K_PUSHX && kind == EV_K_PUSHX) {
+            if (p == EV_K_PUSH2X && kind >= EV_K_OPX0 && kind <= EV_K_OPX3) {
                 pending = ~0u;
-                put(EV_K_PUSH2X);
+                put(EV_K_PXCH0 + (kind - EV_K_OPX0));
+                return;
+            }
+            if (p == EV_K_PUSHX && kind == EV_K_PUSHX) {
+                pending = EV_K_PUSH2X;
                 return;
             }
             if (p <= EV_K_OPS2 && kind <= EV_K_OPS2) {
@@ -175,16 +180,18 @@ struct Sink {
     {
         const uint32_t p = pending;
         const bool none = kind == ~0u;
-        const bool ch = (p == EV_K_PUSHX || p == EV_K_LOADX) && kind - EV_K_OPX0 < 4u;
-        const bool xx = p == EV_K_PUSHX && kind == EV_K_PUSHX;
+        const bool opx = kind - EV_K_OPX0 < 4u;
+        const bool ch = (p == EV_K_PUSHX || p == EV_K_LOADX) && opx;
+        const bool pxch = p == EV_K_PUSH2X && opx;
+        const bool xx = p == EV_K_PUSHX && kind == EV_K_PUSHX;  // fused into a pending PUSH2X
         const bool ops = p <= EV_K_OPS2 && kind <= EV_K_OPS2;
-        const bool fused = ch || xx || ops;
+        const bool fused = ch || pxch || ops;
         const uint32_t fk = ch ? (p == EV_K_PUSHX ? EV_K_CH0 : EV_K_LCH0) + (kind - EV_K_OPX0)
-                               : (xx ? EV_K_PUSH2X : EV_K_OPS00 + p * 3u + kind);
+                               : (pxch ? EV_K_PXCH0 + (kind - EV_K_OPX0) : EV_K_OPS00 + p * 3u + kind);
         const bool defer = kind == EV_K_PUSHX || kind == EV_K_LOADX || kind <= EV_K_OPS2;
-        const uint32_t e1 = none ? ~0u : (fused ? fk : p);
-        const uint32_t e2 = (none || fused || defer) ? ~0u : kind;
-        pending = none ? p : ((fused || !defer) ? ~0u : kind);
+        const uint32_t e1 = (none || xx) ? ~0u : (fused ? fk : p);
+        const uint32_t e2 = (none || xx || fused || defer) ? ~0u : kind;
+        pending = none ? p : (xx ? EV_K_PUSH2X : ((fused || !defer) ? ~0u : kind));
         put_if(e1);
         put_if(e2);
     }
@@ -789,7 +796,8 @@ __global__ void k_seg_check(const uint32_t* __restrict__ codes, const SegIn* __r
             const bool lref = k >= EV_K_LOADREF0 && k < EV_K_LOADREF0 + EV_RING;
             const bool push1 = (k >= EV_K_CH0 && k <= EV_K_CH3) || k == EV_K_PUSHX || pref;
             const int32_t need = ops1 ? 1 : (ops2 ? 2 : 0);
-            const int32_t d = ops1 ? -1 : ops2 ? -2 : push1 ? 1 : (k == EV_K_PUSH2X ? 2 : 0);
+            const bool push2 = k == EV_K_PUSH2X || (k >= EV_K_PXCH0 && k <= EV_K_PXCH3);
+            const int32_t d = ops1 ? -1 : ops2 ? -2 : push1 ? 1 : (push2 ? 2 : 0);
             uint32_t w = idx < need ? 1u : 0u;
             // a REF's ring slot follows from its index within the work item
             const uint32_t slot = (ref0 + ins) & (EV_RING - 1);

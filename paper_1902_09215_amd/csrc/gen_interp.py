@@ -63,7 +63,8 @@ KINDS = ["OPS0", "OPS1", "OPS2", "OPS3", "OPX0", "OPX1", "OPX2", "OPX3",
          "CH0", "CH1", "CH2", "CH3", "LCH0", "LCH1", "LCH2", "LCH3",
          "PUSHX", "LOADX", "OUTT", "OUTX", "FLUSH", "OUTBOT", "END",
          "SPILL", "FILL", "OUTMEM", "PUSH2X"] + [f"OPS{a}{b}" for a in range(3) for b in range(3)] \
-    + [f"PUSHREF{r}" for r in range(RING)] + [f"LOADREF{r}" for r in range(RING)]
+    + [f"PUSHREF{r}" for r in range(RING)] + [f"LOADREF{r}" for r in range(RING)] \
+    + ["PXCH0", "PXCH1", "PXCH2", "PXCH3"]
 NK = len(KINDS)
 TBASE = (POS - 2) * NK * NSTRIDE  # first byte of the position-15 and -31 handlers
 TABLE_BYTES = TBASE + 2 * NK * TSTRIDE
@@ -172,6 +173,14 @@ def handler(kind: str, pos: int) -> list[str]:
     elif k == "PUSH2X":
         body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v13, %[x]", "v_mov_b32_e32 v14, %[x]",
                 "s_add_u32 s55, s55, 2"]
+    elif k.startswith("PXCH"):
+        op = int(k[4])
+        # two pushes of x, then a function of x: push x; push op(x, x)
+        if op == 3:
+            routine = "divpxch"
+        else:
+            body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v13, %[x]", f"{VOP[op]} v14, %[x], %[x]",
+                    "s_add_u32 s55, s55, 2"]
     elif k == "LOADX":
         body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v12, %[x]"]
     elif k in ("OUTT", "OUTBOT", "SPILL", "FILL", "OUTMEM") or k.startswith("PUSHREF") or k.startswith("LOADREF"):
@@ -200,12 +209,14 @@ def routines() -> list[str]:
             "v_mov_b32_e32 v4, %[x]"]
     out += DIV_BODY.splitlines()
     out += ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v12, v6", "s_setpc_b64 s[44:45]"]
-    for name, dst, inc in (("divch", "v13", True), ("divlch", "v12", False)):
+    for name, dst, inc in (("divch", "v13", 1), ("divlch", "v12", 0), ("divpxch", "v14", 2)):
         out += [f".L{name}%=:", "s_set_gpr_idx_off", "v_mov_b32_e32 v4, %[x]", "v_mov_b32_e32 v5, %[x]"]
         out += DIV_BODY.splitlines()
         out += ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {dst}, v6"]
+        if name == "divpxch":
+            out += ["v_mov_b32_e32 v13, %[x]"]
         if inc:
-            out += ["s_add_u32 s55, s55, 1"]
+            out += [f"s_add_u32 s55, s55, {inc}"]
         out += ["s_setpc_b64 s[44:45]"]
     # a value from the previous level's slots (rows read downwards): REF j of
     # a work item takes ring register j % RING, loaded RING REFs earlier, and
