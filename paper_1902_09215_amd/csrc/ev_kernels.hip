@@ -39,6 +39,23 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t n, uint32_t v)
     if (i < n) p[i] = v;
 }
 
+// A copy between device memory and the host's pinned staging buffer, done
+// by the stream's own compute queue: a small transfer then needs no handoff
+// to a DMA engine and back (which costs more than the copy).  16-byte moves
+// when both ends and the size allow, else 4-byte, else bytes.
+__global__ void k_copy(uint8_t* __restrict__ dst, const uint8_t* __restrict__ src, uint64_t n, uint32_t w)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i * w >= n) return;
+    if (w == 16)
+        reinterpret_cast<u32x4*>(dst)[i] = reinterpret_cast<const u32x4*>(src)[i];
+    else if (w == 4)
+        reinterpret_cast<uint32_t*>(dst)[i] = reinterpret_cast<const uint32_t*>(src)[i];
+    else
+        dst[i] = src[i];
+    __threadfence_system();  // host-visible before the stream's next marker
+}
+
 // Protected division and the three other functions (Sec. 2.1, Table 1).
 __device__ __forceinline__ float apply_op(uint32_t t, float a, float b)
 {
@@ -464,6 +481,8 @@ __global__ __launch_bounds__(1024) void k_plan_bases(const TreeLvl* __restrict__
     const uint32_t per = (n_trees + 1023u) / 1024u;
     const uint32_t i0 = t * per < n_trees ? t * per : n_trees, i1 = i0 + per < n_trees ? i0 + per : n_trees;
     uint64_t so = 0, sf = 0, sc = 0;
+    // (unrolled, so that a thread's loads are in flight together)
+#pragma unroll 4
     for (uint32_t i = i0; i < i1; i++) {
         so += sum[i].n_out;
         sf += sum[i].n_frag;
@@ -482,6 +501,7 @@ __global__ __launch_bounds__(1024) void k_plan_bases(const TreeLvl* __restrict__
         __syncthreads();
     }
     uint64_t o = po[t] - so, f = pf[t] - sf, c = pc[t] - sc;
+#pragma unroll 4
     for (uint32_t i = i0; i < i1; i++) {
         const TreeLvl tl = trees[i];
         base[tl.tree] = TreeBase{o, f, c, tl.chunk_first, tl.n_chunks, tl.rank_full, tl.rank_last};
@@ -756,79 +776,92 @@ __global__ void k_seg_check(const uint32_t* __restrict__ codes, const SegIn* __r
     // bad: 1 a code names another position or no handler, 2 the window or
     // slab leaves its bounds, 4 END misplaced, 8 boundary position, 16/32
     // slots written/read differ from the plan
-    // codes are read in aligned blocks of four, the next block in flight
-    // (at most seven codes past the stream, inside the buffer's zero tail)
-    const uint32_t sk = (uint32_t)(b & 3u);
+    // codes are read in aligned blocks of four, sixteen codes a step with
+    // the next sixteen in flight (one lane per segment leaves few waves to
+    // hide a load's latency); at most 31 codes past the stream are read,
+    // inside the buffer's zero tail
+    const uint32_t sk = (uint32_t)(b & 3u), total = sk + len;
     const uint32_t* cb = codes + (b - sk);
-    u32x4 nxt = *reinterpret_cast<const u32x4*>(cb);
-    for (uint32_t q0 = 0; q0 < sk + len; q0 += 4) {
-        const u32x4 cur = nxt;
-        nxt = *reinterpret_cast<const u32x4*>(cb + q0 + 4);
-        const uint32_t jlo = q0 ? 0u : sk, jend = sk + len - q0 < 4u ? sk + len - q0 : 4u;
-        for (uint32_t j = jlo; j < jend; j++) {
-            const uint32_t i = q0 + j - sk;
-            const uint32_t v = j >= 2 ? (j == 3 ? cur.w : cur.z) : (j == 1 ? cur.y : cur.x);
-            // decode: handler base and stride of this position
-            const uint32_t pos = (uint32_t)((b + i) & (EV_CODE_POS - 1));
-            const uint32_t sh = 5u + code_tr(pos);  // log2 of the stride
-            const uint32_t base = code_base(pos);
-            const uint32_t rel = v - base;
-            const uint32_t k = rel >> sh;
-            if (v < base || (rel & ((1u << sh) - 1u)) || k >= EV_NK) bad |= 1;
-            if (ended) bad |= 4;
-            if (tail) {
-                // after a FLUSH only the chunk's final slot writes and END may
-                // follow, none of which moves the window (a short path for
-                // the long runs of OUTMEM and OUTBOT)
-                const bool isF = k == EV_K_FLUSH, isB = k == EV_K_OUTBOT, isM = k == EV_K_OUTMEM;
-                const bool isT = k == EV_K_OUTT, isX = k == EV_K_OUTX, isE = k == EV_K_END;
-                const bool w = !(isF || isB || isM || isT || isX || isE) || (isB && fl >= idx) || (isM && fl >= slab);
-                fl = isF ? 0 : fl + ((isB || isM) ? 1 : 0);
-                outs += (isB || isM || isT || isX) ? 1u : 0u;
-                ended |= isE ? 1u : 0u;
-                if (w) bad |= 2;
-                continue;
-            }
-            // stack actions of the common kinds, with selects
-            const bool ops1 = k <= EV_K_OPS3;
-            const bool ops2 = k >= EV_K_OPS00 && k <= EV_K_OPS22;
-            const bool pref = k >= EV_K_PUSHREF0 && k < EV_K_PUSHREF0 + EV_RING;
-            const bool lref = k >= EV_K_LOADREF0 && k < EV_K_LOADREF0 + EV_RING;
-            const bool push1 = (k >= EV_K_CH0 && k <= EV_K_CH3) || k == EV_K_PUSHX || pref;
-            const int32_t need = ops1 ? 1 : (ops2 ? 2 : 0);
-            const bool push2 = k == EV_K_PUSH2X || (k >= EV_K_PXCH0 && k <= EV_K_PXCH3);
-            const int32_t d = ops1 ? -1 : ops2 ? -2 : push1 ? 1 : (push2 ? 2 : 0);
-            uint32_t w = idx < need ? 1u : 0u;
-            // a REF's ring slot follows from its index within the work item
-            const uint32_t slot = (ref0 + ins) & (EV_RING - 1);
-            if ((pref && k - EV_K_PUSHREF0 != slot) || (lref && k - EV_K_LOADREF0 != slot)) bad |= 1;
-            idx += d;
-            m += (uint32_t)d;
-            ins += (pref || lref) ? 1u : 0u;
-            if (k >= EV_K_OUTT && k <= EV_K_OUTMEM) {  // the rare kinds
-                if (k == EV_K_END) ended = 1;
-                if (k == EV_K_FLUSH) {
-                    fl = 0;
-                    tail = 1;
-                } else if (k == EV_K_OUTBOT) {
-                    w |= fl >= idx;
-                    fl++;
-                } else if (k == EV_K_OUTMEM) {
-                    w |= fl >= slab;
-                    fl++;
-                } else if (k == EV_K_SPILL) {
-                    w |= idx < (int32_t)EV_VHALF;
-                    idx -= EV_VHALF;
-                    slab += EV_VHALF;
-                } else if (k == EV_K_FILL) {
-                    w |= slab < (int32_t)EV_VHALF || idx > (int32_t)EV_VHALF - 1;
-                    idx += EV_VHALF;
-                    slab -= EV_VHALF;
+    auto ld = [&](uint32_t q) { return *reinterpret_cast<const u32x4*>(cb + q); };
+    u32x4 n0 = ld(0), n1 = ld(4), n2 = ld(8), n3 = ld(12);
+    for (uint32_t q0 = 0; q0 < total; q0 += 16) {
+        const u32x4 c0 = n0, c1 = n1, c2 = n2, c3 = n3;
+        n0 = ld(q0 + 16);
+        n1 = ld(q0 + 20);
+        n2 = ld(q0 + 24);
+        n3 = ld(q0 + 28);
+#pragma unroll
+        for (uint32_t h = 0; h < 4; h++) {
+            const uint32_t qb = q0 + 4 * h;
+            if (qb >= total) break;
+            const u32x4 cur = h == 0 ? c0 : (h == 1 ? c1 : (h == 2 ? c2 : c3));
+            const uint32_t jlo = qb ? 0u : sk, jend = total - qb < 4u ? total - qb : 4u;
+            for (uint32_t j = jlo; j < jend; j++) {
+                const uint32_t i = qb + j - sk;
+                const uint32_t v = j >= 2 ? (j == 3 ? cur.w : cur.z) : (j == 1 ? cur.y : cur.x);
+                // decode: handler base and stride of this position
+                const uint32_t pos = (uint32_t)((b + i) & (EV_CODE_POS - 1));
+                const uint32_t sh = 5u + code_tr(pos);  // log2 of the stride
+                const uint32_t base = code_base(pos);
+                const uint32_t rel = v - base;
+                const uint32_t k = rel >> sh;
+                if (v < base || (rel & ((1u << sh) - 1u)) || k >= EV_NK) bad |= 1;
+                if (ended) bad |= 4;
+                if (tail) {
+                    // after a FLUSH only the chunk's final slot writes and END may
+                    // follow, none of which moves the window (a short path for
+                    // the long runs of OUTMEM and OUTBOT)
+                    const bool isF = k == EV_K_FLUSH, isB = k == EV_K_OUTBOT, isM = k == EV_K_OUTMEM;
+                    const bool isT = k == EV_K_OUTT, isX = k == EV_K_OUTX, isE = k == EV_K_END;
+                    const bool w =
+                        !(isF || isB || isM || isT || isX || isE) || (isB && fl >= idx) || (isM && fl >= slab);
+                    fl = isF ? 0 : fl + ((isB || isM) ? 1 : 0);
+                    outs += (isB || isM || isT || isX) ? 1u : 0u;
+                    ended |= isE ? 1u : 0u;
+                    if (w) bad |= 2;
+                    continue;
                 }
-                outs += (k == EV_K_OUTT || k == EV_K_OUTX || k == EV_K_OUTBOT || k == EV_K_OUTMEM);
+                // stack actions of the common kinds, with selects
+                const bool ops1 = k <= EV_K_OPS3;
+                const bool ops2 = k >= EV_K_OPS00 && k <= EV_K_OPS22;
+                const bool pref = k >= EV_K_PUSHREF0 && k < EV_K_PUSHREF0 + EV_RING;
+                const bool lref = k >= EV_K_LOADREF0 && k < EV_K_LOADREF0 + EV_RING;
+                const bool push1 = (k >= EV_K_CH0 && k <= EV_K_CH3) || k == EV_K_PUSHX || pref;
+                const int32_t need = ops1 ? 1 : (ops2 ? 2 : 0);
+                const bool push2 = k == EV_K_PUSH2X || (k >= EV_K_PXCH0 && k <= EV_K_PXCH3);
+                const int32_t d = ops1 ? -1 : ops2 ? -2 : push1 ? 1 : (push2 ? 2 : 0);
+                uint32_t w = idx < need ? 1u : 0u;
+                // a REF's ring slot follows from its index within the work item
+                const uint32_t slot = (ref0 + ins) & (EV_RING - 1);
+                if ((pref && k - EV_K_PUSHREF0 != slot) || (lref && k - EV_K_LOADREF0 != slot)) bad |= 1;
+                idx += d;
+                m += (uint32_t)d;
+                ins += (pref || lref) ? 1u : 0u;
+                if (k >= EV_K_OUTT && k <= EV_K_OUTMEM) {  // the rare kinds
+                    if (k == EV_K_END) ended = 1;
+                    if (k == EV_K_FLUSH) {
+                        fl = 0;
+                        tail = 1;
+                    } else if (k == EV_K_OUTBOT) {
+                        w |= fl >= idx;
+                        fl++;
+                    } else if (k == EV_K_OUTMEM) {
+                        w |= fl >= slab;
+                        fl++;
+                    } else if (k == EV_K_SPILL) {
+                        w |= idx < (int32_t)EV_VHALF;
+                        idx -= EV_VHALF;
+                        slab += EV_VHALF;
+                    } else if (k == EV_K_FILL) {
+                        w |= slab < (int32_t)EV_VHALF || idx > (int32_t)EV_VHALF - 1;
+                        idx += EV_VHALF;
+                        slab -= EV_VHALF;
+                    }
+                    outs += (k == EV_K_OUTT || k == EV_K_OUTX || k == EV_K_OUTBOT || k == EV_K_OUTMEM);
+                }
+                w |= idx < 0 || idx > (int32_t)EV_VSTACK - 1 || slab < 0 || slab > (int32_t)slab_entries;
+                if (w) bad |= 2;
             }
-            w |= idx < 0 || idx > (int32_t)EV_VSTACK - 1 || slab < 0 || slab > (int32_t)slab_entries;
-            if (w) bad |= 2;
         }
     }
     if ((ended != 0) != (g.last != 0)) bad |= 4;
@@ -1326,6 +1359,15 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3(cdiv(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void* dst, const void* src, uint64_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const uint64_t a = (uint64_t)(uintptr_t)dst | (uint64_t)(uintptr_t)src | n;
+    const uint32_t w = (a & 15) == 0 ? 16u : ((a & 3) == 0 ? 4u : 1u);
+    hipLaunchKernelGGL(k_copy, dim3(cdiv(n / w, 256)), dim3(256), 0, s, (uint8_t*)dst, (const uint8_t*)src, n, w);
     return hipGetLastError();
 }
 

@@ -6,6 +6,8 @@
 
 namespace ev {
 hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
+// n bytes, by a kernel on s (one end may be pinned host memory)
+hipError_t launch_copy(void* dst, const void* src, uint64_t n, hipStream_t s);
 hipError_t launch_seg_build(const ChunkIn* ch, const ChunkSegs* cg, uint32_t n, uint32_t seg_len, uint32_t head,
                             SegIn* seg, hipStream_t s);
 hipError_t launch_plan_chunks(const TreeLvl* trees, uint32_t n_trees, uint32_t seg_len, uint32_t head, ChunkIn* ch,

@@ -469,7 +469,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
             if ((st = dev_alloc(c, n * sizeof(RunChunk), (void**)&LL.d_run)) != EV_OK) { cleanup(); return st; }
             // 512 zero bytes after the stream (written with the work items):
             // the interpreter reads up to 192 bytes past a stream's last code
-            // block, the validator up to 28
+            // block, the validator up to 124
             if ((st = dev_alloc(c, sc * 4 + 512, (void**)&LL.codes)) != EV_OK) { cleanup(); return st; }
         }
 
@@ -654,7 +654,8 @@ ev_status stage(Exec& x, size_t n, void** out)
             x.pin = nullptr;
             x.pin_cap = 0;
             const size_t cap = std::max<size_t>(n, (size_t)4 << 20);
-            hipError_t e = hipHostMalloc((void**)&x.pin, cap, hipHostMallocDefault);
+            // coherent: the copy kernel reads and writes it directly
+            hipError_t e = hipHostMalloc((void**)&x.pin, cap, hipHostMallocCoherent);
             if (e != hipSuccess) {
                 (void)hipGetLastError();
                 x.pin = nullptr;
@@ -670,6 +671,10 @@ ev_status stage(Exec& x, size_t n, void** out)
 
 // Large transfers pass through the staging buffer in pieces of this size.
 static constexpr size_t STAGE_PIECE = (size_t)64 << 20;
+// Transfers up to this size are copied by a kernel on the stream's compute
+// queue: a DMA-engine copy between kernels costs a handoff between queues
+// (measured 15-40 us around each), far more than such a copy itself.
+static constexpr size_t KERNEL_COPY_MAX = (size_t)1 << 20;
 
 // Host-to-device copy on x's stream (src may be reused on return).
 ev_status put(Exec& x, void* dst, const void* src, size_t n)
@@ -680,7 +685,10 @@ ev_status put(Exec& x, void* dst, const void* src, size_t n)
         ev_status st = stage(x, k, &p);
         if (st != EV_OK) return st;
         std::memcpy(p, (const uint8_t*)src + o, k);
-        HIPCHK(hipMemcpyAsync((uint8_t*)dst + o, p, k, hipMemcpyHostToDevice, x.stream));
+        if (k <= KERNEL_COPY_MAX)
+            HIPCHK(launch_copy((uint8_t*)dst + o, p, k, x.stream));
+        else
+            HIPCHK(hipMemcpyAsync((uint8_t*)dst + o, p, k, hipMemcpyHostToDevice, x.stream));
     }
     return EV_OK;
 }
@@ -693,7 +701,10 @@ ev_status get(Exec& x, void* dst, const void* src, size_t n)
         void* p = nullptr;
         ev_status st = stage(x, k, &p);
         if (st != EV_OK) return st;
-        HIPCHK(hipMemcpyAsync(p, (const uint8_t*)src + o, k, hipMemcpyDeviceToHost, x.stream));
+        if (k <= KERNEL_COPY_MAX)
+            HIPCHK(launch_copy(p, (const uint8_t*)src + o, k, x.stream));
+        else
+            HIPCHK(hipMemcpyAsync(p, (const uint8_t*)src + o, k, hipMemcpyDeviceToHost, x.stream));
         x.pin_out.push_back(Exec::Out{(uint8_t*)dst + o, p, k});
     }
     return EV_OK;
