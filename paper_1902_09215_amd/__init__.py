@@ -324,6 +324,7 @@ def ev_get_plan_info(ctx, pop) -> dict:
 
 
 EV_TUNE_NO_REGSTACK = 0x1
+EV_TUNE_TEST_FAIL_CHECK = 0x100
 
 
 def ev_set_tuning(ctx, chunk: int = 0, lds_depth: int = 0, flags: int = 0, chunk_hi: int = 0):

@@ -139,6 +139,7 @@ struct RunArgs {
     uint64_t slab_entries;  // rows of 64 floats per slab
     uint32_t* flag;         // set to 1 if the interpreter's table cannot be used (see gen_interp.py)
     uint32_t refs;          // 1 at the skeleton levels: REF slots are read ahead
+    const uint32_t* verdict;  // the validator's flags for these code streams: nonzero runs nothing
 };
 
 // A work item as the evaluator sees it (32 bytes).

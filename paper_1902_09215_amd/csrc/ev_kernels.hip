@@ -1316,6 +1316,9 @@ namespace ev {
 // register window run on k_eval instead.
 __global__ __launch_bounds__(64) void k_run(RunArgs a)
 {
+    // a level whose code streams failed validation runs none of them (the
+    // host reports the failure when it reads the verdict)
+    if (a.verdict && *a.verdict) return;
     const uint32_t lane = threadIdx.x;
     const_u4p chunks = (const_u4p)(global_u4p)(const void*)a.chunks;
     // this wave's spill slab: slab_entries rows of 64 lanes

@@ -205,6 +205,20 @@ void plan_free(ev_ctx* c, Plan& pl)
     pl.fin_slot.clear();
     dev_free(c, pl.d_fin);
     pl.d_fin = nullptr;
+    dev_free(c, pl.d_err);
+    pl.d_err = nullptr;
+    pl.err_pending = false;
+}
+
+ev_status plan_verdict(Pop* P)
+{
+    Plan& pl = P->plan;
+    if (!pl.err_pending) return EV_OK;
+    if (pl.h_err[0])  // stays pending: every later evaluation fails the same way
+        return fail(EV_EDEVICE, "internal: malformed code stream at level %d (flags %u, segment %u)", pl.err_level,
+                    pl.h_err[0], pl.h_err[1]);
+    pl.err_pending = false;
+    return EV_OK;
 }
 
 void rescache_free(ev_ctx* c, ResCache& r)
@@ -235,7 +249,7 @@ void pop_free(ev_ctx* c, Pop* P)
 // per tree (its range at the level, its first input slot, where it ends);
 // chunks, segments and their numbering are made on the device, and the host
 // waits once per level, for the trees' totals that size the level's buffers.
-ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
+ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_check = false)
 {
     hipStream_t s = x.stream;
     const int32_t M = P->M;
@@ -530,7 +544,16 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
                 cleanup();
                 return st;
             }
-            // the last level: its validation must pass before the plan is used
+            // the last level: its validation must pass before the plan is
+            // used, checked here, or (defer_check) by its k_run launches on
+            // the device and by the host with the first evaluation
+            if (c->test_fail_check && run_items)
+                HIPCHK(launch_fill_u32((uint32_t*)d_err + 2 * level, 1, 0x100u, s));
+            if (defer_check) {
+                pl.err_level = level;
+                pl.err_pending = true;
+                break;
+            }
             if ((st = get(x, verr, (uint32_t*)d_err + 2 * level, 8)) || (st = sync(x))) {
                 cleanup();
                 return st;
@@ -552,6 +575,8 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
                         (unsigned long long)(t < M ? rl[t] : 0), (unsigned long long)(t < M ? prev_len[t] : 0));
         }
     }
+    pl.d_err = (uint32_t*)d_err;  // the plan keeps the validator's words
+    d_err = nullptr;
     cleanup();
     pl.bytes = 0;
     for (auto& L : pl.levels) pl.bytes += (uint64_t)L.n_chunks * sizeof(EvalChunk) + (uint64_t)L.n_run * sizeof(RunChunk);
@@ -561,7 +586,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree)
 // Make a population from device bytes (takes ownership of d_bytes, also on
 // failure).
 ev_status pop_build(ev_ctx* c, Exec& x, uint8_t* d_bytes, const std::vector<uint64_t>& h_off, Pop** out, int32_t* bad,
-                    uint64_t* d_off)
+                    uint64_t* d_off, bool defer_check)
 {
     *out = nullptr;
     Pop* P = new Pop();
@@ -576,7 +601,7 @@ ev_status pop_build(ev_ctx* c, Exec& x, uint8_t* d_bytes, const std::vector<uint
         if ((st = put(x, P->d_off, h_off.data(), h_off.size() * sizeof(uint64_t))) != EV_OK) { pop_free(c, P); return st; }
     }
     if ((st = dev_alloc(c, (size_t)std::max(1, P->M) * sizeof(float), (void**)&P->d_fit)) != EV_OK) { pop_free(c, P); return st; }
-    if ((st = plan_build(c, x, P, bad)) != EV_OK) { pop_free(c, P); return st; }
+    if ((st = plan_build(c, x, P, bad, defer_check)) != EV_OK) { pop_free(c, P); return st; }
     *out = P;
     return EV_OK;
 }
@@ -801,8 +826,15 @@ ev_status rescache_build(ev_ctx* c, Exec& x, Pop* P, int32_t table, ResCache** o
 // Queue the evaluation of P on table on c->stream; fit/per_case are device
 // pointers (per_case nullable).
 ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, float* d_per_case, bool timed,
-                       int32_t* d_hits)
+                       int32_t* d_hits, bool verdict_at_sync)
 {
+    if (P->plan.err_pending) {
+        // the plan's last validation verdict: read with the caller's next
+        // sync (then checked by plan_verdict), or here
+        ev_status st = get(x, P->plan.h_err, P->plan.d_err + 2 * P->plan.err_level, 8);
+        if (st == EV_OK && !verdict_at_sync && (st = sync(x)) == EV_OK) st = plan_verdict(P);
+        if (st != EV_OK) return st;
+    }
     const CaseTable& ct = c->tables[table];
     const int32_t N = ct.N;
     const uint32_t n_cb = (uint32_t)((N + 63) / 64);
@@ -843,7 +875,7 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
         const Level& L = P->plan.levels[li];
         if (timed && li == 0) HIPCHK(hipEventRecord(x.evi0, s));
         if (L.n_run) {
-            RunArgs r;
+            RunArgs r{};
             r.codes = L.codes;
             r.chunks = L.d_run;
             r.n_items = L.n_run * n_cb;
@@ -858,6 +890,7 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
             r.slab = x.d_gstack;
             r.slab_entries = L.slab_entries;
             r.flag = c->d_flag;
+            r.verdict = P->plan.d_err ? P->plan.d_err + 2 * li : nullptr;
             HIPCHK(launch_run(r, (uint32_t)std::min<uint64_t>((uint64_t)c->grid_run, r.n_items), s));
         }
         if (L.n_chunks == 0) {
@@ -905,7 +938,7 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
 // host waits once, for the offsets it needs to size the new buffer.
 ev_status crossover_build_dev(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const int32_t* d_mum, const int32_t* d_dad,
                               const uint64_t* d_p, const uint64_t* d_q, int32_t n, uint64_t cap, Pop** out,
-                              int32_t* n_capped)
+                              int32_t* n_capped, bool defer_check)
 {
     hipStream_t s = x.stream;
     const size_t qn = std::max<size_t>(1, 2 * (size_t)n);
@@ -961,7 +994,7 @@ ev_status crossover_build_dev(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const in
     // later use of it is ordered after the copy on the context's one stream
     cleanup();
     if (n_capped) *n_capped = (int32_t)capped;
-    return pop_build(c, x, d_child, off, out, nullptr, d_off);
+    return pop_build(c, x, d_child, off, out, nullptr, d_off, defer_check);
 }
 
 // The same from host arrays, checked against the parents first.
@@ -1258,17 +1291,21 @@ ev_status ev_eval_fitness(ev_ctx* c, ev_pop pop, int32_t table, float* fitness, 
             d_hits = P->d_hits;
         }
     }
-    ev_status st = eval_enqueue(c, c->main, P, table, P->d_fit, d_pc, true, d_hits);
+    const bool verdict = P->plan.err_pending;
+    ev_status st = eval_enqueue(c, c->main, P, table, P->d_fit, d_pc, true, d_hits, true);
     if (st != EV_OK) return st;
-    P->fit_valid = true;
     if (flags & EV_OUT_DEVICE) {
         if (P->M) HIPCHK(hipMemcpyAsync(fitness, P->d_fit, (size_t)P->M * 4, hipMemcpyDeviceToDevice, c->stream));
+        if (verdict && ((st = sync(c->main)) != EV_OK || (st = plan_verdict(P)) != EV_OK)) return st;
+        P->fit_valid = true;
         return EV_OK;
     }
     if ((st = get(c->main, fitness, P->d_fit, (size_t)P->M * 4)) != EV_OK) return st;
     if (per_case && (st = get(c->main, per_case, d_pc, (size_t)P->M * N * 4)) != EV_OK) return st;
     if (hits && (st = get(c->main, hits, d_hits, (size_t)P->M * 4)) != EV_OK) return st;
-    return sync(c->main);
+    if ((st = sync(c->main)) != EV_OK || (st = plan_verdict(P)) != EV_OK) return st;
+    P->fit_valid = true;
+    return EV_OK;
 }
 
 ev_status ev_crossover(ev_ctx* c, ev_pop mums_pop, ev_pop dads_pop, const int32_t* mum, const int32_t* dad,
@@ -1310,7 +1347,9 @@ ev_status ev_generation(ev_ctx* c, ev_pop parents, const float* fitness, uint64_
         return hip_fail(e, "selection");
     }
     Pop* C = nullptr;
-    st = crossover_build_dev(c, c->main, P, P, d_mum, d_dad, d_p, d_q, M, size_cap, &C, n_capped);
+    // the children's last validation verdict is read with their first
+    // evaluation (their k_run launches check it on the device)
+    st = crossover_build_dev(c, c->main, P, P, d_mum, d_dad, d_p, d_q, M, size_cap, &C, n_capped, true);
     dev_free(c, d_sel);
     if (st != EV_OK) return st;
     *out = pop_register(c, C);
@@ -1337,6 +1376,7 @@ ev_status ev_set_tuning(ev_ctx* c, uint32_t chunk, uint32_t chunk_hi, uint32_t l
     if ((chunk != 0 && chunk < 64) || (chunk_hi != 0 && chunk_hi < 64))
         return fail(EV_EINVAL, "work items must be at least 64 tokens");
     c->use_run = c->run_ok && (flags & EV_TUNE_NO_REGSTACK) == 0;
+    c->test_fail_check = (flags & EV_TUNE_TEST_FAIL_CHECK) != 0;
     if (chunk) c->chunk = chunk;
     if (chunk_hi) c->chunk_hi = chunk_hi;
     if (lds_depth) c->lds_depth = (int)lds_depth;

@@ -45,6 +45,14 @@ struct Plan {
     std::vector<int32_t> fin_level;  // per tree: level holding its value
     std::vector<uint32_t> fin_slot;  // and the slot
     uint32_t* d_fin = nullptr;       // both on the device: level, slot per tree
+    // The validator's words, two per level (flags, first failing segment).
+    // err_pending: the last level's were not yet read by the host; its k_run
+    // launches check them on the device, and the host reads them with the
+    // first evaluation (h_err).
+    uint32_t* d_err = nullptr;
+    int err_level = 0;
+    bool err_pending = false;
+    uint32_t h_err[2] = {0, 0};
     uint32_t chunk = 0;
     int D = 64;
     uint64_t chunks_total = 0, slots_total = 0, max_stack = 0, bytes = 0;
@@ -119,6 +127,7 @@ struct ev_ctx {
     int grid_run = 0;
     bool use_run = true;  // register-stack kernel for the items that fit it
     bool run_ok = true;   // the register-stack kernel can run here (probed at creation)
+    bool test_fail_check = false;  // EV_TUNE_TEST_FAIL_CHECK
     uint32_t* d_flag = nullptr;  // the probe's flag word
     uint32_t chunk = 4096;     // tokens per work item at level 0
     uint32_t chunk_hi = 0;     // at the skeleton levels (0: twice chunk)
@@ -166,19 +175,26 @@ void exec_free(ev_ctx* c, Exec& x);
 
 void pop_free(ev_ctx* c, Pop* P);
 // d_off: the offsets already on the device (adopted), or nullptr to upload h_off
+// defer_check: leave the last plan level's validation verdict to the device
+// and to the first evaluation (Plan::err_pending)
 ev_status pop_build(ev_ctx* c, Exec& x, uint8_t* d_bytes, const std::vector<uint64_t>& h_off, Pop** out,
-                    int32_t* bad, uint64_t* d_off = nullptr);
+                    int32_t* bad, uint64_t* d_off = nullptr, bool defer_check = false);
+// after a sync that followed eval_enqueue(P): the deferred verdict, if any
+ev_status plan_verdict(Pop* P);
 ev_pop pop_register(ev_ctx* c, Pop* P);
 Pop* pop_get(ev_ctx* c, ev_pop id);
 
+// verdict_at_sync: a plan's deferred validation verdict (Plan::err_pending)
+// is fetched with the caller's next sync(x), after which the caller calls
+// plan_verdict(P); otherwise it is checked here, with a sync of its own
 ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, float* d_per_case, bool timed,
-                       int32_t* d_hits);
+                       int32_t* d_hits, bool verdict_at_sync = false);
 ev_status crossover_build(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const int32_t* mum, const int32_t* dad,
                           const uint64_t* p, const uint64_t* q, int32_t n, uint64_t cap, Pop** out,
                           int32_t* n_capped);
 ev_status crossover_build_dev(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const int32_t* d_mum, const int32_t* d_dad,
                               const uint64_t* d_p, const uint64_t* d_q, int32_t n, uint64_t cap, Pop** out,
-                              int32_t* n_capped);
+                              int32_t* n_capped, bool defer_check = false);
 
 void serve_stop(ev_ctx* c);
 

@@ -333,6 +333,47 @@ def test_generation_with_caller_fitness(ev):
     assert not (np.array_equal(ko, ao) and np.array_equal(kb, ab))
 
 
+def test_deferred_validation_verdict(ev):
+    # The children of ev_generation leave their last plan level's validation
+    # verdict to the device and to their first evaluation.  A verdict forced
+    # to fail from the host (test hook) makes that evaluation fail with
+    # EV_EDEVICE, every time, while a plan built by ev_load_trees is refused
+    # at once; with the hook off, the same children evaluate as the oracle.
+    x, y = workloads.cases(48)
+    sizes = workloads.loguniform_sizes(43, 60, 10, 20000)
+    buf, off = workloads.random_population(43, sizes)
+    seed, cap = 99, 15_000_000
+    with ev.Context(x, y) as c:
+        pop = c.load(buf, off)
+        fit, _ = c.eval(pop)
+        good, _ = ev.ev_generation(c.ctx, pop, seed, 0, 2, cap)
+        gfit, _ = c.eval(good)
+        gbuf, goff = ev.ev_get_trees(c.ctx, good)
+        assert same_bits(gfit, oracle.eval_population(gbuf, goff, x, y, threads=8)).all()
+        assert same_bits(c.eval(good)[0], gfit).all()
+
+        ev.ev_set_tuning(c.ctx, flags=ev.EV_TUNE_TEST_FAIL_CHECK)
+        bad, _ = ev.ev_generation(c.ctx, pop, seed, 0, 2, cap)
+        bbuf, boff = ev.ev_get_trees(c.ctx, bad)
+        assert np.array_equal(bbuf, gbuf) and np.array_equal(boff, goff)
+        for _ in range(2):
+            with pytest.raises(ev.EvError) as e:
+                c.eval(bad)
+            assert e.value.code == ev.EV_EDEVICE and "malformed code stream" in str(e.value)
+        with pytest.raises(ev.EvError) as e:
+            c.load(buf, off)
+        assert e.value.code == ev.EV_EDEVICE
+        # parents and earlier children are untouched
+        assert same_bits(c.eval(pop)[0], fit).all()
+        assert same_bits(c.eval(good)[0], gfit).all()
+
+        ev.ev_set_tuning(c.ctx, flags=0)
+        again, _ = ev.ev_generation(c.ctx, pop, seed, 0, 2, cap)
+        assert same_bits(c.eval(again)[0], gfit).all()
+        for q in (bad, good, again):
+            ev.ev_free_pop(c.ctx, q)
+
+
 def test_caller_allocator(ev):
     # Every device block of a context can come from the caller's allocator
     # (here torch's caching allocator); results are the same, and every block
