@@ -89,6 +89,8 @@ constexpr int EV_MAX_LEVELS = 64;
 // Where each tree's value ends up: its level's result rows, and its slot.
 struct FitArgs {
     const float* res[EV_MAX_LEVELS + 1];
+    uint32_t n_out[EV_MAX_LEVELS + 1];  // slots of each level
+    uint32_t n_levels;
     const uint32_t* fin;  // per tree: level, slot
     const float* y;
     int32_t N;

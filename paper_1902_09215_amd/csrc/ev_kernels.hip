@@ -1028,7 +1028,15 @@ __global__ void k_fitness(FitArgs a)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.M) return;
-    const float* r = a.res[a.fin[2 * t]] + (size_t)a.fin[2 * t + 1] * (size_t)a.N;
+    const uint32_t lv = a.fin[2 * t], slot = a.fin[2 * t + 1];
+    if (lv >= a.n_levels || slot >= a.n_out[lv]) {
+        // no such slot: a plan inconsistency, reported as NaN, never read
+        a.fit[t] = __int_as_float(0x7fc00000);
+        if (a.hits) a.hits[t] = 0;
+        for (int32_t i = 0; a.per_case && i < a.N; i++) a.per_case[(size_t)t * (size_t)a.N + i] = a.fit[t];
+        return;
+    }
+    const float* r = a.res[lv] + (size_t)slot * (size_t)a.N;
     float s = 0.0f;
     int32_t h = 0;
     for (int32_t i = 0; i < a.N; i++) {

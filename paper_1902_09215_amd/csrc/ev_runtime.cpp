@@ -916,7 +916,11 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
         if (timed) HIPCHK(hipEventRecord(x.evl[li], s));
     }
     FitArgs fa = {};
-    for (size_t li = 0; li < nl; li++) fa.res[li] = rc->res[li];
+    for (size_t li = 0; li < nl; li++) {
+        fa.res[li] = rc->res[li];
+        fa.n_out[li] = P->plan.levels[li].n_out;
+    }
+    fa.n_levels = (uint32_t)nl;
     fa.fin = P->plan.d_fin;
     fa.y = ct.d_y;
     fa.N = N;
