@@ -54,7 +54,8 @@ import sys
 
 VSTACK = int(os.environ.get("EV_VSTACK", "56"))  # register-stack entries: v12 .. v12+VSTACK-1
 HALF = VSTACK // 2  # entries moved by one spill or fill
-RING = 8  # slot values read ahead: v[12+VSTACK] .. v[12+VSTACK+RING-1]
+RING = int(os.environ.get("EV_RING", "8"))  # slot values read ahead: v[12+VSTACK] .. v[12+VSTACK+RING-1]
+assert RING in (4, 8, 16, 32), "the ring size must be a power of two up to 32"
 RING0 = 12 + VSTACK
 POS = 32  # positions per 128-byte code block
 NSTRIDE = 32  # bytes per handler at ordinary positions
