@@ -473,41 +473,56 @@ __global__ __launch_bounds__(64) void k_plan_trees(const TreeLvl* __restrict__ t
 // One block: the trees' bases over the level's chunks, in sequence order
 // (which is tree order): exclusive sums of their slots, fragment tokens and
 // codes, stored by tree id with the tree's chunk range and bucket ranks.
+// Rounds of 1024 consecutive trees (coalesced reads), each scanned by wave
+// shuffles and the waves' totals, on top of the previous rounds' total.
 __global__ __launch_bounds__(1024) void k_plan_bases(const TreeLvl* __restrict__ trees, uint32_t n_trees,
                                                      const TreeSum* __restrict__ sum, TreeBase* __restrict__ base)
 {
-    __shared__ uint64_t po[1024], pf[1024], pc[1024];
-    const uint32_t t = threadIdx.x;
-    const uint32_t per = (n_trees + 1023u) / 1024u;
-    const uint32_t i0 = t * per < n_trees ? t * per : n_trees, i1 = i0 + per < n_trees ? i0 + per : n_trees;
-    uint64_t so = 0, sf = 0, sc = 0;
-    // (unrolled, so that a thread's loads are in flight together)
-#pragma unroll 4
-    for (uint32_t i = i0; i < i1; i++) {
-        so += sum[i].n_out;
-        sf += sum[i].n_frag;
-        sc += sum[i].n_codes;
-    }
-    po[t] = so;
-    pf[t] = sf;
-    pc[t] = sc;
+    __shared__ uint64_t wo[16], wf[16], wc[16], carry[3];
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+    if (t == 0) carry[0] = carry[1] = carry[2] = 0;
     __syncthreads();
-    for (uint32_t d = 1; d < 1024; d <<= 1) {
-        const uint64_t a = t >= d ? po[t - d] : 0, b = t >= d ? pf[t - d] : 0, c = t >= d ? pc[t - d] : 0;
+    for (uint32_t r0 = 0; r0 < n_trees; r0 += 1024) {
+        const uint32_t i = r0 + t;
+        uint64_t o = 0, f = 0, c = 0;
+        if (i < n_trees) {
+            o = sum[i].n_out;
+            f = sum[i].n_frag;
+            c = sum[i].n_codes;
+        }
+        uint64_t so = o, sf = f, sc = c;  // inclusive sums within the wave
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint64_t ao = __shfl_up(so, d), af = __shfl_up(sf, d), ac = __shfl_up(sc, d);
+            if (lane >= d) {
+                so += ao;
+                sf += af;
+                sc += ac;
+            }
+        }
+        if (lane == 63) {
+            wo[w] = so;
+            wf[w] = sf;
+            wc[w] = sc;
+        }
         __syncthreads();
-        po[t] += a;
-        pf[t] += b;
-        pc[t] += c;
+        uint64_t bo = carry[0], bf = carry[1], bc = carry[2];
+        for (uint32_t k = 0; k < w; k++) {
+            bo += wo[k];
+            bf += wf[k];
+            bc += wc[k];
+        }
+        if (i < n_trees) {
+            const TreeLvl tl = trees[i];
+            base[tl.tree] = TreeBase{bo + so - o, bf + sf - f, bc + sc - c, tl.chunk_first, tl.n_chunks, tl.rank_full,
+                                     tl.rank_last};
+        }
+        __syncthreads();  // every thread has read carry and the waves' totals
+        if (t == 1023) {  // the round's total (trees past the end add zero)
+            carry[0] = bo + so;
+            carry[1] = bf + sf;
+            carry[2] = bc + sc;
+        }
         __syncthreads();
-    }
-    uint64_t o = po[t] - so, f = pf[t] - sf, c = pc[t] - sc;
-#pragma unroll 4
-    for (uint32_t i = i0; i < i1; i++) {
-        const TreeLvl tl = trees[i];
-        base[tl.tree] = TreeBase{o, f, c, tl.chunk_first, tl.n_chunks, tl.rank_full, tl.rank_last};
-        o += sum[i].n_out;
-        f += sum[i].n_frag;
-        c += sum[i].n_codes;
     }
 }
 

@@ -401,7 +401,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
             (st = realloc(&d_loc, n * 3 * sizeof(uint64_t))) || (st = realloc(&d_inend, n * sizeof(uint32_t))) ||
             (st = realloc(&d_sum, nt * sizeof(TreeSum))) ||
             (st = realloc(&d_tb, (size_t)std::max(1, M) * sizeof(TreeBase))) ||
-            (st = put(x, d_tl, tl.data(), tl_bytes)) || (st = put(x, (uint8_t*)d_tl + tl_bytes, cursor, sizeof(cursor)))) {
+            (st = put2(x, d_tl, tl.data(), tl_bytes, cursor, sizeof(cursor)))) {
             cleanup();
             return st;
         }
@@ -715,6 +715,22 @@ ev_status put(Exec& x, void* dst, const void* src, size_t n)
         else
             HIPCHK(hipMemcpyAsync((uint8_t*)dst + o, p, k, hipMemcpyHostToDevice, x.stream));
     }
+    return EV_OK;
+}
+
+// Two host buffers to consecutive device bytes, as one transfer.
+ev_status put2(Exec& x, void* dst, const void* a, size_t na, const void* b, size_t nb)
+{
+    if (na + nb > KERNEL_COPY_MAX) {
+        ev_status st = put(x, dst, a, na);
+        return st != EV_OK ? st : put(x, (uint8_t*)dst + na, b, nb);
+    }
+    void* p = nullptr;
+    ev_status st = stage(x, na + nb, &p);
+    if (st != EV_OK) return st;
+    std::memcpy(p, a, na);
+    std::memcpy((uint8_t*)p + na, b, nb);
+    HIPCHK(launch_copy(dst, p, na + nb, x.stream));
     return EV_OK;
 }
 

@@ -169,6 +169,7 @@ void dev_cache_release(ev_ctx* c);
 ev_status exec_init(Exec& x, hipStream_t given);
 ev_status stage(Exec& x, size_t n, void** out);
 ev_status put(Exec& x, void* dst, const void* src, size_t n);
+ev_status put2(Exec& x, void* dst, const void* a, size_t na, const void* b, size_t nb);
 ev_status get(Exec& x, void* dst, const void* src, size_t n);
 ev_status sync(Exec& x);
 void exec_free(ev_ctx* c, Exec& x);
