@@ -227,7 +227,10 @@ ev_status ev_get_plan_info(ev_ctx *ctx, ev_pop pop, ev_plan_info *info);
  * saves whole levels), lds_depth = operand-stack entries kept in LDS
  * per wave by the general interpreter (64 or 128).  flags:
  * EV_TUNE_NO_REGSTACK runs every work item on the general interpreter
- * instead of the register-stack one.  Plans made afterwards use them;
+ * instead of the register-stack one.  EV_TUNE_NO_RECORD makes the plan
+ * builder emit codes by a second pass of the structure machine instead of
+ * placing what its counting pass recorded (levels too large to record,
+ * over about 250 million tokens, always do).  Plans made afterwards use them;
  * results never depend on them.  EV_TUNE_TEST_FAIL_CHECK is a test hook
  * for the error path of code-stream validation: plans made afterwards
  * record their last level as failing it (the plan is refused, or, for the
@@ -235,6 +238,7 @@ ev_status ev_get_plan_info(ev_ctx *ctx, ev_pop pop, ev_plan_info *info);
  * evaluation, that evaluation fails with EV_EDEVICE and runs none of the
  * level's codes). */
 #define EV_TUNE_NO_REGSTACK 0x1u
+#define EV_TUNE_NO_RECORD 0x2u
 #define EV_TUNE_TEST_FAIL_CHECK 0x100u
 ev_status ev_set_tuning(ev_ctx *ctx, uint32_t chunk, uint32_t chunk_hi, uint32_t lds_depth, uint32_t flags);
 

@@ -324,6 +324,7 @@ def ev_get_plan_info(ctx, pop) -> dict:
 
 
 EV_TUNE_NO_REGSTACK = 0x1
+EV_TUNE_NO_RECORD = 0x2
 EV_TUNE_TEST_FAIL_CHECK = 0x100
 
 

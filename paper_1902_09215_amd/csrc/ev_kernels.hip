@@ -130,10 +130,22 @@ struct Sink {
     uint32_t n_codes, n_frag, n_out, n_in;
     uint32_t pending;  // an action waiting for a partner to fuse with, or ~0u
     uint32_t ref;      // index of the next REF within the work item (its ring slot mod EV_RING)
+    // Recording (the count pass): the segment's code kinds, one byte each,
+    // and its fragment tokens in emission order, each into a region of the
+    // given capacity (nullptr: not recorded); ovf is set if one overflows.
+    uint8_t* rk;
+    uint8_t* rf;
+    uint32_t rk_cap, rf_cap, ovf;
 
-    __device__ void put(uint32_t kind)
+    __device__ __forceinline__ void put(uint32_t kind)
     {
         if (codes) codes[at] = code_value(at, kind);
+        if (rk) {
+            if (n_codes < rk_cap)
+                rk[n_codes] = (uint8_t)kind;
+            else
+                ovf = 1;
+        }
         at++;
         n_codes++;
     }
@@ -178,9 +190,15 @@ struct Sink {
         }
         put(kind);
     }
-    __device__ void ftok(uint32_t t)
+    __device__ __forceinline__ void ftok(uint32_t t)
     {
         if (frag) frag[--w] = (uint8_t)t;
+        if (rf) {
+            if (n_frag < rf_cap)
+                rf[n_frag] = (uint8_t)t;
+            else
+                ovf = 1;
+        }
         n_frag++;
     }
     // put(e) unless e is ~0u, without branching on e
@@ -188,6 +206,12 @@ struct Sink {
     {
         const uint32_t has = e != ~0u ? 1u : 0u;
         if (codes && has) codes[at] = code_value(at, e);
+        if (rk && has) {
+            if (n_codes < rk_cap)
+                rk[n_codes] = (uint8_t)e;
+            else
+                ovf = 1;
+        }
         at += has;
         n_codes += has;
     }
@@ -667,15 +691,33 @@ __global__ __launch_bounds__(64) void k_seg_scan(const ChunkSegs* __restrict__ c
     }
 }
 
+// Where a segment's recording goes: regions ordered like the segments'
+// tokens, which a level's segments cover in index order, so that they never
+// overlap (kinds: at most 4 per token plus the boundary's spills and fills;
+// fragment tokens: at most 2 per token).  A chunk's first segment, which
+// ends with the chunk's flush, is not recorded.
+__device__ __forceinline__ uint64_t rec_kinds_at(const SegIn& g, uint32_t si) { return 5ull * g.start + 48ull * si; }
+__device__ __forceinline__ uint64_t rec_frags_at(const SegIn& g, uint32_t si) { return 3ull * g.start + 16ull * si; }
+
+// Per segment: its counts; with rk/rf, also the recording of its codes'
+// kinds and fragment tokens (set *ovf if a region was too small).
 __global__ void k_seg_count(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs, uint32_t n,
-                            const SegStart* __restrict__ st, SegCount* __restrict__ out)
+                            const SegStart* __restrict__ st, SegCount* __restrict__ out, uint8_t* __restrict__ rk,
+                            uint8_t* __restrict__ rf, uint32_t* __restrict__ ovf)
 {
     const uint32_t si = blockIdx.x * blockDim.x + threadIdx.x;
     if (si >= n) return;
     const SegIn g = segs[si];
-    Sink o{nullptr, 0, nullptr, 0, 0, 0, 0, 0, ~0u, st[si].ref0};
+    Sink o{nullptr, 0, nullptr, 0, 0, 0, 0, 0, ~0u, st[si].ref0, nullptr, nullptr, 0, 0, 0};
+    if (rk && !g.last) {
+        o.rk = rk + rec_kinds_at(g, si);
+        o.rf = rf + rec_frags_at(g, si);
+        o.rk_cap = 4u * g.len + 40u;
+        o.rf_cap = 2u * g.len + 16u;
+    }
     const uint32_t maxtop = run_segment(seq, g.start, g.len, st[si].cnt, st[si].P, g.last != 0, o);
     out[si] = SegCount{o.n_codes, o.n_frag, o.n_out, o.n_in, maxtop, 0};
+    if (o.ovf) atomicOr(ovf, 1u);
 }
 
 // Per chunk, one wave: totals for the plan (first launch, no code_begin),
@@ -754,18 +796,82 @@ __global__ __launch_bounds__(64) void k_seg_chunk(const ChunkSegs* __restrict__ 
     }
 }
 
+__device__ __forceinline__ void emit_segment(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs,
+                                             uint32_t si, const SegStart* __restrict__ st,
+                                             const uint64_t* __restrict__ seg_code, const uint64_t* __restrict__ seg_frag,
+                                             uint8_t* __restrict__ dst, uint32_t* __restrict__ codes)
+{
+    const SegIn g = segs[si];
+    const bool has_codes = codes && seg_code[si] != ~0ull;
+    if (!dst && !has_codes) return;
+    Sink o{has_codes ? codes : nullptr, has_codes ? seg_code[si] : 0, dst, dst ? seg_frag[si] : 0, 0, 0, 0, 0, ~0u,
+           st[si].ref0, nullptr, nullptr, 0, 0, 0};
+    run_segment(seq, g.start, g.len, st[si].cnt, st[si].P, g.last != 0, o);
+}
+
 __global__ void k_seg_emit(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs, uint32_t n,
                            const SegStart* __restrict__ st, const uint64_t* __restrict__ seg_code,
                            const uint64_t* __restrict__ seg_frag, uint8_t* __restrict__ dst, uint32_t* __restrict__ codes)
 {
     const uint32_t si = blockIdx.x * blockDim.x + threadIdx.x;
     if (si >= n) return;
-    const SegIn g = segs[si];
-    const bool has_codes = codes && seg_code[si] != ~0ull;
-    if (!dst && !has_codes) return;
-    Sink o{has_codes ? codes : nullptr, has_codes ? seg_code[si] : 0, dst, dst ? seg_frag[si] : 0, 0, 0, 0, 0, ~0u,
-           st[si].ref0};
-    run_segment(seq, g.start, g.len, st[si].cnt, st[si].P, g.last != 0, o);
+    emit_segment(seq, segs, si, st, seg_code, seg_frag, dst, codes);
+}
+
+// The first segment of every chunk (recorded levels: the other segments are
+// placed from their recordings).
+__global__ void k_seg_emit_heads(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs,
+                                 const ChunkSegs* __restrict__ cseg, uint32_t n_chunks,
+                                 const SegStart* __restrict__ st, const uint64_t* __restrict__ seg_code,
+                                 const uint64_t* __restrict__ seg_frag, uint8_t* __restrict__ dst,
+                                 uint32_t* __restrict__ codes)
+{
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chunks) return;
+    const ChunkSegs cs = cseg[c];
+    if (cs.n_seg) emit_segment(seq, segs, cs.first, st, seg_code, seg_frag, dst, codes);
+}
+
+// A recorded segment's codes and fragment tokens to their places, one wave
+// per segment: each kind becomes its handler's offset at the code's final
+// position.  Writes outside [0, n_codes) or [0, n_frag) are skipped and
+// flagged (err), which the validator's words carry to the host.
+__global__ __launch_bounds__(64) void k_seg_place(const SegIn* __restrict__ segs, uint32_t n,
+                                                  const SegCount* __restrict__ cnt, const uint64_t* __restrict__ seg_code,
+                                                  const uint64_t* __restrict__ seg_frag, const uint8_t* __restrict__ rk,
+                                                  const uint8_t* __restrict__ rf, uint32_t* __restrict__ codes,
+                                                  uint64_t n_codes, uint8_t* __restrict__ dst, uint64_t n_frag,
+                                                  uint32_t* __restrict__ err)
+{
+    const uint32_t lane = threadIdx.x;
+    uint32_t bad = 0;
+    for (uint32_t si = blockIdx.x; si < n; si += gridDim.x) {
+        const SegIn g = segs[si];
+        if (g.last) continue;
+        const SegCount q = cnt[si];
+        if (codes && seg_code[si] != ~0ull) {
+            const uint64_t b = seg_code[si];
+            const uint8_t* k = rk + rec_kinds_at(g, si);
+            for (uint32_t i = lane; i < q.n_codes; i += 64) {
+                const uint64_t at = b + i;
+                if (at < n_codes)
+                    codes[at] = code_value(at, k[i]);
+                else
+                    bad = 1;
+            }
+        }
+        if (dst) {
+            const uint64_t w = seg_frag[si];
+            const uint8_t* f = rf + rec_frags_at(g, si);
+            for (uint32_t i = lane; i < q.n_frag; i += 64) {
+                if (i < w && w - 1 - i < n_frag)
+                    dst[w - 1 - i] = f[i];
+                else
+                    bad = 1;
+            }
+        }
+    }
+    if (bad) atomicOr(err, 0x200u);
 }
 
 // Every code must name a handler of its own position and only a chunk's
@@ -1460,10 +1566,31 @@ hipError_t launch_seg_scan(const ChunkSegs* cseg, uint32_t n, const SegFn* fn, S
 }
 
 hipError_t launch_seg_count(const uint8_t* seq, const SegIn* segs, uint32_t n, const SegStart* st, SegCount* out,
-                            hipStream_t s)
+                            uint8_t* rk, uint8_t* rf, uint32_t* ovf, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_count, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, st, out);
+    hipLaunchKernelGGL(k_seg_count, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, st, out, rk, rf, ovf);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_emit_heads(const uint8_t* seq, const SegIn* segs, const ChunkSegs* cseg, uint32_t n_chunks,
+                                 const SegStart* st, const uint64_t* seg_code, const uint64_t* seg_frag, uint8_t* dst,
+                                 uint32_t* codes, hipStream_t s)
+{
+    if (n_chunks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_emit_heads, dim3(cdiv(n_chunks, 64)), dim3(64), 0, s, seq, segs, cseg, n_chunks, st,
+                       seg_code, seg_frag, dst, codes);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_place(const SegIn* segs, uint32_t n, const SegCount* cnt, const uint64_t* seg_code,
+                            const uint64_t* seg_frag, const uint8_t* rk, const uint8_t* rf, uint32_t* codes,
+                            uint64_t n_codes, uint8_t* dst, uint64_t n_frag, uint32_t* err, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const uint32_t grid = n < 16384u ? n : 16384u;
+    hipLaunchKernelGGL(k_seg_place, dim3(grid), dim3(64), 0, s, segs, n, cnt, seg_code, seg_frag, rk, rf, codes,
+                       n_codes, dst, n_frag, err);
     return hipGetLastError();
 }
 

@@ -243,6 +243,10 @@ void pop_free(ev_ctx* c, Pop* P)
     delete P;
 }
 
+// Largest recording of a level's codes and fragments (about 8 bytes per
+// token); larger levels count, then emit.
+static constexpr uint64_t RECORD_MAX = (uint64_t)2 << 30;
+
 // Build the split plan of a population whose bytes are on the device.
 // Level 0 is the trees themselves; each level's chunks produce the next
 // level's skeleton until every tree is one value.  The host keeps what is
@@ -287,18 +291,20 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         }
     }
     uint8_t* cur = P->d_bytes;
+    uint64_t cur_len = P->total;  // bytes of the level's sequence
     bool cur_owned = false;
     int level = 0;
     // per-level device scratch: the level's trees, chunks and segments, the
     // segments' maps, starts, counts and positions, the chunks' numbering
     void *d_tl = nullptr, *d_ch = nullptr, *d_cseg = nullptr, *d_seg = nullptr, *d_fn = nullptr, *d_st = nullptr,
          *d_cnt = nullptr, *d_stat = nullptr, *d_loc = nullptr, *d_inend = nullptr, *d_sum = nullptr, *d_tb = nullptr,
-         *d_cb = nullptr, *d_fe = nullptr, *d_scode = nullptr, *d_sfrag = nullptr, *d_err = nullptr;
+         *d_cb = nullptr, *d_fe = nullptr, *d_scode = nullptr, *d_sfrag = nullptr, *d_err = nullptr, *d_rk = nullptr,
+         *d_rf = nullptr;
     ev_status st = EV_OK;
     // also frees a skeleton not yet handed to a level
     auto cleanup = [&]() {
         for (void** p : {&d_tl, &d_ch, &d_cseg, &d_seg, &d_fn, &d_st, &d_cnt, &d_stat, &d_loc, &d_inend, &d_sum, &d_tb,
-                         &d_cb, &d_fe, &d_scode, &d_sfrag, &d_err}) {
+                         &d_cb, &d_fe, &d_scode, &d_sfrag, &d_err, &d_rk, &d_rf}) {
             dev_free(c, *p);
             *p = nullptr;
         }
@@ -399,7 +405,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
             (st = realloc(&d_fn, n_seg * sizeof(SegFn))) || (st = realloc(&d_st, n_seg * sizeof(SegStart))) ||
             (st = realloc(&d_cnt, n_seg * sizeof(SegCount))) || (st = realloc(&d_stat, n * sizeof(ChunkStat))) ||
             (st = realloc(&d_loc, n * 3 * sizeof(uint64_t))) || (st = realloc(&d_inend, n * sizeof(uint32_t))) ||
-            (st = realloc(&d_sum, nt * sizeof(TreeSum))) ||
+            (st = realloc(&d_sum, (nt + 1) * sizeof(TreeSum))) ||
             (st = realloc(&d_tb, (size_t)std::max(1, M) * sizeof(TreeBase))) ||
             (st = put2(x, d_tl, tl.data(), tl_bytes, cursor, sizeof(cursor)))) {
             cleanup();
@@ -414,14 +420,28 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         HIPCHK(launch_seg_build((ChunkIn*)d_ch, (ChunkSegs*)d_cseg, (uint32_t)n, seg_len, head, (SegIn*)d_seg, s));
         HIPCHK(launch_seg_fn(cur, (SegIn*)d_seg, n_seg, (SegFn*)d_fn, level == 0 ? TOK_X : TOK_REF, s));
         HIPCHK(launch_seg_scan((ChunkSegs*)d_cseg, (uint32_t)n, (SegFn*)d_fn, (SegStart*)d_st, (ChunkStat*)d_stat, s));
-        HIPCHK(launch_seg_count(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (SegCount*)d_cnt, s));
+        // The count pass also records the segments' code kinds and fragment
+        // tokens when the recording fits, so that emission only has to place
+        // them (and run the chunks' first segments); the overflow flag rides
+        // in the totals' extra record.
+        const uint64_t rk_bytes = 5 * cur_len + 48 * (uint64_t)n_seg + 64;
+        const uint64_t rf_bytes = 3 * cur_len + 16 * (uint64_t)n_seg + 64;
+        const bool record = c->use_record && rk_bytes + rf_bytes <= RECORD_MAX;
+        uint32_t* d_ovf = &((TreeSum*)d_sum)[nt].bad;
+        if (record && ((st = realloc(&d_rk, rk_bytes)) || (st = realloc(&d_rf, rf_bytes)))) {
+            cleanup();
+            return st;
+        }
+        HIPCHK(launch_fill_u32((uint32_t*)((TreeSum*)d_sum + nt), sizeof(TreeSum) / 4, 0u, s));
+        HIPCHK(launch_seg_count(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (SegCount*)d_cnt,
+                                record ? (uint8_t*)d_rk : nullptr, record ? (uint8_t*)d_rf : nullptr, d_ovf, s));
         HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, (uint32_t)n, (SegCount*)d_cnt, (ChunkStat*)d_stat, nullptr, nullptr,
                                 nullptr, nullptr, s));
         HIPCHK(launch_plan_trees((TreeLvl*)d_tl, nt, (ChunkStat*)d_stat, (uint32_t)level, prev_out, d_cloc, d_oloc,
                                  d_floc, (uint32_t*)d_inend, (TreeSum*)d_sum, s));
         HIPCHK(launch_plan_bases((TreeLvl*)d_tl, nt, (TreeSum*)d_sum, (TreeBase*)d_tb, s));
-        tsum.resize(nt);
-        if ((st = get(x, tsum.data(), d_sum, nt * sizeof(TreeSum))) ||
+        tsum.resize(nt + 1);
+        if ((st = get(x, tsum.data(), d_sum, (nt + 1) * sizeof(TreeSum))) ||
             (level > 0 && (st = get(x, verr, (uint32_t*)d_err + 2 * (level - 1), 8))) || (st = sync(x))) {
             cleanup();
             return st;
@@ -526,8 +546,17 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         if (any || run_items) {
             HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, (uint32_t)n, (SegCount*)d_cnt, (ChunkStat*)d_stat,
                                     (uint64_t*)d_cb, (uint64_t*)d_fe, (uint64_t*)d_scode, (uint64_t*)d_sfrag, s));
-            HIPCHK(launch_seg_emit(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode, (uint64_t*)d_sfrag,
-                                   d_next, run_items ? LL.codes : nullptr, s));
+            if (record && tsum[nt].bad == 0) {
+                HIPCHK(launch_seg_place((SegIn*)d_seg, n_seg, (SegCount*)d_cnt, (uint64_t*)d_scode, (uint64_t*)d_sfrag,
+                                        (uint8_t*)d_rk, (uint8_t*)d_rf, run_items ? LL.codes : nullptr, sc, d_next, sf,
+                                        (uint32_t*)d_err + 2 * level, s));
+                HIPCHK(launch_seg_emit_heads(cur, (SegIn*)d_seg, (ChunkSegs*)d_cseg, (uint32_t)n, (SegStart*)d_st,
+                                             (uint64_t*)d_scode, (uint64_t*)d_sfrag, d_next,
+                                             run_items ? LL.codes : nullptr, s));
+            } else {
+                HIPCHK(launch_seg_emit(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode,
+                                       (uint64_t*)d_sfrag, d_next, run_items ? LL.codes : nullptr, s));
+            }
             if (run_items)
                 HIPCHK(launch_seg_check(LL.codes, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode,
                                         (SegCount*)d_cnt, LL.slab_entries, (uint32_t*)d_err + 2 * level, s));
@@ -565,6 +594,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
             break;
         }
         cur = d_next;
+        cur_len = sf;
         cur_owned = true;
         level++;
         if (level > MAX_LEVELS) {
@@ -1397,6 +1427,7 @@ ev_status ev_set_tuning(ev_ctx* c, uint32_t chunk, uint32_t chunk_hi, uint32_t l
         return fail(EV_EINVAL, "work items must be at least 64 tokens");
     c->use_run = c->run_ok && (flags & EV_TUNE_NO_REGSTACK) == 0;
     c->test_fail_check = (flags & EV_TUNE_TEST_FAIL_CHECK) != 0;
+    c->use_record = (flags & EV_TUNE_NO_RECORD) == 0;
     if (chunk) c->chunk = chunk;
     if (chunk_hi) c->chunk_hi = chunk_hi;
     if (lds_depth) c->lds_depth = (int)lds_depth;

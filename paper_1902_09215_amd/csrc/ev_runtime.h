@@ -128,6 +128,7 @@ struct ev_ctx {
     bool use_run = true;  // register-stack kernel for the items that fit it
     bool run_ok = true;   // the register-stack kernel can run here (probed at creation)
     bool test_fail_check = false;  // EV_TUNE_TEST_FAIL_CHECK
+    bool use_record = true;        // the count pass records codes for emission (EV_TUNE_NO_RECORD clears it)
     uint32_t* d_flag = nullptr;  // the probe's flag word
     uint32_t chunk = 4096;     // tokens per work item at level 0
     uint32_t chunk_hi = 0;     // at the skeleton levels (0: twice chunk)

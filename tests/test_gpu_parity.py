@@ -51,12 +51,13 @@ def run(ev, buf, off, x, y, chunk=0, lds=0, per_case=True, flags=0, chunk_hi=0):
 
 
 def check(ev, buf, off, x, y, chunk=0, lds=0, threads=8, what="", both=True, chunk_hi=0):
-    """Both interpreters (register-stack and general) against the oracle:
-    per-case values, fitness and hits."""
+    """Both interpreters (register-stack and general), and both ways of
+    emitting the codes (placing the counting pass's recording, or a second
+    pass), against the oracle: per-case values, fitness and hits."""
     want_fit, want_pc = oracle.eval_population(buf, off, x, y, threads=threads, per_case=True)
     want_hits = oracle.hits(want_pc, y)
     info = None
-    for flags in ((0, ev.EV_TUNE_NO_REGSTACK) if both else (0,)):
+    for flags in ((0, ev.EV_TUNE_NO_REGSTACK, ev.EV_TUNE_NO_RECORD) if both else (0,)):
         fit, pc, inf, hits = run(ev, buf, off, x, y, chunk, lds, flags=flags, chunk_hi=chunk_hi)
         assert_same(pc, want_pc, f"per-case {what} flags={flags}")
         assert_same(fit, want_fit, f"fitness {what} flags={flags}")
