@@ -230,7 +230,7 @@ ev_status ev_get_plan_info(ev_ctx *ctx, ev_pop pop, ev_plan_info *info);
  * instead of the register-stack one.  EV_TUNE_NO_RECORD makes the plan
  * builder emit codes by a second pass of the structure machine instead of
  * placing what its counting pass recorded (levels too large to record,
- * over about 250 million tokens, always do).  Plans made afterwards use them;
+ * over about 190 million tokens, always do).  Plans made afterwards use them;
  * results never depend on them.  EV_TUNE_TEST_FAIL_CHECK is a test hook
  * for the error path of code-stream validation: plans made afterwards
  * record their last level as failing it (the plan is refused, or, for the

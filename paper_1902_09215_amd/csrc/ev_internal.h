@@ -119,6 +119,14 @@ struct SegCount {
     uint32_t n_codes, n_frag, n_out, n_in, maxtop, pad;
 };
 
+// What a segment's recording leaves out: the chunk end's runs of n1 slot
+// writes from the slab (inserted before recorded kind a1) and n2 from the
+// window (before a2), and the REF tokens after its nfr recorded fragment
+// tokens.
+struct SegRec {
+    uint32_t a1, n1, a2, n2, nfr, pad;
+};
+
 // A work item of the register-stack kernel (16 bytes).
 struct RunChunk {
     uint64_t code_begin;  // index of its first code in the level's code stream

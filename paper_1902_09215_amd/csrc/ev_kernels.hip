@@ -131,23 +131,61 @@ struct Sink {
     uint32_t pending;  // an action waiting for a partner to fuse with, or ~0u
     uint32_t ref;      // index of the next REF within the work item (its ring slot mod EV_RING)
     // Recording (the count pass): the segment's code kinds, one byte each,
-    // and its fragment tokens in emission order, each into a region of the
-    // given capacity (nullptr: not recorded); ovf is set if one overflows.
+    // stored four at a time (rk is 4-byte aligned), and its fragment tokens
+    // in emission order, each into a region of the given capacity (nullptr:
+    // not recorded); ovf is set if one overflows.  The chunk-end runs of slot
+    // writes are not recorded, only where they go (rec).
     uint8_t* rk;
     uint8_t* rf;
     uint32_t rk_cap, rf_cap, ovf;
+    uint32_t nr, kacc;  // kinds recorded, and the word being filled
+    SegRec rec;
 
-    __device__ __forceinline__ void put(uint32_t kind)
+    __device__ __forceinline__ void rec_kind(uint32_t kind)
     {
-        if (codes) codes[at] = code_value(at, kind);
-        if (rk) {
-            if (n_codes < rk_cap)
-                rk[n_codes] = (uint8_t)kind;
+        const uint32_t j = nr++;
+        kacc |= kind << (8u * (j & 3u));
+        if ((j & 3u) == 3u) {
+            if ((j & ~3u) + 4u <= rk_cap)
+                *reinterpret_cast<uint32_t*>(rk + (j & ~3u)) = kacc;
+            else
+                ovf = 1;
+            kacc = 0;
+        }
+    }
+    // the last, partly filled word
+    __device__ __forceinline__ void rec_end()
+    {
+        if (rk && (nr & 3u)) {
+            if ((nr & ~3u) + 4u <= rk_cap)
+                *reinterpret_cast<uint32_t*>(rk + (nr & ~3u)) = kacc;
             else
                 ovf = 1;
         }
+    }
+    __device__ __forceinline__ void put(uint32_t kind)
+    {
+        if (codes) codes[at] = code_value(at, kind);
+        if (rk) rec_kind(kind);
         at++;
         n_codes++;
+    }
+    // count codes of one kind (which: 1 the memory run, 2 the window run)
+    __device__ __forceinline__ void run(uint32_t kind, uint32_t count, uint32_t which)
+    {
+        if (rk) {
+            if (which == 1) {
+                rec.a1 = nr;
+                rec.n1 = count;
+            } else {
+                rec.a2 = nr;
+                rec.n2 = count;
+            }
+        } else if (codes) {
+            for (uint32_t i = 0; i < count; i++) codes[at + i] = code_value(at + i, kind);
+        }
+        at += count;
+        n_codes += count;
     }
     __device__ void flush()
     {
@@ -201,17 +239,20 @@ struct Sink {
         }
         n_frag++;
     }
+    // count fragment tokens t (the chunk-end REFs, last in emission order;
+    // not recorded)
+    __device__ __forceinline__ void ftok_run(uint32_t t, uint32_t count)
+    {
+        if (frag)
+            for (uint32_t i = 0; i < count; i++) frag[--w] = (uint8_t)t;
+        n_frag += count;
+    }
     // put(e) unless e is ~0u, without branching on e
     __device__ __forceinline__ void put_if(uint32_t e)
     {
         const uint32_t has = e != ~0u ? 1u : 0u;
         if (codes && has) codes[at] = code_value(at, e);
-        if (rk && has) {
-            if (n_codes < rk_cap)
-                rk[n_codes] = (uint8_t)e;
-            else
-                ovf = 1;
-        }
+        if (rk && has) rec_kind(e);
         at += has;
         n_codes += has;
     }
@@ -359,18 +400,19 @@ __device__ uint32_t run_segment(const uint8_t* __restrict__ seq, uint64_t start,
     // (nothing is pending after a FLUSH, so the runs are put directly)
     if (base > 0) {
         o.code(EV_K_FLUSH);
-        for (uint32_t i = 0; i < base; i++) o.put(EV_K_OUTMEM);
+        o.run(EV_K_OUTMEM, base, 1);
     }
     if (m > base) {
         o.code(EV_K_FLUSH);
-        for (uint32_t i = base; i < m; i++) o.put(EV_K_OUTBOT);
+        o.run(EV_K_OUTBOT, m - base, 2);
     }
     if (tv) o.code(EV_K_OUTT);
     if (P) o.code(EV_K_OUTX);
     o.code(EV_K_END);
     const uint32_t left = m + tv + P;
     o.n_out += left;
-    for (uint32_t i = 0; i < left; i++) o.ftok(TOK_REF);
+    o.rec.nfr = o.n_frag;
+    o.ftok_run(TOK_REF, left);
     return maxtop;
 }
 
@@ -693,23 +735,23 @@ __global__ __launch_bounds__(64) void k_seg_scan(const ChunkSegs* __restrict__ c
 
 // Where a segment's recording goes: regions ordered like the segments'
 // tokens, which a level's segments cover in index order, so that they never
-// overlap (kinds: at most 4 per token plus the boundary's spills and fills;
-// fragment tokens: at most 2 per token).  A chunk's first segment, which
-// ends with the chunk's flush, is not recorded.
-__device__ __forceinline__ uint64_t rec_kinds_at(const SegIn& g, uint32_t si) { return 5ull * g.start + 48ull * si; }
+// overlap (kinds: at most 4 per token plus the boundary's spills and fills,
+// or the chunk end's flushes and last codes; fragment tokens: at most 2 per
+// token).  Kind regions are 8-byte aligned.
+__device__ __forceinline__ uint64_t rec_kinds_at(const SegIn& g, uint32_t si) { return 8ull * g.start + 64ull * si; }
 __device__ __forceinline__ uint64_t rec_frags_at(const SegIn& g, uint32_t si) { return 3ull * g.start + 16ull * si; }
 
 // Per segment: its counts; with rk/rf, also the recording of its codes'
 // kinds and fragment tokens (set *ovf if a region was too small).
 __global__ void k_seg_count(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs, uint32_t n,
                             const SegStart* __restrict__ st, SegCount* __restrict__ out, uint8_t* __restrict__ rk,
-                            uint8_t* __restrict__ rf, uint32_t* __restrict__ ovf)
+                            uint8_t* __restrict__ rf, SegRec* __restrict__ rec, uint32_t* __restrict__ ovf)
 {
     const uint32_t si = blockIdx.x * blockDim.x + threadIdx.x;
     if (si >= n) return;
     const SegIn g = segs[si];
-    Sink o{nullptr, 0, nullptr, 0, 0, 0, 0, 0, ~0u, st[si].ref0, nullptr, nullptr, 0, 0, 0};
-    if (rk && !g.last) {
+    Sink o{nullptr, 0, nullptr, 0, 0, 0, 0, 0, ~0u, st[si].ref0, nullptr, nullptr, 0, 0, 0, 0, 0, SegRec{}};
+    if (rk) {
         o.rk = rk + rec_kinds_at(g, si);
         o.rf = rf + rec_frags_at(g, si);
         o.rk_cap = 4u * g.len + 40u;
@@ -717,7 +759,12 @@ __global__ void k_seg_count(const uint8_t* __restrict__ seq, const SegIn* __rest
     }
     const uint32_t maxtop = run_segment(seq, g.start, g.len, st[si].cnt, st[si].P, g.last != 0, o);
     out[si] = SegCount{o.n_codes, o.n_frag, o.n_out, o.n_in, maxtop, 0};
-    if (o.ovf) atomicOr(ovf, 1u);
+    if (rk) {
+        o.rec_end();
+        if (!g.last) o.rec.nfr = o.n_frag;
+        rec[si] = o.rec;
+        if (o.ovf) atomicOr(ovf, 1u);
+    }
 }
 
 // Per chunk, one wave: totals for the plan (first launch, no code_begin),
@@ -805,7 +852,7 @@ __device__ __forceinline__ void emit_segment(const uint8_t* __restrict__ seq, co
     const bool has_codes = codes && seg_code[si] != ~0ull;
     if (!dst && !has_codes) return;
     Sink o{has_codes ? codes : nullptr, has_codes ? seg_code[si] : 0, dst, dst ? seg_frag[si] : 0, 0, 0, 0, 0, ~0u,
-           st[si].ref0, nullptr, nullptr, 0, 0, 0};
+           st[si].ref0, nullptr, nullptr, 0, 0, 0, 0, 0, SegRec{}};
     run_segment(seq, g.start, g.len, st[si].cnt, st[si].P, g.last != 0, o);
 }
 
@@ -818,26 +865,15 @@ __global__ void k_seg_emit(const uint8_t* __restrict__ seq, const SegIn* __restr
     emit_segment(seq, segs, si, st, seg_code, seg_frag, dst, codes);
 }
 
-// The first segment of every chunk (recorded levels: the other segments are
-// placed from their recordings).
-__global__ void k_seg_emit_heads(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs,
-                                 const ChunkSegs* __restrict__ cseg, uint32_t n_chunks,
-                                 const SegStart* __restrict__ st, const uint64_t* __restrict__ seg_code,
-                                 const uint64_t* __restrict__ seg_frag, uint8_t* __restrict__ dst,
-                                 uint32_t* __restrict__ codes)
-{
-    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_chunks) return;
-    const ChunkSegs cs = cseg[c];
-    if (cs.n_seg) emit_segment(seq, segs, cs.first, st, seg_code, seg_frag, dst, codes);
-}
-
 // A recorded segment's codes and fragment tokens to their places, one wave
 // per segment: each kind becomes its handler's offset at the code's final
-// position.  Writes outside [0, n_codes) or [0, n_frag) are skipped and
-// flagged (err), which the validator's words carry to the host.
+// position, and a chunk's end gets its runs of slot writes and REF tokens
+// back.  Writes outside [0, n_codes) or [0, n_frag), and reads past a
+// recording, are skipped and flagged (err), which the validator's words
+// carry to the host.
 __global__ __launch_bounds__(64) void k_seg_place(const SegIn* __restrict__ segs, uint32_t n,
-                                                  const SegCount* __restrict__ cnt, const uint64_t* __restrict__ seg_code,
+                                                  const SegCount* __restrict__ cnt, const SegRec* __restrict__ rec,
+                                                  const uint64_t* __restrict__ seg_code,
                                                   const uint64_t* __restrict__ seg_frag, const uint8_t* __restrict__ rk,
                                                   const uint8_t* __restrict__ rf, uint32_t* __restrict__ codes,
                                                   uint64_t n_codes, uint8_t* __restrict__ dst, uint64_t n_frag,
@@ -847,15 +883,31 @@ __global__ __launch_bounds__(64) void k_seg_place(const SegIn* __restrict__ segs
     uint32_t bad = 0;
     for (uint32_t si = blockIdx.x; si < n; si += gridDim.x) {
         const SegIn g = segs[si];
-        if (g.last) continue;
         const SegCount q = cnt[si];
+        const SegRec r = rec[si];
+        const uint32_t cap_k = 4u * g.len + 40u, cap_f = 2u * g.len + 16u;
         if (codes && seg_code[si] != ~0ull) {
             const uint64_t b = seg_code[si];
             const uint8_t* k = rk + rec_kinds_at(g, si);
             for (uint32_t i = lane; i < q.n_codes; i += 64) {
+                // recorded kinds, with the memory run (n1 codes) inserted
+                // before recorded kind a1 and the window run (n2) before a2
+                uint32_t kind, src = i;
+                if (i >= r.a1 && i < r.a1 + r.n1) {
+                    kind = EV_K_OUTMEM;
+                } else {
+                    if (i >= r.a1 + r.n1) src -= r.n1;
+                    if (src >= r.a2 && src < r.a2 + r.n2) {
+                        kind = EV_K_OUTBOT;
+                    } else {
+                        if (src >= r.a2 + r.n2) src -= r.n2;
+                        kind = src < cap_k ? k[src] : 0u;
+                        bad |= src < cap_k ? 0u : 1u;
+                    }
+                }
                 const uint64_t at = b + i;
                 if (at < n_codes)
-                    codes[at] = code_value(at, k[i]);
+                    codes[at] = code_value(at, kind);
                 else
                     bad = 1;
             }
@@ -864,8 +916,10 @@ __global__ __launch_bounds__(64) void k_seg_place(const SegIn* __restrict__ segs
             const uint64_t w = seg_frag[si];
             const uint8_t* f = rf + rec_frags_at(g, si);
             for (uint32_t i = lane; i < q.n_frag; i += 64) {
+                const uint8_t t = i < r.nfr ? (i < cap_f ? f[i] : (uint8_t)0xFF) : (uint8_t)TOK_REF;
+                bad |= (i < r.nfr && i >= cap_f) ? 1u : 0u;
                 if (i < w && w - 1 - i < n_frag)
-                    dst[w - 1 - i] = f[i];
+                    dst[w - 1 - i] = t;
                 else
                     bad = 1;
             }
@@ -1566,30 +1620,21 @@ hipError_t launch_seg_scan(const ChunkSegs* cseg, uint32_t n, const SegFn* fn, S
 }
 
 hipError_t launch_seg_count(const uint8_t* seq, const SegIn* segs, uint32_t n, const SegStart* st, SegCount* out,
-                            uint8_t* rk, uint8_t* rf, uint32_t* ovf, hipStream_t s)
+                            uint8_t* rk, uint8_t* rf, SegRec* rec, uint32_t* ovf, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_count, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, st, out, rk, rf, ovf);
+    hipLaunchKernelGGL(k_seg_count, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, st, out, rk, rf, rec, ovf);
     return hipGetLastError();
 }
 
-hipError_t launch_seg_emit_heads(const uint8_t* seq, const SegIn* segs, const ChunkSegs* cseg, uint32_t n_chunks,
-                                 const SegStart* st, const uint64_t* seg_code, const uint64_t* seg_frag, uint8_t* dst,
-                                 uint32_t* codes, hipStream_t s)
-{
-    if (n_chunks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_emit_heads, dim3(cdiv(n_chunks, 64)), dim3(64), 0, s, seq, segs, cseg, n_chunks, st,
-                       seg_code, seg_frag, dst, codes);
-    return hipGetLastError();
-}
-
-hipError_t launch_seg_place(const SegIn* segs, uint32_t n, const SegCount* cnt, const uint64_t* seg_code,
-                            const uint64_t* seg_frag, const uint8_t* rk, const uint8_t* rf, uint32_t* codes,
-                            uint64_t n_codes, uint8_t* dst, uint64_t n_frag, uint32_t* err, hipStream_t s)
+hipError_t launch_seg_place(const SegIn* segs, uint32_t n, const SegCount* cnt, const SegRec* rec,
+                            const uint64_t* seg_code, const uint64_t* seg_frag, const uint8_t* rk, const uint8_t* rf,
+                            uint32_t* codes, uint64_t n_codes, uint8_t* dst, uint64_t n_frag, uint32_t* err,
+                            hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const uint32_t grid = n < 16384u ? n : 16384u;
-    hipLaunchKernelGGL(k_seg_place, dim3(grid), dim3(64), 0, s, segs, n, cnt, seg_code, seg_frag, rk, rf, codes,
+    hipLaunchKernelGGL(k_seg_place, dim3(grid), dim3(64), 0, s, segs, n, cnt, rec, seg_code, seg_frag, rk, rf, codes,
                        n_codes, dst, n_frag, err);
     return hipGetLastError();
 }

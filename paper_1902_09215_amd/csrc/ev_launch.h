@@ -25,15 +25,13 @@ hipError_t launch_seg_fn(const uint8_t* seq, const SegIn* segs, uint32_t n, SegF
                          hipStream_t s);
 hipError_t launch_seg_scan(const ChunkSegs* cseg, uint32_t n, const SegFn* fn, SegStart* st, ChunkStat* cstat,
                            hipStream_t s);
-// rk/rf (nullable): record the segments' code kinds and fragment tokens
+// rk/rf/rec (nullable): record the segments' code kinds and fragment tokens
 hipError_t launch_seg_count(const uint8_t* seq, const SegIn* segs, uint32_t n, const SegStart* st, SegCount* out,
-                            uint8_t* rk, uint8_t* rf, uint32_t* ovf, hipStream_t s);
-hipError_t launch_seg_emit_heads(const uint8_t* seq, const SegIn* segs, const ChunkSegs* cseg, uint32_t n_chunks,
-                                 const SegStart* st, const uint64_t* seg_code, const uint64_t* seg_frag, uint8_t* dst,
-                                 uint32_t* codes, hipStream_t s);
-hipError_t launch_seg_place(const SegIn* segs, uint32_t n, const SegCount* cnt, const uint64_t* seg_code,
-                            const uint64_t* seg_frag, const uint8_t* rk, const uint8_t* rf, uint32_t* codes,
-                            uint64_t n_codes, uint8_t* dst, uint64_t n_frag, uint32_t* err, hipStream_t s);
+                            uint8_t* rk, uint8_t* rf, SegRec* rec, uint32_t* ovf, hipStream_t s);
+hipError_t launch_seg_place(const SegIn* segs, uint32_t n, const SegCount* cnt, const SegRec* rec,
+                            const uint64_t* seg_code, const uint64_t* seg_frag, const uint8_t* rk, const uint8_t* rf,
+                            uint32_t* codes, uint64_t n_codes, uint8_t* dst, uint64_t n_frag, uint32_t* err,
+                            hipStream_t s);
 hipError_t launch_seg_chunk(const ChunkSegs* cseg, uint32_t n, const SegCount* cnt, ChunkStat* cstat,
                             const uint64_t* code_begin, const uint64_t* frag_end, uint64_t* seg_code, uint64_t* seg_frag,
                             hipStream_t s);

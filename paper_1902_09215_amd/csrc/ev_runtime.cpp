@@ -243,7 +243,7 @@ void pop_free(ev_ctx* c, Pop* P)
     delete P;
 }
 
-// Largest recording of a level's codes and fragments (about 8 bytes per
+// Largest recording of a level's codes and fragments (about 11 bytes per
 // token); larger levels count, then emit.
 static constexpr uint64_t RECORD_MAX = (uint64_t)2 << 30;
 
@@ -299,12 +299,12 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
     void *d_tl = nullptr, *d_ch = nullptr, *d_cseg = nullptr, *d_seg = nullptr, *d_fn = nullptr, *d_st = nullptr,
          *d_cnt = nullptr, *d_stat = nullptr, *d_loc = nullptr, *d_inend = nullptr, *d_sum = nullptr, *d_tb = nullptr,
          *d_cb = nullptr, *d_fe = nullptr, *d_scode = nullptr, *d_sfrag = nullptr, *d_err = nullptr, *d_rk = nullptr,
-         *d_rf = nullptr;
+         *d_rf = nullptr, *d_rec = nullptr;
     ev_status st = EV_OK;
     // also frees a skeleton not yet handed to a level
     auto cleanup = [&]() {
         for (void** p : {&d_tl, &d_ch, &d_cseg, &d_seg, &d_fn, &d_st, &d_cnt, &d_stat, &d_loc, &d_inend, &d_sum, &d_tb,
-                         &d_cb, &d_fe, &d_scode, &d_sfrag, &d_err, &d_rk, &d_rf}) {
+                         &d_cb, &d_fe, &d_scode, &d_sfrag, &d_err, &d_rk, &d_rf, &d_rec}) {
             dev_free(c, *p);
             *p = nullptr;
         }
@@ -424,17 +424,19 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         // tokens when the recording fits, so that emission only has to place
         // them (and run the chunks' first segments); the overflow flag rides
         // in the totals' extra record.
-        const uint64_t rk_bytes = 5 * cur_len + 48 * (uint64_t)n_seg + 64;
+        const uint64_t rk_bytes = 8 * cur_len + 64 * (uint64_t)n_seg + 64;
         const uint64_t rf_bytes = 3 * cur_len + 16 * (uint64_t)n_seg + 64;
         const bool record = c->use_record && rk_bytes + rf_bytes <= RECORD_MAX;
         uint32_t* d_ovf = &((TreeSum*)d_sum)[nt].bad;
-        if (record && ((st = realloc(&d_rk, rk_bytes)) || (st = realloc(&d_rf, rf_bytes)))) {
+        if (record && ((st = realloc(&d_rk, rk_bytes)) || (st = realloc(&d_rf, rf_bytes)) ||
+                       (st = realloc(&d_rec, (uint64_t)n_seg * sizeof(SegRec))))) {
             cleanup();
             return st;
         }
         HIPCHK(launch_fill_u32((uint32_t*)((TreeSum*)d_sum + nt), sizeof(TreeSum) / 4, 0u, s));
         HIPCHK(launch_seg_count(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (SegCount*)d_cnt,
-                                record ? (uint8_t*)d_rk : nullptr, record ? (uint8_t*)d_rf : nullptr, d_ovf, s));
+                                record ? (uint8_t*)d_rk : nullptr, record ? (uint8_t*)d_rf : nullptr,
+                                record ? (SegRec*)d_rec : nullptr, d_ovf, s));
         HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, (uint32_t)n, (SegCount*)d_cnt, (ChunkStat*)d_stat, nullptr, nullptr,
                                 nullptr, nullptr, s));
         HIPCHK(launch_plan_trees((TreeLvl*)d_tl, nt, (ChunkStat*)d_stat, (uint32_t)level, prev_out, d_cloc, d_oloc,
@@ -547,12 +549,10 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
             HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, (uint32_t)n, (SegCount*)d_cnt, (ChunkStat*)d_stat,
                                     (uint64_t*)d_cb, (uint64_t*)d_fe, (uint64_t*)d_scode, (uint64_t*)d_sfrag, s));
             if (record && tsum[nt].bad == 0) {
-                HIPCHK(launch_seg_place((SegIn*)d_seg, n_seg, (SegCount*)d_cnt, (uint64_t*)d_scode, (uint64_t*)d_sfrag,
-                                        (uint8_t*)d_rk, (uint8_t*)d_rf, run_items ? LL.codes : nullptr, sc, d_next, sf,
-                                        (uint32_t*)d_err + 2 * level, s));
-                HIPCHK(launch_seg_emit_heads(cur, (SegIn*)d_seg, (ChunkSegs*)d_cseg, (uint32_t)n, (SegStart*)d_st,
-                                             (uint64_t*)d_scode, (uint64_t*)d_sfrag, d_next,
-                                             run_items ? LL.codes : nullptr, s));
+                HIPCHK(launch_seg_place((SegIn*)d_seg, n_seg, (SegCount*)d_cnt, (SegRec*)d_rec, (uint64_t*)d_scode,
+                                        (uint64_t*)d_sfrag, (uint8_t*)d_rk, (uint8_t*)d_rf,
+                                        run_items ? LL.codes : nullptr, sc, d_next, sf, (uint32_t*)d_err + 2 * level,
+                                        s));
             } else {
                 HIPCHK(launch_seg_emit(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode,
                                        (uint64_t*)d_sfrag, d_next, run_items ? LL.codes : nullptr, s));
