@@ -869,47 +869,144 @@ __global__ void k_seg_emit(const uint8_t* __restrict__ seq, const SegIn* __restr
 // per segment: each kind becomes its handler's offset at the code's final
 // position, and a chunk's end gets its runs of slot writes and REF tokens
 // back.  Writes outside [0, n_codes) or [0, n_frag), and reads past a
-// recording, are skipped and flagged (err), which the validator's words
-// carry to the host.
+// recording, are skipped and flagged.
+//
+// The wave also validates the segment's codes as k_seg_check does, 64 codes
+// at a time: the window index, slab depth, slot-write count since the last
+// FLUSH, REF count and the FLUSH and END states before each code are
+// prefix sums (or prefix ORs) of per-code steps, taken with ballots and
+// shuffles, carried from batch to batch.  Flags go to err[0] (0x200 for a
+// placement fault), the first failing segment to err[1].
 __global__ __launch_bounds__(64) void k_seg_place(const SegIn* __restrict__ segs, uint32_t n,
                                                   const SegCount* __restrict__ cnt, const SegRec* __restrict__ rec,
+                                                  const SegStart* __restrict__ st,
                                                   const uint64_t* __restrict__ seg_code,
                                                   const uint64_t* __restrict__ seg_frag, const uint8_t* __restrict__ rk,
                                                   const uint8_t* __restrict__ rf, uint32_t* __restrict__ codes,
                                                   uint64_t n_codes, uint8_t* __restrict__ dst, uint64_t n_frag,
-                                                  uint32_t* __restrict__ err)
+                                                  uint32_t slab_entries, uint32_t* __restrict__ err)
 {
     const uint32_t lane = threadIdx.x;
-    uint32_t bad = 0;
+    const uint64_t lt = (1ull << lane) - 1ull;  // the lanes before this one
     for (uint32_t si = blockIdx.x; si < n; si += gridDim.x) {
         const SegIn g = segs[si];
         const SegCount q = cnt[si];
         const SegRec r = rec[si];
         const uint32_t cap_k = 4u * g.len + 40u, cap_f = 2u * g.len + 16u;
+        uint32_t bad = 0;
         if (codes && seg_code[si] != ~0ull) {
             const uint64_t b = seg_code[si];
-            const uint8_t* k = rk + rec_kinds_at(g, si);
-            for (uint32_t i = lane; i < q.n_codes; i += 64) {
+            const uint8_t* kp = rk + rec_kinds_at(g, si);
+            // the machine's state before the batch
+            const SegStart s0 = st[si];
+            const uint32_t tv0 = s0.cnt > s0.P ? 1u : 0u, m0 = s0.cnt - tv0 - s0.P;
+            int32_t slab = (int32_t)norm_base(m0), idx = (int32_t)(m0 - (uint32_t)slab);
+            uint32_t ins = 0, nbm = 0, nbm_flush = 0, outs = 0;
+            bool tail = false, ended = false;
+            for (uint32_t i0 = 0; i0 < q.n_codes; i0 += 64) {
+                const uint32_t i = i0 + lane;
+                const bool live = i < q.n_codes;
                 // recorded kinds, with the memory run (n1 codes) inserted
                 // before recorded kind a1 and the window run (n2) before a2
-                uint32_t kind, src = i;
-                if (i >= r.a1 && i < r.a1 + r.n1) {
-                    kind = EV_K_OUTMEM;
-                } else {
-                    if (i >= r.a1 + r.n1) src -= r.n1;
-                    if (src >= r.a2 && src < r.a2 + r.n2) {
-                        kind = EV_K_OUTBOT;
+                uint32_t k = EV_NK;  // none
+                if (live) {
+                    uint32_t src = i;
+                    if (i >= r.a1 && i < r.a1 + r.n1) {
+                        k = EV_K_OUTMEM;
                     } else {
-                        if (src >= r.a2 + r.n2) src -= r.n2;
-                        kind = src < cap_k ? k[src] : 0u;
-                        bad |= src < cap_k ? 0u : 1u;
+                        if (i >= r.a1 + r.n1) src -= r.n1;
+                        if (src >= r.a2 && src < r.a2 + r.n2) {
+                            k = EV_K_OUTBOT;
+                        } else {
+                            if (src >= r.a2 + r.n2) src -= r.n2;
+                            k = src < cap_k ? kp[src] : 0u;
+                            bad |= src < cap_k ? 0u : 0x200u;
+                        }
+                    }
+                    const uint64_t at = b + i;
+                    if (at < n_codes)
+                        codes[at] = code_value(at, k);
+                    else
+                        bad |= 0x200u;
+                    if (k >= EV_NK) bad |= 1u;
+                }
+                // the code's kind class
+                const bool isF = k == EV_K_FLUSH, isE = k == EV_K_END, isB = k == EV_K_OUTBOT, isM = k == EV_K_OUTMEM;
+                const bool isT = k == EV_K_OUTT, isX = k == EV_K_OUTX;
+                const bool ops1 = k <= EV_K_OPS3;
+                const bool ops2 = k >= EV_K_OPS00 && k <= EV_K_OPS22;
+                const bool pref = k >= EV_K_PUSHREF0 && k < EV_K_PUSHREF0 + EV_RING;
+                const bool lref = k >= EV_K_LOADREF0 && k < EV_K_LOADREF0 + EV_RING;
+                const bool push1 = (k >= EV_K_CH0 && k <= EV_K_CH3) || k == EV_K_PUSHX || pref;
+                const bool push2 = k == EV_K_PUSH2X || (k >= EV_K_PXCH0 && k <= EV_K_PXCH3);
+                const bool spill = k == EV_K_SPILL, fill = k == EV_K_FILL;
+                // FLUSH, END and slot-write states before this code
+                const uint64_t bF = __ballot(isF), bE = __ballot(isE), bBM = __ballot(isB || isM);
+                const bool tail_b = tail || (bF & lt) != 0;
+                const bool ended_b = ended || (bE & lt) != 0;
+                uint32_t at_flush = nbm_flush;  // slot writes before the last FLUSH before this code
+                if (bF & lt) {
+                    const uint32_t l = 63u - (uint32_t)__clzll(bF & lt);
+                    at_flush = nbm + (uint32_t)__popcll(bBM & ((1ull << l) - 1ull));
+                }
+                const int32_t fl = (int32_t)(nbm + (uint32_t)__popcll(bBM & lt) - at_flush);
+                // window and slab steps (none after a FLUSH)
+                const int32_t need = ops1 ? 1 : (ops2 ? 2 : 0);
+                int32_t di = ops1 ? -1 : ops2 ? -2 : push1 ? 1 : (push2 ? 2 : 0);
+                di += spill ? -(int32_t)EV_VHALF : (fill ? (int32_t)EV_VHALF : 0);
+                int32_t ds = spill ? (int32_t)EV_VHALF : (fill ? -(int32_t)EV_VHALF : 0);
+                const bool isref = (pref || lref) && !tail_b;
+                if (tail_b) di = ds = 0;
+                int32_t si_ = di, ss_ = ds;  // inclusive sums over the batch
+                for (uint32_t d = 1; d < 64; d <<= 1) {
+                    const int32_t ti = __shfl_up(si_, d, 64), ts = __shfl_up(ss_, d, 64);
+                    if (lane >= d) {
+                        si_ += ti;
+                        ss_ += ts;
                     }
                 }
-                const uint64_t at = b + i;
-                if (at < n_codes)
-                    codes[at] = code_value(at, kind);
-                else
-                    bad = 1;
+                const int32_t ib = idx + si_ - di, sb = slab + ss_ - ds;  // before this code
+                const int32_t ia = idx + si_, sa = slab + ss_;           // after it
+                const uint64_t bR = __ballot(isref);
+                const uint32_t ins_b = ins + (uint32_t)__popcll(bR & lt);
+                if (live) {
+                    if (ended_b) bad |= 4u;
+                    uint32_t w = 0;
+                    if (tail_b) {
+                        // only the chunk's final slot writes and END, none
+                        // of which moves the window
+                        w |= !(isF || isB || isM || isT || isX || isE) ? 1u : 0u;
+                        w |= (isB && fl >= ib) || (isM && fl >= sb) ? 1u : 0u;
+                    } else {
+                        w |= ib < need ? 1u : 0u;
+                        const uint32_t slot = (s0.ref0 + ins_b) & (EV_RING - 1u);
+                        if ((pref && k - EV_K_PUSHREF0 != slot) || (lref && k - EV_K_LOADREF0 != slot)) bad |= 1u;
+                        w |= (isB && fl >= ib) || (isM && fl >= sb) ? 1u : 0u;
+                        w |= spill && ib < (int32_t)EV_VHALF ? 1u : 0u;
+                        w |= fill && (sb < (int32_t)EV_VHALF || ib > (int32_t)EV_VHALF - 1) ? 1u : 0u;
+                        w |= ia < 0 || ia > (int32_t)EV_VSTACK - 1 || sa < 0 || sa > (int32_t)slab_entries ? 1u : 0u;
+                    }
+                    if (w) bad |= 2u;
+                }
+                // carry to the next batch
+                idx += __shfl(si_, 63, 64);
+                slab += __shfl(ss_, 63, 64);
+                ins += (uint32_t)__popcll(bR);
+                if (bF) {
+                    const uint32_t l = 63u - (uint32_t)__clzll(bF);
+                    nbm_flush = nbm + (uint32_t)__popcll(bBM & ((1ull << l) - 1ull));
+                }
+                nbm += (uint32_t)__popcll(bBM);
+                outs += (uint32_t)__popcll(__ballot(isB || isM || isT || isX));
+                tail = tail || bF != 0;
+                ended = ended || bE != 0;
+            }
+            if (lane == 0) {
+                if (ended != (g.last != 0)) bad |= 4u;
+                // a segment hands the next one the window in its boundary position
+                if (!g.last && (uint32_t)slab != norm_base((uint32_t)(idx + slab))) bad |= 8u;
+                if (outs != q.n_out) bad |= 16u;
+                if (ins != q.n_in) bad |= 32u;
             }
         }
         if (dst) {
@@ -917,15 +1014,18 @@ __global__ __launch_bounds__(64) void k_seg_place(const SegIn* __restrict__ segs
             const uint8_t* f = rf + rec_frags_at(g, si);
             for (uint32_t i = lane; i < q.n_frag; i += 64) {
                 const uint8_t t = i < r.nfr ? (i < cap_f ? f[i] : (uint8_t)0xFF) : (uint8_t)TOK_REF;
-                bad |= (i < r.nfr && i >= cap_f) ? 1u : 0u;
+                bad |= (i < r.nfr && i >= cap_f) ? 0x200u : 0u;
                 if (i < w && w - 1 - i < n_frag)
                     dst[w - 1 - i] = t;
                 else
-                    bad = 1;
+                    bad |= 0x200u;
             }
         }
+        if (bad) {
+            atomicOr(err, bad);
+            atomicMin(err + 1, si);
+        }
     }
-    if (bad) atomicOr(err, 0x200u);
 }
 
 // Every code must name a handler of its own position and only a chunk's
@@ -1627,15 +1727,15 @@ hipError_t launch_seg_count(const uint8_t* seq, const SegIn* segs, uint32_t n, c
     return hipGetLastError();
 }
 
-hipError_t launch_seg_place(const SegIn* segs, uint32_t n, const SegCount* cnt, const SegRec* rec,
+hipError_t launch_seg_place(const SegIn* segs, uint32_t n, const SegCount* cnt, const SegRec* rec, const SegStart* st,
                             const uint64_t* seg_code, const uint64_t* seg_frag, const uint8_t* rk, const uint8_t* rf,
-                            uint32_t* codes, uint64_t n_codes, uint8_t* dst, uint64_t n_frag, uint32_t* err,
-                            hipStream_t s)
+                            uint32_t* codes, uint64_t n_codes, uint8_t* dst, uint64_t n_frag, uint32_t slab_entries,
+                            uint32_t* err, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const uint32_t grid = n < 16384u ? n : 16384u;
-    hipLaunchKernelGGL(k_seg_place, dim3(grid), dim3(64), 0, s, segs, n, cnt, rec, seg_code, seg_frag, rk, rf, codes,
-                       n_codes, dst, n_frag, err);
+    hipLaunchKernelGGL(k_seg_place, dim3(grid), dim3(64), 0, s, segs, n, cnt, rec, st, seg_code, seg_frag, rk, rf,
+                       codes, n_codes, dst, n_frag, slab_entries, err);
     return hipGetLastError();
 }
 

@@ -28,10 +28,11 @@ hipError_t launch_seg_scan(const ChunkSegs* cseg, uint32_t n, const SegFn* fn, S
 // rk/rf/rec (nullable): record the segments' code kinds and fragment tokens
 hipError_t launch_seg_count(const uint8_t* seq, const SegIn* segs, uint32_t n, const SegStart* st, SegCount* out,
                             uint8_t* rk, uint8_t* rf, SegRec* rec, uint32_t* ovf, hipStream_t s);
-hipError_t launch_seg_place(const SegIn* segs, uint32_t n, const SegCount* cnt, const SegRec* rec,
+// places recorded segments and validates their codes (as launch_seg_check)
+hipError_t launch_seg_place(const SegIn* segs, uint32_t n, const SegCount* cnt, const SegRec* rec, const SegStart* st,
                             const uint64_t* seg_code, const uint64_t* seg_frag, const uint8_t* rk, const uint8_t* rf,
-                            uint32_t* codes, uint64_t n_codes, uint8_t* dst, uint64_t n_frag, uint32_t* err,
-                            hipStream_t s);
+                            uint32_t* codes, uint64_t n_codes, uint8_t* dst, uint64_t n_frag, uint32_t slab_entries,
+                            uint32_t* err, hipStream_t s);
 hipError_t launch_seg_chunk(const ChunkSegs* cseg, uint32_t n, const SegCount* cnt, ChunkStat* cstat,
                             const uint64_t* code_begin, const uint64_t* frag_end, uint64_t* seg_code, uint64_t* seg_frag,
                             hipStream_t s);

@@ -549,17 +549,18 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
             HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, (uint32_t)n, (SegCount*)d_cnt, (ChunkStat*)d_stat,
                                     (uint64_t*)d_cb, (uint64_t*)d_fe, (uint64_t*)d_scode, (uint64_t*)d_sfrag, s));
             if (record && tsum[nt].bad == 0) {
-                HIPCHK(launch_seg_place((SegIn*)d_seg, n_seg, (SegCount*)d_cnt, (SegRec*)d_rec, (uint64_t*)d_scode,
-                                        (uint64_t*)d_sfrag, (uint8_t*)d_rk, (uint8_t*)d_rf,
-                                        run_items ? LL.codes : nullptr, sc, d_next, sf, (uint32_t*)d_err + 2 * level,
-                                        s));
+                // placement validates the codes as it writes them
+                HIPCHK(launch_seg_place((SegIn*)d_seg, n_seg, (SegCount*)d_cnt, (SegRec*)d_rec, (SegStart*)d_st,
+                                        (uint64_t*)d_scode, (uint64_t*)d_sfrag, (uint8_t*)d_rk, (uint8_t*)d_rf,
+                                        run_items ? LL.codes : nullptr, sc, d_next, sf, LL.slab_entries,
+                                        (uint32_t*)d_err + 2 * level, s));
             } else {
                 HIPCHK(launch_seg_emit(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode,
                                        (uint64_t*)d_sfrag, d_next, run_items ? LL.codes : nullptr, s));
+                if (run_items)
+                    HIPCHK(launch_seg_check(LL.codes, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode,
+                                            (SegCount*)d_cnt, LL.slab_entries, (uint32_t*)d_err + 2 * level, s));
             }
-            if (run_items)
-                HIPCHK(launch_seg_check(LL.codes, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode,
-                                        (SegCount*)d_cnt, LL.slab_entries, (uint32_t*)d_err + 2 * level, s));
         }
         if (!any) {
             // where each tree's value is, for the fitness kernel
