@@ -957,14 +957,16 @@ __global__ __launch_bounds__(64) void k_seg_place(const SegIn* __restrict__ segs
                 int32_t ds = spill ? (int32_t)EV_VHALF : (fill ? -(int32_t)EV_VHALF : 0);
                 const bool isref = (pref || lref) && !tail_b;
                 if (tail_b) di = ds = 0;
-                int32_t si_ = di, ss_ = ds;  // inclusive sums over the batch
+                // inclusive sums over the batch, both in one word: each step
+                // biased by 32 into its own 16 bits (at most 64 x 64 each)
+                static_assert(EV_VHALF <= 32u, "window steps must fit the 16-bit scan halves");
+                uint32_t ps = (uint32_t)(di + 32) | ((uint32_t)(ds + 32) << 16);
                 for (uint32_t d = 1; d < 64; d <<= 1) {
-                    const int32_t ti = __shfl_up(si_, d, 64), ts = __shfl_up(ss_, d, 64);
-                    if (lane >= d) {
-                        si_ += ti;
-                        ss_ += ts;
-                    }
+                    const uint32_t t = __shfl_up(ps, d, 64);
+                    if (lane >= d) ps += t;
                 }
+                const int32_t si_ = (int32_t)(ps & 0xFFFFu) - 32 * (int32_t)(lane + 1);
+                const int32_t ss_ = (int32_t)(ps >> 16) - 32 * (int32_t)(lane + 1);
                 const int32_t ib = idx + si_ - di, sb = slab + ss_ - ds;  // before this code
                 const int32_t ia = idx + si_, sa = slab + ss_;           // after it
                 const uint64_t bR = __ballot(isref);
