@@ -225,7 +225,8 @@ ev_status ev_get_plan_info(ev_ctx *ctx, ev_pop pop, ev_plan_info *info);
  * of the split at level 0, chunk_hi = at the skeleton levels (default:
  * twice chunk: a skeleton level is short, and a longer work item there
  * saves whole levels), lds_depth = operand-stack entries kept in LDS
- * per wave by the general interpreter (64 or 128).  flags:
+ * per wave by the general interpreter (64 or 128).  flags (each call
+ * replaces the previous ones; 0 is the default behaviour):
  * EV_TUNE_NO_REGSTACK runs every work item on the general interpreter
  * instead of the register-stack one.  EV_TUNE_NO_RECORD makes the plan
  * builder emit codes by a second pass of the structure machine instead of
