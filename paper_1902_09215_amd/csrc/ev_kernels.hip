@@ -1356,15 +1356,25 @@ __global__ __launch_bounds__(64) void k_subtree_end(const uint8_t* __restrict__ 
             const uint32_t word = i >= 8 ? (i >= 12 ? v.w : v.z) : (i >= 4 ? v.y : v.x);
             return (word >> (8 * (i & 3))) & 255u;
         };
-        int32_t c = 0;
+        // the lane's net count and its lowest running value
+        int32_t c = 0, cmin = 0;
 #pragma unroll
-        for (int j = 0; j < 64; j++) c += addr + j >= a ? (tok_at(j) < TOK_X ? 1 : -1) : 0;
+        for (int j = 0; j < 64; j++) {
+            c += addr + j >= a ? (tok_at(j) < TOK_X ? 1 : -1) : 0;
+            cmin = c < cmin ? c : cmin;
+        }
         int32_t pre = c;
         for (int d = 1; d < 64; d <<= 1) {
             const int32_t o = __shfl_up(pre, d, 64);
             if ((int)lane >= d) pre += o;
         }
         const int32_t before = pre - c;
+        // no lane whose running count reaches zero: the end is further on
+        if (!__ballot(open + before + cmin <= 0)) {
+            open += __shfl(pre, 63, 64);
+            w += 4096;
+            continue;
+        }
         int32_t hit = -1, cc = 0;
 #pragma unroll
         for (int j = 0; j < 64; j++) {
