@@ -195,8 +195,9 @@ def calibrate_copy():
 
 
 def kernel_hash():
-    """Hash of what the level-0 k_run launch runs: the interpreter generator
-    and the kernel's own source text."""
+    """Hash of what the level-0 k_run launch runs: the interpreter generator,
+    the kernel's own source text and the default work-item size (which sets
+    the launch's items)."""
     import hashlib
 
     h = hashlib.sha256()
@@ -205,6 +206,8 @@ def kernel_hash():
     src = open(os.path.join(ROOT, "paper_1902_09215_amd/csrc/ev_kernels.hip")).read()
     i = src.index("void k_run(RunArgs a)")
     h.update(src[i:src.index("\n}\n", i)].encode())
+    hdr = open(os.path.join(ROOT, "paper_1902_09215_amd/csrc/ev_runtime.h")).read()
+    h.update("".join(l for l in hdr.splitlines() if "uint32_t chunk = " in l).encode())
     return h.hexdigest()[:16]
 
 

@@ -130,7 +130,7 @@ struct ev_ctx {
     bool test_fail_check = false;  // EV_TUNE_TEST_FAIL_CHECK
     bool use_record = true;        // the count pass records codes for emission (EV_TUNE_NO_RECORD clears it)
     uint32_t* d_flag = nullptr;  // the probe's flag word
-    uint32_t chunk = 4096;     // tokens per work item at level 0
+    uint32_t chunk = 6144;     // tokens per work item at level 0
     uint32_t chunk_hi = 0;     // at the skeleton levels (0: twice chunk)
     int lds_depth = 64;
 

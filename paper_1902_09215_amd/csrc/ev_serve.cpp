@@ -62,10 +62,11 @@ struct Serve {
 
 // Device bytes a job may hold at its peak: the trees, one byte per node per
 // split level (skeletons shrink fast), per-case values of every tree and
-// intermediate slots (a few hundred per 4096-token chunk).
+// intermediate slots (a few hundred per 4096 tokens, whatever the work-item
+// size).
 static uint64_t footprint(uint64_t nodes, uint64_t trees, int32_t N, uint32_t chunk)
 {
-    const uint64_t chunks = nodes / chunk + trees;
+    const uint64_t chunks = nodes / (chunk < 4096u ? chunk : 4096u) + trees;
     return 2 * nodes + 1024 + trees * (64 + 8ull * N) + chunks * (96 + 256ull * 4 * N);
 }
 
