@@ -426,12 +426,21 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         // in the totals' extra record.
         const uint64_t rk_bytes = 8 * cur_len + 64 * (uint64_t)n_seg + 64;
         const uint64_t rf_bytes = 3 * cur_len + 16 * (uint64_t)n_seg + 64;
-        const bool record = c->use_record && rk_bytes + rf_bytes <= RECORD_MAX;
+        bool record = c->use_record && rk_bytes + rf_bytes <= RECORD_MAX;
         uint32_t* d_ovf = &((TreeSum*)d_sum)[nt].bad;
         if (record && ((st = realloc(&d_rk, rk_bytes)) || (st = realloc(&d_rf, rf_bytes)) ||
                        (st = realloc(&d_rec, (uint64_t)n_seg * sizeof(SegRec))))) {
-            cleanup();
-            return st;
+            if (st != EV_ENOMEM) {
+                cleanup();
+                return st;
+            }
+            // no room to record: count, then emit
+            for (void** p : {&d_rk, &d_rf, &d_rec}) {
+                dev_free(c, *p);
+                *p = nullptr;
+            }
+            record = false;
+            st = EV_OK;
         }
         HIPCHK(launch_fill_u32((uint32_t*)((TreeSum*)d_sum + nt), sizeof(TreeSum) / 4, 0u, s));
         HIPCHK(launch_seg_count(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (SegCount*)d_cnt,
