@@ -1407,6 +1407,21 @@ __device__ __forceinline__ uint8_t child_byte(const uint8_t* __restrict__ mums, 
     return mums[x.mum_off + x.ep + 1 + (i - b)];
 }
 
+// 16 bytes from p (any alignment): five aligned words, shifted together.  It
+// reads up to 3 bytes before p and after p + 16, inside the buffer (its base
+// is aligned) or its padding.
+__device__ __forceinline__ u32x4 load16_at(const uint8_t* __restrict__ p)
+{
+    const uint64_t addr = (uint64_t)(uintptr_t)p;
+    const uint32_t* q = reinterpret_cast<const uint32_t*>(addr & ~(uint64_t)3);
+    const uint32_t sh = (uint32_t)(addr & 3u) * 8u;
+    const uint32_t r0 = q[0], r1 = q[1], r2 = q[2], r3 = q[3];
+    if (!sh) return u32x4{r0, r1, r2, r3};
+    const uint32_t r4 = q[4];
+    return u32x4{(r0 >> sh) | (r1 << (32u - sh)), (r1 >> sh) | (r2 << (32u - sh)), (r2 >> sh) | (r3 << (32u - sh)),
+                 (r3 >> sh) | (r4 << (32u - sh))};
+}
+
 __global__ void k_xo_copy(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
                           const XoPlan* __restrict__ plan, const uint64_t* __restrict__ off, uint32_t n_children,
                           uint8_t* __restrict__ dst, uint8_t* __restrict__ pad, uint32_t pad_len)
@@ -1421,21 +1436,33 @@ __global__ void k_xo_copy(const uint8_t* __restrict__ mums, const uint8_t* __res
     if (lo >= x.child_len) return;
     const uint64_t hi = lo + 4096u < x.child_len ? lo + 4096u : x.child_len;
     const uint64_t a = x.p, b = x.p + (x.eq - x.q + 1);
-    // output words [w0, w1) lie wholly inside this child's bytes [lo, hi)
+    // output 16-byte words [w0, w1) lie wholly inside this child's bytes [lo, hi)
     const uint64_t o0 = x.child_off + lo, o1 = x.child_off + hi;
-    const uint64_t w0 = (o0 + 3) & ~(uint64_t)3, w1 = o1 & ~(uint64_t)3;
+    const uint64_t w0 = (o0 + 15) & ~(uint64_t)15, w1 = o1 & ~(uint64_t)15;
     if (w0 >= w1) {
         for (uint64_t o = o0 + threadIdx.x; o < o1; o += blockDim.x)
             dst[o] = child_byte(mums, dads, x, o - x.child_off, a, b);
         return;
     }
-    for (uint64_t w = w0 + 4u * threadIdx.x; w < w1; w += 4u * blockDim.x) {
-        const uint64_t i = w - x.child_off;
-        const uint32_t v = (uint32_t)child_byte(mums, dads, x, i, a, b) |
-                           ((uint32_t)child_byte(mums, dads, x, i + 1, a, b) << 8) |
-                           ((uint32_t)child_byte(mums, dads, x, i + 2, a, b) << 16) |
-                           ((uint32_t)child_byte(mums, dads, x, i + 3, a, b) << 24);
-        *reinterpret_cast<uint32_t*>(dst + w) = v;
+    for (uint64_t w = w0 + 16u * threadIdx.x; w < w1; w += 16u * blockDim.x) {
+        const uint64_t i = w - x.child_off;  // the word's first byte in the child
+        u32x4 v;
+        if (x.copy_mum || i + 15 < a) {
+            v = load16_at(mums + x.mum_off + i);
+        } else if (i >= a && i + 15 < b) {
+            v = load16_at(dads + x.dad_off + x.q + (i - a));
+        } else if (i >= b) {
+            v = load16_at(mums + x.mum_off + x.ep + 1 + (i - b));
+        } else {  // the word spans a cut: byte by byte
+            uint32_t r[4];
+            for (int k = 0; k < 4; k++)
+                r[k] = (uint32_t)child_byte(mums, dads, x, i + 4 * k, a, b) |
+                       ((uint32_t)child_byte(mums, dads, x, i + 4 * k + 1, a, b) << 8) |
+                       ((uint32_t)child_byte(mums, dads, x, i + 4 * k + 2, a, b) << 16) |
+                       ((uint32_t)child_byte(mums, dads, x, i + 4 * k + 3, a, b) << 24);
+            v = u32x4{r[0], r[1], r[2], r[3]};
+        }
+        *reinterpret_cast<u32x4*>(dst + w) = v;
     }
     const uint32_t t = threadIdx.x;
     if (t < w0 - o0) dst[o0 + t] = child_byte(mums, dads, x, o0 + t - x.child_off, a, b);
