@@ -1426,14 +1426,23 @@ __global__ void k_xo_copy(const uint8_t* __restrict__ mums, const uint8_t* __res
                           const XoPlan* __restrict__ plan, const uint64_t* __restrict__ off, uint32_t n_children,
                           uint8_t* __restrict__ dst, uint8_t* __restrict__ pad, uint32_t pad_len)
 {
-    if (blockIdx.x == 0 && blockIdx.y == 0)  // the buffer's padding of 0xFF after the children
+    if (blockIdx.x == 0)  // the buffer's padding of 0xFF after the children
         for (uint32_t i = threadIdx.x; i < pad_len; i += blockDim.x) pad[i] = 0xFF;
-    const uint32_t j = blockIdx.y;
-    if (j >= n_children) return;
+    // block b copies piece b: the child j with pf[j] <= b < pf[j + 1]
+    const uint64_t* pf = off + n_children + 4;
+    const uint64_t pb = blockIdx.x;
+    uint32_t j = 0, hi_j = n_children;
+    while (hi_j - j > 1) {
+        const uint32_t mid = (j + hi_j) / 2;
+        if (pf[mid] <= pb)
+            j = mid;
+        else
+            hi_j = mid;
+    }
     XoPlan x = plan[j];
     x.child_off = off[j];
-    const uint64_t lo = (uint64_t)blockIdx.x * 4096u;
-    if (lo >= x.child_len) return;
+    const uint64_t lo = (pb - pf[j]) * 4096u;
+    if (pb < pf[j] || lo >= x.child_len) return;
     const uint64_t hi = lo + 4096u < x.child_len ? lo + 4096u : x.child_len;
     const uint64_t a = x.p, b = x.p + (x.eq - x.q + 1);
     // output 16-byte words [w0, w1) lie wholly inside this child's bytes [lo, hi)
@@ -1518,7 +1527,7 @@ __global__ void k_xo_plan(const uint64_t* __restrict__ moff, const uint64_t* __r
 // off[n + 2] the longest child.
 __global__ __launch_bounds__(1024) void k_xo_offsets(uint64_t* __restrict__ off, uint32_t n)
 {
-    __shared__ uint64_t part[1024];
+    __shared__ uint64_t part[1024], partp[1024];
     __shared__ unsigned long long s_max;
     __shared__ uint32_t s_capped;
     const uint32_t t = threadIdx.x;
@@ -1528,31 +1537,41 @@ __global__ __launch_bounds__(1024) void k_xo_offsets(uint64_t* __restrict__ off,
     }
     const uint32_t per = (n + 1023u) / 1024u;
     const uint32_t j0 = t * per < n ? t * per : n, j1 = j0 + per < n ? j0 + per : n;
-    uint64_t mine = 0, mx = 0;
+    uint64_t mine = 0, minep = 0, mx = 0;
     uint32_t capped = 0;
     for (uint32_t j = j0; j < j1; j++) {
         const uint64_t v = off[j], l = v & ~(1ull << 63);
         mine += l;
+        minep += (l + 4095) / 4096;  // the child's 4 KiB copy pieces
         mx = l > mx ? l : mx;
         capped += (uint32_t)(v >> 63);
     }
     part[t] = mine;
+    partp[t] = minep;
     __syncthreads();
     atomicMax(&s_max, (unsigned long long)mx);
     atomicAdd(&s_capped, capped);
     for (uint32_t d = 1; d < 1024; d <<= 1) {
-        const uint64_t v = t >= d ? part[t - d] : 0;
+        const uint64_t v = t >= d ? part[t - d] : 0, vp = t >= d ? partp[t - d] : 0;
         __syncthreads();
         part[t] += v;
+        partp[t] += vp;
         __syncthreads();
     }
-    uint64_t at = part[t] - mine;
+    uint64_t at = part[t] - mine, atp = partp[t] - minep;
+    uint64_t* pf = off + n + 4;  // first copy piece of each child
     for (uint32_t j = j0; j < j1; j++) {
         const uint64_t l = off[j] & ~(1ull << 63);
         off[j] = at;
+        pf[j] = atp;
         at += l;
+        atp += (l + 4095) / 4096;
     }
-    if (t == 1023) off[n] = part[1023];
+    if (t == 1023) {
+        off[n] = part[1023];
+        pf[n] = partp[1023];
+        off[n + 3] = partp[1023];
+    }
     if (t == 0) {
         off[n + 1] = s_capped;
         off[n + 2] = s_max;
@@ -1857,11 +1876,11 @@ hipError_t launch_subtree_end(const uint8_t* buf, const uint64_t* base, const ui
 }
 
 hipError_t launch_xo_copy(const uint8_t* mums, const uint8_t* dads, const XoPlan* plan, const uint64_t* off,
-                          uint32_t n, uint64_t max_child, uint8_t* dst, uint8_t* pad, uint32_t pad_len, hipStream_t s)
+                          uint32_t n, uint64_t pieces, uint8_t* dst, uint8_t* pad, uint32_t pad_len, hipStream_t s)
 {
-    if (n == 0 || max_child == 0) return hipMemsetAsync(pad, 0xFF, pad_len, s);
-    hipLaunchKernelGGL(k_xo_copy, dim3(cdiv(max_child, 4096), n), dim3(256), 0, s, mums, dads, plan, off, n, dst, pad,
-                       pad_len);
+    if (n == 0 || pieces == 0) return hipMemsetAsync(pad, 0xFF, pad_len, s);
+    if (pieces > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_xo_copy, dim3((uint32_t)pieces), dim3(256), 0, s, mums, dads, plan, off, n, dst, pad, pad_len);
     return hipGetLastError();
 }
 

@@ -52,7 +52,7 @@ hipError_t launch_fitness(const FitArgs& a, hipStream_t s);
 hipError_t launch_subtree_end(const uint8_t* buf, const uint64_t* base, const uint64_t* pos, uint32_t n,
                               uint64_t* end_out, hipStream_t s);
 hipError_t launch_xo_copy(const uint8_t* mums, const uint8_t* dads, const XoPlan* plan, const uint64_t* off,
-                          uint32_t n, uint64_t max_child, uint8_t* dst, uint8_t* pad, uint32_t pad_len, hipStream_t s);
+                          uint32_t n, uint64_t pieces, uint8_t* dst, uint8_t* pad, uint32_t pad_len, hipStream_t s);
 hipError_t launch_xo_query(const uint64_t* moff, const uint64_t* doff, const int32_t* mum, const int32_t* dad,
                            const uint64_t* p, const uint64_t* q, uint32_t n, uint64_t* qb, uint64_t* qp, hipStream_t s);
 hipError_t launch_xo_plan(const uint64_t* moff, const uint64_t* doff, const int32_t* mum, const int32_t* dad,

@@ -1010,13 +1010,14 @@ ev_status crossover_build_dev(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const in
     ev_status st;
     if ((st = dev_alloc(c, qn * 8, &d_b)) || (st = dev_alloc(c, qn * 8, &d_qp)) || (st = dev_alloc(c, qn * 8, &d_e)) ||
         (st = dev_alloc(c, std::max<size_t>(1, n) * sizeof(XoPlan), &d_plan)) ||
-        (st = dev_alloc(c, ((size_t)n + 3) * 8, (void**)&d_off))) {
+        (st = dev_alloc(c, (2 * (size_t)n + 5) * 8, (void**)&d_off))) {
         cleanup();
         dev_free(c, d_off);
         return st;
     }
-    // the offsets, then the number capped and the longest child
-    std::vector<uint64_t> off((size_t)n + 3, 0);
+    // the offsets, then the number capped, the longest child and the number
+    // of 4 KiB copy pieces (each child's first piece follows on the device)
+    std::vector<uint64_t> off((size_t)n + 4, 0);
     if (n > 0) {
         uint64_t* qb = (uint64_t*)d_b;
         uint64_t* qp = (uint64_t*)d_qp;
@@ -1030,7 +1031,7 @@ ev_status crossover_build_dev(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const in
         }
         HIPCHK(launch_xo_plan(mums->d_off, dads->d_off, d_mum, d_dad, d_p, d_q, ends, (uint32_t)n, cap, (XoPlan*)d_plan,
                               d_off, s));
-        if ((st = get(x, off.data(), d_off, ((size_t)n + 3) * 8)) || (st = sync(x))) {
+        if ((st = get(x, off.data(), d_off, ((size_t)n + 4) * 8)) || (st = sync(x))) {
             cleanup();
             dev_free(c, d_off);
             return st;
@@ -1046,9 +1047,9 @@ ev_status crossover_build_dev(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const in
         dev_free(c, d_off);
         return st;
     }
-    const uint64_t capped = off[n + 1], longest = off[n + 2];
+    const uint64_t capped = off[n + 1], pieces = off[n + 3];
     off.resize((size_t)n + 1);
-    HIPCHK(launch_xo_copy(mums->d_bytes, dads->d_bytes, (XoPlan*)d_plan, d_off, (uint32_t)n, longest, d_child,
+    HIPCHK(launch_xo_copy(mums->d_bytes, dads->d_bytes, (XoPlan*)d_plan, d_off, (uint32_t)n, pieces, d_child,
                           d_child + off[n], (uint32_t)EV_POP_PAD, s));
     // the scratch goes back to the cache while the copy may still run: every
     // later use of it is ordered after the copy on the context's one stream
