@@ -164,7 +164,12 @@ ev_status ev_crossover(ev_ctx *ctx, ev_pop mums_pop, ev_pop dads_pop, const int3
  *   ((r+1) << 8) | (c/4), mapped to [0, M) by (w * M) >> 32; the points use
  *   purpose 0x300, p from (w1:w0) and q from (w3:w2), each mapped to
  *   [0, n) by the high 64 bits of the 128-bit product; better = lower MAE,
- *   NaN worst, ties keep the earlier candidate. */
+ *   NaN worst, ties keep the earlier candidate.
+ * The children are planned without waiting for the validation of their last
+ * plan level: their interpreter launches check its result on the device and
+ * run none of that level's codes if it failed, and their first
+ * ev_eval_fitness reads it and then fails with EV_EDEVICE (an internal
+ * fault: the plan builder emitted a stream it should not have). */
 ev_status ev_generation(ev_ctx *ctx, ev_pop parents, const float *fitness, uint64_t seed, uint64_t gen,
                         int32_t tournament, uint64_t size_cap, ev_pop *out_children, int32_t *n_capped);
 
