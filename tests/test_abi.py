@@ -38,3 +38,41 @@ def test_library_loads_and_binding_matches_header():
     for n in declared():
         assert hasattr(lib, n)
     assert sorted(ev.EXPORTS) == declared()
+
+
+def header_constants():
+    """Every EV_ constant the header defines, by #define or in an enum."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    vals = {}
+    for name, v in re.findall(r"#define\s+(EV_[A-Z0-9_]+)\s+(0x[0-9a-fA-F]+|\d+)u?\b", src):
+        vals[name] = int(v, 0)
+    for body in re.findall(r"enum\s*\{(.*?)\}", src, flags=re.S):
+        for name, v in re.findall(r"(EV_[A-Z0-9_]+)\s*=\s*(-?\d+)", body):
+            vals[name] = int(v)
+    return vals
+
+
+def test_binding_constants_match_header():
+    # the binding restates the header's flags, status codes, opcodes and job
+    # kinds for Python callers: they must agree (no library needed)
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location(
+        "ev_binding_consts", os.path.join(ROOT, "paper_1902_09215_amd", "__init__.py"))
+    src = open(spec.origin).read()
+    vals = header_constants()
+    assert len(vals) >= 20
+    bound = {}
+    for line in src.splitlines():
+        m = re.match(r"^((?:EV_[A-Z0-9_]+\s*,\s*)*EV_[A-Z0-9_]+)\s*=\s*(.+)$", line)
+        if not m:
+            continue
+        names = [n.strip() for n in m.group(1).split(",")]
+        exprs = [e.strip() for e in m.group(2).split(",")]
+        if len(names) == len(exprs):
+            for n, e in zip(names, exprs):
+                bound[n] = int(e, 0)
+    missing = sorted(n for n in vals if n != "EV_H" and n not in bound)
+    assert not missing, f"constants the binding does not define: {missing}"
+    wrong = sorted(n for n in bound if n in vals and bound[n] != vals[n])
+    assert not wrong, f"constants that disagree with the header: {wrong}"
