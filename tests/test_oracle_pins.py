@@ -406,3 +406,65 @@ def test_fitness_divides_once_by_n():
         differs += int(want != np.float32(v) * (np.float32(1) / np.float32(48)))
         assert oracle.fitness(out, y) == want
     assert differs > 0
+
+
+def test_population_rows_match_per_tree_evaluation():
+    # Each row t of the population result is tree t's own evaluation: its
+    # per-case values against the recursive evaluator above, its fitness
+    # against a plain ascending binary32 sum of |out - y| divided by N.
+    x, y = workloads.cases(48)
+    rng = np.random.default_rng(31)
+    trees = [np.array([X], np.uint8)]  # a single leaf first
+    for n in list(rng.integers(0, 40, 20) * 2 + 1) + [1, 3, 255]:
+        sizes = np.array([n], np.uint64)
+        b, _ = workloads.random_population(int(rng.integers(1 << 30)), sizes)
+        trees.append(b)
+    trees.append(np.array([X], np.uint8))  # and a single leaf last
+    off = np.zeros(len(trees) + 1, np.uint64)
+    off[1:] = np.cumsum([t.size for t in trees])
+    buf = np.concatenate(trees)
+    for threads in (1, 5):
+        fit, pc = oracle.eval_population(buf, off, x, y, threads=threads, per_case=True)
+        assert pc.shape == (len(trees), 48)
+        for t, tree in enumerate(trees):
+            want = ref_eval(tree, x)
+            assert same_bits(pc[t], want).all(), t
+            s = np.float32(0)
+            for i in range(48):
+                s = np.float32(s + np.float32(abs(np.float32(want[i] - y[i]))))
+            assert same_bits(fit[t], np.float32(s / np.float32(48))), t
+
+
+def tournament_by_hand(fit, M, k, seed, gen, child, role):
+    # Candidate c of a tournament is word c % 4 of the Philox block with
+    # counter (child, ((role + 1) << 8) | c // 4, gen lo, gen hi) under key
+    # (seed lo, seed hi), mapped to [0, M) by a 32x32 multiply-high; the
+    # first-drawn candidate among those of least fitness wins.
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    cands = []
+    for c in range(k):
+        w = oracle.philox4x32_10([child, ((role + 1) << 8) | (c // 4), gen & 0xFFFFFFFF, gen >> 32], key)
+        cands.append((int(w[c % 4]) * M) >> 32)
+    best = min(float(fit[c]) for c in cands)
+    return next(c for c in cands if float(fit[c]) == best), cands
+
+
+@pytest.mark.parametrize("k", [2, 7])
+def test_tournament_ties_keep_the_earlier_draw(k):
+    M = 16
+    sizes = np.full(M, 9, np.uint64)
+    rng = np.random.default_rng(k)
+    all_equal = np.full(M, 0.25, np.float32)
+    # two fitness levels only, so most tournaments hold several tied best
+    partly = np.where(rng.random(M) < 0.5, 0.5, 0.75).astype(np.float32)
+    seen_tie = 0
+    for fit in (all_equal, partly):
+        for child in range(200):
+            m, d, _, _ = oracle.choose(fit, k, 0xABCDEF12345, 9, child, sizes)
+            for role, got in ((0, m), (1, d)):
+                want, cands = tournament_by_hand(fit, M, k, 0xABCDEF12345, 9, child, role)
+                best = min(float(fit[c]) for c in cands)
+                tied = {c for c in cands if float(fit[c]) == best}
+                seen_tie += len(tied) > 1
+                assert got == want, (k, child, role, cands)
+    assert seen_tie > 100  # the rule was exercised, not a unique best
