@@ -1,19 +1,21 @@
 """Benchmark: GP operations per second (tree nodes x fitness cases / s) on one MI355X.
 
-Default workload: 4000 uniformly random trees with node counts log-uniform in
-[10, 1e5] (about 4.3e7 nodes), 48 fitness cases in [-1, 1].  One step is one
-generation of the method's hot path on that population: size-2 tournament
-selection and Philox-drawn crossover points, subtree crossover, the structure
-scan and split of the children, their evaluation on every case and their
-fitness.  Every step starts from the same resident parents, so the work per
-step is stationary.  value = sum over steps of child nodes x cases / timed
-wall time.
+Default workload: the giant population, 48 uniformly random trees of 4e8
+nodes each (1.92e10 nodes, 19.2 GB of one-byte opcodes), 48 fitness cases in
+[-1, 1].  One step is one generation of the method's hot path on that
+population: size-2 tournament selection and Philox-drawn crossover points,
+subtree crossover, the structure scan and split of the children, their
+evaluation on every case and their fitness.  Every step starts from the same
+resident parents, so the work per step is stationary.  value = sum over steps
+of child nodes x cases / timed wall time.
 
 Also reported: evaluation alone on the resident parents (device time and
-p50/p99 latency per call), the dominant kernel (level-0 interpreter) against
-the FP32 VALU roofline, and the C oracle timed on the host cores.
+p50/p99 latency per call), the plain form (one tree per launch, timed the
+same way), the dominant kernel (the level-0 interpreter launch) against the
+FP32 vector ALU peak, and the C oracle timed on the host cores.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|tiny|giant]
+  python bench.py [--gpus 1] [--steps K] [--warmup W]
+                  [--workload giant_max|giant|batched|tiny|serving]
 """
 from __future__ import annotations
 
@@ -28,8 +30,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_GPOPS = 256 * 64 * 2 * 2.4e9  # one FP32 op per lane, two per packed issue, 2.4 GHz
+# FP32 vector peak of the MI355X: 256 CUs x 64 lanes x 2.4 GHz, an FMA
+# counted as two operations and packed FP32 as two lanes per issue
+PEAK_FP32 = 157.3e12
+# one plain (non-FMA, unpacked) FP32 operation per lane per cycle
 PEAK_UNPACKED = 256 * 64 * 2.4e9
+WORKLOAD_NAMES = {"batched": "batched uneven population: 4000 random trees, log-uniform 10..1e5 nodes",
+                  "tiny": "100 ramped half-and-half trees, depth 2-6",
+                  "giant": "48 random trees, log-uniform 1e6..4e8 nodes",
+                  "giant_max": "giant population: 48 random trees of 4e8 nodes (19.2 GB of opcodes)"}
 
 
 def pct(a, q):
@@ -42,7 +51,7 @@ def cpu_baseline(buf, off, x, y, fit, n_cases, budget_s=12.0):
     populations too large for that, the evaluation of the smallest trees."""
     import oracle
 
-    threads = min(os.cpu_count() or 1, 64)
+    threads = min(len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count() or 1, 64)
     if int(off[-1]) > 2e8:
         sizes = np.diff(off)
         order = np.argsort(sizes)
@@ -54,7 +63,9 @@ def cpu_baseline(buf, off, x, y, fit, n_cases, budget_s=12.0):
         oracle.eval_population(np.concatenate(parts), soff, x, y, threads=threads)
         el = time.perf_counter() - t0
         return {"value": int(soff[-1]) * n_cases / el, "unit": "GPops/s", "cores": threads, "kind": "oracle",
-                "sample": f"oracle evaluation of the {len(take)} smallest trees ({int(soff[-1])} nodes), {el:.1f} s"}
+                "cpu_model": cpu_model(),
+                "sample": f"oracle evaluation (no selection or crossover) of the {len(take)} smallest trees "
+                          f"({int(soff[-1])} nodes), one tree per thread, {el:.1f} s"}
     done_nodes, t0, gens = 0, time.perf_counter(), 0
     while True:
         cbuf, coff, _ = oracle.generation(buf, off, fit, 2, 1234, 10_000 + gens, 15_000_000)
@@ -65,8 +76,19 @@ def cpu_baseline(buf, off, x, y, fit, n_cases, budget_s=12.0):
         if el >= budget_s or gens >= 50:
             break
     return {"value": done_nodes * n_cases / el, "unit": "GPops/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{gens} oracle generations of the {off.size - 1}-tree population "
                       f"(selection+crossover single-threaded, evaluation on {threads} threads), {el:.1f} s"}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def serve_bench(args, ev, workloads):
@@ -234,14 +256,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batched")
-    ap.add_argument("--eval-reps", type=int, default=50)
+    ap.add_argument("--workload", default="giant_max")
+    ap.add_argument("--eval-reps", type=int, default=20)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--lds", type=int, default=0)
     ap.add_argument("--chunk-hi", type=int, default=0, help="work-item size of the skeleton levels")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--plain-trees", type=int, default=300)
-    ap.add_argument("--cap", type=int, default=15_000_000, help="child size cap of the generation step")
+    ap.add_argument("--plain-trees", type=int, default=-1,
+                    help="trees evaluated one per launch (default: all 48 of a giant population, else 300)")
+    ap.add_argument("--cap", type=int, default=-1,
+                    help="child size cap of the generation step (default: 15e6 nodes, none for the giant "
+                         "populations)")
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
     ap.add_argument("--load", type=float, default=0.8, help="serving: offered load as a fraction of capacity")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -260,9 +285,12 @@ def main():
 
     if args.workload == "serving":
         return serve_bench(args, ev, workloads)
+    giant = args.workload.startswith("giant")
+    cap = args.cap if args.cap >= 0 else (2**62 if giant else 15_000_000)
     buf, off, n_cases = workloads.workload(args.workload)
     x, y = workloads.cases(n_cases)
     M = off.size - 1
+    print(f"# {args.workload}: {M} trees, {int(off[-1])} nodes", file=sys.stderr, flush=True)
     c = ev.Context(x, y, device=0)
     if args.chunk or args.lds or args.chunk_hi:
         ev.ev_set_tuning(c.ctx, args.chunk, args.lds, 0, args.chunk_hi)
@@ -270,10 +298,12 @@ def main():
     parents = c.load(buf, off)
     t_load = time.perf_counter() - t_load
     plan = ev.ev_get_plan_info(c.ctx, parents)
+    levels = [ev.ev_get_level_info(c.ctx, parents, i) for i in range(plan["levels"])]
+    funcs = ev.level_functions(c.ctx, parents)
     fit, _ = c.eval(parents)
 
     # ---- evaluation alone on the resident parents
-    dev_ms, int_ms, lat = [], [], []
+    dev_ms, int_ms, lat, lvl_ms = [], [], [], []
     for r in range(args.warmup + args.eval_reps):
         t0 = time.perf_counter()
         ev.ev_eval_fitness(c.ctx, parents)
@@ -283,49 +313,59 @@ def main():
             lat.append((t1 - t0) * 1e3)
             dev_ms.append(a)
             int_ms.append(b)
+            lvl_ms.append(ev.ev_last_level_times(c.ctx))
+    print(f"# evaluation: {np.median(dev_ms):.3f} ms device", file=sys.stderr, flush=True)
     nodes = int(off[-1])
     eval_gpops = nodes * n_cases / (np.median(dev_ms) * 1e-3)
     interp_ms = float(np.mean(int_ms))
-    interp_gpops = nodes * n_cases / (interp_ms * 1e-3)
+    # the dominant kernel: the level-0 interpreter launch.  Its algorithmic
+    # work is one FP32 operation per function node it evaluates, per case
+    # (leaves are loads, not arithmetic); the functions that span a work-item
+    # boundary run in later launches and are not counted here.
+    flops0 = funcs[0] * n_cases
+    achieved = flops0 / (interp_ms * 1e-3)
 
     # ---- generation steps (the whole hot path)
     seed = 0x5EED
     for w in range(args.warmup):
-        kids, _ = ev.ev_generation(c.ctx, parents, seed, 1_000_000 + w, 2, args.cap)
+        kids, _ = ev.ev_generation(c.ctx, parents, seed, 1_000_000 + w, 2, cap)
         ev.ev_eval_fitness(c.ctx, kids)
         ev.ev_free_pop(c.ctx, kids)
     step_ms, child_nodes = [], 0
-    t_all = time.perf_counter()
     for s in range(args.steps):
         t0 = time.perf_counter()
-        kids, _ = ev.ev_generation(c.ctx, parents, seed, s, 2, args.cap)
+        kids, _ = ev.ev_generation(c.ctx, parents, seed, s, 2, cap)
         ev.ev_eval_fitness(c.ctx, kids)
         t1 = time.perf_counter()
         child_nodes += ev.ev_pop_info(c.ctx, kids)[1]
         ev.ev_free_pop(c.ctx, kids)
         step_ms.append((t1 - t0) * 1e3)
-    total_s = time.perf_counter() - t_all
     value = child_nodes * n_cases / sum(step_ms) * 1e3
+    print(f"# generation step: {np.mean(step_ms):.3f} ms", file=sys.stderr, flush=True)
 
-    # ---- the plain form: one tree per launch (its own population and call)
+    # ---- the plain form: one tree per launch (its own population and call),
+    # timed like the batched evaluation, by HIP events around the call's kernels
     plain = None
-    if args.workload in ("batched", "tiny"):
+    n_plain = args.plain_trees if args.plain_trees >= 0 else (M if giant else 300)
+    if n_plain > 0 and args.workload in ("batched", "tiny", "giant", "giant_max"):
         rng = np.random.default_rng(7)
-        pick = np.sort(rng.choice(M, size=min(M, args.plain_trees), replace=False))
+        pick = np.sort(rng.choice(M, size=min(M, n_plain), replace=False))
         t_plain, nodes_plain, same = 0.0, 0, True
         for t in pick:
             tb = np.ascontiguousarray(buf[off[t]:off[t + 1]])
             p1 = c.load(tb, np.array([0, tb.size], np.uint64))
             f1, _ = c.eval(p1)  # first call builds device caches
-            t0 = time.perf_counter()
             f1, _ = c.eval(p1)
-            t_plain += time.perf_counter() - t0
+            t_plain += ev.ev_last_timing(c.ctx)[0] * 1e-3
             nodes_plain += tb.size
             same &= f1.view(np.uint32)[0] == fit.view(np.uint32)[t] or (np.isnan(f1[0]) and np.isnan(fit[t]))
             ev.ev_free_pop(c.ctx, p1)
-        plain = {"gpops_per_s": nodes_plain * n_cases / t_plain, "trees": int(pick.size),
+        plain_gpops = nodes_plain * n_cases / t_plain
+        plain = {"gpops_per_s": plain_gpops, "trees": int(pick.size),
                  "ms_per_tree": t_plain / pick.size * 1e3, "bitexact_vs_batched": bool(same),
-                 "batched_speedup": eval_gpops / (nodes_plain * n_cases / t_plain)}
+                 "timing": "device time (HIP events) of each single-tree ev_eval_fitness, as for the batched figure",
+                 "batched_speedup": eval_gpops / plain_gpops}
+        print(f"# plain form: {plain_gpops:.3e} GPops/s", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu:
@@ -345,40 +385,40 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": {"batched": "batched uneven population: 4000 random trees, log-uniform 10..1e5 nodes",
-                         "tiny": "100 ramped half-and-half trees, depth 2-6",
-                         "giant": "48 random trees, log-uniform 1e6..4e8 nodes",
-                         "giant_max": "48 random trees of 4e8 nodes"}.get(args.workload, args.workload),
+            "workload": WORKLOAD_NAMES.get(args.workload, args.workload),
             "trees": M, "nodes": nodes, "fitness_cases": n_cases,
             "step": "generation: tournament(2) + Philox points + subtree crossover + scan/split + eval + fitness",
-            "chunk": plan and ev.ev_get_plan_info(c.ctx, parents)["levels"] and None,
+            "child_size_cap": cap if cap < 2**62 else None,
         },
         "p50_step_ms": pct(step_ms, 50),
         "p99_step_ms": pct(step_ms, 99),
         "eval": {
             "gpops_per_s": eval_gpops,
             "device_ms_median": float(np.median(dev_ms)),
+            "level_ms_median": [float(v) for v in np.median(np.asarray(lvl_ms), axis=0)] if lvl_ms else None,
             "p50_latency_ms": pct(lat, 50),
             "p99_latency_ms": pct(lat, 99),
             "plan": plan,
+            "levels": levels,
             "load_and_plan_s": t_load,
         },
         "roofline": {
             "kernel": "k_run (level-0 register-stack interpreter launch)",
             "bound": "alu",
-            "achieved": interp_gpops / 1e12,
-            "peak": PEAK_GPOPS / 1e12,
-            "unit": "TGPops/s",
-            "frac": interp_gpops / PEAK_GPOPS,
-            "frac_unpacked": interp_gpops / PEAK_UNPACKED,
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP32 / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32,
+            "frac_of_unpacked_fp32": achieved / PEAK_UNPACKED,
             "avg_launch_ms": interp_ms,
-            "work_per_launch": f"{nodes} level-0 tokens x {n_cases} cases",
+            "work_per_launch": f"{funcs[0]} function nodes evaluated by the level-0 launch x {n_cases} cases "
+                               f"(one FP32 operation each)",
+            "gpops_per_s_level0": levels[0]["tokens"] * n_cases / (interp_ms * 1e-3),
             "traffic": measured_traffic(args.workload),
         },
         "plain_one_tree_per_launch": plain,
         "cpu_baseline": cpu,
     }
-    del line["config"]["chunk"]
     print(json.dumps(line), flush=True)
     c.close()
 

@@ -226,6 +226,22 @@ typedef struct {
 
 ev_status ev_get_plan_info(ev_ctx *ctx, ev_pop pop, ev_plan_info *info);
 
+/* One level of the split plan.  Each tree with work at the level is one
+ * prefix tree over the functions and leaves of its sequence there (at the
+ * skeleton levels a leaf stands for a value an earlier level computed), so
+ * the level holds (tokens - trees) / 2 functions, and the functions its own
+ * launch evaluates are those less the next level's. */
+typedef struct {
+    uint64_t tokens;  /* tokens of the level's sequence, over all its trees */
+    uint32_t trees;   /* trees with work at this level */
+    uint32_t items;   /* work items */
+    uint32_t slots;   /* result slots the level writes */
+    uint32_t pad;
+} ev_level_info;
+
+/* Errors: EV_EINVAL (level out of range), EV_ENOTFOUND. */
+ev_status ev_get_level_info(ev_ctx *ctx, ev_pop pop, int32_t level, ev_level_info *info);
+
 /* Tuning knobs (0 keeps the current value): chunk = tokens per work item
  * of the split at level 0, chunk_hi = at the skeleton levels (default:
  * twice chunk: a skeleton level is short, and a longer work item there

@@ -27,7 +27,7 @@ EV_JOB_EVAL, EV_JOB_CROSSOVER = 0, 1
 EXPORTS = [
     "ev_create", "ev_add_cases", "ev_destroy", "ev_last_error", "ev_load_trees", "ev_pop_info",
     "ev_get_trees", "ev_free_pop", "ev_eval_fitness", "ev_crossover", "ev_generation", "ev_submit",
-    "ev_poll", "ev_wait", "ev_result", "ev_job_timing", "ev_get_plan_info", "ev_set_tuning",
+    "ev_poll", "ev_wait", "ev_result", "ev_job_timing", "ev_get_plan_info", "ev_get_level_info", "ev_set_tuning",
     "ev_autotune", "ev_last_level_times", "ev_last_timing",
 ]
 
@@ -41,6 +41,11 @@ class EvError(RuntimeError):
 class ev_plan_info(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("chunks", ctypes.c_uint64), ("slots", ctypes.c_uint64),
                 ("max_stack", ctypes.c_uint64), ("plan_bytes", ctypes.c_uint64)]
+
+
+class ev_level_info(ctypes.Structure):
+    _fields_ = [("tokens", ctypes.c_uint64), ("trees", ctypes.c_uint32), ("items", ctypes.c_uint32),
+                ("slots", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -97,6 +102,7 @@ def load_library(path: str = LIB_PATH):
         "ev_result": [P, u64, P, P, i32, ctypes.POINTER(i32)],
         "ev_job_timing": [P, u64, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)],
         "ev_get_plan_info": [P, i32, ctypes.POINTER(ev_plan_info)],
+        "ev_get_level_info": [P, i32, i32, ctypes.POINTER(ev_level_info)],
         "ev_set_tuning": [P, u32, u32, u32, u32],
         "ev_autotune": [P, i32, i32, i32, ctypes.POINTER(u32), ctypes.POINTER(ctypes.c_float)],
         "ev_last_level_times": [P, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)],
@@ -321,6 +327,19 @@ def ev_get_plan_info(ctx, pop) -> dict:
     info = ev_plan_info()
     _check(_lib.ev_get_plan_info(ctx, pop, ctypes.byref(info)))
     return {k: getattr(info, k) for k, _ in ev_plan_info._fields_}
+
+
+def ev_get_level_info(ctx, pop, level: int) -> dict:
+    info = ev_level_info()
+    _check(_lib.ev_get_level_info(ctx, pop, level, ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in ev_level_info._fields_ if k != "pad"}
+
+
+def level_functions(ctx, pop) -> list:
+    """Function nodes each plan level's launch evaluates (see ev.h)."""
+    lv = [ev_get_level_info(ctx, pop, i) for i in range(ev_get_plan_info(ctx, pop)["levels"])]
+    f = [(v["tokens"] - v["trees"]) // 2 for v in lv] + [0]
+    return [f[i] - f[i + 1] for i in range(len(lv))]
 
 
 EV_TUNE_NO_REGSTACK = 0x1

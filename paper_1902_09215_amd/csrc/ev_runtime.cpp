@@ -497,6 +497,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         L.n_out = (uint32_t)so;
         L.max_m = run_items ? 0 : max_m;
         L.tokens = tokens;
+        L.trees = nt;
         // a stack deeper than the register window spills half-windows to a
         // slab; so does one that reaches the window's upper quarter at a
         // segment boundary, where the window is re-centred
@@ -1427,6 +1428,21 @@ ev_status ev_get_plan_info(ev_ctx* c, ev_pop pop, ev_plan_info* info)
     info->slots = P->plan.slots_total;
     info->max_stack = P->plan.max_stack;
     info->plan_bytes = P->plan.bytes;
+    return EV_OK;
+}
+
+ev_status ev_get_level_info(ev_ctx* c, ev_pop pop, int32_t level, ev_level_info* info)
+{
+    if (!c || !info) return fail(EV_EINVAL, "bad arguments");
+    Pop* P = pop_get(c, pop);
+    if (!P) return fail(EV_ENOTFOUND, "no population %d", pop);
+    if (level < 0 || level >= (int32_t)P->plan.levels.size()) return fail(EV_EINVAL, "no plan level %d", level);
+    const Level& L = P->plan.levels[level];
+    info->tokens = L.tokens;
+    info->trees = L.trees;
+    info->items = L.n_run + L.n_chunks;
+    info->slots = L.n_out;
+    info->pad = 0;
     return EV_OK;
 }
 

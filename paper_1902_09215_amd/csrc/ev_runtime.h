@@ -35,6 +35,7 @@ struct Level {
     RunChunk* d_run = nullptr;      // work items of the register-stack kernel (k_run)
     uint32_t n_run = 0;
     uint64_t tokens = 0;            // tokens over all work items of the level
+    uint32_t trees = 0;             // trees with work at the level
     uint32_t slab_entries = 0;      // spill-slab rows per wave of k_run (0: no spills)
     uint32_t n_out = 0;  // result slots written by this level
     uint32_t max_m = 0;  // deepest physical operand stack of a k_eval item

@@ -334,6 +334,48 @@ def test_generation_with_caller_fitness(ev):
     assert not (np.array_equal(ko, ao) and np.array_equal(kb, ab))
 
 
+def test_device_pointer_load_and_device_outputs(ev):
+    # ev_load_trees with EV_DEVICE_PTR (bytes and offsets in device memory,
+    # here torch tensors) and ev_eval_fitness with EV_OUT_DEVICE (fitness,
+    # per-case values and hits written to device tensors): the same results
+    # as the oracle, and the same as the host-pointer forms.
+    import torch
+
+    x, y = workloads.cases(48)
+    sizes = workloads.loguniform_sizes(45, 300, 1, 30000)
+    buf, off = workloads.random_population(45, sizes)
+    want_fit, want_pc = oracle.eval_population(buf, off, x, y, threads=8, per_case=True)
+    M = off.size - 1
+    with ev.Context(x, y) as c:
+        dbuf = torch.from_numpy(buf).cuda()
+        doff = torch.from_numpy(off.view(np.int64)).cuda()
+        torch.cuda.synchronize()
+        pop = ev.ev_load_trees(c.ctx, dbuf, doff)
+        del dbuf, doff
+        gbuf, goff = ev.ev_get_trees(c.ctx, pop)
+        assert np.array_equal(gbuf, buf) and np.array_equal(goff, off)
+        fit = torch.full((M,), -1.0, dtype=torch.float32, device="cuda")
+        pc = torch.full((M, 48), -1.0, dtype=torch.float32, device="cuda")
+        hits = torch.full((M,), -1, dtype=torch.int32, device="cuda")
+        for _ in range(2):  # the second call reuses the cached result slots
+            ev.ev_eval_fitness(c.ctx, pop, 0, out=fit, out_per_case=pc, out_hits=hits)
+            torch.cuda.synchronize()
+            assert_same(fit.cpu().numpy(), want_fit, "device fitness")
+            assert_same(pc.cpu().numpy(), want_pc, "device per-case")
+            assert np.array_equal(hits.cpu().numpy(), oracle.hits(want_pc, y))
+        hf, hpc = c.eval(pop, per_case=True)
+        assert_same(hf, want_fit, "host fitness")
+        assert_same(hpc, want_pc, "host per-case")
+        # a malformed tree in device memory is refused like a host one
+        bad = buf.copy()
+        bad[int(off[7])] = 9
+        dbad, doff = torch.from_numpy(bad).cuda(), torch.from_numpy(off.view(np.int64)).cuda()
+        torch.cuda.synchronize()
+        with pytest.raises(ev.EvError) as e:
+            ev.ev_load_trees(c.ctx, dbad, doff)
+        assert e.value.code == ev.EV_EMALFORMED and e.value.bad_tree == 7
+
+
 def test_deferred_validation_verdict(ev):
     # The children of ev_generation leave their last plan level's validation
     # verdict to the device and to their first evaluation.  A verdict forced
@@ -564,47 +606,112 @@ def test_serving_crossover_jobs(ev):
     assert_same(fit, wf, "served crossover")
 
 
-def test_giant_population_sampled(ev):
-    # 48 random trees with log-uniform sizes in [1e6, 4e8] (about 3.2e9
-    # nodes), evaluated in the benchmark's launch configuration; the oracle
-    # recomputes a sample of trees (the three smallest, the median and the
-    # largest), each bit for bit.
+def oracle_in_background(buf, off, x, y, threads=None):
+    """Start the oracle's evaluation of a population on every host core in a
+    thread (the C call releases the interpreter lock), so that it overlaps the
+    device work; returns a function that waits for (fitness, per_case)."""
+    import threading
+
+    threads = threads or max(1, len(os.sched_getaffinity(0)))
+    out = {}
+
+    def work():
+        try:
+            out["r"] = oracle.eval_population(buf, off, x, y, threads=threads, per_case=True)
+        except BaseException as e:  # noqa: BLE001 - re-raised in the waiting thread
+            out["e"] = e
+
+    th = threading.Thread(target=work, daemon=True)
+    th.start()
+
+    def wait():
+        th.join()
+        if "e" in out:
+            raise out["e"]
+        return out["r"]
+
+    return wait
+
+
+@pytest.mark.timeout(600)
+def test_giant_population_all_trees(ev):
+    # 48 random trees with log-uniform sizes in [1e6, 4e8] (about 4.4e9
+    # nodes), evaluated in the benchmark's launch configuration; every tree's
+    # per-case values and fitness against the oracle, bit for bit.
     buf, off, n = workloads.workload("giant")
     x, y = workloads.cases(n)
     sizes = np.diff(off)
     print(f"giant: {int(off[-1])} nodes, largest {int(sizes.max())}", flush=True)
+    want = oracle_in_background(buf, off, x, y)
     with ev.Context(x, y) as c:
         pop = c.load(buf, off)
         info = ev.ev_get_plan_info(c.ctx, pop)
-        fit, pc = c.eval(pop, per_case=True)
+        fit, pc, hits = c.eval(pop, per_case=True, hits=True)
     print(f"giant plan {info}", flush=True)
-    order = np.argsort(sizes)
-    sample = sorted(set(order[:3].tolist() + [int(order[len(order) // 2]), int(order[-1])]))
-    parts = [buf[off[t]:off[t + 1]] for t in sample]
-    soff = workloads.offsets_from_sizes([p.size for p in parts])
-    want_fit, want_pc = oracle.eval_population(np.concatenate(parts), soff, x, y, threads=len(sample), per_case=True)
-    assert_same(fit[sample], want_fit, "giant fitness")
-    assert_same(pc[sample], want_pc, "giant per-case")
+    want_fit, want_pc = want()
+    assert_same(pc, want_pc, "giant per-case")
+    assert_same(fit, want_fit, "giant fitness")
+    assert np.array_equal(hits, oracle.hits(want_pc, y))
 
 
-def test_giant_max_population_sampled(ev):
-    # 48 random trees of 4e8 nodes (19.2e9 nodes, the 20 GB population),
-    # evaluated whole in the benchmark's launch configuration; the oracle
-    # recomputes two trees, each bit for bit.
+@pytest.fixture(scope="module")
+def giant_max():
     buf, off, n = workloads.workload("giant_max")
     x, y = workloads.cases(n)
+    return buf, off, x, y
+
+
+@pytest.mark.timeout(900)
+def test_giant_max_population_all_trees(ev, giant_max):
+    # 48 random trees of 4e8 nodes (19.2e9 nodes, the 20 GB population),
+    # evaluated whole in the benchmark's launch configuration; all 48 trees
+    # against the oracle, bit for bit.
+    buf, off, x, y = giant_max
     print(f"giant_max: {int(off[-1])} nodes", flush=True)
+    want = oracle_in_background(buf, off, x, y)
     with ev.Context(x, y) as c:
         pop = c.load(buf, off)
         info = ev.ev_get_plan_info(c.ctx, pop)
         fit, pc = c.eval(pop, per_case=True)
     print(f"giant_max plan {info}", flush=True)
-    sample = [0, 47]
-    parts = [buf[off[t]:off[t + 1]] for t in sample]
-    soff = workloads.offsets_from_sizes([p.size for p in parts])
-    want_fit, want_pc = oracle.eval_population(np.concatenate(parts), soff, x, y, threads=len(sample), per_case=True)
-    assert_same(fit[sample], want_fit, "giant_max fitness")
-    assert_same(pc[sample], want_pc, "giant_max per-case")
+    want_fit, want_pc = want()
+    assert_same(pc, want_pc, "giant_max per-case")
+    assert_same(fit, want_fit, "giant_max fitness")
+
+
+@pytest.mark.timeout(600)
+def test_giant_max_crossover_matches_oracle(ev, giant_max):
+    # Children of 4e8-node parents (64-bit child offsets, multi-GB children,
+    # subtree ends found by scans over long subtrees): the children's bytes
+    # against the oracle's crossover, then their evaluation against the
+    # oracle.  Points include the roots (p = 0: the child is the dad's
+    # subtree; q = 0: the whole dad is inserted) and points with long
+    # subtrees (the first few nodes, whose subtrees span most of the tree).
+    buf, off, x, y = giant_max
+    sizes = np.diff(off).astype(np.int64)
+    rng = np.random.default_rng(2024)
+    mum = np.array([0, 5, 47, 12, 30], np.int32)
+    dad = np.array([47, 5, 1, 33, 30], np.int32)
+    p = np.array([0, 1, int(rng.integers(0, sizes[47])), 2, int(rng.integers(0, sizes[30]))], np.uint64)
+    q = np.array([3, 0, int(rng.integers(0, sizes[1])), 1, 2], np.uint64)
+    want_kids = [oracle.crossover(buf[off[m]:off[m + 1]], buf[off[d]:off[d + 1]], int(pp), int(qq))
+                 for m, d, pp, qq in zip(mum, dad, p, q)]
+    print("giant_max crossover: child sizes", [k.size for k in want_kids], flush=True)
+    koff = workloads.offsets_from_sizes([k.size for k in want_kids])
+    kbuf = np.concatenate(want_kids)
+    want = oracle_in_background(kbuf, koff, x, y)
+    with ev.Context(x, y) as c:
+        pop = c.load(buf, off)
+        kids, capped = ev.ev_crossover(c.ctx, pop, pop, mum, dad, p, q)
+        assert capped == 0
+        got_buf, got_off = ev.ev_get_trees(c.ctx, kids)
+        assert np.array_equal(got_off, koff)
+        assert np.array_equal(got_buf, kbuf)
+        del got_buf
+        fit, pc = c.eval(kids, per_case=True)
+    want_fit, want_pc = want()
+    assert_same(pc, want_pc, "giant_max children per-case")
+    assert_same(fit, want_fit, "giant_max children fitness")
 
 
 def test_single_tree_populations(ev):
