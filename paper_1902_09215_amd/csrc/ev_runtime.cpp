@@ -40,11 +40,12 @@ ev_status hip_fail(hipError_t e, const char* what)
 // size classes and handed out again, so the plan and crossover temporaries
 // of every generation cost no hipMalloc/hipFree (hipFree synchronizes the
 // device).  A block goes back to the cache while work that uses it may
-// still be queued: all of a context's work runs on its one stream, so the
-// block's next user is ordered after it, and hipFree waits for the device.
-// The budget bounds live bytes; when live plus cached bytes would exceed
-// what the device can hold, the cached blocks idle the longest are
-// released first.
+// still be queued on the freeing thread's stream; the cache (ev_cache.h)
+// hands it out again at once on that stream, whose later work is ordered
+// after it, but on another stream only after the freeing stream has been
+// waited for.  The budget bounds live bytes; when live plus cached bytes
+// would exceed what the device can hold, the cached blocks idle the longest
+// are released first.
 // Powers of two up to 256 MiB, then steps of 2^(1/4) (rounded to 2 MiB): a
 // large block serves requests from about 84% of its size up, so the large
 // buffers of successive generations, whose sizes wander by a few percent,
@@ -68,15 +69,32 @@ static size_t size_class(size_t bytes)
     return cls;
 }
 
-// Hand a cached block back: to the caller's allocator, once the context's
-// stream has finished every queued use of it (hipFree waits by itself).
-static void block_free(ev_ctx* c, void* p)
+static thread_local Exec* tl_exec = nullptr;
+
+ExecScope::ExecScope(Exec* x) : prev(tl_exec) { tl_exec = x; }
+ExecScope::~ExecScope() { tl_exec = prev; }
+
+Exec* current_exec(ev_ctx* c) { return tl_exec ? tl_exec : &c->main; }
+
+bool table_get(ev_ctx* c, int32_t table, CaseTable* out)
 {
-    if (c->ext.alloc) {
-        (void)hipStreamSynchronize(c->main.stream);
-        c->ext.free(p, c->ext.user);
-    } else {
-        (void)hipFree(p);
+    std::lock_guard<std::mutex> g(c->pop_mu);
+    if (table < 0 || table >= (int32_t)c->tables.size()) return false;
+    *out = c->tables[(size_t)table];
+    return true;
+}
+
+// Hand cached blocks back: to the caller's allocator once every stream of
+// the device has finished with them (hipFree waits by itself).
+static void blocks_free(ev_ctx* c, const std::vector<std::pair<void*, size_t>>& blocks)
+{
+    if (blocks.empty()) return;
+    if (c->ext.alloc) (void)hipDeviceSynchronize();
+    for (auto& b : blocks) {
+        if (c->ext.alloc)
+            c->ext.free(b.first, c->ext.user);
+        else
+            (void)hipFree(b.first);
     }
 }
 
@@ -87,57 +105,23 @@ static hipError_t block_alloc(ev_ctx* c, void** out, size_t bytes)
     return *out ? hipSuccess : hipErrorOutOfMemory;
 }
 
-static void cache_release(ev_ctx* c)
-{
-    for (auto& kv : c->cache)
-        for (void* p : kv.second) block_free(c, p);
-    c->cache.clear();
-    c->cache_tick.clear();
-    c->cached = 0;
-}
-
-// Release cached blocks, those idle the longest first, until `need` more
-// bytes fit under the hold limit (or nothing is cached).
-static void cache_trim(ev_ctx* c, size_t need)
-{
-    if (c->in_use + c->cached + need <= c->hold_limit) return;
-    std::vector<std::pair<uint64_t, void*>> order;
-    order.reserve(c->cache_tick.size());
-    for (auto& kv : c->cache_tick) order.push_back({kv.second, kv.first});
-    std::sort(order.begin(), order.end());
-    for (auto& o : order) {
-        if (c->in_use + c->cached + need <= c->hold_limit) break;
-        void* p = o.second;
-        const size_t cls = c->sizes_cached[p];
-        auto& bin = c->cache[cls];
-        bin.erase(std::find(bin.begin(), bin.end(), p));
-        c->cache_tick.erase(p);
-        c->sizes_cached.erase(p);
-        c->cached -= cls;
-        block_free(c, p);
-    }
-}
-
 ev_status dev_alloc(ev_ctx* c, size_t bytes, void** out)
 {
     *out = nullptr;
     const size_t cls = size_class(bytes);
+    const StreamClock* clk = &current_exec(c)->clock;
+    std::vector<std::pair<void*, size_t>> release;
     {
         std::lock_guard<std::mutex> g(c->mem_mu);
         if (c->budget && c->in_use + cls > c->budget)
             return fail(EV_ENOMEM, "memory budget exceeded (%zu + %zu > %zu bytes)", (size_t)c->in_use, cls,
                         (size_t)c->budget);
-        // the same size class, or for a large request the next one up
-        const size_t slack = cls >= (256ull << 20) ? cls / 4 : 0;
-        for (auto it = c->cache.lower_bound(cls); it != c->cache.end() && it->first <= cls + slack; ++it) {
-            if (it->second.empty()) continue;
-            const size_t got = it->first;
-            if (c->budget && c->in_use + got > c->budget) break;
-            *out = it->second.back();
-            it->second.pop_back();
-            c->cache_tick.erase(*out);
-            c->sizes_cached.erase(*out);
-            c->cached -= got;
+        // the same size class, or for a large request up to a class a
+        // quarter larger, within the budget
+        size_t hi = cls + (cls >= (256ull << 20) ? cls / 4 : 0);
+        if (c->budget) hi = std::min<size_t>(hi, std::max<size_t>(cls, c->budget - c->in_use));
+        size_t got = 0;
+        if ((*out = c->cache.take(cls, hi, clk, &got)) != nullptr) {
             c->in_use += got;
             c->sizes[*out] = got;
             return EV_OK;
@@ -145,20 +129,25 @@ ev_status dev_alloc(ev_ctx* c, size_t bytes, void** out)
         // Live and cached blocks together stay below the device's free
         // memory: the driver accepts allocations beyond it and then moves
         // buffers out of HBM while kernels use them.
-        cache_trim(c, cls);
-        if (c->in_use + cls > c->hold_limit)
+        if (c->in_use + c->cache.bytes() + cls > c->hold_limit)
+            release = c->cache.evict_oldest(c->in_use + c->cache.bytes() + cls - c->hold_limit);
+        if (c->in_use + cls > c->hold_limit) {
+            // not even with an empty cache
+            blocks_free(c, release);
             return fail(EV_ENOMEM, "device memory exhausted (%zu + %zu > %zu bytes held)", (size_t)c->in_use, cls,
                         (size_t)c->hold_limit);
+        }
         c->in_use += cls;
     }
+    blocks_free(c, release);
     hipError_t e = block_alloc(c, out, cls);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        std::lock_guard<std::mutex> g(c->mem_mu);
-        cache_release(c);
+        dev_cache_release(c);
         e = block_alloc(c, out, cls);
         if (e != hipSuccess) {
             (void)hipGetLastError();
+            std::lock_guard<std::mutex> g(c->mem_mu);
             c->in_use -= cls;
             *out = nullptr;
             return fail(EV_ENOMEM, "hipMalloc(%zu): %s", cls, hipGetErrorString(e));
@@ -172,22 +161,24 @@ ev_status dev_alloc(ev_ctx* c, size_t bytes, void** out)
 void dev_free(ev_ctx* c, void* p)
 {
     if (!p) return;
+    const StreamClock* clk = &current_exec(c)->clock;
     std::lock_guard<std::mutex> g(c->mem_mu);
     auto it = c->sizes.find(p);
     if (it == c->sizes.end()) return;
     const size_t cls = it->second;
     c->sizes.erase(it);
     c->in_use -= cls;
-    c->cache[cls].push_back(p);
-    c->cache_tick[p] = c->tick++;
-    c->sizes_cached[p] = cls;
-    c->cached += cls;
+    c->cache.put(p, cls, clk);
 }
 
 void dev_cache_release(ev_ctx* c)
 {
-    std::lock_guard<std::mutex> g(c->mem_mu);
-    cache_release(c);
+    std::vector<std::pair<void*, size_t>> release;
+    {
+        std::lock_guard<std::mutex> g(c->mem_mu);
+        release = c->cache.evict_all();
+    }
+    blocks_free(c, release);
 }
 
 // ------------------------------------------------------------- plans
@@ -662,6 +653,27 @@ Pop* pop_get(ev_ctx* c, ev_pop id)
     return it == c->pops.end() ? nullptr : it->second;
 }
 
+Pop* pop_acquire(ev_ctx* c, ev_pop id)
+{
+    std::lock_guard<std::mutex> g(c->pop_mu);
+    auto it = c->pops.find(id);
+    if (it == c->pops.end()) return nullptr;
+    it->second->refs++;
+    return it->second;
+}
+
+// The caller has waited for its own work on P; if P was freed meanwhile and
+// this was its last user, its blocks go to the cache for the caller's stream.
+void pop_release(ev_ctx* c, Pop* P)
+{
+    bool last = false;
+    {
+        std::lock_guard<std::mutex> g(c->pop_mu);
+        last = --P->refs == 0 && P->dead;
+    }
+    if (last) pop_free(c, P);
+}
+
 // ----------------------------------------------------------- evaluation
 
 ev_status ensure_gstack(ev_ctx* c, Exec& x, size_t bytes)
@@ -694,10 +706,12 @@ ev_status exec_init(Exec& x, hipStream_t given)
         x.stream = given;
         x.own_stream = false;
     } else {
+        // default priority (streams of other priorities are not used)
         hipError_t e = hipStreamCreateWithFlags(&x.stream, hipStreamNonBlocking);
         if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
         x.own_stream = true;
     }
+    x.clock.stream = x.stream;
     (void)hipEventCreateWithFlags(&x.done, hipEventDisableTiming);
     (void)hipEventCreate(&x.ev0);
     (void)hipEventCreate(&x.ev1);
@@ -798,8 +812,10 @@ ev_status sync(Exec& x)
 {
     hipError_t e = hipEventRecord(x.done, x.stream);
     if (e == hipSuccess) e = hipEventSynchronize(x.done);
-    if (e == hipSuccess)
+    if (e == hipSuccess) {
         for (const Exec::Out& o : x.pin_out) std::memcpy(o.dst, o.src, o.n);
+        x.clock.waits.fetch_add(1);  // everything queued before this call has finished
+    }
     x.pin_out.clear();
     x.pin_off = 0;
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -809,6 +825,7 @@ ev_status sync(Exec& x)
 void exec_free(ev_ctx* c, Exec& x)
 {
     if (x.stream) (void)hipStreamSynchronize(x.stream);
+    ExecScope scope(&x);
     if (x.pin) (void)hipHostFree(x.pin);
     x.pin = nullptr;
     x.pin_cap = x.pin_off = 0;
@@ -826,6 +843,11 @@ void exec_free(ev_ctx* c, Exec& x)
     if (x.evi0) (void)hipEventDestroy(x.evi0);
     if (x.evi1) (void)hipEventDestroy(x.evi1);
     x.done = x.ev0 = x.ev1 = x.evi0 = x.evi1 = nullptr;
+    {
+        // the stream has drained: what it freed is free for every stream
+        std::lock_guard<std::mutex> g(c->mem_mu);
+        c->cache.forget(&x.clock);
+    }
     if (x.own_stream && x.stream) (void)hipStreamDestroy(x.stream);
     x.stream = nullptr;
 }
@@ -861,7 +883,9 @@ ev_status rescache_get(ev_ctx* c, Exec& x, Pop* P, int32_t table, ResCache** out
 ev_status rescache_build(ev_ctx* c, Exec& x, Pop* P, int32_t table, ResCache** out)
 {
     ResCache r;
-    const int32_t N = c->tables[table].N;
+    CaseTable ct;
+    if (!table_get(c, table, &ct)) return fail(EV_EINVAL, "no case table %d", table);
+    const int32_t N = ct.N;
     r.N = N;
     ev_status st;
     for (auto& L : P->plan.levels) {
@@ -892,7 +916,8 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
         if (st == EV_OK && !verdict_at_sync && (st = sync(x)) == EV_OK) st = plan_verdict(P);
         if (st != EV_OK) return st;
     }
-    const CaseTable& ct = c->tables[table];
+    CaseTable ct;
+    if (!table_get(c, table, &ct)) return fail(EV_EINVAL, "no case table %d", table);
     const int32_t N = ct.N;
     const uint32_t n_cb = (uint32_t)((N + 63) / 64);
     const int D = P->plan.D;
@@ -1172,7 +1197,9 @@ static ev_status run_probe(ev_ctx* c)
     r.n_items = 1;
     r.n_cb = 1;
     r.counter = counter;
-    r.x = c->tables[0].d_x;
+    CaseTable t0;
+    (void)table_get(c, 0, &t0);
+    r.x = t0.d_x;
     r.N = 1;
     r.rowb = 4;
     r.in_res = slot;
@@ -1310,6 +1337,10 @@ ev_status ev_free_pop(ev_ctx* c, ev_pop pop)
         if (it == c->pops.end()) return fail(EV_ENOTFOUND, "no population %d", pop);
         P = it->second;
         c->pops.erase(it);
+        if (P->refs > 0) {
+            P->dead = true;  // a serving job still reads it: freed when it is done
+            return EV_OK;
+        }
     }
     (void)hipSetDevice(c->device);
     (void)sync(c->main);
@@ -1323,9 +1354,10 @@ ev_status ev_eval_fitness(ev_ctx* c, ev_pop pop, int32_t table, float* fitness, 
     if (!c || !fitness) return fail(EV_EINVAL, "ev_eval_fitness: bad arguments");
     Pop* P = pop_get(c, pop);
     if (!P) return fail(EV_ENOTFOUND, "no population %d", pop);
-    if (table < 0 || table >= (int32_t)c->tables.size()) return fail(EV_EINVAL, "no case table %d", table);
+    CaseTable ct;
+    if (!table_get(c, table, &ct)) return fail(EV_EINVAL, "no case table %d", table);
     HIPCHK(hipSetDevice(c->device));
-    const int32_t N = c->tables[table].N;
+    const int32_t N = ct.N;
     float* d_pc = nullptr;
     if (per_case) {
         if (flags & EV_OUT_DEVICE) {
@@ -1466,7 +1498,8 @@ ev_status ev_autotune(ev_ctx* c, ev_pop pop, int32_t table, int32_t reps, uint32
     if (!c || reps < 1) return fail(EV_EINVAL, "ev_autotune: bad arguments");
     Pop* P = pop_get(c, pop);
     if (!P) return fail(EV_ENOTFOUND, "no population %d", pop);
-    if (table < 0 || table >= (int32_t)c->tables.size()) return fail(EV_EINVAL, "no case table %d", table);
+    CaseTable ct;
+    if (!table_get(c, table, &ct)) return fail(EV_EINVAL, "no case table %d", table);
     HIPCHK(hipSetDevice(c->device));
     Exec& x = c->main;
     // re-plan P with work items of `chunk` tokens

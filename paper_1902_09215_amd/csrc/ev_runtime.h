@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/ev.h"
+#include "ev_cache.h"
 #include "ev_internal.h"
 #include "ev_launch.h"
 
@@ -77,6 +78,11 @@ struct Pop {
     int32_t* d_hits = nullptr;  // the last evaluation's hits, when asked for
     bool fit_valid = false;
     std::map<int32_t, ResCache> res;
+    // serving jobs using the population off the caller's thread (guarded by
+    // the context's pop_mu); ev_free_pop of a population still in use only
+    // unregisters it, and the last job to release it frees it
+    int32_t refs = 0;
+    bool dead = false;
 };
 
 // Host-side working vectors of plan_build, kept across calls so that their
@@ -95,6 +101,10 @@ struct PlanScratch {
 struct Exec {
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // the stream's identity and completed waits, for the block cache: a
+    // block this Exec frees is reused at once on its own stream, and on
+    // another only after a later wait here
+    StreamClock clock;
     uint32_t* d_counters = nullptr;
     size_t n_counters = 0;
     float* d_gstack = nullptr;
@@ -143,14 +153,10 @@ struct ev_ctx {
     uint64_t budget = 0, in_use = 0;
     uint64_t hold_limit = ~0ull;  // live + cached bytes, below the device's free memory
     std::unordered_map<void*, size_t> sizes;   // live blocks and their size class
-    std::map<size_t, std::vector<void*>> cache;  // freed blocks by size class
-    std::unordered_map<void*, uint64_t> cache_tick;    // cached block -> when it was freed
-    std::unordered_map<void*, size_t> sizes_cached;    // cached block -> its size class
-    uint64_t tick = 0;
-    uint64_t cached = 0;
+    ev::BlockCache cache;                        // freed blocks, stream-ordered
 
     std::mutex pop_mu;
-    std::vector<ev::CaseTable> tables;
+    std::deque<ev::CaseTable> tables;  // stable: serving workers hold references while tables are added
     std::map<ev_pop, ev::Pop*> pops;
     ev_pop next_pop = 1;
 
@@ -164,9 +170,24 @@ extern thread_local std::string g_err;
 ev_status fail(ev_status code, const char* fmt, ...);
 ev_status hip_fail(hipError_t e, const char* what);
 
+// Device blocks.  Both act for the calling thread's Exec (set with
+// ExecScope; the context's own Exec when none is set): a block freed while
+// that Exec's queued work may still use it is reused at once on the same
+// stream, and on other streams only after that Exec's next wait.
 ev_status dev_alloc(ev_ctx* c, size_t bytes, void** out);
 void dev_free(ev_ctx* c, void* p);
 void dev_cache_release(ev_ctx* c);
+
+// The Exec on whose stream the calling thread queues its work.
+struct ExecScope {
+    explicit ExecScope(Exec* x);
+    ~ExecScope();
+    Exec* prev;
+};
+Exec* current_exec(ev_ctx* c);
+
+// A case table by index (copied under the lock); false if there is none.
+bool table_get(ev_ctx* c, int32_t table, CaseTable* out);
 
 ev_status exec_init(Exec& x, hipStream_t given);
 ev_status stage(Exec& x, size_t n, void** out);
@@ -186,6 +207,9 @@ ev_status pop_build(ev_ctx* c, Exec& x, uint8_t* d_bytes, const std::vector<uint
 ev_status plan_verdict(Pop* P);
 ev_pop pop_register(ev_ctx* c, Pop* P);
 Pop* pop_get(ev_ctx* c, ev_pop id);
+// pin / unpin a registered population for work on another thread
+Pop* pop_acquire(ev_ctx* c, ev_pop id);
+void pop_release(ev_ctx* c, Pop* P);
 
 // verdict_at_sync: a plan's deferred validation verdict (Plan::err_pending)
 // is fetched with the caller's next sync(x), after which the caller calls

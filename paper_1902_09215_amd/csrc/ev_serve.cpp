@@ -5,10 +5,12 @@
 // device footprint fits the budget beside the jobs already in flight, and
 // fold every other queued evaluation request on the same case table that
 // also fits into the same device launch (continuous batching).  Several
-// workers run at once: one batches, stages and plans on the host while the
-// others' kernels run.  All device work goes to the context's one stream,
-// in the order the workers enqueue it.  Each tree's result depends only on
-// the tree, never on the batch it rode in.
+// workers run at once, each on its own stream: their batches overlap on the
+// device, and one batches, stages and plans on the host while the others'
+// kernels run.  Device blocks move between the workers' streams through the
+// stream-ordered block cache (ev_cache.h), and a population a crossover job
+// reads stays alive until the job is done.  Each tree's result depends only
+// on the tree, never on the batch it rode in or on what ran beside it.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -94,7 +96,7 @@ static ev_status run_eval_batch(ev_ctx* c, Exec& x, std::vector<Job*>& batch)
     }
     const int32_t M = (int32_t)off.size() - 1;
     const int32_t table = batch[0]->table;
-    const int32_t N = c->tables[table].N;
+    const int32_t N = batch[0]->N;
     ev_status st = EV_OK;
     uint8_t* d = nullptr;
     Pop* P = nullptr;
@@ -140,14 +142,18 @@ static ev_status run_eval_batch(ev_ctx* c, Exec& x, std::vector<Job*>& batch)
 
 static ev_status run_crossover(ev_ctx* c, Exec& x, Job* j)
 {
-    Pop* par = pop_get(c, j->parents);
+    Pop* par = pop_acquire(c, j->parents);
     if (!par) return fail(EV_ENOTFOUND, "no population %d", j->parents);
     Pop* C = nullptr;
     int32_t capped = 0;
     ev_status st = crossover_build(c, x, par, par, j->mum.data(), j->dad.data(), j->p.data(), j->q.data(), j->n,
                                    j->size_cap, &C, &capped);
-    if (st != EV_OK) return st;
-    const int32_t N = c->tables[j->table].N;
+    if (st != EV_OK) {
+        (void)sync(x);
+        pop_release(c, par);
+        return st;
+    }
+    const int32_t N = j->N;
     float* d_pc = nullptr;
     st = dev_alloc(c, (size_t)std::max(1, C->M) * N * sizeof(float), (void**)&d_pc);
     if (st == EV_OK) st = eval_enqueue(c, x, C, j->table, C->d_fit, d_pc, false, nullptr);
@@ -162,6 +168,7 @@ static ev_status run_crossover(ev_ctx* c, Exec& x, Job* j)
     else (void)sync(x);
     dev_free(c, d_pc);
     pop_free(c, C);
+    pop_release(c, par);
     return st;
 }
 
@@ -182,6 +189,7 @@ static bool fits(ev_ctx* c, Serve* S, uint64_t fp)
 static void worker(ev_ctx* c, Serve* S, Exec* x)
 {
     (void)hipSetDevice(c->device);
+    ExecScope scope(x);  // blocks this thread frees are tagged with its stream
     for (;;) {
         std::vector<Job*> batch;
         {
@@ -227,13 +235,13 @@ static Serve* serve_get(ev_ctx* c)
     if (c->serve) return c->serve;
     Serve* S = new Serve();
     S->budget = c->budget;
-    // Workers overlap their host work (batching, planning, staging) with the
-    // device work of the others; all of them enqueue on the context's one
-    // stream, each with its own scratch, staging and completion event.
-    const int W = 3;
+    // Each worker has its own stream (default priority), scratch, staging
+    // and completion event: batches overlap on the device, and a worker's
+    // host work (batching, planning, staging) overlaps the others' kernels.
+    const int W = 4;
     for (int i = 0; i < W; i++) {
         auto x = std::make_unique<Exec>();
-        if (exec_init(*x, c->main.stream) != EV_OK) break;
+        if (exec_init(*x, nullptr) != EV_OK) break;
         S->execs.push_back(std::move(x));
     }
     for (auto& x : S->execs) S->workers.emplace_back(worker, c, S, x.get());
@@ -271,11 +279,13 @@ extern "C" {
 ev_status ev_submit(ev_ctx* c, const ev_job* job, ev_ticket* out)
 {
     if (!c || !job || !out) return fail(EV_EINVAL, "ev_submit: bad arguments");
-    if (job->table < 0 || job->table >= (int32_t)c->tables.size()) return fail(EV_EINVAL, "no case table %d", job->table);
+    CaseTable ct;
+    if (!table_get(c, job->table, &ct)) return fail(EV_EINVAL, "no case table %d", job->table);
     auto j = std::make_unique<Job>();
     j->kind = job->kind;
     j->table = job->table;
-    const int32_t N = c->tables[job->table].N;
+    const int32_t N = ct.N;
+    j->N = N;
     if (job->kind == EV_JOB_EVAL) {
         if (job->n_trees < 0 || (job->n_trees > 0 && (!job->off || !job->bytes)))
             return fail(EV_EINVAL, "ev_submit: bad trees");
@@ -297,10 +307,16 @@ ev_status ev_submit(ev_ctx* c, const ev_job* job, ev_ticket* out)
         }
         j->footprint = footprint(j->off.back(), (uint64_t)j->n, N, c->chunk);
     } else if (job->kind == EV_JOB_CROSSOVER) {
-        Pop* par = pop_get(c, job->parents);
-        if (!par) return fail(EV_ENOTFOUND, "no population %d", job->parents);
         if (job->n_children < 0 || (job->n_children > 0 && (!job->mum || !job->dad || !job->p || !job->q)))
             return fail(EV_EINVAL, "ev_submit: bad crossover arrays");
+        Pop* par = pop_acquire(c, job->parents);
+        if (!par) return fail(EV_ENOTFOUND, "no population %d", job->parents);
+        // host-side checks only: the population stays pinned while they read it
+        struct Unpin {
+            ev_ctx* c;
+            Pop* P;
+            ~Unpin() { pop_release(c, P); }
+        } unpin{c, par};
         j->n = job->n_children;
         j->parents = job->parents;
         j->mum.assign(job->mum, job->mum + j->n);

@@ -606,6 +606,54 @@ def test_serving_crossover_jobs(ev):
     assert_same(fit, wf, "served crossover")
 
 
+def test_serving_parents_freed_while_jobs_run(ev):
+    # Crossover jobs read a resident population on the workers' streams; the
+    # caller frees it right after submitting.  Jobs that had started finish
+    # with the oracle's results (the population lives until the last one is
+    # done); jobs that had not are refused with EV_ENOTFOUND.  Evaluation
+    # jobs submitted beside them are unaffected.
+    x, y = workloads.cases(48)
+    rng = np.random.default_rng(53)
+    sizes = workloads.loguniform_sizes(53, 64, 1, 200000)
+    buf, off = workloads.random_population(53, sizes)
+    esizes = workloads.loguniform_sizes(54, 40, 10, 300000)
+    ebuf, eoff = workloads.random_population(54, esizes)
+    want_e = oracle.eval_population(ebuf, eoff, x, y, threads=8)
+    with ev.Context(x, y) as c:
+        for rep in range(3):
+            pop = c.load(buf, off)
+            jobs, evals = [], []
+            for k in range(24):
+                mum = rng.integers(0, 64, 4).astype(np.int32)
+                dad = rng.integers(0, 64, 4).astype(np.int32)
+                p = np.array([rng.integers(0, sizes[m]) for m in mum], np.uint64)
+                q = np.array([rng.integers(0, sizes[d]) for d in dad], np.uint64)
+                jobs.append(((mum, dad, p, q), ev.ev_submit_crossover(c.ctx, pop, mum, dad, p, q)))
+                t = int(rng.integers(0, 40))
+                evals.append((t, ev.ev_submit_eval(c.ctx, ebuf[eoff[t]:eoff[t + 1]],
+                                                   np.array([0, esizes[t]], np.uint64))))
+            ev.ev_free_pop(c.ctx, pop)
+            done = 0
+            for (mum, dad, p, q), tk in jobs:
+                st = ev.ev_wait(c.ctx, tk)
+                if st == ev.EV_ENOTFOUND:
+                    with pytest.raises(ev.EvError):
+                        ev.ev_result(c.ctx, tk, 4, 48)
+                    continue
+                assert st == 0, st
+                f, _ = ev.ev_result(c.ctx, tk, 4, 48)
+                kids = [oracle.crossover(buf[off[m]:off[m + 1]], buf[off[d]:off[d + 1]], int(pp), int(qq))
+                        for m, d, pp, qq in zip(mum, dad, p, q)]
+                koff = workloads.offsets_from_sizes([kk.size for kk in kids])
+                assert_same(f, oracle.eval_population(np.concatenate(kids), koff, x, y), f"rep {rep} crossover")
+                done += 1
+            for t, tk in evals:
+                assert ev.ev_wait(c.ctx, tk) == 0
+                f, _ = ev.ev_result(c.ctx, tk, 1, 48)
+                assert_same(f, want_e[t:t + 1], f"rep {rep} eval of tree {t}")
+            print(f"rep {rep}: {done} of {len(jobs)} crossover jobs ran", flush=True)
+
+
 def oracle_in_background(buf, off, x, y, threads=None):
     """Start the oracle's evaluation of a population on every host core in a
     thread (the C call releases the interpreter lock), so that it overlaps the
