@@ -252,7 +252,11 @@ ev_status ev_get_level_info(ev_ctx *ctx, ev_pop pop, int32_t level, ev_level_inf
  * instead of the register-stack one.  EV_TUNE_NO_RECORD makes the plan
  * builder emit codes by a second pass of the structure machine instead of
  * placing what its counting pass recorded (levels too large to record,
- * over about 190 million tokens, always do).  Plans made afterwards use them;
+ * over about 300 million tokens, always do).  EV_TUNE_NO_REUSE plans the
+ * children of ev_crossover and ev_generation from scratch instead of taking
+ * over the code streams and skeleton fragments of their mum's level-0 work
+ * items that crossover leaves intact (a child is its mum with one subtree
+ * replaced, Sec. 3.1).  Plans made afterwards use them;
  * results never depend on them.  EV_TUNE_TEST_FAIL_CHECK is a test hook
  * for the error path of code-stream validation: plans made afterwards
  * record their last level as failing it (the plan is refused, or, for the
@@ -261,6 +265,7 @@ ev_status ev_get_level_info(ev_ctx *ctx, ev_pop pop, int32_t level, ev_level_inf
  * level's codes). */
 #define EV_TUNE_NO_REGSTACK 0x1u
 #define EV_TUNE_NO_RECORD 0x2u
+#define EV_TUNE_NO_REUSE 0x4u
 #define EV_TUNE_TEST_FAIL_CHECK 0x100u
 ev_status ev_set_tuning(ev_ctx *ctx, uint32_t chunk, uint32_t chunk_hi, uint32_t lds_depth, uint32_t flags);
 

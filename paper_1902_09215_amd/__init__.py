@@ -344,6 +344,7 @@ def level_functions(ctx, pop) -> list:
 
 EV_TUNE_NO_REGSTACK = 0x1
 EV_TUNE_NO_RECORD = 0x2
+EV_TUNE_NO_REUSE = 0x4
 EV_TUNE_TEST_FAIL_CHECK = 0x100
 
 

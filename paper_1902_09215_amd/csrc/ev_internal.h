@@ -43,6 +43,11 @@ struct SegIn {
     uint32_t last;  // holds the chunk's first token (read last)
 };
 
+// Bytes of one segment's recording regions (its code kinds, its fragment
+// tokens) at a level whose segments hold at most seg_len tokens.
+constexpr uint64_t rec_kinds_stride(uint32_t seg_len) { return 4ull * seg_len + 64ull; }
+constexpr uint64_t rec_frags_stride(uint32_t seg_len) { return 2ull * seg_len + 16ull; }
+
 struct ChunkSegs {
     uint32_t first;  // first segment (token order)
     uint32_t n_seg;
@@ -177,6 +182,35 @@ struct EvalArgs {
 };
 
 static_assert(sizeof(EvalChunk) == 32, "EvalChunk layout");
+
+// Level 0 of a planned population, per tree: its range of chunks (the
+// chunks themselves, in token order, are kept with the plan so that a child
+// can take over those crossover leaves intact).
+struct L0Tree {
+    uint32_t chunk_first, n_chunks;
+};
+
+// A child's level 0 from its mum's (Sec. 3.1: the child is its mum with the
+// subtree at p replaced): the mum's chunks wholly before p and wholly after
+// the end ep of that subtree keep their tokens, so their codes and skeleton
+// fragments are the mum's; only the tokens between them are planned.
+struct ReuseRun {
+    uint64_t mid_start, mid_len;  // the child's tokens planned afresh (child offsets)
+    int64_t shift;                // child length - mum length: where the kept suffix lands
+    uint64_t mum_off;             // the mum's first token in its population
+    uint32_t src_first;           // the mum's first level-0 chunk (index into its chunk tables)
+    uint32_t n_pre;               // mum chunks 0 .. n_pre-1 kept, at their own offsets
+    uint32_t ks, n_suf;           // mum chunks ks .. ks+n_suf-1 kept, at their offsets + shift
+    uint32_t mum, pad;            // the mum's index in its population
+};
+
+// A child as the chunk kernel of a reusing plan sees it.
+struct TreeReuse {
+    uint64_t start;  // the child's first token in the level's sequence
+    ReuseRun r;
+    uint32_t chunk_first, seg_first, tree, C;  // C: the fresh chunks' size
+    uint32_t n_mid, mid_last;                  // fresh chunks (all C tokens but the last)
+};
 
 struct XoPlan {
     uint64_t mum_off, dad_off;  // tree starts in the parents' buffers

@@ -495,7 +495,10 @@ __global__ __launch_bounds__(64) void k_plan_trees(const TreeLvl* __restrict__ t
         const uint32_t j = tl.chunk_first + (in ? k : 0);
         ChunkStat q = {};
         if (in) q = cs[j];
-        uint64_t so = q.n_out, sf = q.n_frag, sc = q.n_codes, si = q.n_in;
+        // every chunk's codes start a 128-byte block (its codes are then the
+        // same words wherever the block lands, so a child's plan can copy them)
+        const uint64_t padc = ((uint64_t)q.n_codes + (EV_CODE_POS - 1)) & ~(uint64_t)(EV_CODE_POS - 1);
+        uint64_t so = q.n_out, sf = q.n_frag, sc = padc, si = q.n_in;
         int64_t sn = q.net;
         for (int d = 1; d < 64; d <<= 1) {
             const uint64_t a = __shfl_up(so, d, 64), b = __shfl_up(sf, d, 64), c = __shfl_up(sc, d, 64),
@@ -510,7 +513,7 @@ __global__ __launch_bounds__(64) void k_plan_trees(const TreeLvl* __restrict__ t
             }
         }
         if (in) {
-            code_loc[j] = c_code + sc - q.n_codes;
+            code_loc[j] = c_code + sc - padc;
             out_loc[j] = c_out + so;
             frag_loc[j] = c_frag + sf;
             const uint64_t ie = c_in + si;
@@ -594,13 +597,15 @@ __global__ __launch_bounds__(1024) void k_plan_bases(const TreeLvl* __restrict__
 
 // Per chunk: its global numbering from its tree's bases, and its work item,
 // placed longest first (bucket_start: the first place of each length
-// bucket; the tree gives the chunk's rank inside its bucket).
+// bucket; the tree gives the chunk's rank inside its bucket), or at
+// item_at[j] when the places were made with the chunks.
 __global__ void k_plan_items(const ChunkIn* __restrict__ ch, uint32_t n, const TreeBase* __restrict__ base,
                              const uint64_t* __restrict__ code_loc, const uint64_t* __restrict__ out_loc,
                              const uint64_t* __restrict__ frag_loc, const uint32_t* __restrict__ in_end,
                              const uint32_t* __restrict__ bucket_start, uint64_t* __restrict__ code_begin,
                              uint64_t* __restrict__ frag_end, RunChunk* __restrict__ run, EvalChunk* __restrict__ slow,
-                             uint32_t* __restrict__ code_tail, uint8_t* __restrict__ frag_tail)
+                             uint32_t* __restrict__ code_tail, uint8_t* __restrict__ frag_tail,
+                             const uint32_t* __restrict__ item_at)
 {
     if (blockIdx.x == 0) {
         // the padding after the level's code stream (zeros) and after the
@@ -617,11 +622,207 @@ __global__ void k_plan_items(const ChunkIn* __restrict__ ch, uint32_t n, const T
     code_begin[j] = run ? cb : ~0ull;
     frag_end[j] = b.frag + frag_loc[j];
     const uint32_t k = j - b.chunk_first;
-    const uint32_t at = bucket_start[len_bucket(c.len)] + (k + 1 < b.n_chunks ? b.rank_full + k : b.rank_last);
+    const uint32_t at = item_at ? item_at[j]
+                                : bucket_start[len_bucket(c.len)] + (k + 1 < b.n_chunks ? b.rank_full + k : b.rank_last);
     if (run)
         run[at] = RunChunk{cb, in_end[j], oe};
     else
         slow[at] = EvalChunk{c.start, c.len, in_end[j], oe, c.tree, 0, 0};
+}
+
+// ------------------------------------------ children reusing their mum's level 0
+//
+// A child of Sec. 3.1's crossover is its mum with the subtree at p (ending
+// at ep) replaced by a subtree of the dad.  The right-to-left structure
+// machine of a level-0 chunk starts from an empty stack at the chunk's end,
+// so a chunk's codes and skeleton fragment depend on its own tokens alone:
+// the mum's chunks wholly before p and wholly after ep are the child's too.
+// Only the tokens between them are planned; the rest is copied.
+
+// One thread per child: which of its mum's chunks it keeps, and the tokens
+// to plan.  A child over the size cap is a copy of its mum and keeps every
+// chunk.  The mum's chunks lie in token order, so the chunk holding p and
+// the first chunk after ep are found by binary search.
+__global__ void k_reuse_runs(const XoPlan* __restrict__ plan, const int32_t* __restrict__ mum,
+                             const L0Tree* __restrict__ trees, const ChunkIn* __restrict__ mum_ch, uint32_t n,
+                             ReuseRun* __restrict__ out)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const XoPlan x = plan[j];
+    const L0Tree t = trees[mum[j]];
+    ReuseRun r;
+    r.src_first = t.chunk_first;
+    r.mum_off = x.mum_off;
+    r.mum = (uint32_t)mum[j];
+    r.pad = 0;
+    r.n_pre = r.ks = r.n_suf = 0;
+    r.mid_start = 0;
+    r.mid_len = x.child_len;
+    r.shift = 0;
+    if (x.copy_mum) {
+        r.n_pre = t.n_chunks;
+        r.ks = t.n_chunks;
+        r.mid_start = x.child_len;
+        r.mid_len = 0;
+    } else if (t.n_chunks > 1) {
+        const ChunkIn* c = mum_ch + t.chunk_first;
+        // kp: the chunks ending at or before p; ks: the first starting after ep
+        uint32_t lo = 0, hi = t.n_chunks;
+        while (lo < hi) {
+            const uint32_t m = (lo + hi) / 2;
+            if (c[m].start - x.mum_off + c[m].len <= x.p) lo = m + 1; else hi = m;
+        }
+        const uint32_t kp = lo;
+        lo = kp;
+        hi = t.n_chunks;
+        while (lo < hi) {
+            const uint32_t m = (lo + hi) / 2;
+            if (c[m].start - x.mum_off <= x.ep) lo = m + 1; else hi = m;
+        }
+        const uint32_t ks = lo;
+        const uint64_t mum_len = c[t.n_chunks - 1].start - x.mum_off + c[t.n_chunks - 1].len;
+        r.n_pre = kp;
+        r.ks = ks;
+        r.n_suf = t.n_chunks - ks;
+        r.shift = (int64_t)x.child_len - (int64_t)mum_len;
+        r.mid_start = c[kp].start - x.mum_off;
+        const uint64_t mid_end = ks < t.n_chunks ? (uint64_t)((int64_t)(c[ks].start - x.mum_off) + r.shift) : x.child_len;
+        r.mid_len = mid_end - r.mid_start;
+    }
+    out[j] = r;
+}
+
+// One block per child: its chunk records in token order (kept prefix,
+// fresh chunks, kept suffix), the segments of its fresh chunks, and each
+// chunk's source (the mum's chunk index, or ~0u for a fresh chunk).  Block
+// 0 also initializes the validator's words, as k_plan_chunks does.
+__global__ __launch_bounds__(64) void k_reuse_chunks(const TreeReuse* __restrict__ trees, uint32_t n_trees,
+                                                     const ChunkIn* __restrict__ mum_ch, uint32_t seg_len, uint32_t head,
+                                                     ChunkIn* __restrict__ ch, ChunkSegs* __restrict__ cg,
+                                                     uint32_t* __restrict__ src, uint32_t* __restrict__ err_init,
+                                                     uint32_t n_err)
+{
+    const uint32_t i = blockIdx.x;
+    if (i == 0 && err_init)
+        for (uint32_t k = threadIdx.x; k < n_err; k += blockDim.x) err_init[k] = (k & 1u) ? UINT32_MAX : 0u;
+    if (i >= n_trees) return;
+    const TreeReuse t = trees[i];
+    const uint32_t n_chunks = t.r.n_pre + t.n_mid + t.r.n_suf;
+    const uint32_t full = seg_count(t.C, seg_len, head);
+    for (uint32_t k = threadIdx.x; k < n_chunks; k += blockDim.x) {
+        uint64_t off;
+        uint32_t len, from = ~0u, first = 0, nseg = 0;
+        if (k < t.r.n_pre || k >= t.r.n_pre + t.n_mid) {
+            const bool pre = k < t.r.n_pre;
+            from = t.r.src_first + (pre ? k : t.r.ks + (k - t.r.n_pre - t.n_mid));
+            const ChunkIn mc = mum_ch[from];
+            off = (uint64_t)((int64_t)(mc.start - t.r.mum_off) + (pre ? 0 : t.r.shift));
+            len = mc.len;
+        } else {
+            const uint32_t m = k - t.r.n_pre;
+            off = t.r.mid_start + (uint64_t)m * t.C;
+            len = m + 1 == t.n_mid ? t.mid_last : t.C;
+            first = t.seg_first + m * full;
+            nseg = seg_count(len, seg_len, head);
+        }
+        const uint32_t j = t.chunk_first + k;
+        ch[j] = ChunkIn{t.start + off, len, t.tree};
+        cg[j] = ChunkSegs{first, nseg};
+        src[j] = from;
+    }
+}
+
+// Work items longest first, for plans whose chunk lengths the host does not
+// know: a counting sort on the length's bit count on the device.  Each wave
+// takes one atomic per distinct bucket among its lanes; the order inside a
+// bucket does not matter.
+__global__ void k_item_hist(const ChunkIn* __restrict__ ch, uint32_t n, uint32_t* __restrict__ hist)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = j < n;
+    const uint32_t b = in ? len_bucket(ch[j].len) : EV_LEN_BUCKETS;
+    uint64_t todo = __ballot(in);
+    while (todo) {
+        const uint32_t lead = (uint32_t)__ffsll((unsigned long long)todo) - 1u;
+        const uint32_t b0 = __shfl(b, (int)lead, 64);
+        const uint64_t same = __ballot(in && b == b0);
+        if ((threadIdx.x & 63u) == lead) atomicAdd(&hist[b0], (uint32_t)__popcll(same));
+        todo &= ~same;
+    }
+}
+
+// hist -> each bucket's first place (one thread; 33 buckets)
+__global__ void k_item_cursor(uint32_t* __restrict__ hist)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint32_t a = 0;
+    for (uint32_t k = 0; k < EV_LEN_BUCKETS; k++) {
+        const uint32_t v = hist[k];
+        hist[k] = a;
+        a += v;
+    }
+}
+
+__global__ void k_item_place(const ChunkIn* __restrict__ ch, uint32_t n, uint32_t* __restrict__ cursor,
+                             uint32_t* __restrict__ item_at)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = j < n;
+    const uint32_t b = in ? len_bucket(ch[j].len) : EV_LEN_BUCKETS;
+    const uint64_t lt = (1ull << (threadIdx.x & 63u)) - 1ull;
+    uint64_t todo = __ballot(in);
+    while (todo) {
+        const uint32_t lead = (uint32_t)__ffsll((unsigned long long)todo) - 1u;
+        const uint32_t b0 = __shfl(b, (int)lead, 64);
+        const uint64_t same = __ballot(in && b == b0);
+        uint32_t base = 0;
+        if ((threadIdx.x & 63u) == lead) base = atomicAdd(&cursor[b0], (uint32_t)__popcll(same));
+        base = __shfl(base, (int)lead, 64);
+        if (in && b == b0) item_at[j] = base + (uint32_t)__popcll(same & lt);
+        todo &= ~same;
+    }
+}
+
+// Kept chunks take their mum's totals (after the fresh chunks' were made).
+__global__ void k_reuse_stats(const uint32_t* __restrict__ src, uint32_t n, const ChunkStat* __restrict__ mum_stat,
+                              ChunkStat* __restrict__ cstat)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t f = src[j];
+    if (f != ~0u) cstat[j] = mum_stat[f];
+}
+
+// One block per chunk: a kept chunk's codes (whole 128-byte blocks: every
+// chunk's codes start a block in both plans) and its skeleton fragment
+// (bytes [frag_end - n_frag, frag_end) of each level-1 skeleton).
+__global__ __launch_bounds__(256) void k_reuse_copy(const uint32_t* __restrict__ src, uint32_t n,
+                                                    const ChunkStat* __restrict__ cstat,
+                                                    const uint64_t* __restrict__ code_begin,
+                                                    const uint64_t* __restrict__ frag_end,
+                                                    const uint64_t* __restrict__ mum_code,
+                                                    const uint64_t* __restrict__ mum_frag,
+                                                    const uint32_t* __restrict__ mum_codes,
+                                                    const uint8_t* __restrict__ mum_skel, uint32_t* __restrict__ codes,
+                                                    uint8_t* __restrict__ skel)
+{
+    const uint32_t j = blockIdx.x;
+    if (j >= n) return;
+    const uint32_t f = src[j];
+    if (f == ~0u) return;
+    const ChunkStat q = cstat[j];
+    if (codes) {
+        const u32x4* a = reinterpret_cast<const u32x4*>(mum_codes + mum_code[f]);
+        u32x4* b = reinterpret_cast<u32x4*>(codes + code_begin[j]);
+        const uint32_t words = ((q.n_codes + (EV_CODE_POS - 1)) & ~(EV_CODE_POS - 1)) / 4u;
+        for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) b[w] = a[w];
+    }
+    if (skel) {
+        const uint8_t* a = mum_skel + (mum_frag[f] - q.n_frag);
+        uint8_t* b = skel + (frag_end[j] - q.n_frag);
+        for (uint32_t w = threadIdx.x; w < q.n_frag; w += blockDim.x) b[w] = a[w];
+    }
 }
 
 // Per segment: its cnt map (a, b), validity counters and input references.
@@ -733,27 +934,29 @@ __global__ __launch_bounds__(64) void k_seg_scan(const ChunkSegs* __restrict__ c
     }
 }
 
-// Where a segment's recording goes: regions ordered like the segments'
-// tokens, which a level's segments cover in index order, so that they never
-// overlap (kinds: at most 4 per token plus the boundary's spills and fills,
-// or the chunk end's flushes and last codes; fragment tokens: at most 2 per
-// token).  Kind regions are 8-byte aligned.
-__device__ __forceinline__ uint64_t rec_kinds_at(const SegIn& g, uint32_t si) { return 8ull * g.start + 64ull * si; }
-__device__ __forceinline__ uint64_t rec_frags_at(const SegIn& g, uint32_t si) { return 3ull * g.start + 16ull * si; }
+// Where a segment's recording goes: one region per segment, by its index,
+// each as large as the longest segment of the level needs (kinds: at most 4
+// per token plus the boundary's spills and fills, or the chunk end's flushes
+// and last codes; fragment tokens: at most 2 per token), so that they never
+// overlap whichever tokens the level's segments cover.  Kind regions are
+// 8-byte aligned.
+__device__ __forceinline__ uint64_t rec_kinds_at(uint32_t si, uint32_t seg_len) { return rec_kinds_stride(seg_len) * si; }
+__device__ __forceinline__ uint64_t rec_frags_at(uint32_t si, uint32_t seg_len) { return rec_frags_stride(seg_len) * si; }
 
 // Per segment: its counts; with rk/rf, also the recording of its codes'
 // kinds and fragment tokens (set *ovf if a region was too small).
 __global__ void k_seg_count(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs, uint32_t n,
                             const SegStart* __restrict__ st, SegCount* __restrict__ out, uint8_t* __restrict__ rk,
-                            uint8_t* __restrict__ rf, SegRec* __restrict__ rec, uint32_t* __restrict__ ovf)
+                            uint8_t* __restrict__ rf, SegRec* __restrict__ rec, uint32_t* __restrict__ ovf,
+                            uint32_t seg_len)
 {
     const uint32_t si = blockIdx.x * blockDim.x + threadIdx.x;
     if (si >= n) return;
     const SegIn g = segs[si];
     Sink o{nullptr, 0, nullptr, 0, 0, 0, 0, 0, ~0u, st[si].ref0, nullptr, nullptr, 0, 0, 0, 0, 0, SegRec{}};
     if (rk) {
-        o.rk = rk + rec_kinds_at(g, si);
-        o.rf = rf + rec_frags_at(g, si);
+        o.rk = rk + rec_kinds_at(si, seg_len);
+        o.rf = rf + rec_frags_at(si, seg_len);
         o.rk_cap = 4u * g.len + 40u;
         o.rf_cap = 2u * g.len + 16u;
     }
@@ -884,7 +1087,7 @@ __global__ __launch_bounds__(64) void k_seg_place(const SegIn* __restrict__ segs
                                                   const uint64_t* __restrict__ seg_frag, const uint8_t* __restrict__ rk,
                                                   const uint8_t* __restrict__ rf, uint32_t* __restrict__ codes,
                                                   uint64_t n_codes, uint8_t* __restrict__ dst, uint64_t n_frag,
-                                                  uint32_t slab_entries, uint32_t* __restrict__ err)
+                                                  uint32_t slab_entries, uint32_t* __restrict__ err, uint32_t seg_len)
 {
     const uint32_t lane = threadIdx.x;
     const uint64_t lt = (1ull << lane) - 1ull;  // the lanes before this one
@@ -896,7 +1099,7 @@ __global__ __launch_bounds__(64) void k_seg_place(const SegIn* __restrict__ segs
         uint32_t bad = 0;
         if (codes && seg_code[si] != ~0ull) {
             const uint64_t b = seg_code[si];
-            const uint8_t* kp = rk + rec_kinds_at(g, si);
+            const uint8_t* kp = rk + rec_kinds_at(si, seg_len);
             // the machine's state before the batch
             const SegStart s0 = st[si];
             const uint32_t tv0 = s0.cnt > s0.P ? 1u : 0u, m0 = s0.cnt - tv0 - s0.P;
@@ -1013,7 +1216,7 @@ __global__ __launch_bounds__(64) void k_seg_place(const SegIn* __restrict__ segs
         }
         if (dst) {
             const uint64_t w = seg_frag[si];
-            const uint8_t* f = rf + rec_frags_at(g, si);
+            const uint8_t* f = rf + rec_frags_at(si, seg_len);
             for (uint32_t i = lane; i < q.n_frag; i += 64) {
                 const uint8_t t = i < r.nfr ? (i < cap_f ? f[i] : (uint8_t)0xFF) : (uint8_t)TOK_REF;
                 bad |= (i < r.nfr && i >= cap_f) ? 0x200u : 0u;
@@ -1753,11 +1956,58 @@ hipError_t launch_plan_items(const ChunkIn* ch, uint32_t n, const TreeBase* base
                              const uint64_t* out_loc, const uint64_t* frag_loc, const uint32_t* in_end,
                              const uint32_t* cursor,
                              uint64_t* code_begin, uint64_t* frag_end, RunChunk* run, EvalChunk* slow,
-                             uint32_t* code_tail, uint8_t* frag_tail, hipStream_t s)
+                             uint32_t* code_tail, uint8_t* frag_tail, const uint32_t* item_at, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_plan_items, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, base, code_loc, out_loc, frag_loc,
-                       in_end, cursor, code_begin, frag_end, run, slow, code_tail, frag_tail);
+                       in_end, cursor, code_begin, frag_end, run, slow, code_tail, frag_tail, item_at);
+    return hipGetLastError();
+}
+
+hipError_t launch_reuse_runs(const XoPlan* plan, const int32_t* mum, const L0Tree* trees, const ChunkIn* mum_ch,
+                             uint32_t n, ReuseRun* out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reuse_runs, dim3(cdiv(n, 256)), dim3(256), 0, s, plan, mum, trees, mum_ch, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reuse_chunks(const TreeReuse* trees, uint32_t n_trees, const ChunkIn* mum_ch, uint32_t seg_len,
+                               uint32_t head, ChunkIn* ch, ChunkSegs* cg, uint32_t* src, uint32_t* err_init,
+                               uint32_t n_err, hipStream_t s)
+{
+    if (n_trees == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reuse_chunks, dim3(n_trees), dim3(64), 0, s, trees, n_trees, mum_ch, seg_len, head, ch, cg,
+                       src, err_init, n_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_item_sort(const ChunkIn* ch, uint32_t n, uint32_t* hist, uint32_t* item_at, hipStream_t s)
+{
+    hipError_t e = launch_fill_u32(hist, EV_LEN_BUCKETS, 0u, s);
+    if (e != hipSuccess || n == 0) return e;
+    hipLaunchKernelGGL(k_item_hist, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, hist);
+    hipLaunchKernelGGL(k_item_cursor, dim3(1), dim3(64), 0, s, hist);
+    hipLaunchKernelGGL(k_item_place, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, hist, item_at);
+    return hipGetLastError();
+}
+
+hipError_t launch_reuse_stats(const uint32_t* src, uint32_t n, const ChunkStat* mum_stat, ChunkStat* cstat,
+                              hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reuse_stats, dim3(cdiv(n, 256)), dim3(256), 0, s, src, n, mum_stat, cstat);
+    return hipGetLastError();
+}
+
+hipError_t launch_reuse_copy(const uint32_t* src, uint32_t n, const ChunkStat* cstat, const uint64_t* code_begin,
+                             const uint64_t* frag_end, const uint64_t* mum_code, const uint64_t* mum_frag,
+                             const uint32_t* mum_codes, const uint8_t* mum_skel, uint32_t* codes, uint8_t* skel,
+                             hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reuse_copy, dim3(n), dim3(256), 0, s, src, n, cstat, code_begin, frag_end, mum_code, mum_frag,
+                       mum_codes, mum_skel, codes, skel);
     return hipGetLastError();
 }
 
@@ -1778,22 +2028,23 @@ hipError_t launch_seg_scan(const ChunkSegs* cseg, uint32_t n, const SegFn* fn, S
 }
 
 hipError_t launch_seg_count(const uint8_t* seq, const SegIn* segs, uint32_t n, const SegStart* st, SegCount* out,
-                            uint8_t* rk, uint8_t* rf, SegRec* rec, uint32_t* ovf, hipStream_t s)
+                            uint8_t* rk, uint8_t* rf, SegRec* rec, uint32_t* ovf, uint32_t seg_len, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_count, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, st, out, rk, rf, rec, ovf);
+    hipLaunchKernelGGL(k_seg_count, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, st, out, rk, rf, rec, ovf,
+                       seg_len);
     return hipGetLastError();
 }
 
 hipError_t launch_seg_place(const SegIn* segs, uint32_t n, const SegCount* cnt, const SegRec* rec, const SegStart* st,
                             const uint64_t* seg_code, const uint64_t* seg_frag, const uint8_t* rk, const uint8_t* rf,
                             uint32_t* codes, uint64_t n_codes, uint8_t* dst, uint64_t n_frag, uint32_t slab_entries,
-                            uint32_t* err, hipStream_t s)
+                            uint32_t* err, uint32_t seg_len, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const uint32_t grid = n < 16384u ? n : 16384u;
     hipLaunchKernelGGL(k_seg_place, dim3(grid), dim3(64), 0, s, segs, n, cnt, rec, st, seg_code, seg_frag, rk, rf,
-                       codes, n_codes, dst, n_frag, slab_entries, err);
+                       codes, n_codes, dst, n_frag, slab_entries, err, seg_len);
     return hipGetLastError();
 }
 

@@ -20,19 +20,33 @@ hipError_t launch_plan_items(const ChunkIn* ch, uint32_t n, const TreeBase* base
                              const uint64_t* out_loc, const uint64_t* frag_loc, const uint32_t* in_end,
                              const uint32_t* cursor,
                              uint64_t* code_begin, uint64_t* frag_end, RunChunk* run, EvalChunk* slow,
-                             uint32_t* code_tail, uint8_t* frag_tail, hipStream_t s);
+                             uint32_t* code_tail, uint8_t* frag_tail, const uint32_t* item_at, hipStream_t s);
+// children reusing their mum's level-0 chunks
+hipError_t launch_reuse_runs(const XoPlan* plan, const int32_t* mum, const L0Tree* trees, const ChunkIn* mum_ch,
+                             uint32_t n, ReuseRun* out, hipStream_t s);
+hipError_t launch_reuse_chunks(const TreeReuse* trees, uint32_t n_trees, const ChunkIn* mum_ch, uint32_t seg_len,
+                               uint32_t head, ChunkIn* ch, ChunkSegs* cg, uint32_t* src, uint32_t* err_init,
+                               uint32_t n_err, hipStream_t s);
+// work-item places, longest first (hist: EV_LEN_BUCKETS words of scratch)
+hipError_t launch_item_sort(const ChunkIn* ch, uint32_t n, uint32_t* hist, uint32_t* item_at, hipStream_t s);
+hipError_t launch_reuse_stats(const uint32_t* src, uint32_t n, const ChunkStat* mum_stat, ChunkStat* cstat,
+                              hipStream_t s);
+hipError_t launch_reuse_copy(const uint32_t* src, uint32_t n, const ChunkStat* cstat, const uint64_t* code_begin,
+                             const uint64_t* frag_end, const uint64_t* mum_code, const uint64_t* mum_frag,
+                             const uint32_t* mum_codes, const uint8_t* mum_skel, uint32_t* codes, uint8_t* skel,
+                             hipStream_t s);
 hipError_t launch_seg_fn(const uint8_t* seq, const SegIn* segs, uint32_t n, SegFn* out, uint32_t max_tok,
                          hipStream_t s);
 hipError_t launch_seg_scan(const ChunkSegs* cseg, uint32_t n, const SegFn* fn, SegStart* st, ChunkStat* cstat,
                            hipStream_t s);
 // rk/rf/rec (nullable): record the segments' code kinds and fragment tokens
 hipError_t launch_seg_count(const uint8_t* seq, const SegIn* segs, uint32_t n, const SegStart* st, SegCount* out,
-                            uint8_t* rk, uint8_t* rf, SegRec* rec, uint32_t* ovf, hipStream_t s);
+                            uint8_t* rk, uint8_t* rf, SegRec* rec, uint32_t* ovf, uint32_t seg_len, hipStream_t s);
 // places recorded segments and validates their codes (as launch_seg_check)
 hipError_t launch_seg_place(const SegIn* segs, uint32_t n, const SegCount* cnt, const SegRec* rec, const SegStart* st,
                             const uint64_t* seg_code, const uint64_t* seg_frag, const uint8_t* rk, const uint8_t* rf,
                             uint32_t* codes, uint64_t n_codes, uint8_t* dst, uint64_t n_frag, uint32_t slab_entries,
-                            uint32_t* err, hipStream_t s);
+                            uint32_t* err, uint32_t seg_len, hipStream_t s);
 hipError_t launch_seg_chunk(const ChunkSegs* cseg, uint32_t n, const SegCount* cnt, ChunkStat* cstat,
                             const uint64_t* code_begin, const uint64_t* frag_end, uint64_t* seg_code, uint64_t* seg_frag,
                             hipStream_t s);

@@ -199,6 +199,13 @@ void plan_free(ev_ctx* c, Plan& pl)
     dev_free(c, pl.d_err);
     pl.d_err = nullptr;
     pl.err_pending = false;
+    for (void* q : {(void*)pl.l0_ch, (void*)pl.l0_stat, (void*)pl.l0_code, (void*)pl.l0_frag, (void*)pl.l0_tree})
+        dev_free(c, q);
+    pl.l0_ch = nullptr;
+    pl.l0_stat = nullptr;
+    pl.l0_code = pl.l0_frag = nullptr;
+    pl.l0_tree = nullptr;
+    pl.l0_n = 0;
 }
 
 ev_status plan_verdict(Pop* P)
@@ -244,7 +251,11 @@ static constexpr uint64_t RECORD_MAX = (uint64_t)2 << 30;
 // per tree (its range at the level, its first input slot, where it ends);
 // chunks, segments and their numbering are made on the device, and the host
 // waits once per level, for the trees' totals that size the level's buffers.
-ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_check = false)
+// With reuse, level 0 takes over the chunks of each child's mum that its
+// crossover left intact (their codes and skeleton fragments are copied) and
+// plans only the tokens between them.
+ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_check = false,
+                     const ReuseSpec* reuse = nullptr)
 {
     hipStream_t s = x.stream;
     const int32_t M = P->M;
@@ -290,12 +301,13 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
     void *d_tl = nullptr, *d_ch = nullptr, *d_cseg = nullptr, *d_seg = nullptr, *d_fn = nullptr, *d_st = nullptr,
          *d_cnt = nullptr, *d_stat = nullptr, *d_loc = nullptr, *d_inend = nullptr, *d_sum = nullptr, *d_tb = nullptr,
          *d_cb = nullptr, *d_fe = nullptr, *d_scode = nullptr, *d_sfrag = nullptr, *d_err = nullptr, *d_rk = nullptr,
-         *d_rf = nullptr, *d_rec = nullptr;
+         *d_rf = nullptr, *d_rec = nullptr, *d_tr = nullptr, *d_src = nullptr, *d_at = nullptr, *d_l0t = nullptr;
     ev_status st = EV_OK;
     // also frees a skeleton not yet handed to a level
     auto cleanup = [&]() {
         for (void** p : {&d_tl, &d_ch, &d_cseg, &d_seg, &d_fn, &d_st, &d_cnt, &d_stat, &d_loc, &d_inend, &d_sum, &d_tb,
-                         &d_cb, &d_fe, &d_scode, &d_sfrag, &d_err, &d_rk, &d_rf, &d_rec}) {
+                         &d_cb, &d_fe, &d_scode, &d_sfrag, &d_err, &d_rk, &d_rf, &d_rec, &d_tr, &d_src, &d_at,
+                         &d_l0t}) {
             dev_free(c, *p);
             *p = nullptr;
         }
@@ -331,8 +343,17 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
     // inside a power of two does not matter)
     auto bucket = [](uint64_t len) { return len ? (uint32_t)__builtin_clz((uint32_t)len) : 32u; };
 
+    std::vector<TreeReuse> trv;  // level 0 of a reusing plan: the children's runs
+    if (reuse) {
+        const Plan& mp = reuse->mum->plan;
+        if (!mp.l0_n || (int64_t)reuse->runs->size() != M || !c->use_run) {
+            cleanup();
+            return fail(EV_EDEVICE, "internal: reuse without the mum's level-0 chunks");
+        }
+    }
     for (;;) {
         const uint64_t C = level == 0 ? C0 : C1;
+        const bool reusing = level == 0 && reuse != nullptr;
         // Segments are 256 tokens at level 0 and 64 at the skeleton levels,
         // which have few tokens and need the extra parallelism; a chunk's
         // first segment, which also emits the chunk's final flush, is a
@@ -341,9 +362,58 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         const uint32_t head = seg_len / 4;
         auto nseg = [&](uint64_t len) -> uint64_t { return len <= head ? 1 : 1 + (len - head + seg_len - 1) / seg_len; };
         tl.clear();
+        trv.clear();
         std::fill(hist, hist + EV_LEN_BUCKETS, 0u);
         uint64_t n = 0, ns = 0, tokens = 0;
-        for (int32_t t = 0; t < M; t++) {
+        for (int32_t t = 0; reusing && t < M; t++) {
+            // the child's kept chunks (from the mum's tables, checked against
+            // the child's length here so that no kernel reads past them) and
+            // its fresh tokens in chunks of C
+            const ReuseRun& r = (*reuse->runs)[t];
+            const Pop* mp_pop = reuse->mum;
+            const Plan& mp = mp_pop->plan;
+            const uint64_t len = rl[t];
+            const uint64_t n_mid = (r.mid_len + C - 1) / C;
+            const bool mum_ok =
+                r.mum < (uint32_t)mp_pop->M && r.mum_off == mp_pop->h_off[r.mum] &&
+                (r.n_suf == 0 || r.shift == (int64_t)len - (int64_t)(mp_pop->h_off[r.mum + 1] - r.mum_off));
+            const bool ok = mum_ok && (uint64_t)r.src_first + r.ks + r.n_suf <= mp.l0_n && r.n_pre <= r.ks &&
+                            (uint64_t)r.src_first + r.n_pre <= mp.l0_n && r.mid_start <= len &&
+                            r.mid_len <= len - r.mid_start && n_mid < 0xFFFFFFF0ull &&
+                            (r.n_pre > 0 || r.mid_start == 0) && (r.n_suf > 0 || r.mid_start + r.mid_len == len);
+            if (!ok) {
+                cleanup();
+                return fail(EV_EDEVICE, "internal: inconsistent reuse of tree %d's mum", t);
+            }
+            TreeReuse v{};
+            v.start = rs[t];
+            v.r = r;
+            v.chunk_first = (uint32_t)n;
+            v.seg_first = (uint32_t)ns;
+            v.tree = (uint32_t)t;
+            v.C = (uint32_t)C;
+            v.n_mid = (uint32_t)n_mid;
+            v.mid_last = n_mid ? (uint32_t)(r.mid_len - (n_mid - 1) * C) : 0u;
+            trv.push_back(v);
+            const uint64_t nc = r.n_pre + n_mid + r.n_suf;
+            TreeLvl w{};
+            w.start = rs[t];
+            w.len = len;
+            w.chunk_first = (uint32_t)n;
+            w.n_chunks = (uint32_t)nc;
+            w.seg_first = (uint32_t)ns;
+            w.C = (uint32_t)C;
+            w.tree = (uint32_t)t;
+            tl.push_back(w);
+            n += nc;
+            if (n_mid) ns += (n_mid - 1) * nseg(C) + nseg(v.mid_last);
+            tokens += len;
+            if (n > 0xFFFFFFF0ull || ns > 0xFFFFFFF0ull) {
+                cleanup();
+                return fail(EV_ECAP, "too many work items or structure segments at level %d", level);
+            }
+        }
+        for (int32_t t = 0; !reusing && t < M; t++) {
             if (!active[t]) continue;
             const uint64_t len = rl[t];
             // One work item when the tree is small, or when the last split
@@ -406,8 +476,20 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         uint64_t* d_oloc = d_cloc + n;
         uint64_t* d_floc = d_oloc + n;
         const uint64_t prev_out = pl.levels.empty() ? 0 : pl.levels.back().n_out;
-        HIPCHK(launch_plan_chunks((TreeLvl*)d_tl, nt, seg_len, head, (ChunkIn*)d_ch, (ChunkSegs*)d_cseg,
-                                  level == 0 ? (uint32_t*)d_err : nullptr, N_ERR, s));
+        if (reusing) {
+            if ((st = realloc(&d_tr, nt * sizeof(TreeReuse))) || (st = realloc(&d_src, n * sizeof(uint32_t))) ||
+                (st = realloc(&d_at, (n + EV_LEN_BUCKETS) * sizeof(uint32_t))) ||
+                (st = put(x, d_tr, trv.data(), nt * sizeof(TreeReuse)))) {
+                cleanup();
+                return st;
+            }
+            HIPCHK(launch_reuse_chunks((TreeReuse*)d_tr, nt, reuse->mum->plan.l0_ch, seg_len, head, (ChunkIn*)d_ch,
+                                       (ChunkSegs*)d_cseg, (uint32_t*)d_src, (uint32_t*)d_err, N_ERR, s));
+            HIPCHK(launch_item_sort((ChunkIn*)d_ch, (uint32_t)n, (uint32_t*)d_at + n, (uint32_t*)d_at, s));
+        } else {
+            HIPCHK(launch_plan_chunks((TreeLvl*)d_tl, nt, seg_len, head, (ChunkIn*)d_ch, (ChunkSegs*)d_cseg,
+                                      level == 0 ? (uint32_t*)d_err : nullptr, N_ERR, s));
+        }
         HIPCHK(launch_seg_build((ChunkIn*)d_ch, (ChunkSegs*)d_cseg, (uint32_t)n, seg_len, head, (SegIn*)d_seg, s));
         HIPCHK(launch_seg_fn(cur, (SegIn*)d_seg, n_seg, (SegFn*)d_fn, level == 0 ? TOK_X : TOK_REF, s));
         HIPCHK(launch_seg_scan((ChunkSegs*)d_cseg, (uint32_t)n, (SegFn*)d_fn, (SegStart*)d_st, (ChunkStat*)d_stat, s));
@@ -415,8 +497,8 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         // tokens when the recording fits, so that emission only has to place
         // them (and run the chunks' first segments); the overflow flag rides
         // in the totals' extra record.
-        const uint64_t rk_bytes = 8 * cur_len + 64 * (uint64_t)n_seg + 64;
-        const uint64_t rf_bytes = 3 * cur_len + 16 * (uint64_t)n_seg + 64;
+        const uint64_t rk_bytes = rec_kinds_stride(seg_len) * n_seg + 64;
+        const uint64_t rf_bytes = rec_frags_stride(seg_len) * n_seg + 64;
         bool record = c->use_record && rk_bytes + rf_bytes <= RECORD_MAX;
         uint32_t* d_ovf = &((TreeSum*)d_sum)[nt].bad;
         if (record && ((st = realloc(&d_rk, rk_bytes)) || (st = realloc(&d_rf, rf_bytes)) ||
@@ -436,9 +518,11 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         HIPCHK(launch_fill_u32((uint32_t*)((TreeSum*)d_sum + nt), sizeof(TreeSum) / 4, 0u, s));
         HIPCHK(launch_seg_count(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (SegCount*)d_cnt,
                                 record ? (uint8_t*)d_rk : nullptr, record ? (uint8_t*)d_rf : nullptr,
-                                record ? (SegRec*)d_rec : nullptr, d_ovf, s));
+                                record ? (SegRec*)d_rec : nullptr, d_ovf, seg_len, s));
         HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, (uint32_t)n, (SegCount*)d_cnt, (ChunkStat*)d_stat, nullptr, nullptr,
                                 nullptr, nullptr, s));
+        if (reusing)
+            HIPCHK(launch_reuse_stats((uint32_t*)d_src, (uint32_t)n, reuse->mum->plan.l0_stat, (ChunkStat*)d_stat, s));
         HIPCHK(launch_plan_trees((TreeLvl*)d_tl, nt, (ChunkStat*)d_stat, (uint32_t)level, prev_out, d_cloc, d_oloc,
                                  d_floc, (uint32_t*)d_inend, (TreeSum*)d_sum, s));
         HIPCHK(launch_plan_bases((TreeLvl*)d_tl, nt, (TreeSum*)d_sum, (TreeBase*)d_tb, s));
@@ -545,7 +629,8 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         HIPCHK(launch_plan_items((ChunkIn*)d_ch, (uint32_t)n, (TreeBase*)d_tb, d_cloc, d_oloc, d_floc,
                                  (uint32_t*)d_inend, (uint32_t*)((uint8_t*)d_tl + tl_bytes), (uint64_t*)d_cb,
                                  (uint64_t*)d_fe, run_items ? LL.d_run : nullptr, run_items ? nullptr : LL.d_chunks,
-                                 run_items ? LL.codes + sc : nullptr, any ? d_next + sf : nullptr, s));
+                                 run_items ? LL.codes + sc : nullptr, any ? d_next + sf : nullptr,
+                                 reusing ? (uint32_t*)d_at : nullptr, s));
         if (any || run_items) {
             HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, (uint32_t)n, (SegCount*)d_cnt, (ChunkStat*)d_stat,
                                     (uint64_t*)d_cb, (uint64_t*)d_fe, (uint64_t*)d_scode, (uint64_t*)d_sfrag, s));
@@ -554,7 +639,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
                 HIPCHK(launch_seg_place((SegIn*)d_seg, n_seg, (SegCount*)d_cnt, (SegRec*)d_rec, (SegStart*)d_st,
                                         (uint64_t*)d_scode, (uint64_t*)d_sfrag, (uint8_t*)d_rk, (uint8_t*)d_rf,
                                         run_items ? LL.codes : nullptr, sc, d_next, sf, LL.slab_entries,
-                                        (uint32_t*)d_err + 2 * level, s));
+                                        (uint32_t*)d_err + 2 * level, seg_len, s));
             } else {
                 HIPCHK(launch_seg_emit(cur, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode,
                                        (uint64_t*)d_sfrag, d_next, run_items ? LL.codes : nullptr, s));
@@ -562,6 +647,30 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
                     HIPCHK(launch_seg_check(LL.codes, (SegIn*)d_seg, n_seg, (SegStart*)d_st, (uint64_t*)d_scode,
                                             (SegCount*)d_cnt, LL.slab_entries, (uint32_t*)d_err + 2 * level, s));
             }
+        }
+        if (reusing) {
+            const Plan& mp = reuse->mum->plan;
+            HIPCHK(launch_reuse_copy((uint32_t*)d_src, (uint32_t)n, (ChunkStat*)d_stat, (uint64_t*)d_cb,
+                                     (uint64_t*)d_fe, mp.l0_code, mp.l0_frag, mp.levels[0].codes,
+                                     mp.levels.size() > 1 ? mp.levels[1].seq : nullptr, LL.codes, any ? d_next : nullptr,
+                                     s));
+        }
+        if (level == 0 && run_items && any) {
+            // level 0's chunks stay with the plan (for children that reuse them)
+            std::vector<L0Tree> l0t((size_t)std::max(1, M), L0Tree{0, 0});
+            for (uint32_t i = 0; i < nt; i++) l0t[tl[i].tree] = L0Tree{tl[i].chunk_first, tl[i].n_chunks};
+            if ((st = dev_alloc(c, l0t.size() * sizeof(L0Tree), &d_l0t)) ||
+                (st = put(x, d_l0t, l0t.data(), l0t.size() * sizeof(L0Tree)))) {
+                cleanup();
+                return st;
+            }
+            pl.l0_n = (uint32_t)n;
+            pl.l0_ch = (ChunkIn*)d_ch;
+            pl.l0_stat = (ChunkStat*)d_stat;
+            pl.l0_code = (uint64_t*)d_cb;
+            pl.l0_frag = (uint64_t*)d_fe;
+            pl.l0_tree = (L0Tree*)d_l0t;
+            d_ch = d_stat = d_cb = d_fe = d_l0t = nullptr;
         }
         if (!any) {
             // where each tree's value is, for the fitness kernel
@@ -618,7 +727,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
 // Make a population from device bytes (takes ownership of d_bytes, also on
 // failure).
 ev_status pop_build(ev_ctx* c, Exec& x, uint8_t* d_bytes, const std::vector<uint64_t>& h_off, Pop** out, int32_t* bad,
-                    uint64_t* d_off, bool defer_check)
+                    uint64_t* d_off, bool defer_check, const ReuseSpec* reuse)
 {
     *out = nullptr;
     Pop* P = new Pop();
@@ -633,7 +742,7 @@ ev_status pop_build(ev_ctx* c, Exec& x, uint8_t* d_bytes, const std::vector<uint
         if ((st = put(x, P->d_off, h_off.data(), h_off.size() * sizeof(uint64_t))) != EV_OK) { pop_free(c, P); return st; }
     }
     if ((st = dev_alloc(c, (size_t)std::max(1, P->M) * sizeof(float), (void**)&P->d_fit)) != EV_OK) { pop_free(c, P); return st; }
-    if ((st = plan_build(c, x, P, bad, defer_check)) != EV_OK) { pop_free(c, P); return st; }
+    if ((st = plan_build(c, x, P, bad, defer_check, reuse)) != EV_OK) { pop_free(c, P); return st; }
     *out = P;
     return EV_OK;
 }
@@ -1044,6 +1153,15 @@ ev_status crossover_build_dev(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const in
     // the offsets, then the number capped, the longest child and the number
     // of 4 KiB copy pieces (each child's first piece follows on the device)
     std::vector<uint64_t> off((size_t)n + 4, 0);
+    // the mum's level-0 chunks each child keeps (read with the offsets)
+    const bool reuse_ok = c->use_reuse && c->use_run && mums->plan.l0_n > 0 && n > 0;
+    std::vector<ReuseRun> runs;
+    void* d_runs = nullptr;
+    if (reuse_ok && (st = dev_alloc(c, (size_t)n * sizeof(ReuseRun), &d_runs)) != EV_OK) {
+        cleanup();
+        dev_free(c, d_off);
+        return st;
+    }
     if (n > 0) {
         uint64_t* qb = (uint64_t*)d_b;
         uint64_t* qp = (uint64_t*)d_qp;
@@ -1057,11 +1175,19 @@ ev_status crossover_build_dev(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const in
         }
         HIPCHK(launch_xo_plan(mums->d_off, dads->d_off, d_mum, d_dad, d_p, d_q, ends, (uint32_t)n, cap, (XoPlan*)d_plan,
                               d_off, s));
-        if ((st = get(x, off.data(), d_off, ((size_t)n + 4) * 8)) || (st = sync(x))) {
+        if (reuse_ok) {
+            runs.resize((size_t)n);
+            HIPCHK(launch_reuse_runs((XoPlan*)d_plan, d_mum, mums->plan.l0_tree, mums->plan.l0_ch, (uint32_t)n,
+                                     (ReuseRun*)d_runs, s));
+            st = get(x, runs.data(), d_runs, (size_t)n * sizeof(ReuseRun));
+        }
+        if (st || (st = get(x, off.data(), d_off, ((size_t)n + 4) * 8)) || (st = sync(x))) {
             cleanup();
+            dev_free(c, d_runs);
             dev_free(c, d_off);
             return st;
         }
+        dev_free(c, d_runs);
     } else if ((st = put(x, d_off, off.data(), 8)) != EV_OK) {
         cleanup();
         dev_free(c, d_off);
@@ -1081,7 +1207,8 @@ ev_status crossover_build_dev(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const in
     // later use of it is ordered after the copy on the context's one stream
     cleanup();
     if (n_capped) *n_capped = (int32_t)capped;
-    return pop_build(c, x, d_child, off, out, nullptr, d_off, defer_check);
+    const ReuseSpec spec{mums, &runs};
+    return pop_build(c, x, d_child, off, out, nullptr, d_off, defer_check, reuse_ok ? &spec : nullptr);
 }
 
 // The same from host arrays, checked against the parents first.
@@ -1487,6 +1614,7 @@ ev_status ev_set_tuning(ev_ctx* c, uint32_t chunk, uint32_t chunk_hi, uint32_t l
     c->use_run = c->run_ok && (flags & EV_TUNE_NO_REGSTACK) == 0;
     c->test_fail_check = (flags & EV_TUNE_TEST_FAIL_CHECK) != 0;
     c->use_record = (flags & EV_TUNE_NO_RECORD) == 0;
+    c->use_reuse = (flags & EV_TUNE_NO_REUSE) == 0;
     if (chunk) c->chunk = chunk;
     if (chunk_hi) c->chunk_hi = chunk_hi;
     if (lds_depth) c->lds_depth = (int)lds_depth;

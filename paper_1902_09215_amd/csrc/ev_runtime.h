@@ -58,6 +58,25 @@ struct Plan {
     uint32_t chunk = 0;
     int D = 64;
     uint64_t chunks_total = 0, slots_total = 0, max_stack = 0, bytes = 0;
+    // Level 0's chunks, kept when the level was planned for the
+    // register-stack kernel and has a next level, so that children can take
+    // over the ones crossover leaves intact: per chunk (token order) its
+    // record, totals, first code and fragment end in levels[1].seq; per tree
+    // its range of chunks.
+    uint32_t l0_n = 0;
+    ChunkIn* l0_ch = nullptr;
+    ChunkStat* l0_stat = nullptr;
+    uint64_t* l0_code = nullptr;
+    uint64_t* l0_frag = nullptr;
+    L0Tree* l0_tree = nullptr;
+};
+
+struct Pop;
+
+// Children planned from their mum's level 0 (one ReuseRun per child).
+struct ReuseSpec {
+    const Pop* mum;
+    const std::vector<ReuseRun>* runs;
 };
 
 // Intermediate results of one population for one case table.
@@ -140,6 +159,7 @@ struct ev_ctx {
     bool run_ok = true;   // the register-stack kernel can run here (probed at creation)
     bool test_fail_check = false;  // EV_TUNE_TEST_FAIL_CHECK
     bool use_record = true;        // the count pass records codes for emission (EV_TUNE_NO_RECORD clears it)
+    bool use_reuse = true;         // children take over their mums' level-0 chunks (EV_TUNE_NO_REUSE clears it)
     uint32_t* d_flag = nullptr;  // the probe's flag word
     uint32_t chunk = 6144;     // tokens per work item at level 0
     uint32_t chunk_hi = 0;     // at the skeleton levels (0: twice chunk)
@@ -201,8 +221,10 @@ void pop_free(ev_ctx* c, Pop* P);
 // d_off: the offsets already on the device (adopted), or nullptr to upload h_off
 // defer_check: leave the last plan level's validation verdict to the device
 // and to the first evaluation (Plan::err_pending)
+// reuse: the children's level 0 taken over from their mums' where it can be
 ev_status pop_build(ev_ctx* c, Exec& x, uint8_t* d_bytes, const std::vector<uint64_t>& h_off, Pop** out,
-                    int32_t* bad, uint64_t* d_off = nullptr, bool defer_check = false);
+                    int32_t* bad, uint64_t* d_off = nullptr, bool defer_check = false,
+                    const ReuseSpec* reuse = nullptr);
 // after a sync that followed eval_enqueue(P): the deferred verdict, if any
 ev_status plan_verdict(Pop* P);
 ev_pop pop_register(ev_ctx* c, Pop* P);

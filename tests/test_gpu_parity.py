@@ -278,6 +278,125 @@ def test_generations_match_oracle(ev):
             pop, buf, off = kids, wbuf, woff
 
 
+def crossover_cases(buf, off, C, rng):
+    """Crossover points around a mum's level-0 chunk boundaries (chunks of C
+    tokens from the tree's root): p on a boundary and just before one, p
+    whose subtree ends just before or on a boundary, the root (nothing
+    kept), leaves, q = 0 (the whole dad inserted), random points."""
+    sizes = np.diff(off).astype(np.int64)
+    big = [t for t in range(sizes.size) if sizes[t] > 4 * C]
+    mum, dad, p, q = [], [], [], []
+    for m in big[:12]:
+        tree = buf[off[m]:off[m + 1]]
+        ends = np.array([oracle.subtree_end(tree, k) for k in range(tree.size)])
+        pts = {0, C, C - 1, 2 * C, 2 * C + 1, int(tree.size) - 1}
+        for want in (C - 1, 0, 1):  # subtree ending just before / on / after a boundary
+            hit = np.nonzero(((ends + 1) % C == (want + 1) % C) & (np.arange(tree.size) > 0))[0]
+            if hit.size:
+                pts.add(int(rng.choice(hit)))
+        leaves = np.nonzero(tree == X)[0]
+        pts.add(int(rng.choice(leaves)))
+        pts.update(int(v) for v in rng.integers(0, tree.size, 3))
+        for pp in sorted(v for v in pts if 0 <= v < tree.size):
+            d = int(rng.integers(0, sizes.size))
+            qq = 0 if rng.random() < 0.2 else int(rng.integers(0, sizes[d]))
+            mum.append(m), dad.append(d), p.append(pp), q.append(qq)
+    return (np.array(mum, np.int32), np.array(dad, np.int32), np.array(p, np.uint64), np.array(q, np.uint64))
+
+
+@pytest.mark.parametrize("chunk", [64, 300])
+def test_children_reuse_their_mums_chunks(ev, chunk):
+    # A child keeps its mum's level-0 work items that crossover leaves intact
+    # (their codes and skeleton fragments are copied) and plans only the
+    # tokens between them.  Around every kind of chunk boundary, and for
+    # children over the size cap (copies of their mum), the children's bytes,
+    # per-case values and fitness equal the oracle's and a plan from scratch.
+    x, y = workloads.cases(48)
+    rng = np.random.default_rng(chunk)
+    sizes = workloads.loguniform_sizes(61, 40, 3, 6000)
+    buf, off = workloads.random_population(61, sizes)
+    mum, dad, p, q = crossover_cases(buf, off, chunk, rng)
+    print(f"chunk {chunk}: {mum.size} children", flush=True)
+    kids = [oracle.crossover(buf[off[m]:off[m + 1]], buf[off[d]:off[d + 1]], int(pp), int(qq))
+            for m, d, pp, qq in zip(mum, dad, p, q)]
+    koff = workloads.offsets_from_sizes([k.size for k in kids])
+    kbuf = np.concatenate(kids)
+    want_fit, want_pc = oracle.eval_population(kbuf, koff, x, y, threads=8, per_case=True)
+    results = {}
+    for flags in (0, ev.EV_TUNE_NO_REUSE, ev.EV_TUNE_NO_RECORD):
+        with ev.Context(x, y) as c:
+            ev.ev_set_tuning(c.ctx, chunk, 0, flags)
+            pop = c.load(buf, off)
+            k, capped = ev.ev_crossover(c.ctx, pop, pop, mum, dad, p, q)
+            assert capped == 0
+            gb, go = ev.ev_get_trees(c.ctx, k)
+            assert np.array_equal(go, koff) and np.array_equal(gb, kbuf)
+            fit, pc = c.eval(k, per_case=True)
+            assert_same(pc, want_pc, f"children per-case flags={flags}")
+            assert_same(fit, want_fit, f"children fitness flags={flags}")
+            # children over the cap are copies of their mums: all kept
+            cap = int(np.diff(koff).min()) - 1
+            k2, capped2 = ev.ev_crossover(c.ctx, pop, pop, mum, dad, p, q, size_cap=max(cap, 1))
+            gb2, go2 = ev.ev_get_trees(c.ctx, k2)
+            f2, pc2 = c.eval(k2, per_case=True)
+            results[flags] = (gb2, go2, f2, pc2, capped2)
+            # and the children of children (non-uniform chunks in the mum)
+            j = np.arange(mum.size, dtype=np.int32)
+            ksz = np.diff(koff).astype(np.int64)
+            p3 = np.array([int(rng.integers(0, s)) if s > 1 else 0 for s in ksz], np.uint64)
+            q3 = np.array([int(rng.integers(0, ksz[(i + 1) % ksz.size])) for i in range(ksz.size)], np.uint64)
+            d3 = ((j + 1) % mum.size).astype(np.int32)
+            g3, _ = ev.ev_crossover(c.ctx, k, k, j, d3, p3, q3)
+            gb3, go3 = ev.ev_get_trees(c.ctx, g3)
+            f3, pc3 = c.eval(g3, per_case=True)
+            want3 = [oracle.crossover(kids[a], kids[b], int(pp), int(qq)) for a, b, pp, qq in zip(j, d3, p3, q3)]
+            w3off = workloads.offsets_from_sizes([w.size for w in want3])
+            w3buf = np.concatenate(want3)
+            assert np.array_equal(go3, w3off) and np.array_equal(gb3, w3buf)
+            wf3, wpc3 = oracle.eval_population(w3buf, w3off, x, y, threads=8, per_case=True)
+            assert_same(pc3, wpc3, f"grandchildren per-case flags={flags}")
+            assert_same(f3, wf3, f"grandchildren fitness flags={flags}")
+    a, b = results[0], results[ev.EV_TUNE_NO_REUSE]
+    assert a[4] == b[4] == mum.size
+    mums = [buf[off[m]:off[m + 1]] for m in mum]
+    moff = workloads.offsets_from_sizes([t.size for t in mums])
+    mbuf = np.concatenate(mums)
+    for r in results.values():
+        assert np.array_equal(r[0], mbuf) and np.array_equal(r[1], moff)
+    wf, wpc = oracle.eval_population(mbuf, moff, x, y, threads=8, per_case=True)
+    for flags, r in results.items():
+        assert_same(r[2], wf, f"capped children fitness flags={flags}")
+        assert_same(r[3], wpc, f"capped children per-case flags={flags}")
+
+
+def test_generations_reusing_chunks_match_oracle(ev):
+    # Generations of trees spanning many 64-token work items: every child
+    # plan takes over its mum's intact chunks, and the mum's own chunks came
+    # from its mum's, so chunk layouts grow uneven over the generations.
+    x, y = workloads.cases(48)
+    sizes = workloads.loguniform_sizes(62, 48, 200, 3000)
+    buf, off = workloads.random_population(62, sizes)
+    seed, gens, cap = 777, 25, 15_000_000
+    with ev.Context(x, y) as c:
+        ev.ev_set_tuning(c.ctx, 64)
+        pop = c.load(buf, off)
+        fit, _ = c.eval(pop)
+        wfit = oracle.eval_population(buf, off, x, y, threads=8)
+        assert_same(fit, wfit, "gen 0")
+        for g in range(gens):
+            kids, capped = ev.ev_generation(c.ctx, pop, seed, g, 2, cap)
+            wbuf, woff, wcap = oracle.generation(buf, off, wfit, 2, seed, g, cap)
+            gbuf, goff = ev.ev_get_trees(c.ctx, kids)
+            assert capped == wcap
+            assert np.array_equal(goff, woff) and np.array_equal(gbuf, wbuf), f"gen {g} trees"
+            fit, pc = c.eval(kids, per_case=True)
+            wfit, wpc = oracle.eval_population(wbuf, woff, x, y, threads=8, per_case=True)
+            assert_same(pc, wpc, f"gen {g + 1} per-case")
+            assert_same(fit, wfit, f"gen {g + 1} fitness")
+            ev.ev_free_pop(c.ctx, pop)
+            pop, buf, off = kids, wbuf, woff
+
+
 def test_generations_tournament_7_population_500(ev):
     # Table 1's tournament size (7) on a population of 500: trees, fitness and
     # hits bit-identical to the oracle's generations.
