@@ -173,6 +173,28 @@ ev_status ev_crossover(ev_ctx *ctx, ev_pop mums_pop, ev_pop dads_pop, const int3
 ev_status ev_generation(ev_ctx *ctx, ev_pop parents, const float *fitness, uint64_t seed, uint64_t gen,
                         int32_t tournament, uint64_t size_cap, ev_pop *out_children, int32_t *n_capped);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ev_eval_fitness of a population with device outputs (as with
+ * EV_OUT_DEVICE) that allocates nothing.  The work counters, the plan
+ * levels' intermediate result slots and the interpreter's spill slabs live
+ * in a static device array of EV_STATIC_SCRATCH_BYTES, which each device
+ * the library runs on holds until the process ends; the spill slabs take
+ * what the result slots leave, and a level runs on as many waves as have a
+ * slab there.  fitness[n_trees] (required), per_case[n_trees * N] and
+ * hits[n_trees] (nullable) are device pointers; the call returns once the
+ * work is queued on the context's stream and does not change the fitness
+ * kept with the population.  Every call on a device shares that device's
+ * array, and it keeps the last call's contents: calls on one context are
+ * ordered by its stream, but calls that overlap on one device from
+ * different contexts race.  Errors: EV_EINVAL (bad arguments, or a
+ * population whose plan's validation verdict is still to be read: a child of
+ * ev_generation not yet evaluated with ev_eval_fitness), EV_ENOTFOUND,
+ * EV_ECAP (the result slots need more than the array). */
+#define EV_STATIC_SCRATCH_BYTES 0x4000000u /* 64 MiB */
+ev_status ev_eval_fitness_static(ev_ctx *ctx, ev_pop pop, int32_t table, float *fitness, float *per_case,
+                                 int32_t *hits);
+
 /* ---- serving: continuously batched evaluation / crossover requests ---- */
 
 enum { EV_JOB_EVAL = 0, EV_JOB_CROSSOVER = 1 };

@@ -22,13 +22,14 @@ LIB_PATH = os.path.join(_HERE, "libev.so")
 EV_OK, EV_EINVAL, EV_EMALFORMED, EV_ENOMEM, EV_ECAP, EV_EBUSY, EV_ENOTFOUND, EV_EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 EV_ADD, EV_SUB, EV_MUL, EV_DIV, EV_X = 0, 1, 2, 3, 4
 EV_DEVICE_PTR, EV_OUT_DEVICE = 0x1, 0x2
+EV_STATIC_SCRATCH_BYTES = 0x4000000
 EV_JOB_EVAL, EV_JOB_CROSSOVER = 0, 1
 
 EXPORTS = [
     "ev_create", "ev_add_cases", "ev_destroy", "ev_last_error", "ev_load_trees", "ev_pop_info",
     "ev_get_trees", "ev_free_pop", "ev_eval_fitness", "ev_crossover", "ev_generation", "ev_submit",
     "ev_poll", "ev_wait", "ev_result", "ev_job_timing", "ev_get_plan_info", "ev_get_level_info", "ev_set_tuning",
-    "ev_autotune", "ev_last_level_times", "ev_last_timing",
+    "ev_autotune", "ev_last_level_times", "ev_last_timing", "ev_eval_fitness_static",
 ]
 
 
@@ -107,6 +108,7 @@ def load_library(path: str = LIB_PATH):
         "ev_autotune": [P, i32, i32, i32, ctypes.POINTER(u32), ctypes.POINTER(ctypes.c_float)],
         "ev_last_level_times": [P, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)],
         "ev_last_timing": [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+        "ev_eval_fitness_static": [P, i32, i32, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -241,6 +243,12 @@ def ev_eval_fitness(ctx, pop, table: int = 0, per_case: bool = False, out=None, 
     _check(_lib.ev_eval_fitness(ctx, pop, table, _ptr(fit), _ptr(pc), _ptr(h), 0))
     res = (fit[:n], pc[:n] if pc is not None else None)
     return res + (h[:n],) if hits else res
+
+
+def ev_eval_fitness_static(ctx, pop, out, table: int = 0, out_per_case=None, out_hits=None):
+    """ev_eval_fitness into device tensors with no allocation (see ev.h)."""
+    _check(_lib.ev_eval_fitness_static(ctx, pop, table, _ptr(out), _ptr(out_per_case), _ptr(out_hits)))
+    return out
 
 
 _table_sizes: dict = {}

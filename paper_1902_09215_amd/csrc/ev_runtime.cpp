@@ -1013,6 +1013,115 @@ ev_status rescache_build(ev_ctx* c, Exec& x, Pop* P, int32_t table, ResCache** o
     return EV_OK;
 }
 
+// The buffers an evaluation's kernels use besides the plan: the work
+// counters (two per level), each level's result slots (with EV_RING rows in
+// front of the pointer) and the spill slabs of the waves.
+struct EvalBufs {
+    uint32_t* counters = nullptr;
+    std::vector<float*> res;
+    float* slab = nullptr;
+    size_t slab_bytes = 0;
+};
+
+// Spill-slab bytes one wave of a level's interpreter needs (0: none).
+static size_t slab_per_wave(const Level& L, int D)
+{
+    if (L.n_run) return L.slab_entries ? (size_t)L.slab_entries * 64 * sizeof(float) : 0;
+    if (L.n_chunks && L.max_m + 16 > (uint32_t)D) return (size_t)(L.max_m + 16) * 64 * sizeof(float);
+    return 0;
+}
+
+// Queue the kernels of one evaluation of P on x's stream.  A level's grid is
+// cut to the waves whose spill slabs fit b.slab_bytes.
+static ev_status eval_launch(ev_ctx* c, Exec& x, Pop* P, const CaseTable& ct, const EvalBufs& b, float* d_fit,
+                             float* d_per_case, int32_t* d_hits, bool timed)
+{
+    const int32_t N = ct.N;
+    const uint32_t n_cb = (uint32_t)((N + 63) / 64);
+    const int D = P->plan.D;
+    const size_t nl = P->plan.levels.size();
+    const uint32_t grid_max = (uint32_t)c->grid_eval[D == 128 ? 1 : 0];
+    auto grid_for = [&](const Level& L, uint64_t items, uint32_t grid) -> uint32_t {
+        uint64_t g = std::min<uint64_t>(grid, items);
+        const size_t w = slab_per_wave(L, D);
+        if (w) g = std::min<uint64_t>(g, b.slab_bytes / w);
+        return (uint32_t)g;
+    };
+    for (const Level& L : P->plan.levels)
+        if ((L.n_run || L.n_chunks) && grid_for(L, 1, 1) == 0)
+            return fail(EV_ECAP, "no room for one wave's spill slab (%zu bytes)", slab_per_wave(L, D));
+    hipStream_t s = x.stream;
+    if (timed) {
+        while (x.evl.size() < nl) {
+            hipEvent_t e = nullptr;
+            HIPCHK(hipEventCreate(&e));
+            x.evl.push_back(e);
+        }
+        x.n_levels_timed = (uint32_t)nl;
+    }
+    if (timed) HIPCHK(hipEventRecord(x.ev0, s));
+    HIPCHK(launch_fill_u32(b.counters, (uint32_t)(2 * nl), 0u, s));
+    for (size_t li = 0; li < nl; li++) {
+        const Level& L = P->plan.levels[li];
+        if (timed && li == 0) HIPCHK(hipEventRecord(x.evi0, s));
+        if (L.n_run) {
+            RunArgs r{};
+            r.codes = L.codes;
+            r.chunks = L.d_run;
+            r.n_items = L.n_run * n_cb;
+            r.n_cb = n_cb;
+            r.counter = b.counters + nl + li;
+            r.x = ct.d_x;
+            r.N = N;
+            r.rowb = (uint32_t)N * 4u;
+            r.in_res = li ? b.res[li - 1] : nullptr;
+            r.refs = li ? 1u : 0u;
+            r.out_res = b.res[li];
+            r.slab = b.slab;
+            r.slab_entries = L.slab_entries;
+            r.flag = c->d_flag;
+            r.verdict = P->plan.d_err ? P->plan.d_err + 2 * li : nullptr;
+            HIPCHK(launch_run(r, grid_for(L, r.n_items, (uint32_t)c->grid_run), s));
+        }
+        if (L.n_chunks == 0) {
+            if (timed && li == 0) HIPCHK(hipEventRecord(x.evi1, s));
+            if (timed) HIPCHK(hipEventRecord(x.evl[li], s));
+            continue;
+        }
+        EvalArgs a;
+        a.seq = L.seq;
+        a.chunks = L.d_chunks;
+        a.n_items = L.n_chunks * n_cb;
+        a.n_cb = n_cb;
+        a.counter = b.counters + li;
+        a.x = ct.d_x;
+        a.N = N;
+        a.gstack_entries = L.max_m + 16;
+        a.in_res = li ? b.res[li - 1] : nullptr;
+        a.out_res = b.res[li];
+        a.gstack = b.slab;
+        HIPCHK(launch_eval(D, a, grid_for(L, a.n_items, grid_max), s));
+        if (timed && li == 0) HIPCHK(hipEventRecord(x.evi1, s));
+        if (timed) HIPCHK(hipEventRecord(x.evl[li], s));
+    }
+    FitArgs fa = {};
+    for (size_t li = 0; li < nl; li++) {
+        fa.res[li] = b.res[li];
+        fa.n_out[li] = P->plan.levels[li].n_out;
+    }
+    fa.n_levels = (uint32_t)nl;
+    fa.fin = P->plan.d_fin;
+    fa.y = ct.d_y;
+    fa.N = N;
+    fa.M = (uint32_t)P->M;
+    fa.fit = d_fit;
+    fa.per_case = d_per_case;
+    fa.hits = d_hits;
+    HIPCHK(launch_fitness(fa, s));
+    if (timed) HIPCHK(hipEventRecord(x.ev1, s));
+    return EV_OK;
+}
+
 // Queue the evaluation of P on table on c->stream; fit/per_case are device
 // pointers (per_case nullable).
 ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, float* d_per_case, bool timed,
@@ -1035,93 +1144,49 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
     if ((st = rescache_get(c, x, P, table, &rc)) != EV_OK) return st;
     const size_t nl = P->plan.levels.size();
     if ((st = ensure_counters(c, x, 2 * nl)) != EV_OK) return st;
-    // global stack slabs for levels whose stacks can outgrow the LDS ring
+    // spill slabs for every wave of each level's grid
     const uint32_t grid_max = (uint32_t)c->grid_eval[D == 128 ? 1 : 0];
     size_t need = 0;
     for (auto& L : P->plan.levels) {
-        if (L.n_chunks && L.max_m + 16 > (uint32_t)D) {
-            const uint64_t items = (uint64_t)L.n_chunks * n_cb;
-            const uint32_t grid = (uint32_t)std::min<uint64_t>(grid_max, items);
-            need = std::max(need, (size_t)grid * (L.max_m + 16) * 64 * sizeof(float));
-        }
-        if (L.n_run && L.slab_entries) {
-            const uint64_t items = (uint64_t)L.n_run * n_cb;
-            const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)c->grid_run, items);
-            need = std::max(need, (size_t)grid * L.slab_entries * 64 * sizeof(float));
-        }
+        const uint64_t items = (uint64_t)(L.n_run + L.n_chunks) * n_cb;
+        const uint64_t grid = std::min<uint64_t>(L.n_run ? (uint64_t)c->grid_run : grid_max, items);
+        need = std::max(need, (size_t)grid * slab_per_wave(L, D));
     }
     if ((st = ensure_gstack(c, x, need)) != EV_OK) return st;
-    hipStream_t s = x.stream;
-    if (timed) {
-        while (x.evl.size() < nl) {
-            hipEvent_t e = nullptr;
-            HIPCHK(hipEventCreate(&e));
-            x.evl.push_back(e);
-        }
-        x.n_levels_timed = (uint32_t)nl;
+    EvalBufs b;
+    b.counters = x.d_counters;
+    b.res = rc->res;
+    b.slab = x.d_gstack;
+    b.slab_bytes = x.gstack_bytes;
+    return eval_launch(c, x, P, ct, b, d_fit, d_per_case, d_hits, timed);
+}
+
+// The same with every buffer of the kernels carved from [scratch, scratch +
+// bytes) and no allocation: the population's plan must be settled (its
+// validation verdict read), the outputs are device pointers.
+ev_status eval_in_scratch(ev_ctx* c, Pop* P, int32_t table, float* d_fit, float* d_per_case, int32_t* d_hits,
+                          uint8_t* scratch, size_t bytes)
+{
+    if (P->plan.err_pending)
+        return fail(EV_EINVAL, "population not evaluated yet: its plan's validation verdict is still to be read");
+    CaseTable ct;
+    if (!table_get(c, table, &ct)) return fail(EV_EINVAL, "no case table %d", table);
+    const size_t nl = P->plan.levels.size();
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    size_t at = up(2 * nl * sizeof(uint32_t));
+    EvalBufs b;
+    b.counters = (uint32_t*)scratch;
+    for (const Level& L : P->plan.levels) {
+        const size_t rows = (size_t)std::max<uint32_t>(L.n_out, 1) + EV_RING;
+        const size_t need = rows * (size_t)ct.N * sizeof(float);
+        if (at + need > bytes)
+            return fail(EV_ECAP, "the population's result slots need more than the %zu bytes of static scratch", bytes);
+        b.res.push_back((float*)(scratch + at) + (size_t)EV_RING * ct.N);
+        at = up(at + need);
     }
-    if (timed) HIPCHK(hipEventRecord(x.ev0, s));
-    HIPCHK(launch_fill_u32(x.d_counters, (uint32_t)(2 * nl), 0u, s));
-    for (size_t li = 0; li < nl; li++) {
-        const Level& L = P->plan.levels[li];
-        if (timed && li == 0) HIPCHK(hipEventRecord(x.evi0, s));
-        if (L.n_run) {
-            RunArgs r{};
-            r.codes = L.codes;
-            r.chunks = L.d_run;
-            r.n_items = L.n_run * n_cb;
-            r.n_cb = n_cb;
-            r.counter = x.d_counters + nl + li;
-            r.x = ct.d_x;
-            r.N = N;
-            r.rowb = (uint32_t)N * 4u;
-            r.in_res = li ? rc->res[li - 1] : nullptr;
-            r.refs = li ? 1u : 0u;
-            r.out_res = rc->res[li];
-            r.slab = x.d_gstack;
-            r.slab_entries = L.slab_entries;
-            r.flag = c->d_flag;
-            r.verdict = P->plan.d_err ? P->plan.d_err + 2 * li : nullptr;
-            HIPCHK(launch_run(r, (uint32_t)std::min<uint64_t>((uint64_t)c->grid_run, r.n_items), s));
-        }
-        if (L.n_chunks == 0) {
-            if (timed && li == 0) HIPCHK(hipEventRecord(x.evi1, s));
-            if (timed) HIPCHK(hipEventRecord(x.evl[li], s));
-            continue;
-        }
-        EvalArgs a;
-        a.seq = L.seq;
-        a.chunks = L.d_chunks;
-        a.n_items = L.n_chunks * n_cb;
-        a.n_cb = n_cb;
-        a.counter = x.d_counters + li;
-        a.x = ct.d_x;
-        a.N = N;
-        a.gstack_entries = L.max_m + 16;
-        a.in_res = li ? rc->res[li - 1] : nullptr;
-        a.out_res = rc->res[li];
-        a.gstack = x.d_gstack;
-        const uint32_t grid = (uint32_t)std::min<uint64_t>(grid_max, a.n_items);
-        HIPCHK(launch_eval(D, a, grid, s));
-        if (timed && li == 0) HIPCHK(hipEventRecord(x.evi1, s));
-        if (timed) HIPCHK(hipEventRecord(x.evl[li], s));
-    }
-    FitArgs fa = {};
-    for (size_t li = 0; li < nl; li++) {
-        fa.res[li] = rc->res[li];
-        fa.n_out[li] = P->plan.levels[li].n_out;
-    }
-    fa.n_levels = (uint32_t)nl;
-    fa.fin = P->plan.d_fin;
-    fa.y = ct.d_y;
-    fa.N = N;
-    fa.M = (uint32_t)P->M;
-    fa.fit = d_fit;
-    fa.per_case = d_per_case;
-    fa.hits = d_hits;
-    HIPCHK(launch_fitness(fa, s));
-    if (timed) HIPCHK(hipEventRecord(x.ev1, s));
-    return EV_OK;
+    b.slab = (float*)(scratch + std::min(at, bytes));
+    b.slab_bytes = at < bytes ? bytes - at : 0;
+    return eval_launch(c, c->main, P, ct, b, d_fit, d_per_case, d_hits, false);
 }
 
 // ----------------------------------------------------------- crossover
@@ -1292,6 +1357,7 @@ ev_status ev_create(ev_ctx** out, int device, const float* x, const float* y, in
     ev_status st = ev_add_cases(c, x, y, n_cases, &tid);
     if (st == EV_OK) st = dev_alloc(c, 256, (void**)&c->d_flag);
     if (st == EV_OK) st = run_probe(c);
+    if (st == EV_OK) st = static_scratch_init(device);
     if (st != EV_OK) { ev_destroy(c); return st; }
     *out = c;
     return EV_OK;

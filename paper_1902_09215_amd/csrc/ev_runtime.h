@@ -238,6 +238,12 @@ void pop_release(ev_ctx* c, Pop* P);
 // plan_verdict(P); otherwise it is checked here, with a sync of its own
 ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, float* d_per_case, bool timed,
                        int32_t* d_hits, bool verdict_at_sync = false);
+// Look up this device's copy of the static scratch array (device current).
+ev_status static_scratch_init(int device);
+// eval_enqueue on the context's stream with no allocation: counters,
+// result slots and spill slabs carved from [scratch, scratch + bytes)
+ev_status eval_in_scratch(ev_ctx* c, Pop* P, int32_t table, float* d_fit, float* d_per_case, int32_t* d_hits,
+                          uint8_t* scratch, size_t bytes);
 ev_status crossover_build(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const int32_t* mum, const int32_t* dad,
                           const uint64_t* p, const uint64_t* q, int32_t n, uint64_t cap, Pop** out,
                           int32_t* n_capped);

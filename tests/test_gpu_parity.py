@@ -356,12 +356,14 @@ def test_children_reuse_their_mums_chunks(ev, chunk):
             wf3, wpc3 = oracle.eval_population(w3buf, w3off, x, y, threads=8, per_case=True)
             assert_same(pc3, wpc3, f"grandchildren per-case flags={flags}")
             assert_same(f3, wf3, f"grandchildren fitness flags={flags}")
-    a, b = results[0], results[ev.EV_TUNE_NO_REUSE]
-    assert a[4] == b[4] == mum.size
-    mums = [buf[off[m]:off[m + 1]] for m in mum]
-    moff = workloads.offsets_from_sizes([t.size for t in mums])
-    mbuf = np.concatenate(mums)
+    # a child over the cap is a copy of its mum (a one-node child is not over it)
+    cap = max(int(np.diff(koff).min()) - 1, 1)
+    over = np.diff(koff) > cap
+    capk = [buf[off[m]:off[m + 1]] if o else kk for m, o, kk in zip(mum, over, kids)]
+    moff = workloads.offsets_from_sizes([t.size for t in capk])
+    mbuf = np.concatenate(capk)
     for r in results.values():
+        assert r[4] == int(over.sum()) > 0
         assert np.array_equal(r[0], mbuf) and np.array_equal(r[1], moff)
     wf, wpc = oracle.eval_population(mbuf, moff, x, y, threads=8, per_case=True)
     for flags, r in results.items():
