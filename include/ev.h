@@ -9,6 +9,9 @@
  *   opcodes, root first, children in order.  Tokens:
  *       EV_ADD 0, EV_SUB 1, EV_MUL 2, EV_DIV 3  functions of two arguments
  *       EV_X   4                                the input
+ *       EV_C0 + i (6 + i), i < n_consts         ephemeral random constant i
+ *                                               (Sec. 2.1, Table 1; see
+ *                                               ev_set_constants)
  *   "op A B" is A op B; EV_DIV is protected division,
  *   (B != 0) ? A / B : 1.0f (Sec. 2.1 and the footnote of Table 1).
  *   All arithmetic is IEEE binary32, round to nearest even, subnormals
@@ -65,7 +68,7 @@ enum {
     EV_EDEVICE = -7     /* HIP runtime error */
 };
 
-enum { EV_ADD = 0, EV_SUB = 1, EV_MUL = 2, EV_DIV = 3, EV_X = 4 };
+enum { EV_ADD = 0, EV_SUB = 1, EV_MUL = 2, EV_DIV = 3, EV_X = 4, EV_C0 = 6, EV_MAX_CONSTS = 250 };
 
 /* flags */
 #define EV_DEVICE_PTR 0x1u /* ev_load_trees: bytes/off are device pointers */
@@ -103,6 +106,16 @@ ev_status ev_create(ev_ctx **out, int device, const float *x, const float *y, in
 /* Add another case table (host x[n], y[n]); *table receives its index. */
 ev_status ev_add_cases(ev_ctx *ctx, const float *x, const float *y, int32_t n_cases, int32_t *table);
 
+/* The context's ephemeral random constants (Sec. 2.1, Table 1: about 250
+ * constants drawn at random from -1.000 .. +1.000, a terminal like x whose
+ * value is the same on every case): token EV_C0 + i stands for consts[i],
+ * i < n <= EV_MAX_CONSTS; trees holding a token EV_C0 + n or above (or 5)
+ * are malformed.  Host array, copied.  Only while the context holds no
+ * population and serving has not started (EV_EINVAL otherwise).  Trees with
+ * constants are evaluated by the token-reading interpreter, and children in
+ * a context with constants are planned from scratch. */
+ev_status ev_set_constants(ev_ctx *ctx, const float *consts, int32_t n);
+
 /* Release every population, plan, job and device buffer of the context. */
 ev_status ev_destroy(ev_ctx *ctx);
 
@@ -112,7 +125,8 @@ const char *ev_last_error(void);
 /* Load n_trees trees.  bytes holds every tree back to back, tree t at
  * bytes[off[t], off[t+1]); off has n_trees+1 entries, off[0] = 0.  With
  * EV_DEVICE_PTR both are device pointers, else host pointers.  Every tree
- * is validated (Sec. 2.2 word: tokens 0..4, one complete prefix tree); on
+ * is validated (Sec. 2.2 word: tokens 0..4 and the context's constant
+ * tokens, one complete prefix tree); on
  * failure nothing is loaded, EV_EMALFORMED is returned and *bad_tree
  * (nullable) is the first bad tree.  The structure plan used by
  * ev_eval_fitness is built here.  *out_pop receives the handle. */
@@ -194,6 +208,28 @@ ev_status ev_generation(ev_ctx *ctx, ev_pop parents, const float *fitness, uint6
 #define EV_STATIC_SCRATCH_BYTES 0x4000000u /* 64 MiB */
 ev_status ev_eval_fitness_static(ev_ctx *ctx, ev_pop pop, int32_t table, float *fitness, float *per_case,
                                  int32_t *hits);
+
+/* Statistics of a population's last ev_eval_fitness, as the paper reports
+ * its runs generation by generation (Sec. 4: the columns of its result
+ * tables, and its plots of size, depth and fitness convergence). */
+typedef struct {
+    float best_fitness;  /* least MAE (NaN is worst) */
+    int32_t best_tree;   /* its index, the first of equals */
+    int32_t best_hits;   /* its hits (Sec. 3.2); -1 unless that evaluation
+                            returned hits to host memory */
+    int32_t converged;   /* trees whose MAE equals the best's bit for bit, or
+                            is NaN with a NaN best (the convergence column) */
+    double mean_fitness; /* over trees with a finite MAE; NaN if none */
+    uint64_t best_size, min_size, max_size; /* nodes */
+    double mean_size;
+    uint32_t best_depth, min_depth, max_depth; /* edges on the longest path from the root */
+    uint32_t pad;
+    double mean_depth;
+} ev_pop_stats;
+
+/* depth (nullable): host array of n_trees receiving every tree's depth.
+ * Errors: EV_EINVAL (no evaluation yet), EV_ENOTFOUND, EV_ENOMEM. */
+ev_status ev_population_stats(ev_ctx *ctx, ev_pop pop, ev_pop_stats *stats, uint32_t *depth);
 
 /* ---- serving: continuously batched evaluation / crossover requests ---- */
 

@@ -7,6 +7,8 @@
  *     external stack whose frames hold one float per test case (Sec. 2.2);
  *   - the functions are +, -, x and protected division
  *     (y!=0) ? x/y : 1.0f (Sec. 2.1, Table 1 footnote);
+ *   - the terminals are x and up to 250 ephemeral random constants, each a
+ *     fixed value the same on every case (Sec. 2.1, Table 1);
  *   - fitness is the mean absolute error over the cases (Table 1, Sec. 3.2),
  *     summed by a plain ascending loop so the order is fixed (Sec. 2.2);
  *   - crossover copies the mum up to the removed subtree, then the dad's
@@ -31,24 +33,35 @@ float or_op(int op, float a, float b)
     }
 }
 
+/* A leaf: x, or one of the n_consts constants (tokens OR_C0 ..). */
+static int is_leaf(uint8_t tok, int32_t n_consts)
+{
+    return tok == OR_X || (tok >= OR_C0 && tok < OR_C0 + n_consts);
+}
+
 int or_validate(const uint8_t *t, uint64_t n, uint64_t *max_stack)
+{
+    return or_validate_c(t, n, 0, max_stack);
+}
+
+int or_validate_c(const uint8_t *t, uint64_t n, int32_t n_consts, uint64_t *max_stack)
 {
     /* Open-slot counter: starts at one (the root), each token fills one slot
      * and a function opens two.  The word is one tree iff the counter is
      * positive before every token and zero after the last. */
     int64_t c = 1;
     for (uint64_t i = 0; i < n; i++) {
-        if (t[i] > OR_X) return 0;
+        if (t[i] >= OR_X && !is_leaf(t[i], n_consts)) return 0;
         if (c < 1) return 0;
         c -= 1;
-        if (t[i] != OR_X) c += 2;
+        if (t[i] < OR_X) c += 2;
     }
     if (n == 0 || c != 0) return 0;
     if (max_stack) {
         /* height of the right-to-left machine: +1 per X, -1 per function */
         int64_t h = 0, m = 0;
         for (uint64_t i = n; i-- > 0;) {
-            h += (t[i] == OR_X) ? 1 : -1;
+            h += (t[i] < OR_X) ? -1 : 1;
             if (h > m) m = h;
         }
         *max_stack = (uint64_t)m;
@@ -58,8 +71,14 @@ int or_validate(const uint8_t *t, uint64_t n, uint64_t *max_stack)
 
 int or_eval_cases(const uint8_t *t, uint64_t n, const float *x, int32_t N, float *out)
 {
+    return or_eval_cases_c(t, n, x, N, NULL, 0, out);
+}
+
+int or_eval_cases_c(const uint8_t *t, uint64_t n, const float *x, int32_t N, const float *consts,
+                    int32_t n_consts, float *out)
+{
     uint64_t depth;
-    if (!or_validate(t, n, &depth)) return -1;
+    if (!or_validate_c(t, n, n_consts, &depth)) return -1;
     float *stack = (float *)malloc(sizeof(float) * (size_t)depth * (size_t)(N > 0 ? N : 1));
     if (!stack) return -1;
     uint64_t sp = 0; /* number of frames on the stack */
@@ -68,6 +87,11 @@ int or_eval_cases(const uint8_t *t, uint64_t n, const float *x, int32_t N, float
         if (tok == OR_X) {
             float *f = stack + (size_t)sp * (size_t)N;
             for (int32_t i = 0; i < N; i++) f[i] = x[i];
+            sp++;
+        } else if (tok >= OR_C0) {
+            /* an ephemeral random constant: the same value on every case */
+            float *f = stack + (size_t)sp * (size_t)N;
+            for (int32_t i = 0; i < N; i++) f[i] = consts[tok - OR_C0];
             sp++;
         } else {
             /* top frame = first argument, the frame below = second */
@@ -102,6 +126,8 @@ typedef struct {
     const uint64_t *off;
     int32_t M, N;
     const float *x, *y;
+    const float *consts;
+    int32_t n_consts;
     float *fitness, *per_case;
     int32_t next;
     int64_t status;
@@ -118,7 +144,9 @@ static void *pop_eval_worker(void *arg)
         pthread_mutex_unlock(&pe->mu);
         if (t >= pe->M) break;
         float *o = pe->per_case ? pe->per_case + (size_t)t * (size_t)pe->N : tmp;
-        int rc = tmp ? or_eval_cases(pe->buf + pe->off[t], pe->off[t + 1] - pe->off[t], pe->x, pe->N, o) : -1;
+        int rc = tmp ? or_eval_cases_c(pe->buf + pe->off[t], pe->off[t + 1] - pe->off[t], pe->x, pe->N, pe->consts,
+                                       pe->n_consts, o)
+                     : -1;
         if (rc != 0) {
             pthread_mutex_lock(&pe->mu);
             if (pe->status == 0 || -(pe->status) - 1 > t) pe->status = -(int64_t)t - 1;
@@ -135,8 +163,16 @@ int64_t or_eval_population(const uint8_t *buf, const uint64_t *off, int32_t M,
                            const float *x, const float *y, int32_t N,
                            float *fitness, float *per_case, int32_t threads)
 {
+    return or_eval_population_c(buf, off, M, x, y, N, NULL, 0, fitness, per_case, threads);
+}
+
+int64_t or_eval_population_c(const uint8_t *buf, const uint64_t *off, int32_t M,
+                             const float *x, const float *y, int32_t N, const float *consts,
+                             int32_t n_consts, float *fitness, float *per_case, int32_t threads)
+{
     pop_eval pe;
     pe.buf = buf; pe.off = off; pe.M = M; pe.N = N; pe.x = x; pe.y = y;
+    pe.consts = consts; pe.n_consts = n_consts;
     pe.fitness = fitness; pe.per_case = per_case; pe.next = 0; pe.status = 0;
     pthread_mutex_init(&pe.mu, NULL);
     if (threads < 1) threads = 1;
@@ -151,13 +187,36 @@ int64_t or_eval_population(const uint8_t *buf, const uint64_t *off, int32_t M,
     return pe.status;
 }
 
+int64_t or_depth(const uint8_t *t, uint64_t n)
+{
+    /* Right to left, as the evaluator reads the tree: a leaf is a subtree of
+     * depth 0, a function one more than the deeper of its two arguments
+     * (Sec. 4 plots depth against size; the root is at depth 0, as in the
+     * ramped half-and-half depths of Table 1). */
+    if (!or_validate_c(t, n, 256 - OR_C0, NULL)) return -1;
+    int64_t *h = (int64_t *)malloc(sizeof(int64_t) * (size_t)((n + 1) / 2 + 1));
+    if (!h) return -1;
+    uint64_t sp = 0;
+    for (uint64_t k = n; k-- > 0;) {
+        if (t[k] >= OR_X) {
+            h[sp++] = 0;
+        } else {
+            int64_t a = h[--sp], b = h[--sp];
+            h[sp++] = 1 + (a > b ? a : b);
+        }
+    }
+    int64_t d = h[0];
+    free(h);
+    return d;
+}
+
 uint64_t or_subtree_end(const uint8_t *t, uint64_t n, uint64_t p)
 {
     /* the subtree at p is complete once the slots it opened are all filled */
     int64_t open = 1;
     for (uint64_t k = p; k < n; k++) {
         open -= 1;
-        if (t[k] != OR_X) open += 2;
+        if (t[k] < OR_X) open += 2;
         if (open == 0) return k;
     }
     return n - 1; /* not reached for a valid tree */

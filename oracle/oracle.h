@@ -10,7 +10,8 @@
  * Build: gcc -O2 -ffp-contract=off (no -ffast-math, no FTZ/DAZ).
  *
  * Tokens (one byte per node, root first, Sec. 2.2):
- *   0 ADD, 1 SUB, 2 MUL, 3 DIV (protected), 4 X.
+ *   0 ADD, 1 SUB, 2 MUL, 3 DIV (protected), 4 X, and 6 + i for constant i
+ *   of a table of up to 250 ephemeral random constants (Sec. 2.1, Table 1).
  * A node "op A B" means A op B: the first argument is evaluated by the first
  * nested EVAL call (Sec. 2.2) and protected division returns
  * (y!=0) ? x/y : 1.0f with x the first argument (Table 1 footnote).
@@ -24,6 +25,9 @@
 #define OR_MUL 2
 #define OR_DIV 3
 #define OR_X 4
+/* tokens OR_C0 .. OR_C0 + n_consts - 1: ephemeral random constants (5 is
+ * never a valid token of a tree) */
+#define OR_C0 6
 
 /* one function node applied to binary32 operands, round-to-nearest-even */
 float or_op(int op, float a, float b);
@@ -32,11 +36,16 @@ float or_op(int op, float a, float b);
  * *max_stack (nullable) receives the largest stack height reached by the
  * right-to-left stack machine of or_eval_cases. */
 int or_validate(const uint8_t *t, uint64_t n, uint64_t *max_stack);
+/* The same over tokens 0..4 and the n_consts constant tokens. */
+int or_validate_c(const uint8_t *t, uint64_t n, int32_t n_consts, uint64_t *max_stack);
 
 /* Value of the tree on each of the N cases x[0..N).  Explicit stack of
  * N-float frames, tokens processed right to left (Sec. 2.2).  Returns 0,
  * or -1 for an invalid tree / allocation failure. */
 int or_eval_cases(const uint8_t *t, uint64_t n, const float *x, int32_t N, float *out);
+/* The same with constants: token OR_C0 + i pushes consts[i] on every case. */
+int or_eval_cases_c(const uint8_t *t, uint64_t n, const float *x, int32_t N, const float *consts,
+                    int32_t n_consts, float *out);
 
 /* Mean absolute error, binary32, cases summed in ascending order with a
  * plain loop (Sec. 2.2 last paragraph, Sec. 3.2, Table 1). */
@@ -52,6 +61,13 @@ int32_t or_hits(const float *out, const float *y, int32_t N);
 int64_t or_eval_population(const uint8_t *buf, const uint64_t *off, int32_t M,
                            const float *x, const float *y, int32_t N,
                            float *fitness, float *per_case, int32_t threads);
+int64_t or_eval_population_c(const uint8_t *buf, const uint64_t *off, int32_t M,
+                             const float *x, const float *y, int32_t N, const float *consts,
+                             int32_t n_consts, float *fitness, float *per_case, int32_t threads);
+
+/* Depth of a valid tree (edges on its longest root-to-leaf path; a lone
+ * leaf has depth 0), or -1 for an invalid tree. */
+int64_t or_depth(const uint8_t *t, uint64_t n);
 
 /* End (inclusive) of the subtree rooted at p. */
 uint64_t or_subtree_end(const uint8_t *t, uint64_t n, uint64_t p);

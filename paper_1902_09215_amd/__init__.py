@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libev.so")
 
 EV_OK, EV_EINVAL, EV_EMALFORMED, EV_ENOMEM, EV_ECAP, EV_EBUSY, EV_ENOTFOUND, EV_EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 EV_ADD, EV_SUB, EV_MUL, EV_DIV, EV_X = 0, 1, 2, 3, 4
+EV_C0, EV_MAX_CONSTS = 6, 250
 EV_DEVICE_PTR, EV_OUT_DEVICE = 0x1, 0x2
 EV_STATIC_SCRATCH_BYTES = 0x4000000
 EV_JOB_EVAL, EV_JOB_CROSSOVER = 0, 1
@@ -29,7 +30,8 @@ EXPORTS = [
     "ev_create", "ev_add_cases", "ev_destroy", "ev_last_error", "ev_load_trees", "ev_pop_info",
     "ev_get_trees", "ev_free_pop", "ev_eval_fitness", "ev_crossover", "ev_generation", "ev_submit",
     "ev_poll", "ev_wait", "ev_result", "ev_job_timing", "ev_get_plan_info", "ev_get_level_info", "ev_set_tuning",
-    "ev_autotune", "ev_last_level_times", "ev_last_timing", "ev_eval_fitness_static",
+    "ev_autotune", "ev_last_level_times", "ev_last_timing", "ev_eval_fitness_static", "ev_population_stats",
+    "ev_set_constants",
 ]
 
 
@@ -47,6 +49,14 @@ class ev_plan_info(ctypes.Structure):
 class ev_level_info(ctypes.Structure):
     _fields_ = [("tokens", ctypes.c_uint64), ("trees", ctypes.c_uint32), ("items", ctypes.c_uint32),
                 ("slots", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
+class ev_pop_stats(ctypes.Structure):
+    _fields_ = [("best_fitness", ctypes.c_float), ("best_tree", ctypes.c_int32), ("best_hits", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("mean_fitness", ctypes.c_double), ("best_size", ctypes.c_uint64),
+                ("min_size", ctypes.c_uint64), ("max_size", ctypes.c_uint64), ("mean_size", ctypes.c_double),
+                ("best_depth", ctypes.c_uint32), ("min_depth", ctypes.c_uint32), ("max_depth", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("mean_depth", ctypes.c_double)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -109,6 +119,8 @@ def load_library(path: str = LIB_PATH):
         "ev_last_level_times": [P, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)],
         "ev_last_timing": [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
         "ev_eval_fitness_static": [P, i32, i32, P, P, P],
+        "ev_population_stats": [P, i32, ctypes.POINTER(ev_pop_stats), P],
+        "ev_set_constants": [P, P, i32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -178,6 +190,12 @@ def ev_add_cases(ctx, x, y) -> int:
     return t.value
 
 
+def ev_set_constants(ctx, consts):
+    """The context's ephemeral random constants: token 6 + i is consts[i]."""
+    c = np.ascontiguousarray(consts, np.float32)
+    _check(_lib.ev_set_constants(ctx, _ptr(c) if c.size else None, c.size))
+
+
 def ev_destroy(ctx):
     _check(_lib.ev_destroy(ctx))
 
@@ -243,6 +261,19 @@ def ev_eval_fitness(ctx, pop, table: int = 0, per_case: bool = False, out=None, 
     _check(_lib.ev_eval_fitness(ctx, pop, table, _ptr(fit), _ptr(pc), _ptr(h), 0))
     res = (fit[:n], pc[:n] if pc is not None else None)
     return res + (h[:n],) if hits else res
+
+
+def ev_population_stats(ctx, pop, depths: bool = False):
+    """Statistics of the population's last evaluation (see ev.h): a dict,
+    with every tree's depth under "depths" when asked for."""
+    st = ev_pop_stats()
+    n, _ = ev_pop_info(ctx, pop)
+    d = np.empty(max(n, 1), np.uint32) if depths else None
+    _check(_lib.ev_population_stats(ctx, pop, ctypes.byref(st), _ptr(d)))
+    out = {k: getattr(st, k) for k, _ in ev_pop_stats._fields_ if k != "pad"}
+    if depths:
+        out["depths"] = d[:n]
+    return out
 
 
 def ev_eval_fitness_static(ctx, pop, out, table: int = 0, out_per_case=None, out_hits=None):

@@ -5,6 +5,13 @@
 namespace ev {
 
 enum : uint32_t { TOK_ADD = 0, TOK_SUB = 1, TOK_MUL = 2, TOK_DIV = 3, TOK_X = 4, TOK_REF = 5 };
+// Tokens TOK_C0 .. TOK_C0 + n_consts - 1: ephemeral random constants (leaves
+// whose value is the same on every case).
+constexpr uint32_t TOK_C0 = 6;
+constexpr uint32_t MAX_CONSTS = 250;
+// ChunkStat.bad / SegFn.bad flags: a token outside the level's alphabet, and
+// (not an error) a constant seen
+constexpr uint32_t BAD_TOKEN = 1u, HAS_CONST = 4u;
 
 // Register-stack entries of k_run (the interpreter's VGPR window).
 #include "ev_interp.inc"
@@ -110,14 +117,14 @@ struct SegFn {
     int32_t net;       // sum over tokens of (+1 function, -1 leaf)
     int32_t minpref;   // minimum of that running sum before a token
     uint32_t bad, n_in;
-    uint32_t left_x;   // its first token is an X
-    uint32_t pad;
+    uint32_t left_x;   // its first token is a leaf (x or a constant)
+    uint32_t left_tok; // and which
 };
 
 struct SegStart {
     uint32_t cnt, P;
     uint32_t ref0;  // REF tokens the chunk's later segments hold (read before this one)
-    uint32_t pad;
+    uint32_t ptok;  // with P: the pending leaf's token (x or a constant)
 };
 
 struct SegCount {
@@ -179,6 +186,7 @@ struct EvalArgs {
     const float* in_res;
     float* out_res;
     float* gstack;
+    const float* consts;  // the constants' values (token TOK_C0 + i is consts[i])
 };
 
 static_assert(sizeof(EvalChunk) == 32, "EvalChunk layout");
@@ -210,6 +218,14 @@ struct TreeReuse {
     ReuseRun r;
     uint32_t chunk_first, seg_first, tree, C;  // C: the fresh chunks' size
     uint32_t n_mid, mid_last;                  // fresh chunks (all C tokens but the last)
+};
+
+// A population's statistics as the device reduces them (see ev_pop_stats).
+struct PopStatsDev {
+    double sum_fit;      // over finite fitness values
+    double sum_size;
+    uint64_t min_size, max_size;
+    uint32_t best, n_finite, converged, pad;
 };
 
 struct XoPlan {

@@ -311,9 +311,12 @@ __device__ __forceinline__ void for_tokens_rev(const uint8_t* __restrict__ seq, 
 // the chunk's first token (it ends with the chunk's flush and END); other
 // segments end by putting the window in its boundary position.
 __device__ uint32_t run_segment(const uint8_t* __restrict__ seq, uint64_t start, uint32_t len, uint32_t cnt_in,
-                                uint32_t P_in, bool last, Sink& o)
+                                uint32_t P_in, uint32_t ptok_in, bool last, Sink& o)
 {
-    uint32_t P = P_in;
+    // P: the token read before is a leaf whose push is still pending: x, or
+    // an ephemeral random constant (token ptok), which the structure treats
+    // alike (a plan holding constants runs on k_eval, which reads tokens)
+    uint32_t P = P_in, ptok = ptok_in;
     uint32_t tv = cnt_in > P ? 1u : 0u;
     uint32_t m = cnt_in - tv - P;
     uint32_t base = norm_base(m), maxtop = m;
@@ -322,19 +325,22 @@ __device__ uint32_t run_segment(const uint8_t* __restrict__ seq, uint64_t start,
         // token kinds do not diverge: a function finding two values without
         // a FILL, and an x needing no SPILL.  The rest take the full path.
         const uint32_t cnt = m + tv + P;
+        const bool leaf = t == TOK_X || t >= TOK_C0;
         const bool fast_fn = t < TOK_X && cnt >= 2 && (P || m != base || base == 0);
-        const bool fast_x = t == TOK_X && !(P && tv && m + 1 - base > EV_VSTACK - 1);
+        const bool fast_x = leaf && !(P && tv && m + 1 - base > EV_VSTACK - 1);
         if (fast_fn || fast_x) {
             const uint32_t kx = !P ? ~0u : (tv ? EV_K_PUSHX : EV_K_LOADX);
             const uint32_t kind = fast_fn ? (P ? EV_K_OPX0 + t : EV_K_OPS0 + t) : kx;
             m = fast_fn ? m - (P ? 0u : 1u) : m + ((P && tv) ? 1u : 0u);
             tv = fast_fn ? tv : (tv | P);
             P = fast_fn ? 0u : 1u;
+            ptok = fast_fn ? ptok : t;
             o.code_fast(kind);
             maxtop = m > maxtop ? m : maxtop;
             return;
         }
-        if (t == TOK_X) {
+        if (leaf) {
+            ptok = t;
             if (!P) {
                 P = 1;
             } else if (tv) {
@@ -381,7 +387,7 @@ __device__ uint32_t run_segment(const uint8_t* __restrict__ seq, uint64_t start,
             } else {
                 if (cnt == 1) {
                     if (!P) { o.code(EV_K_OUTT); o.n_out++; }
-                    o.ftok(P ? TOK_X : TOK_REF);
+                    o.ftok(P ? ptok : TOK_REF);
                 }
                 o.ftok(t);
                 tv = 0; P = 0; m = 0;
@@ -519,7 +525,9 @@ __global__ __launch_bounds__(64) void k_plan_trees(const TreeLvl* __restrict__ t
             const uint64_t ie = c_in + si;
             in_end[j] = (uint32_t)ie;
             if (ie > prev_out) bad |= 2u;
-            if (level == 0 && (q.bad || c_open + (sn - q.net) + q.minpref < 1)) bad |= 1u;
+            if (level == 0 && ((q.bad & BAD_TOKEN) || c_open + (sn - q.net) + q.minpref < 1)) bad |= 1u;
+            if (q.bad & BAD_TOKEN) bad |= level == 0 ? 1u : 2u;
+            bad |= q.bad & HAS_CONST;
             maxtop = q.maxtop > maxtop ? q.maxtop : maxtop;
             max_m = q.max_m > max_m ? q.max_m : max_m;
         }
@@ -827,7 +835,7 @@ __global__ __launch_bounds__(256) void k_reuse_copy(const uint32_t* __restrict__
 
 // Per segment: its cnt map (a, b), validity counters and input references.
 __global__ void k_seg_fn(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs, uint32_t n,
-                         SegFn* __restrict__ out, uint32_t max_tok)
+                         SegFn* __restrict__ out, uint32_t ref_ok, uint32_t n_consts)
 {
     const uint32_t si = blockIdx.x * blockDim.x + threadIdx.x;
     if (si >= n) return;
@@ -835,7 +843,9 @@ __global__ void k_seg_fn(const uint8_t* __restrict__ seq, const SegIn* __restric
     int32_t a = 0, b = INT32_MIN / 2, R = 0, maxR = INT32_MIN;
     uint32_t bad = 0, n_in = 0, last_t = 0;
     for_tokens_rev(seq, g.start, g.len, [&](const uint32_t t) {
-        bad |= t > max_tok;
+        const bool is_const = t >= TOK_C0 && t < TOK_C0 + n_consts;
+        bad |= (t > TOK_REF && !is_const) || (t == TOK_REF && !ref_ok) ? BAD_TOKEN : 0u;
+        bad |= is_const ? HAS_CONST : 0u;
         n_in += t == TOK_REF;
         if (t < TOK_X) {
             a -= 1;
@@ -856,8 +866,8 @@ __global__ void k_seg_fn(const uint8_t* __restrict__ seq, const SegIn* __restric
     f.minpref = R - maxR;
     f.bad = bad;
     f.n_in = n_in;
-    f.left_x = last_t == TOK_X;
-    f.pad = 0;
+    f.left_x = last_t == TOK_X || last_t >= TOK_C0;
+    f.left_tok = last_t;
     out[si] = f;
 }
 
@@ -879,12 +889,12 @@ __global__ __launch_bounds__(64) void k_seg_scan(const ChunkSegs* __restrict__ c
     const ChunkSegs cs = cseg[ci];
     constexpr int32_t NONE = INT32_MIN / 2;
     int32_t c = 0, suf = 0, mmin = INT32_MAX;
-    uint32_t P = 0, refs = 0, bad = 0;
+    uint32_t P = 0, Ptok = TOK_X, refs = 0, bad = 0;
     for (uint32_t g = 0; g < cs.n_seg; g += 64) {
         const uint32_t r = g + (uint32_t)lane;
         const bool in = r < cs.n_seg;
         const uint32_t k = in ? cs.n_seg - 1 - r : 0;
-        SegFn f = {0, NONE, 0, 0, 0, 0, 0, 0};
+        SegFn f = {0, NONE, 0, 0, 0, 0, 0, TOK_X};
         if (in) f = fn[cs.first + k];
         int32_t A = f.a, B = f.b, net = f.net;
         uint32_t nin = f.n_in;
@@ -899,16 +909,17 @@ __global__ __launch_bounds__(64) void k_seg_scan(const ChunkSegs* __restrict__ c
             }
         }
         int32_t Ae = __shfl_up(A, 1, 64), Be = __shfl_up(B, 1, 64);
-        uint32_t ne = __shfl_up(nin, 1, 64), Pe = __shfl_up(f.left_x, 1, 64);
+        uint32_t ne = __shfl_up(nin, 1, 64), Pe = __shfl_up(f.left_x, 1, 64), Te = __shfl_up(f.left_tok, 1, 64);
         if (lane == 0) {
             Ae = 0;
             Be = NONE;
             ne = 0;
             Pe = P;
+            Te = Ptok;
         }
         if (in) {
             const int32_t cnt = c + Ae > Be ? c + Ae : Be;
-            st[cs.first + k] = SegStart{(uint32_t)cnt, Pe, refs + ne, 0};
+            st[cs.first + k] = SegStart{(uint32_t)cnt, Pe, refs + ne, Te};
             const int32_t v = f.minpref - (suf + net);
             mmin = v < mmin ? v : mmin;
             bad |= f.bad;
@@ -917,6 +928,7 @@ __global__ __launch_bounds__(64) void k_seg_scan(const ChunkSegs* __restrict__ c
         c = c + A63 > B63 ? c + A63 : B63;
         const uint32_t last = (cs.n_seg - g < 64u ? cs.n_seg - g : 64u) - 1u;
         P = __shfl(f.left_x, (int)last, 64);
+        Ptok = __shfl(f.left_tok, (int)last, 64);
         refs += __shfl(nin, 63, 64);
         suf += __shfl(net, 63, 64);
     }
@@ -960,7 +972,7 @@ __global__ void k_seg_count(const uint8_t* __restrict__ seq, const SegIn* __rest
         o.rk_cap = 4u * g.len + 40u;
         o.rf_cap = 2u * g.len + 16u;
     }
-    const uint32_t maxtop = run_segment(seq, g.start, g.len, st[si].cnt, st[si].P, g.last != 0, o);
+    const uint32_t maxtop = run_segment(seq, g.start, g.len, st[si].cnt, st[si].P, st[si].ptok, g.last != 0, o);
     out[si] = SegCount{o.n_codes, o.n_frag, o.n_out, o.n_in, maxtop, 0};
     if (rk) {
         o.rec_end();
@@ -1056,7 +1068,7 @@ __device__ __forceinline__ void emit_segment(const uint8_t* __restrict__ seq, co
     if (!dst && !has_codes) return;
     Sink o{has_codes ? codes : nullptr, has_codes ? seg_code[si] : 0, dst, dst ? seg_frag[si] : 0, 0, 0, 0, 0, ~0u,
            st[si].ref0, nullptr, nullptr, 0, 0, 0, 0, 0, SegRec{}};
-    run_segment(seq, g.start, g.len, st[si].cnt, st[si].P, g.last != 0, o);
+    run_segment(seq, g.start, g.len, st[si].cnt, st[si].P, st[si].ptok, g.last != 0, o);
 }
 
 __global__ void k_seg_emit(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs, uint32_t n,
@@ -1406,14 +1418,16 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
 
         uint32_t cnt = 0, P = 0, m = 0, lo = 0;
         uint32_t in_slot = c.in_end, out_slot = c.out_end;
-        float T = 0.0f;
+        float T = 0.0f, pv = 0.0f;  // pv: the pending leaf's value (x or a constant) while P
 
 #define RING(e) ring[((e) & (D - 1)) * 64u + lane]
 #define STEP(tok)                                                                   \
     do {                                                                            \
         const uint32_t t_ = (tok);                                                  \
-        if (t_ == TOK_X) {                                                          \
-            if (P) { RING(m) = T; m++; T = xv; } else { P = 1; }                    \
+        if (t_ == TOK_X || t_ >= TOK_C0) {                                          \
+            const float lv_ = t_ == TOK_X ? xv : a.consts[t_ - TOK_C0];             \
+            if (P) { RING(m) = T; m++; T = pv; } else { P = 1; }                    \
+            pv = lv_;                                                               \
             cnt++;                                                                  \
         } else if (t_ < TOK_X) {                                                    \
             if (cnt < 2) {                                                          \
@@ -1424,7 +1438,7 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
                 cnt = 0; P = 0; m = 0; lo = 0;                                      \
             } else {                                                                \
                 float av, bv;                                                       \
-                if (P) { av = xv; bv = T; P = 0; }                                  \
+                if (P) { av = pv; bv = T; P = 0; }                                  \
                 else { m--; av = T; bv = RING(m); }                                 \
                 T = apply_op(t_, av, bv);                                           \
                 cnt--;                                                              \
@@ -1432,7 +1446,7 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
         } else {                                                                    \
             in_slot--;                                                              \
             const float r_ = act ? in_res[(size_t)in_slot * (size_t)N + cs] : 0.0f; \
-            if (P) { RING(m) = T; m++; T = xv; P = 0; }                             \
+            if (P) { RING(m) = T; m++; T = pv; P = 0; }                             \
             RING(m) = T; m++; T = r_;                                               \
             cnt++;                                                                  \
         }                                                                           \
@@ -1489,7 +1503,7 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
             }
             if (P) {
                 out_slot--;
-                if (act) out_res[(size_t)out_slot * (size_t)N + cs] = xv;
+                if (act) out_res[(size_t)out_slot * (size_t)N + cs] = pv;
             }
         }
 #undef RING
@@ -1853,6 +1867,149 @@ __global__ void k_select(const float* __restrict__ fit, const uint64_t* __restri
 
 namespace ev {
 
+// ---------------------------------------------- population statistics (Sec. 4)
+
+__device__ __forceinline__ bool stat_better(float a, uint32_t ia, float b, uint32_t ib)
+{
+    // lower MAE wins, NaN is worst, and of equals the lower index (the first)
+    if (a != a) return (b != b) && ia < ib;
+    if (b != b) return true;
+    return a < b || (a == b && ia < ib);
+}
+
+// One block: the best tree (least fitness, NaN worst, the first of equals),
+// how many trees share its fitness bit for bit (or are NaN with a NaN best),
+// the sum and count of the finite fitness values and the sizes' sum, minimum
+// and maximum.
+__global__ __launch_bounds__(1024) void k_pop_stats(const float* __restrict__ fit, const uint64_t* __restrict__ off,
+                                                    uint32_t M, PopStatsDev* __restrict__ out)
+{
+    __shared__ float sf[1024];
+    __shared__ uint32_t si[1024];
+    __shared__ double sd[1024], ss[1024];
+    __shared__ uint64_t smin[1024], smax[1024];
+    __shared__ uint32_t sc[1024];
+    const uint32_t t = threadIdx.x;
+    float bf = __int_as_float(0x7fc00000);
+    uint32_t bi = 0xFFFFFFFFu, nfin = 0;
+    double sum = 0.0, size_sum = 0.0;
+    uint64_t mn = ~0ull, mx = 0;
+    for (uint32_t i = t; i < M; i += blockDim.x) {
+        const float f = fit[i];
+        if (bi == 0xFFFFFFFFu || stat_better(f, i, bf, bi)) {
+            bf = f;
+            bi = i;
+        }
+        if (isfinite(f)) {
+            sum += (double)f;
+            nfin++;
+        }
+        const uint64_t n = off[i + 1] - off[i];
+        size_sum += (double)n;
+        mn = n < mn ? n : mn;
+        mx = n > mx ? n : mx;
+    }
+    sf[t] = bf;
+    si[t] = bi;
+    sd[t] = sum;
+    ss[t] = size_sum;
+    smin[t] = mn;
+    smax[t] = mx;
+    sc[t] = nfin;
+    __syncthreads();
+    for (uint32_t d = 512; d > 0; d >>= 1) {
+        if (t < d) {
+            if (si[t + d] != 0xFFFFFFFFu && (si[t] == 0xFFFFFFFFu || stat_better(sf[t + d], si[t + d], sf[t], si[t]))) {
+                sf[t] = sf[t + d];
+                si[t] = si[t + d];
+            }
+            sd[t] += sd[t + d];
+            ss[t] += ss[t + d];
+            smin[t] = smin[t + d] < smin[t] ? smin[t + d] : smin[t];
+            smax[t] = smax[t + d] > smax[t] ? smax[t + d] : smax[t];
+            sc[t] += sc[t + d];
+        }
+        __syncthreads();
+    }
+    const float best = sf[0];
+    const uint32_t bu = __float_as_uint(best);
+    const bool best_nan = best != best;
+    uint32_t conv = 0;
+    for (uint32_t i = t; i < M; i += blockDim.x) {
+        const float f = fit[i];
+        conv += (__float_as_uint(f) == bu || (best_nan && f != f)) ? 1u : 0u;
+    }
+    __syncthreads();
+    const uint32_t nfin_all = sc[0];
+    __syncthreads();
+    sc[t] = conv;
+    __syncthreads();
+    for (uint32_t d = 512; d > 0; d >>= 1) {
+        if (t < d) sc[t] += sc[t + d];
+        __syncthreads();
+    }
+    if (t == 0) *out = PopStatsDev{sd[0], ss[0], smin[0], smax[0], si[0], nfin_all, sc[0], 0};
+}
+
+// One wave per tree: the greatest height the right-to-left stack machine
+// reaches on it (a leaf pushes, a function pops two and pushes one), which
+// bounds the depth pass's stack.  Lane l takes the l-th of 64 consecutive
+// parts; the parts combine from the right.
+__global__ __launch_bounds__(64) void k_tree_height(const uint8_t* __restrict__ buf, const uint64_t* __restrict__ off,
+                                                    uint32_t M, uint32_t* __restrict__ height)
+{
+    const uint32_t t = blockIdx.x;
+    if (t >= M) return;
+    const uint32_t lane = threadIdx.x;
+    const uint64_t a = off[t], n = off[t + 1] - a;
+    const uint64_t per = (n + 63) / 64;
+    const uint64_t lo = a + per * lane < a + n ? a + per * lane : a + n;
+    const uint64_t hi = lo + per < a + n ? lo + per : a + n;
+    int64_t run = 0, best = 0;  // the part's running height from its right end, and its peak
+    for (uint64_t k = hi; k-- > lo;) {
+        run += buf[k] < TOK_X ? -1 : 1;  // a function pops two and pushes one, a leaf pushes
+        best = run > best ? run : best;
+    }
+    // the height entering each part from its right: sum of the parts to its right
+    int64_t suf = run;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t o = __shfl_down(suf, d, 64);
+        if ((int)lane + d < 64) suf += o;
+    }
+    const int64_t enter = suf - run;
+    int64_t peak = enter + best;
+    for (int d = 32; d > 0; d >>= 1) {
+        const int64_t o = __shfl_xor(peak, d, 64);
+        peak = o > peak ? o : peak;
+    }
+    if (lane == 0) height[t] = (uint32_t)(peak > 0 ? peak : 1);
+}
+
+// One thread per tree: its depth (root at 0), right to left: a leaf is a
+// subtree of depth 0, a function one more than the deeper of its two
+// arguments; the subtrees' depths wait on a stack in [stack + base[t], ...).
+__global__ void k_tree_depth(const uint8_t* __restrict__ buf, const uint64_t* __restrict__ off, uint32_t M,
+                             const uint64_t* __restrict__ base, uint32_t* __restrict__ stack, uint32_t* __restrict__ depth)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M) return;
+    uint32_t* st = stack + base[t];
+    const uint64_t cap = base[t + 1] - base[t];
+    uint64_t sp = 0;
+    for (uint64_t k = off[t + 1]; k-- > off[t];) {
+        if (buf[k] >= TOK_X) {  // a leaf: x or a constant
+            if (sp < cap) st[sp] = 0;
+            sp++;
+        } else {
+            const uint32_t x = sp >= 1 && sp - 1 < cap ? st[sp - 1] : 0u;
+            const uint32_t y = sp >= 2 && sp - 2 < cap ? st[sp - 2] : 0u;
+            sp = sp >= 1 ? sp - 1 : 0;
+            if (sp >= 1 && sp - 1 < cap) st[sp - 1] = 1u + (x > y ? x : y);
+        }
+    }
+    depth[t] = cap ? st[0] : 0u;
+}
+
 // --------------------------------------------------- register-stack kernel
 //
 // One wave runs the threaded codes of one work item (lane = test case); see
@@ -2011,11 +2168,32 @@ hipError_t launch_reuse_copy(const uint32_t* src, uint32_t n, const ChunkStat* c
     return hipGetLastError();
 }
 
-hipError_t launch_seg_fn(const uint8_t* seq, const SegIn* segs, uint32_t n, SegFn* out, uint32_t max_tok,
-                         hipStream_t s)
+hipError_t launch_pop_stats(const float* fit, const uint64_t* off, uint32_t M, PopStatsDev* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pop_stats, dim3(1), dim3(1024), 0, s, fit, off, M, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_height(const uint8_t* buf, const uint64_t* off, uint32_t M, uint32_t* height, hipStream_t s)
+{
+    if (M == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tree_height, dim3(M), dim3(64), 0, s, buf, off, M, height);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_depth(const uint8_t* buf, const uint64_t* off, uint32_t M, const uint64_t* base, uint32_t* stack,
+                             uint32_t* depth, hipStream_t s)
+{
+    if (M == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tree_depth, dim3(cdiv(M, 64)), dim3(64), 0, s, buf, off, M, base, stack, depth);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_fn(const uint8_t* seq, const SegIn* segs, uint32_t n, SegFn* out, uint32_t ref_ok,
+                         uint32_t n_consts, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_fn, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, out, max_tok);
+    hipLaunchKernelGGL(k_seg_fn, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, out, ref_ok, n_consts);
     return hipGetLastError();
 }
 

@@ -35,8 +35,15 @@ hipError_t launch_reuse_copy(const uint32_t* src, uint32_t n, const ChunkStat* c
                              const uint64_t* frag_end, const uint64_t* mum_code, const uint64_t* mum_frag,
                              const uint32_t* mum_codes, const uint8_t* mum_skel, uint32_t* codes, uint8_t* skel,
                              hipStream_t s);
-hipError_t launch_seg_fn(const uint8_t* seq, const SegIn* segs, uint32_t n, SegFn* out, uint32_t max_tok,
-                         hipStream_t s);
+// population statistics: best fitness and convergence, sizes; trees' stack
+// heights (bounds for the depth pass's stacks) and depths
+hipError_t launch_pop_stats(const float* fit, const uint64_t* off, uint32_t M, PopStatsDev* out, hipStream_t s);
+hipError_t launch_tree_height(const uint8_t* buf, const uint64_t* off, uint32_t M, uint32_t* height, hipStream_t s);
+hipError_t launch_tree_depth(const uint8_t* buf, const uint64_t* off, uint32_t M, const uint64_t* base, uint32_t* stack,
+                             uint32_t* depth, hipStream_t s);
+// ref_ok: REF tokens belong to the level's alphabet; n_consts constant tokens do
+hipError_t launch_seg_fn(const uint8_t* seq, const SegIn* segs, uint32_t n, SegFn* out, uint32_t ref_ok,
+                         uint32_t n_consts, hipStream_t s);
 hipError_t launch_seg_scan(const ChunkSegs* cseg, uint32_t n, const SegFn* fn, SegStart* st, ChunkStat* cstat,
                            hipStream_t s);
 // rk/rf/rec (nullable): record the segments' code kinds and fragment tokens

@@ -3,6 +3,7 @@
 #include "ev_runtime.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -343,6 +344,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
     // inside a power of two does not matter)
     auto bucket = [](uint64_t len) { return len ? (uint32_t)__builtin_clz((uint32_t)len) : 32u; };
 
+    bool plan_run = c->use_run;  // items on the register-stack kernel (no constants seen)
     std::vector<TreeReuse> trv;  // level 0 of a reusing plan: the children's runs
     if (reuse) {
         const Plan& mp = reuse->mum->plan;
@@ -491,7 +493,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
                                       level == 0 ? (uint32_t*)d_err : nullptr, N_ERR, s));
         }
         HIPCHK(launch_seg_build((ChunkIn*)d_ch, (ChunkSegs*)d_cseg, (uint32_t)n, seg_len, head, (SegIn*)d_seg, s));
-        HIPCHK(launch_seg_fn(cur, (SegIn*)d_seg, n_seg, (SegFn*)d_fn, level == 0 ? TOK_X : TOK_REF, s));
+        HIPCHK(launch_seg_fn(cur, (SegIn*)d_seg, n_seg, (SegFn*)d_fn, level == 0 ? 0u : 1u, (uint32_t)c->n_consts, s));
         HIPCHK(launch_seg_scan((ChunkSegs*)d_cseg, (uint32_t)n, (SegFn*)d_fn, (SegStart*)d_st, (ChunkStat*)d_stat, s));
         // The count pass also records the segments' code kinds and fragment
         // tokens when the recording fits, so that emission only has to place
@@ -544,6 +546,9 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         for (uint32_t i = 0; i < nt; i++) {
             const TreeSum& q = tsum[i];
             const uint32_t t = tl[i].tree;
+            // trees with constants run on the token-reading interpreter,
+            // at every level (their skeletons may hold constants too)
+            if (q.bad & HAS_CONST) plan_run = false;
             if (q.bad & 1u) {
                 cleanup();
                 if (bad_tree) *bad_tree = (int32_t)t;
@@ -564,7 +569,11 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
             pl.max_stack = std::max<uint64_t>(pl.max_stack, q.maxtop + 1);
         }
         if (so > 0xFFFFFFF0ull) { cleanup(); return fail(EV_ECAP, "too many intermediate results"); }
-        const bool run_items = c->use_run;
+        if (reusing && !plan_run) {
+            cleanup();
+            return fail(EV_EDEVICE, "internal: reused level-0 chunks in a plan without the register-stack kernel");
+        }
+        const bool run_items = plan_run;
 
         Level L;
         L.seq = cur;
@@ -1100,6 +1109,7 @@ static ev_status eval_launch(ev_ctx* c, Exec& x, Pop* P, const CaseTable& ct, co
         a.in_res = li ? b.res[li - 1] : nullptr;
         a.out_res = b.res[li];
         a.gstack = b.slab;
+        a.consts = c->d_const;
         HIPCHK(launch_eval(D, a, grid_for(L, a.n_items, grid_max), s));
         if (timed && li == 0) HIPCHK(hipEventRecord(x.evi1, s));
         if (timed) HIPCHK(hipEventRecord(x.evl[li], s));
@@ -1219,7 +1229,7 @@ ev_status crossover_build_dev(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const in
     // of 4 KiB copy pieces (each child's first piece follows on the device)
     std::vector<uint64_t> off((size_t)n + 4, 0);
     // the mum's level-0 chunks each child keeps (read with the offsets)
-    const bool reuse_ok = c->use_reuse && c->use_run && mums->plan.l0_n > 0 && n > 0;
+    const bool reuse_ok = c->use_reuse && c->use_run && c->n_consts == 0 && mums->plan.l0_n > 0 && n > 0;
     std::vector<ReuseRun> runs;
     void* d_runs = nullptr;
     if (reuse_ok && (st = dev_alloc(c, (size_t)n * sizeof(ReuseRun), &d_runs)) != EV_OK) {
@@ -1356,6 +1366,10 @@ ev_status ev_create(ev_ctx** out, int device, const float* x, const float* y, in
     int32_t tid = 0;
     ev_status st = ev_add_cases(c, x, y, n_cases, &tid);
     if (st == EV_OK) st = dev_alloc(c, 256, (void**)&c->d_flag);
+    if (st == EV_OK && (st = dev_alloc(c, 256 * sizeof(float), (void**)&c->d_const)) == EV_OK) {
+        const std::vector<float> zero(256, 0.0f);
+        st = put(c->main, c->d_const, zero.data(), zero.size() * sizeof(float));
+    }
     if (st == EV_OK) st = run_probe(c);
     if (st == EV_OK) st = static_scratch_init(device);
     if (st != EV_OK) { ev_destroy(c); return st; }
@@ -1448,6 +1462,7 @@ ev_status ev_destroy(ev_ctx* c)
     c->pops.clear();
     for (auto& t : c->tables) { dev_free(c, t.d_x); dev_free(c, t.d_y); }
     dev_free(c, c->d_flag);
+    dev_free(c, c->d_const);
     exec_free(c, c->main);
     dev_cache_release(c);
     delete c;
@@ -1581,6 +1596,7 @@ ev_status ev_eval_fitness(ev_ctx* c, ev_pop pop, int32_t table, float* fitness, 
     const bool verdict = P->plan.err_pending;
     ev_status st = eval_enqueue(c, c->main, P, table, P->d_fit, d_pc, true, d_hits, true);
     if (st != EV_OK) return st;
+    P->hits_valid = false;
     if (flags & EV_OUT_DEVICE) {
         if (P->M) HIPCHK(hipMemcpyAsync(fitness, P->d_fit, (size_t)P->M * 4, hipMemcpyDeviceToDevice, c->stream));
         if (verdict && ((st = sync(c->main)) != EV_OK || (st = plan_verdict(P)) != EV_OK)) return st;
@@ -1592,6 +1608,82 @@ ev_status ev_eval_fitness(ev_ctx* c, ev_pop pop, int32_t table, float* fitness, 
     if (hits && (st = get(c->main, hits, d_hits, (size_t)P->M * 4)) != EV_OK) return st;
     if ((st = sync(c->main)) != EV_OK || (st = plan_verdict(P)) != EV_OK) return st;
     P->fit_valid = true;
+    P->hits_valid = hits != nullptr;
+    return EV_OK;
+}
+
+ev_status ev_population_stats(ev_ctx* c, ev_pop pop, ev_pop_stats* out, uint32_t* depth)
+{
+    if (!c || !out) return fail(EV_EINVAL, "ev_population_stats: bad arguments");
+    Pop* P = pop_get(c, pop);
+    if (!P) return fail(EV_ENOTFOUND, "no population %d", pop);
+    if (!P->fit_valid) return fail(EV_EINVAL, "ev_population_stats: the population has not been evaluated");
+    HIPCHK(hipSetDevice(c->device));
+    Exec& x = c->main;
+    const uint32_t M = (uint32_t)P->M;
+    *out = ev_pop_stats{};
+    if (M == 0) return EV_OK;
+    void *d_ps = nullptr, *d_h = nullptr, *d_base = nullptr, *d_stack = nullptr;
+    auto cleanup = [&]() {
+        (void)sync(x);
+        for (void* q : {d_ps, d_h, d_base, d_stack}) dev_free(c, q);
+    };
+    ev_status st;
+    PopStatsDev ps{};
+    std::vector<uint32_t> h(M), d(M);
+    if ((st = dev_alloc(c, sizeof(PopStatsDev), &d_ps)) || (st = dev_alloc(c, (size_t)M * 8, &d_h))) {
+        cleanup();
+        return st;
+    }
+    HIPCHK(launch_pop_stats(P->d_fit, P->d_off, M, (PopStatsDev*)d_ps, x.stream));
+    HIPCHK(launch_tree_height(P->d_bytes, P->d_off, M, (uint32_t*)d_h, x.stream));
+    if ((st = get(x, &ps, d_ps, sizeof ps)) || (st = get(x, h.data(), d_h, (size_t)M * 4)) || (st = sync(x))) {
+        cleanup();
+        return st;
+    }
+    // each tree's depth stack: as many entries as its stack machine's height
+    std::vector<uint64_t> base((size_t)M + 1, 0);
+    for (uint32_t t = 0; t < M; t++) base[t + 1] = base[t] + h[t];
+    int32_t best_hits = -1;
+    if ((st = dev_alloc(c, base.size() * 8, &d_base)) || (st = dev_alloc(c, base[M] * 4 + 4, &d_stack)) ||
+        (st = put(x, d_base, base.data(), base.size() * 8))) {
+        cleanup();
+        return st;
+    }
+    HIPCHK(launch_tree_depth(P->d_bytes, P->d_off, M, (uint64_t*)d_base, (uint32_t*)d_stack, (uint32_t*)d_h,
+                             x.stream));
+    float bf = 0;
+    if (ps.best >= M) {
+        cleanup();
+        return fail(EV_EDEVICE, "internal: no best tree among %u", M);
+    }
+    if ((st = get(x, d.data(), d_h, (size_t)M * 4)) || (st = get(x, &bf, P->d_fit + ps.best, 4)) ||
+        (P->hits_valid && (st = get(x, &best_hits, P->d_hits + ps.best, 4))) || (st = sync(x))) {
+        cleanup();
+        return st;
+    }
+    cleanup();
+    out->best_fitness = bf;
+    out->best_tree = (int32_t)ps.best;
+    out->best_hits = best_hits;
+    out->converged = (int32_t)ps.converged;
+    out->mean_fitness = ps.n_finite ? ps.sum_fit / ps.n_finite : std::nan("");
+    out->best_size = P->h_off[ps.best + 1] - P->h_off[ps.best];
+    out->min_size = ps.min_size;
+    out->max_size = ps.max_size;
+    out->mean_size = ps.sum_size / M;
+    uint64_t dsum = 0;
+    uint32_t dmin = UINT32_MAX, dmax = 0;
+    for (uint32_t t = 0; t < M; t++) {
+        dsum += d[t];
+        dmin = std::min(dmin, d[t]);
+        dmax = std::max(dmax, d[t]);
+    }
+    out->best_depth = d[ps.best];
+    out->min_depth = dmin;
+    out->max_depth = dmax;
+    out->mean_depth = (double)dsum / M;
+    if (depth) std::memcpy(depth, d.data(), (size_t)M * 4);
     return EV_OK;
 }
 
@@ -1653,6 +1745,25 @@ ev_status ev_get_plan_info(ev_ctx* c, ev_pop pop, ev_plan_info* info)
     info->slots = P->plan.slots_total;
     info->max_stack = P->plan.max_stack;
     info->plan_bytes = P->plan.bytes;
+    return EV_OK;
+}
+
+ev_status ev_set_constants(ev_ctx* c, const float* consts, int32_t n)
+{
+    if (!c || n < 0 || n > (int32_t)MAX_CONSTS || (n > 0 && !consts))
+        return fail(EV_EINVAL, "ev_set_constants: bad arguments");
+    {
+        std::lock_guard<std::mutex> g(c->pop_mu);
+        if (!c->pops.empty()) return fail(EV_EINVAL, "ev_set_constants: the context holds populations");
+    }
+    if (c->serve) return fail(EV_EINVAL, "ev_set_constants: the serving loop has started");
+    HIPCHK(hipSetDevice(c->device));
+    std::vector<float> v(256, 0.0f);
+    for (int32_t i = 0; i < n; i++) v[(size_t)i] = consts[i];
+    ev_status st = put(c->main, c->d_const, v.data(), v.size() * sizeof(float));
+    if (st == EV_OK) st = sync(c->main);
+    if (st != EV_OK) return st;
+    c->n_consts = n;
     return EV_OK;
 }
 

@@ -96,6 +96,7 @@ struct Pop {
     float* d_fit = nullptr;
     int32_t* d_hits = nullptr;  // the last evaluation's hits, when asked for
     bool fit_valid = false;
+    bool hits_valid = false;    // d_hits holds the last evaluation's hits
     std::map<int32_t, ResCache> res;
     // serving jobs using the population off the caller's thread (guarded by
     // the context's pop_mu); ev_free_pop of a population still in use only
@@ -161,6 +162,9 @@ struct ev_ctx {
     bool use_record = true;        // the count pass records codes for emission (EV_TUNE_NO_RECORD clears it)
     bool use_reuse = true;         // children take over their mums' level-0 chunks (EV_TUNE_NO_REUSE clears it)
     uint32_t* d_flag = nullptr;  // the probe's flag word
+    // ephemeral random constants (Sec. 2.1): token 6 + i is d_const[i]
+    int32_t n_consts = 0;
+    float* d_const = nullptr;
     uint32_t chunk = 6144;     // tokens per work item at level 0
     uint32_t chunk_hi = 0;     // at the skeleton levels (0: twice chunk)
     int lds_depth = 64;

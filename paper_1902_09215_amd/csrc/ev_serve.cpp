@@ -300,8 +300,9 @@ ev_status ev_submit(ev_ctx* c, const ev_job* job, ev_ticket* out)
             int64_t open = 1;
             for (uint64_t k = j->off[t]; k < j->off[t + 1]; k++) {
                 const uint8_t b = j->bytes[k];
-                if (b > EV_X || open < 1) { open = -1; break; }
-                open += (b == EV_X) ? -1 : 1;
+                const bool leaf = b == EV_X || (b >= TOK_C0 && b < TOK_C0 + (uint32_t)c->n_consts);
+                if ((b > EV_X && !leaf) || open < 1) { open = -1; break; }
+                open += leaf ? -1 : 1;
             }
             if (open != 0) return fail(EV_EMALFORMED, "ev_submit: tree %d is not a valid prefix tree", t);
         }

@@ -424,6 +424,145 @@ def test_generations_tournament_7_population_500(ev):
             pop, buf, off = kids, wbuf, woff
 
 
+@pytest.mark.parametrize("chunk", [64, 512, 1 << 20])
+def test_constants_match_oracle(ev, chunk):
+    # Ephemeral random constants (Sec. 2.1, Table 1): 250 constants from
+    # -1.000 .. +1.000 as terminals beside x; constant-rich trees (half the
+    # leaves constants), split at several work-item sizes so that constants
+    # also reach the skeleton levels; per-case values, fitness and hits equal
+    # the oracle's, and single-constant trees give their constant.
+    x, y = workloads.cases(48)
+    consts = workloads.erc_table(81, 250)
+    sizes = workloads.loguniform_sizes(82, 300, 1, 20000)
+    buf, off = workloads.random_population(82, sizes)
+    buf = workloads.with_constants(buf, 83, 250, 0.5)
+    singles = np.arange(6, 256, dtype=np.uint8)
+    buf = np.concatenate([buf, singles])
+    off = np.concatenate([off, off[-1] + np.arange(1, singles.size + 1, dtype=np.uint64)])
+    want_fit, want_pc = oracle.eval_population(buf, off, x, y, threads=8, per_case=True, consts=consts)
+    assert (want_pc[-250:] == consts[:, None]).all()
+    with ev.Context(x, y) as c:
+        ev.ev_set_constants(c.ctx, consts)
+        ev.ev_set_tuning(c.ctx, chunk)
+        pop = c.load(buf, off)
+        fit, pc, hits = c.eval(pop, per_case=True, hits=True)
+    assert_same(pc, want_pc, f"constants per-case chunk={chunk}")
+    assert_same(fit, want_fit, f"constants fitness chunk={chunk}")
+    assert np.array_equal(hits, oracle.hits(want_pc, y))
+
+
+def test_constants_in_generations_and_serving(ev):
+    # children of constant-rich parents (planned from scratch in a context
+    # with constants), their evaluation, and served requests, against the
+    # oracle; tokens outside the table are refused
+    x, y = workloads.cases(48)
+    consts = workloads.erc_table(84, 100)
+    pbuf, poff = workloads.rhh_population(workloads.SEED_BASE + 8, 64, 2, 6)
+    pbuf = workloads.with_constants(pbuf, 85, 100, 0.4)
+    seed, cap = 91, 15_000_000
+    with ev.Context(x, y) as c:
+        ev.ev_set_constants(c.ctx, consts)
+        pop = c.load(pbuf, poff)
+        fit, _ = c.eval(pop)
+        wfit = oracle.eval_population(pbuf, poff, x, y, threads=8, consts=consts)
+        assert_same(fit, wfit, "parents")
+        buf, off = pbuf, poff
+        for g in range(8):
+            kids, capped = ev.ev_generation(c.ctx, pop, seed, g, 7, cap)
+            wbuf, woff, wcap = oracle.generation(buf, off, wfit, 7, seed, g, cap)
+            gbuf, goff = ev.ev_get_trees(c.ctx, kids)
+            assert capped == wcap and np.array_equal(goff, woff) and np.array_equal(gbuf, wbuf), f"gen {g}"
+            fit, _ = c.eval(kids)
+            wfit = oracle.eval_population(wbuf, woff, x, y, threads=8, consts=consts)
+            assert_same(fit, wfit, f"gen {g + 1}")
+            ev.ev_free_pop(c.ctx, pop)
+            pop, buf, off = kids, wbuf, woff
+        tickets = [ev.ev_submit_eval(c.ctx, buf[off[t]:off[t + 1]], np.array([0, off[t + 1] - off[t]], np.uint64))
+                   for t in range(0, 64, 3)]
+        for k, tk in zip(range(0, 64, 3), tickets):
+            assert ev.ev_wait(c.ctx, tk) == 0
+            f, _ = ev.ev_result(c.ctx, tk, 1, 48)
+            assert_same(f, wfit[k:k + 1], f"served tree {k}")
+        bad = np.array([ADD, X, 6 + 100], np.uint8)
+        with pytest.raises(ev.EvError) as e:
+            c.load(bad, np.array([0, 3], np.uint64))
+        assert e.value.code == ev.EV_EMALFORMED
+        with pytest.raises(ev.EvError) as e:
+            c.load(np.array([ADD, X, 5], np.uint8), np.array([0, 3], np.uint64))
+        assert e.value.code == ev.EV_EMALFORMED
+        with pytest.raises(ev.EvError):
+            ev.ev_set_constants(c.ctx, consts)  # populations are held
+
+
+def assert_stats(got, want, what):
+    for k in ("best_tree", "best_hits", "converged", "best_size", "best_depth", "min_size", "max_size",
+              "min_depth", "max_depth"):
+        assert got[k] == want[k], f"{what}: {k} {got[k]} != {want[k]}"
+    assert same_bits(np.float32(got["best_fitness"]), np.float32(want["best_fitness"])), what
+    for k in ("mean_size", "mean_depth"):
+        assert got[k] == pytest.approx(want[k], rel=1e-12), f"{what}: {k}"
+    # a mean of float32 values summed in double in another order
+    assert got["mean_fitness"] == pytest.approx(want["mean_fitness"], rel=1e-9, nan_ok=True), f"{what}: mean_fitness"
+
+
+def test_population_4000_generations_with_statistics(ev):
+    # Table 1's population of 4000 trees with tournaments of 7: every
+    # generation's trees, fitness and hits equal the oracle's, and so do the
+    # per-generation statistics the paper reports (Sec. 4: best error, its
+    # hits, convergence on the best fitness, sizes and depths).
+    x, y = workloads.cases(48)
+    buf, off = workloads.rhh_population(workloads.SEED_BASE + 7, 4000, 2, 6)
+    seed, gens, cap = 4000, 12, 15_000_000
+    with ev.Context(x, y) as c:
+        pop = c.load(buf, off)
+        fit, _, hits = c.eval(pop, hits=True)
+        wfit, wpc = oracle.eval_population(buf, off, x, y, threads=8, per_case=True)
+        assert_same(fit, wfit, "gen 0")
+        for g in range(gens + 1):
+            st = ev.ev_population_stats(c.ctx, pop, depths=True)
+            want = oracle.population_stats(buf, off, wfit, oracle.hits(wpc, y))
+            assert_stats(st, want, f"gen {g}")
+            assert np.array_equal(st["depths"], want["depths"]), f"gen {g} depths"
+            print(f"gen {g}: best {st['best_fitness']:.6g} hits {st['best_hits']} conv {st['converged']} "
+                  f"size {st['mean_size']:.1f} depth {st['mean_depth']:.2f}", flush=True)
+            if g == gens:
+                break
+            kids, capped = ev.ev_generation(c.ctx, pop, seed, g, 7, cap)
+            wbuf, woff, wcap = oracle.generation(buf, off, wfit, 7, seed, g, cap)
+            gbuf, goff = ev.ev_get_trees(c.ctx, kids)
+            assert capped == wcap
+            assert np.array_equal(goff, woff) and np.array_equal(gbuf, wbuf), f"gen {g} trees"
+            fit, _, hits = c.eval(kids, hits=True)
+            wfit, wpc = oracle.eval_population(wbuf, woff, x, y, threads=8, per_case=True)
+            assert_same(fit, wfit, f"gen {g + 1} fitness")
+            assert np.array_equal(hits, oracle.hits(wpc, y)), f"gen {g + 1} hits"
+            ev.ev_free_pop(c.ctx, pop)
+            pop, buf, off = kids, wbuf, woff
+        # statistics without hits, and of a population with NaN fitness
+        c.eval(pop)
+        assert ev.ev_population_stats(c.ctx, pop)["best_hits"] == -1
+
+
+def test_population_statistics_of_special_trees(ev):
+    # depths of combs, a full tree and a single leaf; with x = inf some
+    # trees' errors are inf and others NaN (inf - inf), which rank worst
+    xs = np.array([np.inf, 0.5], np.float32)
+    ys = np.zeros(2, np.float32)
+    trees = [np.array([X], np.uint8), np.array([ADD] * 30 + [X] * 31, np.uint8),
+             np.array([MUL, X] * 25 + [X], np.uint8), np.array([SUB, X, X], np.uint8)]
+    full = workloads.rhh_population(workloads.SEED_BASE + 1, 10, 6, 6)
+    trees.append(full[0][full[1][0]:full[1][1]])
+    off = workloads.offsets_from_sizes([t.size for t in trees])
+    buf = np.concatenate(trees)
+    with ev.Context(xs, ys) as c:
+        pop = c.load(buf, off)
+        fit, pc, hits = c.eval(pop, per_case=True, hits=True)
+        st = ev.ev_population_stats(c.ctx, pop, depths=True)
+    want = oracle.population_stats(buf, off, fit, hits)
+    assert list(st["depths"]) == [0, 30, 25, 1, 6] == list(want["depths"])
+    assert_stats(st, want, "special trees")
+
+
 def test_generation_with_caller_fitness(ev):
     # ev_generation's tournaments over a caller-given device fitness vector:
     # the same children as the oracle's generation over that vector.

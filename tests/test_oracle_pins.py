@@ -468,3 +468,136 @@ def test_tournament_ties_keep_the_earlier_draw(k):
                 seen_tie += len(tied) > 1
                 assert got == want, (k, child, role, cands)
     assert seen_tie > 100  # the rule was exercised, not a unique best
+
+
+# ------------------------------------------------------------ depth, statistics
+
+def ref_depth(tree):
+    """Recursive depth (root 0) written here independently."""
+    def d(i):
+        if tree[i] == X:
+            return 0, i + 1
+        a, j = d(i + 1)
+        b, k = d(j)
+        return 1 + max(a, b), k
+
+    v, end = d(0)
+    assert end == len(tree)
+    return v
+
+
+def test_depth_exhaustive_small_trees_and_closed_forms():
+    for n in range(1, 10, 2):
+        for tree in all_trees(n):
+            assert oracle.depth(tree) == ref_depth(tree)
+    for k in range(1, 40):
+        left = np.array([ADD] * k + [X] * (k + 1), np.uint8)        # op op ... x x ...
+        right = np.array([MUL, X] * k + [X], np.uint8)              # op x op x ... x
+        assert oracle.depth(left) == k and oracle.depth(right) == k
+    # full trees of ramped half-and-half: depth d, 2^(d+1) - 1 nodes
+    buf, off = workloads.rhh_population(workloads.SEED_BASE + 1, 100, 2, 6)
+    for i in range(0, 100):
+        if (i // 5) % 2 == 0:
+            t = buf[off[i]:off[i + 1]]
+            d = 2 + i % 5
+            assert t.size == 2 ** (d + 1) - 1 and oracle.depth(t) == d
+    with pytest.raises(ValueError):
+        oracle.depth(np.array([ADD, X], np.uint8))
+
+
+def test_depth_of_random_trees():
+    rng = np.random.default_rng(5)
+    for i in range(200):
+        n = int(rng.integers(0, 2000)) * 2 + 1
+        t = workloads.random_tree(77, i, n)
+        assert oracle.depth(t) == workloads.depth(t)  # the generator's own left-to-right count
+    # the random-tree law the paper quotes (depth near sqrt(2 pi size))
+    n = 20001
+    ds = [oracle.depth(workloads.random_tree(78, i, n)) for i in range(60)]
+    assert 0.7 < np.mean(ds) / np.sqrt(2 * np.pi * n) < 1.3
+
+
+def test_population_statistics_closed_forms():
+    # fitness with NaN (worst), ties (first kept), and the convergence count
+    trees = [np.array([X], np.uint8), np.array([SUB, X, X], np.uint8), np.array([ADD, ADD, X, X, X], np.uint8),
+             np.array([MUL, X, X], np.uint8), np.array([X], np.uint8)]
+    off = workloads.offsets_from_sizes([t.size for t in trees])
+    buf = np.concatenate(trees)
+    fit = np.array([np.nan, 0.25, 0.125, 0.125, np.inf], np.float32)
+    hits = np.array([0, 3, 7, 9, 1], np.int32)
+    s = oracle.population_stats(buf, off, fit, hits)
+    assert s["best_tree"] == 2 and s["best_fitness"] == 0.125 and s["best_hits"] == 7
+    assert s["best_size"] == 5 and s["best_depth"] == 2 and s["converged"] == 2
+    assert s["min_size"] == 1 and s["max_size"] == 5 and s["mean_size"] == 13 / 5
+    assert s["max_depth"] == 2 and s["min_depth"] == 0 and s["mean_depth"] == (0 + 1 + 2 + 1 + 0) / 5
+    assert s["mean_fitness"] == (0.25 + 0.125 + 0.125) / 3
+    allnan = oracle.population_stats(buf, off, np.full(5, np.nan, np.float32), hits)
+    assert allnan["best_tree"] == 0 and allnan["converged"] == 5 and np.isnan(allnan["mean_fitness"])
+
+
+# ------------------------------------------------- ephemeral random constants
+
+def ref_eval_c(tree, x, consts):
+    """Recursive evaluation with constant leaves (token 6 + i is consts[i])."""
+    x = np.asarray(x, np.float32)
+
+    def ev(i):
+        t = int(tree[i])
+        if t == X:
+            return x.copy(), i + 1
+        if t >= 6:
+            return np.full(x.shape, consts[t - 6], np.float32), i + 1
+        a, j = ev(i + 1)
+        b, k = ev(j)
+        return ref_op(t, a, b), k
+
+    v, end = ev(0)
+    assert end == len(tree)
+    return v
+
+
+def test_constant_table_draw():
+    c = workloads.erc_table(11, 250)
+    assert c.size == 250 and len(set(c.tolist())) == 250
+    k = np.round(c.astype(np.float64) * 1000.0)
+    assert np.all(np.abs(k) <= 1000)
+    assert np.array_equal(c, (k / 1000.0).astype(np.float32))  # each the binary32 nearest k/1000
+
+
+def test_constant_trees_evaluate_to_their_constant():
+    x, y = workloads.cases(48)
+    consts = workloads.erc_table(12, 250)
+    for i in (0, 1, 77, 249):
+        tree = np.array([6 + i], np.uint8)
+        out = oracle.eval_cases(tree, x, consts)
+        assert (out.view(np.uint32) == np.full(48, consts[i], np.float32).view(np.uint32)).all()
+        s = np.float32(0)
+        for v in y:
+            s = np.float32(s + np.float32(abs(np.float32(consts[i] - v))))
+        assert oracle.fitness(out, y) == np.float32(s / np.float32(48))
+    # c - c is 0 and c % c is 1 for a nonzero constant
+    i = int(np.argmax(np.abs(consts)))
+    assert (oracle.eval_cases(np.array([SUB, 6 + i, 6 + i], np.uint8), x, consts) == 0).all()
+    assert (oracle.eval_cases(np.array([DIV, 6 + i, 6 + i], np.uint8), x, consts) == 1).all()
+
+
+def test_constant_rich_trees_against_recursive_reference():
+    x, _ = workloads.cases(48)
+    consts = workloads.erc_table(13, 250)
+    rng = np.random.default_rng(14)
+    for i in range(300):
+        n = int(rng.integers(0, 60)) * 2 + 1
+        t = workloads.with_constants(workloads.random_tree(15, i, n), 16 + i, 250, 0.5)
+        assert same_bits(oracle.eval_cases(t, x, consts), ref_eval_c(t, x, consts)).all()
+
+
+def test_constant_tokens_are_validated_against_the_table():
+    assert oracle.validate(np.array([ADD, 6, 255], np.uint8), 250)[0]
+    assert not oracle.validate(np.array([ADD, 6, 255], np.uint8), 249)[0]
+    assert not oracle.validate(np.array([ADD, X, 5], np.uint8), 250)[0]  # 5 is never a tree token
+    assert not oracle.validate(np.array([ADD, X, 6], np.uint8), 0)[0]
+    with pytest.raises(ValueError):
+        oracle.eval_cases(np.array([ADD, X, 7], np.uint8), np.zeros(4, np.float32), np.zeros(1, np.float32))
+    # crossover and subtree ends treat constants as leaves
+    t = np.array([MUL, 9, ADD, X, 200], np.uint8)
+    assert oracle.subtree_end(t, 1) == 1 and oracle.subtree_end(t, 2) == 4 and oracle.depth(t) == 2

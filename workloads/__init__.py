@@ -58,6 +58,8 @@ def _load():
     lib.wl_random_pop.argtypes = [ctypes.c_uint64, ctypes.c_int32, P, P, ctypes.c_int32]
     lib.wl_depth.argtypes = [P, ctypes.c_uint64, P]
     lib.wl_depth.restype = ctypes.c_int64
+    lib.wl_erc_table.argtypes = [ctypes.c_uint64, ctypes.c_int32, P]
+    lib.wl_relabel_leaves.argtypes = [ctypes.c_uint64, P, ctypes.c_uint64, ctypes.c_int32, ctypes.c_double]
     _lib = lib
     return lib
 
@@ -130,6 +132,22 @@ def depth(tree: np.ndarray) -> int:
     tree = np.ascontiguousarray(tree, dtype=np.uint8)
     scratch = np.empty(tree.size + 2, np.int64)
     return int(lib.wl_depth(_ptr(tree), tree.size, _ptr(scratch)))
+
+
+def erc_table(seed: int, n: int = 250) -> np.ndarray:
+    """n distinct ephemeral random constants from the 2001 values k/1000,
+    k = -1000..1000 (binary32 nearest each)."""
+    out = np.empty(n, np.float32)
+    _load().wl_erc_table(seed, n, _ptr(out))
+    return out
+
+
+def with_constants(buf, seed: int, n_consts: int = 250, p_x: float = 0.5) -> np.ndarray:
+    """A copy of the trees in buf with each x leaf turned into a random
+    constant token (6 + j) with probability 1 - p_x."""
+    b = np.array(buf, dtype=np.uint8, copy=True)
+    _load().wl_relabel_leaves(seed, _ptr(b), b.size, n_consts, p_x)
+    return b
 
 
 # ------------------------------------------------------------ workloads

@@ -254,3 +254,34 @@ int64_t wl_depth(const uint8_t *t, uint64_t n, int64_t *scratch)
     }
     return sp == 0 ? maxd : -1;
 }
+
+/* Ephemeral random constants (Sec. 2.1, Table 1): n distinct values drawn at
+ * random from the 2001 numbers -1.000, -0.999, ..., +1.000, each the
+ * binary32 nearest k/1000 (computed in binary64, rounded once).  A partial
+ * Fisher-Yates shuffle of the 2001 indices. */
+void wl_erc_table(uint64_t seed, int32_t n, float *out)
+{
+    int32_t idx[2001];
+    for (int32_t i = 0; i < 2001; i++) idx[i] = i - 1000;
+    wl_rng r;
+    rng_seed(&r, seed, 0xE2C);
+    if (n > 2001) n = 2001;
+    for (int32_t i = 0; i < n; i++) {
+        int32_t j = i + (int32_t)(rng_next(&r) % (uint64_t)(2001 - i));
+        int32_t t = idx[i]; idx[i] = idx[j]; idx[j] = t;
+        out[i] = (float)((double)idx[i] / 1000.0);
+    }
+}
+
+/* Leaves of the trees in buf[0, len): each X becomes constant token
+ * 6 + j, j uniform over the n_consts constants, with probability 1 - p_x. */
+void wl_relabel_leaves(uint64_t seed, uint8_t *buf, uint64_t len, int32_t n_consts, double p_x)
+{
+    wl_rng r;
+    rng_seed(&r, seed, 0x1EAF);
+    for (uint64_t i = 0; i < len; i++) {
+        if (buf[i] != WL_X || n_consts < 1) continue;
+        if (rng_unit(&r) < p_x) continue;
+        buf[i] = (uint8_t)(6 + (int32_t)(rng_next(&r) % (uint64_t)n_consts));
+    }
+}
