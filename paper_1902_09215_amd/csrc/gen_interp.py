@@ -26,12 +26,18 @@ this once per device and falls back to k_eval if ever needed).  Every
 handler is placed with .org at its exact offset, so a handler that outgrew
 its slot is an assembler error, never a wrong jump.
 
-Register use inside the block:
-  v[12 + m]       top of the operand stack (T); v[12..12+m-1] the entries
+Register use inside the block (W0 = 7):
+  v[W0 + m]       top of the operand stack (T); v[W0..W0+m-1] the entries
                   below it, oldest first.  m = s55.  Relative access uses
                   GPR-index mode (s_set_gpr_idx_on), set once per handler.
-  v[12+VSTACK ..] the ring of slot values read ahead at the skeleton levels
-  v4..v10         temporaries (division), v4 also a staging register
+  v[W0+VSTACK ..] HEAD registers above the window: a division works in
+                  place, its temporaries just above T (relative, like the
+                  stack), so it moves no operand in or out
+  then            the ring of slot values read ahead at the skeleton levels
+  then            x+x, x-x, x*x and x%x, made once per work item: a
+                  function of two x leaves (about one function in four in a
+                  random tree) is then a register move, a division included
+  v4, v5          staging registers
   %[x], %[lane4]  the lane's input value and byte offset (not clobbered)
   s[40:41] code block pointer (128-byte aligned), s[42:43] handler table,
   s[44:45] jump target (the next handler), s[46:47] routine target,
@@ -52,11 +58,15 @@ from __future__ import annotations
 import os
 import sys
 
-VSTACK = int(os.environ.get("EV_VSTACK", "56"))  # register-stack entries: v12 .. v12+VSTACK-1
+W0 = 7  # T at v[W0 + m]; v[W0 - 1 + m] the entry below it
+VSTACK = int(os.environ.get("EV_VSTACK", "48"))  # register-stack entries: v[W0] .. v[W0+VSTACK-1]
 HALF = VSTACK // 2  # entries moved by one spill or fill
-RING = int(os.environ.get("EV_RING", "8"))  # slot values read ahead: v[12+VSTACK] .. v[12+VSTACK+RING-1]
+HEAD = 6  # division temporaries above the window (relative to T)
+RING = int(os.environ.get("EV_RING", "8"))  # slot values read ahead
 assert RING in (4, 8, 16, 32), "the ring size must be a power of two up to 32"
-RING0 = 12 + VSTACK
+RING0 = W0 + VSTACK + HEAD
+XX0 = RING0 + RING  # x+x, x-x, x*x, x%x
+NREG = XX0 + 4
 POS = 32  # positions per 128-byte code block
 NSTRIDE = 32  # bytes per handler at ordinary positions
 TSTRIDE = 64  # bytes per handler at positions 15 and 31 (they also refill)
@@ -83,25 +93,33 @@ def code_of(pos: int, kind: int) -> int:
     return (pos - pos // 16) * NK * NSTRIDE + kind * NSTRIDE
 
 
-# Correctly rounded binary32 division a/b (the sequence hipcc emits for
-# IEEE-mode division on gfx950), then protection: b != 0 ? a/b : 1.0f.
-# a in v4, b in v5, result in v6.
-DIV_BODY = """\
-  v_div_scale_f32 v6, s[56:57], v5, v5, v4
-  v_rcp_f32_e32 v7, v6
-  v_div_scale_f32 v8, vcc, v4, v5, v4
-  v_fma_f32 v9, -v6, v7, 1.0
-  v_fmac_f32_e32 v7, v9, v7
-  v_mul_f32_e32 v9, v8, v7
-  v_fma_f32 v10, -v6, v9, v8
-  v_fmac_f32_e32 v9, v10, v7
-  v_fma_f32 v6, -v6, v9, v8
-  v_div_fmas_f32 v6, v6, v7, v9
-  v_div_fixup_f32 v6, v6, v5, v4
-  v_cmp_neq_f32_e32 vcc, 0, v5
-  s_nop 1
-  v_cndmask_b32_e32 v6, 1.0, v6, vcc
-"""
+def div_body(a: int, b: int, t: int, r: int) -> list[str]:
+    """Correctly rounded binary32 division a/b (the sequence hipcc emits for
+    IEEE-mode division on gfx950), then protection: b != 0 ? a/b : 1.0f.
+    Operands v[a], v[b], temporaries v[t] .. v[t+4], result v[r]; under
+    full GPR-index mode all of them are relative to T."""
+    d, rc, n, e, q = (f"v{t + i}" for i in range(5))
+    A, B, R = f"v{a}", f"v{b}", f"v{r}"
+    return [
+        f"v_div_scale_f32 {d}, s[56:57], {B}, {B}, {A}",
+        f"v_rcp_f32_e32 {rc}, {d}",
+        f"v_div_scale_f32 {n}, vcc, {A}, {B}, {A}",
+        f"v_fma_f32 {e}, -{d}, {rc}, 1.0",
+        f"v_fmac_f32_e32 {rc}, {e}, {rc}",
+        f"v_mul_f32_e32 {e}, {n}, {rc}",
+        f"v_fma_f32 {q}, -{d}, {e}, {n}",
+        f"v_fmac_f32_e32 {e}, {q}, {rc}",
+        f"v_fma_f32 {d}, -{d}, {e}, {n}",
+        f"v_div_fmas_f32 {d}, {d}, {rc}, {e}",
+        f"v_div_fixup_f32 {d}, {d}, {B}, {A}",
+        f"v_cmp_neq_f32_e32 vcc, 0, {B}",
+        "s_nop 1",
+        f"v_cndmask_b32_e32 {R}, 1.0, {d}, vcc",
+    ]
+
+
+FULL = "gpr_idx(SRC0,SRC1,SRC2,DST)"
+T, BELOW, ABOVE, ABOVE2 = f"v{W0}", f"v{W0 - 1}", f"v{W0 + 1}", f"v{W0 + 2}"
 
 
 def next_target(pos: int) -> list[str]:
@@ -138,52 +156,43 @@ def handler(kind: str, pos: int) -> list[str]:
     body: list[str]
     routine = None
     if k in ("OPS0", "OPS1", "OPS2"):
-        # T' = op(T, below): dst v[11+m], src0 v[12+m] (T), src1 v[11+m]
-        body = ["s_set_gpr_idx_on s55, gpr_idx(SRC0,SRC1,DST)", f"{VOP[int(k[3])]} v11, v12, v11",
+        # T' = op(T, below): the entry below becomes T
+        body = ["s_set_gpr_idx_on s55, gpr_idx(SRC0,SRC1,DST)", f"{VOP[int(k[3])]} {BELOW}, {T}, {BELOW}",
                 "s_sub_u32 s55, s55, 1"]
     elif k == "OPS3":
         routine = "divops"
     elif len(k) == 5 and k.startswith("OPS"):
         # two pops in a row: the second works one entry lower
         a, b = int(k[3]), int(k[4])
-        body = ["s_set_gpr_idx_on s55, gpr_idx(SRC0,SRC1,DST)", f"{VOP[a]} v11, v12, v11",
-                f"{VOP[b]} v10, v11, v10", "s_sub_u32 s55, s55, 2"]
+        body = ["s_set_gpr_idx_on s55, gpr_idx(SRC0,SRC1,DST)", f"{VOP[a]} {BELOW}, {T}, {BELOW}",
+                f"{VOP[b]} v{W0 - 2}, {BELOW}, v{W0 - 2}", "s_sub_u32 s55, s55, 2"]
     elif k.startswith("OPX"):
         op = int(k[3])
         # T = op(x, T)
         if op == 3:
             routine = "divopx"
         else:
-            body = ["s_set_gpr_idx_on s55, gpr_idx(SRC1,DST)", f"{VOP[op]} v12, %[x], v12"]
+            body = ["s_set_gpr_idx_on s55, gpr_idx(SRC1,DST)", f"{VOP[op]} {T}, %[x], {T}"]
     elif k.startswith("CH"):
         op = int(k[2])
-        # push T; T = op(x, x)
-        if op == 3:
-            routine = "divch"
-        else:
-            body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"{VOP[op]} v13, %[x], %[x]", "s_add_u32 s55, s55, 1"]
+        # push T; T = op(x, x), made once per work item
+        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {ABOVE}, v{XX0 + op}", "s_add_u32 s55, s55, 1"]
     elif k.startswith("LCH"):
         op = int(k[3])
         # T = op(x, x) with no value below
-        if op == 3:
-            routine = "divlch"
-        else:
-            body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"{VOP[op]} v12, %[x], %[x]"]
+        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {T}, v{XX0 + op}"]
     elif k == "PUSHX":
-        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v13, %[x]", "s_add_u32 s55, s55, 1"]
+        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {ABOVE}, %[x]", "s_add_u32 s55, s55, 1"]
     elif k == "PUSH2X":
-        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v13, %[x]", "v_mov_b32_e32 v14, %[x]",
+        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {ABOVE}, %[x]", f"v_mov_b32_e32 {ABOVE2}, %[x]",
                 "s_add_u32 s55, s55, 2"]
     elif k.startswith("PXCH"):
         op = int(k[4])
         # two pushes of x, then a function of x: push x; push op(x, x)
-        if op == 3:
-            routine = "divpxch"
-        else:
-            body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v13, %[x]", f"{VOP[op]} v14, %[x], %[x]",
-                    "s_add_u32 s55, s55, 2"]
+        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {ABOVE}, %[x]",
+                f"v_mov_b32_e32 {ABOVE2}, v{XX0 + op}", "s_add_u32 s55, s55, 2"]
     elif k == "LOADX":
-        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v12, %[x]"]
+        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {T}, %[x]"]
     elif k in ("OUTT", "OUTBOT", "SPILL", "FILL", "OUTMEM") or k.startswith("PUSHREF") or k.startswith("LOADREF"):
         routine = k.lower()
     elif k == "OUTX":
@@ -201,58 +210,50 @@ def handler(kind: str, pos: int) -> list[str]:
 
 def routines() -> list[str]:
     out = []
-    out += [".Ldivops%=:", "s_set_gpr_idx_on s55, gpr_idx(SRC0)", "v_mov_b32_e32 v4, v12",
-            "v_mov_b32_e32 v5, v11", "s_set_gpr_idx_off"]
-    out += DIV_BODY.splitlines()
-    out += ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v11, v6", "s_sub_u32 s55, s55, 1",
-            "s_setpc_b64 s[44:45]"]
-    out += [".Ldivopx%=:", "s_set_gpr_idx_on s55, gpr_idx(SRC0)", "v_mov_b32_e32 v5, v12", "s_set_gpr_idx_off",
-            "v_mov_b32_e32 v4, %[x]"]
-    out += DIV_BODY.splitlines()
-    out += ["s_set_gpr_idx_on s55, gpr_idx(DST)", "v_mov_b32_e32 v12, v6", "s_setpc_b64 s[44:45]"]
-    for name, dst, inc in (("divch", "v13", 1), ("divlch", "v12", 0), ("divpxch", "v14", 2)):
-        out += [f".L{name}%=:", "s_set_gpr_idx_off", "v_mov_b32_e32 v4, %[x]", "v_mov_b32_e32 v5, %[x]"]
-        out += DIV_BODY.splitlines()
-        out += ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {dst}, v6"]
-        if name == "divpxch":
-            out += ["v_mov_b32_e32 v13, %[x]"]
-        if inc:
-            out += [f"s_add_u32 s55, s55, {inc}"]
-        out += ["s_setpc_b64 s[44:45]"]
+    # T' = T / below (the entry below becomes T), worked in place: every
+    # operand relative to T, the temporaries just above it
+    out += [".Ldivops%=:", f"s_set_gpr_idx_on s55, {FULL}"]
+    out += div_body(W0, W0 - 1, W0 + 1, W0 - 1)
+    out += ["s_sub_u32 s55, s55, 1", "s_setpc_b64 s[44:45]"]
+    # T = x / T: x copied just above T first
+    out += [".Ldivopx%=:", "s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {ABOVE}, %[x]",
+            f"s_set_gpr_idx_mode {FULL}"]
+    out += div_body(W0 + 1, W0, W0 + 2, W0)
+    out += ["s_setpc_b64 s[44:45]"]
     # a value from the previous level's slots (rows read downwards): REF j of
     # a work item takes ring register j % RING, loaded RING REFs earlier, and
     # starts the load of the row REF j + RING will take.  Vector memory
     # operations complete in issue order, so at most RING-1 later loads can
     # still be outstanding when REF j's row has arrived.
     for r in range(RING):
-        for name, dst, inc in ((f"pushref{r}", "v13", True), (f"loadref{r}", "v12", False)):
+        for name, dst, inc in ((f"pushref{r}", ABOVE, True), (f"loadref{r}", T, False)):
             out += [f".L{name}%=:", f"s_waitcnt vmcnt({RING - 1})", "s_set_gpr_idx_on s55, gpr_idx(DST)",
                     f"v_mov_b32_e32 {dst}, v{RING0 + r}", "s_set_gpr_idx_off"]
             if inc:
                 out += ["s_add_u32 s55, s55, 1"]
             out += row_dec(50) + [f"global_load_dword v{RING0 + r}, %[lane4], s[50:51]", "s_setpc_b64 s[44:45]"]
     # T to the next output slot (rows written downwards)
-    out += [".Loutt%=:", "s_set_gpr_idx_on s55, gpr_idx(SRC0)", "v_mov_b32_e32 v4, v12", "s_set_gpr_idx_off"]
+    out += [".Loutt%=:", "s_set_gpr_idx_on s55, gpr_idx(SRC0)", f"v_mov_b32_e32 v4, {T}", "s_set_gpr_idx_off"]
     out += row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]", "s_setpc_b64 s[44:45]"]
     # chunk-end flush of the window entry s59
-    out += [".Loutbot%=:", "s_set_gpr_idx_on s59, gpr_idx(SRC0)", "v_mov_b32_e32 v4, v12", "s_set_gpr_idx_off",
+    out += [".Loutbot%=:", "s_set_gpr_idx_on s59, gpr_idx(SRC0)", f"v_mov_b32_e32 v4, {T}", "s_set_gpr_idx_off",
             "s_add_u32 s59, s59, 1"] + row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]",
                                                      "s_setpc_b64 s[44:45]"]
     # spill: the window's bottom HALF entries to the slab, then shift down
     groups = [(g0, min(16, HALF - g0)) for g0 in range(0, HALF, 16)]
     out += [".Lspill%=:", "s_set_gpr_idx_off"]
     for g0, n in groups:
-        out += [f"global_store_dword %[slane], v{12 + g0 + i}, s[60:61]" + (f" offset:{256 * i}" if i else "")
+        out += [f"global_store_dword %[slane], v{W0 + g0 + i}, s[60:61]" + (f" offset:{256 * i}" if i else "")
                 for i in range(n)]
         out += [f"s_add_u32 s60, s60, {256 * n}", "s_addc_u32 s61, s61, 0"]
-    out += [f"v_mov_b32_e32 v{12 + i}, v{12 + HALF + i}" for i in range(VSTACK - HALF)]
+    out += [f"v_mov_b32_e32 v{W0 + i}, v{W0 + HALF + i}" for i in range(VSTACK - HALF)]
     out += [f"s_sub_u32 s55, s55, {HALF}", "s_setpc_b64 s[44:45]"]
     # fill: shift up, then the top HALF entries of the slab into the bottom
     out += [".Lfill%=:", "s_set_gpr_idx_off"]
-    out += [f"v_mov_b32_e32 v{12 + HALF + i}, v{12 + i}" for i in range(VSTACK - HALF)]
+    out += [f"v_mov_b32_e32 v{W0 + HALF + i}, v{W0 + i}" for i in range(VSTACK - HALF)]
     for g0, n in reversed(groups):
         out += [f"s_sub_u32 s60, s60, {256 * n}", "s_subb_u32 s61, s61, 0"]
-        out += [f"global_load_dword v{12 + g0 + i}, %[slane], s[60:61]" + (f" offset:{256 * i}" if i else "")
+        out += [f"global_load_dword v{W0 + g0 + i}, %[slane], s[60:61]" + (f" offset:{256 * i}" if i else "")
                 for i in range(n)]
     out += ["s_waitcnt vmcnt(0)", f"s_add_u32 s55, s55, {HALF}", "s_setpc_b64 s[44:45]"]
     # chunk-end flush of an entry that lives in the slab (entry s59)
@@ -279,6 +280,12 @@ def generate() -> str:
         "s_cbranch_scc1 .Lnoref%=",
     ] + sum((row_dec(50) + [f"global_load_dword v{RING0 + r}, %[lane4], s[50:51]"] for r in range(RING)), []) + [
         ".Lnoref%=:",
+        # x+x, x-x, x*x and x%x, once per work item (no index mode is on)
+        f"v_add_f32_e32 v{XX0}, %[x], %[x]",
+        f"v_sub_f32_e32 v{XX0 + 1}, %[x], %[x]",
+        f"v_mul_f32_e32 v{XX0 + 2}, %[x], %[x]",
+        f"v_mov_b32_e32 v{W0}, %[x]",
+    ] + div_body(W0, W0, W0 + 1, XX0 + 3) + [
         # the lower half holds the next block's codes when we start in the upper half
         "s_cmp_lt_u32 s59, 16",
         "s_cselect_b32 s58, 0, 0x80",
@@ -324,7 +331,7 @@ def generate() -> str:
 def write(path: str) -> None:
     text = generate()
     body = "\n".join('    "' + ln.replace('"', '\\"') + '\\n"' for ln in text.splitlines())
-    clob = ", ".join([f'"v{i}"' for i in range(4, RING0 + RING)] + [f'"s{i}"' for i in range(40, 64)]
+    clob = ", ".join([f'"v{i}"' for i in range(4, NREG)] + [f'"s{i}"' for i in range(40, 64)]
                      + [f'"s{i}"' for i in range(64, 96)] + ['"m0"', '"vcc"', '"scc"'])
     src = ("// Generated by gen_interp.py: threaded-code interpreter for k_run.\n"
            f"#define EV_CODE_POS {POS}u\n#define EV_CODE_NSTRIDE {NSTRIDE}u\n#define EV_CODE_TSTRIDE {TSTRIDE}u\n"
