@@ -286,6 +286,10 @@ def main():
     ap.add_argument("--lds", type=int, default=0)
     ap.add_argument("--chunk-hi", type=int, default=0, help="work-item size of the skeleton levels")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default work-item sizes and grid instead of the autotuner's choice")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "profiles", "tune_cache.txt"),
+                    help="autotuner cache file read at start (a choice found there skips the search)")
     ap.add_argument("--plain-trees", type=int, default=-1,
                     help="trees evaluated one per launch (default: all 48 of a giant population, else 300)")
     ap.add_argument("--cap", type=int, default=-1,
@@ -321,6 +325,14 @@ def main():
     t_load = time.perf_counter()
     parents = c.load(buf, off)
     t_load = time.perf_counter() - t_load
+    tuning = None
+    if not args.no_autotune and not (args.chunk or args.lds or args.chunk_hi):
+        if os.path.exists(args.tune_cache):
+            ev.ev_tune_cache_load(args.tune_cache)
+        t0 = time.perf_counter()
+        tuning = ev.ev_autotune_ex(c.ctx, parents, 0, 2)
+        tuning["search_s"] = time.perf_counter() - t0
+        print(f"# tuning: {tuning}", file=sys.stderr, flush=True)
     plan = ev.ev_get_plan_info(c.ctx, parents)
     levels = [ev.ev_get_level_info(c.ctx, parents, i) for i in range(plan["levels"])]
     funcs = ev.level_functions(c.ctx, parents)
@@ -413,6 +425,7 @@ def main():
             "trees": M, "nodes": nodes, "fitness_cases": n_cases,
             "step": "generation: tournament(2) + Philox points + subtree crossover + scan/split + eval + fitness",
             "child_size_cap": cap if cap < 2**62 else None,
+            "tuning": tuning,
         },
         "p50_step_ms": pct(step_ms, 50),
         "p99_step_ms": pct(step_ms, 99),

@@ -338,6 +338,39 @@ ev_status ev_set_tuning(ev_ctx *ctx, uint32_t chunk, uint32_t chunk_hi, uint32_t
 ev_status ev_autotune(ev_ctx *ctx, ev_pop pop, int32_t table, int32_t reps, uint32_t *best_chunk,
                       float *best_ms);
 
+/* The autotuner's search (ev_autotune_ex): the work-item size of level 0
+ * and of the skeleton levels, and how many waves per compute unit the
+ * register-stack interpreter's persistent grid runs (fewer waves give each
+ * more of a SIMD's issue slots).  Results never depend on them. */
+typedef struct {
+    uint32_t chunk;         /* tokens per level-0 work item */
+    uint32_t chunk_hi;      /* tokens per work item at the skeleton levels */
+    uint32_t waves_per_cu;  /* interpreter waves per compute unit (0: as many as fit) */
+    uint32_t from_cache;    /* 1: taken from the tuning cache, no search */
+    float ms;               /* median evaluation time with them */
+} ev_tune_choice;
+
+#define EV_AUTOTUNE_NO_CACHE 0x1u /* search even if the cache holds a choice */
+
+/* Coordinate search: the level-0 work-item size among 1024 .. 32768 tokens
+ * (the skeleton levels at twice it), then the skeleton size (1, 2 or 4 times
+ * it), then the waves per compute unit (all that fit, or 4 or 8 fewer), each
+ * timed by `reps` evaluations of pop on case table `table` with device
+ * events.  The choice is applied to the context (and pop is left planned
+ * with it) and kept in a per-process cache keyed by (device architecture,
+ * number of cases, the population's size in powers of two of nodes and of
+ * trees); a later call for a population of the same key takes it from there
+ * unless EV_AUTOTUNE_NO_CACHE.  Errors: EV_EINVAL, EV_ENOTFOUND, EV_ENOMEM,
+ * EV_EDEVICE. */
+ev_status ev_autotune_ex(ev_ctx *ctx, ev_pop pop, int32_t table, int32_t reps, uint32_t flags,
+                         ev_tune_choice *choice);
+
+/* The tuning cache as text (one line per key) to a file, and read back
+ * (merged; later lines win).  Errors: EV_EINVAL (unreadable or unwritable
+ * file, malformed line). */
+ev_status ev_tune_cache_save(const char *path);
+ev_status ev_tune_cache_load(const char *path);
+
 /* Device time in milliseconds of each plan level of the last
  * ev_eval_fitness on this context (levels in evaluation order; the first
  * also holds the counter reset before it).  ms[0..min(cap, levels)) is

@@ -31,7 +31,7 @@ EXPORTS = [
     "ev_get_trees", "ev_free_pop", "ev_eval_fitness", "ev_crossover", "ev_generation", "ev_submit",
     "ev_poll", "ev_wait", "ev_result", "ev_job_timing", "ev_get_plan_info", "ev_get_level_info", "ev_set_tuning",
     "ev_autotune", "ev_last_level_times", "ev_last_timing", "ev_eval_fitness_static", "ev_population_stats",
-    "ev_set_constants",
+    "ev_set_constants", "ev_autotune_ex", "ev_tune_cache_save", "ev_tune_cache_load",
 ]
 
 
@@ -57,6 +57,11 @@ class ev_pop_stats(ctypes.Structure):
                 ("min_size", ctypes.c_uint64), ("max_size", ctypes.c_uint64), ("mean_size", ctypes.c_double),
                 ("best_depth", ctypes.c_uint32), ("min_depth", ctypes.c_uint32), ("max_depth", ctypes.c_uint32),
                 ("pad", ctypes.c_uint32), ("mean_depth", ctypes.c_double)]
+
+
+class ev_tune_choice(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_uint32), ("chunk_hi", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
+                ("from_cache", ctypes.c_uint32), ("ms", ctypes.c_float)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -121,6 +126,9 @@ def load_library(path: str = LIB_PATH):
         "ev_eval_fitness_static": [P, i32, i32, P, P, P],
         "ev_population_stats": [P, i32, ctypes.POINTER(ev_pop_stats), P],
         "ev_set_constants": [P, P, i32],
+        "ev_autotune_ex": [P, i32, i32, i32, u32, ctypes.POINTER(ev_tune_choice)],
+        "ev_tune_cache_save": [ctypes.c_char_p],
+        "ev_tune_cache_load": [ctypes.c_char_p],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -379,6 +387,25 @@ def level_functions(ctx, pop) -> list:
     lv = [ev_get_level_info(ctx, pop, i) for i in range(ev_get_plan_info(ctx, pop)["levels"])]
     f = [(v["tokens"] - v["trees"]) // 2 for v in lv] + [0]
     return [f[i] - f[i + 1] for i in range(len(lv))]
+
+
+EV_AUTOTUNE_NO_CACHE = 0x1
+
+
+def ev_autotune_ex(ctx, pop, table: int = 0, reps: int = 3, flags: int = 0) -> dict:
+    """Search work-item sizes and the interpreter's waves per CU (see ev.h);
+    the choice is applied to the context and cached per process."""
+    t = ev_tune_choice()
+    _check(_lib.ev_autotune_ex(ctx, pop, table, reps, flags, ctypes.byref(t)))
+    return {k: getattr(t, k) for k, _ in ev_tune_choice._fields_}
+
+
+def ev_tune_cache_save(path: str):
+    _check(load_library().ev_tune_cache_save(path.encode()))
+
+
+def ev_tune_cache_load(path: str):
+    _check(load_library().ev_tune_cache_load(path.encode()))
 
 
 EV_TUNE_NO_REGSTACK = 0x1

@@ -3,6 +3,7 @@
 #include "ev_runtime.h"
 
 #include <algorithm>
+#include <tuple>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1361,6 +1362,7 @@ ev_status ev_create(ev_ctx** out, int device, const float* x, const float* y, in
     {
         int bpc = 0;
         if (run_occupancy(&bpc) != hipSuccess || bpc < 1) bpc = 1;
+        c->run_bpc = bpc;
         c->grid_run = bpc * c->num_cus;
     }
     int32_t tid = 0;
@@ -1798,54 +1800,216 @@ ev_status ev_set_tuning(ev_ctx* c, uint32_t chunk, uint32_t chunk_hi, uint32_t l
     return EV_OK;
 }
 
-ev_status ev_autotune(ev_ctx* c, ev_pop pop, int32_t table, int32_t reps, uint32_t* best_chunk, float* best_ms)
+// ------------------------------------------------------------- autotuner
+
+struct TuneKey {
+    std::string arch;
+    int32_t n_cases;
+    int32_t size_bin, tree_bin;
+    bool operator<(const TuneKey& o) const
+    {
+        return std::tie(arch, n_cases, size_bin, tree_bin) < std::tie(o.arch, o.n_cases, o.size_bin, o.tree_bin);
+    }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, ev_tune_choice> g_tune_cache;
+
+static int32_t log2_bin(uint64_t v)
 {
-    if (!c || reps < 1) return fail(EV_EINVAL, "ev_autotune: bad arguments");
+    int32_t b = 0;
+    while (v > 1) {
+        v >>= 1;
+        b++;
+    }
+    return b;
+}
+
+// Apply a choice to the context: work-item sizes and the interpreter's grid.
+static void tune_apply(ev_ctx* c, const ev_tune_choice& t)
+{
+    if (t.chunk) c->chunk = t.chunk;
+    c->chunk_hi = t.chunk_hi;
+    const int w = t.waves_per_cu && (int)t.waves_per_cu < c->run_bpc ? (int)t.waves_per_cu : c->run_bpc;
+    c->grid_run = std::max(1, w) * c->num_cus;
+}
+
+extern "C" ev_status ev_autotune_ex(ev_ctx* c, ev_pop pop, int32_t table, int32_t reps, uint32_t flags,
+                                    ev_tune_choice* choice)
+{
+    if (!c || reps < 1) return fail(EV_EINVAL, "ev_autotune_ex: bad arguments");
     Pop* P = pop_get(c, pop);
     if (!P) return fail(EV_ENOTFOUND, "no population %d", pop);
     CaseTable ct;
     if (!table_get(c, table, &ct)) return fail(EV_EINVAL, "no case table %d", table);
     HIPCHK(hipSetDevice(c->device));
     Exec& x = c->main;
-    // re-plan P with work items of `chunk` tokens
-    auto replan = [&](uint32_t chunk) -> ev_status {
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, c->device));
+    const TuneKey key{prop.gcnArchName, ct.N, log2_bin(std::max<uint64_t>(1, P->total)),
+                      log2_bin((uint64_t)std::max(1, P->M))};
+    // re-plan P with the context's current sizes
+    auto replan = [&]() -> ev_status {
         if (ev_status st = sync(x)) return st;
         for (auto& kv : P->res) rescache_free(c, kv.second);
         P->res.clear();
         plan_free(c, P->plan);
-        const uint32_t keep = c->chunk;
-        c->chunk = chunk;
-        ev_status st = plan_build(c, x, P, nullptr);
-        c->chunk = keep;
-        return st;
+        return plan_build(c, x, P, nullptr);
     };
-    static const uint32_t cand[] = {1024, 2048, 4096, 8192, 16384, 32768, 65536};
-    uint32_t best = 0;
-    float best_t = 0;
-    for (uint32_t chunk : cand) {
-        ev_status st = replan(chunk);
-        if (st == EV_ENOMEM) continue;  // a finer split may not fit: skip it
-        if (st != EV_OK) return st;
+    // median device time of `reps` evaluations (after one that warms up)
+    auto measure = [&](float* med) -> ev_status {
         std::vector<float> t;
-        for (int32_t r = 0; r <= reps; r++) {  // the first run warms the caches
-            if ((st = eval_enqueue(c, x, P, table, P->d_fit, nullptr, true, nullptr)) != EV_OK) return st;
-            if ((st = sync(x)) != EV_OK) return st;
+        for (int32_t r = 0; r <= reps; r++) {
+            ev_status st = eval_enqueue(c, x, P, table, P->d_fit, nullptr, true, nullptr);
+            if (st == EV_OK) st = sync(x);
+            if (st != EV_OK) return st;
             float ms = 0;
             HIPCHK(hipEventElapsedTime(&ms, x.ev0, x.ev1));
             if (r) t.push_back(ms);
         }
         std::sort(t.begin(), t.end());
-        const float med = t[t.size() / 2];
-        if (!best || med < best_t) {
-            best = chunk;
-            best_t = med;
+        *med = t[t.size() / 2];
+        return EV_OK;
+    };
+    if (!(flags & EV_AUTOTUNE_NO_CACHE)) {
+        ev_tune_choice hit{};
+        bool found = false;
+        {
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                hit = it->second;
+                found = true;
+            }
+        }
+        if (found) {
+            tune_apply(c, hit);
+            if (ev_status st = replan()) return st;
+            hit.from_cache = 1;
+            if (choice) *choice = hit;
+            return EV_OK;
         }
     }
-    if (!best) return fail(EV_ENOMEM, "ev_autotune: no candidate plan fits in memory");
-    if (ev_status st = replan(best)) return st;
-    c->chunk = best;
-    if (best_chunk) *best_chunk = best;
-    if (best_ms) *best_ms = best_t;
+    const ev_tune_choice start{c->chunk, c->chunk_hi, 0, 0, 0.0f};
+    ev_tune_choice best = start;
+    bool have = false;
+    // try one setting; keep it if faster.  A setting whose plan does not fit
+    // in memory is skipped.
+    auto trial = [&](ev_tune_choice t, bool plan) -> ev_status {
+        tune_apply(c, t);
+        if (plan) {
+            ev_status st = replan();
+            if (st == EV_ENOMEM) return EV_OK;
+            if (st != EV_OK) return st;
+        }
+        float ms = 0;
+        if (ev_status st = measure(&ms)) {
+            if (st != EV_ENOMEM) return st;
+            // result slots that do not fit beside the rest: skip the setting
+            for (auto& kv : P->res) rescache_free(c, kv.second);
+            P->res.clear();
+            return EV_OK;
+        }
+        t.ms = ms;
+        if (!have || ms < best.ms) {
+            best = t;
+            have = true;
+        }
+        return EV_OK;
+    };
+    static const uint32_t cand[] = {1024, 2048, 4096, 6144, 8192, 12288, 16384, 32768};
+    ev_status st = EV_OK;
+    for (uint32_t ch : cand) {
+        if (ch > 2 * std::max<uint64_t>(64, P->total)) break;  // no split from here on
+        // very large populations: items under 4096 tokens multiply the plan and slots
+        if (P->total > (1ull << 30) && ch < 4096) continue;
+        if ((st = trial(ev_tune_choice{ch, 0, 0, 0, 0.0f}, true)) != EV_OK) break;
+    }
+    if (st == EV_OK && have) {
+        const uint32_t ch = best.chunk;
+        for (uint32_t mul : {1u, 4u})
+            if ((st = trial(ev_tune_choice{ch, ch * mul, 0, 0, 0.0f}, true)) != EV_OK) break;
+    }
+    if (st == EV_OK && have) {
+        // the grid: the plan of the best sizes, fewer waves per CU
+        const ev_tune_choice b = best;
+        tune_apply(c, b);
+        if ((st = replan()) == EV_OK) {
+            for (int less : {4, 8}) {
+                if (c->run_bpc - less < 1) break;
+                ev_tune_choice t = b;
+                t.waves_per_cu = (uint32_t)(c->run_bpc - less);
+                if ((st = trial(t, false)) != EV_OK) break;
+            }
+        }
+    }
+    if (st != EV_OK) {
+        tune_apply(c, start);
+        return st;
+    }
+    if (!have) {
+        tune_apply(c, start);
+        return fail(EV_ENOMEM, "ev_autotune: no candidate plan fits in memory");
+    }
+    tune_apply(c, best);
+    if ((st = replan()) != EV_OK) return st;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    if (choice) *choice = best;
+    return EV_OK;
+}
+
+extern "C" ev_status ev_tune_cache_save(const char* path)
+{
+    if (!path) return fail(EV_EINVAL, "ev_tune_cache_save: NULL path");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(EV_EINVAL, "ev_tune_cache_save: cannot write %s", path);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    std::fprintf(f, "# arch n_cases size_bin tree_bin chunk chunk_hi waves_per_cu ms\n");
+    for (auto& kv : g_tune_cache)
+        std::fprintf(f, "%s %d %d %d %u %u %u %.6g\n", kv.first.arch.c_str(), kv.first.n_cases, kv.first.size_bin,
+                     kv.first.tree_bin, kv.second.chunk, kv.second.chunk_hi, kv.second.waves_per_cu, kv.second.ms);
+    const bool ok = std::fclose(f) == 0;
+    return ok ? EV_OK : fail(EV_EINVAL, "ev_tune_cache_save: write to %s failed", path);
+}
+
+extern "C" ev_status ev_tune_cache_load(const char* path)
+{
+    if (!path) return fail(EV_EINVAL, "ev_tune_cache_load: NULL path");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(EV_EINVAL, "ev_tune_cache_load: cannot read %s", path);
+    std::map<TuneKey, ev_tune_choice> got;
+    char line[512];
+    int ln = 0;
+    while (std::fgets(line, sizeof line, f)) {
+        ln++;
+        if (line[0] == '#' || line[0] == '\n') continue;
+        char arch[256];
+        int n, sb, tb;
+        unsigned ch, hi, w;
+        float ms;
+        if (std::sscanf(line, "%255s %d %d %d %u %u %u %f", arch, &n, &sb, &tb, &ch, &hi, &w, &ms) != 8 || ch < 64 ||
+            (hi != 0 && hi < 64)) {
+            std::fclose(f);
+            return fail(EV_EINVAL, "ev_tune_cache_load: %s line %d is malformed", path, ln);
+        }
+        got[TuneKey{arch, n, sb, tb}] = ev_tune_choice{ch, hi, w, 0, ms};
+    }
+    std::fclose(f);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (auto& kv : got) g_tune_cache[kv.first] = kv.second;
+    return EV_OK;
+}
+
+extern "C" ev_status ev_autotune(ev_ctx* c, ev_pop pop, int32_t table, int32_t reps, uint32_t* best_chunk,
+                                 float* best_ms)
+{
+    ev_tune_choice t{};
+    ev_status st = ev_autotune_ex(c, pop, table, reps, EV_AUTOTUNE_NO_CACHE, &t);
+    if (st != EV_OK) return st;
+    if (best_chunk) *best_chunk = t.chunk;
+    if (best_ms) *best_ms = t.ms;
     return EV_OK;
 }
 

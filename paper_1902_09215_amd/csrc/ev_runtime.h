@@ -156,6 +156,7 @@ struct ev_ctx {
     int num_cus = 0;
     int grid_eval[2] = {0, 0};
     int grid_run = 0;
+    int run_bpc = 0;  // interpreter waves per compute unit that fit (occupancy)
     bool use_run = true;  // register-stack kernel for the items that fit it
     bool run_ok = true;   // the register-stack kernel can run here (probed at creation)
     bool test_fail_check = false;  // EV_TUNE_TEST_FAIL_CHECK

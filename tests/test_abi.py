@@ -76,3 +76,29 @@ def test_binding_constants_match_header():
     assert not missing, f"constants the binding does not define: {missing}"
     wrong = sorted(n for n in bound if n in vals and bound[n] != vals[n])
     assert not wrong, f"constants that disagree with the header: {wrong}"
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libev.so not built")
+def test_tuning_cache_file_round_trip(tmp_path):
+    # the autotuner's cache as text: loaded, saved and loaded again unchanged
+    # (host code only), and a malformed line refused
+    import paper_1902_09215_amd as ev
+
+    ev.load_library()
+    src = tmp_path / "tune.txt"
+    src.write_text("# arch n_cases size_bin tree_bin chunk chunk_hi waves_per_cu ms\n"
+                   "gfx950:sramecc+:xnack- 48 34 5 8192 16384 20 157.5\n"
+                   "gfx950:sramecc+:xnack- 1024 20 3 2048 0 0 1.25\n")
+    ev.ev_tune_cache_load(str(src))
+    out = tmp_path / "out.txt"
+    ev.ev_tune_cache_save(str(out))
+    lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
+    assert "gfx950:sramecc+:xnack- 48 34 5 8192 16384 20 157.5" in lines
+    assert "gfx950:sramecc+:xnack- 1024 20 3 2048 0 0 1.25" in lines
+    bad = tmp_path / "bad.txt"
+    bad.write_text("gfx950 48 34 five 8192 16384 20 1.0\n")
+    with pytest.raises(ev.EvError) as e:
+        ev.ev_tune_cache_load(str(bad))
+    assert e.value.code == ev.EV_EINVAL
+    with pytest.raises(ev.EvError):
+        ev.ev_tune_cache_load(str(tmp_path / "missing.txt"))

@@ -756,13 +756,31 @@ def test_autotune_keeps_results(ev):
         pop = c.load(buf, off)
         fit0, pc0 = c.eval(pop, per_case=True)
         chunk, ms = ev.ev_autotune(c.ctx, pop, 0, 3)
-        assert chunk in (1024, 2048, 4096, 8192, 16384, 32768, 65536) and ms > 0
+        assert chunk in (1024, 2048, 4096, 6144, 8192, 12288, 16384, 32768) and ms > 0
         fit1, pc1 = c.eval(pop, per_case=True)
         pop2 = c.load(buf, off)  # planned with the tuned size
         fit2, _ = c.eval(pop2)
+        # the full search (sizes at both levels, waves per CU), then the cache
+        t = ev.ev_autotune_ex(c.ctx, pop, 0, 2, ev.EV_AUTOTUNE_NO_CACHE)
+        assert t["from_cache"] == 0 and t["ms"] > 0 and t["chunk"] >= 1024
+        assert t["chunk_hi"] in (0, t["chunk"], 4 * t["chunk"])
+        fit3, pc3 = c.eval(pop, per_case=True)
+        again = ev.ev_autotune_ex(c.ctx, pop2, 0, 2)
+        assert again["from_cache"] == 1
+        assert (again["chunk"], again["chunk_hi"], again["waves_per_cu"]) == (t["chunk"], t["chunk_hi"],
+                                                                             t["waves_per_cu"])
+        fit4, pc4 = c.eval(pop2, per_case=True)
+        # children planned and evaluated with the tuned grid
+        ev.ev_set_tuning(c.ctx, 4096)
+        k, _ = ev.ev_generation(c.ctx, pop, 7, 0, 2, 10**7)
+        fk, _ = c.eval(k)
+        kb, ko = ev.ev_get_trees(c.ctx, k)
     assert_same(fit0, fit1, "fitness after autotune")
     assert_same(pc0, pc1, "per-case after autotune")
     assert_same(fit0, fit2, "fitness of a population planned with the tuned size")
+    assert_same(pc0, pc3, "per-case after the full search")
+    assert_same(pc0, pc4, "per-case with the cached choice")
+    assert_same(fk, oracle.eval_population(kb, ko, x, y, threads=8), "children after tuning")
 
 
 def test_serving_results_same_alone_and_mixed(ev):
