@@ -288,7 +288,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default work-item sizes and grid instead of the autotuner's choice")
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "profiles", "tune_cache.txt"),
+    ap.add_argument("--tune-cache", default="",
                     help="autotuner cache file read at start (a choice found there skips the search)")
     ap.add_argument("--plain-trees", type=int, default=-1,
                     help="trees evaluated one per launch (default: all 48 of a giant population, else 300)")
@@ -327,7 +327,7 @@ def main():
     t_load = time.perf_counter() - t_load
     tuning = None
     if not args.no_autotune and not (args.chunk or args.lds or args.chunk_hi):
-        if os.path.exists(args.tune_cache):
+        if args.tune_cache and os.path.exists(args.tune_cache):
             ev.ev_tune_cache_load(args.tune_cache)
         t0 = time.perf_counter()
         tuning = ev.ev_autotune_ex(c.ctx, parents, 0, 2)
