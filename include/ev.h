@@ -187,6 +187,47 @@ ev_status ev_crossover(ev_ctx *ctx, ev_pop mums_pop, ev_pop dads_pop, const int3
 ev_status ev_generation(ev_ctx *ctx, ev_pop parents, const float *fitness, uint64_t seed, uint64_t gen,
                         int32_t tournament, uint64_t size_cap, ev_pop *out_children, int32_t *n_capped);
 
+/* Sec. 2.3's generational loop: n_gen generations of ev_generation, each
+ * followed by the children's evaluation on case table `table`, starting
+ * from `parents` (fitness as in ev_generation: a device pointer to their
+ * values, or NULL for those of their last ev_eval_fitness) at generation
+ * number gen0.  Generation i uses gen0 + i in its draws, so the trees and
+ * fitness values are those of the loop written out with ev_generation and
+ * ev_eval_fitness, bit for bit.
+ *
+ * Each generation (selection, crossover, the children's split plan, their
+ * evaluation and fitness) is replayed from a HIP graph captured once, with
+ * no host wait inside it: buffers are sized for capacities (twice the sizes
+ * last seen) and the plan is made on the device.  A generation that exceeds
+ * a capacity is void and done again on the host-driven path; the graphs are
+ * then captured again for new capacities.  Graphs and buffers stay with the
+ * context for the next call with the same population size, case table,
+ * tournament, seed, size cap and tuning (ev_destroy frees them).  With
+ * EV_EVOLVE_NO_GRAPH every generation runs on the host-driven path (the
+ * plain form); so does a context with ephemeral constants.
+ *
+ * Outputs: *out the last generation as a new population (planned, its
+ * fitness as of its evaluation); fit_history[n_gen * n_trees] (host,
+ * nullable) each generation's children's fitness; capped_history[n_gen]
+ * (host, nullable) each generation's children over size_cap; *report
+ * (nullable) the counts of replayed and fallen-back generations and
+ * captures, and the loop's wall time.  Errors: as ev_generation and
+ * ev_eval_fitness; a graph that cannot be captured gives EV_EDEVICE. */
+typedef struct {
+    int32_t generations;  /* generations run */
+    int32_t replayed;     /* ... replayed from a captured graph */
+    int32_t fallbacks;    /* ... done again on the host-driven path (a capacity was exceeded) */
+    int32_t captures;     /* graphs captured */
+    uint64_t capped;      /* children over the size cap, over all generations */
+    double ms;            /* wall time of the call */
+    double ms_capture;    /* of which capturing and instantiating graphs */
+} ev_evolve_report;
+#define EV_EVOLVE_NO_GRAPH 0x1u
+#define EV_EVOLVE_TEST_TIGHT 0x2u /* capacities of exactly the sizes last seen: exercises the fallback */
+ev_status ev_evolve(ev_ctx *ctx, ev_pop parents, const float *fitness, int32_t table, uint64_t seed,
+                    uint64_t gen0, int32_t n_gen, int32_t tournament, uint64_t size_cap, uint32_t flags,
+                    ev_pop *out, float *fit_history, int32_t *capped_history, ev_evolve_report *report);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):
  * ev_eval_fitness of a population with device outputs (as with

@@ -31,7 +31,7 @@ EXPORTS = [
     "ev_get_trees", "ev_free_pop", "ev_eval_fitness", "ev_crossover", "ev_generation", "ev_submit",
     "ev_poll", "ev_wait", "ev_result", "ev_job_timing", "ev_get_plan_info", "ev_get_level_info", "ev_set_tuning",
     "ev_autotune", "ev_last_level_times", "ev_last_timing", "ev_eval_fitness_static", "ev_population_stats",
-    "ev_set_constants", "ev_autotune_ex", "ev_tune_cache_save", "ev_tune_cache_load",
+    "ev_set_constants", "ev_autotune_ex", "ev_tune_cache_save", "ev_tune_cache_load", "ev_evolve",
 ]
 
 
@@ -49,6 +49,12 @@ class ev_plan_info(ctypes.Structure):
 class ev_level_info(ctypes.Structure):
     _fields_ = [("tokens", ctypes.c_uint64), ("trees", ctypes.c_uint32), ("items", ctypes.c_uint32),
                 ("slots", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
+class ev_evolve_report(ctypes.Structure):
+    _fields_ = [("generations", ctypes.c_int32), ("replayed", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
+                ("captures", ctypes.c_int32), ("capped", ctypes.c_uint64), ("ms", ctypes.c_double),
+                ("ms_capture", ctypes.c_double)]
 
 
 class ev_pop_stats(ctypes.Structure):
@@ -129,6 +135,8 @@ def load_library(path: str = LIB_PATH):
         "ev_autotune_ex": [P, i32, i32, i32, u32, ctypes.POINTER(ev_tune_choice)],
         "ev_tune_cache_save": [ctypes.c_char_p],
         "ev_tune_cache_load": [ctypes.c_char_p],
+        "ev_evolve": [P, i32, P, i32, u64, u64, i32, i32, u64, u32, ctypes.POINTER(i32), P, P,
+                      ctypes.POINTER(ev_evolve_report)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -319,6 +327,23 @@ def ev_generation(ctx, parents, seed: int, gen: int, tournament: int = 2, size_c
     return out.value, capped.value
 
 
+def ev_evolve(ctx, parents, seed: int, gen0: int, n_gen: int, tournament: int = 2, size_cap: int = 2**63,
+              table: int = 0, flags: int = 0, fitness=None, history: bool = True):
+    """n_gen generations from parents; returns (population, fitness history
+    [n_gen, n_trees] or None, capped counts [n_gen] or None, report dict).
+    fitness: a torch CUDA tensor of the parents' fitness, or None for the
+    values of their last evaluation."""
+    m = ctypes.c_int32()
+    _check(_lib.ev_pop_info(ctx, parents, ctypes.byref(m), None))
+    fh = np.zeros((n_gen, m.value), np.float32) if history else None
+    ch = np.zeros(n_gen, np.int32) if history else None
+    out = ctypes.c_int32()
+    rep = ev_evolve_report()
+    _check(_lib.ev_evolve(ctx, parents, _ptr(fitness), table, seed, gen0, n_gen, tournament, size_cap, flags,
+                          ctypes.byref(out), _ptr(fh), _ptr(ch), ctypes.byref(rep)))
+    return out.value, fh, ch, {k: getattr(rep, k) for k, _ in ev_evolve_report._fields_}
+
+
 def ev_submit_eval(ctx, buf, off, table: int = 0) -> int:
     buf = np.ascontiguousarray(buf, np.uint8)
     off = np.ascontiguousarray(off, np.uint64)
@@ -390,6 +415,8 @@ def level_functions(ctx, pop) -> list:
 
 
 EV_AUTOTUNE_NO_CACHE = 0x1
+EV_EVOLVE_NO_GRAPH = 0x1
+EV_EVOLVE_TEST_TIGHT = 0x2
 
 
 def ev_autotune_ex(ctx, pop, table: int = 0, reps: int = 3, flags: int = 0) -> dict:

@@ -13,6 +13,8 @@ constexpr uint32_t MAX_CONSTS = 250;
 // (not an error) a constant seen
 constexpr uint32_t BAD_TOKEN = 1u, HAS_CONST = 4u;
 
+struct GLevel;  // a level's live counts in a device-made plan (below)
+
 // Register-stack entries of k_run (the interpreter's VGPR window).
 #include "ev_interp.inc"
 constexpr uint32_t EV_VSTACK_ENTRIES = EV_VSTACK;
@@ -110,6 +112,7 @@ struct FitArgs {
     float* fit;
     float* per_case;
     int32_t* hits;  // nullable: per tree, the cases within 0.01 of the target
+    const GLevel* gl;  // nullable: a device-made plan's levels (their slot counts replace n_out)
 };
 
 struct SegFn {
@@ -162,6 +165,7 @@ struct RunArgs {
     uint32_t* flag;         // set to 1 if the interpreter's table cannot be used (see gen_interp.py)
     uint32_t refs;          // 1 at the skeleton levels: REF slots are read ahead
     const uint32_t* verdict;  // the validator's flags for these code streams: nonzero runs nothing
+    const GLevel* gl;         // nullable: a device-made level (its item count and spill rows replace n_items, slab_entries)
 };
 
 // A work item as the evaluator sees it (32 bytes).
@@ -226,6 +230,55 @@ struct PopStatsDev {
     double sum_size;
     uint64_t min_size, max_size;
     uint32_t best, n_finite, converged, pad;
+};
+
+// A generation replayed from a captured graph (Sec. 2.3's loop with no
+// host wait inside a generation) plans its children on the device.  Its
+// buffers are sized for capacities fixed at capture and its launches for
+// those capacities; each level's live counts are made on the device
+// (k_g_begin, k_g_end) and the kernels take them from the level's GLevel,
+// doing nothing past them.  A count over its capacity voids the generation
+// (GStatus), which the host then runs again on the host-driven path.
+struct GLevel {
+    uint32_t nt, n, n_seg;   // the level's trees, work items and structure segments
+    uint32_t record;         // the count pass records codes (fixed at capture)
+    uint32_t record_ovf;     // a recording region overflowed: emit and check instead of place
+    uint32_t slab_entries;   // spill rows per wave of k_run
+    uint32_t any;            // some tree goes on to the next level
+    uint32_t pad;
+    uint64_t tokens, prev_out;  // the level's tokens; the previous level's slots
+    uint64_t so, sf, sc;        // slots, next skeleton tokens, codes (with each item's padding)
+};
+
+// A tree's state between the levels of a device-made plan.
+struct GTree {
+    uint64_t rs, rl, prev_len;  // its range in the level's sequence; its length a level before
+    uint32_t ref_base, active;  // its first input slot; it has work at the level
+};
+
+// A level's capacities (fixed at capture).
+struct GCap {
+    uint64_t n, n_seg, so, sf, sc;
+    uint32_t slab, pad;
+};
+
+// Why a replayed generation is void (GStatus.poison bits).
+enum : uint32_t {
+    G_OVF_BYTES = 1u,       // the children's bytes or copy pieces
+    G_OVF_ITEMS = 2u,       // work items or segments of a level
+    G_OVF_SIZES = 4u,       // slots, skeleton tokens or codes of a level
+    G_OVF_SLAB = 8u,        // spill rows
+    G_OVF_LEVELS = 16u,     // more levels than captured
+    G_MALFORMED = 32u,      // a child is not a valid prefix tree
+    G_INCONSISTENT = 64u,   // input slots out of range
+    G_CONSTS = 128u,        // a constant token (not planned for the register-stack kernel)
+    G_INVALID_CODES = 256u  // a level's code streams failed validation
+};
+
+struct GStatus {
+    uint32_t poison, level;  // the reasons; the level of the first
+    uint32_t levels, pad;    // levels the plan used
+    uint64_t child_bytes, capped;
 };
 
 struct XoPlan {

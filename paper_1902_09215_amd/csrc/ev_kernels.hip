@@ -43,6 +43,12 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t n, uint32_t v)
 // by the stream's own compute queue: a small transfer then needs no handoff
 // to a DMA engine and back (which costs more than the copy).  16-byte moves
 // when both ends and the size allow, else 4-byte, else bytes.
+__global__ void k_fill_u8(uint8_t* __restrict__ p, uint64_t n, uint8_t v)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ void k_copy(uint8_t* __restrict__ dst, const uint8_t* __restrict__ src, uint64_t n, uint32_t w)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -430,8 +436,9 @@ __device__ uint32_t run_segment(const uint8_t* __restrict__ seq, uint64_t start,
 // also emits the chunk's final flush (a slot per value left), so it is kept
 // short to keep its lane from lagging behind the wave.
 __global__ void k_seg_build(const ChunkIn* __restrict__ ch, const ChunkSegs* __restrict__ cg, uint32_t n,
-                            uint32_t seg_len, uint32_t head, SegIn* __restrict__ seg)
+                            uint32_t seg_len, uint32_t head, SegIn* __restrict__ seg, const GLevel* __restrict__ gl)
 {
+    if (gl) n = gl->n;
     const uint32_t j = blockIdx.x;
     if (j >= n) return;
     const ChunkIn c = ch[j];
@@ -456,8 +463,9 @@ __device__ __forceinline__ uint32_t seg_count(uint32_t len, uint32_t seg_len, ui
 __global__ __launch_bounds__(64) void k_plan_chunks(const TreeLvl* __restrict__ trees, uint32_t n_trees,
                                                     uint32_t seg_len, uint32_t head, ChunkIn* __restrict__ ch,
                                                     ChunkSegs* __restrict__ cg, uint32_t* __restrict__ err_init,
-                                                    uint32_t n_err)
+                                                    uint32_t n_err, const GLevel* __restrict__ gl)
 {
+    if (gl) n_trees = gl->nt;
     const uint32_t i = blockIdx.x;
     if (i == 0 && err_init)  // the validator's words of every level: no flags, no failing segment
         for (uint32_t k = threadIdx.x; k < n_err; k += blockDim.x) err_init[k] = (k & 1u) ? UINT32_MAX : 0u;
@@ -486,8 +494,12 @@ __global__ __launch_bounds__(64) void k_plan_trees(const TreeLvl* __restrict__ t
                                                    const ChunkStat* __restrict__ cs, uint32_t level, uint64_t prev_out,
                                                    uint64_t* __restrict__ code_loc, uint64_t* __restrict__ out_loc,
                                                    uint64_t* __restrict__ frag_loc, uint32_t* __restrict__ in_end,
-                                                   TreeSum* __restrict__ sum)
+                                                   TreeSum* __restrict__ sum, const GLevel* __restrict__ gl)
 {
+    if (gl) {
+        n_trees = gl->nt;
+        prev_out = gl->prev_out;
+    }
     const uint32_t i = blockIdx.x;
     if (i >= n_trees) return;
     const int lane = (int)threadIdx.x;
@@ -553,8 +565,10 @@ __global__ __launch_bounds__(64) void k_plan_trees(const TreeLvl* __restrict__ t
 // Rounds of 1024 consecutive trees (coalesced reads), each scanned by wave
 // shuffles and the waves' totals, on top of the previous rounds' total.
 __global__ __launch_bounds__(1024) void k_plan_bases(const TreeLvl* __restrict__ trees, uint32_t n_trees,
-                                                     const TreeSum* __restrict__ sum, TreeBase* __restrict__ base)
+                                                     const TreeSum* __restrict__ sum, TreeBase* __restrict__ base,
+                                                     const GLevel* __restrict__ gl)
 {
+    if (gl) n_trees = gl->nt;
     __shared__ uint64_t wo[16], wf[16], wc[16], carry[3];
     const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
     if (t == 0) carry[0] = carry[1] = carry[2] = 0;
@@ -613,8 +627,13 @@ __global__ void k_plan_items(const ChunkIn* __restrict__ ch, uint32_t n, const T
                              const uint32_t* __restrict__ bucket_start, uint64_t* __restrict__ code_begin,
                              uint64_t* __restrict__ frag_end, RunChunk* __restrict__ run, EvalChunk* __restrict__ slow,
                              uint32_t* __restrict__ code_tail, uint8_t* __restrict__ frag_tail,
-                             const uint32_t* __restrict__ item_at)
+                             const uint32_t* __restrict__ item_at, const GLevel* __restrict__ gl)
 {
+    if (gl) {  // the tails follow the level's live totals
+        n = gl->n;
+        if (code_tail) code_tail += gl->sc;
+        if (frag_tail) frag_tail += gl->sf;
+    }
     if (blockIdx.x == 0) {
         // the padding after the level's code stream (zeros) and after the
         // next level's skeleton (0xFF): the readers' wide loads reach it
@@ -745,8 +764,10 @@ __global__ __launch_bounds__(64) void k_reuse_chunks(const TreeReuse* __restrict
 // know: a counting sort on the length's bit count on the device.  Each wave
 // takes one atomic per distinct bucket among its lanes; the order inside a
 // bucket does not matter.
-__global__ void k_item_hist(const ChunkIn* __restrict__ ch, uint32_t n, uint32_t* __restrict__ hist)
+__global__ void k_item_hist(const ChunkIn* __restrict__ ch, uint32_t n, uint32_t* __restrict__ hist,
+                            const GLevel* __restrict__ gl)
 {
+    if (gl) n = gl->n;
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = j < n;
     const uint32_t b = in ? len_bucket(ch[j].len) : EV_LEN_BUCKETS;
@@ -773,8 +794,9 @@ __global__ void k_item_cursor(uint32_t* __restrict__ hist)
 }
 
 __global__ void k_item_place(const ChunkIn* __restrict__ ch, uint32_t n, uint32_t* __restrict__ cursor,
-                             uint32_t* __restrict__ item_at)
+                             uint32_t* __restrict__ item_at, const GLevel* __restrict__ gl)
 {
+    if (gl) n = gl->n;
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = j < n;
     const uint32_t b = in ? len_bucket(ch[j].len) : EV_LEN_BUCKETS;
@@ -835,8 +857,9 @@ __global__ __launch_bounds__(256) void k_reuse_copy(const uint32_t* __restrict__
 
 // Per segment: its cnt map (a, b), validity counters and input references.
 __global__ void k_seg_fn(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs, uint32_t n,
-                         SegFn* __restrict__ out, uint32_t ref_ok, uint32_t n_consts)
+                         SegFn* __restrict__ out, uint32_t ref_ok, uint32_t n_consts, const GLevel* __restrict__ gl)
 {
+    if (gl) n = gl->n_seg;
     const uint32_t si = blockIdx.x * blockDim.x + threadIdx.x;
     if (si >= n) return;
     const SegIn g = segs[si];
@@ -881,8 +904,9 @@ __global__ void k_seg_fn(const uint8_t* __restrict__ seq, const SegIn* __restric
 // over segments k.. n-1, which reading order accumulates.
 __global__ __launch_bounds__(64) void k_seg_scan(const ChunkSegs* __restrict__ cseg, uint32_t n,
                                                  const SegFn* __restrict__ fn, SegStart* __restrict__ st,
-                                                 ChunkStat* __restrict__ cstat)
+                                                 ChunkStat* __restrict__ cstat, const GLevel* __restrict__ gl)
 {
+    if (gl) n = gl->n;
     const uint32_t ci = blockIdx.x;
     if (ci >= n) return;
     const int lane = (int)threadIdx.x;
@@ -960,8 +984,9 @@ __device__ __forceinline__ uint64_t rec_frags_at(uint32_t si, uint32_t seg_len) 
 __global__ void k_seg_count(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs, uint32_t n,
                             const SegStart* __restrict__ st, SegCount* __restrict__ out, uint8_t* __restrict__ rk,
                             uint8_t* __restrict__ rf, SegRec* __restrict__ rec, uint32_t* __restrict__ ovf,
-                            uint32_t seg_len)
+                            uint32_t seg_len, const GLevel* __restrict__ gl)
 {
+    if (gl) n = gl->n_seg;
     const uint32_t si = blockIdx.x * blockDim.x + threadIdx.x;
     if (si >= n) return;
     const SegIn g = segs[si];
@@ -991,8 +1016,9 @@ __global__ __launch_bounds__(64) void k_seg_chunk(const ChunkSegs* __restrict__ 
                                                   const SegCount* __restrict__ cnt, ChunkStat* __restrict__ cstat,
                                                   const uint64_t* __restrict__ code_begin,
                                                   const uint64_t* __restrict__ frag_end, uint64_t* __restrict__ seg_code,
-                                                  uint64_t* __restrict__ seg_frag)
+                                                  uint64_t* __restrict__ seg_frag, const GLevel* __restrict__ gl)
 {
+    if (gl) n = gl->n;
     const uint32_t ci = blockIdx.x;
     if (ci >= n) return;
     const int lane = (int)threadIdx.x;
@@ -1073,8 +1099,13 @@ __device__ __forceinline__ void emit_segment(const uint8_t* __restrict__ seq, co
 
 __global__ void k_seg_emit(const uint8_t* __restrict__ seq, const SegIn* __restrict__ segs, uint32_t n,
                            const SegStart* __restrict__ st, const uint64_t* __restrict__ seg_code,
-                           const uint64_t* __restrict__ seg_frag, uint8_t* __restrict__ dst, uint32_t* __restrict__ codes)
+                           const uint64_t* __restrict__ seg_frag, uint8_t* __restrict__ dst, uint32_t* __restrict__ codes,
+                           const GLevel* __restrict__ gl)
 {
+    if (gl) {  // the fallback of a recording level only
+        if (gl->record && !gl->record_ovf) return;
+        n = gl->n_seg;
+    }
     const uint32_t si = blockIdx.x * blockDim.x + threadIdx.x;
     if (si >= n) return;
     emit_segment(seq, segs, si, st, seg_code, seg_frag, dst, codes);
@@ -1099,8 +1130,16 @@ __global__ __launch_bounds__(64) void k_seg_place(const SegIn* __restrict__ segs
                                                   const uint64_t* __restrict__ seg_frag, const uint8_t* __restrict__ rk,
                                                   const uint8_t* __restrict__ rf, uint32_t* __restrict__ codes,
                                                   uint64_t n_codes, uint8_t* __restrict__ dst, uint64_t n_frag,
-                                                  uint32_t slab_entries, uint32_t* __restrict__ err, uint32_t seg_len)
+                                                  uint32_t slab_entries, uint32_t* __restrict__ err, uint32_t seg_len,
+                                                  const GLevel* __restrict__ gl)
 {
+    if (gl) {  // not when a recording region overflowed (emit and check run instead)
+        if (gl->record_ovf) return;
+        n = gl->n_seg;
+        n_codes = gl->sc;
+        n_frag = gl->sf;
+        slab_entries = gl->slab_entries;
+    }
     const uint32_t lane = threadIdx.x;
     const uint64_t lt = (1ull << lane) - 1ull;  // the lanes before this one
     for (uint32_t si = blockIdx.x; si < n; si += gridDim.x) {
@@ -1253,8 +1292,14 @@ __global__ __launch_bounds__(64) void k_seg_place(const SegIn* __restrict__ segs
 // gave the segment.  Anything else fails the plan before a code runs.
 __global__ void k_seg_check(const uint32_t* __restrict__ codes, const SegIn* __restrict__ segs, uint32_t n,
                             const SegStart* __restrict__ st, const uint64_t* __restrict__ seg_code,
-                            const SegCount* __restrict__ cnt, uint32_t slab_entries, uint32_t* __restrict__ err)
+                            const SegCount* __restrict__ cnt, uint32_t slab_entries, uint32_t* __restrict__ err,
+                            const GLevel* __restrict__ gl)
 {
+    if (gl) {  // with emission (the fallback of a recording level)
+        if (gl->record && !gl->record_ovf) return;
+        n = gl->n_seg;
+        slab_entries = gl->slab_entries;
+    }
     const uint32_t si = blockIdx.x * blockDim.x + threadIdx.x;
     if (si >= n) return;
     const uint64_t b = seg_code[si];
@@ -1523,7 +1568,7 @@ __global__ void k_fitness(FitArgs a)
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.M) return;
     const uint32_t lv = a.fin[2 * t], slot = a.fin[2 * t + 1];
-    if (lv >= a.n_levels || slot >= a.n_out[lv]) {
+    if (lv >= a.n_levels || slot >= (a.gl ? a.gl[lv].so : (uint64_t)a.n_out[lv])) {
         // no such slot: a plan inconsistency, reported as NaN, never read
         a.fit[t] = __int_as_float(0x7fc00000);
         if (a.hits) a.hits[t] = 0;
@@ -1641,8 +1686,13 @@ __device__ __forceinline__ u32x4 load16_at(const uint8_t* __restrict__ p)
 
 __global__ void k_xo_copy(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
                           const XoPlan* __restrict__ plan, const uint64_t* __restrict__ off, uint32_t n_children,
-                          uint8_t* __restrict__ dst, uint8_t* __restrict__ pad, uint32_t pad_len)
+                          uint8_t* __restrict__ dst, uint8_t* __restrict__ pad, uint32_t pad_len,
+                          const uint32_t* __restrict__ stop)
 {
+    // with stop (a replayed generation): nothing when the children do not
+    // fit their buffer, and the padding goes after their total
+    if (stop && *stop) return;
+    if (!pad) pad = dst + off[n_children];
     if (blockIdx.x == 0)  // the buffer's padding of 0xFF after the children
         for (uint32_t i = threadIdx.x; i < pad_len; i += blockDim.x) pad[i] = 0xFF;
     // block b copies piece b: the child j with pf[j] <= b < pf[j + 1]
@@ -1846,10 +1896,11 @@ __device__ __forceinline__ uint64_t mulhi_u64(uint64_t u, uint64_t n) { return _
 
 __global__ void k_select(const float* __restrict__ fit, const uint64_t* __restrict__ off, uint32_t M, int32_t k,
                          uint64_t seed, uint64_t gen, int32_t* __restrict__ mum, int32_t* __restrict__ dad,
-                         uint64_t* __restrict__ p, uint64_t* __restrict__ q)
+                         uint64_t* __restrict__ p, uint64_t* __restrict__ q, const uint64_t* __restrict__ gen_at)
 {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
+    if (gen_at) gen = *gen_at;  // a replayed generation's number
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const int32_t mm = tournament(fit, M, k, k0, k1, gen, j, 0);
     const int32_t dd = tournament(fit, M, k, k0, k1, gen, j, 1);
@@ -2020,6 +2071,10 @@ __global__ __launch_bounds__(64) void k_run(RunArgs a)
     // a level whose code streams failed validation runs none of them (the
     // host reports the failure when it reads the verdict)
     if (a.verdict && *a.verdict) return;
+    if (a.gl) {  // a device-made level: its live item count and spill rows
+        a.n_items = a.gl->n * a.n_cb;
+        a.slab_entries = a.gl->slab_entries;
+    }
     const uint32_t lane = threadIdx.x;
     const_u4p chunks = (const_u4p)(global_u4p)(const void*)a.chunks;
     // this wave's spill slab: slab_entries rows of 64 lanes
@@ -2051,6 +2106,247 @@ __global__ __launch_bounds__(64) void k_run(RunArgs a)
     }
 }
 
+
+}  // namespace ev
+
+namespace ev {
+
+// ------------------------------------------- a generation replayed from a graph
+//
+// Sec. 2.3's generation with no host wait inside it: the children's plan is
+// made level by level on the device.  k_g_init takes the children's
+// offsets, k_g_begin lays out a level's work items from the trees still
+// active (the host-driven plan's rules: items of C tokens, one item for a
+// small tree or a skeleton that did not halve), the structure kernels run on
+// the level's live counts, and k_g_end reads the trees' totals, places each
+// tree's value or its next range, and checks the totals against the
+// capacities the buffers were made for.  Any overflow voids the generation
+// (GStatus.poison) and stops every later step of it.
+
+__device__ __forceinline__ void g_poison(GStatus* st, uint32_t bits, uint32_t level)
+{
+    const uint32_t old = atomicOr(&st->poison, bits);
+    if (!old) st->level = level;
+}
+
+// The children from their offsets (k_xo_offsets' layout: off[M] the total,
+// off[M + 1] the number capped, off[M + 3] the copy pieces): each tree
+// active at level 0 over its own bytes.
+__global__ void k_g_init(const uint64_t* __restrict__ off, uint32_t M, GTree* __restrict__ tr, uint64_t bytes_cap,
+                         uint32_t pad_len, uint64_t pieces_cap, GStatus* __restrict__ st)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0) {
+        const uint64_t total = off[M], pieces = off[M + 3];
+        st->child_bytes = total;
+        st->capped = off[M + 1];
+        if (total + pad_len > bytes_cap || pieces > pieces_cap) g_poison(st, G_OVF_BYTES, 0);
+    }
+    if (j < M) tr[j] = GTree{off[j], off[j + 1] - off[j], 0, 0, 1};
+}
+
+__device__ __forceinline__ uint64_t g_nseg(uint64_t len, uint32_t seg_len, uint32_t head)
+{
+    return len <= head ? 1 : 1 + (len - head + seg_len - 1) / seg_len;
+}
+
+// One block: the level's trees, in tree order, with their chunks and
+// segments numbered by exclusive scans (rounds of 1024 trees, each scanned
+// by wave shuffles and the waves' totals on top of the rounds before).
+__global__ __launch_bounds__(1024) void k_g_begin(const GTree* __restrict__ tr, uint32_t M, GLevel* __restrict__ gls,
+                                                  uint32_t level, const GCap* __restrict__ caps, uint64_t C,
+                                                  uint32_t seg_len, uint32_t head, uint32_t record,
+                                                  TreeLvl* __restrict__ tl, GStatus* __restrict__ st)
+{
+    __shared__ uint64_t wsum[3][16], carry[3];
+    __shared__ unsigned long long s_tok;
+    __shared__ uint32_t s_bad;
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+    const bool live = st->poison == 0 && (level == 0 || gls[level - 1].any != 0);
+    if (!live) {
+        if (t == 0) {
+            GLevel v = {};
+            v.record = record;
+            gls[level] = v;
+        }
+        return;
+    }
+    if (t == 0) {
+        carry[0] = carry[1] = carry[2] = 0;
+        s_tok = 0;
+        s_bad = 0;
+    }
+    __syncthreads();
+    for (uint32_t r0 = 0; r0 < M; r0 += 1024) {
+        const uint32_t i = r0 + t;
+        GTree q = {};
+        if (i < M) q = tr[i];
+        const bool act = i < M && q.active != 0;
+        const uint64_t len = act ? q.rl : 0;
+        const bool whole = len <= C || (level > 0 && len * 2 > q.prev_len);
+        const uint64_t Ct = whole ? len : C;
+        const uint64_t nc = act ? (whole ? 1 : (len + C - 1) / C) : 0;
+        const uint64_t ns = act ? (nc - 1) * g_nseg(Ct, seg_len, head) + g_nseg(len - (nc - 1) * Ct, seg_len, head) : 0;
+        if (act && whole && len > 0xFFFFFFFFull) atomicOr(&s_bad, 1u);
+        uint64_t a = act ? 1 : 0, b = nc, c = ns, tok = len;
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint64_t a0 = __shfl_up(a, d, 64), b0 = __shfl_up(b, d, 64), c0 = __shfl_up(c, d, 64);
+            if (lane >= d) {
+                a += a0;
+                b += b0;
+                c += c0;
+            }
+        }
+        for (int d = 32; d > 0; d >>= 1) tok += __shfl_xor(tok, d, 64);
+        if (lane == 63) {
+            wsum[0][w] = a;
+            wsum[1][w] = b;
+            wsum[2][w] = c;
+        }
+        if (lane == 0 && tok) atomicAdd(&s_tok, (unsigned long long)tok);
+        __syncthreads();
+        uint64_t ba = carry[0], bb = carry[1], bc = carry[2];
+        for (uint32_t k = 0; k < w; k++) {
+            ba += wsum[0][k];
+            bb += wsum[1][k];
+            bc += wsum[2][k];
+        }
+        if (act) {
+            TreeLvl v;
+            v.start = q.rs;
+            v.len = len;
+            v.chunk_first = (uint32_t)(bb + b - nc);
+            v.n_chunks = (uint32_t)nc;
+            v.seg_first = (uint32_t)(bc + c - ns);
+            v.C = (uint32_t)Ct;
+            v.tree = i;
+            v.ref_base = q.ref_base;
+            v.rank_full = v.rank_last = 0;  // places come from the device counting sort
+            tl[(uint32_t)(ba + a - 1)] = v;
+        }
+        __syncthreads();  // every thread has read carry and the waves' totals
+        if (t == 1023) {
+            carry[0] = ba + a;
+            carry[1] = bb + b;
+            carry[2] = bc + c;
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const GCap cp = caps[level];
+        GLevel v = {};
+        v.record = record;
+        v.tokens = s_tok;
+        v.prev_out = level ? gls[level - 1].so : 0;
+        if (s_bad || carry[1] > cp.n || carry[2] > cp.n_seg) {
+            g_poison(st, G_OVF_ITEMS, level);
+        } else {
+            v.nt = (uint32_t)carry[0];
+            v.n = (uint32_t)carry[1];
+            v.n_seg = (uint32_t)carry[2];
+        }
+        gls[level] = v;
+    }
+}
+
+// One block: the level's totals from its trees' (in the level's order), the
+// trees that end here (their value's level and slot) and the next level's
+// ranges, checked against the capacities.
+__global__ __launch_bounds__(1024) void k_g_end(GTree* __restrict__ tr, GLevel* __restrict__ gls, uint32_t level,
+                                                const GCap* __restrict__ caps, uint32_t n_levels,
+                                                const TreeLvl* __restrict__ tl, const TreeSum* __restrict__ sum,
+                                                const TreeBase* __restrict__ tb, uint32_t* __restrict__ fin,
+                                                GStatus* __restrict__ st)
+{
+    __shared__ unsigned long long s_so, s_sf, s_sc;
+    __shared__ uint32_t s_top, s_bad, s_any;
+    const uint32_t t = threadIdx.x;
+    const uint32_t nt = gls[level].nt;
+    if (nt == 0) return;  // no work at this level, or voided
+    if (t == 0) {
+        s_so = s_sf = s_sc = 0;
+        s_top = s_bad = s_any = 0;
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < nt; i += blockDim.x) {
+        const TreeSum q = sum[i];
+        const uint32_t tree = tl[i].tree;
+        const TreeBase b = tb[tree];
+        uint32_t bad = 0;
+        if (q.bad & 1u) bad |= G_MALFORMED;
+        if (q.bad & 2u) bad |= G_INCONSISTENT;
+        if (q.bad & HAS_CONST) bad |= G_CONSTS;
+        if (bad) atomicOr(&s_bad, bad);
+        atomicMax(&s_top, q.maxtop);
+        atomicAdd(&s_so, (unsigned long long)q.n_out);
+        atomicAdd(&s_sf, (unsigned long long)q.n_frag);
+        atomicAdd(&s_sc, (unsigned long long)q.n_codes);
+        if (q.n_frag == 1) {
+            fin[2 * (size_t)tree] = level;
+            fin[2 * (size_t)tree + 1] = (uint32_t)(b.out + q.n_out - 1);
+            tr[tree].active = 0;
+        } else {
+            s_any = 1;
+            GTree r = tr[tree];
+            r.prev_len = r.rl;
+            r.rs = b.frag;
+            r.rl = q.n_frag;
+            r.ref_base = (uint32_t)b.out;
+            tr[tree] = r;
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        const GCap cp = caps[level];
+        uint32_t bad = s_bad;
+        const uint32_t top = s_top;
+        // the host-driven plan's rule: spill rows when the stack reaches
+        // past the window's re-centring point
+        const uint32_t slab = top + 1 > EV_VSTACK_ENTRIES - EV_VHALF / 2 ? top + EV_VHALF : 0u;
+        if (s_so > cp.so || s_sf > cp.sf || s_sc > cp.sc || s_so > 0xFFFFFFF0ull) bad |= G_OVF_SIZES;
+        if (slab > cp.slab) bad |= G_OVF_SLAB;
+        if (s_any && level + 1 >= n_levels) bad |= G_OVF_LEVELS;
+        GLevel& g = gls[level];
+        if (bad) {
+            g_poison(st, bad, level);
+            g.nt = g.n = g.n_seg = 0;
+            g.any = 0;
+        } else {
+            g.so = s_so;
+            g.sf = s_sf;
+            g.sc = s_sc;
+            g.slab_entries = slab;
+            g.any = s_any;
+            st->levels = level + 1;
+        }
+    }
+}
+
+// The generation's verdict: code streams that failed validation void it
+// too.  The status, the levels' counts and the children's fitness go to
+// pinned host memory (read after the replay), and the generation number
+// steps on.
+__global__ __launch_bounds__(256) void k_g_finish(GStatus* __restrict__ st, const GLevel* __restrict__ gls,
+                                                  uint32_t n_levels, const uint32_t* __restrict__ err,
+                                                  const float* __restrict__ fit, uint32_t M,
+                                                  uint64_t* __restrict__ gen_at, GStatus* __restrict__ h_st,
+                                                  GLevel* __restrict__ h_levels, float* __restrict__ h_fit)
+{
+    const uint32_t t = threadIdx.x;
+    if (t == 0) {
+        const uint32_t used = st->levels;
+        for (uint32_t l = 0; l < used && l < n_levels; l++)
+            if (err[2 * l]) {
+                g_poison(st, G_INVALID_CODES, l);
+                break;
+            }
+        *h_st = *st;
+        *gen_at += 1;
+    }
+    for (uint32_t l = t; l < n_levels; l += blockDim.x) h_levels[l] = gls[l];
+    for (uint32_t j = t; j < M; j += blockDim.x) h_fit[j] = fit[j];
+}
+
 }  // namespace ev
 
 // ------------------------------------------------------------ launchers
@@ -2066,6 +2362,13 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u8, dim3(cdiv(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(void* dst, const void* src, uint64_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
@@ -2076,36 +2379,37 @@ hipError_t launch_copy(void* dst, const void* src, uint64_t n, hipStream_t s)
 }
 
 hipError_t launch_seg_build(const ChunkIn* ch, const ChunkSegs* cg, uint32_t n, uint32_t seg_len, uint32_t head,
-                            SegIn* seg, hipStream_t s)
+                            SegIn* seg, hipStream_t s, const GLevel* gl)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_build, dim3(n), dim3(64), 0, s, ch, cg, n, seg_len, head, seg);
+    hipLaunchKernelGGL(k_seg_build, dim3(n), dim3(64), 0, s, ch, cg, n, seg_len, head, seg, gl);
     return hipGetLastError();
 }
 
 hipError_t launch_plan_chunks(const TreeLvl* trees, uint32_t n_trees, uint32_t seg_len, uint32_t head, ChunkIn* ch,
-                              ChunkSegs* cg, uint32_t* err_init, uint32_t n_err, hipStream_t s)
+                              ChunkSegs* cg, uint32_t* err_init, uint32_t n_err, hipStream_t s, const GLevel* gl)
 {
     if (n_trees == 0) return hipSuccess;
     hipLaunchKernelGGL(k_plan_chunks, dim3(n_trees), dim3(64), 0, s, trees, n_trees, seg_len, head, ch, cg, err_init,
-                       n_err);
+                       n_err, gl);
     return hipGetLastError();
 }
 
-hipError_t launch_plan_bases(const TreeLvl* trees, uint32_t n_trees, const TreeSum* sum, TreeBase* base, hipStream_t s)
+hipError_t launch_plan_bases(const TreeLvl* trees, uint32_t n_trees, const TreeSum* sum, TreeBase* base, hipStream_t s,
+                             const GLevel* gl)
 {
     if (n_trees == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_plan_bases, dim3(1), dim3(1024), 0, s, trees, n_trees, sum, base);
+    hipLaunchKernelGGL(k_plan_bases, dim3(1), dim3(1024), 0, s, trees, n_trees, sum, base, gl);
     return hipGetLastError();
 }
 
 hipError_t launch_plan_trees(const TreeLvl* trees, uint32_t n_trees, const ChunkStat* cs, uint32_t level,
                              uint64_t prev_out, uint64_t* code_loc, uint64_t* out_loc, uint64_t* frag_loc,
-                             uint32_t* in_end, TreeSum* sum, hipStream_t s)
+                             uint32_t* in_end, TreeSum* sum, hipStream_t s, const GLevel* gl)
 {
     if (n_trees == 0) return hipSuccess;
     hipLaunchKernelGGL(k_plan_trees, dim3(n_trees), dim3(64), 0, s, trees, n_trees, cs, level, prev_out, code_loc,
-                       out_loc, frag_loc, in_end, sum);
+                       out_loc, frag_loc, in_end, sum, gl);
     return hipGetLastError();
 }
 
@@ -2113,11 +2417,12 @@ hipError_t launch_plan_items(const ChunkIn* ch, uint32_t n, const TreeBase* base
                              const uint64_t* out_loc, const uint64_t* frag_loc, const uint32_t* in_end,
                              const uint32_t* cursor,
                              uint64_t* code_begin, uint64_t* frag_end, RunChunk* run, EvalChunk* slow,
-                             uint32_t* code_tail, uint8_t* frag_tail, const uint32_t* item_at, hipStream_t s)
+                             uint32_t* code_tail, uint8_t* frag_tail, const uint32_t* item_at, hipStream_t s,
+                             const GLevel* gl)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_plan_items, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, base, code_loc, out_loc, frag_loc,
-                       in_end, cursor, code_begin, frag_end, run, slow, code_tail, frag_tail, item_at);
+                       in_end, cursor, code_begin, frag_end, run, slow, code_tail, frag_tail, item_at, gl);
     return hipGetLastError();
 }
 
@@ -2139,13 +2444,14 @@ hipError_t launch_reuse_chunks(const TreeReuse* trees, uint32_t n_trees, const C
     return hipGetLastError();
 }
 
-hipError_t launch_item_sort(const ChunkIn* ch, uint32_t n, uint32_t* hist, uint32_t* item_at, hipStream_t s)
+hipError_t launch_item_sort(const ChunkIn* ch, uint32_t n, uint32_t* hist, uint32_t* item_at, hipStream_t s,
+                            const GLevel* gl)
 {
     hipError_t e = launch_fill_u32(hist, EV_LEN_BUCKETS, 0u, s);
     if (e != hipSuccess || n == 0) return e;
-    hipLaunchKernelGGL(k_item_hist, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, hist);
+    hipLaunchKernelGGL(k_item_hist, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, hist, gl);
     hipLaunchKernelGGL(k_item_cursor, dim3(1), dim3(64), 0, s, hist);
-    hipLaunchKernelGGL(k_item_place, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, hist, item_at);
+    hipLaunchKernelGGL(k_item_place, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, hist, item_at, gl);
     return hipGetLastError();
 }
 
@@ -2190,67 +2496,69 @@ hipError_t launch_tree_depth(const uint8_t* buf, const uint64_t* off, uint32_t M
 }
 
 hipError_t launch_seg_fn(const uint8_t* seq, const SegIn* segs, uint32_t n, SegFn* out, uint32_t ref_ok,
-                         uint32_t n_consts, hipStream_t s)
+                         uint32_t n_consts, hipStream_t s, const GLevel* gl)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_fn, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, out, ref_ok, n_consts);
+    hipLaunchKernelGGL(k_seg_fn, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, out, ref_ok, n_consts, gl);
     return hipGetLastError();
 }
 
 hipError_t launch_seg_scan(const ChunkSegs* cseg, uint32_t n, const SegFn* fn, SegStart* st, ChunkStat* cstat,
-                           hipStream_t s)
+                           hipStream_t s, const GLevel* gl)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_scan, dim3(n), dim3(64), 0, s, cseg, n, fn, st, cstat);
+    hipLaunchKernelGGL(k_seg_scan, dim3(n), dim3(64), 0, s, cseg, n, fn, st, cstat, gl);
     return hipGetLastError();
 }
 
 hipError_t launch_seg_count(const uint8_t* seq, const SegIn* segs, uint32_t n, const SegStart* st, SegCount* out,
-                            uint8_t* rk, uint8_t* rf, SegRec* rec, uint32_t* ovf, uint32_t seg_len, hipStream_t s)
+                            uint8_t* rk, uint8_t* rf, SegRec* rec, uint32_t* ovf, uint32_t seg_len, hipStream_t s,
+                            const GLevel* gl)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_seg_count, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, st, out, rk, rf, rec, ovf,
-                       seg_len);
+                       seg_len, gl);
     return hipGetLastError();
 }
 
 hipError_t launch_seg_place(const SegIn* segs, uint32_t n, const SegCount* cnt, const SegRec* rec, const SegStart* st,
                             const uint64_t* seg_code, const uint64_t* seg_frag, const uint8_t* rk, const uint8_t* rf,
                             uint32_t* codes, uint64_t n_codes, uint8_t* dst, uint64_t n_frag, uint32_t slab_entries,
-                            uint32_t* err, uint32_t seg_len, hipStream_t s)
+                            uint32_t* err, uint32_t seg_len, hipStream_t s, const GLevel* gl)
 {
     if (n == 0) return hipSuccess;
     const uint32_t grid = n < 16384u ? n : 16384u;
     hipLaunchKernelGGL(k_seg_place, dim3(grid), dim3(64), 0, s, segs, n, cnt, rec, st, seg_code, seg_frag, rk, rf,
-                       codes, n_codes, dst, n_frag, slab_entries, err, seg_len);
+                       codes, n_codes, dst, n_frag, slab_entries, err, seg_len, gl);
     return hipGetLastError();
 }
 
 hipError_t launch_seg_chunk(const ChunkSegs* cseg, uint32_t n, const SegCount* cnt, ChunkStat* cstat,
                             const uint64_t* code_begin, const uint64_t* frag_end, uint64_t* seg_code, uint64_t* seg_frag,
-                            hipStream_t s)
+                            hipStream_t s, const GLevel* gl)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_seg_chunk, dim3(n), dim3(64), 0, s, cseg, n, cnt, cstat, code_begin, frag_end,
-                       seg_code, seg_frag);
+                       seg_code, seg_frag, gl);
     return hipGetLastError();
 }
 
 hipError_t launch_seg_emit(const uint8_t* seq, const SegIn* segs, uint32_t n, const SegStart* st, const uint64_t* seg_code,
-                           const uint64_t* seg_frag, uint8_t* dst, uint32_t* codes, hipStream_t s)
+                           const uint64_t* seg_frag, uint8_t* dst, uint32_t* codes, hipStream_t s, const GLevel* gl)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_emit, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, st, seg_code, seg_frag, dst, codes);
+    hipLaunchKernelGGL(k_seg_emit, dim3(cdiv(n, 64)), dim3(64), 0, s, seq, segs, n, st, seg_code, seg_frag, dst, codes,
+                       gl);
     return hipGetLastError();
 }
 
 hipError_t launch_seg_check(const uint32_t* codes, const SegIn* segs, uint32_t n, const SegStart* st,
                             const uint64_t* seg_code, const SegCount* cnt, uint32_t slab_entries, uint32_t* err,
-                            hipStream_t s)
+                            hipStream_t s, const GLevel* gl)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_seg_check, dim3(cdiv(n, 64)), dim3(64), 0, s, codes, segs, n, st, seg_code, cnt, slab_entries,
-                       err);
+                       err, gl);
     return hipGetLastError();
 }
 
@@ -2305,11 +2613,13 @@ hipError_t launch_subtree_end(const uint8_t* buf, const uint64_t* base, const ui
 }
 
 hipError_t launch_xo_copy(const uint8_t* mums, const uint8_t* dads, const XoPlan* plan, const uint64_t* off,
-                          uint32_t n, uint64_t pieces, uint8_t* dst, uint8_t* pad, uint32_t pad_len, hipStream_t s)
+                          uint32_t n, uint64_t pieces, uint8_t* dst, uint8_t* pad, uint32_t pad_len, hipStream_t s,
+                          const uint32_t* stop)
 {
-    if (n == 0 || pieces == 0) return hipMemsetAsync(pad, 0xFF, pad_len, s);
+    if (n == 0 || pieces == 0) return launch_fill_u8(pad, pad_len, 0xFF, s);
     if (pieces > 0x7FFFFFFFull) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_xo_copy, dim3((uint32_t)pieces), dim3(256), 0, s, mums, dads, plan, off, n, dst, pad, pad_len);
+    hipLaunchKernelGGL(k_xo_copy, dim3((uint32_t)pieces), dim3(256), 0, s, mums, dads, plan, off, n, dst, pad, pad_len,
+                       stop);
     return hipGetLastError();
 }
 
@@ -2334,10 +2644,41 @@ hipError_t launch_xo_plan(const uint64_t* moff, const uint64_t* doff, const int3
 }
 
 hipError_t launch_select(const float* fit, const uint64_t* off, uint32_t M, int32_t k, uint64_t seed, uint64_t gen,
-                         int32_t* mum, int32_t* dad, uint64_t* p, uint64_t* q, hipStream_t s)
+                         int32_t* mum, int32_t* dad, uint64_t* p, uint64_t* q, hipStream_t s, const uint64_t* gen_at)
 {
     if (M == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_select, dim3(cdiv(M, 64)), dim3(64), 0, s, fit, off, M, k, seed, gen, mum, dad, p, q);
+    hipLaunchKernelGGL(k_select, dim3(cdiv(M, 64)), dim3(64), 0, s, fit, off, M, k, seed, gen, mum, dad, p, q, gen_at);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_g_init(const uint64_t* off, uint32_t M, GTree* tr, uint64_t bytes_cap, uint32_t pad_len,
+                         uint64_t pieces_cap, GStatus* st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_g_init, dim3(cdiv(M ? M : 1, 256)), dim3(256), 0, s, off, M, tr, bytes_cap, pad_len,
+                       pieces_cap, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_g_begin(const GTree* tr, uint32_t M, GLevel* gls, uint32_t level, const GCap* caps, uint64_t C,
+                          uint32_t seg_len, uint32_t head, uint32_t record, TreeLvl* tl, GStatus* st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_g_begin, dim3(1), dim3(1024), 0, s, tr, M, gls, level, caps, C, seg_len, head, record, tl, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_g_end(GTree* tr, GLevel* gls, uint32_t level, const GCap* caps, uint32_t n_levels, const TreeLvl* tl,
+                        const TreeSum* sum, const TreeBase* tb, uint32_t* fin, GStatus* st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_g_end, dim3(1), dim3(1024), 0, s, tr, gls, level, caps, n_levels, tl, sum, tb, fin, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_g_finish(GStatus* st, const GLevel* gls, uint32_t n_levels, const uint32_t* err, const float* fit,
+                           uint32_t M, uint64_t* gen_at, GStatus* h_st, GLevel* h_levels, float* h_fit, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_g_finish, dim3(1), dim3(256), 0, s, st, gls, n_levels, err, fit, M, gen_at, h_st, h_levels,
+                       h_fit);
     return hipGetLastError();
 }
 

@@ -30,12 +30,6 @@ ev_status hip_fail(hipError_t e, const char* what)
     return fail(EV_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIPCHK(x)                                           \
-    do {                                                    \
-        hipError_t e_ = (x);                                \
-        if (e_ != hipSuccess) return hip_fail(e_, #x);      \
-    } while (0)
-
 // ------------------------------------------------------------- memory
 
 // Device memory goes through a per-context cache: freed blocks are kept in
@@ -589,6 +583,9 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         L.slab_entries = run_items && slab_top + 1 > EV_VSTACK_ENTRIES - EV_VHALF / 2 ? slab_top + EV_VHALF : 0;
         L.n_chunks = run_items ? 0 : (uint32_t)n;
         L.n_run = run_items ? (uint32_t)n : 0;
+        L.n_seg = n_seg;
+        L.n_codes = run_items ? sc : 0;
+        L.n_frag = sf;
         pl.chunks_total += n;
         pl.slots_total += so;
         pl.levels.push_back(L);  // owns what is allocated below, freed with the plan
@@ -1459,6 +1456,7 @@ ev_status ev_destroy(ev_ctx* c)
     if (!c) return fail(EV_EINVAL, "ev_destroy: NULL context");
     (void)hipSetDevice(c->device);
     serve_stop(c);
+    evolve_release(c);
     (void)sync(c->main);
     for (auto& kv : c->pops) pop_free(c, kv.second);
     c->pops.clear();
@@ -1504,7 +1502,7 @@ ev_status ev_load_trees(ev_ctx* c, const uint8_t* bytes, const uint64_t* off, in
         dev_free(c, d);
         return st;
     }
-    if (e == hipSuccess) e = hipMemsetAsync(d + total, 0xFF, EV_POP_PAD, c->stream);
+    if (e == hipSuccess) e = launch_fill_u8(d + total, EV_POP_PAD, 0xFF, c->stream);
     if (e != hipSuccess) { dev_free(c, d); return hip_fail(e, "upload trees"); }
     Pop* P = nullptr;
     ev_status st2 = pop_build(c, c->main, d, h_off, &P, bad_tree);

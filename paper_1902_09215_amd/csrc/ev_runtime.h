@@ -40,6 +40,9 @@ struct Level {
     uint32_t slab_entries = 0;      // spill-slab rows per wave of k_run (0: no spills)
     uint32_t n_out = 0;  // result slots written by this level
     uint32_t max_m = 0;  // deepest physical operand stack of a k_eval item
+    uint32_t n_seg = 0;     // structure segments
+    uint64_t n_codes = 0;   // codes of the register-stack items (with each item's padding)
+    uint64_t n_frag = 0;    // tokens of the next level's skeleton
 };
 
 struct Plan {
@@ -148,6 +151,7 @@ struct Exec {
 
 struct Job;
 struct Serve;
+struct GenGraph;
 
 }  // namespace ev
 
@@ -187,6 +191,8 @@ struct ev_ctx {
 
     ev::Serve* serve = nullptr;
     std::mutex serve_init_mu;
+
+    ev::GenGraph* evolve = nullptr;  // ev_evolve's captured generations, kept for the next call
 };
 
 namespace ev {
@@ -194,6 +200,12 @@ namespace ev {
 extern thread_local std::string g_err;
 ev_status fail(ev_status code, const char* fmt, ...);
 ev_status hip_fail(hipError_t e, const char* what);
+// return the failure of a HIP call
+#define HIPCHK(x)                                      \
+    do {                                               \
+        hipError_t e_ = (x);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #x); \
+    } while (0)
 
 // Device blocks.  Both act for the calling thread's Exec (set with
 // ExecScope; the context's own Exec when none is set): a block freed while
@@ -257,5 +269,8 @@ ev_status crossover_build_dev(ev_ctx* c, Exec& x, Pop* mums, Pop* dads, const in
                               int32_t* n_capped, bool defer_check = false);
 
 void serve_stop(ev_ctx* c);
+
+// Release a context's replayed-generation graphs and their buffers.
+void evolve_release(ev_ctx* c);
 
 }  // namespace ev

@@ -109,7 +109,7 @@ static ev_status run_eval_batch(ev_ctx* c, Exec& x, std::vector<Job*>& batch)
             at += j->bytes.size();
         }
         if (st == EV_OK) {
-            hipError_t e = hipMemsetAsync(d + total, 0xFF, EV_POP_PAD, x.stream);
+            hipError_t e = launch_fill_u8(d + total, EV_POP_PAD, 0xFF, x.stream);
             if (e != hipSuccess) st = hip_fail(e, "serve upload");
         }
         if (st != EV_OK) {
