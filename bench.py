@@ -15,7 +15,12 @@ same way), the dominant kernel (the level-0 interpreter launch) against the
 FP32 vector ALU peak, and the C oracle timed on the host cores.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
-                  [--workload giant_max|giant|batched|tiny|serving]
+                  [--workload giant_max|giant|batched|tiny|loop|serving]
+
+The loop workload is the generational loop (population 48 from ramped
+half-and-half trees of depth 2-6, size-2 tournaments, 15e6-node cap): a step
+is one generation of the evolving population, run by ev_evolve from captured
+graphs, and the same generations on the host-driven path beside it.
 """
 from __future__ import annotations
 
@@ -241,9 +246,8 @@ def calibrate_copy():
 
 
 def kernel_hash():
-    """Hash of what the level-0 k_run launch runs: the interpreter generator,
-    the kernel's own source text and the default work-item size (which sets
-    the launch's items)."""
+    """Hash of what the level-0 k_run launch runs: the interpreter generator
+    and the kernel's own source text."""
     import hashlib
 
     h = hashlib.sha256()
@@ -252,14 +256,14 @@ def kernel_hash():
     src = open(os.path.join(ROOT, "paper_1902_09215_amd/csrc/ev_kernels.hip")).read()
     i = src.index("void k_run(RunArgs a)")
     h.update(src[i:src.index("\n}\n", i)].encode())
-    hdr = open(os.path.join(ROOT, "paper_1902_09215_amd/csrc/ev_runtime.h")).read()
-    h.update("".join(l for l in hdr.splitlines() if "uint32_t chunk = " in l).encode())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, chunk):
     """HBM bytes per level-0 k_run launch from the committed counter summary
-    of this workload, or None when the kernel sources changed since."""
+    of this workload, or None when the kernel sources or the level-0
+    work-item size (which sets the launch's items) differ from the ones the
+    counters were taken with."""
     import re
 
     path = os.path.join(ROOT, "profiles", f"k_run_{workload}_traffic.md")
@@ -267,12 +271,85 @@ def measured_traffic(workload):
         return None
     text = open(path).read()
     vals = dict(re.findall(r"^- (\w+): ([0-9a-f.e+]+)$", text, re.M))
-    if vals.get("kernel_hash") != kernel_hash():
+    if vals.get("kernel_hash") != kernel_hash() or vals.get("chunk") != str(chunk):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def evolve_pair(ev, c, parents, seed, gen0, gens, cap, tournament=2):
+    """The same generations from the same parents, replayed from graphs and
+    on the host-driven path: (graph report, plain report, bit-exact)."""
+    kg, fg, cg, rg = ev.ev_evolve(c.ctx, parents, seed, gen0, gens, tournament, cap)
+    kp, fp, cp, rp = ev.ev_evolve(c.ctx, parents, seed, gen0, gens, tournament, cap, flags=ev.EV_EVOLVE_NO_GRAPH)
+    same = bool((fg.view(np.uint32) == fp.view(np.uint32)).all() or
+                ((fg.view(np.uint32) == fp.view(np.uint32)) | (np.isnan(fg) & np.isnan(fp))).all())
+    same &= bool(np.array_equal(cg, cp)) and rg["nodes"] == rp["nodes"]
+    ev.ev_free_pop(c.ctx, kg)
+    ev.ev_free_pop(c.ctx, kp)
+    return rg, rp, same
+
+
+def graph_summary(rg, rp, same, n_cases):
+    g_ms, p_ms = rg["ms"] / max(1, rg["generations"]), rp["ms"] / max(1, rp["generations"])
+    return {"generations": rg["generations"], "ms_per_generation": g_ms,
+            "gpops_per_s": rg["nodes"] * n_cases / (rg["ms"] * 1e-3),
+            "replayed": rg["replayed"], "fallbacks": rg["fallbacks"], "captures": rg["captures"],
+            "ms_capture": rg["ms_capture"],
+            "plain_host_driven": {"ms_per_generation": p_ms, "gpops_per_s": rp["nodes"] * n_cases / (rp["ms"] * 1e-3)},
+            "speedup_vs_host_driven": p_ms / g_ms, "bitexact_vs_host_driven": same,
+            "timing": "wall time of one ev_evolve call over the generations (host waits included)"}
+
+
+def loop_bench(args, ev, workloads):
+    """The generational loop: population 48, ramped half-and-half depth 2-6,
+    tournaments of 2, 15e6-node cap.  The first `warmup` generations evolve
+    the population (and capture the graphs); the next `steps` generations are
+    timed, replayed from graphs, and again on the host-driven path."""
+    x, y = workloads.cases(48)
+    buf, off = workloads.rhh_population(workloads.SEED_BASE + 4, 48, 2, 6)
+    seed, cap = 0x5EED0004, 15_000_000
+    c = ev.Context(x, y, device=0)
+    pop = c.load(buf, off)
+    c.eval(pop)
+    warm = args.warmup
+    start, _, _, _ = ev.ev_evolve(c.ctx, pop, seed, 0, warm, 2, cap, history=False)
+    rg, rp, same = evolve_pair(ev, c, start, seed, warm, args.steps, cap)
+    cpu = None
+    if not args.no_cpu:
+        sb, so = ev.ev_get_trees(c.ctx, start)
+        sf, _ = c.eval(start)
+        cpu = cpu_baseline(sb, so, x, y, sf, 48)
+    summ = graph_summary(rg, rp, same, 48)
+    print(f"# loop: {summ}", file=sys.stderr, flush=True)
+    line = {
+        "metric": "GPops/s (tree nodes x fitness cases /s) on 1 MI355X; p99 eval latency",
+        "value": summ["gpops_per_s"],
+        "unit": "GPops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": summ["ms_per_generation"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "generational loop: population 48, ramped half-and-half depth 2-6 start, "
+                        f"tournament 2, 15e6-node cap, generations {warm}..{warm + args.steps - 1}",
+            "trees": 48, "fitness_cases": 48,
+            "step": "one generation replayed from a captured HIP graph: tournament(2) + Philox points + "
+                    "subtree crossover + device-made split plan + eval + fitness",
+        },
+        "graph_loop": summ,
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    c.close()
 
 
 def main():
@@ -295,6 +372,9 @@ def main():
     ap.add_argument("--cap", type=int, default=-1,
                     help="child size cap of the generation step (default: 15e6 nodes, none for the giant "
                          "populations)")
+    ap.add_argument("--graph-gens", type=int, default=20,
+                    help="generations of the graph-replayed loop reported beside the step (not the giant "
+                         "populations)")
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
     ap.add_argument("--load", type=float, default=0.8, help="serving: offered load as a fraction of capacity")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -313,6 +393,8 @@ def main():
 
     if args.workload == "serving":
         return serve_bench(args, ev, workloads)
+    if args.workload == "loop":
+        return loop_bench(args, ev, workloads)
     giant = args.workload.startswith("giant")
     cap = args.cap if args.cap >= 0 else (2**62 if giant else 15_000_000)
     buf, off, n_cases = workloads.workload(args.workload)
@@ -333,6 +415,8 @@ def main():
         tuning = ev.ev_autotune_ex(c.ctx, parents, 0, 2)
         tuning["search_s"] = time.perf_counter() - t0
         print(f"# tuning: {tuning}", file=sys.stderr, flush=True)
+    # the level-0 work-item size in use
+    chunk0 = args.chunk or (tuning["chunk"] if tuning else 6144)
     plan = ev.ev_get_plan_info(c.ctx, parents)
     levels = [ev.ev_get_level_info(c.ctx, parents, i) for i in range(plan["levels"])]
     funcs = ev.level_functions(c.ctx, parents)
@@ -378,6 +462,14 @@ def main():
         step_ms.append((t1 - t0) * 1e3)
     value = child_nodes * n_cases / sum(step_ms) * 1e3
     print(f"# generation step: {np.mean(step_ms):.3f} ms", file=sys.stderr, flush=True)
+
+    # ---- the same step as a loop of generations replayed from captured
+    # graphs (the population evolves), and on the host-driven path
+    graph_loop = None
+    if not giant and args.graph_gens > 0:
+        ev.ev_free_pop(c.ctx, ev.ev_evolve(c.ctx, parents, seed, 0, 1, 2, cap, history=False)[0])  # capture
+        graph_loop = graph_summary(*evolve_pair(ev, c, parents, seed, 0, args.graph_gens, cap), n_cases)
+        print(f"# graph loop: {graph_loop['ms_per_generation']:.3f} ms per generation", file=sys.stderr, flush=True)
 
     # ---- the plain form: one tree per launch (its own population and call),
     # timed like the batched evaluation, by HIP events around the call's kernels
@@ -451,9 +543,10 @@ def main():
             "work_per_launch": f"{funcs[0]} function nodes evaluated by the level-0 launch x {n_cases} cases "
                                f"(one FP32 operation each)",
             "gpops_per_s_level0": levels[0]["tokens"] * n_cases / (interp_ms * 1e-3),
-            "traffic": measured_traffic(args.workload),
+            "traffic": measured_traffic(args.workload, chunk0),
         },
         "plain_one_tree_per_launch": plain,
+        "graph_loop": graph_loop,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

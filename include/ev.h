@@ -219,6 +219,7 @@ typedef struct {
     int32_t fallbacks;    /* ... done again on the host-driven path (a capacity was exceeded) */
     int32_t captures;     /* graphs captured */
     uint64_t capped;      /* children over the size cap, over all generations */
+    uint64_t nodes;       /* children's nodes, over all generations */
     double ms;            /* wall time of the call */
     double ms_capture;    /* of which capturing and instantiating graphs */
 } ev_evolve_report;
@@ -336,6 +337,7 @@ typedef struct {
     uint32_t items;   /* work items */
     uint32_t slots;   /* result slots the level writes */
     uint32_t pad;
+    uint64_t codes;   /* threaded codes of its register-stack work items (0 for the general kernel's) */
 } ev_level_info;
 
 /* Errors: EV_EINVAL (level out of range), EV_ENOTFOUND. */
@@ -355,8 +357,11 @@ ev_status ev_get_level_info(ev_ctx *ctx, ev_pop pop, int32_t level, ev_level_inf
  * children of ev_crossover and ev_generation from scratch instead of taking
  * over the code streams and skeleton fragments of their mum's level-0 work
  * items that crossover leaves intact (a child is its mum with one subtree
- * replaced, Sec. 3.1).  Plans made afterwards use them;
- * results never depend on them.  EV_TUNE_TEST_FAIL_CHECK is a test hook
+ * replaced, Sec. 3.1).  EV_TUNE_NO_CHAIN evaluates each skeleton level in
+ * a launch of its own instead of all of them in one launch where a tree's
+ * work items at a level start as soon as its items of the level before are
+ * done.  Plans made and evaluations run afterwards use them; results never
+ * depend on them.  EV_TUNE_TEST_FAIL_CHECK is a test hook
  * for the error path of code-stream validation: plans made afterwards
  * record their last level as failing it (the plan is refused, or, for the
  * children of ev_generation, whose verdict is read with their first
@@ -365,6 +370,7 @@ ev_status ev_get_level_info(ev_ctx *ctx, ev_pop pop, int32_t level, ev_level_inf
 #define EV_TUNE_NO_REGSTACK 0x1u
 #define EV_TUNE_NO_RECORD 0x2u
 #define EV_TUNE_NO_REUSE 0x4u
+#define EV_TUNE_NO_CHAIN 0x8u
 #define EV_TUNE_TEST_FAIL_CHECK 0x100u
 ev_status ev_set_tuning(ev_ctx *ctx, uint32_t chunk, uint32_t chunk_hi, uint32_t lds_depth, uint32_t flags);
 

@@ -48,12 +48,13 @@ class ev_plan_info(ctypes.Structure):
 
 class ev_level_info(ctypes.Structure):
     _fields_ = [("tokens", ctypes.c_uint64), ("trees", ctypes.c_uint32), ("items", ctypes.c_uint32),
-                ("slots", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+                ("slots", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("codes", ctypes.c_uint64)]
 
 
 class ev_evolve_report(ctypes.Structure):
     _fields_ = [("generations", ctypes.c_int32), ("replayed", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
-                ("captures", ctypes.c_int32), ("capped", ctypes.c_uint64), ("ms", ctypes.c_double),
+                ("captures", ctypes.c_int32), ("capped", ctypes.c_uint64), ("nodes", ctypes.c_uint64),
+                ("ms", ctypes.c_double),
                 ("ms_capture", ctypes.c_double)]
 
 
@@ -438,6 +439,7 @@ def ev_tune_cache_load(path: str):
 EV_TUNE_NO_REGSTACK = 0x1
 EV_TUNE_NO_RECORD = 0x2
 EV_TUNE_NO_REUSE = 0x4
+EV_TUNE_NO_CHAIN = 0x8
 EV_TUNE_TEST_FAIL_CHECK = 0x100
 
 

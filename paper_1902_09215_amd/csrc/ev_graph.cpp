@@ -32,7 +32,7 @@ namespace ev {
 
 // Sizes of one plan level (observed, or capacities).
 struct LevelSize {
-    uint64_t n = 0, n_seg = 0, so = 0, sf = 0, sc = 0, slab = 0;
+    uint64_t n = 0, n_seg = 0, so = 0, sf = 0, sc = 0, slab = 0, tokens = 0;
 };
 
 static constexpr uint32_t G_N_ERR = 2 * (EV_MAX_LEVELS + 1);
@@ -88,7 +88,8 @@ struct GenGraph {
     uint64_t *cb = nullptr, *fe = nullptr, *scode = nullptr, *sfrag = nullptr;
     uint8_t *rk = nullptr, *rf = nullptr;
     SegRec* rec = nullptr;
-    uint32_t* at = nullptr;
+    uint32_t* cursor = nullptr;  // each length bucket's first place
+    std::vector<uint32_t> seg_len;  // per level
     uint8_t* skel[2] = {nullptr, nullptr};
     std::vector<uint32_t*> codes;
     std::vector<RunChunk*> run;
@@ -178,6 +179,7 @@ static std::vector<LevelSize> sizes_of(const Plan& pl)
         s.sf = L.n_frag;
         s.sc = L.n_codes;
         s.slab = L.slab_entries;
+        s.tokens = L.tokens;
         v.push_back(s);
     }
     return v;
@@ -195,14 +197,16 @@ static std::vector<LevelSize> sizes_of(const GLevel* lv, uint32_t levels)
         s.sf = lv[l].sf;
         s.sc = lv[l].sc;
         s.slab = lv[l].slab_entries;
+        s.tokens = lv[l].tokens;
         v.push_back(s);
     }
     return v;
 }
 
-// Capacities with room to grow: twice what was seen, and floors that keep
-// small plans from re-capturing at every step; two levels more than seen,
-// sized like the largest skeleton level.
+// Capacities with room to grow: twice what was seen, with floors that keep
+// small plans from re-capturing at every step, and one level more than seen
+// (sized like the largest skeleton level).  Segments are bounded through the
+// tokens and items, whatever segment length the sizes were seen with.
 static std::vector<LevelSize> caps_from(const std::vector<LevelSize>& seen, uint32_t* levels)
 {
     auto grow = [](uint64_t v, uint64_t floor) { return std::max<uint64_t>(2 * v, floor); };
@@ -212,7 +216,7 @@ static std::vector<LevelSize> caps_from(const std::vector<LevelSize>& seen, uint
         const LevelSize& s = seen[l];
         LevelSize k;
         k.n = grow(s.n, 64);
-        k.n_seg = grow(s.n_seg, 256);
+        k.tokens = grow(s.tokens, 1 << 16);
         k.so = grow(s.so, 256);
         k.sf = grow(s.sf, 4096);
         k.sc = grow(s.sc, 8192);
@@ -220,15 +224,15 @@ static std::vector<LevelSize> caps_from(const std::vector<LevelSize>& seen, uint
         caps.push_back(k);
         if (l > 0) {
             hi.n = std::max(hi.n, k.n);
-            hi.n_seg = std::max(hi.n_seg, k.n_seg);
+            hi.tokens = std::max(hi.tokens, k.tokens);
             hi.so = std::max(hi.so, k.so);
             hi.sf = std::max(hi.sf, k.sf);
             hi.sc = std::max(hi.sc, k.sc);
         }
     }
-    if (caps.empty()) caps.push_back(LevelSize{64, 256, 256, 4096, 8192, 0});
+    if (caps.empty()) caps.push_back(LevelSize{64, 0, 256, 4096, 8192, 0, 1 << 16});
     if (hi.n == 0) hi = caps[0];
-    const size_t want = std::min<size_t>(caps.size() + 2, EV_MAX_LEVELS);
+    const size_t want = std::min<size_t>(caps.size() + 1, EV_MAX_LEVELS);
     while (caps.size() < want) caps.push_back(hi);
     *levels = (uint32_t)caps.size();
     return caps;
@@ -236,12 +240,12 @@ static std::vector<LevelSize> caps_from(const std::vector<LevelSize>& seen, uint
 
 static bool near_caps(const std::vector<LevelSize>& seen, const std::vector<LevelSize>& caps, uint64_t slab_max)
 {
-    if (seen.size() + 1 >= caps.size()) return true;
+    if (seen.size() >= caps.size()) return true;
     auto near = [](uint64_t v, uint64_t cap) { return v * 4 > cap * 3; };
     for (size_t l = 0; l < seen.size(); l++) {
         const LevelSize &s = seen[l], &k = caps[l];
-        if (near(s.n, k.n) || near(s.n_seg, k.n_seg) || near(s.so, k.so) || near(s.sf, k.sf) || near(s.sc, k.sc) ||
-            near(s.slab, slab_max))
+        if (near(s.n, k.n) || near(s.n_seg, k.n_seg) || near(s.tokens, k.tokens) || near(s.so, k.so) ||
+            near(s.sf, k.sf) || near(s.sc, k.sc) || near(s.slab, slab_max))
             return true;
     }
     return false;
@@ -259,16 +263,22 @@ static ev_status g_alloc(ev_ctx* c, GenGraph& g, size_t count, T** out)
 }
 
 // The plan's buffers for capacities `caps` (the previous ones are freed).
-static ev_status plan_blocks_make(ev_ctx* c, GenGraph& g, const std::vector<LevelSize>& caps, uint32_t levels,
+static ev_status plan_blocks_make(ev_ctx* c, GenGraph& g, const std::vector<LevelSize>& caps_in, uint32_t levels,
                                   uint64_t slab_rows)
 {
     plan_blocks_free(c, g);
-    g.caps = caps;
+    g.caps = caps_in;
     g.L = levels;
     g.n_max = g.nseg_max = 0;
+    g.seg_len.assign(levels, 0);
     uint64_t sf_max = 0, rk_bytes = 0, rf_bytes = 0;
     for (uint32_t l = 0; l < levels; l++) {
-        const uint32_t seg_len = l == 0 ? SEG_TOKENS : SEG_TOKENS / 4;
+        // each level's segment length, and its segments through its tokens
+        // and items: a chunk of len tokens has at most 2 + len / seg_len
+        const uint32_t seg_len = seg_len_for((int)l, g.caps[l].tokens);
+        g.seg_len[l] = seg_len;
+        g.caps[l].n_seg = std::max<uint64_t>(g.caps[l].n_seg, 2 * g.caps[l].n + g.caps[l].tokens / seg_len + 1);
+        const std::vector<LevelSize>& caps = g.caps;
         g.n_max = std::max(g.n_max, caps[l].n);
         g.nseg_max = std::max(g.nseg_max, caps[l].n_seg);
         sf_max = std::max(sf_max, caps[l].sf);
@@ -278,6 +288,7 @@ static ev_status plan_blocks_make(ev_ctx* c, GenGraph& g, const std::vector<Leve
     if (g.n_max > 0xFFFFFFF0ull || g.nseg_max > 0xFFFFFFF0ull) return fail(EV_ECAP, "ev_evolve: plan too large");
     g.record = g.use_record && rk_bytes + rf_bytes <= G_RECORD_MAX;
     g.slab_max = slab_rows;
+    const std::vector<LevelSize>& caps = g.caps;
     const size_t M = (size_t)g.M;
     ev_status st = EV_OK;
     auto A = [&](auto count, auto** out) {
@@ -306,7 +317,7 @@ static ev_status plan_blocks_make(ev_ctx* c, GenGraph& g, const std::vector<Leve
     A(g.n_max, &g.fe);
     A(g.nseg_max, &g.scode);
     A(g.nseg_max, &g.sfrag);
-    A(g.n_max + EV_LEN_BUCKETS, &g.at);
+    A(EV_LEN_BUCKETS, &g.cursor);
     if (g.record) {
         A(rk_bytes, &g.rk);
         A(rf_bytes, &g.rf);
@@ -405,12 +416,12 @@ static hipError_t enqueue_generation(ev_ctx* c, GenGraph& g, int a, hipStream_t 
     auto E = [&](hipError_t r) {
         if (e == hipSuccess) e = r;
     };
-    E(launch_fill_u32((uint32_t*)g.st, sizeof(GStatus) / 4, 0u, s));
     E(launch_select(g.fit[a], g.off[a], M, g.k, g.seed, 0, g.mum, g.dad, g.p, g.q, s, g.gen_at));
     E(launch_xo_query(g.off[a], g.off[a], g.mum, g.dad, g.p, g.q, M, g.qb, g.qp, s));
     E(launch_subtree_end(g.bytes[a], g.qb, g.qp, 2 * M, g.ends, s));
     E(launch_xo_plan(g.off[a], g.off[a], g.mum, g.dad, g.p, g.q, g.ends, M, g.cap, g.plan, g.off[b], s));
-    E(launch_g_init(g.off[b], M, g.tr, g.bytes_cap, (uint32_t)EV_POP_PAD, g.pieces_cap, g.st, s));
+    E(launch_g_init(g.off[b], M, g.tr, g.bytes_cap, (uint32_t)EV_POP_PAD, g.pieces_cap, g.st, g.counters, 2 * g.L,
+                    s));
     E(launch_xo_copy(g.bytes[a], g.bytes[a], g.plan, g.off[b], M, g.pieces_cap, g.bytes[b], nullptr,
                      (uint32_t)EV_POP_PAD, s, &g.st->poison));
     uint64_t* cloc = g.loc;
@@ -418,15 +429,15 @@ static hipError_t enqueue_generation(ev_ctx* c, GenGraph& g, int a, hipStream_t 
     uint64_t* floc = g.loc + 2 * g.n_max;
     for (uint32_t l = 0; l < g.L; l++) {
         const uint64_t C = l == 0 ? g.C0 : g.C1;
-        const uint32_t seg_len = l == 0 ? SEG_TOKENS : SEG_TOKENS / 4, head = seg_len / 4;
+        const uint32_t seg_len = g.seg_len[l], head = seg_len / 4;
         const LevelSize& k = g.caps[l];
         const uint32_t kn = (uint32_t)k.n, kns = (uint32_t)k.n_seg;
         GLevel* gl = g.gls + l;
         const uint8_t* seq = l == 0 ? g.bytes[b] : g.skel[l & 1];
         uint8_t* next = g.skel[(l + 1) & 1];
-        E(launch_g_begin(g.tr, M, g.gls, l, g.d_caps, C, seg_len, head, g.record ? 1u : 0u, g.tl, g.st, s));
+        E(launch_g_begin(g.tr, M, g.gls, l, g.d_caps, C, seg_len, head, g.record ? 1u : 0u, g.tl, g.cursor, g.st,
+                         s));
         E(launch_plan_chunks(g.tl, M, seg_len, head, g.ch, g.cseg, l == 0 ? g.err : nullptr, G_N_ERR, s, gl));
-        E(launch_item_sort(g.ch, kn, g.at + g.n_max, g.at, s, gl));
         E(launch_seg_build(g.ch, g.cseg, kn, seg_len, head, g.seg, s, gl));
         E(launch_seg_fn(seq, g.seg, kns, g.fn, l ? 1u : 0u, 0u, s, gl));
         E(launch_seg_scan(g.cseg, kn, g.fn, g.sst, g.stat, s, gl));
@@ -434,18 +445,21 @@ static hipError_t enqueue_generation(ev_ctx* c, GenGraph& g, int a, hipStream_t 
                            g.record ? g.rec : nullptr, &gl->record_ovf, seg_len, s, gl));
         E(launch_seg_chunk(g.cseg, kn, g.cnt, g.stat, nullptr, nullptr, nullptr, nullptr, s, gl));
         E(launch_plan_trees(g.tl, M, g.stat, l, 0, cloc, oloc, floc, g.inend, g.sum, s, gl));
-        E(launch_plan_bases(g.tl, M, g.sum, g.tb, s, gl));
         E(launch_g_end(g.tr, g.gls, l, g.d_caps, g.L, g.tl, g.sum, g.tb, g.fin, g.st, s));
-        E(launch_plan_items(g.ch, kn, g.tb, cloc, oloc, floc, g.inend, nullptr, g.cb, g.fe, g.run[l], nullptr,
-                            g.codes[l], next, g.at, s, gl));
+        E(launch_plan_items(g.ch, kn, g.tb, cloc, oloc, floc, g.inend, g.cursor, g.cb, g.fe, g.run[l], nullptr,
+                            g.codes[l], next, nullptr, s, gl));
         E(launch_seg_chunk(g.cseg, kn, g.cnt, g.stat, g.cb, g.fe, g.scode, g.sfrag, s, gl));
-        if (g.record)
+        // placement of the recording (a recording that overflowed voids the
+        // generation), or emission and validation when the level is too
+        // large to record
+        if (g.record) {
             E(launch_seg_place(g.seg, kns, g.cnt, g.rec, g.sst, g.scode, g.sfrag, g.rk, g.rf, g.codes[l], k.sc, next,
                                k.sf, 0, g.err + 2 * l, seg_len, s, gl));
-        E(launch_seg_emit(seq, g.seg, kns, g.sst, g.scode, g.sfrag, next, g.codes[l], s, gl));
-        E(launch_seg_check(g.codes[l], g.seg, kns, g.sst, g.scode, g.cnt, 0, g.err + 2 * l, s, gl));
+        } else {
+            E(launch_seg_emit(seq, g.seg, kns, g.sst, g.scode, g.sfrag, next, g.codes[l], s, gl));
+            E(launch_seg_check(g.codes[l], g.seg, kns, g.sst, g.scode, g.cnt, 0, g.err + 2 * l, s, gl));
+        }
     }
-    E(launch_fill_u32(g.counters, 2 * g.L, 0u, s));
     for (uint32_t l = 0; l < g.L; l++) {
         RunArgs r{};
         r.codes = g.codes[l];
@@ -464,7 +478,7 @@ static hipError_t enqueue_generation(ev_ctx* c, GenGraph& g, int a, hipStream_t 
         r.refs = l ? 1u : 0u;
         r.verdict = g.err + 2 * l;
         r.gl = g.gls + l;
-        E(launch_run(r, g.grid, s));
+        E(launch_run(r, (uint32_t)std::min<uint64_t>(g.grid, (uint64_t)r.n_items), s));
     }
     FitArgs fa = {};
     for (uint32_t l = 0; l < g.L; l++) fa.res[l] = g.res[l];
@@ -510,7 +524,7 @@ static ev_status capture(ev_ctx* c, GenGraph& g, int a)
 // same kernels and draws as the graph's): its children's plan sizes and
 // capped count.  The population buffers grow when the children need it.
 static ev_status host_generation(ev_ctx* c, GenGraph& g, int a, uint64_t gen, std::vector<LevelSize>* seen,
-                                 int32_t* capped)
+                                 int32_t* capped, uint64_t* nodes)
 {
     Exec& x = c->main;
     hipStream_t s = c->stream;
@@ -548,6 +562,7 @@ static ev_status host_generation(ev_ctx* c, GenGraph& g, int a, uint64_t gen, st
     HIPCHK(hipMemcpyAsync(g.off[b], kids->d_off, ((size_t)M + 1) * 8, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(g.fit[b], kids->d_fit, (size_t)M * 4, hipMemcpyDeviceToDevice, s));
     *seen = sizes_of(kids->plan);
+    *nodes = kids->total;
     const uint64_t next = gen + 1;
     if ((st = put(x, g.gen_at, &next, 8)) == EV_OK) st = sync(x);
     pop_free(c, kids);
@@ -644,6 +659,7 @@ extern "C" ev_status ev_evolve(ev_ctx* c, ev_pop parents, const float* fitness, 
             kids->fit_valid = true;
             if (capped_history) capped_history[i] = capped;
             rep.capped += (uint64_t)capped;
+            rep.nodes += kids->total;
             rep.generations++;
             if (cur != P) pop_free(c, cur);
             cur = kids;
@@ -757,9 +773,10 @@ extern "C" ev_status ev_evolve(ev_ctx* c, ev_pop parents, const float* fitness, 
         const GStatus gs = *G.h_st;
         std::vector<LevelSize> seen;
         int32_t capped = 0;
+        uint64_t nodes = gs.child_bytes;
         if (gs.poison) {
             // void: done again on the host-driven path, then new capacities
-            if ((st = host_generation(c, G, a, gen, &seen, &capped)) != EV_OK) return st;
+            if ((st = host_generation(c, G, a, gen, &seen, &capped, &nodes)) != EV_OK) return st;
             rep.fallbacks++;
             if ((st = replan(c, G, seen, tight)) != EV_OK) return st;
         } else {
@@ -776,6 +793,7 @@ extern "C" ev_status ev_evolve(ev_ctx* c, ev_pop parents, const float* fitness, 
         if (fit_history) std::memcpy(fit_history + (size_t)i * M, G.h_fit, (size_t)M * 4);
         if (capped_history) capped_history[i] = capped;
         rep.capped += (uint64_t)capped;
+        rep.nodes += nodes;
         rep.generations++;
         G.cur = b;
     }

@@ -52,6 +52,15 @@ struct SegIn {
     uint32_t last;  // holds the chunk's first token (read last)
 };
 
+// A level's segment length: SEG_TOKENS at a large level 0, a quarter of it
+// at a small one and at the skeleton levels, which have few tokens and need
+// the extra lanes (each segment is one lane of the structure passes).
+constexpr uint64_t SEG_BIG_LEVEL = 1ull << 26;
+constexpr uint32_t seg_len_for(int level, uint64_t tokens)
+{
+    return level == 0 && tokens >= SEG_BIG_LEVEL ? SEG_TOKENS : SEG_TOKENS / 4;
+}
+
 // Bytes of one segment's recording regions (its code kinds, its fragment
 // tokens) at a level whose segments hold at most seg_len tokens.
 constexpr uint64_t rec_kinds_stride(uint32_t seg_len) { return 4ull * seg_len + 64ull; }
@@ -166,6 +175,39 @@ struct RunArgs {
     uint32_t refs;          // 1 at the skeleton levels: REF slots are read ahead
     const uint32_t* verdict;  // the validator's flags for these code streams: nonzero runs nothing
     const GLevel* gl;         // nullable: a device-made level (its item count and spill rows replace n_items, slab_entries)
+};
+
+// One plan level of a chained launch of the register-stack kernel.
+struct RunLevel {
+    const uint32_t* codes;
+    const RunChunk* chunks;
+    const uint32_t* item_tree;  // per work item: its tree
+    const float* in_res;        // the previous level's slot rows
+    float* out_res;
+    const uint32_t* verdict;    // the validator's flags for the level's code streams
+    uint32_t first;             // the level's first place in the launch's queue
+    uint32_t n_items;           // work items x case blocks
+    uint32_t refs, pad;
+};
+
+// Several levels in one launch: a work item of a level waits for its tree's
+// items of the level before (need: work items per level and tree; done:
+// finished items x case blocks, cleared before the launch).
+struct ChainArgs {
+    const RunLevel* levels;
+    uint32_t n_levels;
+    uint32_t total;  // items of every level
+    uint32_t n_cb;
+    uint32_t M;      // trees (the stride of need and done)
+    uint32_t* counter;
+    const uint32_t* need;
+    uint32_t* done;
+    const float* x;
+    int32_t N;
+    uint32_t rowb;
+    float* slab;
+    uint64_t slab_entries;
+    uint32_t* flag;
 };
 
 // A work item as the evaluator sees it (32 bytes).

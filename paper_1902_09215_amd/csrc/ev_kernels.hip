@@ -627,7 +627,8 @@ __global__ void k_plan_items(const ChunkIn* __restrict__ ch, uint32_t n, const T
                              const uint32_t* __restrict__ bucket_start, uint64_t* __restrict__ code_begin,
                              uint64_t* __restrict__ frag_end, RunChunk* __restrict__ run, EvalChunk* __restrict__ slow,
                              uint32_t* __restrict__ code_tail, uint8_t* __restrict__ frag_tail,
-                             const uint32_t* __restrict__ item_at, const GLevel* __restrict__ gl)
+                             const uint32_t* __restrict__ item_at, const GLevel* __restrict__ gl,
+                             uint32_t* __restrict__ item_tree)
 {
     if (gl) {  // the tails follow the level's live totals
         n = gl->n;
@@ -651,6 +652,7 @@ __global__ void k_plan_items(const ChunkIn* __restrict__ ch, uint32_t n, const T
     const uint32_t k = j - b.chunk_first;
     const uint32_t at = item_at ? item_at[j]
                                 : bucket_start[len_bucket(c.len)] + (k + 1 < b.n_chunks ? b.rank_full + k : b.rank_last);
+    if (item_tree) item_tree[at] = c.tree;
     if (run)
         run[at] = RunChunk{cb, in_end[j], oe};
     else
@@ -2131,16 +2133,22 @@ __device__ __forceinline__ void g_poison(GStatus* st, uint32_t bits, uint32_t le
 
 // The children from their offsets (k_xo_offsets' layout: off[M] the total,
 // off[M + 1] the number capped, off[M + 3] the copy pieces): each tree
-// active at level 0 over its own bytes.
+// active at level 0 over its own bytes.  Block 0 also starts the
+// generation's status and clears the interpreter's work counters.
 __global__ void k_g_init(const uint64_t* __restrict__ off, uint32_t M, GTree* __restrict__ tr, uint64_t bytes_cap,
-                         uint32_t pad_len, uint64_t pieces_cap, GStatus* __restrict__ st)
+                         uint32_t pad_len, uint64_t pieces_cap, GStatus* __restrict__ st,
+                         uint32_t* __restrict__ counters, uint32_t n_counters)
 {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0)
+        for (uint32_t k = threadIdx.x; k < n_counters; k += blockDim.x) counters[k] = 0;
     if (j == 0) {
         const uint64_t total = off[M], pieces = off[M + 3];
-        st->child_bytes = total;
-        st->capped = off[M + 1];
-        if (total + pad_len > bytes_cap || pieces > pieces_cap) g_poison(st, G_OVF_BYTES, 0);
+        GStatus s0 = {};
+        s0.child_bytes = total;
+        s0.capped = off[M + 1];
+        if (total + pad_len > bytes_cap || pieces > pieces_cap) s0.poison = G_OVF_BYTES;
+        *st = s0;
     }
     if (j < M) tr[j] = GTree{off[j], off[j + 1] - off[j], 0, 0, 1};
 }
@@ -2152,15 +2160,20 @@ __device__ __forceinline__ uint64_t g_nseg(uint64_t len, uint32_t seg_len, uint3
 
 // One block: the level's trees, in tree order, with their chunks and
 // segments numbered by exclusive scans (rounds of 1024 trees, each scanned
-// by wave shuffles and the waves' totals on top of the rounds before).
+// by wave shuffles and the waves' totals on top of the rounds before), and
+// their work items' places longest first: each length bucket's first place
+// (bucket_start, after the counts of every tree) and each tree's ranks in
+// its buckets (taken with shared atomics: the order inside a bucket does
+// not matter).
 __global__ __launch_bounds__(1024) void k_g_begin(const GTree* __restrict__ tr, uint32_t M, GLevel* __restrict__ gls,
                                                   uint32_t level, const GCap* __restrict__ caps, uint64_t C,
                                                   uint32_t seg_len, uint32_t head, uint32_t record,
-                                                  TreeLvl* __restrict__ tl, GStatus* __restrict__ st)
+                                                  TreeLvl* __restrict__ tl, uint32_t* __restrict__ bucket_start,
+                                                  GStatus* __restrict__ st)
 {
     __shared__ uint64_t wsum[3][16], carry[3];
     __shared__ unsigned long long s_tok;
-    __shared__ uint32_t s_bad;
+    __shared__ uint32_t s_bad, hist[EV_LEN_BUCKETS], rank[EV_LEN_BUCKETS];
     const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
     const bool live = st->poison == 0 && (level == 0 || gls[level - 1].any != 0);
     if (!live) {
@@ -2176,6 +2189,7 @@ __global__ __launch_bounds__(1024) void k_g_begin(const GTree* __restrict__ tr, 
         s_tok = 0;
         s_bad = 0;
     }
+    if (t < EV_LEN_BUCKETS) hist[t] = rank[t] = 0;
     __syncthreads();
     for (uint32_t r0 = 0; r0 < M; r0 += 1024) {
         const uint32_t i = r0 + t;
@@ -2186,8 +2200,13 @@ __global__ __launch_bounds__(1024) void k_g_begin(const GTree* __restrict__ tr, 
         const bool whole = len <= C || (level > 0 && len * 2 > q.prev_len);
         const uint64_t Ct = whole ? len : C;
         const uint64_t nc = act ? (whole ? 1 : (len + C - 1) / C) : 0;
-        const uint64_t ns = act ? (nc - 1) * g_nseg(Ct, seg_len, head) + g_nseg(len - (nc - 1) * Ct, seg_len, head) : 0;
+        const uint64_t last = act ? len - (nc - 1) * Ct : 0;
+        const uint64_t ns = act ? (nc - 1) * g_nseg(Ct, seg_len, head) + g_nseg(last, seg_len, head) : 0;
         if (act && whole && len > 0xFFFFFFFFull) atomicOr(&s_bad, 1u);
+        if (act) {
+            if (nc > 1) atomicAdd(&hist[len_bucket((uint32_t)Ct)], (uint32_t)(nc - 1));
+            atomicAdd(&hist[len_bucket((uint32_t)last)], 1u);
+        }
         uint64_t a = act ? 1 : 0, b = nc, c = ns, tok = len;
         for (uint32_t d = 1; d < 64; d <<= 1) {
             const uint64_t a0 = __shfl_up(a, d, 64), b0 = __shfl_up(b, d, 64), c0 = __shfl_up(c, d, 64);
@@ -2221,7 +2240,7 @@ __global__ __launch_bounds__(1024) void k_g_begin(const GTree* __restrict__ tr, 
             v.C = (uint32_t)Ct;
             v.tree = i;
             v.ref_base = q.ref_base;
-            v.rank_full = v.rank_last = 0;  // places come from the device counting sort
+            v.rank_full = v.rank_last = 0;  // below
             tl[(uint32_t)(ba + a - 1)] = v;
         }
         __syncthreads();  // every thread has read carry and the waves' totals
@@ -2232,89 +2251,144 @@ __global__ __launch_bounds__(1024) void k_g_begin(const GTree* __restrict__ tr, 
         }
         __syncthreads();
     }
+    const uint32_t nt = (uint32_t)carry[0];
+    const GCap cp = caps[level];
+    const bool over = s_bad || carry[1] > cp.n || carry[2] > cp.n_seg;
     if (t == 0) {
-        const GCap cp = caps[level];
         GLevel v = {};
         v.record = record;
         v.tokens = s_tok;
         v.prev_out = level ? gls[level - 1].so : 0;
-        if (s_bad || carry[1] > cp.n || carry[2] > cp.n_seg) {
+        if (over) {
             g_poison(st, G_OVF_ITEMS, level);
         } else {
-            v.nt = (uint32_t)carry[0];
+            v.nt = nt;
             v.n = (uint32_t)carry[1];
             v.n_seg = (uint32_t)carry[2];
+            // each bucket's first place
+            for (uint32_t k = 0, acc = 0; k < EV_LEN_BUCKETS; k++) {
+                bucket_start[k] = acc;
+                acc += hist[k];
+            }
         }
         gls[level] = v;
     }
+    if (over) return;
+    // the trees' ranks in their buckets (their records were written above
+    // by this block)
+    __syncthreads();
+    for (uint32_t i = t; i < nt; i += blockDim.x) {
+        TreeLvl v = tl[i];
+        const uint32_t nc = v.n_chunks;
+        const uint32_t last = (uint32_t)(v.len - (uint64_t)(nc - 1) * v.C);
+        v.rank_full = nc > 1 ? atomicAdd(&rank[len_bucket(v.C)], nc - 1) : 0u;
+        v.rank_last = atomicAdd(&rank[len_bucket(last)], 1u);
+        tl[i] = v;
+    }
 }
 
-// One block: the level's totals from its trees' (in the level's order), the
-// trees that end here (their value's level and slot) and the next level's
-// ranges, checked against the capacities.
+// One block: the trees' bases over the level's chunks, in the level's order
+// (exclusive sums of their slots, fragment tokens and codes, stored by tree
+// id with the tree's chunk range and bucket ranks, as k_plan_bases makes
+// them), the trees that end here (their value's level and slot) and the
+// next level's ranges; the level's totals are checked against the
+// capacities.
 __global__ __launch_bounds__(1024) void k_g_end(GTree* __restrict__ tr, GLevel* __restrict__ gls, uint32_t level,
                                                 const GCap* __restrict__ caps, uint32_t n_levels,
                                                 const TreeLvl* __restrict__ tl, const TreeSum* __restrict__ sum,
-                                                const TreeBase* __restrict__ tb, uint32_t* __restrict__ fin,
+                                                TreeBase* __restrict__ tb, uint32_t* __restrict__ fin,
                                                 GStatus* __restrict__ st)
 {
-    __shared__ unsigned long long s_so, s_sf, s_sc;
+    __shared__ uint64_t wo[16], wf[16], wc[16], carry[3];
     __shared__ uint32_t s_top, s_bad, s_any;
-    const uint32_t t = threadIdx.x;
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
     const uint32_t nt = gls[level].nt;
     if (nt == 0) return;  // no work at this level, or voided
     if (t == 0) {
-        s_so = s_sf = s_sc = 0;
+        carry[0] = carry[1] = carry[2] = 0;
         s_top = s_bad = s_any = 0;
     }
     __syncthreads();
-    for (uint32_t i = t; i < nt; i += blockDim.x) {
-        const TreeSum q = sum[i];
-        const uint32_t tree = tl[i].tree;
-        const TreeBase b = tb[tree];
-        uint32_t bad = 0;
-        if (q.bad & 1u) bad |= G_MALFORMED;
-        if (q.bad & 2u) bad |= G_INCONSISTENT;
-        if (q.bad & HAS_CONST) bad |= G_CONSTS;
-        if (bad) atomicOr(&s_bad, bad);
-        atomicMax(&s_top, q.maxtop);
-        atomicAdd(&s_so, (unsigned long long)q.n_out);
-        atomicAdd(&s_sf, (unsigned long long)q.n_frag);
-        atomicAdd(&s_sc, (unsigned long long)q.n_codes);
-        if (q.n_frag == 1) {
-            fin[2 * (size_t)tree] = level;
-            fin[2 * (size_t)tree + 1] = (uint32_t)(b.out + q.n_out - 1);
-            tr[tree].active = 0;
-        } else {
-            s_any = 1;
-            GTree r = tr[tree];
-            r.prev_len = r.rl;
-            r.rs = b.frag;
-            r.rl = q.n_frag;
-            r.ref_base = (uint32_t)b.out;
-            tr[tree] = r;
+    for (uint32_t r0 = 0; r0 < nt; r0 += 1024) {
+        const uint32_t i = r0 + t;
+        TreeSum q = {};
+        if (i < nt) q = sum[i];
+        const uint64_t o = q.n_out, f = q.n_frag, c = q.n_codes;
+        uint64_t so = o, sf = f, sc = c;  // inclusive sums within the wave
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint64_t ao = __shfl_up(so, d), af = __shfl_up(sf, d), ac = __shfl_up(sc, d);
+            if (lane >= d) {
+                so += ao;
+                sf += af;
+                sc += ac;
+            }
         }
+        if (lane == 63) {
+            wo[w] = so;
+            wf[w] = sf;
+            wc[w] = sc;
+        }
+        __syncthreads();
+        uint64_t bo = carry[0], bf = carry[1], bc = carry[2];
+        for (uint32_t k = 0; k < w; k++) {
+            bo += wo[k];
+            bf += wf[k];
+            bc += wc[k];
+        }
+        if (i < nt) {
+            const TreeLvl v = tl[i];
+            const uint32_t tree = v.tree;
+            const TreeBase b{bo + so - o, bf + sf - f, bc + sc - c, v.chunk_first, v.n_chunks, v.rank_full, v.rank_last};
+            tb[tree] = b;
+            uint32_t bad = 0;
+            if (q.bad & 1u) bad |= G_MALFORMED;
+            if (q.bad & 2u) bad |= G_INCONSISTENT;
+            if (q.bad & HAS_CONST) bad |= G_CONSTS;
+            if (bad) atomicOr(&s_bad, bad);
+            atomicMax(&s_top, q.maxtop);
+            if (q.n_frag == 1) {
+                fin[2 * (size_t)tree] = level;
+                fin[2 * (size_t)tree + 1] = (uint32_t)(b.out + q.n_out - 1);
+                tr[tree].active = 0;
+            } else {
+                s_any = 1;
+                GTree r = tr[tree];
+                r.prev_len = r.rl;
+                r.rs = b.frag;
+                r.rl = q.n_frag;
+                r.ref_base = (uint32_t)b.out;
+                tr[tree] = r;
+            }
+        }
+        __syncthreads();  // every thread has read carry and the waves' totals
+        if (t == 1023) {
+            carry[0] = bo + so;
+            carry[1] = bf + sf;
+            carry[2] = bc + sc;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     if (t == 0) {
         const GCap cp = caps[level];
+        GLevel& g = gls[level];
         uint32_t bad = s_bad;
         const uint32_t top = s_top;
+        const uint64_t so = carry[0], sf = carry[1], sc = carry[2];
         // the host-driven plan's rule: spill rows when the stack reaches
         // past the window's re-centring point
         const uint32_t slab = top + 1 > EV_VSTACK_ENTRIES - EV_VHALF / 2 ? top + EV_VHALF : 0u;
-        if (s_so > cp.so || s_sf > cp.sf || s_sc > cp.sc || s_so > 0xFFFFFFF0ull) bad |= G_OVF_SIZES;
+        if (so > cp.so || sf > cp.sf || sc > cp.sc || so > 0xFFFFFFF0ull) bad |= G_OVF_SIZES;
         if (slab > cp.slab) bad |= G_OVF_SLAB;
         if (s_any && level + 1 >= n_levels) bad |= G_OVF_LEVELS;
-        GLevel& g = gls[level];
+        if (g.record && g.record_ovf) bad |= G_OVF_ITEMS;  // a recording region was too small
         if (bad) {
             g_poison(st, bad, level);
             g.nt = g.n = g.n_seg = 0;
             g.any = 0;
         } else {
-            g.so = s_so;
-            g.sf = s_sf;
-            g.sc = s_sc;
+            g.so = so;
+            g.sf = sf;
+            g.sc = sc;
             g.slab_entries = slab;
             g.any = s_any;
             st->levels = level + 1;
@@ -2345,6 +2419,74 @@ __global__ __launch_bounds__(256) void k_g_finish(GStatus* __restrict__ st, cons
     }
     for (uint32_t l = t; l < n_levels; l += blockDim.x) h_levels[l] = gls[l];
     for (uint32_t j = t; j < M; j += blockDim.x) h_fit[j] = fit[j];
+}
+
+// The skeleton levels in one persistent launch (Sec. 2.2's subtrees
+// combined level by level, without a barrier between levels): the queue
+// holds the levels' work items level after level, and an item of level l
+// of tree t waits until every item of level l - 1 of tree t has finished.
+// Every item it waits for sits earlier in the queue, and a wave takes its
+// next item only after finishing its current one, so the earliest
+// unfinished item always runs and the wait ends.  Slot rows cross compute
+// units through agent-scope release (after an item) and acquire (before).
+__global__ __launch_bounds__(64) void k_run_chain(ChainArgs a)
+{
+    const uint32_t lane = threadIdx.x;
+    const uint64_t smem = (uint64_t)(uintptr_t)a.slab + (uint64_t)blockIdx.x * a.slab_entries * 256u;
+    uint32_t item = wave_pop(a.counter);
+    while (item < a.total) {
+        const uint32_t next = wave_pop(a.counter);
+        uint32_t l = 0;
+        while (l + 1 < a.n_levels && item >= a.levels[l + 1].first) l++;
+        const RunLevel L = a.levels[l];
+        const uint32_t local = item - L.first;
+        const uint32_t ci = local / a.n_cb;
+        const uint32_t cb = local - ci * a.n_cb;
+        const uint32_t tree = (uint32_t)__builtin_amdgcn_readfirstlane(L.item_tree[ci]);
+        if (l > 0) {
+            const uint32_t* dp = a.done + (size_t)(l - 1) * a.M + tree;
+            const uint32_t want = a.need[(size_t)(l - 1) * a.M + tree] * a.n_cb;
+            while (__hip_atomic_load(dp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want)
+                __builtin_amdgcn_s_sleep(4);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        // a level whose code streams failed validation runs none of them
+        // (its items still count as done)
+        if (!(L.verdict && *L.verdict)) {
+            const_u4p chunks = (const_u4p)(global_u4p)(const void*)L.chunks;
+            const u32x4 d = chunks[ci];
+            const uint64_t code_begin = (uint64_t)d.x | ((uint64_t)d.y << 32);
+            const int32_t cs = (int32_t)(cb * 64u + lane);
+            if (cs < a.N) {
+                // wave-uniform operands in scalar registers (readfirstlane
+                // returns an int: each half goes through uint32_t, so that
+                // the low word is not sign-extended into the high one)
+                auto uni = [](uint64_t v) {
+                    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+                    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+                    return (uint64_t)lo | ((uint64_t)hi << 32);
+                };
+                const float xv = a.x[cs];
+                const uint32_t lane4 = (uint32_t)cs * 4u;
+                const uint64_t cptr = uni((uint64_t)(uintptr_t)L.codes + (code_begin & ~(uint64_t)31) * 4u);
+                const uint32_t j0 = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(code_begin & 31u));
+                const uint64_t inp = uni((uint64_t)(uintptr_t)L.in_res + (uint64_t)d.z * a.rowb);
+                const uint64_t outp = uni((uint64_t)(uintptr_t)L.out_res + (uint64_t)d.w * a.rowb);
+                const uint32_t slane = lane * 4u;
+                const uint32_t refs = (uint32_t)__builtin_amdgcn_readfirstlane(L.refs);
+                asm volatile(EV_INTERP_ASM
+                             :
+                             : [x] "v"(xv), [lane4] "v"(lane4), [slane] "v"(slane), [cptr] "s"(cptr), [j0] "s"(j0),
+                               [inp] "s"(inp), [outp] "s"(outp), [rowb] "s"(a.rowb), [smem] "s"(smem),
+                               [flag] "s"(a.flag), [refs] "s"(refs)
+                             : EV_INTERP_CLOBBERS);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) __hip_atomic_fetch_add(a.done + (size_t)l * a.M + tree, 1u, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        item = next;
+    }
 }
 
 }  // namespace ev
@@ -2418,11 +2560,11 @@ hipError_t launch_plan_items(const ChunkIn* ch, uint32_t n, const TreeBase* base
                              const uint32_t* cursor,
                              uint64_t* code_begin, uint64_t* frag_end, RunChunk* run, EvalChunk* slow,
                              uint32_t* code_tail, uint8_t* frag_tail, const uint32_t* item_at, hipStream_t s,
-                             const GLevel* gl)
+                             const GLevel* gl, uint32_t* item_tree)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_plan_items, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, base, code_loc, out_loc, frag_loc,
-                       in_end, cursor, code_begin, frag_end, run, slow, code_tail, frag_tail, item_at, gl);
+                       in_end, cursor, code_begin, frag_end, run, slow, code_tail, frag_tail, item_at, gl, item_tree);
     return hipGetLastError();
 }
 
@@ -2588,6 +2730,19 @@ hipError_t run_occupancy(int* blocks_per_cu)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, reinterpret_cast<const void*>(&k_run), 64, 0);
 }
 
+hipError_t chain_occupancy(int* blocks_per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, reinterpret_cast<const void*>(&k_run_chain), 64,
+                                                        0);
+}
+
+hipError_t launch_run_chain(const ChainArgs& a, uint32_t grid, hipStream_t s)
+{
+    if (a.total == 0 || grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_run_chain, dim3(grid), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_run(const RunArgs& a, uint32_t grid, hipStream_t s)
 {
     if (a.n_items == 0 || grid == 0) return hipSuccess;
@@ -2653,22 +2808,24 @@ hipError_t launch_select(const float* fit, const uint64_t* off, uint32_t M, int3
 
 
 hipError_t launch_g_init(const uint64_t* off, uint32_t M, GTree* tr, uint64_t bytes_cap, uint32_t pad_len,
-                         uint64_t pieces_cap, GStatus* st, hipStream_t s)
+                         uint64_t pieces_cap, GStatus* st, uint32_t* counters, uint32_t n_counters, hipStream_t s)
 {
     hipLaunchKernelGGL(k_g_init, dim3(cdiv(M ? M : 1, 256)), dim3(256), 0, s, off, M, tr, bytes_cap, pad_len,
-                       pieces_cap, st);
+                       pieces_cap, st, counters, n_counters);
     return hipGetLastError();
 }
 
 hipError_t launch_g_begin(const GTree* tr, uint32_t M, GLevel* gls, uint32_t level, const GCap* caps, uint64_t C,
-                          uint32_t seg_len, uint32_t head, uint32_t record, TreeLvl* tl, GStatus* st, hipStream_t s)
+                          uint32_t seg_len, uint32_t head, uint32_t record, TreeLvl* tl, uint32_t* bucket_start,
+                          GStatus* st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_g_begin, dim3(1), dim3(1024), 0, s, tr, M, gls, level, caps, C, seg_len, head, record, tl, st);
+    hipLaunchKernelGGL(k_g_begin, dim3(1), dim3(1024), 0, s, tr, M, gls, level, caps, C, seg_len, head, record, tl,
+                       bucket_start, st);
     return hipGetLastError();
 }
 
 hipError_t launch_g_end(GTree* tr, GLevel* gls, uint32_t level, const GCap* caps, uint32_t n_levels, const TreeLvl* tl,
-                        const TreeSum* sum, const TreeBase* tb, uint32_t* fin, GStatus* st, hipStream_t s)
+                        const TreeSum* sum, TreeBase* tb, uint32_t* fin, GStatus* st, hipStream_t s)
 {
     hipLaunchKernelGGL(k_g_end, dim3(1), dim3(1024), 0, s, tr, gls, level, caps, n_levels, tl, sum, tb, fin, st);
     return hipGetLastError();

@@ -27,7 +27,7 @@ hipError_t launch_plan_items(const ChunkIn* ch, uint32_t n, const TreeBase* base
                              const uint32_t* cursor,
                              uint64_t* code_begin, uint64_t* frag_end, RunChunk* run, EvalChunk* slow,
                              uint32_t* code_tail, uint8_t* frag_tail, const uint32_t* item_at, hipStream_t s,
-                            const GLevel* gl = nullptr);
+                            const GLevel* gl = nullptr, uint32_t* item_tree = nullptr);
 // children reusing their mum's level-0 chunks
 hipError_t launch_reuse_runs(const XoPlan* plan, const int32_t* mum, const L0Tree* trees, const ChunkIn* mum_ch,
                              uint32_t n, ReuseRun* out, hipStream_t s);
@@ -77,6 +77,9 @@ hipError_t eval_occupancy(int D, int* blocks_per_cu);
 hipError_t launch_eval(int D, const EvalArgs& a, uint32_t grid, hipStream_t s);
 hipError_t run_occupancy(int* blocks_per_cu);
 hipError_t launch_run(const RunArgs& a, uint32_t grid, hipStream_t s);
+// the skeleton levels of a plan in one launch (see k_run_chain)
+hipError_t chain_occupancy(int* blocks_per_cu);
+hipError_t launch_run_chain(const ChainArgs& a, uint32_t grid, hipStream_t s);
 
 
 hipError_t launch_fitness(const FitArgs& a, hipStream_t s);
@@ -96,11 +99,12 @@ hipError_t launch_select(const float* fit, const uint64_t* off, uint32_t M, int3
 // a generation replayed from a graph: the children's trees, each plan
 // level's first and last step, and the generation's verdict
 hipError_t launch_g_init(const uint64_t* off, uint32_t M, GTree* tr, uint64_t bytes_cap, uint32_t pad_len,
-                         uint64_t pieces_cap, GStatus* st, hipStream_t s);
+                         uint64_t pieces_cap, GStatus* st, uint32_t* counters, uint32_t n_counters, hipStream_t s);
 hipError_t launch_g_begin(const GTree* tr, uint32_t M, GLevel* gls, uint32_t level, const GCap* caps, uint64_t C,
-                          uint32_t seg_len, uint32_t head, uint32_t record, TreeLvl* tl, GStatus* st, hipStream_t s);
+                          uint32_t seg_len, uint32_t head, uint32_t record, TreeLvl* tl, uint32_t* bucket_start,
+                          GStatus* st, hipStream_t s);
 hipError_t launch_g_end(GTree* tr, GLevel* gls, uint32_t level, const GCap* caps, uint32_t n_levels, const TreeLvl* tl,
-                        const TreeSum* sum, const TreeBase* tb, uint32_t* fin, GStatus* st, hipStream_t s);
+                        const TreeSum* sum, TreeBase* tb, uint32_t* fin, GStatus* st, hipStream_t s);
 hipError_t launch_g_finish(GStatus* st, const GLevel* gls, uint32_t n_levels, const uint32_t* err, const float* fit,
                            uint32_t M, uint64_t* gen_at, GStatus* h_st, GLevel* h_levels, float* h_fit, hipStream_t s);
 }  // namespace ev

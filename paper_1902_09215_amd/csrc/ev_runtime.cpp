@@ -186,8 +186,11 @@ void plan_free(ev_ctx* c, Plan& pl)
         dev_free(c, L.d_chunks);
         dev_free(c, L.codes);
         dev_free(c, L.d_run);
+        dev_free(c, L.d_item_tree);
     }
     pl.levels.clear();
+    dev_free(c, pl.d_need);
+    pl.d_need = nullptr;
     pl.fin_level.clear();
     pl.fin_slot.clear();
     dev_free(c, pl.d_fin);
@@ -222,6 +225,8 @@ void rescache_free(ev_ctx* c, ResCache& r)
 
     dev_free(c, r.d_per_case);
     r.d_per_case = nullptr;
+    dev_free(c, r.d_chain);
+    r.d_chain = nullptr;
 }
 
 void pop_free(ev_ctx* c, Pop* P)
@@ -340,6 +345,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
     auto bucket = [](uint64_t len) { return len ? (uint32_t)__builtin_clz((uint32_t)len) : 32u; };
 
     bool plan_run = c->use_run;  // items on the register-stack kernel (no constants seen)
+    std::vector<uint32_t> need_all;  // per level and tree: work items (register-stack levels)
     std::vector<TreeReuse> trv;  // level 0 of a reusing plan: the children's runs
     if (reuse) {
         const Plan& mp = reuse->mum->plan;
@@ -351,11 +357,11 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
     for (;;) {
         const uint64_t C = level == 0 ? C0 : C1;
         const bool reusing = level == 0 && reuse != nullptr;
-        // Segments are 256 tokens at level 0 and 64 at the skeleton levels,
-        // which have few tokens and need the extra parallelism; a chunk's
-        // first segment, which also emits the chunk's final flush, is a
-        // quarter of that.
-        const uint32_t seg_len = level == 0 ? SEG_TOKENS : SEG_TOKENS / 4;
+        // Segments are 256 tokens at a large level 0 and 64 at a small one
+        // and at the skeleton levels, which need the extra parallelism; a
+        // chunk's first segment, which also emits the chunk's final flush,
+        // is a quarter of that.
+        const uint32_t seg_len = seg_len_for(level, cur_len);
         const uint32_t head = seg_len / 4;
         auto nseg = [&](uint64_t len) -> uint64_t { return len <= head ? 1 : 1 + (len - head + seg_len - 1) / seg_len; };
         tl.clear();
@@ -569,6 +575,11 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
             return fail(EV_EDEVICE, "internal: reused level-0 chunks in a plan without the register-stack kernel");
         }
         const bool run_items = plan_run;
+        if (run_items && need_all.size() == (size_t)level * M) {
+            // each tree's work items at this level, for the chained launch
+            need_all.resize((size_t)(level + 1) * M, 0u);
+            for (uint32_t i = 0; i < nt; i++) need_all[(size_t)level * M + tl[i].tree] = tl[i].n_chunks;
+        }
 
         Level L;
         L.seq = cur;
@@ -595,6 +606,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
             if ((st = dev_alloc(c, n * sizeof(EvalChunk), (void**)&LL.d_chunks)) != EV_OK) { cleanup(); return st; }
         } else {
             if ((st = dev_alloc(c, n * sizeof(RunChunk), (void**)&LL.d_run)) != EV_OK) { cleanup(); return st; }
+            if ((st = dev_alloc(c, n * sizeof(uint32_t), (void**)&LL.d_item_tree)) != EV_OK) { cleanup(); return st; }
             // 512 zero bytes after the stream (written with the work items):
             // the interpreter reads up to 192 bytes past a stream's last code
             // block, the validator up to 124
@@ -637,7 +649,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
                                  (uint32_t*)d_inend, (uint32_t*)((uint8_t*)d_tl + tl_bytes), (uint64_t*)d_cb,
                                  (uint64_t*)d_fe, run_items ? LL.d_run : nullptr, run_items ? nullptr : LL.d_chunks,
                                  run_items ? LL.codes + sc : nullptr, any ? d_next + sf : nullptr,
-                                 reusing ? (uint32_t*)d_at : nullptr, s));
+                                 reusing ? (uint32_t*)d_at : nullptr, s, nullptr, run_items ? LL.d_item_tree : nullptr));
         if (any || run_items) {
             HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, (uint32_t)n, (SegCount*)d_cnt, (ChunkStat*)d_stat,
                                     (uint64_t*)d_cb, (uint64_t*)d_fe, (uint64_t*)d_scode, (uint64_t*)d_sfrag, s));
@@ -725,6 +737,13 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
     }
     pl.d_err = (uint32_t*)d_err;  // the plan keeps the validator's words
     d_err = nullptr;
+    if (pl.levels.size() >= 3 && need_all.size() == pl.levels.size() * (size_t)M) {
+        if ((st = dev_alloc(c, need_all.size() * sizeof(uint32_t), (void**)&pl.d_need)) != EV_OK ||
+            (st = put(x, pl.d_need, need_all.data(), need_all.size() * sizeof(uint32_t))) != EV_OK) {
+            cleanup();
+            return st;
+        }
+    }
     cleanup();
     pl.bytes = 0;
     for (auto& L : pl.levels) pl.bytes += (uint64_t)L.n_chunks * sizeof(EvalChunk) + (uint64_t)L.n_run * sizeof(RunChunk);
@@ -1028,7 +1047,22 @@ struct EvalBufs {
     std::vector<float*> res;
     float* slab = nullptr;
     size_t slab_bytes = 0;
+    // the skeleton levels in one launch: their RunLevel records and the
+    // done counters ((levels - 1) x trees words); null: a launch per level
+    const RunLevel* chain = nullptr;
+    uint32_t* done = nullptr;
 };
+
+// The skeleton levels of P go in one chained launch: three levels or more,
+// every one on the register-stack kernel.
+static bool chain_applies(ev_ctx* c, const Pop* P)
+{
+    const Plan& pl = P->plan;
+    if (!c->use_chain || !pl.d_need || pl.levels.size() < 3) return false;
+    for (const Level& L : pl.levels)
+        if (L.n_chunks || !L.n_run || !L.d_item_tree) return false;
+    return true;
+}
 
 // Spill-slab bytes one wave of a level's interpreter needs (0: none).
 static size_t slab_per_wave(const Level& L, int D)
@@ -1068,8 +1102,42 @@ static ev_status eval_launch(ev_ctx* c, Exec& x, Pop* P, const CaseTable& ct, co
     }
     if (timed) HIPCHK(hipEventRecord(x.ev0, s));
     HIPCHK(launch_fill_u32(b.counters, (uint32_t)(2 * nl), 0u, s));
+    const bool chained = b.chain && b.done && nl >= 3;
+    if (chained) HIPCHK(launch_fill_u32(b.done, (uint32_t)((nl - 1) * (size_t)P->M), 0u, s));
     for (size_t li = 0; li < nl; li++) {
         const Level& L = P->plan.levels[li];
+        if (chained && li >= 1) {
+            if (li == 1) {
+                // levels 1 .. nl-1 in one launch (k_run_chain)
+                ChainArgs ca{};
+                ca.levels = b.chain;
+                ca.n_levels = (uint32_t)(nl - 1);
+                uint64_t total = 0, rows = 0;
+                for (size_t k = 1; k < nl; k++) {
+                    total += (uint64_t)P->plan.levels[k].n_run * n_cb;
+                    rows = std::max<uint64_t>(rows, P->plan.levels[k].slab_entries);
+                }
+                if (total > 0xFFFFFFF0ull) return fail(EV_ECAP, "too many skeleton work items for one launch");
+                ca.total = (uint32_t)total;
+                ca.n_cb = n_cb;
+                ca.M = (uint32_t)P->M;
+                ca.counter = b.counters + nl + 1;
+                ca.need = P->plan.d_need + P->M;  // from level 1 on
+                ca.done = b.done;
+                ca.x = ct.d_x;
+                ca.N = N;
+                ca.rowb = (uint32_t)N * 4u;
+                ca.slab = b.slab;
+                ca.slab_entries = rows;
+                ca.flag = c->d_flag;
+                uint64_t g = std::min<uint64_t>((uint64_t)c->grid_chain, total);
+                if (rows) g = std::min<uint64_t>(g, b.slab_bytes / (rows * 64 * sizeof(float)));
+                if (g == 0) return fail(EV_ECAP, "no room for one wave's spill slab (%llu rows)", (unsigned long long)rows);
+                HIPCHK(launch_run_chain(ca, (uint32_t)g, s));
+            }
+            if (timed) HIPCHK(hipEventRecord(x.evl[li], s));
+            continue;
+        }
         if (timed && li == 0) HIPCHK(hipEventRecord(x.evi0, s));
         if (L.n_run) {
             RunArgs r{};
@@ -1151,21 +1219,59 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
     ev_status st;
     if ((st = rescache_get(c, x, P, table, &rc)) != EV_OK) return st;
     const size_t nl = P->plan.levels.size();
-    if ((st = ensure_counters(c, x, 2 * nl)) != EV_OK) return st;
+    const bool chain = chain_applies(c, P);
+    // the work counters, then (chained) the done counters of levels 1 ..
+    if ((st = ensure_counters(c, x, 2 * nl + (chain ? (nl - 1) * (size_t)P->M : 0))) != EV_OK) return st;
     // spill slabs for every wave of each level's grid
     const uint32_t grid_max = (uint32_t)c->grid_eval[D == 128 ? 1 : 0];
-    size_t need = 0;
-    for (auto& L : P->plan.levels) {
+    size_t need = 0, chain_rows = 0;
+    uint64_t chain_items = 0;
+    for (size_t li = 0; li < nl; li++) {
+        const Level& L = P->plan.levels[li];
         const uint64_t items = (uint64_t)(L.n_run + L.n_chunks) * n_cb;
+        if (chain && li >= 1) {
+            chain_rows = std::max<size_t>(chain_rows, L.slab_entries);
+            chain_items += items;
+            continue;
+        }
         const uint64_t grid = std::min<uint64_t>(L.n_run ? (uint64_t)c->grid_run : grid_max, items);
         need = std::max(need, (size_t)grid * slab_per_wave(L, D));
     }
+    if (chain)
+        need = std::max(need, (size_t)std::min<uint64_t>(c->grid_chain, chain_items) * chain_rows * 64 * sizeof(float));
     if ((st = ensure_gstack(c, x, need)) != EV_OK) return st;
+    if (chain && !rc->d_chain) {
+        // the skeleton levels as the chained launch sees them (kept with
+        // the result slots of this case table)
+        std::vector<RunLevel> rl(nl - 1);
+        uint64_t first = 0;
+        for (size_t li = 1; li < nl; li++) {
+            const Level& L = P->plan.levels[li];
+            RunLevel& r = rl[li - 1];
+            r.codes = L.codes;
+            r.chunks = L.d_run;
+            r.item_tree = L.d_item_tree;
+            r.in_res = rc->res[li - 1];
+            r.out_res = rc->res[li];
+            r.verdict = P->plan.d_err ? P->plan.d_err + 2 * li : nullptr;
+            r.first = (uint32_t)first;
+            r.n_items = L.n_run * n_cb;
+            r.refs = 1;
+            first += (uint64_t)L.n_run * n_cb;
+        }
+        if ((st = dev_alloc(c, rl.size() * sizeof(RunLevel), (void**)&rc->d_chain)) != EV_OK ||
+            (st = put(x, rc->d_chain, rl.data(), rl.size() * sizeof(RunLevel))) != EV_OK)
+            return st;
+    }
     EvalBufs b;
     b.counters = x.d_counters;
     b.res = rc->res;
     b.slab = x.d_gstack;
     b.slab_bytes = x.gstack_bytes;
+    if (chain) {
+        b.chain = rc->d_chain;
+        b.done = x.d_counters + 2 * nl;
+    }
     return eval_launch(c, x, P, ct, b, d_fit, d_per_case, d_hits, timed);
 }
 
@@ -1361,6 +1467,9 @@ ev_status ev_create(ev_ctx** out, int device, const float* x, const float* y, in
         if (run_occupancy(&bpc) != hipSuccess || bpc < 1) bpc = 1;
         c->run_bpc = bpc;
         c->grid_run = bpc * c->num_cus;
+        bpc = 0;
+        if (chain_occupancy(&bpc) != hipSuccess || bpc < 1) bpc = 1;
+        c->grid_chain = bpc * c->num_cus;
     }
     int32_t tid = 0;
     ev_status st = ev_add_cases(c, x, y, n_cases, &tid);
@@ -1414,18 +1523,60 @@ static ev_status run_probe(ev_ctx* c)
     r.slab_entries = 0;
     r.flag = c->d_flag;
     r.refs = 0;
-    uint32_t flag = 0;
+    uint32_t flag = 0, flag2 = 0;
     if (st == EV_OK) {
         hipError_t e = launch_run(r, 1, x.stream);
         if (e != hipSuccess) st = hip_fail(e, "probe launch");
     }
     if (st == EV_OK) st = get(x, &flag, c->d_flag, 4);
+    // the same one-code stream through the chained launch (its own copy of
+    // the handler table): one level, one item, its tree's done counter
+    RunLevel* lv = (RunLevel*)((char*)buf + 3072);       // [3072, 3136)
+    uint32_t* done = (uint32_t*)((char*)buf + 1536);       // [1536, 1540)
+    uint32_t* counter2 = (uint32_t*)((char*)buf + 1792);   // [1792, 1796)
+    uint32_t* item_tree = (uint32_t*)((char*)buf + 1800);  // [1800, 1804)
+    if (st == EV_OK) {
+        RunLevel l0{};
+        l0.codes = codes;
+        l0.chunks = chunk;
+        l0.item_tree = item_tree;
+        l0.in_res = slot;
+        l0.out_res = slot;
+        l0.first = 0;
+        l0.n_items = 1;
+        l0.refs = 0;
+        const uint32_t z4[4] = {0, 0, 0, 0};
+        if ((st = put(x, lv, &l0, sizeof l0)) == EV_OK && (st = put(x, done, z4, 4)) == EV_OK &&
+            (st = put(x, counter2, z4, 4)) == EV_OK && (st = put(x, item_tree, z4, 4)) == EV_OK &&
+            (st = put(x, c->d_flag, &zero, 4)) == EV_OK) {
+            ChainArgs ca{};
+            ca.levels = lv;
+            ca.n_levels = 1;
+            ca.total = 1;
+            ca.n_cb = 1;
+            ca.M = 1;
+            ca.counter = counter2;
+            ca.need = done;
+            ca.done = done;
+            ca.x = t0.d_x;
+            ca.N = 1;
+            ca.rowb = 4;
+            ca.flag = c->d_flag;
+            hipError_t e = launch_run_chain(ca, 1, x.stream);
+            if (e != hipSuccess) st = hip_fail(e, "probe launch");
+        }
+    }
+    if (st == EV_OK) st = get(x, &flag2, c->d_flag, 4);
     if (st == EV_OK) st = sync(x);
     else (void)sync(x);
     dev_free(c, buf);
     if (st == EV_OK && flag) {
         c->run_ok = false;
         c->use_run = false;
+    }
+    if (st == EV_OK && (flag || flag2)) {
+        c->grid_chain = 0;
+        c->use_chain = false;
     }
     return st;
 }
@@ -1779,6 +1930,7 @@ ev_status ev_get_level_info(ev_ctx* c, ev_pop pop, int32_t level, ev_level_info*
     info->items = L.n_run + L.n_chunks;
     info->slots = L.n_out;
     info->pad = 0;
+    info->codes = L.n_codes;
     return EV_OK;
 }
 
@@ -1792,6 +1944,7 @@ ev_status ev_set_tuning(ev_ctx* c, uint32_t chunk, uint32_t chunk_hi, uint32_t l
     c->test_fail_check = (flags & EV_TUNE_TEST_FAIL_CHECK) != 0;
     c->use_record = (flags & EV_TUNE_NO_RECORD) == 0;
     c->use_reuse = (flags & EV_TUNE_NO_REUSE) == 0;
+    c->use_chain = c->grid_chain > 0 && (flags & EV_TUNE_NO_CHAIN) == 0;
     if (chunk) c->chunk = chunk;
     if (chunk_hi) c->chunk_hi = chunk_hi;
     if (lds_depth) c->lds_depth = (int)lds_depth;

@@ -35,6 +35,7 @@ struct Level {
     uint32_t* codes = nullptr;      // threaded codes of the register-stack items
     RunChunk* d_run = nullptr;      // work items of the register-stack kernel (k_run)
     uint32_t n_run = 0;
+    uint32_t* d_item_tree = nullptr;  // per register-stack work item: its tree
     uint64_t tokens = 0;            // tokens over all work items of the level
     uint32_t trees = 0;             // trees with work at the level
     uint32_t slab_entries = 0;      // spill-slab rows per wave of k_run (0: no spills)
@@ -58,6 +59,9 @@ struct Plan {
     int err_level = 0;
     bool err_pending = false;
     uint32_t h_err[2] = {0, 0};
+    // per level and tree (levels x trees): the tree's work items, for the
+    // chained launch of the skeleton levels (null when it does not apply)
+    uint32_t* d_need = nullptr;
     uint32_t chunk = 0;
     int D = 64;
     uint64_t chunks_total = 0, slots_total = 0, max_stack = 0, bytes = 0;
@@ -87,6 +91,7 @@ struct ResCache {
     int32_t N = 0;
     std::vector<float*> res;     // per level: n_out * N floats (EV_RING padding rows before)
     float* d_per_case = nullptr;
+    RunLevel* d_chain = nullptr;  // the skeleton levels as the chained launch sees them
 };
 
 struct Pop {
@@ -166,6 +171,8 @@ struct ev_ctx {
     bool test_fail_check = false;  // EV_TUNE_TEST_FAIL_CHECK
     bool use_record = true;        // the count pass records codes for emission (EV_TUNE_NO_RECORD clears it)
     bool use_reuse = true;         // children take over their mums' level-0 chunks (EV_TUNE_NO_REUSE clears it)
+    bool use_chain = true;         // the skeleton levels in one launch (EV_TUNE_NO_CHAIN clears it)
+    int grid_chain = 0;
     uint32_t* d_flag = nullptr;  // the probe's flag word
     // ephemeral random constants (Sec. 2.1): token 6 + i is d_const[i]
     int32_t n_consts = 0;

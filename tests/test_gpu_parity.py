@@ -96,6 +96,27 @@ def test_skeleton_split_invariance(ev, chunk_hi):
     assert info["levels"] >= 2
 
 
+@pytest.mark.parametrize("n_cases", [48, 130])
+def test_skeleton_levels_chained_and_separate(ev, n_cases):
+    # many skeleton levels (64-token work items), evaluated in one chained
+    # launch (a tree's items at a level start once its items of the level
+    # before are done) and in one launch per level, against the oracle;
+    # deep trees spill at the skeleton levels too
+    x, y = workloads.cases(n_cases)
+    sizes = workloads.loguniform_sizes(79, 90, 10, 300000)
+    buf, off = workloads.random_population(79, sizes)
+    deep = np.array([ADD, MUL, SUB, DIV] * 2500 + [X] * 10001, np.uint8)
+    buf = np.concatenate([buf, deep])
+    off = np.append(off, off[-1] + deep.size).astype(np.uint64)
+    want_fit, want_pc = oracle.eval_population(buf, off, x, y, threads=8, per_case=True)
+    for flags in (0, ev.EV_TUNE_NO_CHAIN):
+        fit, pc, info, hits = run(ev, buf, off, x, y, chunk=64, flags=flags)
+        print(f"flags {flags}: levels {info['levels']}", flush=True)
+        assert info["levels"] >= 4
+        assert_same(pc, want_pc, f"per-case flags={flags}")
+        assert_same(fit, want_fit, f"fitness flags={flags}")
+
+
 def test_deep_stacks_spill_to_memory(ev):
     # (((x+x)*x)-x)... leans left: the right-to-left stack holds every leaf
     x, y = workloads.cases(48)
