@@ -317,6 +317,17 @@ def loop_bench(args, ev, workloads):
     warm = args.warmup
     start, _, _, _ = ev.ev_evolve(c.ctx, pop, seed, 0, warm, 2, cap, history=False)
     rg, rp, same = evolve_pair(ev, c, start, seed, warm, args.steps, cap)
+    # the memory-lean heap over the same generations
+    kl, fl, cl, rl = ev.ev_evolve(c.ctx, start, seed, warm, args.steps, 2, cap, flags=ev.EV_EVOLVE_LEAN)
+    kg, fg, _, _ = ev.ev_evolve(c.ctx, start, seed, warm, args.steps, 2, cap)
+    lean = {"ms_per_generation": rl["ms"] / max(1, rl["generations"]),
+            "peak_tree_bytes": rl["lean_peak_bytes"], "two_buffer_tree_bytes": rl["lean_two_buffer_bytes"],
+            "peak_fraction": rl["lean_peak_bytes"] / max(1, rl["lean_two_buffer_bytes"]),
+            "arena_bytes": rl["lean_arena_bytes"], "repacks": rl["lean_repacks"],
+            "bitexact_vs_graph": bool(((fl.view(np.uint32) == fg.view(np.uint32)) |
+                                       (np.isnan(fl) & np.isnan(fg))).all())}
+    for k in (kl, kg):
+        ev.ev_free_pop(c.ctx, k)
     cpu = None
     if not args.no_cpu:
         sb, so = ev.ev_get_trees(c.ctx, start)
@@ -345,6 +356,7 @@ def loop_bench(args, ev, workloads):
                     "subtree crossover + device-made split plan + eval + fitness",
         },
         "graph_loop": summ,
+        "lean_heap": lean,
         "roofline": None,
         "cpu_baseline": cpu,
     }

@@ -206,6 +206,16 @@ ev_status ev_generation(ev_ctx *ctx, ev_pop parents, const float *fitness, uint6
  * EV_EVOLVE_NO_GRAPH every generation runs on the host-driven path (the
  * plain form); so does a context with ephemeral constants.
  *
+ * With EV_EVOLVE_LEAN the loop keeps the population as a heap of trees
+ * (Sec. 2.3's early deletion of parents, with a heap of the population's
+ * own): one device arena, every tree anywhere in it.  Each generation's
+ * children are made in batches, in the order of their lower parent index,
+ * and a parent's bytes are reused for later children as soon as its last
+ * child is made, so about 1.25 populations' worth of trees are alive at
+ * once instead of 2.  The children are evaluated in place; the draws and
+ * results are those of the other forms, bit for bit.  Host-driven (one wait
+ * for the children's lengths per generation, then one per plan level).
+ *
  * Outputs: *out the last generation as a new population (planned, its
  * fitness as of its evaluation); fit_history[n_gen * n_trees] (host,
  * nullable) each generation's children's fitness; capped_history[n_gen]
@@ -222,9 +232,15 @@ typedef struct {
     uint64_t nodes;       /* children's nodes, over all generations */
     double ms;            /* wall time of the call */
     double ms_capture;    /* of which capturing and instantiating graphs */
+    /* EV_EVOLVE_LEAN: the most tree bytes alive at once in a generation, what
+     * separate parent and child buffers would hold (parents + children), the
+     * heap's capacity, and how often it was replaced by a larger one */
+    uint64_t lean_peak_bytes, lean_two_buffer_bytes, lean_arena_bytes;
+    int32_t lean_repacks, pad;
 } ev_evolve_report;
 #define EV_EVOLVE_NO_GRAPH 0x1u
 #define EV_EVOLVE_TEST_TIGHT 0x2u /* capacities of exactly the sizes last seen: exercises the fallback */
+#define EV_EVOLVE_LEAN 0x4u       /* the memory-lean loop (below) */
 ev_status ev_evolve(ev_ctx *ctx, ev_pop parents, const float *fitness, int32_t table, uint64_t seed,
                     uint64_t gen0, int32_t n_gen, int32_t tournament, uint64_t size_cap, uint32_t flags,
                     ev_pop *out, float *fit_history, int32_t *capped_history, ev_evolve_report *report);

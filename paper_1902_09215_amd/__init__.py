@@ -55,7 +55,9 @@ class ev_evolve_report(ctypes.Structure):
     _fields_ = [("generations", ctypes.c_int32), ("replayed", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
                 ("captures", ctypes.c_int32), ("capped", ctypes.c_uint64), ("nodes", ctypes.c_uint64),
                 ("ms", ctypes.c_double),
-                ("ms_capture", ctypes.c_double)]
+                ("ms_capture", ctypes.c_double), ("lean_peak_bytes", ctypes.c_uint64),
+                ("lean_two_buffer_bytes", ctypes.c_uint64), ("lean_arena_bytes", ctypes.c_uint64),
+                ("lean_repacks", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class ev_pop_stats(ctypes.Structure):
@@ -342,7 +344,7 @@ def ev_evolve(ctx, parents, seed: int, gen0: int, n_gen: int, tournament: int = 
     rep = ev_evolve_report()
     _check(_lib.ev_evolve(ctx, parents, _ptr(fitness), table, seed, gen0, n_gen, tournament, size_cap, flags,
                           ctypes.byref(out), _ptr(fh), _ptr(ch), ctypes.byref(rep)))
-    return out.value, fh, ch, {k: getattr(rep, k) for k, _ in ev_evolve_report._fields_}
+    return out.value, fh, ch, {k: getattr(rep, k) for k, _ in ev_evolve_report._fields_ if k != "pad"}
 
 
 def ev_submit_eval(ctx, buf, off, table: int = 0) -> int:
@@ -418,6 +420,7 @@ def level_functions(ctx, pop) -> list:
 EV_AUTOTUNE_NO_CACHE = 0x1
 EV_EVOLVE_NO_GRAPH = 0x1
 EV_EVOLVE_TEST_TIGHT = 0x2
+EV_EVOLVE_LEAN = 0x4
 
 
 def ev_autotune_ex(ctx, pop, table: int = 0, reps: int = 3, flags: int = 0) -> dict:

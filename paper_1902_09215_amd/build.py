@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["ev_kernels.hip", "ev_runtime.cpp", "ev_serve.cpp", "ev_static.hip", "ev_graph.cpp"]
+SOURCES = ["ev_kernels.hip", "ev_runtime.cpp", "ev_serve.cpp", "ev_static.hip", "ev_graph.cpp", "ev_lean.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # binary32 arithmetic exactly as written: no contraction, no fast math

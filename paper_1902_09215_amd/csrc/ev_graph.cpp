@@ -614,6 +614,13 @@ extern "C" ev_status ev_evolve(ev_ctx* c, ev_pop parents, const float* fitness, 
     Exec& x = c->main;
     hipStream_t s = c->stream;
     const int32_t M = P->M;
+    if ((flags & EV_EVOLVE_LEAN) && M > 0) {
+        ev_status st = evolve_lean(c, P, fitness, table, seed, gen0, n_gen, tournament, size_cap, out, fit_history,
+                                   capped_history, &rep);
+        rep.ms = ms_since(t0);
+        if (report) *report = rep;
+        return st;
+    }
     const bool graphs = !(flags & EV_EVOLVE_NO_GRAPH) && c->use_run && c->n_consts == 0 && M > 0;
     ev_status st = EV_OK;
 

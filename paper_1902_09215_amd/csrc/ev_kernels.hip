@@ -1686,32 +1686,12 @@ __device__ __forceinline__ u32x4 load16_at(const uint8_t* __restrict__ p)
                  (r3 >> sh) | (r4 << (32u - sh))};
 }
 
-__global__ void k_xo_copy(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
-                          const XoPlan* __restrict__ plan, const uint64_t* __restrict__ off, uint32_t n_children,
-                          uint8_t* __restrict__ dst, uint8_t* __restrict__ pad, uint32_t pad_len,
-                          const uint32_t* __restrict__ stop)
+// Piece `piece` (4 KiB) of child x (x.child_off: where its bytes go in dst).
+__device__ __forceinline__ void xo_copy_piece(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
+                                              const XoPlan& x, uint64_t piece, uint8_t* __restrict__ dst)
 {
-    // with stop (a replayed generation): nothing when the children do not
-    // fit their buffer, and the padding goes after their total
-    if (stop && *stop) return;
-    if (!pad) pad = dst + off[n_children];
-    if (blockIdx.x == 0)  // the buffer's padding of 0xFF after the children
-        for (uint32_t i = threadIdx.x; i < pad_len; i += blockDim.x) pad[i] = 0xFF;
-    // block b copies piece b: the child j with pf[j] <= b < pf[j + 1]
-    const uint64_t* pf = off + n_children + 4;
-    const uint64_t pb = blockIdx.x;
-    uint32_t j = 0, hi_j = n_children;
-    while (hi_j - j > 1) {
-        const uint32_t mid = (j + hi_j) / 2;
-        if (pf[mid] <= pb)
-            j = mid;
-        else
-            hi_j = mid;
-    }
-    XoPlan x = plan[j];
-    x.child_off = off[j];
-    const uint64_t lo = (pb - pf[j]) * 4096u;
-    if (pb < pf[j] || lo >= x.child_len) return;
+    const uint64_t lo = piece * 4096u;
+    if (lo >= x.child_len) return;
     const uint64_t hi = lo + 4096u < x.child_len ? lo + 4096u : x.child_len;
     const uint64_t a = x.p, b = x.p + (x.eq - x.q + 1);
     // output 16-byte words [w0, w1) lie wholly inside this child's bytes [lo, hi)
@@ -1747,6 +1727,57 @@ __global__ void k_xo_copy(const uint8_t* __restrict__ mums, const uint8_t* __res
     if (t < o1 - w1) dst[w1 + t] = child_byte(mums, dads, x, w1 + t - x.child_off, a, b);
 }
 
+// The child holding copy piece pb: the j with pf[j] <= pb < pf[j + 1].
+__device__ __forceinline__ uint32_t piece_child(const uint64_t* __restrict__ pf, uint32_t n, uint64_t pb)
+{
+    uint32_t j = 0, hi_j = n;
+    while (hi_j - j > 1) {
+        const uint32_t mid = (j + hi_j) / 2;
+        if (pf[mid] <= pb)
+            j = mid;
+        else
+            hi_j = mid;
+    }
+    return j;
+}
+
+__global__ void k_xo_copy(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
+                          const XoPlan* __restrict__ plan, const uint64_t* __restrict__ off, uint32_t n_children,
+                          uint8_t* __restrict__ dst, uint8_t* __restrict__ pad, uint32_t pad_len,
+                          const uint32_t* __restrict__ stop)
+{
+    // with stop (a replayed generation): nothing when the children do not
+    // fit their buffer, and the padding goes after their total
+    if (stop && *stop) return;
+    if (!pad) pad = dst + off[n_children];
+    if (blockIdx.x == 0)  // the buffer's padding of 0xFF after the children
+        for (uint32_t i = threadIdx.x; i < pad_len; i += blockDim.x) pad[i] = 0xFF;
+    // block b copies piece b of its child
+    const uint64_t* pf = off + n_children + 4;
+    const uint64_t pb = blockIdx.x;
+    const uint32_t j = piece_child(pf, n_children, pb);
+    if (pb < pf[j]) return;
+    XoPlan x = plan[j];
+    x.child_off = off[j];
+    xo_copy_piece(mums, dads, x, pb - pf[j], dst);
+}
+
+// A batch of children to places of their own, for a population kept as a
+// heap of trees: child k of the batch is plan[idx[k]], written at
+// dst + at[k]; pf is the batch's prefix of 4 KiB copy pieces (n + 1
+// entries).  Both parents live in `src`.
+__global__ void k_xo_copy_at(const uint8_t* __restrict__ src, const XoPlan* __restrict__ plan,
+                             const uint32_t* __restrict__ idx, const uint64_t* __restrict__ at,
+                             const uint64_t* __restrict__ pf, uint32_t n, uint8_t* __restrict__ dst)
+{
+    const uint64_t pb = blockIdx.x;
+    const uint32_t k = piece_child(pf, n, pb);
+    if (pb < pf[k] || pb >= pf[n]) return;
+    XoPlan x = plan[idx[k]];
+    x.child_off = at[k];
+    xo_copy_piece(src, src, x, pb - pf[k], dst);
+}
+
 // Per child j: the two subtree queries, (tree start, point) in the mum's
 // and the dad's buffer, at j and n + j.
 __global__ void k_xo_query(const uint64_t* __restrict__ moff, const uint64_t* __restrict__ doff,
@@ -1770,12 +1801,14 @@ __global__ void k_xo_plan(const uint64_t* __restrict__ moff, const uint64_t* __r
                           const int32_t* __restrict__ mum, const int32_t* __restrict__ dad,
                           const uint64_t* __restrict__ p, const uint64_t* __restrict__ q,
                           const uint64_t* __restrict__ ends, uint32_t n, uint64_t cap, XoPlan* __restrict__ plan,
-                          uint64_t* __restrict__ len)
+                          uint64_t* __restrict__ len, const uint64_t* __restrict__ mlen)
 {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     XoPlan x;
-    const uint64_t m0 = moff[mum[j]], nm = moff[mum[j] + 1] - m0;
+    // the mum's start, and its length from the offsets or (a heap of trees)
+    // from mlen
+    const uint64_t m0 = moff[mum[j]], nm = mlen ? mlen[mum[j]] : moff[mum[j] + 1] - m0;
     x.mum_off = m0;
     x.dad_off = doff[dad[j]];
     x.p = p[j];
@@ -1898,7 +1931,8 @@ __device__ __forceinline__ uint64_t mulhi_u64(uint64_t u, uint64_t n) { return _
 
 __global__ void k_select(const float* __restrict__ fit, const uint64_t* __restrict__ off, uint32_t M, int32_t k,
                          uint64_t seed, uint64_t gen, int32_t* __restrict__ mum, int32_t* __restrict__ dad,
-                         uint64_t* __restrict__ p, uint64_t* __restrict__ q, const uint64_t* __restrict__ gen_at)
+                         uint64_t* __restrict__ p, uint64_t* __restrict__ q, const uint64_t* __restrict__ gen_at,
+                         const uint64_t* __restrict__ len)
 {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
@@ -1912,8 +1946,9 @@ __global__ void k_select(const float* __restrict__ fit, const uint64_t* __restri
     const uint64_t uq = ((uint64_t)w[3] << 32) | w[2];
     mum[j] = mm;
     dad[j] = dd;
-    p[j] = mulhi_u64(up, off[mm + 1] - off[mm]);
-    q[j] = mulhi_u64(uq, off[dd + 1] - off[dd]);
+    // sizes: from the offsets, or (a heap of trees) from the lengths
+    p[j] = mulhi_u64(up, len ? len[mm] : off[mm + 1] - off[mm]);
+    q[j] = mulhi_u64(uq, len ? len[dd] : off[dd + 1] - off[dd]);
 }
 
 }  // namespace ev
@@ -2778,6 +2813,15 @@ hipError_t launch_xo_copy(const uint8_t* mums, const uint8_t* dads, const XoPlan
     return hipGetLastError();
 }
 
+hipError_t launch_xo_copy_at(const uint8_t* src, const XoPlan* plan, const uint32_t* idx, const uint64_t* at,
+                            const uint64_t* pf, uint32_t n, uint64_t pieces, uint8_t* dst, hipStream_t s)
+{
+    if (n == 0 || pieces == 0) return hipSuccess;
+    if (pieces > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_xo_copy_at, dim3((uint32_t)pieces), dim3(256), 0, s, src, plan, idx, at, pf, n, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_xo_query(const uint64_t* moff, const uint64_t* doff, const int32_t* mum, const int32_t* dad,
                            const uint64_t* p, const uint64_t* q, uint32_t n, uint64_t* qb, uint64_t* qp, hipStream_t s)
 {
@@ -2788,10 +2832,11 @@ hipError_t launch_xo_query(const uint64_t* moff, const uint64_t* doff, const int
 
 hipError_t launch_xo_plan(const uint64_t* moff, const uint64_t* doff, const int32_t* mum, const int32_t* dad,
                           const uint64_t* p, const uint64_t* q, const uint64_t* ends, uint32_t n, uint64_t cap,
-                          XoPlan* plan, uint64_t* off, hipStream_t s)
+                          XoPlan* plan, uint64_t* off, hipStream_t s, const uint64_t* mlen)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_xo_plan, dim3(cdiv(n, 256)), dim3(256), 0, s, moff, doff, mum, dad, p, q, ends, n, cap, plan, off);
+    hipLaunchKernelGGL(k_xo_plan, dim3(cdiv(n, 256)), dim3(256), 0, s, moff, doff, mum, dad, p, q, ends, n, cap, plan, off,
+                       mlen);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_xo_offsets, dim3(1), dim3(1024), 0, s, off, n);
@@ -2799,10 +2844,12 @@ hipError_t launch_xo_plan(const uint64_t* moff, const uint64_t* doff, const int3
 }
 
 hipError_t launch_select(const float* fit, const uint64_t* off, uint32_t M, int32_t k, uint64_t seed, uint64_t gen,
-                         int32_t* mum, int32_t* dad, uint64_t* p, uint64_t* q, hipStream_t s, const uint64_t* gen_at)
+                         int32_t* mum, int32_t* dad, uint64_t* p, uint64_t* q, hipStream_t s, const uint64_t* gen_at,
+                         const uint64_t* len)
 {
     if (M == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_select, dim3(cdiv(M, 64)), dim3(64), 0, s, fit, off, M, k, seed, gen, mum, dad, p, q, gen_at);
+    hipLaunchKernelGGL(k_select, dim3(cdiv(M, 64)), dim3(64), 0, s, fit, off, M, k, seed, gen, mum, dad, p, q, gen_at,
+                       len);
     return hipGetLastError();
 }
 

@@ -92,10 +92,13 @@ hipError_t launch_xo_query(const uint64_t* moff, const uint64_t* doff, const int
                            const uint64_t* p, const uint64_t* q, uint32_t n, uint64_t* qb, uint64_t* qp, hipStream_t s);
 hipError_t launch_xo_plan(const uint64_t* moff, const uint64_t* doff, const int32_t* mum, const int32_t* dad,
                           const uint64_t* p, const uint64_t* q, const uint64_t* ends, uint32_t n, uint64_t cap,
-                          XoPlan* plan, uint64_t* off, hipStream_t s);
+                          XoPlan* plan, uint64_t* off, hipStream_t s, const uint64_t* mlen = nullptr);
+// a batch of children to places of their own (see k_xo_copy_at)
+hipError_t launch_xo_copy_at(const uint8_t* src, const XoPlan* plan, const uint32_t* idx, const uint64_t* at,
+                             const uint64_t* pf, uint32_t n, uint64_t pieces, uint8_t* dst, hipStream_t s);
 hipError_t launch_select(const float* fit, const uint64_t* off, uint32_t M, int32_t k, uint64_t seed, uint64_t gen,
                          int32_t* mum, int32_t* dad, uint64_t* p, uint64_t* q, hipStream_t s,
-                         const uint64_t* gen_at = nullptr);
+                         const uint64_t* gen_at = nullptr, const uint64_t* len = nullptr);
 // a generation replayed from a graph: the children's trees, each plan
 // level's first and last step, and the generation's verdict
 hipError_t launch_g_init(const uint64_t* off, uint32_t M, GTree* tr, uint64_t bytes_cap, uint32_t pad_len,

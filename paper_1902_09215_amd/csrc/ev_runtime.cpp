@@ -255,8 +255,7 @@ static constexpr uint64_t RECORD_MAX = (uint64_t)2 << 30;
 // With reuse, level 0 takes over the chunks of each child's mum that its
 // crossover left intact (their codes and skeleton fragments are copied) and
 // plans only the tokens between them.
-ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_check = false,
-                     const ReuseSpec* reuse = nullptr)
+ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_check, const ReuseSpec* reuse)
 {
     hipStream_t s = x.stream;
     const int32_t M = P->M;
@@ -286,7 +285,8 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
     ref_base.assign(M, 0);
     active.assign(M, 1);
     for (int32_t t = 0; t < M; t++) {
-        rs[t] = P->h_off[t];
+        // a heap of trees (h_start) keeps each tree anywhere in the buffer
+        rs[t] = P->h_start.empty() ? P->h_off[t] : P->h_start[t];
         rl[t] = P->h_off[t + 1] - P->h_off[t];
         if (rl[t] == 0) {
             if (bad_tree) *bad_tree = t;

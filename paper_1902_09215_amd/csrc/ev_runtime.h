@@ -98,6 +98,10 @@ struct Pop {
     uint8_t* d_bytes = nullptr;
     uint64_t* d_off = nullptr;
     std::vector<uint64_t> h_off;
+    // when not empty, tree t's bytes start at d_bytes + h_start[t] (a heap of
+    // trees, used only inside the memory-lean loop); h_off then holds the
+    // prefix sums of the lengths
+    std::vector<uint64_t> h_start;
     int32_t M = 0;
     uint64_t total = 0;
     Plan plan;
@@ -279,5 +283,12 @@ void serve_stop(ev_ctx* c);
 
 // Release a context's replayed-generation graphs and their buffers.
 void evolve_release(ev_ctx* c);
+// The memory-lean loop of ev_evolve (EV_EVOLVE_LEAN): arguments as there.
+ev_status evolve_lean(ev_ctx* c, Pop* P, const float* fitness, int32_t table, uint64_t seed, uint64_t gen0,
+                      int32_t n_gen, int32_t tournament, uint64_t size_cap, ev_pop* out, float* fit_history,
+                      int32_t* capped_history, ev_evolve_report* rep);
+// build a population's split plan (bad_tree: the first malformed tree)
+ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_check = false,
+                     const ReuseSpec* reuse = nullptr);
 
 }  // namespace ev

@@ -158,3 +158,26 @@ def test_evolve_capped_children_and_device_fitness(ev):
         assert fh0.shape == (0, 100) and rep0["generations"] == 0
         b0, o0 = ev.ev_get_trees(c.ctx, kids0)
         assert np.array_equal(o0, off) and np.array_equal(b0, buf)
+
+
+@pytest.mark.parametrize("m,k", [(200, 2), (500, 7)])
+def test_evolve_lean_heap(ev, m, k):
+    # the memory-lean loop: the population as a heap of trees, children made
+    # in batches by lower parent index and parents' bytes reused once their
+    # last child is made; every generation equals the oracle's, with fewer
+    # bytes alive than separate parent and child buffers would hold
+    x, y = workloads.cases(48)
+    buf, off = workloads.rhh_population(workloads.SEED_BASE + 9 + k, m, 2, 6)
+    seed, cap, gens = 31 + k, 15_000_000, 40
+    want = oracle_loop(buf, off, x, y, seed, 0, gens, k, cap)
+    with ev.Context(x, y) as c:
+        pop = c.load(buf, off)
+        c.eval(pop)
+        kids, fh, ch, rep = ev.ev_evolve(c.ctx, pop, seed, 0, gens, k, cap, flags=ev.EV_EVOLVE_LEAN)
+        print(f"report: {rep}", flush=True)
+        check_run(ev, c, kids, fh, ch, want, f"lean heap m={m} k={k}")
+        assert rep["generations"] == gens and rep["replayed"] == 0
+        assert 0 < rep["lean_peak_bytes"] < 0.85 * rep["lean_two_buffer_bytes"], rep
+        # the caller's population is untouched
+        b0, o0 = ev.ev_get_trees(c.ctx, pop)
+        assert np.array_equal(o0, off) and np.array_equal(b0, buf)
