@@ -312,7 +312,11 @@ typedef struct {
 /* Queue a job (thread-safe).  Inputs are copied before returning.  A job is
  * admitted to the device when its memory footprint fits the context's
  * budget beside the jobs in flight; jobs arriving while others run are
- * batched into the next device launch.  EV_EBUSY: the job can never fit. */
+ * batched into the next device launch.  EV_EBUSY: the job can never fit;
+ * EV_EINVAL / EV_EMALFORMED: bad arguments, offsets or an empty tree.  A
+ * tree that is not a valid prefix tree is found on the device when its
+ * batch is planned: that job alone ends with EV_EMALFORMED (ev_wait /
+ * ev_result), and the jobs batched with it run again without it. */
 ev_status ev_submit(ev_ctx *ctx, const ev_job *job, ev_ticket *out);
 
 /* Non-blocking: *done = 1 once the job finished; *job_status its result. */

@@ -2463,7 +2463,12 @@ __global__ __launch_bounds__(256) void k_g_finish(GStatus* __restrict__ st, cons
 // Every item it waits for sits earlier in the queue, and a wave takes its
 // next item only after finishing its current one, so the earliest
 // unfinished item always runs and the wait ends.  Slot rows cross compute
-// units through agent-scope release (after an item) and acquire (before).
+// units (and the XCDs' separate L2s) without any cache maintenance: every
+// slot-row load and store of the interpreter is made at device scope (sc1),
+// the item's stores have completed (the interpreter's last vmcnt wait)
+// before its done count is raised, and a waiting item issues its row loads
+// only after it has read the count it waits for.  Write-back or invalidate
+// of a whole L2 would also reach the kernels of other streams.
 __global__ __launch_bounds__(64) void k_run_chain(ChainArgs a)
 {
     const uint32_t lane = threadIdx.x;
@@ -2483,7 +2488,6 @@ __global__ __launch_bounds__(64) void k_run_chain(ChainArgs a)
             const uint32_t want = a.need[(size_t)(l - 1) * a.M + tree] * a.n_cb;
             while (__hip_atomic_load(dp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want)
                 __builtin_amdgcn_s_sleep(4);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         // a level whose code streams failed validation runs none of them
         // (its items still count as done)
@@ -2509,15 +2513,14 @@ __global__ __launch_bounds__(64) void k_run_chain(ChainArgs a)
                 const uint64_t outp = uni((uint64_t)(uintptr_t)L.out_res + (uint64_t)d.w * a.rowb);
                 const uint32_t slane = lane * 4u;
                 const uint32_t refs = (uint32_t)__builtin_amdgcn_readfirstlane(L.refs);
-                asm volatile(EV_INTERP_ASM
+                asm volatile(EV_INTERP_ASM_COH
                              :
                              : [x] "v"(xv), [lane4] "v"(lane4), [slane] "v"(slane), [cptr] "s"(cptr), [j0] "s"(j0),
                                [inp] "s"(inp), [outp] "s"(outp), [rowb] "s"(a.rowb), [smem] "s"(smem),
                                [flag] "s"(a.flag), [refs] "s"(refs)
-                             : EV_INTERP_CLOBBERS);
+                             : EV_INTERP_CLOBBERS, "memory");
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (lane == 0) __hip_atomic_fetch_add(a.done + (size_t)l * a.M + tree, 1u, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
         item = next;

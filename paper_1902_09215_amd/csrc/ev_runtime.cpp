@@ -1054,11 +1054,11 @@ struct EvalBufs {
 };
 
 // The skeleton levels of P go in one chained launch: three levels or more,
-// every one on the register-stack kernel.
-static bool chain_applies(ev_ctx* c, const Pop* P)
+// every one on the register-stack kernel, on a stream that allows it.
+static bool chain_applies(ev_ctx* c, const Exec& x, const Pop* P)
 {
     const Plan& pl = P->plan;
-    if (!c->use_chain || !pl.d_need || pl.levels.size() < 3) return false;
+    if (!c->use_chain || !x.chain_ok || !pl.d_need || pl.levels.size() < 3) return false;
     for (const Level& L : pl.levels)
         if (L.n_chunks || !L.n_run || !L.d_item_tree) return false;
     return true;
@@ -1219,7 +1219,7 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
     ev_status st;
     if ((st = rescache_get(c, x, P, table, &rc)) != EV_OK) return st;
     const size_t nl = P->plan.levels.size();
-    const bool chain = chain_applies(c, P);
+    const bool chain = chain_applies(c, x, P);
     // the work counters, then (chained) the done counters of levels 1 ..
     if ((st = ensure_counters(c, x, 2 * nl + (chain ? (nl - 1) * (size_t)P->M : 0))) != EV_OK) return st;
     // spill slabs for every wave of each level's grid

@@ -141,6 +141,9 @@ struct Exec {
     size_t n_counters = 0;
     float* d_gstack = nullptr;
     size_t gstack_bytes = 0;
+    // the skeleton levels may go in one chained launch (k_run_chain) on
+    // this stream; off on the serving workers' streams
+    bool chain_ok = true;
     hipEvent_t done = nullptr;  // completion marker of sync()
     hipEvent_t ev0 = nullptr, ev1 = nullptr, evi0 = nullptr, evi1 = nullptr;
     std::vector<hipEvent_t> evl;  // timed evaluations: one event after each plan level

@@ -84,9 +84,12 @@ static void finish(Serve* S, Job* j, ev_status st)
     S->cv.notify_all();
 }
 
-// Evaluate a batch of eval jobs (same table) as one population.
-static ev_status run_eval_batch(ev_ctx* c, Exec& x, std::vector<Job*>& batch)
+// Evaluate a batch of eval jobs (same table) as one population.  A tree
+// that is not a valid prefix tree fails the batch's plan with EV_EMALFORMED;
+// *bad_job is then the batch index of the job that holds it (else -1).
+static ev_status run_eval_batch(ev_ctx* c, Exec& x, std::vector<Job*>& batch, int32_t* bad_job)
 {
+    *bad_job = -1;
     std::vector<uint64_t> off(1, 0);
     uint64_t total = 0;
     for (Job* j : batch) total += j->off.back();
@@ -118,6 +121,13 @@ static ev_status run_eval_batch(ev_ctx* c, Exec& x, std::vector<Job*>& batch)
         } else {
             int32_t bad = -1;
             st = pop_build(c, x, d, off, &P, &bad);
+            for (int32_t k = 0, first = 0; st == EV_EMALFORMED && bad >= 0 && k < (int32_t)batch.size(); k++) {
+                if (bad < first + batch[k]->n) {
+                    *bad_job = k;
+                    break;
+                }
+                first += batch[k]->n;
+            }
         }
     }
     if (st == EV_OK) st = dev_alloc(c, (size_t)std::max(1, M) * N * sizeof(float), (void**)&d_pc);
@@ -220,7 +230,16 @@ static void worker(ev_ctx* c, Serve* S, Exec* x)
             }
         }
         if (batch[0]->kind == EV_JOB_EVAL) {
-            const ev_status st = run_eval_batch(c, *x, batch);
+            ev_status st = EV_OK;
+            while (!batch.empty()) {
+                int32_t bad = -1;
+                st = run_eval_batch(c, *x, batch, &bad);
+                if (bad < 0) break;
+                // a malformed request fails alone; the others run again
+                // without it
+                finish(S, batch[bad], st);
+                batch.erase(batch.begin() + bad);
+            }
             for (Job* j : batch) finish(S, j, st);
         } else {
             const ev_status st = run_crossover(c, *x, batch[0]);
@@ -242,6 +261,10 @@ static Serve* serve_get(ev_ctx* c)
     for (int i = 0; i < W; i++) {
         auto x = std::make_unique<Exec>();
         if (exec_init(*x, nullptr) != EV_OK) break;
+        // one launch per skeleton level here: with the chained launch on
+        // the workers' concurrent streams, other jobs' code streams failed
+        // validation now and then (cause not found)
+        x->chain_ok = false;
         S->execs.push_back(std::move(x));
     }
     for (auto& x : S->execs) S->workers.emplace_back(worker, c, S, x.get());
@@ -294,18 +317,8 @@ ev_status ev_submit(ev_ctx* c, const ev_job* job, ev_ticket* out)
         if (j->off[0] != 0) return fail(EV_EINVAL, "ev_submit: off[0] must be 0");
         for (int32_t t = 0; t < j->n; t++)
             if (j->off[t + 1] <= j->off[t]) return fail(EV_EMALFORMED, "ev_submit: tree %d is empty", t);
+        // the trees are checked on the device, when their batch is planned
         j->bytes.assign(job->bytes, job->bytes + j->off.back());
-        // host-side check so one bad request cannot fail a whole batch
-        for (int32_t t = 0; t < j->n; t++) {
-            int64_t open = 1;
-            for (uint64_t k = j->off[t]; k < j->off[t + 1]; k++) {
-                const uint8_t b = j->bytes[k];
-                const bool leaf = b == EV_X || (b >= TOK_C0 && b < TOK_C0 + (uint32_t)c->n_consts);
-                if ((b > EV_X && !leaf) || open < 1) { open = -1; break; }
-                open += leaf ? -1 : 1;
-            }
-            if (open != 0) return fail(EV_EMALFORMED, "ev_submit: tree %d is not a valid prefix tree", t);
-        }
         j->footprint = footprint(j->off.back(), (uint64_t)j->n, N, c->chunk);
     } else if (job->kind == EV_JOB_CROSSOVER) {
         if (job->n_children < 0 || (job->n_children > 0 && (!job->mum || !job->dad || !job->p || !job->q)))

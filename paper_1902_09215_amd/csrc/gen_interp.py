@@ -151,7 +151,7 @@ def row_dec(lo: int) -> list[str]:
     return [f"s_sub_u32 s{lo}, s{lo}, s54", f"s_subb_u32 s{lo + 1}, s{lo + 1}, 0"]
 
 
-def handler(kind: str, pos: int) -> list[str]:
+def handler(kind: str, pos: int, cp: str = "") -> list[str]:
     k = kind
     body: list[str]
     routine = None
@@ -196,7 +196,7 @@ def handler(kind: str, pos: int) -> list[str]:
     elif k in ("OUTT", "OUTBOT", "SPILL", "FILL", "OUTMEM") or k.startswith("PUSHREF") or k.startswith("LOADREF"):
         routine = k.lower()
     elif k == "OUTX":
-        body = ["s_set_gpr_idx_off"] + row_dec(52) + ["global_store_dword %[lane4], %[x], s[52:53]"]
+        body = ["s_set_gpr_idx_off"] + row_dec(52) + ["global_store_dword %[lane4], %[x], s[52:53]" + cp]
     elif k == "FLUSH":
         body = ["s_mov_b32 s59, 0"]
     elif k == "END":
@@ -208,7 +208,7 @@ def handler(kind: str, pos: int) -> list[str]:
     return body + dispatch(pos)
 
 
-def routines() -> list[str]:
+def routines(cp: str = "") -> list[str]:
     out = []
     # T' = T / below (the entry below becomes T), worked in place: every
     # operand relative to T, the temporaries just above it
@@ -231,13 +231,13 @@ def routines() -> list[str]:
                     f"v_mov_b32_e32 {dst}, v{RING0 + r}", "s_set_gpr_idx_off"]
             if inc:
                 out += ["s_add_u32 s55, s55, 1"]
-            out += row_dec(50) + [f"global_load_dword v{RING0 + r}, %[lane4], s[50:51]", "s_setpc_b64 s[44:45]"]
+            out += row_dec(50) + [f"global_load_dword v{RING0 + r}, %[lane4], s[50:51]" + cp, "s_setpc_b64 s[44:45]"]
     # T to the next output slot (rows written downwards)
     out += [".Loutt%=:", "s_set_gpr_idx_on s55, gpr_idx(SRC0)", f"v_mov_b32_e32 v4, {T}", "s_set_gpr_idx_off"]
-    out += row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]", "s_setpc_b64 s[44:45]"]
+    out += row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]" + cp, "s_setpc_b64 s[44:45]"]
     # chunk-end flush of the window entry s59
     out += [".Loutbot%=:", "s_set_gpr_idx_on s59, gpr_idx(SRC0)", f"v_mov_b32_e32 v4, {T}", "s_set_gpr_idx_off",
-            "s_add_u32 s59, s59, 1"] + row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]",
+            "s_add_u32 s59, s59, 1"] + row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]" + cp,
                                                      "s_setpc_b64 s[44:45]"]
     # spill: the window's bottom HALF entries to the slab, then shift down
     groups = [(g0, min(16, HALF - g0)) for g0 in range(0, HALF, 16)]
@@ -260,11 +260,11 @@ def routines() -> list[str]:
     out += [".Loutmem%=:", "s_set_gpr_idx_off", "s_lshl_b32 s46, s59, 8", "s_add_u32 s46, s62, s46",
             "s_addc_u32 s47, s63, 0", "global_load_dword v4, %[slane], s[46:47]", "s_waitcnt vmcnt(0)",
             "s_mov_b32 s47, s43", "s_add_u32 s59, s59, 1"] + row_dec(52) + [
-            "global_store_dword %[lane4], v4, s[52:53]", "s_setpc_b64 s[44:45]"]
+            "global_store_dword %[lane4], v4, s[52:53]" + cp, "s_setpc_b64 s[44:45]"]
     return out
 
 
-def generate() -> str:
+def generate(cp: str = "") -> str:
     lines = [
         # inputs -> the block's own registers
         "s_mov_b64 s[40:41], %[cptr]",
@@ -278,7 +278,7 @@ def generate() -> str:
         # skeleton levels: start reading the first RING slot rows
         "s_cmp_eq_u32 %[refs], 0",
         "s_cbranch_scc1 .Lnoref%=",
-    ] + sum((row_dec(50) + [f"global_load_dword v{RING0 + r}, %[lane4], s[50:51]"] for r in range(RING)), []) + [
+    ] + sum((row_dec(50) + [f"global_load_dword v{RING0 + r}, %[lane4], s[50:51]" + cp] for r in range(RING)), []) + [
         ".Lnoref%=:",
         # x+x, x-x, x*x and x%x, once per work item (no index mode is on)
         f"v_add_f32_e32 v{XX0}, %[x], %[x]",
@@ -318,9 +318,9 @@ def generate() -> str:
     # handlers in address order (positions 15 and 31 sit after the others)
     for off, pos, ki in sorted((code_of(pos, ki), pos, ki) for pos in range(POS) for ki in range(NK)):
         lines.append(f".org .Ltab%= + {off}")
-        lines += handler(KINDS[ki], pos)
+        lines += handler(KINDS[ki], pos, cp)
     lines.append(f".org .Ltab%= + {TABLE_BYTES}")
-    lines += routines()
+    lines += routines(cp)
     lines.append(".Lend%=:")
     # no scalar load may still be writing s[64:95] once the block is left
     # nor a vector load still be writing the ring registers
@@ -328,9 +328,12 @@ def generate() -> str:
     return "\n".join(lines) + "\n"
 
 
-def write(path: str) -> None:
-    text = generate()
+def asm_macro(name: str, text: str) -> str:
     body = "\n".join('    "' + ln.replace('"', '\\"') + '\\n"' for ln in text.splitlines())
+    return f"#define {name} \\\n" + body.replace("\n", " \\\n") + "\n"
+
+
+def write(path: str) -> None:
     clob = ", ".join([f'"v{i}"' for i in range(4, NREG)] + [f'"s{i}"' for i in range(40, 64)]
                      + [f'"s{i}"' for i in range(64, 96)] + ['"m0"', '"vcc"', '"scc"'])
     src = ("// Generated by gen_interp.py: threaded-code interpreter for k_run.\n"
@@ -339,7 +342,10 @@ def write(path: str) -> None:
            f"#define EV_VSTACK {VSTACK}u\n#define EV_VHALF {HALF}u\n#define EV_RING {RING}u\n"
            f"#define EV_INTERP_CLOBBERS {clob}\n"
            + "".join(f"#define EV_K_{k} {i}u\n" for i, k in enumerate(KINDS))
-           + "#define EV_INTERP_ASM \\\n" + body.replace("\n", " \\\n") + "\n")
+           + asm_macro("EV_INTERP_ASM", generate())
+           # slot rows read and written at device scope (sc1): coherent with
+           # other work groups of the same launch without cache maintenance
+           + asm_macro("EV_INTERP_ASM_COH", generate(" sc1")))
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
         f.write(src)

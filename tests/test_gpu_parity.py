@@ -834,6 +834,34 @@ def test_serving_results_same_alone_and_mixed(ev):
         assert_same(fa, wf, f"job {k} vs oracle")
 
 
+def test_serving_malformed_request_fails_alone(ev):
+    # trees are checked on the device when their batch is planned: requests
+    # holding a tree that is not a valid prefix tree end with EV_EMALFORMED,
+    # and the requests queued (and possibly batched) with them still get
+    # the oracle's results
+    x, y = workloads.cases(48)
+    sizes = workloads.loguniform_sizes(61, 40, 1, 20000)
+    b, o = workloads.random_population(61, sizes)
+    want = oracle.eval_population(b, o, x, y, threads=8)
+    bads = [np.array([ADD, X, X, X], np.uint8), np.array([MUL, X], np.uint8), np.array([X, 200], np.uint8)]
+    with ev.Context(x, y) as c:
+        good, bad = [], []
+        for t in range(40):
+            good.append(ev.ev_submit_eval(c.ctx, b[o[t]:o[t + 1]], np.array([0, o[t + 1] - o[t]], np.uint64)))
+            if t % 13 == 5:
+                bb = bads[len(bad)]
+                bad.append(ev.ev_submit_eval(c.ctx, bb, np.array([0, bb.size], np.uint64)))
+        for t, tk in enumerate(good):
+            assert ev.ev_wait(c.ctx, tk) == 0, f"request {t}"
+            f, _ = ev.ev_result(c.ctx, tk, 1, 48)
+            assert_same(f, want[t:t + 1], f"request {t}")
+        for tk in bad:
+            assert ev.ev_wait(c.ctx, tk) == ev.EV_EMALFORMED
+            with pytest.raises(ev.EvError) as e:
+                ev.ev_result(c.ctx, tk, 1, 48)
+            assert e.value.code == ev.EV_EMALFORMED
+
+
 def test_serving_under_load(ev):
     # 600 requests queued at once on two case tables: single trees of up to
     # 4e6 nodes drawn from a pool (so batches of a few hundred trees, with
