@@ -28,8 +28,14 @@ its slot is an assembler error, never a wrong jump.
 
 Register use inside the block (W0 = 7):
   v[W0 + m]       top of the operand stack (T); v[W0..W0+m-1] the entries
-                  below it, oldest first.  m = s55.  Relative access uses
-                  GPR-index mode (s_set_gpr_idx_on), set once per handler.
+                  below it, oldest first.  m = M0[7:0].  Relative access
+                  uses GPR-index mode with SRC0, SRC1 and DST relative,
+                  switched on once per work item: a handler changes M0 only
+                  when the depth changes, and writes a value from a fixed
+                  register (x, x+x, a ring value) into the stack with
+                  v_bfi_b32 d, 0, 0, src, whose third source stays absolute.
+                  Division switches SRC2 on for its fused operations and
+                  back; memory instructions run with the mode off.
   v[W0+VSTACK ..] HEAD registers above the window: a division works in
                   place, its temporaries just above T (relative, like the
                   stack), so it moves no operand in or out
@@ -42,9 +48,10 @@ Register use inside the block (W0 = 7):
   s[40:41] code block pointer (128-byte aligned), s[42:43] handler table,
   s[44:45] jump target (the next handler), s[46:47] routine target,
   s[50:51] read-ahead pointer into the input slot rows, s[52:53] output-slot row pointer,
-  s54 row bytes (cases * 4), s55 window index of T, s[56:57] division
-  scratch, s58 scratch, s59 flush index, s[60:61] next free entry of the
-  wave's spill slab in global memory, s[62:63] the slab's base.
+  s54 row bytes (cases * 4), M0 window index of T (and the mode bits),
+  s[56:57] division scratch, s58 scratch, s59 flush index, s[60:61] next
+  free entry of the wave's spill slab in global memory, s[62:63] the slab's
+  base.
 
 When the structure machine sees the stack outgrow the window it emits SPILL
 (store the bottom half of the window to the slab, shift the window down);
@@ -119,7 +126,14 @@ def div_body(a: int, b: int, t: int, r: int) -> list[str]:
 
 
 FULL = "gpr_idx(SRC0,SRC1,SRC2,DST)"
+MODE = "gpr_idx(SRC0,SRC1,DST)"  # the handlers' mode: SRC2 absolute
 T, BELOW, ABOVE, ABOVE2 = f"v{W0}", f"v{W0 - 1}", f"v{W0 + 1}", f"v{W0 + 2}"
+MODE_ON = f"s_set_gpr_idx_on m0, {MODE}"  # back to the handlers' mode (index unchanged)
+
+
+def put(dst: str, src: str) -> str:
+    """dst (relative) = src (a fixed register), bit for bit."""
+    return f"v_bfi_b32 {dst}, 0, 0, {src}"
 
 
 def next_target(pos: int) -> list[str]:
@@ -157,46 +171,42 @@ def handler(kind: str, pos: int, cp: str = "") -> list[str]:
     routine = None
     if k in ("OPS0", "OPS1", "OPS2"):
         # T' = op(T, below): the entry below becomes T
-        body = ["s_set_gpr_idx_on s55, gpr_idx(SRC0,SRC1,DST)", f"{VOP[int(k[3])]} {BELOW}, {T}, {BELOW}",
-                "s_sub_u32 s55, s55, 1"]
+        body = [f"{VOP[int(k[3])]} {BELOW}, {T}, {BELOW}", "s_sub_u32 m0, m0, 1"]
     elif k == "OPS3":
         routine = "divops"
     elif len(k) == 5 and k.startswith("OPS"):
         # two pops in a row: the second works one entry lower
         a, b = int(k[3]), int(k[4])
-        body = ["s_set_gpr_idx_on s55, gpr_idx(SRC0,SRC1,DST)", f"{VOP[a]} {BELOW}, {T}, {BELOW}",
-                f"{VOP[b]} v{W0 - 2}, {BELOW}, v{W0 - 2}", "s_sub_u32 s55, s55, 2"]
+        body = [f"{VOP[a]} {BELOW}, {T}, {BELOW}", f"{VOP[b]} v{W0 - 2}, {BELOW}, v{W0 - 2}", "s_sub_u32 m0, m0, 2"]
     elif k.startswith("OPX"):
         op = int(k[3])
-        # T = op(x, T)
+        # T = op(x, T): x goes just above T first
         if op == 3:
             routine = "divopx"
         else:
-            body = ["s_set_gpr_idx_on s55, gpr_idx(SRC1,DST)", f"{VOP[op]} {T}, %[x], {T}"]
+            body = [put(ABOVE, "%[x]"), f"{VOP[op]} {T}, {ABOVE}, {T}"]
     elif k.startswith("CH"):
         op = int(k[2])
         # push T; T = op(x, x), made once per work item
-        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {ABOVE}, v{XX0 + op}", "s_add_u32 s55, s55, 1"]
+        body = [put(ABOVE, f"v{XX0 + op}"), "s_add_u32 m0, m0, 1"]
     elif k.startswith("LCH"):
         op = int(k[3])
         # T = op(x, x) with no value below
-        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {T}, v{XX0 + op}"]
+        body = [put(T, f"v{XX0 + op}")]
     elif k == "PUSHX":
-        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {ABOVE}, %[x]", "s_add_u32 s55, s55, 1"]
+        body = [put(ABOVE, "%[x]"), "s_add_u32 m0, m0, 1"]
     elif k == "PUSH2X":
-        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {ABOVE}, %[x]", f"v_mov_b32_e32 {ABOVE2}, %[x]",
-                "s_add_u32 s55, s55, 2"]
+        body = [put(ABOVE, "%[x]"), put(ABOVE2, "%[x]"), "s_add_u32 m0, m0, 2"]
     elif k.startswith("PXCH"):
         op = int(k[4])
         # two pushes of x, then a function of x: push x; push op(x, x)
-        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {ABOVE}, %[x]",
-                f"v_mov_b32_e32 {ABOVE2}, v{XX0 + op}", "s_add_u32 s55, s55, 2"]
+        body = [put(ABOVE, "%[x]"), put(ABOVE2, f"v{XX0 + op}"), "s_add_u32 m0, m0, 2"]
     elif k == "LOADX":
-        body = ["s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {T}, %[x]"]
+        body = [put(T, "%[x]")]
     elif k in ("OUTT", "OUTBOT", "SPILL", "FILL", "OUTMEM") or k.startswith("PUSHREF") or k.startswith("LOADREF"):
         routine = k.lower()
     elif k == "OUTX":
-        body = ["s_set_gpr_idx_off"] + row_dec(52) + ["global_store_dword %[lane4], %[x], s[52:53]" + cp]
+        body = ["s_set_gpr_idx_off"] + row_dec(52) + ["global_store_dword %[lane4], %[x], s[52:53]" + cp, MODE_ON]
     elif k == "FLUSH":
         body = ["s_mov_b32 s59, 0"]
     elif k == "END":
@@ -212,14 +222,13 @@ def routines(cp: str = "") -> list[str]:
     out = []
     # T' = T / below (the entry below becomes T), worked in place: every
     # operand relative to T, the temporaries just above it
-    out += [".Ldivops%=:", f"s_set_gpr_idx_on s55, {FULL}"]
+    out += [".Ldivops%=:", f"s_set_gpr_idx_on m0, {FULL}"]
     out += div_body(W0, W0 - 1, W0 + 1, W0 - 1)
-    out += ["s_sub_u32 s55, s55, 1", "s_setpc_b64 s[44:45]"]
+    out += ["s_sub_u32 m0, m0, 1", MODE_ON, "s_setpc_b64 s[44:45]"]
     # T = x / T: x copied just above T first
-    out += [".Ldivopx%=:", "s_set_gpr_idx_on s55, gpr_idx(DST)", f"v_mov_b32_e32 {ABOVE}, %[x]",
-            f"s_set_gpr_idx_mode {FULL}"]
+    out += [".Ldivopx%=:", put(ABOVE, "%[x]"), f"s_set_gpr_idx_on m0, {FULL}"]
     out += div_body(W0 + 1, W0, W0 + 2, W0)
-    out += ["s_setpc_b64 s[44:45]"]
+    out += [MODE_ON, "s_setpc_b64 s[44:45]"]
     # a value from the previous level's slots (rows read downwards): REF j of
     # a work item takes ring register j % RING, loaded RING REFs earlier, and
     # starts the load of the row REF j + RING will take.  Vector memory
@@ -227,18 +236,19 @@ def routines(cp: str = "") -> list[str]:
     # still be outstanding when REF j's row has arrived.
     for r in range(RING):
         for name, dst, inc in ((f"pushref{r}", ABOVE, True), (f"loadref{r}", T, False)):
-            out += [f".L{name}%=:", f"s_waitcnt vmcnt({RING - 1})", "s_set_gpr_idx_on s55, gpr_idx(DST)",
-                    f"v_mov_b32_e32 {dst}, v{RING0 + r}", "s_set_gpr_idx_off"]
+            out += [f".L{name}%=:", f"s_waitcnt vmcnt({RING - 1})", put(dst, f"v{RING0 + r}")]
             if inc:
-                out += ["s_add_u32 s55, s55, 1"]
-            out += row_dec(50) + [f"global_load_dword v{RING0 + r}, %[lane4], s[50:51]" + cp, "s_setpc_b64 s[44:45]"]
+                out += ["s_add_u32 m0, m0, 1"]
+            out += ["s_set_gpr_idx_off"] + row_dec(50) + [
+                f"global_load_dword v{RING0 + r}, %[lane4], s[50:51]" + cp, MODE_ON, "s_setpc_b64 s[44:45]"]
     # T to the next output slot (rows written downwards)
-    out += [".Loutt%=:", "s_set_gpr_idx_on s55, gpr_idx(SRC0)", f"v_mov_b32_e32 v4, {T}", "s_set_gpr_idx_off"]
-    out += row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]" + cp, "s_setpc_b64 s[44:45]"]
-    # chunk-end flush of the window entry s59
-    out += [".Loutbot%=:", "s_set_gpr_idx_on s59, gpr_idx(SRC0)", f"v_mov_b32_e32 v4, {T}", "s_set_gpr_idx_off",
-            "s_add_u32 s59, s59, 1"] + row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]" + cp,
-                                                     "s_setpc_b64 s[44:45]"]
+    out += [".Loutt%=:", "s_set_gpr_idx_on m0, gpr_idx(SRC0)", f"v_mov_b32_e32 v4, {T}", "s_set_gpr_idx_off"]
+    out += row_dec(52) + ["global_store_dword %[lane4], v4, s[52:53]" + cp, MODE_ON, "s_setpc_b64 s[44:45]"]
+    # chunk-end flush of the window entry s59 (the index of T is kept in s58)
+    out += [".Loutbot%=:", "s_mov_b32 s58, m0", "s_set_gpr_idx_on s59, gpr_idx(SRC0)", f"v_mov_b32_e32 v4, {T}",
+            "s_set_gpr_idx_off", "s_add_u32 s59, s59, 1"] + row_dec(52) + [
+            "global_store_dword %[lane4], v4, s[52:53]" + cp, f"s_set_gpr_idx_on s58, {MODE}",
+            "s_setpc_b64 s[44:45]"]
     # spill: the window's bottom HALF entries to the slab, then shift down
     groups = [(g0, min(16, HALF - g0)) for g0 in range(0, HALF, 16)]
     out += [".Lspill%=:", "s_set_gpr_idx_off"]
@@ -247,7 +257,7 @@ def routines(cp: str = "") -> list[str]:
                 for i in range(n)]
         out += [f"s_add_u32 s60, s60, {256 * n}", "s_addc_u32 s61, s61, 0"]
     out += [f"v_mov_b32_e32 v{W0 + i}, v{W0 + HALF + i}" for i in range(VSTACK - HALF)]
-    out += [f"s_sub_u32 s55, s55, {HALF}", "s_setpc_b64 s[44:45]"]
+    out += [f"s_sub_u32 m0, m0, {HALF}", MODE_ON, "s_setpc_b64 s[44:45]"]
     # fill: shift up, then the top HALF entries of the slab into the bottom
     out += [".Lfill%=:", "s_set_gpr_idx_off"]
     out += [f"v_mov_b32_e32 v{W0 + HALF + i}, v{W0 + i}" for i in range(VSTACK - HALF)]
@@ -255,12 +265,12 @@ def routines(cp: str = "") -> list[str]:
         out += [f"s_sub_u32 s60, s60, {256 * n}", "s_subb_u32 s61, s61, 0"]
         out += [f"global_load_dword v{W0 + g0 + i}, %[slane], s[60:61]" + (f" offset:{256 * i}" if i else "")
                 for i in range(n)]
-    out += ["s_waitcnt vmcnt(0)", f"s_add_u32 s55, s55, {HALF}", "s_setpc_b64 s[44:45]"]
+    out += ["s_waitcnt vmcnt(0)", f"s_add_u32 m0, m0, {HALF}", MODE_ON, "s_setpc_b64 s[44:45]"]
     # chunk-end flush of an entry that lives in the slab (entry s59)
     out += [".Loutmem%=:", "s_set_gpr_idx_off", "s_lshl_b32 s46, s59, 8", "s_add_u32 s46, s62, s46",
             "s_addc_u32 s47, s63, 0", "global_load_dword v4, %[slane], s[46:47]", "s_waitcnt vmcnt(0)",
             "s_mov_b32 s47, s43", "s_add_u32 s59, s59, 1"] + row_dec(52) + [
-            "global_store_dword %[lane4], v4, s[52:53]" + cp, "s_setpc_b64 s[44:45]"]
+            "global_store_dword %[lane4], v4, s[52:53]" + cp, MODE_ON, "s_setpc_b64 s[44:45]"]
     return out
 
 
@@ -304,6 +314,8 @@ def generate(cp: str = "") -> str:
         "s_mov_b32 m0, s59",
         "s_nop 0",
         "s_movrels_b32 s58, s64",
+        # the handlers' index mode, on until END: T at window place 0
+        f"s_set_gpr_idx_on s55, {MODE}",
         "s_add_u32 s44, s42, s58",
         "s_setpc_b64 s[44:45]",
         ".Lcarry%=:",
