@@ -12,14 +12,19 @@
 // launches the graph and, after it, reads a status word, the levels' counts
 // and the children's fitness from pinned memory.
 //
-// Two graphs are captured, parents in buffer A and children in B, and the
-// reverse; they alternate.  A generation whose counts exceed a capacity
-// voids itself (every later step of it does nothing) and is done again on
-// the host-driven path, whose results are the same bit for bit; the
-// capacities are then re-derived from that generation's plan and the
-// graphs captured again.  Counts nearing a capacity trigger the same
-// re-capture after a good generation, so that growing trees (Sec. 4's
-// bloat) rarely reach the fallback.
+// The population rotates through three buffers, and one graph is captured
+// per buffer (parents there, children in the next).  Replays are pipelined:
+// generation i + 1 is launched before the host reads generation i's status,
+// so the host's checks and the next launch overlap the device's work.  The
+// third buffer keeps generation i's parents intact while i + 1 runs, so a
+// voided generation can still be redone.  A generation whose counts exceed
+// a capacity voids itself (every later step of it does nothing) and is done
+// again on the host-driven path, whose results are the same bit for bit;
+// the generation launched after it is discarded, the capacities are
+// re-derived from the redone generation's plan and the graphs captured
+// again.  Counts nearing a capacity trigger the same re-capture after a
+// good generation, so that growing trees (Sec. 4's bloat) rarely reach the
+// fallback.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,6 +41,8 @@ struct LevelSize {
 };
 
 static constexpr uint32_t G_N_ERR = 2 * (EV_MAX_LEVELS + 1);
+static constexpr int NB = 3;  // population buffers (and graphs) in the rotation
+static int nxt(int a) { return a + 1 < NB ? a + 1 : 0; }
 static constexpr uint64_t G_RECORD_MAX = (uint64_t)2 << 30;
 
 struct GenGraph {
@@ -48,12 +55,12 @@ struct GenGraph {
     float* d_x = nullptr;
     const float* d_y = nullptr;
 
-    // the population's two buffers (bytes with their padding, offsets in
-    // the crossover layout, fitness)
+    // the population's buffers (bytes with their padding, offsets in the
+    // crossover layout, fitness)
     uint64_t bytes_cap = 0, pieces_cap = 0;
-    uint8_t* bytes[2] = {nullptr, nullptr};
-    uint64_t* off[2] = {nullptr, nullptr};
-    float* fit[2] = {nullptr, nullptr};
+    uint8_t* bytes[NB] = {};
+    uint64_t* off[NB] = {};
+    float* fit[NB] = {};
     int cur = 0;  // the buffer holding the current parents
 
     // per-generation scratch: selection and crossover
@@ -97,19 +104,21 @@ struct GenGraph {
     float* slab = nullptr;
     uint32_t grid = 0;
 
-    // pinned host: the status, the levels' counts and the children's fitness
-    uint8_t* pin = nullptr;
-    GStatus* h_st = nullptr;
-    GLevel* h_lv = nullptr;
-    float* h_fit = nullptr;
+    // pinned host, per graph: the status, the levels' counts and the
+    // children's fitness of its last replay
+    uint8_t* pin[NB] = {};
+    GStatus* h_st[NB] = {};
+    GLevel* h_lv[NB] = {};
+    float* h_fit[NB] = {};
+    hipEvent_t done[NB] = {};  // the end of each graph's last replay
 
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipGraph_t graph[NB] = {};
+    hipGraphExec_t exec[NB] = {};
 };
 
 static void graphs_drop(GenGraph& g)
 {
-    for (int i = 0; i < 2; i++) {
+    for (int i = 0; i < NB; i++) {
         if (g.exec[i]) (void)hipGraphExecDestroy(g.exec[i]);
         if (g.graph[i]) (void)hipGraphDestroy(g.graph[i]);
         g.exec[i] = nullptr;
@@ -130,7 +139,7 @@ static void plan_blocks_free(ev_ctx* c, GenGraph& g)
 
 static void pop_blocks_free(ev_ctx* c, GenGraph& g)
 {
-    for (int i = 0; i < 2; i++) {
+    for (int i = 0; i < NB; i++) {
         dev_free(c, g.bytes[i]);
         dev_free(c, g.off[i]);
         dev_free(c, g.fit[i]);
@@ -157,7 +166,10 @@ static void gengraph_free(ev_ctx* c, GenGraph* g)
     plan_blocks_free(c, *g);
     pop_blocks_free(c, *g);
     xo_blocks_free(c, *g);
-    if (g->pin) (void)hipHostFree(g->pin);
+    for (int i = 0; i < NB; i++) {
+        if (g->pin[i]) (void)hipHostFree(g->pin[i]);
+        if (g->done[i]) (void)hipEventDestroy(g->done[i]);
+    }
     delete g;
 }
 
@@ -350,7 +362,7 @@ static ev_status plan_blocks_make(ev_ctx* c, GenGraph& g, const std::vector<Leve
     return put(c->main, g.d_caps, dc.data(), dc.size() * sizeof(GCap));
 }
 
-// The population's two buffers for bytes_cap bytes each (with padding),
+// The population's buffers for bytes_cap bytes each (with padding),
 // the current population (buffer `keep` of the old ones, `total` bytes)
 // copied over.  The caller has dropped the graphs (they name the old ones).
 static ev_status pop_blocks_make(ev_ctx* c, GenGraph& g, uint64_t bytes_cap, int keep, uint64_t total)
@@ -358,7 +370,7 @@ static ev_status pop_blocks_make(ev_ctx* c, GenGraph& g, uint64_t bytes_cap, int
     const size_t M = (size_t)std::max(1, g.M);
     GenGraph n;
     ev_status st = EV_OK;
-    for (int i = 0; i < 2 && st == EV_OK; i++) {
+    for (int i = 0; i < NB && st == EV_OK; i++) {
         if ((st = dev_alloc(c, bytes_cap, (void**)&n.bytes[i])) == EV_OK &&
             (st = dev_alloc(c, (2 * M + 6) * 8, (void**)&n.off[i])) == EV_OK)
             st = dev_alloc(c, M * 4, (void**)&n.fit[i]);
@@ -374,7 +386,7 @@ static ev_status pop_blocks_make(ev_ctx* c, GenGraph& g, uint64_t bytes_cap, int
         HIPCHK(hipMemcpyAsync(n.fit[keep], g.fit[keep], M * 4, hipMemcpyDeviceToDevice, s));
     }
     pop_blocks_free(c, g);  // reused by later work on this stream only, after the copies
-    for (int i = 0; i < 2; i++) {
+    for (int i = 0; i < NB; i++) {
         g.bytes[i] = n.bytes[i];
         g.off[i] = n.off[i];
         g.fit[i] = n.fit[i];
@@ -406,10 +418,10 @@ static ev_status xo_blocks_make(ev_ctx* c, GenGraph& g)
     return st;
 }
 
-// Queue one generation, parents in buffer a and children in 1 - a.
+// Queue one generation, parents in buffer a and children in the next.
 static hipError_t enqueue_generation(ev_ctx* c, GenGraph& g, int a, hipStream_t s)
 {
-    const int b = 1 - a;
+    const int b = nxt(a);
     const uint32_t M = (uint32_t)g.M;
     const uint32_t n_cb = (uint32_t)((g.N + 63) / 64);
     hipError_t e = hipSuccess;
@@ -490,7 +502,7 @@ static hipError_t enqueue_generation(ev_ctx* c, GenGraph& g, int a, hipStream_t 
     fa.fit = g.fit[b];
     fa.gl = g.gls;
     E(launch_fitness(fa, s));
-    E(launch_g_finish(g.st, g.gls, g.L, g.err, g.fit[b], M, g.gen_at, g.h_st, g.h_lv, g.h_fit, s));
+    E(launch_g_finish(g.st, g.gls, g.L, g.err, g.fit[b], M, g.gen_at, g.h_st[a], g.h_lv[a], g.h_fit[a], s));
     return e;
 }
 
@@ -520,15 +532,16 @@ static ev_status capture(ev_ctx* c, GenGraph& g, int a)
     return EV_OK;
 }
 
-// One generation on the host-driven path from buffer a into 1 - a (the
+// One generation on the host-driven path from buffer a into the next (the
 // same kernels and draws as the graph's): its children's plan sizes and
-// capped count.  The population buffers grow when the children need it.
+// capped count, their fitness in h_fit[a].  The population buffers grow
+// when the children need it.
 static ev_status host_generation(ev_ctx* c, GenGraph& g, int a, uint64_t gen, std::vector<LevelSize>* seen,
                                  int32_t* capped, uint64_t* nodes)
 {
     Exec& x = c->main;
     hipStream_t s = c->stream;
-    const int b = 1 - a;
+    const int b = nxt(a);
     const int32_t M = g.M;
     std::vector<uint64_t> h_off((size_t)M + 1);
     ev_status st = get(x, h_off.data(), g.off[a], h_off.size() * 8);
@@ -546,7 +559,7 @@ static ev_status host_generation(ev_ctx* c, GenGraph& g, int a, uint64_t gen, st
     st = crossover_build_dev(c, x, &view, &view, g.mum, g.dad, g.p, g.q, M, g.cap, &kids, capped, false);
     if (st != EV_OK) return st;
     if ((st = eval_enqueue(c, x, kids, g.table, kids->d_fit, nullptr, false, nullptr)) != EV_OK ||
-        (st = get(x, g.h_fit, kids->d_fit, (size_t)M * 4)) != EV_OK || (st = sync(x)) != EV_OK) {
+        (st = get(x, g.h_fit[a], kids->d_fit, (size_t)M * 4)) != EV_OK || (st = sync(x)) != EV_OK) {
         pop_free(c, kids);
         return st;
     }
@@ -735,15 +748,18 @@ extern "C" ev_status ev_evolve(ev_ctx* c, ev_pop parents, const float* fitness, 
         g->d_x = ct.d_x;
         g->d_y = ct.d_y;
         const size_t pin_bytes = 256 + EV_MAX_LEVELS * sizeof(GLevel) + (size_t)M * 4;
-        const hipError_t e = hipHostMalloc((void**)&g->pin, pin_bytes, hipHostMallocCoherent);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            delete g;
-            return fail(EV_ENOMEM, "hipHostMalloc(%zu): %s", pin_bytes, hipGetErrorString(e));
+        for (int i = 0; i < NB; i++) {
+            hipError_t e = hipHostMalloc((void**)&g->pin[i], pin_bytes, hipHostMallocCoherent);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&g->done[i], hipEventDisableTiming);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                gengraph_free(c, g);
+                return fail(EV_ENOMEM, "ev_evolve: pinned status or event: %s", hipGetErrorString(e));
+            }
+            g->h_st[i] = (GStatus*)g->pin[i];
+            g->h_lv[i] = (GLevel*)(g->pin[i] + 256);
+            g->h_fit[i] = (float*)(g->pin[i] + 256 + EV_MAX_LEVELS * sizeof(GLevel));
         }
-        g->h_st = (GStatus*)g->pin;
-        g->h_lv = (GLevel*)(g->pin + 256);
-        g->h_fit = (float*)(g->pin + 256 + EV_MAX_LEVELS * sizeof(GLevel));
         if ((st = xo_blocks_make(c, *g)) != EV_OK) {
             gengraph_free(c, g);
             return st;
@@ -766,44 +782,93 @@ extern "C" ev_status ev_evolve(ev_ctx* c, ev_pop parents, const float* fitness, 
     if (st == EV_OK) st = sync(x);
     if (st != EV_OK) return st;
 
-    for (int32_t i = 0; i < n_gen; i++) {
-        const int a = G.cur, b = 1 - a;
-        const uint64_t gen = gen0 + (uint64_t)i;
-        if (!G.exec[a]) {
+    // every buffer's graph, captured while nothing else is queued
+    auto ensure_graphs = [&]() -> ev_status {
+        for (int k = 0; k < NB; k++) {
+            if (G.exec[k]) continue;
             const auto tc = std::chrono::steady_clock::now();
-            if ((st = capture(c, G, a)) != EV_OK) return st;
+            const ev_status r = capture(c, G, k);
+            if (r != EV_OK) return r;
             rep.captures++;
             rep.ms_capture += ms_since(tc);
         }
+        return EV_OK;
+    };
+    auto launch = [&](int a) -> ev_status {
         HIPCHK(hipGraphLaunch(G.exec[a], s));
-        if ((st = sync(x)) != EV_OK) return st;
-        const GStatus gs = *G.h_st;
+        HIPCHK(hipEventRecord(G.done[a], s));
+        return EV_OK;
+    };
+    // generation i + 1, launched before generation i's status was read, is
+    // thrown away: the device's generation counter is set back to it
+    bool ahead = false;
+    auto discard_ahead = [&](uint64_t next_gen) -> ev_status {
+        if (!ahead) return EV_OK;
+        ahead = false;
+        ev_status r = sync(x);
+        if (r == EV_OK) r = put(x, G.gen_at, &next_gen, 8);
+        if (r == EV_OK) r = sync(x);
+        return r;
+    };
+    if (n_gen > 0) {
+        if ((st = ensure_graphs()) != EV_OK) return st;
+        if ((st = launch(G.cur)) != EV_OK) return st;
+    }
+    for (int32_t i = 0; i < n_gen; i++) {
+        const int a = G.cur, b = nxt(a);
+        const uint64_t gen = gen0 + (uint64_t)i;
+        // generation i was launched (by the iteration before, or above);
+        // launch i + 1 from its children before looking at its status
+        if (i + 1 < n_gen && !ahead && G.exec[b]) {
+            if ((st = launch(b)) != EV_OK) return st;
+            ahead = true;
+        }
+        HIPCHK(hipEventSynchronize(G.done[a]));
+        const GStatus gs = *G.h_st[a];
         std::vector<LevelSize> seen;
         int32_t capped = 0;
         uint64_t nodes = gs.child_bytes;
+        bool regraph = false;
         if (gs.poison) {
             // void: done again on the host-driven path, then new capacities
+            if ((st = discard_ahead(gen + 1)) != EV_OK) return st;
             if ((st = host_generation(c, G, a, gen, &seen, &capped, &nodes)) != EV_OK) return st;
             rep.fallbacks++;
             if ((st = replan(c, G, seen, tight)) != EV_OK) return st;
+            regraph = true;
         } else {
             capped = (int32_t)gs.capped;
             rep.replayed++;
-            seen = sizes_of(G.h_lv, gs.levels);
-            if (!tight && near_caps(seen, G.caps, G.slab_max) && (st = replan(c, G, seen, false)) != EV_OK) return st;
+            seen = sizes_of(G.h_lv[a], gs.levels);
             if (gs.child_bytes + EV_POP_PAD > G.bytes_cap * 3 / 4) {
+                // larger population buffers, keeping the children (the
+                // generation after them runs again on the new buffers)
+                if ((st = discard_ahead(gen + 1)) != EV_OK) return st;
                 graphs_drop(G);
                 if ((st = pop_blocks_make(c, G, 2 * (gs.child_bytes + EV_POP_PAD), b, gs.child_bytes)) != EV_OK)
                     return st;
+                regraph = true;
+            }
+            if (!tight && near_caps(seen, G.caps, G.slab_max)) {
+                // the generation ahead (if any) finishes under the old
+                // capacities; its status is read like any other
+                if ((st = replan(c, G, seen, false)) != EV_OK) return st;
+                regraph = true;
             }
         }
-        if (fit_history) std::memcpy(fit_history + (size_t)i * M, G.h_fit, (size_t)M * 4);
+        if (fit_history) std::memcpy(fit_history + (size_t)i * M, G.h_fit[a], (size_t)M * 4);
         if (capped_history) capped_history[i] = capped;
         rep.capped += (uint64_t)capped;
         rep.nodes += nodes;
         rep.generations++;
         G.cur = b;
+        if (i + 1 < n_gen) {
+            if (regraph && (st = ensure_graphs()) != EV_OK) return st;
+            if (!ahead && (st = launch(b)) != EV_OK) return st;
+        }
+        ahead = false;
     }
+    if ((st = sync(x)) != EV_OK) return st;
 
     // the last generation as a population of its own (planned afresh)
     std::vector<uint64_t> h_off((size_t)M + 1);

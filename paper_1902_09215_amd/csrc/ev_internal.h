@@ -53,12 +53,15 @@ struct SegIn {
 };
 
 // A level's segment length: SEG_TOKENS at a large level 0, a quarter of it
-// at a small one and at the skeleton levels, which have few tokens and need
-// the extra lanes (each segment is one lane of the structure passes).
+// at a smaller one and at the skeleton levels, which need the extra lanes
+// (each segment is one lane of the structure passes), and 16 tokens at a
+// level of under 2^20 tokens, whose passes take about the time of one
+// lane's segment.
 constexpr uint64_t SEG_BIG_LEVEL = 1ull << 26;
+constexpr uint64_t SEG_SMALL_LEVEL = 1ull << 20;
 constexpr uint32_t seg_len_for(int level, uint64_t tokens)
 {
-    return level == 0 && tokens >= SEG_BIG_LEVEL ? SEG_TOKENS : SEG_TOKENS / 4;
+    return level == 0 && tokens >= SEG_BIG_LEVEL ? SEG_TOKENS : tokens < SEG_SMALL_LEVEL ? 16u : SEG_TOKENS / 4;
 }
 
 // Bytes of one segment's recording regions (its code kinds, its fragment

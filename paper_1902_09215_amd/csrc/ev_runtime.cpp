@@ -357,10 +357,10 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
     for (;;) {
         const uint64_t C = level == 0 ? C0 : C1;
         const bool reusing = level == 0 && reuse != nullptr;
-        // Segments are 256 tokens at a large level 0 and 64 at a small one
-        // and at the skeleton levels, which need the extra parallelism; a
-        // chunk's first segment, which also emits the chunk's final flush,
-        // is a quarter of that.
+        // Segments are 256 tokens at a large level 0, 64 at a smaller one
+        // and at the skeleton levels, which need the extra parallelism, and
+        // 16 at a level of under 2^20 tokens; a chunk's first segment, which
+        // also emits the chunk's final flush, is a quarter of that.
         const uint32_t seg_len = seg_len_for(level, cur_len);
         const uint32_t head = seg_len / 4;
         auto nseg = [&](uint64_t len) -> uint64_t { return len <= head ? 1 : 1 + (len - head + seg_len - 1) / seg_len; };
