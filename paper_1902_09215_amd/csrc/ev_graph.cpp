@@ -112,17 +112,24 @@ struct GenGraph {
     float* h_fit[NB] = {};
     hipEvent_t done[NB] = {};  // the end of each graph's last replay
 
-    hipGraph_t graph[NB] = {};
-    hipGraphExec_t exec[NB] = {};
+    // per buffer: the graph of all L levels, and one of the first L - 1
+    // (the last level is room to grow; while recent generations have not
+    // needed it, its launches are left out)
+    hipGraph_t graph[NB] = {}, graph_s[NB] = {};
+    hipGraphExec_t exec[NB] = {}, exec_s[NB] = {};
 };
 
 static void graphs_drop(GenGraph& g)
 {
     for (int i = 0; i < NB; i++) {
-        if (g.exec[i]) (void)hipGraphExecDestroy(g.exec[i]);
-        if (g.graph[i]) (void)hipGraphDestroy(g.graph[i]);
-        g.exec[i] = nullptr;
-        g.graph[i] = nullptr;
+        for (hipGraphExec_t* e : {&g.exec[i], &g.exec_s[i]}) {
+            if (*e) (void)hipGraphExecDestroy(*e);
+            *e = nullptr;
+        }
+        for (hipGraph_t* h : {&g.graph[i], &g.graph_s[i]}) {
+            if (*h) (void)hipGraphDestroy(*h);
+            *h = nullptr;
+        }
     }
 }
 
@@ -418,8 +425,9 @@ static ev_status xo_blocks_make(ev_ctx* c, GenGraph& g)
     return st;
 }
 
-// Queue one generation, parents in buffer a and children in the next.
-static hipError_t enqueue_generation(ev_ctx* c, GenGraph& g, int a, hipStream_t s)
+// Queue one generation, parents in buffer a and children in the next, over
+// the first nl plan levels (a generation that needs more voids itself).
+static hipError_t enqueue_generation(ev_ctx* c, GenGraph& g, int a, uint32_t nl, hipStream_t s)
 {
     const int b = nxt(a);
     const uint32_t M = (uint32_t)g.M;
@@ -439,7 +447,7 @@ static hipError_t enqueue_generation(ev_ctx* c, GenGraph& g, int a, hipStream_t 
     uint64_t* cloc = g.loc;
     uint64_t* oloc = g.loc + g.n_max;
     uint64_t* floc = g.loc + 2 * g.n_max;
-    for (uint32_t l = 0; l < g.L; l++) {
+    for (uint32_t l = 0; l < nl; l++) {
         const uint64_t C = l == 0 ? g.C0 : g.C1;
         const uint32_t seg_len = g.seg_len[l], head = seg_len / 4;
         const LevelSize& k = g.caps[l];
@@ -457,7 +465,7 @@ static hipError_t enqueue_generation(ev_ctx* c, GenGraph& g, int a, hipStream_t 
                            g.record ? g.rec : nullptr, &gl->record_ovf, seg_len, s, gl));
         E(launch_seg_chunk(g.cseg, kn, g.cnt, g.stat, nullptr, nullptr, nullptr, nullptr, s, gl));
         E(launch_plan_trees(g.tl, M, g.stat, l, 0, cloc, oloc, floc, g.inend, g.sum, s, gl));
-        E(launch_g_end(g.tr, g.gls, l, g.d_caps, g.L, g.tl, g.sum, g.tb, g.fin, g.st, s));
+        E(launch_g_end(g.tr, g.gls, l, g.d_caps, nl, g.tl, g.sum, g.tb, g.fin, g.st, s));
         E(launch_plan_items(g.ch, kn, g.tb, cloc, oloc, floc, g.inend, g.cursor, g.cb, g.fe, g.run[l], nullptr,
                             g.codes[l], next, nullptr, s, gl));
         E(launch_seg_chunk(g.cseg, kn, g.cnt, g.stat, g.cb, g.fe, g.scode, g.sfrag, s, gl));
@@ -472,7 +480,7 @@ static hipError_t enqueue_generation(ev_ctx* c, GenGraph& g, int a, hipStream_t 
             E(launch_seg_check(g.codes[l], g.seg, kns, g.sst, g.scode, g.cnt, 0, g.err + 2 * l, s, gl));
         }
     }
-    for (uint32_t l = 0; l < g.L; l++) {
+    for (uint32_t l = 0; l < nl; l++) {
         RunArgs r{};
         r.codes = g.codes[l];
         r.chunks = g.run[l];
@@ -493,8 +501,8 @@ static hipError_t enqueue_generation(ev_ctx* c, GenGraph& g, int a, hipStream_t 
         E(launch_run(r, (uint32_t)std::min<uint64_t>(g.grid, (uint64_t)r.n_items), s));
     }
     FitArgs fa = {};
-    for (uint32_t l = 0; l < g.L; l++) fa.res[l] = g.res[l];
-    fa.n_levels = g.L;
+    for (uint32_t l = 0; l < nl; l++) fa.res[l] = g.res[l];
+    fa.n_levels = nl;
     fa.fin = g.fin;
     fa.y = g.d_y;
     fa.N = g.N;
@@ -502,18 +510,19 @@ static hipError_t enqueue_generation(ev_ctx* c, GenGraph& g, int a, hipStream_t 
     fa.fit = g.fit[b];
     fa.gl = g.gls;
     E(launch_fitness(fa, s));
-    E(launch_g_finish(g.st, g.gls, g.L, g.err, g.fit[b], M, g.gen_at, g.h_st[a], g.h_lv[a], g.h_fit[a], s));
+    E(launch_g_finish(g.st, g.gls, nl, g.err, g.fit[b], M, g.gen_at, g.h_st[a], g.h_lv[a], g.h_fit[a], s));
     return e;
 }
 
-// Capture the generation with parents in buffer a.
-static ev_status capture(ev_ctx* c, GenGraph& g, int a)
+// Capture the generation with parents in buffer a, over all levels or
+// (short) all but the last.
+static ev_status capture(ev_ctx* c, GenGraph& g, int a, bool short_form)
 {
     hipStream_t s = c->stream;
     ev_status st = sync(c->main);  // staged uploads have landed; nothing else is queued
     if (st != EV_OK) return st;
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    const hipError_t e = enqueue_generation(c, g, a, s);
+    const hipError_t e = enqueue_generation(c, g, a, short_form ? g.L - 1 : g.L, s);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(s, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -527,8 +536,8 @@ static ev_status capture(ev_ctx* c, GenGraph& g, int a)
         (void)hipGraphDestroy(graph);
         return hip_fail(e3, "hipGraphInstantiate");
     }
-    g.graph[a] = graph;
-    g.exec[a] = ex;
+    (short_form ? g.graph_s : g.graph)[a] = graph;
+    (short_form ? g.exec_s : g.exec)[a] = ex;
     return EV_OK;
 }
 
@@ -783,19 +792,36 @@ extern "C" ev_status ev_evolve(ev_ctx* c, ev_pop parents, const float* fitness, 
     if (st != EV_OK) return st;
 
     // every buffer's graph, captured while nothing else is queued
+    auto capture_timed = [&](int k, bool sf) -> ev_status {
+        const auto tc = std::chrono::steady_clock::now();
+        const ev_status r = capture(c, G, k, sf);
+        if (r != EV_OK) return r;
+        rep.captures++;
+        rep.ms_capture += ms_since(tc);
+        return EV_OK;
+    };
     auto ensure_graphs = [&]() -> ev_status {
         for (int k = 0; k < NB; k++) {
             if (G.exec[k]) continue;
-            const auto tc = std::chrono::steady_clock::now();
-            const ev_status r = capture(c, G, k);
+            const ev_status r = capture_timed(k, false);
             if (r != EV_OK) return r;
-            rep.captures++;
-            rep.ms_capture += ms_since(tc);
         }
         return EV_OK;
     };
+    // The short graph serves while the last SHORT_AFTER generations read
+    // all used fewer than L levels; a generation that needs the last level
+    // voids itself and is redone, and the full graph serves again.  Short
+    // graphs are captured when first needed after a re-capture (the capture
+    // waits for the generation in flight).
+    constexpr int SHORT_AFTER = 2;
+    int fits_short = 0;
     auto launch = [&](int a) -> ev_status {
-        HIPCHK(hipGraphLaunch(G.exec[a], s));
+        const bool sf = fits_short >= SHORT_AFTER && G.L >= 2;
+        if (sf && !G.exec_s[a]) {
+            const ev_status r = capture_timed(a, true);
+            if (r != EV_OK) return r;
+        }
+        HIPCHK(hipGraphLaunch(sf ? G.exec_s[a] : G.exec[a], s));
         HIPCHK(hipEventRecord(G.done[a], s));
         return EV_OK;
     };
@@ -829,6 +855,7 @@ extern "C" ev_status ev_evolve(ev_ctx* c, ev_pop parents, const float* fitness, 
         int32_t capped = 0;
         uint64_t nodes = gs.child_bytes;
         bool regraph = false;
+        const uint32_t L_read = G.L;  // the capacities generation i ran under
         if (gs.poison) {
             // void: done again on the host-driven path, then new capacities
             if ((st = discard_ahead(gen + 1)) != EV_OK) return st;
@@ -856,6 +883,10 @@ extern "C" ev_status ev_evolve(ev_ctx* c, ev_pop parents, const float* fitness, 
                 regraph = true;
             }
         }
+        // how many generations in a row fit the short graph (re-capture
+        // starts the count again)
+        const uint32_t used = gs.poison ? (uint32_t)seen.size() : gs.levels;
+        fits_short = (regraph || used + 1 > L_read) ? 0 : fits_short + 1;
         if (fit_history) std::memcpy(fit_history + (size_t)i * M, G.h_fit[a], (size_t)M * 4);
         if (capped_history) capped_history[i] = capped;
         rep.capped += (uint64_t)capped;
