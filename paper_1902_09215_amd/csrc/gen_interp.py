@@ -180,9 +180,14 @@ def handler(kind: str, pos: int, cp: str = "") -> list[str]:
         body = [f"{VOP[a]} {BELOW}, {T}, {BELOW}", f"{VOP[b]} v{W0 - 2}, {BELOW}, v{W0 - 2}", "s_sub_u32 m0, m0, 2"]
     elif k.startswith("OPX"):
         op = int(k[3])
-        # T = op(x, T): x goes just above T first
+        # T = op(x, T).  x + T and x - T are one fused multiply-add with x as
+        # the (absolute) third source: T * 1 + x and T * -1 + x round once,
+        # exactly as the sum and the difference do.  x * T copies x just
+        # above T first.
         if op == 3:
             routine = "divopx"
+        elif op < 2:
+            body = [f"v_fma_f32 {T}, {T}, {'1.0' if op == 0 else '-1.0'}, %[x]"]
         else:
             body = [put(ABOVE, "%[x]"), f"{VOP[op]} {T}, {ABOVE}, {T}"]
     elif k.startswith("CH"):
