@@ -356,7 +356,8 @@ typedef struct {
     uint32_t trees;   /* trees with work at this level */
     uint32_t items;   /* work items */
     uint32_t slots;   /* result slots the level writes */
-    uint32_t pad;
+    uint32_t launch;  /* the launch of an evaluation (on the context's own stream) that runs the
+                         level: levels with the same value run in one chained launch */
     uint64_t codes;   /* threaded codes of its register-stack work items (0 for the general kernel's) */
 } ev_level_info;
 

@@ -48,7 +48,7 @@ class ev_plan_info(ctypes.Structure):
 
 class ev_level_info(ctypes.Structure):
     _fields_ = [("tokens", ctypes.c_uint64), ("trees", ctypes.c_uint32), ("items", ctypes.c_uint32),
-                ("slots", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("codes", ctypes.c_uint64)]
+                ("slots", ctypes.c_uint32), ("launch", ctypes.c_uint32), ("codes", ctypes.c_uint64)]
 
 
 class ev_evolve_report(ctypes.Structure):

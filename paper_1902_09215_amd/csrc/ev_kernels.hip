@@ -2513,12 +2513,17 @@ __global__ __launch_bounds__(64) void k_run_chain(ChainArgs a)
                 const uint64_t outp = uni((uint64_t)(uintptr_t)L.out_res + (uint64_t)d.w * a.rowb);
                 const uint32_t slane = lane * 4u;
                 const uint32_t refs = (uint32_t)__builtin_amdgcn_readfirstlane(L.refs);
+                // a skeleton item (it reads slots) is on its tree's critical
+                // path: its wave issues ahead of the level-0 waves sharing
+                // its SIMD
+                if (refs) __builtin_amdgcn_s_setprio(3);
                 asm volatile(EV_INTERP_ASM_COH
                              :
                              : [x] "v"(xv), [lane4] "v"(lane4), [slane] "v"(slane), [cptr] "s"(cptr), [j0] "s"(j0),
                                [inp] "s"(inp), [outp] "s"(outp), [rowb] "s"(a.rowb), [smem] "s"(smem),
                                [flag] "s"(a.flag), [refs] "s"(refs)
                              : EV_INTERP_CLOBBERS, "memory");
+                if (refs) __builtin_amdgcn_s_setprio(0);
             }
         }
         if (lane == 0) __hip_atomic_fetch_add(a.done + (size_t)l * a.M + tree, 1u, __ATOMIC_RELAXED,

@@ -227,6 +227,7 @@ void rescache_free(ev_ctx* c, ResCache& r)
     r.d_per_case = nullptr;
     dev_free(c, r.d_chain);
     r.d_chain = nullptr;
+    r.chain_first = -1;
 }
 
 void pop_free(ev_ctx* c, Pop* P)
@@ -737,7 +738,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
     }
     pl.d_err = (uint32_t*)d_err;  // the plan keeps the validator's words
     d_err = nullptr;
-    if (pl.levels.size() >= 3 && need_all.size() == pl.levels.size() * (size_t)M) {
+    if (pl.levels.size() >= 2 && need_all.size() == pl.levels.size() * (size_t)M) {
         if ((st = dev_alloc(c, need_all.size() * sizeof(uint32_t), (void**)&pl.d_need)) != EV_OK ||
             (st = put(x, pl.d_need, need_all.data(), need_all.size() * sizeof(uint32_t))) != EV_OK) {
             cleanup();
@@ -1047,21 +1048,33 @@ struct EvalBufs {
     std::vector<float*> res;
     float* slab = nullptr;
     size_t slab_bytes = 0;
-    // the skeleton levels in one launch: their RunLevel records and the
-    // done counters ((levels - 1) x trees words); null: a launch per level
+    // levels chain_first .. levels-1 in one launch: their RunLevel records
+    // and the done counters (chained levels x trees words); null: a launch
+    // per level
     const RunLevel* chain = nullptr;
     uint32_t* done = nullptr;
+    int chain_first = -1;
 };
 
-// The skeleton levels of P go in one chained launch: three levels or more,
-// every one on the register-stack kernel, on a stream that allows it.
-static bool chain_applies(ev_ctx* c, const Exec& x, const Pop* P)
+// Level-0 sizes (tokens) up to which level 0 joins the chained launch: a
+// tree's skeleton items then start as soon as its own level-0 items are
+// done, beside the rest of level 0.  Larger level 0s keep a launch of their
+// own (their trees' level-0 items cover the whole launch anyway).
+static constexpr uint64_t CHAIN_LEVEL0_MAX = 1ull << 27;
+
+// The first level of P that goes in the chained launch, or -1: every level
+// on the register-stack kernel, on a stream that allows it; from level 0
+// when level 0 is small and there is a level after it, else from level 1
+// when there are two levels after it.
+static int chain_first(ev_ctx* c, const Exec& x, const Pop* P)
 {
     const Plan& pl = P->plan;
-    if (!c->use_chain || !x.chain_ok || !pl.d_need || pl.levels.size() < 3) return false;
+    const size_t nl = pl.levels.size();
+    if (!c->use_chain || !x.chain_ok || !pl.d_need || nl < 2) return -1;
     for (const Level& L : pl.levels)
-        if (L.n_chunks || !L.n_run || !L.d_item_tree) return false;
-    return true;
+        if (L.n_chunks || !L.n_run || !L.d_item_tree) return -1;
+    if (pl.levels[0].tokens <= CHAIN_LEVEL0_MAX) return 0;
+    return nl >= 3 ? 1 : -1;
 }
 
 // Spill-slab bytes one wave of a level's interpreter needs (0: none).
@@ -1102,27 +1115,29 @@ static ev_status eval_launch(ev_ctx* c, Exec& x, Pop* P, const CaseTable& ct, co
     }
     if (timed) HIPCHK(hipEventRecord(x.ev0, s));
     HIPCHK(launch_fill_u32(b.counters, (uint32_t)(2 * nl), 0u, s));
-    const bool chained = b.chain && b.done && nl >= 3;
-    if (chained) HIPCHK(launch_fill_u32(b.done, (uint32_t)((nl - 1) * (size_t)P->M), 0u, s));
+    const size_t cf = b.chain && b.done && b.chain_first >= 0 ? (size_t)b.chain_first : nl;
+    const bool chained = cf < nl;
+    if (chained) HIPCHK(launch_fill_u32(b.done, (uint32_t)((nl - cf) * (size_t)P->M), 0u, s));
     for (size_t li = 0; li < nl; li++) {
         const Level& L = P->plan.levels[li];
-        if (chained && li >= 1) {
-            if (li == 1) {
-                // levels 1 .. nl-1 in one launch (k_run_chain)
+        if (chained && li >= cf) {
+            if (li == cf) {
+                // levels cf .. nl-1 in one launch (k_run_chain)
+                if (timed && li == 0) HIPCHK(hipEventRecord(x.evi0, s));
                 ChainArgs ca{};
                 ca.levels = b.chain;
-                ca.n_levels = (uint32_t)(nl - 1);
+                ca.n_levels = (uint32_t)(nl - cf);
                 uint64_t total = 0, rows = 0;
-                for (size_t k = 1; k < nl; k++) {
+                for (size_t k = cf; k < nl; k++) {
                     total += (uint64_t)P->plan.levels[k].n_run * n_cb;
                     rows = std::max<uint64_t>(rows, P->plan.levels[k].slab_entries);
                 }
-                if (total > 0xFFFFFFF0ull) return fail(EV_ECAP, "too many skeleton work items for one launch");
+                if (total > 0xFFFFFFF0ull) return fail(EV_ECAP, "too many chained work items for one launch");
                 ca.total = (uint32_t)total;
                 ca.n_cb = n_cb;
                 ca.M = (uint32_t)P->M;
-                ca.counter = b.counters + nl + 1;
-                ca.need = P->plan.d_need + P->M;  // from level 1 on
+                ca.counter = b.counters + nl + cf;
+                ca.need = P->plan.d_need + cf * (size_t)P->M;  // from level cf on
                 ca.done = b.done;
                 ca.x = ct.d_x;
                 ca.N = N;
@@ -1134,6 +1149,7 @@ static ev_status eval_launch(ev_ctx* c, Exec& x, Pop* P, const CaseTable& ct, co
                 if (rows) g = std::min<uint64_t>(g, b.slab_bytes / (rows * 64 * sizeof(float)));
                 if (g == 0) return fail(EV_ECAP, "no room for one wave's spill slab (%llu rows)", (unsigned long long)rows);
                 HIPCHK(launch_run_chain(ca, (uint32_t)g, s));
+                if (timed && li == 0) HIPCHK(hipEventRecord(x.evi1, s));
             }
             if (timed) HIPCHK(hipEventRecord(x.evl[li], s));
             continue;
@@ -1219,9 +1235,11 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
     ev_status st;
     if ((st = rescache_get(c, x, P, table, &rc)) != EV_OK) return st;
     const size_t nl = P->plan.levels.size();
-    const bool chain = chain_applies(c, x, P);
-    // the work counters, then (chained) the done counters of levels 1 ..
-    if ((st = ensure_counters(c, x, 2 * nl + (chain ? (nl - 1) * (size_t)P->M : 0))) != EV_OK) return st;
+    const int cfi = chain_first(c, x, P);
+    const bool chain = cfi >= 0;
+    const size_t cf = chain ? (size_t)cfi : nl;
+    // the work counters, then (chained) the done counters of the chained levels
+    if ((st = ensure_counters(c, x, 2 * nl + (chain ? (nl - cf) * (size_t)P->M : 0))) != EV_OK) return st;
     // spill slabs for every wave of each level's grid
     const uint32_t grid_max = (uint32_t)c->grid_eval[D == 128 ? 1 : 0];
     size_t need = 0, chain_rows = 0;
@@ -1229,7 +1247,7 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
     for (size_t li = 0; li < nl; li++) {
         const Level& L = P->plan.levels[li];
         const uint64_t items = (uint64_t)(L.n_run + L.n_chunks) * n_cb;
-        if (chain && li >= 1) {
+        if (chain && li >= cf) {
             chain_rows = std::max<size_t>(chain_rows, L.slab_entries);
             chain_items += items;
             continue;
@@ -1240,28 +1258,35 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
     if (chain)
         need = std::max(need, (size_t)std::min<uint64_t>(c->grid_chain, chain_items) * chain_rows * 64 * sizeof(float));
     if ((st = ensure_gstack(c, x, need)) != EV_OK) return st;
+    if (chain && rc->d_chain && rc->chain_first != cfi) {
+        // made for another first level (queued launches on this stream may
+        // still read it: freed in stream order)
+        dev_free(c, rc->d_chain);
+        rc->d_chain = nullptr;
+    }
     if (chain && !rc->d_chain) {
-        // the skeleton levels as the chained launch sees them (kept with
-        // the result slots of this case table)
-        std::vector<RunLevel> rl(nl - 1);
+        // the chained levels as the chained launch sees them (kept with the
+        // result slots of this case table)
+        std::vector<RunLevel> rl(nl - cf);
         uint64_t first = 0;
-        for (size_t li = 1; li < nl; li++) {
+        for (size_t li = cf; li < nl; li++) {
             const Level& L = P->plan.levels[li];
-            RunLevel& r = rl[li - 1];
+            RunLevel& r = rl[li - cf];
             r.codes = L.codes;
             r.chunks = L.d_run;
             r.item_tree = L.d_item_tree;
-            r.in_res = rc->res[li - 1];
+            r.in_res = li ? rc->res[li - 1] : nullptr;
             r.out_res = rc->res[li];
             r.verdict = P->plan.d_err ? P->plan.d_err + 2 * li : nullptr;
             r.first = (uint32_t)first;
             r.n_items = L.n_run * n_cb;
-            r.refs = 1;
+            r.refs = li ? 1u : 0u;
             first += (uint64_t)L.n_run * n_cb;
         }
         if ((st = dev_alloc(c, rl.size() * sizeof(RunLevel), (void**)&rc->d_chain)) != EV_OK ||
             (st = put(x, rc->d_chain, rl.data(), rl.size() * sizeof(RunLevel))) != EV_OK)
             return st;
+        rc->chain_first = cfi;
     }
     EvalBufs b;
     b.counters = x.d_counters;
@@ -1271,6 +1296,7 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
     if (chain) {
         b.chain = rc->d_chain;
         b.done = x.d_counters + 2 * nl;
+        b.chain_first = cfi;
     }
     return eval_launch(c, x, P, ct, b, d_fit, d_per_case, d_hits, timed);
 }
@@ -1929,7 +1955,9 @@ ev_status ev_get_level_info(ev_ctx* c, ev_pop pop, int32_t level, ev_level_info*
     info->trees = L.trees;
     info->items = L.n_run + L.n_chunks;
     info->slots = L.n_out;
-    info->pad = 0;
+    // the launch of an evaluation on the context's stream that runs the level
+    const int cf = chain_first(c, c->main, P);
+    info->launch = (uint32_t)(cf >= 0 && level >= cf ? cf : level);
     info->codes = L.n_codes;
     return EV_OK;
 }

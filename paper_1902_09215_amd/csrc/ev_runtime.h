@@ -91,7 +91,8 @@ struct ResCache {
     int32_t N = 0;
     std::vector<float*> res;     // per level: n_out * N floats (EV_RING padding rows before)
     float* d_per_case = nullptr;
-    RunLevel* d_chain = nullptr;  // the skeleton levels as the chained launch sees them
+    RunLevel* d_chain = nullptr;  // the chained levels as the chained launch sees them
+    int chain_first = -1;         // the first level d_chain holds
 };
 
 struct Pop {
