@@ -482,6 +482,12 @@ __global__ __launch_bounds__(64) void k_plan_chunks(const TreeLvl* __restrict__ 
 }
 
 __device__ __forceinline__ uint32_t len_bucket(uint32_t len) { return len ? (uint32_t)__clz(len) : 32u; }
+__device__ __forceinline__ uint32_t len_bucket64(uint64_t len) { return len >> 32 ? 0u : len_bucket((uint32_t)len); }
+// the sort key of a work item: its own length, or its tree's
+__device__ __forceinline__ uint32_t item_bucket(const ChunkIn& c, const TreeLvl* tl)
+{
+    return tl ? len_bucket64(tl[c.tree].len) : len_bucket(c.len);
+}
 
 // One wave per tree: the numbering of its chunks' slots, fragment tokens and
 // codes relative to the tree (exclusive for codes, inclusive for slots and
@@ -767,12 +773,12 @@ __global__ __launch_bounds__(64) void k_reuse_chunks(const TreeReuse* __restrict
 // takes one atomic per distinct bucket among its lanes; the order inside a
 // bucket does not matter.
 __global__ void k_item_hist(const ChunkIn* __restrict__ ch, uint32_t n, uint32_t* __restrict__ hist,
-                            const GLevel* __restrict__ gl)
+                            const GLevel* __restrict__ gl, const TreeLvl* __restrict__ tl)
 {
     if (gl) n = gl->n;
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = j < n;
-    const uint32_t b = in ? len_bucket(ch[j].len) : EV_LEN_BUCKETS;
+    const uint32_t b = in ? item_bucket(ch[j], tl) : EV_LEN_BUCKETS;
     uint64_t todo = __ballot(in);
     while (todo) {
         const uint32_t lead = (uint32_t)__ffsll((unsigned long long)todo) - 1u;
@@ -796,12 +802,13 @@ __global__ void k_item_cursor(uint32_t* __restrict__ hist)
 }
 
 __global__ void k_item_place(const ChunkIn* __restrict__ ch, uint32_t n, uint32_t* __restrict__ cursor,
-                             uint32_t* __restrict__ item_at, const GLevel* __restrict__ gl)
+                             uint32_t* __restrict__ item_at, const GLevel* __restrict__ gl,
+                             const TreeLvl* __restrict__ tl)
 {
     if (gl) n = gl->n;
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = j < n;
-    const uint32_t b = in ? len_bucket(ch[j].len) : EV_LEN_BUCKETS;
+    const uint32_t b = in ? item_bucket(ch[j], tl) : EV_LEN_BUCKETS;
     const uint64_t lt = (1ull << (threadIdx.x & 63u)) - 1ull;
     uint64_t todo = __ballot(in);
     while (todo) {
@@ -2630,13 +2637,13 @@ hipError_t launch_reuse_chunks(const TreeReuse* trees, uint32_t n_trees, const C
 }
 
 hipError_t launch_item_sort(const ChunkIn* ch, uint32_t n, uint32_t* hist, uint32_t* item_at, hipStream_t s,
-                            const GLevel* gl)
+                            const GLevel* gl, const TreeLvl* tl)
 {
     hipError_t e = launch_fill_u32(hist, EV_LEN_BUCKETS, 0u, s);
     if (e != hipSuccess || n == 0) return e;
-    hipLaunchKernelGGL(k_item_hist, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, hist, gl);
+    hipLaunchKernelGGL(k_item_hist, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, hist, gl, tl);
     hipLaunchKernelGGL(k_item_cursor, dim3(1), dim3(64), 0, s, hist);
-    hipLaunchKernelGGL(k_item_place, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, hist, item_at, gl);
+    hipLaunchKernelGGL(k_item_place, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, hist, item_at, gl, tl);
     return hipGetLastError();
 }
 

@@ -34,9 +34,10 @@ hipError_t launch_reuse_runs(const XoPlan* plan, const int32_t* mum, const L0Tre
 hipError_t launch_reuse_chunks(const TreeReuse* trees, uint32_t n_trees, const ChunkIn* mum_ch, uint32_t seg_len,
                                uint32_t head, ChunkIn* ch, ChunkSegs* cg, uint32_t* src, uint32_t* err_init,
                                uint32_t n_err, hipStream_t s);
-// work-item places, longest first (hist: EV_LEN_BUCKETS words of scratch)
+// work-item places, longest first (hist: EV_LEN_BUCKETS words of scratch);
+// with tl (the level's trees, indexed by tree), biggest tree first instead
 hipError_t launch_item_sort(const ChunkIn* ch, uint32_t n, uint32_t* hist, uint32_t* item_at, hipStream_t s,
-                            const GLevel* gl = nullptr);
+                            const GLevel* gl = nullptr, const TreeLvl* tl = nullptr);
 hipError_t launch_reuse_stats(const uint32_t* src, uint32_t n, const ChunkStat* mum_stat, ChunkStat* cstat,
                               hipStream_t s);
 hipError_t launch_reuse_copy(const uint32_t* src, uint32_t n, const ChunkStat* cstat, const uint64_t* code_begin,

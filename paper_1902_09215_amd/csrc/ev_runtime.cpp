@@ -340,10 +340,15 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
     auto& tb = W.tb;      // per tree id: its bases over the level's chunks
     tb.resize((size_t)std::max(1, M));
     uint32_t hist[EV_LEN_BUCKETS];
-    // work items go longest first, for the balance of the kernels' dynamic
-    // work queues: a counting sort on the length's bit count (the order
-    // inside a power of two does not matter)
-    auto bucket = [](uint64_t len) { return len ? (uint32_t)__builtin_clz((uint32_t)len) : 32u; };
+    // work items go biggest tree first, a tree's items together: a tree's
+    // next level waits for all of its items at this one (the chained launch
+    // starts it as soon as they are done), and long trees have the long
+    // items, which the kernels' dynamic work queues want first.  A counting
+    // sort on the tree length's bit count (the order inside a power of two
+    // does not matter).
+    auto bucket = [](uint64_t len) {
+        return len >> 32 ? 0u : len ? (uint32_t)__builtin_clz((uint32_t)len) : 32u;
+    };
 
     bool plan_run = c->use_run;  // items on the register-stack kernel (no constants seen)
     std::vector<uint32_t> need_all;  // per level and tree: work items (register-stack levels)
@@ -441,10 +446,11 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
             v.C = (uint32_t)Ct;
             v.tree = (uint32_t)t;
             v.ref_base = (uint32_t)ref_base[t];
-            // the ranks of its work items in their length buckets
-            v.rank_full = hist[bucket(Ct)];
-            hist[bucket(Ct)] += (uint32_t)(nc - 1);
-            v.rank_last = hist[bucket(len - (nc - 1) * Ct)]++;
+            // the ranks of its work items in its length bucket (made
+            // absolute below)
+            v.rank_full = hist[bucket(len)];
+            hist[bucket(len)] += (uint32_t)nc;
+            v.rank_last = v.rank_full + (uint32_t)(nc - 1);
             tl.push_back(v);
             n += nc;
             ns += (nc - 1) * nseg(Ct) + nseg(len - (nc - 1) * Ct);
@@ -457,12 +463,19 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         if (tl.empty()) break;
         const uint32_t nt = (uint32_t)tl.size(), n_seg = (uint32_t)ns;
 
-        // each length bucket's first place
+        // each length bucket's first place; the trees' ranks become places
+        // (the item kernel's per-chunk bucket offsets are then zero)
         uint32_t cursor[EV_LEN_BUCKETS];
         for (uint32_t k = 0, a = 0; k < EV_LEN_BUCKETS; k++) {
             cursor[k] = a;
             a += hist[k];
         }
+        if (!reusing)
+            for (TreeLvl& v : tl) {
+                v.rank_full += cursor[bucket(v.len)];
+                v.rank_last += cursor[bucket(v.len)];
+            }
+        std::fill(cursor, cursor + EV_LEN_BUCKETS, 0u);
         // device: chunks, segments, their counts, and each tree's numbering
         const size_t tl_bytes = nt * sizeof(TreeLvl);
         if ((st = realloc(&d_tl, tl_bytes + sizeof(cursor))) || (st = realloc(&d_ch, n * sizeof(ChunkIn))) ||
@@ -489,7 +502,8 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
             }
             HIPCHK(launch_reuse_chunks((TreeReuse*)d_tr, nt, reuse->mum->plan.l0_ch, seg_len, head, (ChunkIn*)d_ch,
                                        (ChunkSegs*)d_cseg, (uint32_t*)d_src, (uint32_t*)d_err, N_ERR, s));
-            HIPCHK(launch_item_sort((ChunkIn*)d_ch, (uint32_t)n, (uint32_t*)d_at + n, (uint32_t*)d_at, s));
+            HIPCHK(launch_item_sort((ChunkIn*)d_ch, (uint32_t)n, (uint32_t*)d_at + n, (uint32_t*)d_at, s, nullptr,
+                                    (TreeLvl*)d_tl));
         } else {
             HIPCHK(launch_plan_chunks((TreeLvl*)d_tl, nt, seg_len, head, (ChunkIn*)d_ch, (ChunkSegs*)d_cseg,
                                       level == 0 ? (uint32_t*)d_err : nullptr, N_ERR, s));
