@@ -188,17 +188,22 @@ struct RunLevel {
     const float* in_res;        // the previous level's slot rows
     float* out_res;
     const uint32_t* verdict;    // the validator's flags for the level's code streams
-    uint32_t first;             // the level's first place in the launch's queue
+    uint32_t first;             // the record's first place in the launch's queue
     uint32_t n_items;           // work items x case blocks
-    uint32_t refs, pad;
+    uint32_t refs;
+    uint32_t plevel;            // its plan level, counted from the launch's first
 };
 
 // Several levels in one launch: a work item of a level waits for its tree's
 // items of the level before (need: work items per level and tree; done:
-// finished items x case blocks, cleared before the launch).
+// finished items x case blocks, cleared before the launch).  The queue is a
+// list of records, each a run of one level's work items (chunks and
+// item_tree point at the run's first); a level may be split over several
+// records, each of them after every record that holds work its items wait
+// for.
 struct ChainArgs {
     const RunLevel* levels;
-    uint32_t n_levels;
+    uint32_t n_levels;  // records
     uint32_t total;  // items of every level
     uint32_t n_cb;
     uint32_t M;      // trees (the stride of need and done)

@@ -2463,13 +2463,14 @@ __global__ __launch_bounds__(256) void k_g_finish(GStatus* __restrict__ st, cons
     for (uint32_t j = t; j < M; j += blockDim.x) h_fit[j] = fit[j];
 }
 
-// The skeleton levels in one persistent launch (Sec. 2.2's subtrees
+// Several plan levels in one persistent launch (Sec. 2.2's subtrees
 // combined level by level, without a barrier between levels): the queue
-// holds the levels' work items level after level, and an item of level l
-// of tree t waits until every item of level l - 1 of tree t has finished.
-// Every item it waits for sits earlier in the queue, and a wave takes its
-// next item only after finishing its current one, so the earliest
-// unfinished item always runs and the wait ends.  Slot rows cross compute
+// holds runs of the levels' work items, and an item of level l of tree t
+// waits until every item of level l - 1 of tree t has finished.  Every item
+// it waits for sits earlier in the queue.  A wave holds its current item
+// and the next one it took, and starts that one only after finishing the
+// current; so the earliest unfinished item is some wave's current item,
+// everything it waits for is done, and the wait ends.  Slot rows cross compute
 // units (and the XCDs' separate L2s) without any cache maintenance: every
 // slot-row load and store of the interpreter is made at device scope (sc1),
 // the item's stores have completed (the interpreter's last vmcnt wait)
@@ -2490,9 +2491,10 @@ __global__ __launch_bounds__(64) void k_run_chain(ChainArgs a)
         const uint32_t ci = local / a.n_cb;
         const uint32_t cb = local - ci * a.n_cb;
         const uint32_t tree = (uint32_t)__builtin_amdgcn_readfirstlane(L.item_tree[ci]);
-        if (l > 0) {
-            const uint32_t* dp = a.done + (size_t)(l - 1) * a.M + tree;
-            const uint32_t want = a.need[(size_t)(l - 1) * a.M + tree] * a.n_cb;
+        const uint32_t pl = L.plevel;
+        if (pl > 0) {
+            const uint32_t* dp = a.done + (size_t)(pl - 1) * a.M + tree;
+            const uint32_t want = a.need[(size_t)(pl - 1) * a.M + tree] * a.n_cb;
             while (__hip_atomic_load(dp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want)
                 __builtin_amdgcn_s_sleep(4);
         }
@@ -2533,7 +2535,7 @@ __global__ __launch_bounds__(64) void k_run_chain(ChainArgs a)
                 if (refs) __builtin_amdgcn_s_setprio(0);
             }
         }
-        if (lane == 0) __hip_atomic_fetch_add(a.done + (size_t)l * a.M + tree, 1u, __ATOMIC_RELAXED,
+        if (lane == 0) __hip_atomic_fetch_add(a.done + (size_t)pl * a.M + tree, 1u, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
         item = next;
     }

@@ -191,6 +191,8 @@ void plan_free(ev_ctx* c, Plan& pl)
     pl.levels.clear();
     dev_free(c, pl.d_need);
     pl.d_need = nullptr;
+    pl.h_need.clear();
+    pl.h_pos.clear();
     pl.fin_level.clear();
     pl.fin_slot.clear();
     dev_free(c, pl.d_fin);
@@ -228,6 +230,7 @@ void rescache_free(ev_ctx* c, ResCache& r)
     dev_free(c, r.d_chain);
     r.d_chain = nullptr;
     r.chain_first = -1;
+    r.chain_records = 0;
 }
 
 void pop_free(ev_ctx* c, Pop* P)
@@ -352,6 +355,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
 
     bool plan_run = c->use_run;  // items on the register-stack kernel (no constants seen)
     std::vector<uint32_t> need_all;  // per level and tree: work items (register-stack levels)
+    std::vector<uint32_t> pos_all;   // and the place of the tree's first item (~0u: not known)
     std::vector<TreeReuse> trv;  // level 0 of a reusing plan: the children's runs
     if (reuse) {
         const Plan& mp = reuse->mum->plan;
@@ -593,7 +597,11 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         if (run_items && need_all.size() == (size_t)level * M) {
             // each tree's work items at this level, for the chained launch
             need_all.resize((size_t)(level + 1) * M, 0u);
-            for (uint32_t i = 0; i < nt; i++) need_all[(size_t)level * M + tl[i].tree] = tl[i].n_chunks;
+            pos_all.resize((size_t)(level + 1) * M, ~0u);
+            for (uint32_t i = 0; i < nt; i++) {
+                need_all[(size_t)level * M + tl[i].tree] = tl[i].n_chunks;
+                if (!reusing) pos_all[(size_t)level * M + tl[i].tree] = tl[i].rank_full;
+            }
         }
 
         Level L;
@@ -758,6 +766,8 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
             cleanup();
             return st;
         }
+        pl.h_need = std::move(need_all);
+        pl.h_pos = std::move(pos_all);
     }
     cleanup();
     pl.bytes = 0;
@@ -1068,6 +1078,7 @@ struct EvalBufs {
     const RunLevel* chain = nullptr;
     uint32_t* done = nullptr;
     int chain_first = -1;
+    uint32_t chain_records = 0;  // runs of work items in the chained launch's queue
 };
 
 // Level-0 sizes (tokens) up to which level 0 joins the chained launch: a
@@ -1140,7 +1151,7 @@ static ev_status eval_launch(ev_ctx* c, Exec& x, Pop* P, const CaseTable& ct, co
                 if (timed && li == 0) HIPCHK(hipEventRecord(x.evi0, s));
                 ChainArgs ca{};
                 ca.levels = b.chain;
-                ca.n_levels = (uint32_t)(nl - cf);
+                ca.n_levels = b.chain_records;
                 uint64_t total = 0, rows = 0;
                 for (size_t k = cf; k < nl; k++) {
                     total += (uint64_t)P->plan.levels[k].n_run * n_cb;
@@ -1279,28 +1290,70 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
         rc->d_chain = nullptr;
     }
     if (chain && !rc->d_chain) {
-        // the chained levels as the chained launch sees them (kept with the
-        // result slots of this case table)
-        std::vector<RunLevel> rl(nl - cf);
-        uint64_t first = 0;
-        for (size_t li = cf; li < nl; li++) {
-            const Level& L = P->plan.levels[li];
-            RunLevel& r = rl[li - cf];
-            r.codes = L.codes;
-            r.chunks = L.d_run;
-            r.item_tree = L.d_item_tree;
-            r.in_res = li ? rc->res[li - 1] : nullptr;
-            r.out_res = rc->res[li];
-            r.verdict = P->plan.d_err ? P->plan.d_err + 2 * li : nullptr;
-            r.first = (uint32_t)first;
-            r.n_items = L.n_run * n_cb;
-            r.refs = li ? 1u : 0u;
-            first += (uint64_t)L.n_run * n_cb;
+        // the chained launch's queue, kept with the result slots of this
+        // case table: runs of work items (level, first item, count)
+        struct Run {
+            size_t li;
+            uint32_t start, count;
+        };
+        std::vector<Run> runs;
+        const Plan& pl = P->plan;
+        const size_t M = (size_t)P->M;
+        const bool known = cf == 0 && nl >= 2 && pl.h_pos.size() >= 2 * M && pl.h_need.size() >= 2 * M &&
+                           pl.h_pos[0] != ~0u && pl.h_pos[M] != ~0u;
+        if (known) {
+            // Level 0's first wave of items (as many as the launch has
+            // waves), then the skeleton items of the trees whose level-0
+            // items all lie in it (taken in their own order, as long as that
+            // holds), then the rest of level 0, then the other skeleton
+            // items.  Those trees' skeleton items start when their level-0
+            // items end, not after every level-0 item has been taken.
+            const uint32_t n0 = pl.levels[0].n_run, n1 = pl.levels[1].n_run;
+            const uint32_t P0 =
+                (uint32_t)std::min<uint64_t>(n0, std::max<uint64_t>(1, (uint64_t)c->grid_chain / n_cb));
+            std::vector<std::pair<uint32_t, uint32_t>> by1;  // (first level-1 place, tree)
+            for (size_t t = 0; t < M; t++)
+                if (pl.h_need[M + t]) by1.push_back({pl.h_pos[M + t], (uint32_t)t});
+            std::sort(by1.begin(), by1.end());
+            uint32_t K = 0;
+            for (auto& e : by1) {
+                const size_t t = e.second;
+                if (e.first != K || pl.h_pos[t] == ~0u || (uint64_t)pl.h_pos[t] + pl.h_need[t] > P0) break;
+                K += pl.h_need[M + t];
+            }
+            runs.push_back({0, 0, P0});
+            if (K) runs.push_back({1, 0, K});
+            if (n0 > P0) runs.push_back({0, P0, n0 - P0});
+            if (n1 > K) runs.push_back({1, K, n1 - K});
+            for (size_t li = 2; li < nl; li++) runs.push_back({li, 0, pl.levels[li].n_run});
+        } else {
+            for (size_t li = cf; li < nl; li++) runs.push_back({li, 0, pl.levels[li].n_run});
         }
+        std::vector<RunLevel> rl;
+        uint64_t first = 0;
+        for (const Run& u : runs) {
+            if (!u.count) continue;
+            const Level& L = pl.levels[u.li];
+            RunLevel r{};
+            r.codes = L.codes;
+            r.chunks = L.d_run + u.start;
+            r.item_tree = L.d_item_tree + u.start;
+            r.in_res = u.li ? rc->res[u.li - 1] : nullptr;
+            r.out_res = rc->res[u.li];
+            r.verdict = pl.d_err ? pl.d_err + 2 * u.li : nullptr;
+            r.first = (uint32_t)first;
+            r.n_items = u.count * n_cb;
+            r.refs = u.li ? 1u : 0u;
+            r.plevel = (uint32_t)(u.li - cf);
+            rl.push_back(r);
+            first += (uint64_t)u.count * n_cb;
+        }
+        if (rl.empty()) rl.push_back(RunLevel{});
         if ((st = dev_alloc(c, rl.size() * sizeof(RunLevel), (void**)&rc->d_chain)) != EV_OK ||
             (st = put(x, rc->d_chain, rl.data(), rl.size() * sizeof(RunLevel))) != EV_OK)
             return st;
         rc->chain_first = cfi;
+        rc->chain_records = (uint32_t)rl.size();
     }
     EvalBufs b;
     b.counters = x.d_counters;
@@ -1311,6 +1364,7 @@ ev_status eval_enqueue(ev_ctx* c, Exec& x, Pop* P, int32_t table, float* d_fit, 
         b.chain = rc->d_chain;
         b.done = x.d_counters + 2 * nl;
         b.chain_first = cfi;
+        b.chain_records = rc->chain_records;
     }
     return eval_launch(c, x, P, ct, b, d_fit, d_per_case, d_hits, timed);
 }

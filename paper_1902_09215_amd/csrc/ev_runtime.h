@@ -60,8 +60,11 @@ struct Plan {
     bool err_pending = false;
     uint32_t h_err[2] = {0, 0};
     // per level and tree (levels x trees): the tree's work items, for the
-    // chained launch of the skeleton levels (null when it does not apply)
+    // chained launch (null when it does not apply); on the host, with the
+    // place of the tree's first item at the level (its items are together;
+    // ~0u where the places were made on the device and are not known here)
     uint32_t* d_need = nullptr;
+    std::vector<uint32_t> h_need, h_pos;
     uint32_t chunk = 0;
     int D = 64;
     uint64_t chunks_total = 0, slots_total = 0, max_stack = 0, bytes = 0;
@@ -91,8 +94,9 @@ struct ResCache {
     int32_t N = 0;
     std::vector<float*> res;     // per level: n_out * N floats (EV_RING padding rows before)
     float* d_per_case = nullptr;
-    RunLevel* d_chain = nullptr;  // the chained levels as the chained launch sees them
+    RunLevel* d_chain = nullptr;  // the chained launch's queue: runs of the chained levels' items
     int chain_first = -1;         // the first level d_chain holds
+    uint32_t chain_records = 0;   // and its runs
 };
 
 struct Pop {
