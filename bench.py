@@ -434,7 +434,7 @@ def main():
         if args.tune_cache and os.path.exists(args.tune_cache):
             ev.ev_tune_cache_load(args.tune_cache)
         t0 = time.perf_counter()
-        tuning = ev.ev_autotune_ex(c.ctx, parents, 0, 2)
+        tuning = ev.ev_autotune_ex(c.ctx, parents, 0, 2 if giant else 7)  # more timed runs where each is short
         tuning["search_s"] = time.perf_counter() - t0
         print(f"# tuning: {tuning}", file=sys.stderr, flush=True)
     # the level-0 work-item size in use

@@ -467,7 +467,7 @@ static hipError_t enqueue_generation(ev_ctx* c, GenGraph& g, int a, uint32_t nl,
         E(launch_plan_trees(g.tl, M, g.stat, l, 0, cloc, oloc, floc, g.inend, g.sum, s, gl));
         E(launch_g_end(g.tr, g.gls, l, g.d_caps, nl, g.tl, g.sum, g.tb, g.fin, g.st, s));
         E(launch_plan_items(g.ch, kn, g.tb, cloc, oloc, floc, g.inend, g.cursor, g.cb, g.fe, g.run[l], nullptr,
-                            g.codes[l], next, nullptr, s, gl));
+                            g.codes[l], next, s, gl));
         E(launch_seg_chunk(g.cseg, kn, g.cnt, g.stat, g.cb, g.fe, g.scode, g.sfrag, s, gl));
         // placement of the recording (a recording that overflowed voids the
         // generation), or emission and validation when the level is too

@@ -482,12 +482,7 @@ __global__ __launch_bounds__(64) void k_plan_chunks(const TreeLvl* __restrict__ 
 }
 
 __device__ __forceinline__ uint32_t len_bucket(uint32_t len) { return len ? (uint32_t)__clz(len) : 32u; }
-__device__ __forceinline__ uint32_t len_bucket64(uint64_t len) { return len >> 32 ? 0u : len_bucket((uint32_t)len); }
-// the sort key of a work item: its own length, or its tree's
-__device__ __forceinline__ uint32_t item_bucket(const ChunkIn& c, const TreeLvl* tl)
-{
-    return tl ? len_bucket64(tl[c.tree].len) : len_bucket(c.len);
-}
+
 
 // One wave per tree: the numbering of its chunks' slots, fragment tokens and
 // codes relative to the tree (exclusive for codes, inclusive for slots and
@@ -625,16 +620,15 @@ __global__ __launch_bounds__(1024) void k_plan_bases(const TreeLvl* __restrict__
 
 // Per chunk: its global numbering from its tree's bases, and its work item,
 // placed longest first (bucket_start: the first place of each length
-// bucket; the tree gives the chunk's rank inside its bucket), or at
-// item_at[j] when the places were made with the chunks.
+// bucket, zero where the tree's ranks are places already; the tree gives
+// the chunk's rank inside its bucket).
 __global__ void k_plan_items(const ChunkIn* __restrict__ ch, uint32_t n, const TreeBase* __restrict__ base,
                              const uint64_t* __restrict__ code_loc, const uint64_t* __restrict__ out_loc,
                              const uint64_t* __restrict__ frag_loc, const uint32_t* __restrict__ in_end,
                              const uint32_t* __restrict__ bucket_start, uint64_t* __restrict__ code_begin,
                              uint64_t* __restrict__ frag_end, RunChunk* __restrict__ run, EvalChunk* __restrict__ slow,
                              uint32_t* __restrict__ code_tail, uint8_t* __restrict__ frag_tail,
-                             const uint32_t* __restrict__ item_at, const GLevel* __restrict__ gl,
-                             uint32_t* __restrict__ item_tree)
+                             const GLevel* __restrict__ gl, uint32_t* __restrict__ item_tree)
 {
     if (gl) {  // the tails follow the level's live totals
         n = gl->n;
@@ -656,8 +650,7 @@ __global__ void k_plan_items(const ChunkIn* __restrict__ ch, uint32_t n, const T
     code_begin[j] = run ? cb : ~0ull;
     frag_end[j] = b.frag + frag_loc[j];
     const uint32_t k = j - b.chunk_first;
-    const uint32_t at = item_at ? item_at[j]
-                                : bucket_start[len_bucket(c.len)] + (k + 1 < b.n_chunks ? b.rank_full + k : b.rank_last);
+    const uint32_t at = bucket_start[len_bucket(c.len)] + (k + 1 < b.n_chunks ? b.rank_full + k : b.rank_last);
     if (item_tree) item_tree[at] = c.tree;
     if (run)
         run[at] = RunChunk{cb, in_end[j], oe};
@@ -765,61 +758,6 @@ __global__ __launch_bounds__(64) void k_reuse_chunks(const TreeReuse* __restrict
         ch[j] = ChunkIn{t.start + off, len, t.tree};
         cg[j] = ChunkSegs{first, nseg};
         src[j] = from;
-    }
-}
-
-// Work items longest first, for plans whose chunk lengths the host does not
-// know: a counting sort on the length's bit count on the device.  Each wave
-// takes one atomic per distinct bucket among its lanes; the order inside a
-// bucket does not matter.
-__global__ void k_item_hist(const ChunkIn* __restrict__ ch, uint32_t n, uint32_t* __restrict__ hist,
-                            const GLevel* __restrict__ gl, const TreeLvl* __restrict__ tl)
-{
-    if (gl) n = gl->n;
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = j < n;
-    const uint32_t b = in ? item_bucket(ch[j], tl) : EV_LEN_BUCKETS;
-    uint64_t todo = __ballot(in);
-    while (todo) {
-        const uint32_t lead = (uint32_t)__ffsll((unsigned long long)todo) - 1u;
-        const uint32_t b0 = __shfl(b, (int)lead, 64);
-        const uint64_t same = __ballot(in && b == b0);
-        if ((threadIdx.x & 63u) == lead) atomicAdd(&hist[b0], (uint32_t)__popcll(same));
-        todo &= ~same;
-    }
-}
-
-// hist -> each bucket's first place (one thread; 33 buckets)
-__global__ void k_item_cursor(uint32_t* __restrict__ hist)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    uint32_t a = 0;
-    for (uint32_t k = 0; k < EV_LEN_BUCKETS; k++) {
-        const uint32_t v = hist[k];
-        hist[k] = a;
-        a += v;
-    }
-}
-
-__global__ void k_item_place(const ChunkIn* __restrict__ ch, uint32_t n, uint32_t* __restrict__ cursor,
-                             uint32_t* __restrict__ item_at, const GLevel* __restrict__ gl,
-                             const TreeLvl* __restrict__ tl)
-{
-    if (gl) n = gl->n;
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = j < n;
-    const uint32_t b = in ? item_bucket(ch[j], tl) : EV_LEN_BUCKETS;
-    const uint64_t lt = (1ull << (threadIdx.x & 63u)) - 1ull;
-    uint64_t todo = __ballot(in);
-    while (todo) {
-        const uint32_t lead = (uint32_t)__ffsll((unsigned long long)todo) - 1u;
-        const uint32_t b0 = __shfl(b, (int)lead, 64);
-        const uint64_t same = __ballot(in && b == b0);
-        uint32_t base = 0;
-        if ((threadIdx.x & 63u) == lead) base = atomicAdd(&cursor[b0], (uint32_t)__popcll(same));
-        base = __shfl(base, (int)lead, 64);
-        if (in && b == b0) item_at[j] = base + (uint32_t)__popcll(same & lt);
-        todo &= ~same;
     }
 }
 
@@ -2611,12 +2549,12 @@ hipError_t launch_plan_items(const ChunkIn* ch, uint32_t n, const TreeBase* base
                              const uint64_t* out_loc, const uint64_t* frag_loc, const uint32_t* in_end,
                              const uint32_t* cursor,
                              uint64_t* code_begin, uint64_t* frag_end, RunChunk* run, EvalChunk* slow,
-                             uint32_t* code_tail, uint8_t* frag_tail, const uint32_t* item_at, hipStream_t s,
-                             const GLevel* gl, uint32_t* item_tree)
+                             uint32_t* code_tail, uint8_t* frag_tail, hipStream_t s, const GLevel* gl,
+                             uint32_t* item_tree)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_plan_items, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, base, code_loc, out_loc, frag_loc,
-                       in_end, cursor, code_begin, frag_end, run, slow, code_tail, frag_tail, item_at, gl, item_tree);
+                       in_end, cursor, code_begin, frag_end, run, slow, code_tail, frag_tail, gl, item_tree);
     return hipGetLastError();
 }
 
@@ -2635,17 +2573,6 @@ hipError_t launch_reuse_chunks(const TreeReuse* trees, uint32_t n_trees, const C
     if (n_trees == 0) return hipSuccess;
     hipLaunchKernelGGL(k_reuse_chunks, dim3(n_trees), dim3(64), 0, s, trees, n_trees, mum_ch, seg_len, head, ch, cg,
                        src, err_init, n_err);
-    return hipGetLastError();
-}
-
-hipError_t launch_item_sort(const ChunkIn* ch, uint32_t n, uint32_t* hist, uint32_t* item_at, hipStream_t s,
-                            const GLevel* gl, const TreeLvl* tl)
-{
-    hipError_t e = launch_fill_u32(hist, EV_LEN_BUCKETS, 0u, s);
-    if (e != hipSuccess || n == 0) return e;
-    hipLaunchKernelGGL(k_item_hist, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, hist, gl, tl);
-    hipLaunchKernelGGL(k_item_cursor, dim3(1), dim3(64), 0, s, hist);
-    hipLaunchKernelGGL(k_item_place, dim3(cdiv(n, 256)), dim3(256), 0, s, ch, n, hist, item_at, gl, tl);
     return hipGetLastError();
 }
 

@@ -26,18 +26,14 @@ hipError_t launch_plan_items(const ChunkIn* ch, uint32_t n, const TreeBase* base
                              const uint64_t* out_loc, const uint64_t* frag_loc, const uint32_t* in_end,
                              const uint32_t* cursor,
                              uint64_t* code_begin, uint64_t* frag_end, RunChunk* run, EvalChunk* slow,
-                             uint32_t* code_tail, uint8_t* frag_tail, const uint32_t* item_at, hipStream_t s,
-                            const GLevel* gl = nullptr, uint32_t* item_tree = nullptr);
+                             uint32_t* code_tail, uint8_t* frag_tail, hipStream_t s, const GLevel* gl = nullptr,
+                             uint32_t* item_tree = nullptr);
 // children reusing their mum's level-0 chunks
 hipError_t launch_reuse_runs(const XoPlan* plan, const int32_t* mum, const L0Tree* trees, const ChunkIn* mum_ch,
                              uint32_t n, ReuseRun* out, hipStream_t s);
 hipError_t launch_reuse_chunks(const TreeReuse* trees, uint32_t n_trees, const ChunkIn* mum_ch, uint32_t seg_len,
                                uint32_t head, ChunkIn* ch, ChunkSegs* cg, uint32_t* src, uint32_t* err_init,
                                uint32_t n_err, hipStream_t s);
-// work-item places, longest first (hist: EV_LEN_BUCKETS words of scratch);
-// with tl (the level's trees, indexed by tree), biggest tree first instead
-hipError_t launch_item_sort(const ChunkIn* ch, uint32_t n, uint32_t* hist, uint32_t* item_at, hipStream_t s,
-                            const GLevel* gl = nullptr, const TreeLvl* tl = nullptr);
 hipError_t launch_reuse_stats(const uint32_t* src, uint32_t n, const ChunkStat* mum_stat, ChunkStat* cstat,
                               hipStream_t s);
 hipError_t launch_reuse_copy(const uint32_t* src, uint32_t n, const ChunkStat* cstat, const uint64_t* code_begin,

@@ -306,12 +306,12 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
     void *d_tl = nullptr, *d_ch = nullptr, *d_cseg = nullptr, *d_seg = nullptr, *d_fn = nullptr, *d_st = nullptr,
          *d_cnt = nullptr, *d_stat = nullptr, *d_loc = nullptr, *d_inend = nullptr, *d_sum = nullptr, *d_tb = nullptr,
          *d_cb = nullptr, *d_fe = nullptr, *d_scode = nullptr, *d_sfrag = nullptr, *d_err = nullptr, *d_rk = nullptr,
-         *d_rf = nullptr, *d_rec = nullptr, *d_tr = nullptr, *d_src = nullptr, *d_at = nullptr, *d_l0t = nullptr;
+         *d_rf = nullptr, *d_rec = nullptr, *d_tr = nullptr, *d_src = nullptr, *d_l0t = nullptr;
     ev_status st = EV_OK;
     // also frees a skeleton not yet handed to a level
     auto cleanup = [&]() {
         for (void** p : {&d_tl, &d_ch, &d_cseg, &d_seg, &d_fn, &d_st, &d_cnt, &d_stat, &d_loc, &d_inend, &d_sum, &d_tb,
-                         &d_cb, &d_fe, &d_scode, &d_sfrag, &d_err, &d_rk, &d_rf, &d_rec, &d_tr, &d_src, &d_at,
+                         &d_cb, &d_fe, &d_scode, &d_sfrag, &d_err, &d_rk, &d_rf, &d_rec, &d_tr, &d_src,
                          &d_l0t}) {
             dev_free(c, *p);
             *p = nullptr;
@@ -417,6 +417,11 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
             w.seg_first = (uint32_t)ns;
             w.C = (uint32_t)C;
             w.tree = (uint32_t)t;
+            // the ranks of its work items in its length bucket (made
+            // absolute below)
+            w.rank_full = hist[bucket(len)];
+            hist[bucket(len)] += (uint32_t)nc;
+            w.rank_last = w.rank_full + (uint32_t)(nc - 1);
             tl.push_back(w);
             n += nc;
             if (n_mid) ns += (n_mid - 1) * nseg(C) + nseg(v.mid_last);
@@ -474,11 +479,10 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
             cursor[k] = a;
             a += hist[k];
         }
-        if (!reusing)
-            for (TreeLvl& v : tl) {
-                v.rank_full += cursor[bucket(v.len)];
-                v.rank_last += cursor[bucket(v.len)];
-            }
+        for (TreeLvl& v : tl) {
+            v.rank_full += cursor[bucket(v.len)];
+            v.rank_last += cursor[bucket(v.len)];
+        }
         std::fill(cursor, cursor + EV_LEN_BUCKETS, 0u);
         // device: chunks, segments, their counts, and each tree's numbering
         const size_t tl_bytes = nt * sizeof(TreeLvl);
@@ -499,15 +503,12 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         const uint64_t prev_out = pl.levels.empty() ? 0 : pl.levels.back().n_out;
         if (reusing) {
             if ((st = realloc(&d_tr, nt * sizeof(TreeReuse))) || (st = realloc(&d_src, n * sizeof(uint32_t))) ||
-                (st = realloc(&d_at, (n + EV_LEN_BUCKETS) * sizeof(uint32_t))) ||
                 (st = put(x, d_tr, trv.data(), nt * sizeof(TreeReuse)))) {
                 cleanup();
                 return st;
             }
             HIPCHK(launch_reuse_chunks((TreeReuse*)d_tr, nt, reuse->mum->plan.l0_ch, seg_len, head, (ChunkIn*)d_ch,
                                        (ChunkSegs*)d_cseg, (uint32_t*)d_src, (uint32_t*)d_err, N_ERR, s));
-            HIPCHK(launch_item_sort((ChunkIn*)d_ch, (uint32_t)n, (uint32_t*)d_at + n, (uint32_t*)d_at, s, nullptr,
-                                    (TreeLvl*)d_tl));
         } else {
             HIPCHK(launch_plan_chunks((TreeLvl*)d_tl, nt, seg_len, head, (ChunkIn*)d_ch, (ChunkSegs*)d_cseg,
                                       level == 0 ? (uint32_t*)d_err : nullptr, N_ERR, s));
@@ -600,7 +601,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
             pos_all.resize((size_t)(level + 1) * M, ~0u);
             for (uint32_t i = 0; i < nt; i++) {
                 need_all[(size_t)level * M + tl[i].tree] = tl[i].n_chunks;
-                if (!reusing) pos_all[(size_t)level * M + tl[i].tree] = tl[i].rank_full;
+                pos_all[(size_t)level * M + tl[i].tree] = tl[i].rank_full;
             }
         }
 
@@ -672,7 +673,7 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
                                  (uint32_t*)d_inend, (uint32_t*)((uint8_t*)d_tl + tl_bytes), (uint64_t*)d_cb,
                                  (uint64_t*)d_fe, run_items ? LL.d_run : nullptr, run_items ? nullptr : LL.d_chunks,
                                  run_items ? LL.codes + sc : nullptr, any ? d_next + sf : nullptr,
-                                 reusing ? (uint32_t*)d_at : nullptr, s, nullptr, run_items ? LL.d_item_tree : nullptr));
+                                 s, nullptr, run_items ? LL.d_item_tree : nullptr));
         if (any || run_items) {
             HIPCHK(launch_seg_chunk((ChunkSegs*)d_cseg, (uint32_t)n, (SegCount*)d_cnt, (ChunkStat*)d_stat,
                                     (uint64_t*)d_cb, (uint64_t*)d_fe, (uint64_t*)d_scode, (uint64_t*)d_sfrag, s));

@@ -77,12 +77,18 @@ NREG = XX0 + 4
 POS = 32  # positions per 128-byte code block
 NSTRIDE = 32  # bytes per handler at ordinary positions
 TSTRIDE = 64  # bytes per handler at positions 15 and 31 (they also refill)
+# Kinds in table order: within each position's block the kinds a level-0
+# stream uses come first, the rare ones (slot writes, flushes, spills) after,
+# and the skeleton levels' REF kinds last, so that a level-0 launch's hot
+# handlers are one contiguous kilobyte per position and the table's working
+# set stays well inside the instruction cache whatever its alignment.
+# OPS0..OPS2 must be kinds 0..2, and each group (and OUTT..OUTMEM) contiguous.
 KINDS = ["OPS0", "OPS1", "OPS2", "OPS3", "OPX0", "OPX1", "OPX2", "OPX3",
          "CH0", "CH1", "CH2", "CH3", "LCH0", "LCH1", "LCH2", "LCH3",
-         "PUSHX", "LOADX", "OUTT", "OUTX", "FLUSH", "OUTBOT", "END",
-         "SPILL", "FILL", "OUTMEM", "PUSH2X"] + [f"OPS{a}{b}" for a in range(3) for b in range(3)] \
-    + [f"PUSHREF{r}" for r in range(RING)] + [f"LOADREF{r}" for r in range(RING)] \
-    + ["PXCH0", "PXCH1", "PXCH2", "PXCH3"]
+         "PUSHX", "LOADX", "PUSH2X"] + [f"OPS{a}{b}" for a in range(3) for b in range(3)] \
+    + ["PXCH0", "PXCH1", "PXCH2", "PXCH3"] \
+    + ["OUTT", "OUTX", "FLUSH", "OUTBOT", "END", "SPILL", "FILL", "OUTMEM"] \
+    + [f"PUSHREF{r}" for r in range(RING)] + [f"LOADREF{r}" for r in range(RING)]
 NK = len(KINDS)
 TBASE = (POS - 2) * NK * NSTRIDE  # first byte of the position-15 and -31 handlers
 TABLE_BYTES = TBASE + 2 * NK * TSTRIDE
@@ -329,7 +335,10 @@ def generate(cp: str = "") -> str:
         "v_mov_b32_e32 v5, 0",
         "global_store_dword v5, v4, %[flag]",
         "s_branch .Lexit%=",
-        ".p2align 6",
+        # the table starts on a 16 KB boundary: its place relative to the
+        # instruction cache's sets then does not move with unrelated code
+        # (measured: up to 12% apart between placements)
+        ".p2align 14",
         ".Ltab%=:",
     ]
     # handlers in address order (positions 15 and 31 sit after the others)
