@@ -222,13 +222,15 @@ static std::vector<LevelSize> sizes_of(const GLevel* lv, uint32_t levels)
     return v;
 }
 
-// Capacities with room to grow: twice what was seen, with floors that keep
-// small plans from re-capturing at every step, and one level more than seen
-// (sized like the largest skeleton level).  Segments are bounded through the
+// Capacities with room to grow: four times what was seen (twice for plans
+// of over 2^24 tokens, whose buffers are large), with floors that keep small
+// plans from re-capturing at every step, and one level more than seen (sized
+// like the largest skeleton level).  Segments are bounded through the
 // tokens and items, whatever segment length the sizes were seen with.
 static std::vector<LevelSize> caps_from(const std::vector<LevelSize>& seen, uint32_t* levels)
 {
-    auto grow = [](uint64_t v, uint64_t floor) { return std::max<uint64_t>(2 * v, floor); };
+    const uint64_t f = !seen.empty() && seen[0].tokens > (1ull << 24) ? 2 : 4;
+    auto grow = [f](uint64_t v, uint64_t floor) { return std::max<uint64_t>(f * v, floor); };
     std::vector<LevelSize> caps;
     LevelSize hi;  // the largest skeleton level
     for (size_t l = 0; l < seen.size(); l++) {
@@ -368,6 +370,10 @@ static ev_status plan_blocks_make(ev_ctx* c, GenGraph& g, const std::vector<Leve
         dc[l] = GCap{caps[l].n, caps[l].n_seg, caps[l].so, caps[l].sf, caps[l].sc, (uint32_t)slab_rows, 0};
     return put(c->main, g.d_caps, dc.data(), dc.size() * sizeof(GCap));
 }
+
+// Room for a population of `bytes`: four times as much while small (fewer
+// re-captures as trees grow), twice from 16 MB on.
+static uint64_t pop_room(uint64_t bytes) { return (bytes < (1ull << 24) ? 4 : 2) * bytes; }
 
 // The population's buffers for bytes_cap bytes each (with padding),
 // the current population (buffer `keep` of the old ones, `total` bytes)
@@ -575,7 +581,7 @@ static ev_status host_generation(ev_ctx* c, GenGraph& g, int a, uint64_t gen, st
     if (kids->total + EV_POP_PAD > g.bytes_cap) {
         graphs_drop(g);
         // the parents are done with: nothing to keep
-        if ((st = pop_blocks_make(c, g, 2 * (kids->total + EV_POP_PAD), -1, 0)) != EV_OK) {
+        if ((st = pop_blocks_make(c, g, pop_room(kids->total + EV_POP_PAD), -1, 0)) != EV_OK) {
             pop_free(c, kids);
             return st;
         }
@@ -780,7 +786,7 @@ extern "C" ev_status ev_evolve(ev_ctx* c, ev_pop parents, const float* fitness, 
     if (!G.bytes[0] || P->total + EV_POP_PAD > G.bytes_cap * 3 / 4) {
         if ((st = sync(x)) != EV_OK) return st;
         graphs_drop(G);
-        if ((st = pop_blocks_make(c, G, 2 * (P->total + EV_POP_PAD), -1, 0)) != EV_OK) return st;
+        if ((st = pop_blocks_make(c, G, pop_room(P->total + EV_POP_PAD), -1, 0)) != EV_OK) return st;
     }
     G.cur = 0;
     HIPCHK(hipMemcpyAsync(G.bytes[0], P->d_bytes, P->total + EV_POP_PAD, hipMemcpyDeviceToDevice, s));
@@ -872,7 +878,7 @@ extern "C" ev_status ev_evolve(ev_ctx* c, ev_pop parents, const float* fitness, 
                 // generation after them runs again on the new buffers)
                 if ((st = discard_ahead(gen + 1)) != EV_OK) return st;
                 graphs_drop(G);
-                if ((st = pop_blocks_make(c, G, 2 * (gs.child_bytes + EV_POP_PAD), b, gs.child_bytes)) != EV_OK)
+                if ((st = pop_blocks_make(c, G, pop_room(gs.child_bytes + EV_POP_PAD), b, gs.child_bytes)) != EV_OK)
                     return st;
                 regraph = true;
             }
