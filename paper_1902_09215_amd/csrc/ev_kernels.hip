@@ -793,7 +793,17 @@ __global__ __launch_bounds__(256) void k_reuse_copy(const uint32_t* __restrict__
         const u32x4* a = reinterpret_cast<const u32x4*>(mum_codes + mum_code[f]);
         u32x4* b = reinterpret_cast<u32x4*>(codes + code_begin[j]);
         const uint32_t words = ((q.n_codes + (EV_CODE_POS - 1)) & ~(EV_CODE_POS - 1)) / 4u;
-        for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) b[w] = a[w];
+        const uint32_t step = blockDim.x;
+        uint32_t w = threadIdx.x;
+        // four loads in flight per thread
+        for (; w + 3 * step < words; w += 4 * step) {
+            const u32x4 v0 = a[w], v1 = a[w + step], v2 = a[w + 2 * step], v3 = a[w + 3 * step];
+            b[w] = v0;
+            b[w + step] = v1;
+            b[w + 2 * step] = v2;
+            b[w + 3 * step] = v3;
+        }
+        for (; w < words; w += step) b[w] = a[w];
     }
     if (skel) {
         const uint8_t* a = mum_skel + (mum_frag[f] - q.n_frag);
@@ -1604,10 +1614,10 @@ __global__ __launch_bounds__(64) void k_subtree_end(const uint8_t* __restrict__ 
     }
 }
 
-// Copy children: mum[0,p) + dad[q, eq] + mum(ep, nm).  Grid: x = 4 KiB pieces
-// of the child, y = child.  Whole aligned words inside a child are written
-// with one store each; the child's first and last partial words byte by
-// byte (a neighbouring child may share them).
+// Copy children: mum[0,p) + dad[q, eq] + mum(ep, nm), in 4 KiB pieces of
+// each child.  Whole aligned words inside a child are written with one store
+// each; the child's first and last partial words byte by byte (a
+// neighbouring child may share them).
 __device__ __forceinline__ uint8_t child_byte(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
                                               const XoPlan& x, uint64_t i, uint64_t a, uint64_t b)
 {
@@ -1616,30 +1626,74 @@ __device__ __forceinline__ uint8_t child_byte(const uint8_t* __restrict__ mums, 
     return mums[x.mum_off + x.ep + 1 + (i - b)];
 }
 
-// 16 bytes from p (any alignment): five aligned words, shifted together.  It
-// reads up to 3 bytes before p and after p + 16, inside the buffer (its base
-// is aligned) or its padding.
-__device__ __forceinline__ u32x4 load16_at(const uint8_t* __restrict__ p)
+// 16 bytes from p (any alignment) in two steps, so that a thread can have
+// several in flight: the five aligned words around them (a 16-byte load and
+// one more word, read even when p is aligned, so that no branch separates
+// the loads), then the shift.  It reads up to 3 bytes before p and 4 after
+// p + 15, inside the buffer (its base is aligned) or its padding.
+struct Raw16 {
+    uint32_t r[5];
+    uint32_t sh;
+};
+
+__device__ __forceinline__ Raw16 load16_raw(const uint8_t* __restrict__ p)
 {
+    Raw16 w;
     const uint64_t addr = (uint64_t)(uintptr_t)p;
     const uint32_t* q = reinterpret_cast<const uint32_t*>(addr & ~(uint64_t)3);
-    const uint32_t sh = (uint32_t)(addr & 3u) * 8u;
-    const uint32_t r0 = q[0], r1 = q[1], r2 = q[2], r3 = q[3];
-    if (!sh) return u32x4{r0, r1, r2, r3};
-    const uint32_t r4 = q[4];
-    return u32x4{(r0 >> sh) | (r1 << (32u - sh)), (r1 >> sh) | (r2 << (32u - sh)), (r2 >> sh) | (r3 << (32u - sh)),
-                 (r3 >> sh) | (r4 << (32u - sh))};
+    w.sh = (uint32_t)(addr & 3u) * 8u;
+    w.r[0] = q[0];
+    w.r[1] = q[1];
+    w.r[2] = q[2];
+    w.r[3] = q[3];
+    w.r[4] = q[4];
+    return w;
 }
 
-// Piece `piece` (4 KiB) of child x (x.child_off: where its bytes go in dst).
-__device__ __forceinline__ void xo_copy_piece(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
-                                              const XoPlan& x, uint64_t piece, uint8_t* __restrict__ dst)
+__device__ __forceinline__ u32x4 shift16(const Raw16& w)
 {
-    const uint64_t lo = piece * 4096u;
-    if (lo >= x.child_len) return;
-    const uint64_t hi = lo + 4096u < x.child_len ? lo + 4096u : x.child_len;
+    if (!w.sh) return u32x4{w.r[0], w.r[1], w.r[2], w.r[3]};
+    const uint32_t sh = w.sh, up = 32u - sh;
+    return u32x4{(w.r[0] >> sh) | (w.r[1] << up), (w.r[1] >> sh) | (w.r[2] << up), (w.r[2] >> sh) | (w.r[3] << up),
+                 (w.r[3] >> sh) | (w.r[4] << up)};
+}
+
+// Where the child's 16 bytes from i come from: one run of the mum or the
+// dad, or (nullptr) bytes from both sides of a cut.  Every population buffer
+// has EV_POP_PAD bytes of padding after its last tree, so 20 bytes from any
+// tree's start may be read.
+__device__ __forceinline__ const uint8_t* word_src(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
+                                                   const XoPlan& x, uint64_t i, uint64_t a, uint64_t b)
+{
+    if (x.copy_mum || i + 15 < a) return mums + x.mum_off + i;
+    if (i >= a && i + 15 < b) return dads + x.dad_off + x.q + (i - a);
+    if (i >= b) return mums + x.mum_off + x.ep + 1 + (i - b);
+    return nullptr;
+}
+
+__device__ __forceinline__ u32x4 cut_word(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
+                                          const XoPlan& x, uint64_t i, uint64_t a, uint64_t b)
+{
+    uint32_t r[4];
+    for (int k = 0; k < 4; k++)
+        r[k] = (uint32_t)child_byte(mums, dads, x, i + 4 * k, a, b) |
+               ((uint32_t)child_byte(mums, dads, x, i + 4 * k + 1, a, b) << 8) |
+               ((uint32_t)child_byte(mums, dads, x, i + 4 * k + 2, a, b) << 16) |
+               ((uint32_t)child_byte(mums, dads, x, i + 4 * k + 3, a, b) << 24);
+    return u32x4{r[0], r[1], r[2], r[3]};
+}
+
+// Bytes [lo, hi) of child x (x.child_off: where its bytes go in dst), by the
+// whole block.  The output's aligned 16-byte words inside the range take one
+// store each, with four words' loads in flight per thread; the partial
+// words at the range's ends are written byte by byte (the neighbouring
+// range, of this child or another, writes the rest of them).
+__device__ __forceinline__ void xo_copy_range(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
+                                              const XoPlan& x, uint64_t lo, uint64_t hi, uint8_t* __restrict__ dst)
+{
+    if (hi > x.child_len) hi = x.child_len;
+    if (lo >= hi) return;
     const uint64_t a = x.p, b = x.p + (x.eq - x.q + 1);
-    // output 16-byte words [w0, w1) lie wholly inside this child's bytes [lo, hi)
     const uint64_t o0 = x.child_off + lo, o1 = x.child_off + hi;
     const uint64_t w0 = (o0 + 15) & ~(uint64_t)15, w1 = o1 & ~(uint64_t)15;
     if (w0 >= w1) {
@@ -1647,29 +1701,39 @@ __device__ __forceinline__ void xo_copy_piece(const uint8_t* __restrict__ mums, 
             dst[o] = child_byte(mums, dads, x, o - x.child_off, a, b);
         return;
     }
-    for (uint64_t w = w0 + 16u * threadIdx.x; w < w1; w += 16u * blockDim.x) {
-        const uint64_t i = w - x.child_off;  // the word's first byte in the child
-        u32x4 v;
-        if (x.copy_mum || i + 15 < a) {
-            v = load16_at(mums + x.mum_off + i);
-        } else if (i >= a && i + 15 < b) {
-            v = load16_at(dads + x.dad_off + x.q + (i - a));
-        } else if (i >= b) {
-            v = load16_at(mums + x.mum_off + x.ep + 1 + (i - b));
-        } else {  // the word spans a cut: byte by byte
-            uint32_t r[4];
-            for (int k = 0; k < 4; k++)
-                r[k] = (uint32_t)child_byte(mums, dads, x, i + 4 * k, a, b) |
-                       ((uint32_t)child_byte(mums, dads, x, i + 4 * k + 1, a, b) << 8) |
-                       ((uint32_t)child_byte(mums, dads, x, i + 4 * k + 2, a, b) << 16) |
-                       ((uint32_t)child_byte(mums, dads, x, i + 4 * k + 3, a, b) << 24);
-            v = u32x4{r[0], r[1], r[2], r[3]};
+    const uint64_t step = 16u * blockDim.x;
+    uint64_t w = w0 + 16u * threadIdx.x;
+    for (; w + 3 * step < w1; w += 4 * step) {
+        const uint8_t* src[4];
+        Raw16 raw[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            src[u] = word_src(mums, dads, x, w + u * step - x.child_off, a, b);
+            // a word across a cut is put together byte by byte below; its
+            // loads here read the mum's first bytes and are not used
+            raw[u] = load16_raw(src[u] ? src[u] : mums + x.mum_off);
         }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const u32x4 v = src[u] ? shift16(raw[u]) : cut_word(mums, dads, x, w + u * step - x.child_off, a, b);
+            *reinterpret_cast<u32x4*>(dst + w + u * step) = v;
+        }
+    }
+    for (; w < w1; w += step) {
+        const uint8_t* sp = word_src(mums, dads, x, w - x.child_off, a, b);
+        const u32x4 v = sp ? shift16(load16_raw(sp)) : cut_word(mums, dads, x, w - x.child_off, a, b);
         *reinterpret_cast<u32x4*>(dst + w) = v;
     }
     const uint32_t t = threadIdx.x;
     if (t < w0 - o0) dst[o0 + t] = child_byte(mums, dads, x, o0 + t - x.child_off, a, b);
     if (t < o1 - w1) dst[w1 + t] = child_byte(mums, dads, x, w1 + t - x.child_off, a, b);
+}
+
+// Piece `piece` (4 KiB) of child x.
+__device__ __forceinline__ void xo_copy_piece(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
+                                              const XoPlan& x, uint64_t piece, uint8_t* __restrict__ dst)
+{
+    xo_copy_range(mums, dads, x, piece * 4096u, piece * 4096u + 4096u, dst);
 }
 
 // The child holding copy piece pb: the j with pf[j] <= pb < pf[j + 1].
@@ -1686,10 +1750,18 @@ __device__ __forceinline__ uint32_t piece_child(const uint64_t* __restrict__ pf,
     return j;
 }
 
-__global__ void k_xo_copy(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
-                          const XoPlan* __restrict__ plan, const uint64_t* __restrict__ off, uint32_t n_children,
-                          uint8_t* __restrict__ dst, uint8_t* __restrict__ pad, uint32_t pad_len,
-                          const uint32_t* __restrict__ stop)
+// 4 KiB pieces per block of k_xo_copy (64 KiB: enough bytes per block that
+// finding the block's child costs little beside them).
+static constexpr uint32_t XO_BLOCK_PIECES = 16;
+
+// Block b copies the 4 KiB pieces [b * XO_BLOCK_PIECES, (b + 1) *
+// XO_BLOCK_PIECES) of the children (pf: each child's first piece, pf[n] the
+// total), one run of a child's pieces at a time.
+__global__ __launch_bounds__(256) void k_xo_copy(const uint8_t* __restrict__ mums, const uint8_t* __restrict__ dads,
+                                                 const XoPlan* __restrict__ plan, const uint64_t* __restrict__ off,
+                                                 uint32_t n_children, uint8_t* __restrict__ dst,
+                                                 uint8_t* __restrict__ pad, uint32_t pad_len,
+                                                 const uint32_t* __restrict__ stop)
 {
     // with stop (a replayed generation): nothing when the children do not
     // fit their buffer, and the padding goes after their total
@@ -1697,14 +1769,20 @@ __global__ void k_xo_copy(const uint8_t* __restrict__ mums, const uint8_t* __res
     if (!pad) pad = dst + off[n_children];
     if (blockIdx.x == 0)  // the buffer's padding of 0xFF after the children
         for (uint32_t i = threadIdx.x; i < pad_len; i += blockDim.x) pad[i] = 0xFF;
-    // block b copies piece b of its child
     const uint64_t* pf = off + n_children + 4;
-    const uint64_t pb = blockIdx.x;
-    const uint32_t j = piece_child(pf, n_children, pb);
-    if (pb < pf[j]) return;
-    XoPlan x = plan[j];
-    x.child_off = off[j];
-    xo_copy_piece(mums, dads, x, pb - pf[j], dst);
+    const uint64_t pb0 = (uint64_t)blockIdx.x * XO_BLOCK_PIECES;
+    const uint64_t total = pf[n_children];
+    const uint64_t end = pb0 + XO_BLOCK_PIECES < total ? pb0 + XO_BLOCK_PIECES : total;
+    uint64_t pb = pb0;
+    uint32_t j = pb < end ? piece_child(pf, n_children, pb) : 0u;
+    while (pb < end) {
+        while (j + 1 < n_children && pf[j + 1] <= pb) j++;
+        const uint64_t pe = pf[j + 1] < end ? pf[j + 1] : end;
+        XoPlan x = plan[j];
+        x.child_off = off[j];
+        xo_copy_range(mums, dads, x, (pb - pf[j]) * 4096u, (pe - pf[j]) * 4096u, dst);
+        pb = pe;
+    }
 }
 
 // A batch of children to places of their own, for a population kept as a
@@ -2752,8 +2830,8 @@ hipError_t launch_xo_copy(const uint8_t* mums, const uint8_t* dads, const XoPlan
 {
     if (n == 0 || pieces == 0) return launch_fill_u8(pad, pad_len, 0xFF, s);
     if (pieces > 0x7FFFFFFFull) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_xo_copy, dim3((uint32_t)pieces), dim3(256), 0, s, mums, dads, plan, off, n, dst, pad, pad_len,
-                       stop);
+    hipLaunchKernelGGL(k_xo_copy, dim3(cdiv(pieces, XO_BLOCK_PIECES)), dim3(256), 0, s, mums, dads, plan, off, n, dst,
+                       pad, pad_len, stop);
     return hipGetLastError();
 }
 
