@@ -246,9 +246,11 @@ void pop_free(ev_ctx* c, Pop* P)
     delete P;
 }
 
-// Largest recording of a level's codes and fragments (about 11 bytes per
-// token); larger levels count, then emit.
-static constexpr uint64_t RECORD_MAX = (uint64_t)2 << 30;
+// Largest recording of a level's codes and fragments (about 7.3 bytes per
+// token in 64-token segments); larger levels count, then emit.  6 GiB takes
+// the skeleton level of the largest populations (4.7e8 tokens) while their
+// trees hold most of the device.
+static constexpr uint64_t RECORD_MAX = (uint64_t)6 << 30;
 
 // Build the split plan of a population whose bytes are on the device.
 // Level 0 is the trees themselves; each level's chunks produce the next
