@@ -252,6 +252,35 @@ void pop_free(ev_ctx* c, Pop* P)
 // trees hold most of the device.
 static constexpr uint64_t RECORD_MAX = (uint64_t)6 << 30;
 
+// Recording buffer k of x (0: code kinds, 1: fragment tokens, 2: segment
+// records), at least `bytes`.  It stays with x for later plans on x's
+// stream, so that successive generations' plans find it at once: a fresh
+// multi-GB block on a nearly full device costs milliseconds, and the cache
+// may have given its last one back.  It grows by an eighth more than asked.
+static ev_status ensure_rec(ev_ctx* c, Exec& x, int k, size_t bytes, void** out)
+{
+    if (bytes > x.rec_cap[k]) {
+        // queued readers on x's stream finish before the block is used again
+        dev_free(c, x.d_rec_buf[k]);
+        x.d_rec_buf[k] = nullptr;
+        x.rec_cap[k] = 0;
+        const size_t want = bytes + bytes / 8;
+        if (ev_status st = dev_alloc(c, want, &x.d_rec_buf[k])) return st;
+        x.rec_cap[k] = want;
+    }
+    *out = x.d_rec_buf[k];
+    return EV_OK;
+}
+
+static void release_rec(ev_ctx* c, Exec& x)
+{
+    for (int k = 0; k < 3; k++) {
+        dev_free(c, x.d_rec_buf[k]);
+        x.d_rec_buf[k] = nullptr;
+        x.rec_cap[k] = 0;
+    }
+}
+
 // Build the split plan of a population whose bytes are on the device.
 // Level 0 is the trees themselves; each level's chunks produce the next
 // level's skeleton until every tree is one value.  The host keeps what is
@@ -307,14 +336,15 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
     // segments' maps, starts, counts and positions, the chunks' numbering
     void *d_tl = nullptr, *d_ch = nullptr, *d_cseg = nullptr, *d_seg = nullptr, *d_fn = nullptr, *d_st = nullptr,
          *d_cnt = nullptr, *d_stat = nullptr, *d_loc = nullptr, *d_inend = nullptr, *d_sum = nullptr, *d_tb = nullptr,
-         *d_cb = nullptr, *d_fe = nullptr, *d_scode = nullptr, *d_sfrag = nullptr, *d_err = nullptr, *d_rk = nullptr,
-         *d_rf = nullptr, *d_rec = nullptr, *d_tr = nullptr, *d_src = nullptr, *d_l0t = nullptr;
+         *d_cb = nullptr, *d_fe = nullptr, *d_scode = nullptr, *d_sfrag = nullptr, *d_err = nullptr, *d_tr = nullptr,
+         *d_src = nullptr, *d_l0t = nullptr;
+    // the recordings: x's own buffers (see ensure_rec), not freed here
+    void *d_rk = nullptr, *d_rf = nullptr, *d_rec = nullptr;
     ev_status st = EV_OK;
     // also frees a skeleton not yet handed to a level
     auto cleanup = [&]() {
         for (void** p : {&d_tl, &d_ch, &d_cseg, &d_seg, &d_fn, &d_st, &d_cnt, &d_stat, &d_loc, &d_inend, &d_sum, &d_tb,
-                         &d_cb, &d_fe, &d_scode, &d_sfrag, &d_err, &d_rk, &d_rf, &d_rec, &d_tr, &d_src,
-                         &d_l0t}) {
+                         &d_cb, &d_fe, &d_scode, &d_sfrag, &d_err, &d_tr, &d_src, &d_l0t}) {
             dev_free(c, *p);
             *p = nullptr;
         }
@@ -526,17 +556,15 @@ ev_status plan_build(ev_ctx* c, Exec& x, Pop* P, int32_t* bad_tree, bool defer_c
         const uint64_t rf_bytes = rec_frags_stride(seg_len) * n_seg + 64;
         bool record = c->use_record && rk_bytes + rf_bytes <= RECORD_MAX;
         uint32_t* d_ovf = &((TreeSum*)d_sum)[nt].bad;
-        if (record && ((st = realloc(&d_rk, rk_bytes)) || (st = realloc(&d_rf, rf_bytes)) ||
-                       (st = realloc(&d_rec, (uint64_t)n_seg * sizeof(SegRec))))) {
+        if (record && ((st = ensure_rec(c, x, 0, rk_bytes, &d_rk)) || (st = ensure_rec(c, x, 1, rf_bytes, &d_rf)) ||
+                       (st = ensure_rec(c, x, 2, (uint64_t)n_seg * sizeof(SegRec), &d_rec)))) {
             if (st != EV_ENOMEM) {
                 cleanup();
                 return st;
             }
             // no room to record: count, then emit
-            for (void** p : {&d_rk, &d_rf, &d_rec}) {
-                dev_free(c, *p);
-                *p = nullptr;
-            }
+            release_rec(c, x);
+            d_rk = d_rf = d_rec = nullptr;
             record = false;
             st = EV_OK;
         }
@@ -998,6 +1026,7 @@ void exec_free(ev_ctx* c, Exec& x)
     x.d_gstack = nullptr;
     x.d_counters = nullptr;
     x.gstack_bytes = x.n_counters = 0;
+    release_rec(c, x);
     for (hipEvent_t e : x.evl) (void)hipEventDestroy(e);
     x.evl.clear();
     if (x.done) (void)hipEventDestroy(x.done);

@@ -146,6 +146,10 @@ struct Exec {
     size_t n_counters = 0;
     float* d_gstack = nullptr;
     size_t gstack_bytes = 0;
+    // the structure pass's recordings (code kinds, fragment tokens, segment
+    // records), kept from plan to plan on this stream and grown as needed
+    void* d_rec_buf[3] = {nullptr, nullptr, nullptr};
+    size_t rec_cap[3] = {0, 0, 0};
     // the skeleton levels may go in one chained launch (k_run_chain) on
     // this stream; off on the serving workers' streams
     bool chain_ok = true;
