@@ -2140,8 +2140,12 @@ __global__ __launch_bounds__(64) void k_run(RunArgs a)
     }
     const uint32_t lane = threadIdx.x;
     const_u4p chunks = (const_u4p)(global_u4p)(const void*)a.chunks;
-    // this wave's spill slab: slab_entries rows of 64 lanes
+    // this wave's spill slab: slab_entries rows of 64 lanes, whose top
+    // EV_VHALF rows may sit in LDS (the low 32 bits of a shared address are
+    // its LDS offset)
     const uint64_t smem = (uint64_t)(uintptr_t)a.slab + (uint64_t)blockIdx.x * a.slab_entries * 256u;
+    __shared__ float spill_lds[EV_VHALF * 64];
+    const uint32_t lds = (uint32_t)(uintptr_t)spill_lds + lane * 4u;
     uint32_t item = wave_pop(a.counter);
     while (item < a.n_items) {
         const uint32_t next = wave_pop(a.counter);
@@ -2162,7 +2166,7 @@ __global__ __launch_bounds__(64) void k_run(RunArgs a)
                          :
                          : [x] "v"(xv), [lane4] "v"(lane4), [slane] "v"(slane), [cptr] "s"(cptr), [j0] "s"(j0),
                            [inp] "s"(inp), [outp] "s"(outp), [rowb] "s"(a.rowb), [smem] "s"(smem),
-                           [flag] "s"(a.flag), [refs] "s"(a.refs)
+                           [flag] "s"(a.flag), [refs] "s"(a.refs), [lds] "v"(lds)
                          : EV_INTERP_CLOBBERS);
         }
         item = next;
@@ -2500,6 +2504,8 @@ __global__ __launch_bounds__(64) void k_run_chain(ChainArgs a)
 {
     const uint32_t lane = threadIdx.x;
     const uint64_t smem = (uint64_t)(uintptr_t)a.slab + (uint64_t)blockIdx.x * a.slab_entries * 256u;
+    __shared__ float spill_lds[EV_VHALF * 64];  // the slab's top rows (as in k_run)
+    const uint32_t lds = (uint32_t)(uintptr_t)spill_lds + lane * 4u;
     uint32_t item = wave_pop(a.counter);
     while (item < a.total) {
         const uint32_t next = wave_pop(a.counter);
@@ -2549,7 +2555,7 @@ __global__ __launch_bounds__(64) void k_run_chain(ChainArgs a)
                              :
                              : [x] "v"(xv), [lane4] "v"(lane4), [slane] "v"(slane), [cptr] "s"(cptr), [j0] "s"(j0),
                                [inp] "s"(inp), [outp] "s"(outp), [rowb] "s"(a.rowb), [smem] "s"(smem),
-                               [flag] "s"(a.flag), [refs] "s"(refs)
+                               [flag] "s"(a.flag), [refs] "s"(refs), [lds] "v"(lds)
                              : EV_INTERP_CLOBBERS, "memory");
                 if (refs) __builtin_amdgcn_s_setprio(0);
             }

@@ -51,7 +51,8 @@ Register use inside the block (W0 = 7):
   s54 row bytes (cases * 4), M0 window index of T (and the mode bits),
   s[56:57] division scratch, s58 scratch, s59 flush index, s[60:61] next
   free entry of the wave's spill slab in global memory, s[62:63] the slab's
-  base.
+  base, s48 = 1 while the wave's LDS chunk (%[lds]: HALF rows of 64 lanes)
+  holds the slab's top HALF entries.
 
 When the structure machine sees the stack outgrow the window it emits SPILL
 (store the bottom half of the window to the slab, shift the window down);
@@ -260,27 +261,47 @@ def routines(cp: str = "") -> list[str]:
             "s_set_gpr_idx_off", "s_add_u32 s59, s59, 1"] + row_dec(52) + [
             "global_store_dword %[lane4], v4, s[52:53]" + cp, f"s_set_gpr_idx_on s58, {MODE}",
             "s_setpc_b64 s[44:45]"]
-    # spill: the window's bottom HALF entries to the slab, then shift down
-    groups = [(g0, min(16, HALF - g0)) for g0 in range(0, HALF, 16)]
-    out += [".Lspill%=:", "s_set_gpr_idx_off"]
-    for g0, n in groups:
-        out += [f"global_store_dword %[slane], v{W0 + g0 + i}, s[60:61]" + (f" offset:{256 * i}" if i else "")
-                for i in range(n)]
+    # spill: the window's bottom HALF entries to the wave's LDS chunk, which
+    # holds the top HALF entries of the slab; what it held goes on to the
+    # slab in global memory first.  A stack that goes back and forth across a
+    # window boundary then spills and fills through LDS only.
+    tmp = ["v4", "v5"] + [f"v{W0 + VSTACK + i}" for i in range(HEAD)]  # free outside a division
+    out += [".Lspill%=:", "s_set_gpr_idx_off", "s_cmp_eq_u32 s48, 0", "s_cbranch_scc1 .Lspilll%="]
+    for r0 in range(0, HALF, len(tmp)):
+        n = min(len(tmp), HALF - r0)
+        out += [f"ds_read_b32 {tmp[k]}, %[lds] offset:{256 * (r0 + k)}" for k in range(n)]
+        out += ["s_waitcnt lgkmcnt(0)"]
+        out += [f"global_store_dword %[slane], {tmp[k]}, s[60:61]" + (f" offset:{256 * k}" if k else "")
+                for k in range(n)]
         out += [f"s_add_u32 s60, s60, {256 * n}", "s_addc_u32 s61, s61, 0"]
+    out += [".Lspilll%=:"]
+    out += [f"ds_write_b32 %[lds], v{W0 + i}" + (f" offset:{256 * i}" if i else "") for i in range(HALF)]
+    out += ["s_mov_b32 s48, 1"]
     out += [f"v_mov_b32_e32 v{W0 + i}, v{W0 + HALF + i}" for i in range(VSTACK - HALF)]
     out += [f"s_sub_u32 m0, m0, {HALF}", MODE_ON, "s_setpc_b64 s[44:45]"]
-    # fill: shift up, then the top HALF entries of the slab into the bottom
+    # fill: shift up, then the slab's top HALF entries into the bottom: from
+    # the LDS chunk when it holds them, else from global memory
+    groups = [(g0, min(16, HALF - g0)) for g0 in range(0, HALF, 16)]
     out += [".Lfill%=:", "s_set_gpr_idx_off"]
     out += [f"v_mov_b32_e32 v{W0 + HALF + i}, v{W0 + i}" for i in range(VSTACK - HALF)]
+    out += ["s_cmp_eq_u32 s48, 0", "s_cbranch_scc1 .Lfillg%="]
+    out += [f"ds_read_b32 v{W0 + i}, %[lds]" + (f" offset:{256 * i}" if i else "") for i in range(HALF)]
+    out += ["s_mov_b32 s48, 0", "s_waitcnt lgkmcnt(0)", f"s_add_u32 m0, m0, {HALF}", MODE_ON, "s_setpc_b64 s[44:45]"]
+    out += [".Lfillg%=:"]
     for g0, n in reversed(groups):
         out += [f"s_sub_u32 s60, s60, {256 * n}", "s_subb_u32 s61, s61, 0"]
         out += [f"global_load_dword v{W0 + g0 + i}, %[slane], s[60:61]" + (f" offset:{256 * i}" if i else "")
                 for i in range(n)]
     out += ["s_waitcnt vmcnt(0)", f"s_add_u32 m0, m0, {HALF}", MODE_ON, "s_setpc_b64 s[44:45]"]
-    # chunk-end flush of an entry that lives in the slab (entry s59)
-    out += [".Loutmem%=:", "s_set_gpr_idx_off", "s_lshl_b32 s46, s59, 8", "s_add_u32 s46, s62, s46",
+    # chunk-end flush of an entry that lives in the slab (entry s59): in
+    # global memory below the slab pointer, else in the LDS chunk
+    out += [".Loutmem%=:", "s_set_gpr_idx_off", "s_sub_u32 s56, s60, s62", "s_lshr_b32 s56, s56, 8",
+            "s_cmp_lt_u32 s59, s56", "s_cbranch_scc1 .Loutmemg%=",
+            "s_sub_u32 s57, s59, s56", "s_lshl_b32 s57, s57, 8", "v_add_u32_e32 v5, s57, %[lds]",
+            "ds_read_b32 v4, v5", "s_waitcnt lgkmcnt(0)", "s_branch .Loutmemst%=",
+            ".Loutmemg%=:", "s_lshl_b32 s46, s59, 8", "s_add_u32 s46, s62, s46",
             "s_addc_u32 s47, s63, 0", "global_load_dword v4, %[slane], s[46:47]", "s_waitcnt vmcnt(0)",
-            "s_mov_b32 s47, s43", "s_add_u32 s59, s59, 1"] + row_dec(52) + [
+            "s_mov_b32 s47, s43", ".Loutmemst%=:", "s_add_u32 s59, s59, 1"] + row_dec(52) + [
             "global_store_dword %[lane4], v4, s[52:53]" + cp, MODE_ON, "s_setpc_b64 s[44:45]"]
     return out
 
@@ -296,6 +317,7 @@ def generate(cp: str = "") -> str:
         "s_mov_b32 s55, 0",
         "s_mov_b64 s[60:61], %[smem]",
         "s_mov_b64 s[62:63], %[smem]",
+        "s_mov_b32 s48, 0",
         # skeleton levels: start reading the first RING slot rows
         "s_cmp_eq_u32 %[refs], 0",
         "s_cbranch_scc1 .Lnoref%=",
